@@ -1,0 +1,167 @@
+/*
+ * husky.h -- C ABI of the MI355X (gfx950) Huskysort library, libhusky.so.
+ *
+ * Huskysort (Hillyard, Liaozheng, K R; Sec. 3.1 "Overview", Algorithm 1)
+ * sorts objects that are expensive to compare in three steps:
+ *   1. code every object into a 64-bit "husky code" that never inverts the
+ *      order of two objects (Sec. 3.2; for strings, stringToLong,
+ *      Algorithm 4, with the constants of Sec. 4.3);
+ *   2. sort the (code, index) pairs with cheap integer comparisons while the
+ *      indices travel with the codes (the "object swap", Sec. 3.1 Step 2);
+ *   3. remove the inversions that remain, which can only sit among equal
+ *      codes (the role of the final Timsort pass, Sec. 3.1 Step 3).
+ * This library runs all three steps on the GPU: a coalesced encode kernel,
+ * a stable LSD radix sort of (u64 code, u32 index) pairs, and a fix-up that
+ * finds runs of equal codes and sorts each run by the full comparator at
+ * wave, workgroup or device level depending on its length.
+ *
+ * Result.  Every sort returns the STABLE sorting permutation `perm`:
+ * s[perm[k]] <= s[perm[k+1]] under the full comparator, and equal strings
+ * appear in ascending index, so the answer is unique.  Comparators:
+ *   HUSKY_CODER_ASCII7 -- strings of bytes, unsigned byte-lexicographic
+ *     order, a proper prefix first.  The 7-bit code masks each of the first
+ *     nine bytes with 0x7F (Algorithm 4), which preserves order only for
+ *     bytes < 0x80 there; bytes >= 0x80 are allowed from the tenth byte on.
+ *   HUSKY_CODER_UTF16 -- strings of 16-bit code units, code-unit
+ *     lexicographic order (the order of Java's String.compareTo, which the
+ *     paper's final pass uses), a proper prefix first.  The code keeps all
+ *     64 bits of the first four units and is compared unsigned.
+ *
+ * Layout.  `elems` holds all strings back to back: uint8 elements for
+ * ASCII7, uint16 for UTF16.  `offsets` is uint64[n + 1] in ELEMENTS with
+ * offsets[0] = 0, non-decreasing; string i is elems[offsets[i] ..
+ * offsets[i+1]).  Empty strings and NUL elements are allowed.  n < 2^32.
+ *
+ * Memory.  Every pointer argument is a DEVICE pointer owned by the caller,
+ * unless marked "host".  The library allocates no device memory: scratch
+ * space comes from the caller's workspace `ws`, at least
+ * husky_workspace_bytes(n, n_segs) bytes, 256-byte aligned.  The first 16
+ * bytes of the workspace are the device status block (husky_device_status
+ * below), written by every call that takes `ws`.
+ *
+ * Streams and errors.  Calls are enqueued on `stream` (a hipStream_t; NULL
+ * is the default stream) and return after enqueueing.  Argument errors are
+ * detected on the host and returned synchronously; nothing is enqueued then.
+ * Conditions that only the device can see (an ASCII7 byte >= 0x80 among the
+ * first nine bytes) are recorded in the device status block; read it after
+ * synchronizing the stream.  With such a violation `perm` is unspecified.
+ * husky_fixup, husky_sort and husky_sort_batched read small counters back
+ * to the host (synchronizing `stream`) when a run of equal codes is longer
+ * than the workgroup tier's limit, once per refinement round.
+ */
+#ifndef HUSKY_H
+#define HUSKY_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    HUSKY_OK = 0,
+    HUSKY_ERR_ARG = 1,         /* bad argument: null pointer, n >= 2^32, bad coder or bits */
+    HUSKY_ERR_DOMAIN = 2,      /* (device status only) ASCII7 byte >= 0x80 in the first nine */
+    HUSKY_ERR_WORKSPACE = 3,   /* workspace missing, too small or misaligned */
+    HUSKY_ERR_HIP = 4,         /* a HIP runtime call failed */
+    HUSKY_ERR_UNSUPPORTED = 5  /* tuning value outside the compiled variants */
+} husky_status;
+
+typedef enum {
+    HUSKY_CODER_ASCII7 = 0, /* uint8 elements, 9 chars x 7 bits, bits 62..0 */
+    HUSKY_CODER_UTF16 = 1   /* uint16 elements, 4 units x 16 bits, bits 63..0 */
+} husky_coder;
+
+/* Device status block at the start of the workspace (device memory). */
+typedef struct {
+    uint32_t domain_violations; /* ASCII7 strings with a byte >= 0x80 among the first nine */
+    uint32_t large_rounds;      /* device-wide refinement rounds the last fix-up ran */
+    uint32_t runs_fixed;        /* equal-code runs (length >= 2) the last fix-up visited */
+    uint32_t reserved;
+} husky_device_status;
+
+/* Launch tuning.  Zero in a field selects the library default.  The values
+ * the autotuner picks are stored per (device, coder, size band).
+ *   radix_bits -- digit width of every LSD pass: 6, 7 or 8;
+ *   tile_items -- keys per thread in a radix tile (256 threads): 8, 12 or 16;
+ *   t_small    -- equal-code runs of at most this many strings are sorted by
+ *                 one wavefront (2..64);
+ *   t_medium   -- runs of at most this many by one workgroup in LDS
+ *                 (t_small < t_medium <= 8192); longer runs device-wide. */
+typedef struct {
+    int32_t radix_bits;
+    int32_t tile_items;
+    uint32_t t_small;
+    uint32_t t_medium;
+} husky_tuning;
+
+/* Workspace bytes that every call below needs for n strings in n_segs
+ * instances (n_segs = 1 for a single sort). */
+size_t husky_workspace_bytes(uint64_t n, uint64_t n_segs);
+
+/* Step 1 -- Algorithm 4 (stringToLong) over every string, Algorithm 2/3.
+ * codes[i] = sum over j < min(len_i, m) of (e_ij & mask) << w*(m-1-j):
+ * ASCII7 m = 9, w = 7, mask 0x7F; UTF16 m = 4, w = 16, no mask.
+ * idx_or_null: if not NULL receives idx[i] = i (the index array that
+ *   travels with the codes through Step 2).
+ * status: device uint32 that is INCREMENTED by the number of ASCII7 strings
+ *   holding a byte >= 0x80 among their first nine bytes (may be NULL; the
+ *   caller zeroes it).
+ * Errors: HUSKY_ERR_ARG for null elems/offsets/codes with n > 0. */
+husky_status husky_encode(husky_coder coder, const void* elems, const uint64_t* offsets,
+                          uint64_t n, uint64_t* codes, uint32_t* idx_or_null,
+                          uint32_t* status, void* stream);
+
+/* Step 2 -- stable sort of the pairs (codes[i], idx[i]) by codes[i], in place,
+ * comparing only bits [begin_bit, end_bit) of each code (0 <= begin_bit <
+ * end_bit <= 64); equal keys keep their input order.  LSD radix with
+ * tuning->radix_bits per pass; passes whose digit is the same in every key are
+ * skipped.  tuning may be NULL.  Errors: HUSKY_ERR_ARG, HUSKY_ERR_WORKSPACE,
+ * HUSKY_ERR_UNSUPPORTED. */
+husky_status husky_sort_pairs(uint64_t* codes, uint32_t* idx, uint64_t n, int begin_bit,
+                              int end_bit, void* ws, size_t ws_bytes,
+                              const husky_tuning* tuning, void* stream);
+
+/* Step 3 -- given codes sorted ascending with idx carried along (the output
+ * of Step 2), re-sort every run of equal codes by the full comparator so that
+ * idx becomes the stable sorting permutation.  Runs never cross instance
+ * boundaries: seg_offsets_or_null is uint64[n_segs + 1] string offsets of
+ * independent instances (NULL with n_segs = 1 for one instance).  A run whose
+ * members all have the same length <= m (9 ASCII, 4 UTF-16) holds identical
+ * strings already in index order and is left as it is.  idx is updated in
+ * place; sorted_codes is read only.  Errors: HUSKY_ERR_ARG,
+ * HUSKY_ERR_WORKSPACE, HUSKY_ERR_UNSUPPORTED, HUSKY_ERR_HIP. */
+husky_status husky_fixup(husky_coder coder, const void* elems, const uint64_t* offsets,
+                         uint64_t n, const uint64_t* sorted_codes, uint32_t* idx,
+                         const uint64_t* seg_offsets_or_null, uint64_t n_segs, void* ws,
+                         size_t ws_bytes, const husky_tuning* tuning, void* stream);
+
+/* Algorithm 1 end to end on the GPU: encode, stable pair sort, fix-up.
+ * perm receives uint32[n], the stable sorting permutation.  The device status
+ * block in ws reports domain violations.  tuning may be NULL.
+ * Errors: as husky_fixup. */
+husky_status husky_sort(husky_coder coder, const void* elems, const uint64_t* offsets,
+                        uint64_t n, uint32_t* perm, void* ws, size_t ws_bytes,
+                        const husky_tuning* tuning, void* stream);
+
+/* Batched form: n_segs independent instances sorted in the same launches.
+ * n is the total number of strings; seg_offsets is uint64[n_segs + 1]
+ * (device) string offsets, seg_offsets[0] = 0, non-decreasing,
+ * seg_offsets[n_segs] = n.  perm[k] for k in instance j's range is a
+ * GLOBAL string index inside that range: instance j's slice of perm is the
+ * stable sorting permutation of its own strings.  Radix tiles never cross an
+ * instance boundary and neither do runs.  Errors: as husky_fixup. */
+husky_status husky_sort_batched(husky_coder coder, const void* elems, const uint64_t* offsets,
+                                uint64_t n, const uint64_t* seg_offsets, uint64_t n_segs,
+                                uint32_t* perm, void* ws, size_t ws_bytes,
+                                const husky_tuning* tuning, void* stream);
+
+/* Static text for a status code (host). */
+const char* husky_status_string(husky_status s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HUSKY_H */

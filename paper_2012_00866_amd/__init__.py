@@ -1,0 +1,227 @@
+"""MI355X Huskysort: Python binding of libhusky.so (C ABI in include/husky.h).
+
+The binding only marshals arguments: every step of the sort runs in the HIP
+kernels of ``libhusky.so``.  PyTorch provides device memory and the stream.
+If the library has not been built, every call raises ``RuntimeError``; there
+is no fallback.
+
+Strings are passed as a packed element tensor plus uint64 element offsets:
+``elems`` (uint8 for ASCII, int16/uint16 storage of UTF-16 code units) and
+``offsets`` (int64 storage of uint64[n + 1]), both on the GPU.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhusky.so")
+
+CODERS = {"ascii7": 0, "utf16": 1}
+STATUS = {0: "ok", 1: "invalid argument", 2: "domain violation", 3: "workspace",
+          4: "HIP runtime error", 5: "unsupported tuning"}
+
+
+class HuskyError(RuntimeError):
+    def __init__(self, code: int, what: str):
+        super().__init__(f"{what}: {STATUS.get(code, code)} ({code})")
+        self.code = code
+
+
+class DomainError(HuskyError):
+    """An ASCII7 string holds a byte >= 0x80 among its first nine bytes."""
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [("radix_bits", ctypes.c_int32), ("tile_items", ctypes.c_int32),
+                ("t_small", ctypes.c_uint32), ("t_medium", ctypes.c_uint32)]
+
+    def as_dict(self):
+        return {f: int(getattr(self, f)) for f, _ in self._fields_}
+
+
+def make_tuning(radix_bits=0, tile_items=0, t_small=0, t_medium=0) -> Tuning:
+    return Tuning(int(radix_bits), int(tile_items), int(t_small), int(t_medium))
+
+
+_lib = None
+
+EXPORTS = ("husky_workspace_bytes", "husky_encode", "husky_sort_pairs", "husky_fixup",
+           "husky_sort", "husky_sort_batched", "husky_status_string")
+
+
+def load(path: str = LIB_PATH):
+    """Load libhusky.so (raises if it is missing: build it first)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: run `python -m paper_2012_00866_amd.build`")
+    lib = ctypes.CDLL(path)
+    u64, i32, vp, sz = ctypes.c_uint64, ctypes.c_int, ctypes.c_void_p, ctypes.c_size_t
+    tp = ctypes.POINTER(Tuning)
+    lib.husky_workspace_bytes.restype = sz
+    lib.husky_workspace_bytes.argtypes = [u64, u64]
+    lib.husky_encode.restype = i32
+    lib.husky_encode.argtypes = [i32, vp, vp, u64, vp, vp, vp, vp]
+    lib.husky_sort_pairs.restype = i32
+    lib.husky_sort_pairs.argtypes = [vp, vp, u64, i32, i32, vp, sz, tp, vp]
+    lib.husky_fixup.restype = i32
+    lib.husky_fixup.argtypes = [i32, vp, vp, u64, vp, vp, vp, u64, vp, sz, tp, vp]
+    lib.husky_sort.restype = i32
+    lib.husky_sort.argtypes = [i32, vp, vp, u64, vp, vp, sz, tp, vp]
+    lib.husky_sort_batched.restype = i32
+    lib.husky_sort_batched.argtypes = [i32, vp, vp, u64, vp, u64, vp, vp, sz, tp, vp]
+    lib.husky_status_string.restype = ctypes.c_char_p
+    lib.husky_status_string.argtypes = [i32]
+    _lib = lib
+    return lib
+
+
+# ----------------------------------------------------------------- helpers
+def _torch():
+    import torch
+
+    return torch
+
+
+def _ptr(t) -> Optional[int]:
+    return None if t is None else int(t.data_ptr())
+
+
+def _stream(stream=None) -> int:
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return int(s.cuda_stream)
+
+
+def _coder(c) -> int:
+    return CODERS[c] if isinstance(c, str) else int(c)
+
+
+def _check(code: int, what: str):
+    if code != 0:
+        raise HuskyError(code, what)
+
+
+def workspace_bytes(n: int, n_segs: int = 1) -> int:
+    return int(load().husky_workspace_bytes(int(n), int(n_segs)))
+
+
+def alloc_workspace(n: int, n_segs: int = 1, device="cuda"):
+    torch = _torch()
+    return torch.empty(workspace_bytes(n, n_segs), dtype=torch.uint8, device=device)
+
+
+def read_status(ws) -> dict:
+    """Device status block (first 16 bytes of the workspace); synchronizes."""
+    v = ws[:16].cpu().numpy().view(np.uint32)
+    return {"domain_violations": int(v[0]), "large_rounds": int(v[1]), "runs_fixed": int(v[2])}
+
+
+def to_device(batch, device="cuda"):
+    """(elems, offsets) device tensors for a workloads.StringBatch."""
+    torch = _torch()
+    e = batch.elems
+    if e.dtype == np.uint16:
+        e = e.view(np.int16)
+    if e.size == 0:
+        e = np.zeros(8, dtype=e.dtype)
+    elems = torch.from_numpy(np.ascontiguousarray(e)).to(device)
+    offsets = torch.from_numpy(np.ascontiguousarray(batch.offsets).view(np.int64)).to(device)
+    return elems, offsets
+
+
+def _n_of(offsets) -> int:
+    return int(offsets.numel()) - 1
+
+
+# ----------------------------------------------------------------- entry points
+def encode(elems, offsets, coder="ascii7", with_idx=True, status=None, stream=None):
+    """Step 1: (codes int64-storage uint64[n], idx int32-storage uint32[n] or None)."""
+    torch = _torch()
+    lib = load()
+    n = _n_of(offsets)
+    codes = torch.empty(max(n, 1), dtype=torch.int64, device=offsets.device)
+    idx = torch.empty(max(n, 1), dtype=torch.int32, device=offsets.device) if with_idx else None
+    _check(lib.husky_encode(_coder(coder), _ptr(elems), _ptr(offsets), n, _ptr(codes), _ptr(idx),
+                            _ptr(status), _stream(stream)), "husky_encode")
+    return codes[:n], (idx[:n] if idx is not None else None)
+
+
+def sort_pairs(codes, idx, begin_bit=0, end_bit=64, tuning: Optional[Tuning] = None, ws=None,
+               stream=None):
+    """Step 2 in place: stable sort of (codes, idx) by bits [begin_bit, end_bit)."""
+    lib = load()
+    n = int(codes.numel())
+    if ws is None:
+        ws = alloc_workspace(n, 1, codes.device)
+    _check(lib.husky_sort_pairs(_ptr(codes), _ptr(idx), n, int(begin_bit), int(end_bit), _ptr(ws),
+                                ws.numel(), ctypes.byref(tuning) if tuning else None,
+                                _stream(stream)), "husky_sort_pairs")
+    return codes, idx
+
+
+def fixup(elems, offsets, sorted_codes, idx, coder="ascii7", seg_offsets=None,
+          tuning: Optional[Tuning] = None, ws=None, stream=None):
+    """Step 3 in place on idx (runs of equal codes re-sorted by the full comparator)."""
+    lib = load()
+    n = _n_of(offsets)
+    ns = 1 if seg_offsets is None else int(seg_offsets.numel()) - 1
+    if ws is None:
+        ws = alloc_workspace(n, ns, offsets.device)
+    _check(lib.husky_fixup(_coder(coder), _ptr(elems), _ptr(offsets), n, _ptr(sorted_codes),
+                           _ptr(idx), _ptr(seg_offsets), ns, _ptr(ws), ws.numel(),
+                           ctypes.byref(tuning) if tuning else None, _stream(stream)),
+           "husky_fixup")
+    return idx
+
+
+def sort(elems, offsets, coder="ascii7", tuning: Optional[Tuning] = None, ws=None, perm=None,
+         stream=None, check_status=True):
+    """Algorithm 1 on the GPU: returns perm (int32 storage of uint32[n])."""
+    torch = _torch()
+    lib = load()
+    n = _n_of(offsets)
+    if ws is None:
+        ws = alloc_workspace(n, 1, offsets.device)
+    if perm is None:
+        perm = torch.empty(max(n, 1), dtype=torch.int32, device=offsets.device)
+    _check(lib.husky_sort(_coder(coder), _ptr(elems), _ptr(offsets), n, _ptr(perm), _ptr(ws),
+                          ws.numel(), ctypes.byref(tuning) if tuning else None, _stream(stream)),
+           "husky_sort")
+    if check_status:
+        st = read_status(ws)
+        if st["domain_violations"]:
+            raise DomainError(2, f"husky_sort ({st['domain_violations']} strings)")
+    return perm[:n]
+
+
+def sort_batched(elems, offsets, seg_offsets, coder="ascii7", tuning: Optional[Tuning] = None,
+                 ws=None, perm=None, stream=None, check_status=True):
+    """Batched form: every instance sorted on its own; perm holds global indices."""
+    torch = _torch()
+    lib = load()
+    n = _n_of(offsets)
+    ns = int(seg_offsets.numel()) - 1
+    if ws is None:
+        ws = alloc_workspace(n, ns, offsets.device)
+    if perm is None:
+        perm = torch.empty(max(n, 1), dtype=torch.int32, device=offsets.device)
+    _check(lib.husky_sort_batched(_coder(coder), _ptr(elems), _ptr(offsets), n, _ptr(seg_offsets),
+                                  ns, _ptr(perm), _ptr(ws), ws.numel(),
+                                  ctypes.byref(tuning) if tuning else None, _stream(stream)),
+           "husky_sort_batched")
+    if check_status:
+        st = read_status(ws)
+        if st["domain_violations"]:
+            raise DomainError(2, f"husky_sort_batched ({st['domain_violations']} strings)")
+    return perm[:n]
+
+
+def status_string(code: int) -> str:
+    return load().husky_status_string(int(code)).decode()

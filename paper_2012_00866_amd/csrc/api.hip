@@ -1,0 +1,343 @@
+// C ABI of libhusky.so: argument checks, workspace layout and the order of
+// the kernel launches for every entry point declared in include/husky.h.
+// Each step's kernels live in encode.hip (Step 1), radix.hip (Step 2),
+// runs.hip and fixup.hip (Step 3).
+
+#include <algorithm>
+
+#include "../../include/husky.h"
+#include "common.h"
+#include "internal.h"
+
+namespace husky {
+namespace {
+
+constexpr size_t ALIGN = 256;
+constexpr uint32_t MIN_TILE = BLOCK * 8;  // smallest compiled tile
+constexpr uint32_t MIN_T_MEDIUM = 64;
+constexpr uint32_t MAX_T_MEDIUM = 4096;
+constexpr uint32_t MAX_T_SMALL = 64;
+
+size_t align_up(size_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
+
+// Byte offsets of every region inside the caller's workspace.
+struct Layout {
+    size_t status, counters, codes_a, codes_b, idx_b, segs, hist, lookback, tile_counts,
+        run_start, run_end, small, medium, large_a, large_b, total;
+    uint32_t seg_cap, big_cap, tile_cap, lookback_cap, run_cap, small_cap, medium_cap, large_cap;
+};
+
+Layout make_layout(uint64_t n, uint64_t n_segs) {
+    Layout L{};
+    const uint64_t S = n_segs ? n_segs : 1;
+    L.large_cap = (uint32_t)(n / (MIN_T_MEDIUM + 1) + 2);
+    L.seg_cap = (uint32_t)std::max<uint64_t>(S, L.large_cap);
+    // tiles over any set of segments used by one sort: instances or
+    // device-wide fix-up groups
+    L.tile_cap = (uint32_t)(n / MIN_TILE + L.seg_cap + 2);
+    // multi-tile segments hold more than one tile (>= MIN_TILE positions) each
+    L.big_cap = (uint32_t)(n / MIN_TILE + 2);
+    L.lookback_cap = 2 * L.big_cap;  // tiles over multi-tile segments
+    L.run_cap = (uint32_t)(n / 2 + 1);
+    L.small_cap = L.run_cap;
+    L.medium_cap = (uint32_t)(n / 3 + 1);
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        size_t at = o;
+        o = align_up(o + bytes);
+        return at;
+    };
+    L.status = take(sizeof(husky_device_status));
+    L.counters = take(128 * sizeof(uint32_t));
+    L.codes_a = take(n * 8);
+    L.codes_b = take(n * 8);
+    L.idx_b = take(n * 4);
+    L.segs = take((size_t)(L.seg_cap + L.big_cap) * sizeof(SegDesc));
+    L.hist = take((size_t)L.big_cap * MAX_PASSES * 256 * 4);
+    L.lookback = take((size_t)L.lookback_cap * 256 * 8);
+    L.tile_counts = take((size_t)(L.tile_cap + 1) * 4);
+    L.run_start = take((size_t)L.run_cap * 2 * 4);
+    L.run_end = take((size_t)L.run_cap * 4);
+    L.small = take((size_t)L.small_cap * sizeof(RunItem));
+    L.medium = take((size_t)L.medium_cap * sizeof(RunItem));
+    L.large_a = take((size_t)L.large_cap * sizeof(RunItem));
+    L.large_b = take((size_t)L.large_cap * sizeof(RunItem));
+    L.total = o;
+    return L;
+}
+
+// counters region: [0, 64) radix counters; [64, 80) run counters;
+// [80] small count, [81] medium count, [82] large A count, [83] large B count
+constexpr int CNT_RUNS = 64, CNT_SMALL = 80, CNT_MEDIUM = 81, CNT_LARGE_A = 82, CNT_LARGE_B = 83;
+
+struct Ctx {
+    Layout L;
+    uint8_t* ws;
+    RadixScratch rad;
+    RunScratch runs;
+    TierLists tiers;
+    husky_device_status* status;
+    uint32_t* counters;
+    template <typename T>
+    T* at(size_t off) const {
+        return reinterpret_cast<T*>(ws + off);
+    }
+};
+
+Ctx make_ctx(void* ws, uint64_t n, uint64_t n_segs) {
+    Ctx c;
+    c.L = make_layout(n, n_segs);
+    c.ws = (uint8_t*)ws;
+    c.status = c.at<husky_device_status>(c.L.status);
+    c.counters = c.at<uint32_t>(c.L.counters);
+    c.rad.segs = c.at<SegDesc>(c.L.segs);
+    c.rad.hist = c.at<uint32_t>(c.L.hist);
+    c.rad.status = c.at<uint64_t>(c.L.lookback);
+    c.rad.counters = c.counters;
+    c.rad.seg_cap = c.L.seg_cap;
+    c.rad.big_cap = c.L.big_cap;
+    c.rad.tile_cap = c.L.tile_cap;
+    c.rad.lookback_cap = c.L.lookback_cap;
+    c.runs.tile_counts = c.at<uint32_t>(c.L.tile_counts);
+    c.runs.run_start = c.at<uint32_t>(c.L.run_start);
+    c.runs.run_end = c.at<uint32_t>(c.L.run_end);
+    c.runs.counters = c.counters + CNT_RUNS;
+    c.runs.runs_seen = &c.status->runs_fixed;
+    c.runs.tile_cap = c.L.tile_cap;
+    c.runs.run_cap = c.L.run_cap;
+    c.tiers.small = c.at<RunItem>(c.L.small);
+    c.tiers.medium = c.at<RunItem>(c.L.medium);
+    c.tiers.large = c.at<RunItem>(c.L.large_a);
+    c.tiers.small_count = c.counters + CNT_SMALL;
+    c.tiers.medium_count = c.counters + CNT_MEDIUM;
+    c.tiers.large_count = c.counters + CNT_LARGE_A;
+    c.tiers.small_cap = c.L.small_cap;
+    c.tiers.medium_cap = c.L.medium_cap;
+    c.tiers.large_cap = c.L.large_cap;
+    return c;
+}
+
+struct Tune {
+    RadixConfig rc;
+    uint32_t t_small, t_medium;
+};
+
+husky_status resolve_tuning(const husky_tuning* t, Tune* out) {
+    Tune r{{8, 16}, 64, 4096};
+    if (t) {
+        if (t->radix_bits) r.rc.bits = t->radix_bits;
+        if (t->tile_items) r.rc.items = t->tile_items;
+        if (t->t_small) r.t_small = t->t_small;
+        if (t->t_medium) r.t_medium = t->t_medium;
+    }
+    if (r.rc.bits < 6 || r.rc.bits > 8) return HUSKY_ERR_UNSUPPORTED;
+    if (r.rc.items != 8 && r.rc.items != 12 && r.rc.items != 16) return HUSKY_ERR_UNSUPPORTED;
+    if (r.t_small < 2 || r.t_small > MAX_T_SMALL) return HUSKY_ERR_UNSUPPORTED;
+    if (r.t_medium < MIN_T_MEDIUM || r.t_medium > MAX_T_MEDIUM || r.t_medium <= r.t_small)
+        return HUSKY_ERR_UNSUPPORTED;
+    *out = r;
+    return HUSKY_OK;
+}
+
+husky_status check_ws(void* ws, size_t ws_bytes, uint64_t n, uint64_t n_segs) {
+    if (!ws) return HUSKY_ERR_WORKSPACE;
+    if (((uintptr_t)ws) % ALIGN) return HUSKY_ERR_WORKSPACE;
+    if (ws_bytes < make_layout(n, n_segs).total) return HUSKY_ERR_WORKSPACE;
+    return HUSKY_OK;
+}
+
+__global__ void k_set_u32(uint32_t* p, uint32_t v) { *p = v; }
+
+husky_status hip_status(hipError_t e) { return e == hipSuccess ? HUSKY_OK : HUSKY_ERR_HIP; }
+
+#define HUSKY_TRY(expr)                              \
+    do {                                             \
+        hipError_t e_ = (expr);                      \
+        if (e_ != hipSuccess) return HUSKY_ERR_HIP;  \
+    } while (0)
+
+hipError_t read_u32(const uint32_t* dev, uint32_t* host, hipStream_t s) {
+    hipError_t e = hipMemcpyAsync(host, dev, sizeof(uint32_t), hipMemcpyDeviceToHost, s);
+    if (e != hipSuccess) return e;
+    return hipStreamSynchronize(s);
+}
+
+uint32_t tiles_bound(uint64_t n, uint64_t segs, const RadixConfig& rc) {
+    return (uint32_t)((n + rc.tile() - 1) / rc.tile() + segs + 1);
+}
+
+// Step 3 over the segments currently described in c.rad (the instances the
+// codes were sorted in).  `codes` are the sorted codes; `keys`/`keys_alt`
+// are scratch key buffers (may alias `codes` once the runs are found).
+husky_status run_fixup(Ctx& c, const Tune& tn, int coder, const void* elems,
+                       const uint64_t* offsets, uint64_t n, uint64_t n_segs,
+                       const uint64_t* codes, uint64_t* keys, uint64_t* keys_alt, uint32_t* idx,
+                       hipStream_t s) {
+    HUSKY_TRY(zero_u32(c.counters + CNT_SMALL, 4, s));
+    const uint32_t tb = tiles_bound(n, n_segs, tn.rc);
+    HUSKY_TRY(find_runs(codes, c.rad, tn.rc, tb, coder, false, nullptr, c.runs, c.tiers,
+                        tn.t_small, tn.t_medium, s));
+    FixupArgs fa{coder, elems, offsets, (uint32_t)n, idx};
+    uint32_t nl = 0, rounds = 0;
+    HUSKY_TRY(read_u32(c.counters + CNT_LARGE_A, &nl, s));
+    RunItem* cur = c.at<RunItem>(c.L.large_a);
+    RunItem* nxt = c.at<RunItem>(c.L.large_b);
+    uint32_t* cur_cnt = c.counters + CNT_LARGE_A;
+    uint32_t* nxt_cnt = c.counters + CNT_LARGE_B;
+    while (nl > 0) {
+        nl = std::min(nl, c.L.large_cap);
+        HUSKY_TRY(radix_segments_from_items(cur, cur_cnt, c.L.large_cap, c.rad, tn.rc, s));
+        const uint32_t tl = tiles_bound(n, nl, tn.rc);
+        HUSKY_TRY(fixup_large_keys(fa, cur, c.rad, tn.rc, tl, keys, s));
+        HUSKY_TRY(radix_sort_segments(keys, idx, keys_alt, c.at<uint32_t>(c.L.idx_b), 0, 64, nl, tl,
+                                      c.rad, tn.rc, s));
+        TierLists t2 = c.tiers;
+        t2.large = nxt;
+        t2.large_count = nxt_cnt;
+        HUSKY_TRY(zero_u32(nxt_cnt, 1, s));
+        HUSKY_TRY(find_runs(keys, c.rad, tn.rc, tl, coder, true, cur, c.runs, t2, tn.t_small,
+                            tn.t_medium, s));
+        std::swap(cur, nxt);
+        std::swap(cur_cnt, nxt_cnt);
+        HUSKY_TRY(read_u32(cur_cnt, &nl, s));
+        ++rounds;
+    }
+    HUSKY_TRY(fixup_medium(fa, c.tiers, tn.t_medium, s));
+    HUSKY_TRY(fixup_small(fa, c.tiers, tn.t_small, s));
+    hipLaunchKernelGGL(k_set_u32, dim3(1), dim3(1), 0, s, &c.status->large_rounds, rounds);
+    HUSKY_TRY(hipGetLastError());
+    return HUSKY_OK;
+}
+
+husky_status check_common(int coder, const void* elems, const uint64_t* offsets, uint64_t n) {
+    if (coder != HUSKY_CODER_ASCII7 && coder != HUSKY_CODER_UTF16) return HUSKY_ERR_ARG;
+    if (n >= (1ull << 32)) return HUSKY_ERR_ARG;
+    if (n > 0 && (!elems || !offsets)) return HUSKY_ERR_ARG;
+    return HUSKY_OK;
+}
+
+}  // namespace
+}  // namespace husky
+
+using namespace husky;
+
+extern "C" {
+
+size_t husky_workspace_bytes(uint64_t n, uint64_t n_segs) { return make_layout(n, n_segs).total; }
+
+husky_status husky_encode(husky_coder coder, const void* elems, const uint64_t* offsets,
+                          uint64_t n, uint64_t* codes, uint32_t* idx_or_null, uint32_t* status,
+                          void* stream) {
+    husky_status st = check_common(coder, elems, offsets, n);
+    if (st != HUSKY_OK) return st;
+    if (n > 0 && !codes) return HUSKY_ERR_ARG;
+    return hip_status(launch_encode(coder, elems, offsets, (uint32_t)n, codes, idx_or_null, status,
+                                    (hipStream_t)stream));
+}
+
+husky_status husky_sort_pairs(uint64_t* codes, uint32_t* idx, uint64_t n, int begin_bit,
+                              int end_bit, void* ws, size_t ws_bytes, const husky_tuning* tuning,
+                              void* stream) {
+    if (n >= (1ull << 32)) return HUSKY_ERR_ARG;
+    if (n > 0 && (!codes || !idx)) return HUSKY_ERR_ARG;
+    if (begin_bit < 0 || end_bit > 64 || begin_bit >= end_bit) return HUSKY_ERR_ARG;
+    Tune tn;
+    husky_status st = resolve_tuning(tuning, &tn);
+    if (st != HUSKY_OK) return st;
+    st = check_ws(ws, ws_bytes, n, 1);
+    if (st != HUSKY_OK) return st;
+    if (n < 2) return HUSKY_OK;
+    hipStream_t s = (hipStream_t)stream;
+    Ctx c = make_ctx(ws, n, 1);
+    HUSKY_TRY(radix_segments_single((uint32_t)n, c.rad, tn.rc, s));
+    HUSKY_TRY(radix_sort_segments(codes, idx, c.at<uint64_t>(c.L.codes_b), c.at<uint32_t>(c.L.idx_b),
+                                  begin_bit, end_bit, 1, tiles_bound(n, 1, tn.rc), c.rad, tn.rc, s));
+    return HUSKY_OK;
+}
+
+husky_status husky_fixup(husky_coder coder, const void* elems, const uint64_t* offsets, uint64_t n,
+                         const uint64_t* sorted_codes, uint32_t* idx,
+                         const uint64_t* seg_offsets_or_null, uint64_t n_segs, void* ws,
+                         size_t ws_bytes, const husky_tuning* tuning, void* stream) {
+    husky_status st = check_common(coder, elems, offsets, n);
+    if (st != HUSKY_OK) return st;
+    if (n > 0 && (!sorted_codes || !idx)) return HUSKY_ERR_ARG;
+    if (seg_offsets_or_null && (n_segs == 0 || n_segs >= (1ull << 32))) return HUSKY_ERR_ARG;
+    if (!seg_offsets_or_null) n_segs = 1;
+    Tune tn;
+    st = resolve_tuning(tuning, &tn);
+    if (st != HUSKY_OK) return st;
+    st = check_ws(ws, ws_bytes, n, n_segs);
+    if (st != HUSKY_OK) return st;
+    hipStream_t s = (hipStream_t)stream;
+    Ctx c = make_ctx(ws, n, n_segs);
+    HUSKY_TRY(zero_u32((uint32_t*)c.status, 4, s));
+    if (n < 2) return HUSKY_OK;
+    if (seg_offsets_or_null)
+        HUSKY_TRY(radix_segments_from_offsets(seg_offsets_or_null, (uint32_t)n_segs, c.rad, tn.rc, s));
+    else
+        HUSKY_TRY(radix_segments_single((uint32_t)n, c.rad, tn.rc, s));
+    return run_fixup(c, tn, coder, elems, offsets, n, n_segs, sorted_codes, c.at<uint64_t>(c.L.codes_a),
+                     c.at<uint64_t>(c.L.codes_b), idx, s);
+}
+
+static husky_status sort_common(husky_coder coder, const void* elems, const uint64_t* offsets,
+                                uint64_t n, const uint64_t* seg_offsets, uint64_t n_segs,
+                                uint32_t* perm, void* ws, size_t ws_bytes,
+                                const husky_tuning* tuning, void* stream) {
+    husky_status st = check_common(coder, elems, offsets, n);
+    if (st != HUSKY_OK) return st;
+    if (n > 0 && !perm) return HUSKY_ERR_ARG;
+    Tune tn;
+    st = resolve_tuning(tuning, &tn);
+    if (st != HUSKY_OK) return st;
+    st = check_ws(ws, ws_bytes, n, n_segs);
+    if (st != HUSKY_OK) return st;
+    hipStream_t s = (hipStream_t)stream;
+    Ctx c = make_ctx(ws, n, n_segs);
+    HUSKY_TRY(zero_u32((uint32_t*)c.status, 4, s));
+    if (n == 0) return HUSKY_OK;
+    uint64_t* codes = c.at<uint64_t>(c.L.codes_a);
+    uint64_t* codes_b = c.at<uint64_t>(c.L.codes_b);
+    HUSKY_TRY(launch_encode(coder, elems, offsets, (uint32_t)n, codes, perm,
+                            &c.status->domain_violations, s));
+    if (seg_offsets)
+        HUSKY_TRY(radix_segments_from_offsets(seg_offsets, (uint32_t)n_segs, c.rad, tn.rc, s));
+    else
+        HUSKY_TRY(radix_segments_single((uint32_t)n, c.rad, tn.rc, s));
+    const int end_bit = coder == HUSKY_CODER_ASCII7 ? 63 : 64;
+    HUSKY_TRY(radix_sort_segments(codes, perm, codes_b, c.at<uint32_t>(c.L.idx_b), 0, end_bit,
+                                  (uint32_t)n_segs, tiles_bound(n, n_segs, tn.rc), c.rad, tn.rc, s));
+    // the sorted codes are not needed once the runs are listed, so the
+    // device-wide fix-up reuses both code buffers for its keys
+    return run_fixup(c, tn, coder, elems, offsets, n, n_segs, codes, codes, codes_b, perm, s);
+}
+
+husky_status husky_sort(husky_coder coder, const void* elems, const uint64_t* offsets, uint64_t n,
+                        uint32_t* perm, void* ws, size_t ws_bytes, const husky_tuning* tuning,
+                        void* stream) {
+    return sort_common(coder, elems, offsets, n, nullptr, 1, perm, ws, ws_bytes, tuning, stream);
+}
+
+husky_status husky_sort_batched(husky_coder coder, const void* elems, const uint64_t* offsets,
+                                uint64_t n, const uint64_t* seg_offsets, uint64_t n_segs,
+                                uint32_t* perm, void* ws, size_t ws_bytes,
+                                const husky_tuning* tuning, void* stream) {
+    if (!seg_offsets || n_segs == 0 || n_segs >= (1ull << 32)) return HUSKY_ERR_ARG;
+    return sort_common(coder, elems, offsets, n, seg_offsets, n_segs, perm, ws, ws_bytes, tuning,
+                       stream);
+}
+
+const char* husky_status_string(husky_status s) {
+    switch (s) {
+        case HUSKY_OK: return "ok";
+        case HUSKY_ERR_ARG: return "invalid argument";
+        case HUSKY_ERR_DOMAIN: return "ASCII7 byte >= 0x80 among the first nine bytes";
+        case HUSKY_ERR_WORKSPACE: return "workspace missing, misaligned or too small";
+        case HUSKY_ERR_HIP: return "HIP runtime error";
+        case HUSKY_ERR_UNSUPPORTED: return "tuning value not supported";
+    }
+    return "unknown status";
+}
+
+}  // extern "C"

@@ -1,0 +1,110 @@
+// Host-side interfaces between the kernel files and the C ABI layer.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "common.h"
+
+namespace husky {
+
+// ---- encode.hip
+hipError_t launch_encode(int coder, const void* elems, const uint64_t* offsets, uint32_t n,
+                         uint64_t* codes, uint32_t* idx, uint32_t* status, hipStream_t s);
+
+// ---- radix.hip
+struct RadixConfig {
+    int bits;        // digit width: 6, 7 or 8
+    int items;       // keys per thread: 8, 12 or 16 (tile = 256 * items)
+    int tile() const { return BLOCK * items; }
+};
+
+// Device scratch used by one segmented sort; carved from the workspace.
+struct RadixScratch {
+    SegDesc* segs;         // [seg_cap]
+    uint32_t* hist;        // [big_cap][MAX_PASSES][256]
+    uint64_t* status;      // [lookback_cap][256] look-back words
+    uint32_t* counters;    // [64]: per-pass tile counters, totals (see radix.hip)
+    uint32_t seg_cap, big_cap, tile_cap, lookback_cap;
+};
+
+// Build segment descriptors from uint64 string offsets (n_segs + 1 entries).
+hipError_t radix_segments_from_offsets(const uint64_t* seg_offsets, uint32_t n_segs,
+                                       const RadixScratch& sc, const RadixConfig& cfg,
+                                       hipStream_t s);
+// Build segment descriptors for a single segment [0, n).
+hipError_t radix_segments_single(uint32_t n, const RadixScratch& sc, const RadixConfig& cfg,
+                                 hipStream_t s);
+// Build segment descriptors from a fix-up work list (count in device memory).
+hipError_t radix_segments_from_items(const RunItem* items, const uint32_t* count,
+                                     uint32_t max_items, const RadixScratch& sc,
+                                     const RadixConfig& cfg, hipStream_t s);
+
+// Stable sort of (keys, vals) by bits [begin_bit, end_bit) inside every
+// segment described in sc (built by one of the functions above); keys_alt /
+// vals_alt are ping-pong buffers of the same size.  The result ends in
+// keys / vals.  max_tiles / max_segs bound the grid sizes.
+hipError_t radix_sort_segments(uint64_t* keys, uint32_t* vals, uint64_t* keys_alt,
+                               uint32_t* vals_alt, int begin_bit, int end_bit,
+                               uint32_t max_segs, uint32_t max_tiles, const RadixScratch& sc,
+                               const RadixConfig& cfg, hipStream_t s);
+
+// ---- runs.hip
+struct RunScratch {
+    uint32_t* tile_counts;  // [tile_cap + 1]
+    uint32_t* run_start;    // [2 * run_cap]: run heads, then each run's segment
+    uint32_t* run_end;      // [run_cap]
+    uint32_t* counters;     // [16]
+    uint32_t* runs_seen;    // device counter of runs found by the first detection (or null)
+    uint32_t tile_cap, run_cap;
+};
+
+// Fix-up work lists, one per tier (device lists, device counts).
+struct TierLists {
+    RunItem* small;
+    RunItem* medium;
+    RunItem* large;
+    uint32_t* small_count;
+    uint32_t* medium_count;
+    uint32_t* large_count;
+    uint32_t small_cap, medium_cap, large_cap;
+};
+
+// Find runs (length >= 2) of equal keys inside every segment of sc; when
+// `require_cont` is set a run is kept only if its keys carry the
+// "continues" marker (refinement keys).  Appends each kept run to the tier
+// list chosen by its length, with refinement round `round_of_run` (or, for
+// refinement, the segment item's round + 1 read from `items`).
+// `max_tiles` bounds the tile count over every segment (grid size).
+hipError_t find_runs(const uint64_t* keys, const RadixScratch& seg, const RadixConfig& cfg,
+                     uint32_t max_tiles, int coder, bool refinement, const RunItem* items,
+                     const RunScratch& rs, const TierLists& tl, uint32_t t_small,
+                     uint32_t t_medium, hipStream_t s);
+
+// Zero-fill kernels (graph-capture friendly).
+hipError_t zero_u64(uint64_t* p, size_t n, hipStream_t s);
+hipError_t zero_u32(uint32_t* p, size_t n, hipStream_t s);
+
+// ---- fixup.hip
+struct FixupArgs {
+    int coder;
+    const void* elems;
+    const uint64_t* offsets;  // [n + 1]; offsets[n] is the element total
+    uint32_t n;
+    uint32_t* idx;            // permutation being fixed, in place
+};
+
+hipError_t fixup_small(const FixupArgs& a, const TierLists& tl, uint32_t t_small, hipStream_t s);
+hipError_t fixup_medium(const FixupArgs& a, const TierLists& tl, uint32_t t_medium,
+                        hipStream_t s);
+// Refinement keys for every position of the large-tier segments.
+hipError_t fixup_large_keys(const FixupArgs& a, const RunItem* items, const RadixScratch& seg,
+                            const RadixConfig& cfg, uint32_t max_tiles, uint64_t* keys,
+                            hipStream_t s);
+
+// Chunk geometry of the refinement keys.
+constexpr int ascii_m = 9, ascii_chunk = 7;
+constexpr int utf16_m = 4, utf16_chunk = 3;
+
+}  // namespace husky

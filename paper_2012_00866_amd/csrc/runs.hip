@@ -1,0 +1,240 @@
+// Runs of equal keys after a sort: the only places where inversions can
+// remain when the coder is monotone (Sec. 3.2: x > y never yields a smaller
+// code, so after sorting by code every inversion sits among equal codes).
+// The paper checks for this globally (its "perfect" flag, Algorithm 3, and
+// Sec. 3.4) and then re-sorts everything; here every run of two or more equal
+// keys becomes a work item, and only those are re-sorted.
+//
+// A run is a maximal range of equal keys inside a segment (runs never cross
+// segment boundaries).  Three passes over the tile space of the segments:
+//   k_runs_count  -- per tile, the number of run heads (first member of a
+//                    run of length >= 2);
+//   k_runs_scan   -- exclusive scan of the per-tile counts;
+//   k_runs_write  -- ordered compaction: the k-th head and the k-th tail of
+//                    the whole array belong to the same run;
+// then k_runs_classify turns (head, tail) pairs into work items for the
+// wavefront, workgroup or device-wide tier by run length.
+
+#include "common.h"
+#include "internal.h"
+
+namespace husky {
+
+template <int CODER>
+__device__ __forceinline__ bool continues(uint64_t key) {
+    return (key & 0xFull) == (CODER == 0 ? 8ull : 4ull);
+}
+
+// Flags of position i inside segment [s0, s1): multi-run head / tail.
+template <int CODER, bool REFINE>
+__device__ __forceinline__ void run_flags(const uint64_t* __restrict__ keys, uint32_t i,
+                                          uint32_t s0, uint32_t s1, bool& head, bool& tail) {
+    const uint64_t kc = keys[i];
+    const bool has_prev = i > s0, has_next = i + 1 < s1;
+    const bool eq_prev = has_prev && keys[i - 1] == kc;
+    const bool eq_next = has_next && keys[i + 1] == kc;
+    const bool keep = REFINE ? continues<CODER>(kc) : true;
+    head = keep && !eq_prev && eq_next;
+    tail = keep && eq_prev && !eq_next;
+}
+
+template <int CODER, bool REFINE, int ITEMS>
+__global__ __launch_bounds__(BLOCK) void k_runs_count(const uint64_t* __restrict__ keys,
+                                                      const SegDesc* __restrict__ segs,
+                                                      const uint32_t* __restrict__ counters,
+                                                      uint32_t* __restrict__ tile_counts) {
+    constexpr uint32_t TILE = BLOCK * ITEMS;
+    __shared__ uint32_t s_cnt[NWAVES];
+    const uint32_t t = blockIdx.x;
+    if (t >= counters[C_ALL_TILES]) return;
+    const SegDesc d = segs[find_seg(segs, counters[C_NUM_SEGS], t)];
+    const uint32_t lt = t - d.first_tile;
+    const uint32_t base = d.start + lt * TILE;
+    const uint32_t nvalid = min(TILE, d.len - lt * TILE);
+    const uint32_t w = threadIdx.x / WAVE, lane = lane_id();
+    uint32_t heads = 0;
+#pragma unroll
+    for (int k = 0; k < ITEMS; ++k) {
+        const uint32_t p = w * WAVE * ITEMS + k * WAVE + lane;
+        bool h = false, tl = false;
+        if (p < nvalid) run_flags<CODER, REFINE>(keys, base + p, d.start, d.start + d.len, h, tl);
+        heads += (uint32_t)__popcll(ballot(h));
+    }
+    if (lane == 0) s_cnt[w] = heads;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t tot = 0;
+        for (int i = 0; i < NWAVES; ++i) tot += s_cnt[i];
+        tile_counts[t] = tot;
+    }
+}
+
+// Exclusive scan of tile_counts[0, total) in place (one workgroup); the grand
+// total goes to *num_runs.
+__global__ __launch_bounds__(BLOCK) void k_runs_scan(uint32_t* __restrict__ tile_counts,
+                                                     const uint32_t* __restrict__ counters,
+                                                     uint32_t* __restrict__ num_runs) {
+    __shared__ uint32_t scratch[NWAVES];
+    const uint32_t total = counters[C_ALL_TILES];
+    uint32_t carry = 0;
+    for (uint32_t b = 0; b < total; b += BLOCK) {
+        const uint32_t i = b + threadIdx.x;
+        const uint32_t v = i < total ? tile_counts[i] : 0u;
+        uint32_t tot;
+        const uint32_t ex = block_exclusive_sum(v, scratch, &tot);
+        if (i < total) tile_counts[i] = carry + ex;
+        carry += tot;
+    }
+    if (threadIdx.x == 0) *num_runs = carry;
+}
+
+template <int CODER, bool REFINE, int ITEMS>
+__global__ __launch_bounds__(BLOCK) void k_runs_write(const uint64_t* __restrict__ keys,
+                                                      const SegDesc* __restrict__ segs,
+                                                      const uint32_t* __restrict__ counters,
+                                                      const uint32_t* __restrict__ tile_counts,
+                                                      uint32_t* __restrict__ run_start,
+                                                      uint32_t* __restrict__ run_end,
+                                                      uint32_t* __restrict__ run_seg) {
+    constexpr uint32_t TILE = BLOCK * ITEMS;
+    __shared__ uint32_t s_h[NWAVES], s_t[NWAVES];
+    const uint32_t t = blockIdx.x;
+    if (t >= counters[C_ALL_TILES]) return;
+    const uint32_t sidx = find_seg(segs, counters[C_NUM_SEGS], t);
+    const SegDesc d = segs[sidx];
+    const uint32_t lt = t - d.first_tile;
+    const uint32_t base = d.start + lt * TILE;
+    const uint32_t nvalid = min(TILE, d.len - lt * TILE);
+    const uint32_t w = threadIdx.x / WAVE, lane = lane_id();
+
+    bool hf[ITEMS], tf[ITEMS];
+    uint32_t nh = 0, nt = 0;
+#pragma unroll
+    for (int k = 0; k < ITEMS; ++k) {
+        const uint32_t p = w * WAVE * ITEMS + k * WAVE + lane;
+        hf[k] = tf[k] = false;
+        if (p < nvalid) run_flags<CODER, REFINE>(keys, base + p, d.start, d.start + d.len, hf[k], tf[k]);
+        nh += (uint32_t)__popcll(ballot(hf[k]));
+        nt += (uint32_t)__popcll(ballot(tf[k]));
+    }
+    if (lane == 0) {
+        s_h[w] = nh;
+        s_t[w] = nt;
+    }
+    __syncthreads();
+    uint32_t hb = tile_counts[t], tb;
+    // a run that is open at the tile start had its head in an earlier tile
+    {
+        bool open = false;
+        if (base > d.start) {
+            const uint64_t kc = keys[base];
+            open = keys[base - 1] == kc && (REFINE ? continues<CODER>(kc) : true);
+        }
+        tb = hb - (open ? 1u : 0u);
+    }
+    for (uint32_t i = 0; i < w; ++i) {
+        hb += s_h[i];
+        tb += s_t[i];
+    }
+#pragma unroll
+    for (int k = 0; k < ITEMS; ++k) {
+        const uint64_t bh = ballot(hf[k]), bt = ballot(tf[k]);
+        const uint32_t p = w * WAVE * ITEMS + k * WAVE + lane;
+        if (hf[k]) {
+            const uint32_t o = hb + mbcnt(bh);
+            run_start[o] = base + p;
+            run_seg[o] = sidx;
+        }
+        if (tf[k]) run_end[tb + mbcnt(bt)] = base + p;
+        hb += (uint32_t)__popcll(bh);
+        tb += (uint32_t)__popcll(bt);
+    }
+}
+
+// Append one item to a list with one atomic per wavefront and list.
+__device__ __forceinline__ void wave_append(bool take, const RunItem& it, RunItem* list,
+                                            uint32_t* count, uint32_t cap) {
+    const uint64_t m = ballot(take);
+    if (!m) return;
+    const uint32_t leader = (uint32_t)__ffsll((unsigned long long)m) - 1u;
+    uint32_t base = 0;
+    if (lane_id() == leader) base = atomicAdd(count, (uint32_t)__popcll(m));
+    base = readlane(base, (int)leader);
+    if (take) {
+        const uint32_t o = base + mbcnt(m);
+        if (o < cap) list[o] = it;
+    }
+}
+
+__global__ __launch_bounds__(BLOCK) void k_runs_classify(
+    const uint32_t* __restrict__ run_start, const uint32_t* __restrict__ run_end,
+    const uint32_t* __restrict__ run_seg, const uint32_t* __restrict__ num_runs,
+    const RunItem* __restrict__ items, TierLists tl, uint32_t t_small, uint32_t t_medium,
+    uint32_t* __restrict__ runs_seen) {
+    const uint32_t nr = *num_runs;
+    const uint32_t stride = gridDim.x * BLOCK;
+    // loop bound rounded up to a multiple of the block so whole wavefronts
+    // reach the ballots together
+    const uint32_t lim = (nr + BLOCK - 1) / BLOCK * BLOCK;
+    for (uint32_t r = blockIdx.x * BLOCK + threadIdx.x; r < lim; r += stride) {
+        RunItem it{0, 0, 0, 0};
+        bool ok = r < nr;
+        if (ok) {
+            it.start = run_start[r];
+            it.len = run_end[r] - it.start + 1;
+            it.round = items ? items[run_seg[r]].round + 1 : 0;
+        }
+        wave_append(ok && it.len <= t_small, it, tl.small, tl.small_count, tl.small_cap);
+        wave_append(ok && it.len > t_small && it.len <= t_medium, it, tl.medium, tl.medium_count,
+                    tl.medium_cap);
+        wave_append(ok && it.len > t_medium, it, tl.large, tl.large_count, tl.large_cap);
+    }
+    if (runs_seen && blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(runs_seen, nr);
+}
+
+template <int CODER, bool REFINE, int ITEMS>
+static hipError_t find_runs_impl(const uint64_t* keys, const RadixScratch& seg,
+                                 uint32_t max_tiles, const RunItem* items, const RunScratch& rs,
+                                 const TierLists& tl, uint32_t t_small, uint32_t t_medium,
+                                 hipStream_t s) {
+    if (max_tiles == 0) return hipSuccess;
+    uint32_t* num_runs = rs.counters + 0;
+    hipLaunchKernelGGL((k_runs_count<CODER, REFINE, ITEMS>), dim3(max_tiles), dim3(BLOCK), 0, s,
+                       keys, seg.segs, seg.counters, rs.tile_counts);
+    hipLaunchKernelGGL(k_runs_scan, dim3(1), dim3(BLOCK), 0, s, rs.tile_counts, seg.counters,
+                       num_runs);
+    hipLaunchKernelGGL((k_runs_write<CODER, REFINE, ITEMS>), dim3(max_tiles), dim3(BLOCK), 0, s,
+                       keys, seg.segs, seg.counters, rs.tile_counts, rs.run_start, rs.run_end,
+                       rs.run_start + rs.run_cap);
+    const uint32_t blocks = 512;
+    hipLaunchKernelGGL(k_runs_classify, dim3(blocks), dim3(BLOCK), 0, s, rs.run_start, rs.run_end,
+                       rs.run_start + rs.run_cap, num_runs, REFINE ? items : nullptr, tl,
+                       t_small, t_medium, REFINE ? nullptr : rs.runs_seen);
+    return hipGetLastError();
+}
+
+hipError_t find_runs(const uint64_t* keys, const RadixScratch& seg, const RadixConfig& cfg,
+                     uint32_t max_tiles, int coder, bool refinement, const RunItem* items,
+                     const RunScratch& rs, const TierLists& tl, uint32_t t_small,
+                     uint32_t t_medium, hipStream_t s) {
+#define HUSKY_RUNS_CASE(C, R, I)                                                               \
+    if (coder == C && refinement == R && cfg.items == I)                                       \
+        return find_runs_impl<C, R, I>(keys, seg, max_tiles, items, rs, tl, t_small, t_medium, \
+                                       s);
+    HUSKY_RUNS_CASE(0, false, 16)
+    HUSKY_RUNS_CASE(0, true, 16)
+    HUSKY_RUNS_CASE(1, false, 16)
+    HUSKY_RUNS_CASE(1, true, 16)
+    HUSKY_RUNS_CASE(0, false, 12)
+    HUSKY_RUNS_CASE(0, true, 12)
+    HUSKY_RUNS_CASE(1, false, 12)
+    HUSKY_RUNS_CASE(1, true, 12)
+    HUSKY_RUNS_CASE(0, false, 8)
+    HUSKY_RUNS_CASE(0, true, 8)
+    HUSKY_RUNS_CASE(1, false, 8)
+    HUSKY_RUNS_CASE(1, true, 8)
+#undef HUSKY_RUNS_CASE
+    return hipErrorInvalidValue;
+}
+
+}  // namespace husky
