@@ -157,6 +157,21 @@ husky_status husky_sort_batched(husky_coder coder, const void* elems, const uint
                                 uint32_t* perm, void* ws, size_t ws_bytes,
                                 const husky_tuning* tuning, void* stream);
 
+/* Kernel timing (diagnostics).  husky_profile_begin() starts bracketing
+ * every launch of the library with a pair of HIP events recorded on that
+ * launch's stream; husky_profile_end() waits for them and writes, for each
+ * kernel class c < n_classes, the summed milliseconds ms[c] and the launch
+ * count launches[c] (host arrays), then stops profiling.  Classes:
+ * 0 encode, 1 radix histogram, 2 histogram scan, 3 radix onesweep pass,
+ * 4 radix copy-back, 5 single-tile LDS sort, 6 run detection (all four
+ * kernels), 7 wavefront fix-up, 8 workgroup fix-up, 9 device-wide
+ * refinement keys, 10 segment setup, 11 radix onesweep pass of the
+ * device-wide fix-up (class 3 counts only the sort of the codes).  Not for
+ * use during graph capture.
+ * Returns HUSKY_OK or HUSKY_ERR_HIP. */
+void husky_profile_begin(void);
+int husky_profile_end(double* ms, uint32_t* launches, int n_classes);
+
 /* Static text for a status code (host). */
 const char* husky_status_string(husky_status s);
 

@@ -58,6 +58,8 @@ def _load():
         lib.oracle_sort_batched.argtypes = [i32, i32, vp, vp, vp, u64, vp]
         lib.oracle_check_perm.restype = u64
         lib.oracle_check_perm.argtypes = [i32, vp, vp, u64, vp, vp]
+        lib.oracle_check_perm_batched.restype = u64
+        lib.oracle_check_perm_batched.argtypes = [i32, vp, vp, vp, u64, vp, vp]
         _lib = lib
     return _lib
 
@@ -138,4 +140,17 @@ def check_perm(batch, perm: np.ndarray):
     first = np.zeros(1, dtype=np.uint64)
     bad = lib.oracle_check_perm(batch.elem_bytes, _ptr(elems), _ptr(offsets), batch.n,
                                 _ptr(p if p.size else np.zeros(1, np.uint32)), _ptr(first))
+    return int(bad), int(first[0])
+
+
+def check_perm_batched(batch, perm: np.ndarray):
+    """(violations, first bad position) of a batched permutation, instance by instance."""
+    lib = _load()
+    elems, offsets = _prep(batch)
+    seg = np.ascontiguousarray(batch.seg_offsets, dtype=np.uint64)
+    p = np.ascontiguousarray(perm, dtype=np.uint32)
+    first = np.zeros(1, dtype=np.uint64)
+    bad = lib.oracle_check_perm_batched(batch.elem_bytes, _ptr(elems), _ptr(offsets), _ptr(seg),
+                                        seg.size - 1, _ptr(p if p.size else np.zeros(1, np.uint32)),
+                                        _ptr(first))
     return int(bad), int(first[0])

@@ -212,4 +212,38 @@ uint64_t oracle_check_perm(int elem_bytes, const void* elems, const uint64_t* of
     return bad;
 }
 
+// The same check for the batched form: every instance's slice of perm must
+// be a permutation of its own index range, ordered as above.
+uint64_t oracle_check_perm_batched(int elem_bytes, const void* elems, const uint64_t* offsets,
+                                   const uint64_t* seg_offsets, uint64_t n_segs,
+                                   const uint32_t* perm, uint64_t* first_bad) {
+    uint64_t bad = 0;
+    uint64_t n = seg_offsets[n_segs];
+    *first_bad = n;
+    std::vector<uint8_t> seen(n, 0);
+    for (uint64_t s = 0; s < n_segs; ++s) {
+        uint64_t lo = seg_offsets[s], hi = seg_offsets[s + 1];
+        for (uint64_t k = lo; k < hi; ++k) {
+            uint32_t p = perm[k];
+            bool ok = p >= lo && p < hi && !seen[p];
+            if (ok) seen[p] = 1;
+            if (ok && k + 1 < hi) {
+                uint32_t q = perm[k + 1];
+                if (q >= lo && q < hi) {
+                    bool lt_qp = elem_bytes == 1 ? string_less((const uint8_t*)elems, offsets, q, p)
+                                                 : string_less((const uint16_t*)elems, offsets, q, p);
+                    bool lt_pq = elem_bytes == 1 ? string_less((const uint8_t*)elems, offsets, p, q)
+                                                 : string_less((const uint16_t*)elems, offsets, p, q);
+                    ok = lt_pq || (!lt_qp && p < q);
+                }
+            }
+            if (!ok) {
+                if (bad == 0) *first_bad = k;
+                ++bad;
+            }
+        }
+    }
+    return bad;
+}
+
 }  // extern "C"

@@ -51,7 +51,13 @@ def make_tuning(radix_bits=0, tile_items=0, t_small=0, t_medium=0) -> Tuning:
 _lib = None
 
 EXPORTS = ("husky_workspace_bytes", "husky_encode", "husky_sort_pairs", "husky_fixup",
-           "husky_sort", "husky_sort_batched", "husky_status_string")
+           "husky_sort", "husky_sort_batched", "husky_profile_begin", "husky_profile_end",
+           "husky_status_string")
+
+# kernel classes of husky_profile_end (include/husky.h)
+PROFILE_CLASSES = ("encode", "radix_hist", "radix_hist_scan", "radix_onesweep", "radix_copy_back",
+                   "tile_sort", "runs", "fixup_small", "fixup_medium", "large_keys", "segment_setup",
+                   "radix_onesweep_fixup")
 
 
 def load(path: str = LIB_PATH):
@@ -76,6 +82,10 @@ def load(path: str = LIB_PATH):
     lib.husky_sort.argtypes = [i32, vp, vp, u64, vp, vp, sz, tp, vp]
     lib.husky_sort_batched.restype = i32
     lib.husky_sort_batched.argtypes = [i32, vp, vp, u64, vp, u64, vp, vp, sz, tp, vp]
+    lib.husky_profile_begin.restype = None
+    lib.husky_profile_begin.argtypes = []
+    lib.husky_profile_end.restype = i32
+    lib.husky_profile_end.argtypes = [vp, vp, i32]
     lib.husky_status_string.restype = ctypes.c_char_p
     lib.husky_status_string.argtypes = [i32]
     _lib = lib
@@ -221,6 +231,20 @@ def sort_batched(elems, offsets, seg_offsets, coder="ascii7", tuning: Optional[T
         if st["domain_violations"]:
             raise DomainError(2, f"husky_sort_batched ({st['domain_violations']} strings)")
     return perm[:n]
+
+
+def profile_begin():
+    """Start per-launch HIP-event timing of every library kernel."""
+    load().husky_profile_begin()
+
+
+def profile_end() -> dict:
+    """Stop timing; {class: (total_ms, launches)} summed since profile_begin."""
+    k = len(PROFILE_CLASSES)
+    ms = np.zeros(k, dtype=np.float64)
+    cnt = np.zeros(k, dtype=np.uint32)
+    _check(load().husky_profile_end(ms.ctypes.data, cnt.ctypes.data, k), "husky_profile_end")
+    return {c: (float(ms[i]), int(cnt[i])) for i, c in enumerate(PROFILE_CLASSES)}
 
 
 def status_string(code: int) -> str:

@@ -190,7 +190,7 @@ husky_status run_fixup(Ctx& c, const Tune& tn, int coder, const void* elems,
         const uint32_t tl = tiles_bound(n, nl, tn.rc);
         HUSKY_TRY(fixup_large_keys(fa, cur, c.rad, tn.rc, tl, keys, s));
         HUSKY_TRY(radix_sort_segments(keys, idx, keys_alt, c.at<uint32_t>(c.L.idx_b), 0, 64, nl, tl,
-                                      c.rad, tn.rc, s));
+                                      c.rad, tn.rc, P_ONESWEEP_FIX, s));
         TierLists t2 = c.tiers;
         t2.large = nxt;
         t2.large_count = nxt_cnt;
@@ -251,7 +251,8 @@ husky_status husky_sort_pairs(uint64_t* codes, uint32_t* idx, uint64_t n, int be
     Ctx c = make_ctx(ws, n, 1);
     HUSKY_TRY(radix_segments_single((uint32_t)n, c.rad, tn.rc, s));
     HUSKY_TRY(radix_sort_segments(codes, idx, c.at<uint64_t>(c.L.codes_b), c.at<uint32_t>(c.L.idx_b),
-                                  begin_bit, end_bit, 1, tiles_bound(n, 1, tn.rc), c.rad, tn.rc, s));
+                                  begin_bit, end_bit, 1, tiles_bound(n, 1, tn.rc), c.rad, tn.rc,
+                                  P_ONESWEEP, s));
     return HUSKY_OK;
 }
 
@@ -307,7 +308,8 @@ static husky_status sort_common(husky_coder coder, const void* elems, const uint
         HUSKY_TRY(radix_segments_single((uint32_t)n, c.rad, tn.rc, s));
     const int end_bit = coder == HUSKY_CODER_ASCII7 ? 63 : 64;
     HUSKY_TRY(radix_sort_segments(codes, perm, codes_b, c.at<uint32_t>(c.L.idx_b), 0, end_bit,
-                                  (uint32_t)n_segs, tiles_bound(n, n_segs, tn.rc), c.rad, tn.rc, s));
+                                  (uint32_t)n_segs, tiles_bound(n, n_segs, tn.rc), c.rad, tn.rc,
+                                  P_ONESWEEP, s));
     // the sorted codes are not needed once the runs are listed, so the
     // device-wide fix-up reuses both code buffers for its keys
     return run_fixup(c, tn, coder, elems, offsets, n, n_segs, codes, codes, codes_b, perm, s);

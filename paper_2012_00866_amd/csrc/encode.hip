@@ -92,6 +92,7 @@ hipError_t launch_encode(int coder, const void* elems, const uint64_t* offsets, 
                          uint64_t* codes, uint32_t* idx, uint32_t* status, hipStream_t s) {
     if (n == 0) return hipSuccess;
     const uint32_t blocks = (n + BLOCK - 1) / BLOCK;
+    ProfScope ps(P_ENCODE, s);
     if (coder == 0)
         hipLaunchKernelGGL(k_encode<0>, dim3(blocks), dim3(BLOCK), 0, s, (const uint8_t*)elems,
                            offsets, n, codes, idx, status);

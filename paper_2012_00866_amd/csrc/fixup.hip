@@ -174,8 +174,14 @@ __global__ __launch_bounds__(BLOCK) void k_fix_medium(const RunItem* __restrict_
                                     : 0ull;
             }
             __syncthreads();
+            // already in (group, key, position) order -- e.g. a run of
+            // identical strings -- needs no sort
+            bool unsorted = false;
+            for (uint32_t q = tid + 1; q < L; q += BLOCK)
+                unsorted = unsorted || gjk_less(S.gj[q], S.key[q], S.gj[q - 1], S.key[q - 1]);
+            const bool need_sort = __syncthreads_or(unsorted);
             // bitonic sort of (group, key, position) over L2 slots
-            for (uint32_t k = 2; k <= L2; k <<= 1) {
+            for (uint32_t k = 2; need_sort && k <= L2; k <<= 1) {
                 for (uint32_t jj = k >> 1; jj > 0; jj >>= 1) {
                     for (uint32_t i = tid; i < L2 / 2; i += BLOCK) {
                         const uint32_t lo = 2 * i - (i & (jj - 1));
@@ -283,6 +289,7 @@ static uint32_t persistent_blocks() {
 
 hipError_t fixup_small(const FixupArgs& a, const TierLists& tl, uint32_t, hipStream_t s) {
     const uint32_t blocks = persistent_blocks() * 8;
+    ProfScope ps(P_FIX_SMALL, s);
     if (a.coder == 0)
         hipLaunchKernelGGL(k_fix_small<0>, dim3(blocks), dim3(BLOCK), 0, s, tl.small, tl.small_count,
                            tl.small_cap, (const uint8_t*)a.elems, a.offsets, a.n, a.idx);
@@ -304,6 +311,7 @@ static hipError_t medium_impl(const FixupArgs& a, const TierLists& tl, hipStream
     }
     const uint32_t per_cu = lds > 80 * 1024 ? 1 : (lds > 52 * 1024 ? 2 : 3);
     const uint32_t blocks = persistent_blocks() * per_cu;
+    ProfScope ps(P_FIX_MEDIUM, s);
     hipLaunchKernelGGL((k_fix_medium<CODER, MAXL>), dim3(blocks), dim3(BLOCK), lds, s, tl.medium,
                        tl.medium_count, tl.medium_cap, (const uint8_t*)a.elems, a.offsets, a.n,
                        a.idx);
@@ -326,6 +334,7 @@ hipError_t fixup_large_keys(const FixupArgs& a, const RunItem* items, const Radi
                             const RadixConfig& cfg, uint32_t max_tiles, uint64_t* keys,
                             hipStream_t s) {
     if (!max_tiles) return hipSuccess;
+    ProfScope ps(P_LARGE_KEYS, s);
 #define HUSKY_LK(C, I)                                                                       \
     if (a.coder == C && cfg.items == I) {                                                    \
         hipLaunchKernelGGL((k_large_keys<C, I>), dim3(max_tiles), dim3(BLOCK), 0, s, items,  \

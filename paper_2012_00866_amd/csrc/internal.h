@@ -9,6 +9,23 @@
 
 namespace husky {
 
+// ---- profile.hip: per-launch HIP-event timing, off unless husky_profile_begin ran
+enum ProfClass {
+    P_ENCODE = 0, P_HIST = 1, P_HIST_SCAN = 2, P_ONESWEEP = 3, P_COPY_BACK = 4, P_TILE_SORT = 5,
+    P_RUNS = 6, P_FIX_SMALL = 7, P_FIX_MEDIUM = 8, P_LARGE_KEYS = 9, P_SETUP = 10,
+    P_ONESWEEP_FIX = 11, P_NUM = 12
+};
+bool prof_on();
+class ProfScope {
+  public:
+    ProfScope(int cls, hipStream_t s);
+    ~ProfScope();
+  private:
+    int cls_;
+    hipStream_t s_;
+    int idx_;
+};
+
 // ---- encode.hip
 hipError_t launch_encode(int coder, const void* elems, const uint64_t* offsets, uint32_t n,
                          uint64_t* codes, uint32_t* idx, uint32_t* status, hipStream_t s);
@@ -48,7 +65,7 @@ hipError_t radix_segments_from_items(const RunItem* items, const uint32_t* count
 hipError_t radix_sort_segments(uint64_t* keys, uint32_t* vals, uint64_t* keys_alt,
                                uint32_t* vals_alt, int begin_bit, int end_bit,
                                uint32_t max_segs, uint32_t max_tiles, const RadixScratch& sc,
-                               const RadixConfig& cfg, hipStream_t s);
+                               const RadixConfig& cfg, int pclass, hipStream_t s);
 
 // ---- runs.hip
 struct RunScratch {

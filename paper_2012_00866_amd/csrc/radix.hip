@@ -121,6 +121,7 @@ hipError_t radix_segments_from_offsets(const uint64_t* seg_offsets, uint32_t n_s
                                        const RadixScratch& sc, const RadixConfig& cfg,
                                        hipStream_t s) {
     SrcOffsets src{seg_offsets, n_segs};
+    ProfScope ps(P_SETUP, s);
     hipLaunchKernelGGL(k_seg_setup<SrcOffsets>, dim3(1), dim3(BLOCK), 0, s, src, sc.segs,
                        bigs_of(sc), sc.counters, (uint32_t)cfg.tile());
     return hipGetLastError();
@@ -128,6 +129,7 @@ hipError_t radix_segments_from_offsets(const uint64_t* seg_offsets, uint32_t n_s
 hipError_t radix_segments_single(uint32_t n, const RadixScratch& sc, const RadixConfig& cfg,
                                  hipStream_t s) {
     SrcSingle src{n};
+    ProfScope ps(P_SETUP, s);
     hipLaunchKernelGGL(k_seg_setup<SrcSingle>, dim3(1), dim3(BLOCK), 0, s, src, sc.segs,
                        bigs_of(sc), sc.counters, (uint32_t)cfg.tile());
     return hipGetLastError();
@@ -136,6 +138,7 @@ hipError_t radix_segments_from_items(const RunItem* items, const uint32_t* count
                                      uint32_t max_items, const RadixScratch& sc,
                                      const RadixConfig& cfg, hipStream_t s) {
     SrcItems src{items, count, max_items};
+    ProfScope ps(P_SETUP, s);
     hipLaunchKernelGGL(k_seg_setup<SrcItems>, dim3(1), dim3(BLOCK), 0, s, src, sc.segs,
                        bigs_of(sc), sc.counters, (uint32_t)cfg.tile());
     return hipGetLastError();
@@ -153,23 +156,35 @@ __global__ __launch_bounds__(BLOCK) void k_hist(const uint64_t* __restrict__ key
                                                 uint32_t G, int begin_bit, int end_bit,
                                                 int npasses) {
     constexpr int R = 1 << BITS;
-    __shared__ uint32_t s_h[MAX_PASSES * R];
+    constexpr int ROW = MAX_PASSES * R;
+    // one row of counters per wavefront keeps the LDS atomics of different
+    // wavefronts apart; a wavefront whose 64 digits agree adds 64 once
+    __shared__ uint32_t s_h[NWAVES * ROW];
     const uint32_t total = counters[C_BIG_TILES], nb = counters[C_NUM_BIG];
     const uint32_t t0 = blockIdx.x * G;
     if (t0 >= total) return;
     const uint32_t t1 = min(total, t0 + G);
-    for (uint32_t i = threadIdx.x; i < (uint32_t)(npasses * R); i += BLOCK) s_h[i] = 0;
+    const uint32_t w = threadIdx.x / WAVE, lane = lane_id();
+    uint32_t* my = s_h + w * ROW;
+    for (uint32_t i = threadIdx.x; i < (uint32_t)(NWAVES * ROW); i += BLOCK) s_h[i] = 0;
     uint32_t b = find_seg(bigs, nb, t0);
     SegDesc d = bigs[b];
     __syncthreads();
+    auto flush = [&](uint32_t seg) {
+        for (uint32_t i = threadIdx.x; i < (uint32_t)(npasses * R); i += BLOCK) {
+            uint32_t v = 0;
+#pragma unroll
+            for (int ww = 0; ww < NWAVES; ++ww) {
+                v += s_h[ww * ROW + i];
+                s_h[ww * ROW + i] = 0;
+            }
+            if (v) atomicAdd(&hist[(size_t)seg * MAX_PASSES * 256 + (i / R) * 256 + (i % R)], v);
+        }
+    };
     for (uint32_t t = t0; t < t1; ++t) {
         if (b + 1 < nb && bigs[b + 1].first_tile <= t) {
-            // segment changes: flush the previous one
-            for (uint32_t i = threadIdx.x; i < (uint32_t)(npasses * R); i += BLOCK) {
-                uint32_t v = s_h[i];
-                if (v) atomicAdd(&hist[(size_t)b * MAX_PASSES * 256 + (i / R) * 256 + (i % R)], v);
-                s_h[i] = 0;
-            }
+            __syncthreads();
+            flush(b);  // segment changes
             ++b;
             d = bigs[b];
             __syncthreads();
@@ -177,21 +192,28 @@ __global__ __launch_bounds__(BLOCK) void k_hist(const uint64_t* __restrict__ key
         const uint32_t lt = t - d.first_tile;
         const uint32_t pos0 = d.start + lt * tile;
         const uint32_t cnt = min(tile, d.len - lt * tile);
-        for (uint32_t i = threadIdx.x; i < cnt; i += BLOCK) {
-            const uint64_t k = keys[pos0 + i];
+        // whole wavefronts walk the tile so that ballots see all 64 lanes
+        for (uint32_t i0 = w * WAVE; i0 < cnt; i0 += BLOCK) {
+            const uint32_t i = i0 + lane;
+            const bool ok = i < cnt;
+            const uint64_t k = ok ? keys[pos0 + i] : 0ull;
+            const bool full = ballot(ok) == ~0ull;
             for (int p = 0; p < npasses; ++p) {
                 const int sh = begin_bit + p * BITS;
                 const int wd = min(BITS, end_bit - sh);
                 const uint32_t dg = (uint32_t)(k >> sh) & ((1u << wd) - 1u);
-                atomicAdd(&s_h[p * R + dg], 1u);
+                const uint32_t d0 = readlane(dg, 0);
+                if (full && ballot(dg == d0) == ~0ull) {
+                    if (lane == 0) my[p * R + d0] += WAVE;
+                } else if (ok) {
+                    atomicAdd(&my[p * R + dg], 1u);
+                }
             }
         }
         __syncthreads();
     }
-    for (uint32_t i = threadIdx.x; i < (uint32_t)(npasses * R); i += BLOCK) {
-        uint32_t v = s_h[i];
-        if (v) atomicAdd(&hist[(size_t)b * MAX_PASSES * 256 + (i / R) * 256 + (i % R)], v);
-    }
+    __syncthreads();
+    flush(b);
 }
 
 // Exclusive scan of every pass's counts of one big segment (in place) and
@@ -235,24 +257,35 @@ __device__ __forceinline__ void rank_tile(const uint64_t (&keys)[ITEMS], int shi
     const uint32_t tid = threadIdx.x, w = tid / WAVE, lane = lane_id();
     for (uint32_t i = tid; i < (uint32_t)(NWAVES * R); i += BLOCK) s_whist[i] = 0;
     __syncthreads();
-    volatile uint32_t* wh = s_whist + w * R;
+    // Each wavefront owns one histogram row.  Within an iteration every lane
+    // reads its digit's count before the one lane per digit updates it; LDS
+    // operations of one wavefront complete in order, and the empty asm with a
+    // memory clobber keeps the compiler from reusing a count across
+    // iterations.
+    uint32_t* wh = s_whist + w * R;
     uint32_t rank[ITEMS], dig[ITEMS];
 #pragma unroll
     for (int k = 0; k < ITEMS; ++k) {
         const uint32_t p = w * WAVE * ITEMS + k * WAVE + lane;
         const uint32_t d = p < nvalid ? ((uint32_t)(keys[k] >> shift) & dmask) : (uint32_t)(R - 1);
         dig[k] = d;
-        uint64_t peers = ~0ull;
+        // lanes holding the same digit: for every digit bit keep the lanes
+        // whose bit agrees (ballot, inverted where this lane's bit is 0)
+        uint32_t plo = ~0u, phi = ~0u;
 #pragma unroll
         for (int b = 0; b < BITS; ++b) {
-            const bool bit = (d >> b) & 1u;
-            const uint64_t bal = ballot(bit);
-            peers &= bit ? bal : ~bal;
+            const uint32_t bit = (d >> b) & 1u;
+            const uint64_t bal = ballot(bit != 0);
+            const uint32_t flip = bit - 1u;  // 0 when set, all ones when clear
+            plo &= (uint32_t)bal ^ flip;
+            phi &= (uint32_t)(bal >> 32) ^ flip;
         }
-        const uint32_t below = mbcnt(peers);
-        const uint32_t cnt = (uint32_t)__popcll(peers);
+        const uint32_t below = __builtin_amdgcn_mbcnt_hi(phi, __builtin_amdgcn_mbcnt_lo(plo, 0u));
+        const uint32_t cnt = (uint32_t)__popc(plo) + (uint32_t)__popc(phi);
         const uint32_t base = wh[d];
+        __asm__ volatile("" ::: "memory");
         if (below == cnt - 1) wh[d] = base + cnt;
+        __asm__ volatile("" ::: "memory");
         rank[k] = base + below;
     }
     __syncthreads();
@@ -314,10 +347,13 @@ __global__ __launch_bounds__(BLOCK) void k_onesweep(
     __shared__ uint32_t s_tile;
 
     const uint32_t tid = threadIdx.x;
+    // workgroups beyond the tile count leave before taking a tile id, so the
+    // ids handed out are exactly 0 .. tiles-1
+    const uint32_t n_tiles = counters[C_BIG_TILES];
+    if (blockIdx.x >= n_tiles) return;
     if (tid == 0) s_tile = atomicAdd(&counters[C_TILE0 + pass], 1u);
     __syncthreads();
     const uint32_t tile = s_tile;
-    if (tile >= counters[C_BIG_TILES]) return;
     const uint32_t b = find_seg(bigs, counters[C_NUM_BIG], tile);
     const SegDesc d = bigs[b];
     const uint32_t exec = d.aux;
@@ -523,14 +559,17 @@ hipError_t zero_u32(uint32_t* p, size_t n, hipStream_t s) {
 template <int BITS, int ITEMS>
 static hipError_t sort_impl(uint64_t* keys, uint32_t* vals, uint64_t* keys_alt,
                             uint32_t* vals_alt, int begin_bit, int end_bit, uint32_t max_segs,
-                            uint32_t max_tiles, const RadixScratch& sc, hipStream_t s) {
+                            uint32_t max_tiles, const RadixScratch& sc, int pclass,
+                            hipStream_t s) {
     constexpr uint32_t TILE = BLOCK * ITEMS;
     const int npasses = (end_bit - begin_bit + BITS - 1) / BITS;
     SegDesc* bigs = bigs_of(sc);
     // single-tile segments
-    if (max_segs)
+    if (max_segs) {
+        ProfScope ps(P_TILE_SORT, s);
         hipLaunchKernelGGL((k_tile_sort<BITS, ITEMS>), dim3(max_segs), dim3(BLOCK), 0, s, keys,
                            vals, sc.segs, sc.counters, begin_bit, end_bit);
+    }
     if (max_tiles == 0) return hipGetLastError();
     // big segments
     // every multi-tile segment spans two or more tiles, and there are at most
@@ -543,17 +582,25 @@ static hipError_t sort_impl(uint64_t* keys, uint32_t* vals, uint64_t* keys_alt,
     e = zero_u32(sc.counters + C_TILE0, MAX_PASSES, s);
     if (e != hipSuccess) return e;
     const uint32_t G = 8;
-    hipLaunchKernelGGL((k_hist<BITS>), dim3((max_tiles + G - 1) / G), dim3(BLOCK), 0, s, keys,
-                       bigs, sc.counters, sc.hist, TILE, G, begin_bit, end_bit, npasses);
-    hipLaunchKernelGGL((k_hist_scan<BITS>), dim3(max_big), dim3(BLOCK), 0, s, bigs, sc.counters,
-                       sc.hist, npasses);
+    {
+        ProfScope ps(P_HIST, s);
+        hipLaunchKernelGGL((k_hist<BITS>), dim3((max_tiles + G - 1) / G), dim3(BLOCK), 0, s, keys,
+                           bigs, sc.counters, sc.hist, TILE, G, begin_bit, end_bit, npasses);
+    }
+    {
+        ProfScope ps(P_HIST_SCAN, s);
+        hipLaunchKernelGGL((k_hist_scan<BITS>), dim3(max_big), dim3(BLOCK), 0, s, bigs,
+                           sc.counters, sc.hist, npasses);
+    }
     for (int p = 0; p < npasses; ++p) {
         const int shift = begin_bit + p * BITS;
         const uint32_t dmask = (1u << min(BITS, end_bit - shift)) - 1u;  // top digit may be narrower
+        ProfScope ps(pclass, s);
         hipLaunchKernelGGL((k_onesweep<BITS, ITEMS>), dim3(max_tiles), dim3(BLOCK), 0, s, keys,
                            vals, keys_alt, vals_alt, bigs, sc.counters, sc.hist, sc.status, p,
                            shift, dmask);
     }
+    ProfScope ps(P_COPY_BACK, s);
     hipLaunchKernelGGL(k_copy_back, dim3(max_tiles), dim3(BLOCK), 0, s, keys, vals, keys_alt,
                        vals_alt, bigs, sc.counters, TILE);
     return hipGetLastError();
@@ -562,11 +609,11 @@ static hipError_t sort_impl(uint64_t* keys, uint32_t* vals, uint64_t* keys_alt,
 hipError_t radix_sort_segments(uint64_t* keys, uint32_t* vals, uint64_t* keys_alt,
                                uint32_t* vals_alt, int begin_bit, int end_bit,
                                uint32_t max_segs, uint32_t max_tiles, const RadixScratch& sc,
-                               const RadixConfig& cfg, hipStream_t s) {
+                               const RadixConfig& cfg, int pclass, hipStream_t s) {
 #define HUSKY_SORT_CASE(B, I)                                                                 \
     if (cfg.bits == B && cfg.items == I)                                                      \
         return sort_impl<B, I>(keys, vals, keys_alt, vals_alt, begin_bit, end_bit, max_segs, \
-                               max_tiles, sc, s);
+                               max_tiles, sc, pclass, s);
     HUSKY_SORT_CASE(8, 16)
     HUSKY_SORT_CASE(8, 12)
     HUSKY_SORT_CASE(8, 8)

@@ -199,6 +199,7 @@ static hipError_t find_runs_impl(const uint64_t* keys, const RadixScratch& seg,
                                  hipStream_t s) {
     if (max_tiles == 0) return hipSuccess;
     uint32_t* num_runs = rs.counters + 0;
+    ProfScope ps(P_RUNS, s);
     hipLaunchKernelGGL((k_runs_count<CODER, REFINE, ITEMS>), dim3(max_tiles), dim3(BLOCK), 0, s,
                        keys, seg.segs, seg.counters, rs.tile_counts);
     hipLaunchKernelGGL(k_runs_scan, dim3(1), dim3(BLOCK), 0, s, rs.tile_counts, seg.counters,

@@ -219,3 +219,16 @@ def test_empty_and_single():
         b = from_strings(strs)
         perm, _ = oracle.sort(b)
         np.testing.assert_array_equal(perm, _brute(b))
+
+
+def test_check_perm_batched_detects_errors():
+    b = config4(n_inst=10, lo=1, hi=500)
+    perm, _ = oracle.sort_batched(b)
+    assert oracle.check_perm_batched(b, perm)[0] == 0
+    bad = perm.copy()
+    lo = int(b.seg_offsets[3])
+    bad[[lo, lo + 1]] = bad[[lo + 1, lo]]
+    assert oracle.check_perm_batched(b, bad)[0] > 0
+    # a global sort is not a per-instance sort
+    glob, _ = oracle.sort(b)
+    assert oracle.check_perm_batched(b, glob)[0] > 0
