@@ -22,9 +22,10 @@ size_t align_up(size_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
 
 // Byte offsets of every region inside the caller's workspace.
 struct Layout {
-    size_t status, counters, codes_a, codes_b, idx_b, segs, hist, lookback, tile_counts,
-        run_start, run_end, small, medium, large_a, large_b, total;
-    uint32_t seg_cap, big_cap, tile_cap, lookback_cap, run_cap, small_cap, medium_cap, large_cap;
+    size_t status, counters, codes_a, codes_b, idx_b, key0, segs, bigs, korand, binstart, cnt, gtot,
+        tile_counts, run_start, run_end, small, medium, large_a, large_b, total;
+    uint32_t seg_cap, big_cap, tile_cap, big_tile_cap, group_cap, run_cap, small_cap, medium_cap,
+        large_cap;
 };
 
 Layout make_layout(uint64_t n, uint64_t n_segs) {
@@ -37,7 +38,8 @@ Layout make_layout(uint64_t n, uint64_t n_segs) {
     L.tile_cap = (uint32_t)(n / MIN_TILE + L.seg_cap + 2);
     // multi-tile segments hold more than one tile (>= MIN_TILE positions) each
     L.big_cap = (uint32_t)(n / MIN_TILE + 2);
-    L.lookback_cap = 2 * L.big_cap;  // tiles over multi-tile segments
+    L.big_tile_cap = 2 * L.big_cap;
+    L.group_cap = L.big_tile_cap / GROUP_TILES + L.big_cap + 2;
     L.run_cap = (uint32_t)(n / 2 + 1);
     L.small_cap = L.run_cap;
     L.medium_cap = (uint32_t)(n / 3 + 1);
@@ -52,9 +54,13 @@ Layout make_layout(uint64_t n, uint64_t n_segs) {
     L.codes_a = take(n * 8);
     L.codes_b = take(n * 8);
     L.idx_b = take(n * 4);
-    L.segs = take((size_t)(L.seg_cap + L.big_cap) * sizeof(SegDesc));
-    L.hist = take((size_t)L.big_cap * MAX_PASSES * 256 * 4);
-    L.lookback = take((size_t)L.lookback_cap * 256 * 8);
+    L.key0 = take(n * 8);
+    L.segs = take((size_t)L.seg_cap * sizeof(SegDesc));
+    L.bigs = take((size_t)L.big_cap * sizeof(BigDesc));
+    L.korand = take((size_t)L.big_tile_cap * 16);
+    L.binstart = take((size_t)L.big_cap * 256 * 4);
+    L.cnt = take((size_t)L.big_tile_cap * 256 * 4);
+    L.gtot = take((size_t)L.group_cap * 256 * 4);
     L.tile_counts = take((size_t)(L.tile_cap + 1) * 4);
     L.run_start = take((size_t)L.run_cap * 2 * 4);
     L.run_end = take((size_t)L.run_cap * 4);
@@ -67,8 +73,10 @@ Layout make_layout(uint64_t n, uint64_t n_segs) {
 }
 
 // counters region: [0, 64) radix counters; [64, 80) run counters;
-// [80] small count, [81] medium count, [82] large A count, [83] large B count
-constexpr int CNT_RUNS = 64, CNT_SMALL = 80, CNT_MEDIUM = 81, CNT_LARGE_A = 82, CNT_LARGE_B = 83;
+// [80] small count, [81] medium count; [84, 88) and [88, 92) the two
+// device-wide lists: item count, items longer than one tile, their tiles,
+// tiles of all items
+constexpr int CNT_RUNS = 64, CNT_SMALL = 80, CNT_MEDIUM = 81, CNT_LARGE_A = 84, CNT_LARGE_B = 88;
 
 struct Ctx {
     Layout L;
@@ -91,13 +99,16 @@ Ctx make_ctx(void* ws, uint64_t n, uint64_t n_segs) {
     c.status = c.at<husky_device_status>(c.L.status);
     c.counters = c.at<uint32_t>(c.L.counters);
     c.rad.segs = c.at<SegDesc>(c.L.segs);
-    c.rad.hist = c.at<uint32_t>(c.L.hist);
-    c.rad.status = c.at<uint64_t>(c.L.lookback);
+    c.rad.bigs = c.at<BigDesc>(c.L.bigs);
+    c.rad.korand = c.at<uint64_t>(c.L.korand);
+    c.rad.binstart = c.at<uint32_t>(c.L.binstart);
+    c.rad.cnt = c.at<uint32_t>(c.L.cnt);
+    c.rad.gtot = c.at<uint32_t>(c.L.gtot);
     c.rad.counters = c.counters;
     c.rad.seg_cap = c.L.seg_cap;
     c.rad.big_cap = c.L.big_cap;
-    c.rad.tile_cap = c.L.tile_cap;
-    c.rad.lookback_cap = c.L.lookback_cap;
+    c.rad.big_tile_cap = c.L.big_tile_cap;
+    c.rad.group_cap = c.L.group_cap;
     c.runs.tile_counts = c.at<uint32_t>(c.L.tile_counts);
     c.runs.run_start = c.at<uint32_t>(c.L.run_start);
     c.runs.run_end = c.at<uint32_t>(c.L.run_end);
@@ -173,33 +184,44 @@ husky_status run_fixup(Ctx& c, const Tune& tn, int coder, const void* elems,
                        const uint64_t* offsets, uint64_t n, uint64_t n_segs,
                        const uint64_t* codes, uint64_t* keys, uint64_t* keys_alt, uint32_t* idx,
                        hipStream_t s) {
-    HUSKY_TRY(zero_u32(c.counters + CNT_SMALL, 4, s));
+    HUSKY_TRY(zero_u32(c.counters + CNT_SMALL, 12, s));
     const uint32_t tb = tiles_bound(n, n_segs, tn.rc);
     HUSKY_TRY(find_runs(codes, c.rad, tn.rc, tb, coder, false, nullptr, c.runs, c.tiers,
                         tn.t_small, tn.t_medium, s));
-    FixupArgs fa{coder, elems, offsets, (uint32_t)n, idx};
-    uint32_t nl = 0, rounds = 0;
-    HUSKY_TRY(read_u32(c.counters + CNT_LARGE_A, &nl, s));
+    FixupArgs fa{coder, elems, offsets, (uint32_t)n, idx, c.at<uint64_t>(c.L.key0)};
+    uint32_t rounds = 0;
     RunItem* cur = c.at<RunItem>(c.L.large_a);
     RunItem* nxt = c.at<RunItem>(c.L.large_b);
     uint32_t* cur_cnt = c.counters + CNT_LARGE_A;
     uint32_t* nxt_cnt = c.counters + CNT_LARGE_B;
-    while (nl > 0) {
-        nl = std::min(nl, c.L.large_cap);
+    for (;;) {
+        // items, items longer than one tile, their tiles, all their tiles
+        uint32_t st[4];
+        HUSKY_TRY(hipMemcpyAsync(st, cur_cnt, sizeof(st), hipMemcpyDeviceToHost, s));
+        HUSKY_TRY(hipStreamSynchronize(s));
+        const uint32_t nl = std::min(st[0], c.L.large_cap);
+        if (nl == 0) break;
         HUSKY_TRY(radix_segments_from_items(cur, cur_cnt, c.L.large_cap, c.rad, tn.rc, s));
-        const uint32_t tl = tiles_bound(n, nl, tn.rc);
-        HUSKY_TRY(fixup_large_keys(fa, cur, c.rad, tn.rc, tl, keys, s));
-        HUSKY_TRY(radix_sort_segments(keys, idx, keys_alt, c.at<uint32_t>(c.L.idx_b), 0, 64, nl, tl,
-                                      c.rad, tn.rc, P_ONESWEEP_FIX, s));
+        const uint32_t all_tiles = st[3] + 1, big_tiles = st[1] ? st[2] + 1 : 0;
+        HUSKY_TRY(fixup_large_keys(fa, cur, c.rad, tn.rc, all_tiles, keys, s));
+        uint32_t pass_union = 0;
+        if (big_tiles) {
+            HUSKY_TRY(radix_reduce_tiles(keys, big_tiles, c.rad, tn.rc, s));
+            HUSKY_TRY(radix_exec_masks(0, 64, nl, big_tiles, c.rad, tn.rc, s));
+            // the digit passes any group needs: refinement keys hold long
+            // constant stretches, so passes nobody runs are not launched
+            HUSKY_TRY(read_u32(c.counters + C_EXEC_UNION, &pass_union, s));
+        }
+        HUSKY_TRY(radix_sort_segments(keys, idx, keys_alt, c.at<uint32_t>(c.L.idx_b), 0, 64, nl,
+                                      big_tiles, pass_union, c.rad, tn.rc, P_ONESWEEP_FIX, s));
         TierLists t2 = c.tiers;
         t2.large = nxt;
         t2.large_count = nxt_cnt;
-        HUSKY_TRY(zero_u32(nxt_cnt, 1, s));
-        HUSKY_TRY(find_runs(keys, c.rad, tn.rc, tl, coder, true, cur, c.runs, t2, tn.t_small,
-                            tn.t_medium, s));
+        HUSKY_TRY(zero_u32(nxt_cnt, 4, s));
+        HUSKY_TRY(find_runs(keys, c.rad, tn.rc, all_tiles, coder, true, cur, c.runs, t2,
+                            tn.t_small, tn.t_medium, s));
         std::swap(cur, nxt);
         std::swap(cur_cnt, nxt_cnt);
-        HUSKY_TRY(read_u32(cur_cnt, &nl, s));
         ++rounds;
     }
     HUSKY_TRY(fixup_medium(fa, c.tiers, tn.t_medium, s));
@@ -231,7 +253,7 @@ husky_status husky_encode(husky_coder coder, const void* elems, const uint64_t* 
     husky_status st = check_common(coder, elems, offsets, n);
     if (st != HUSKY_OK) return st;
     if (n > 0 && !codes) return HUSKY_ERR_ARG;
-    return hip_status(launch_encode(coder, elems, offsets, (uint32_t)n, codes, idx_or_null, status,
+    return hip_status(launch_encode(coder, elems, offsets, (uint32_t)n, codes, idx_or_null, nullptr, status,
                                     (hipStream_t)stream));
 }
 
@@ -250,9 +272,11 @@ husky_status husky_sort_pairs(uint64_t* codes, uint32_t* idx, uint64_t n, int be
     hipStream_t s = (hipStream_t)stream;
     Ctx c = make_ctx(ws, n, 1);
     HUSKY_TRY(radix_segments_single((uint32_t)n, c.rad, tn.rc, s));
+    const uint32_t tb = tiles_bound(n, 1, tn.rc);
+    HUSKY_TRY(radix_reduce_tiles(codes, tb, c.rad, tn.rc, s));
+    HUSKY_TRY(radix_exec_masks(begin_bit, end_bit, 1, tb, c.rad, tn.rc, s));
     HUSKY_TRY(radix_sort_segments(codes, idx, c.at<uint64_t>(c.L.codes_b), c.at<uint32_t>(c.L.idx_b),
-                                  begin_bit, end_bit, 1, tiles_bound(n, 1, tn.rc), c.rad, tn.rc,
-                                  P_ONESWEEP, s));
+                                  begin_bit, end_bit, 1, tb, ~0u, c.rad, tn.rc, P_ONESWEEP, s));
     return HUSKY_OK;
 }
 
@@ -278,6 +302,9 @@ husky_status husky_fixup(husky_coder coder, const void* elems, const uint64_t* o
         HUSKY_TRY(radix_segments_from_offsets(seg_offsets_or_null, (uint32_t)n_segs, c.rad, tn.rc, s));
     else
         HUSKY_TRY(radix_segments_single((uint32_t)n, c.rad, tn.rc, s));
+    // first refinement key of every string, read in string order
+    HUSKY_TRY(launch_encode(coder, elems, offsets, (uint32_t)n, nullptr, nullptr,
+                            c.at<uint64_t>(c.L.key0), nullptr, s));
     return run_fixup(c, tn, coder, elems, offsets, n, n_segs, sorted_codes, c.at<uint64_t>(c.L.codes_a),
                      c.at<uint64_t>(c.L.codes_b), idx, s);
 }
@@ -300,16 +327,18 @@ static husky_status sort_common(husky_coder coder, const void* elems, const uint
     if (n == 0) return HUSKY_OK;
     uint64_t* codes = c.at<uint64_t>(c.L.codes_a);
     uint64_t* codes_b = c.at<uint64_t>(c.L.codes_b);
-    HUSKY_TRY(launch_encode(coder, elems, offsets, (uint32_t)n, codes, perm,
+    HUSKY_TRY(launch_encode(coder, elems, offsets, (uint32_t)n, codes, perm, c.at<uint64_t>(c.L.key0),
                             &c.status->domain_violations, s));
     if (seg_offsets)
         HUSKY_TRY(radix_segments_from_offsets(seg_offsets, (uint32_t)n_segs, c.rad, tn.rc, s));
     else
         HUSKY_TRY(radix_segments_single((uint32_t)n, c.rad, tn.rc, s));
     const int end_bit = coder == HUSKY_CODER_ASCII7 ? 63 : 64;
+    const uint32_t tb = tiles_bound(n, n_segs, tn.rc);
+    HUSKY_TRY(radix_reduce_tiles(codes, tb, c.rad, tn.rc, s));
+    HUSKY_TRY(radix_exec_masks(0, end_bit, (uint32_t)n_segs, tb, c.rad, tn.rc, s));
     HUSKY_TRY(radix_sort_segments(codes, perm, codes_b, c.at<uint32_t>(c.L.idx_b), 0, end_bit,
-                                  (uint32_t)n_segs, tiles_bound(n, n_segs, tn.rc), c.rad, tn.rc,
-                                  P_ONESWEEP, s));
+                                  (uint32_t)n_segs, tb, ~0u, c.rad, tn.rc, P_ONESWEEP, s));
     // the sorted codes are not needed once the runs are listed, so the
     // device-wide fix-up reuses both code buffers for its keys
     return run_fixup(c, tn, coder, elems, offsets, n, n_segs, codes, codes, codes_b, perm, s);

@@ -22,6 +22,16 @@ struct SegDesc {
 };
 constexpr uint32_t NOT_BIG = 0xFFFFFFFFu;
 
+// A segment that spans two or more radix tiles.
+struct BigDesc {
+    uint32_t start, len;
+    uint32_t first_tile;   // first tile in the multi-tile tile space
+    uint32_t exec;         // mask of the digit passes it runs
+    uint32_t first_group;  // first scan group (GROUP_TILES tiles each)
+    uint32_t ntiles, ngroups, pad;
+};
+constexpr int GROUP_TILES = 64;
+
 // Slots of the segment-sort counter block (device uint32[64]).
 enum : uint32_t {
     C_TILE0 = 0,       // [MAX_PASSES] dynamic tile ids, one per digit pass
@@ -29,6 +39,8 @@ enum : uint32_t {
     C_BIG_TILES = 17,  // tiles over multi-tile segments (onesweep tile space)
     C_NUM_BIG = 18,    // number of multi-tile segments
     C_NUM_SEGS = 19,   // number of segments
+    C_NUM_GROUPS = 20, // scan groups over the multi-tile segments
+    C_EXEC_UNION = 21, // OR of the pass masks of all multi-tile segments
 };
 
 // Largest s < ns with segs[s].first_tile <= tile (segments in tile order).

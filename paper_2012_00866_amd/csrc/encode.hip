@@ -15,37 +15,52 @@
 
 namespace husky {
 
+// Optionally also the first refinement key of every string (key0): the
+// chunk the fix-up compares first inside a run of equal codes (see
+// fixup.hip for its layout).  Computing it here, while the string's bytes are
+// streamed in order, spares the fix-up a random gather per run member.
 template <int CODER>
 __global__ __launch_bounds__(BLOCK) void k_encode(const uint8_t* __restrict__ bytes,
                                                   const uint64_t* __restrict__ offsets,
                                                   uint32_t n,
                                                   uint64_t* __restrict__ codes,
                                                   uint32_t* __restrict__ idx,
+                                                  uint64_t* __restrict__ key0,
                                                   uint32_t* __restrict__ status) {
-    // bytes in the element buffer (uniform scalar load): the two-word window
-    // below is used only where it stays inside the buffer.
+    // bytes in the element buffer (uniform scalar load): the three-word
+    // window below is used only where it stays inside the buffer.
     const uint64_t total_bytes = offsets[n] * (CODER == 0 ? 1u : 2u);
     uint32_t bad_here = 0;
     for (uint32_t i = blockIdx.x * BLOCK + threadIdx.x; i < n; i += gridDim.x * BLOCK) {
         const uint64_t o0 = offsets[i], o1 = offsets[i + 1];
         const uint64_t len = o1 - o0;
-        uint64_t code;
+        // string bytes 0..7 (lo) and 8..15 (mid), little-endian; bytes past
+        // the string are masked off below
+        const uint64_t addr = CODER == 0 ? o0 : o0 * 2;
+        const uint64_t base = addr & ~7ull;
+        const uint32_t sh = (uint32_t)(addr & 7ull) * 8u;
+        const uint64_t need = (CODER == 0 ? 9u : 8u) + (key0 ? 7u : 0u);  // bytes used from addr
+        const uint64_t slen = len * (CODER == 0 ? 1u : 2u);
+        uint64_t lo = 0, mid = 0;
+        if (base + 24 <= total_bytes) {
+            const uint64_t* w = (const uint64_t*)(bytes + base);
+            const uint64_t w0 = w[0], w1 = w[1];
+            const uint64_t w2 = (sh + 8 * need > 128) ? w[2] : 0ull;
+            lo = sh ? ((w0 >> sh) | (w1 << (64 - sh))) : w0;
+            mid = sh ? ((w1 >> sh) | (w2 << (64 - sh))) : w1;
+        } else {
+            const uint64_t m = slen < need ? slen : need;
+            for (uint32_t k = 0; k < 16; ++k)
+                if (k < m) {
+                    const uint64_t b = bytes[addr + k];
+                    if (k < 8) lo |= b << (8 * k);
+                    else mid |= b << (8 * (k - 8));
+                }
+        }
+        uint64_t code, k0 = 0;
         if (CODER == 0) {
             const uint32_t L = len < 9 ? (uint32_t)len : 9u;
-            const uint64_t base = o0 & ~7ull;
-            const uint32_t sh = (uint32_t)(o0 & 7ull) * 8u;
-            uint64_t lo, b8;
-            if (base + 16 <= total_bytes) {
-                const uint64_t* w = (const uint64_t*)(bytes + base);
-                const uint64_t w0 = w[0], w1 = w[1];
-                lo = sh ? ((w0 >> sh) | (w1 << (64 - sh))) : w0;
-                b8 = (w1 >> sh) & 0xFFull;
-            } else {
-                lo = 0;
-                for (uint32_t k = 0; k < 8; ++k)
-                    if (k < L) lo |= (uint64_t)bytes[o0 + k] << (8 * k);
-                b8 = L == 9 ? bytes[o0 + 8] : 0;
-            }
+            const uint64_t b8 = mid & 0xFFull;
             uint64_t c = b8 & 0x7Full;
 #pragma unroll
             for (int j = 0; j < 8; ++j) c |= ((lo >> (8 * j)) & 0x7Full) << (7 * (8 - j));
@@ -53,28 +68,31 @@ __global__ __launch_bounds__(BLOCK) void k_encode(const uint8_t* __restrict__ by
             const uint64_t keep = L >= 8 ? ~0ull : ((1ull << (8 * L)) - 1ull);
             const bool bad = ((lo & 0x8080808080808080ull) & keep) != 0 || (L == 9 && (b8 & 0x80));
             bad_here += bad ? 1u : 0u;
+            if (key0) {
+                const uint64_t rem = len > 9 ? len - 9 : 0;
+                const uint64_t nb = rem < 7 ? rem : 7;
+                const uint64_t clen = rem > 7 ? 8 : rem;
+                const uint64_t w = (mid >> 8) & (nb ? ((1ull << (8 * nb)) - 1ull) : 0ull);
+                k0 = ((uint64_t)L << 60) | ((__builtin_bswap64(w) >> 8) << 4) | clen;
+            }
         } else {
             const uint32_t L = len < 4 ? (uint32_t)len : 4u;
-            uint64_t lo;
-            const uint64_t addr = o0 * 2;
-            const uint64_t base = addr & ~7ull;
-            if (base + 16 <= total_bytes) {
-                const uint32_t sh = (uint32_t)(addr & 7ull) * 8u;
-                const uint64_t* w = (const uint64_t*)(bytes + base);
-                const uint64_t w0 = w[0], w1 = w[1];
-                lo = sh ? ((w0 >> sh) | (w1 << (64 - sh))) : w0;
-            } else {
-                lo = 0;
-                const uint16_t* u = (const uint16_t*)bytes;
-                for (uint32_t k = 0; k < 4; ++k)
-                    if (k < L) lo |= (uint64_t)u[o0 + k] << (16 * k);
-            }
             const uint64_t c = ((lo & 0xFFFFull) << 48) | (((lo >> 16) & 0xFFFFull) << 32) |
                                (((lo >> 32) & 0xFFFFull) << 16) | (lo >> 48);
             code = L == 0 ? 0ull : (c & (~0ull << (16 * (4 - L))));
+            if (key0) {
+                const uint64_t rem = len > 4 ? len - 4 : 0;
+                const uint64_t nu = rem < 3 ? rem : 3;
+                const uint64_t clen = rem > 3 ? 4 : rem;
+                const uint64_t w = mid & (nu ? ((1ull << (16 * nu)) - 1ull) : 0ull);
+                const uint64_t ch = ((w & 0xFFFFull) << 32) | (((w >> 16) & 0xFFFFull) << 16) |
+                                    ((w >> 32) & 0xFFFFull);
+                k0 = ((uint64_t)L << 60) | (ch << 12) | clen;
+            }
         }
-        codes[i] = code;
+        if (codes) codes[i] = code;
         if (idx) idx[i] = i;
+        if (key0) key0[i] = k0;
     }
     if (CODER == 0 && status) {
         // one atomic per wavefront that saw a violation
@@ -89,16 +107,17 @@ __global__ __launch_bounds__(BLOCK) void k_encode(const uint8_t* __restrict__ by
 }
 
 hipError_t launch_encode(int coder, const void* elems, const uint64_t* offsets, uint32_t n,
-                         uint64_t* codes, uint32_t* idx, uint32_t* status, hipStream_t s) {
+                         uint64_t* codes, uint32_t* idx, uint64_t* key0, uint32_t* status,
+                         hipStream_t s) {
     if (n == 0) return hipSuccess;
     const uint32_t blocks = (n + BLOCK - 1) / BLOCK;
     ProfScope ps(P_ENCODE, s);
     if (coder == 0)
         hipLaunchKernelGGL(k_encode<0>, dim3(blocks), dim3(BLOCK), 0, s, (const uint8_t*)elems,
-                           offsets, n, codes, idx, status);
+                           offsets, n, codes, idx, key0, status);
     else
         hipLaunchKernelGGL(k_encode<1>, dim3(blocks), dim3(BLOCK), 0, s, (const uint8_t*)elems,
-                           offsets, n, codes, idx, status);
+                           offsets, n, codes, idx, key0, status);
     return hipGetLastError();
 }
 

@@ -69,7 +69,8 @@ __global__ __launch_bounds__(BLOCK) void k_fix_small(const RunItem* __restrict__
                                                      const uint32_t* __restrict__ count,
                                                      uint32_t cap, const uint8_t* __restrict__ bytes,
                                                      const uint64_t* __restrict__ offsets,
-                                                     uint32_t n, uint32_t* __restrict__ idx) {
+                                                     uint32_t n, uint32_t* __restrict__ idx,
+                                                     const uint64_t* __restrict__ key0) {
     const uint64_t total_bytes = offsets[n] * (CODER == 0 ? 1u : 2u);
     const uint32_t n_items = min(*count, cap);
     const uint32_t lane = lane_id();
@@ -80,16 +81,25 @@ __global__ __launch_bounds__(BLOCK) void k_fix_small(const RunItem* __restrict__
         const bool mine = lane < L;
         uint32_t member = 0;
         uint64_t off = 0, len = 0;
-        if (mine) {
-            member = idx[r.start + lane];
-            off = offsets[member];
-            len = offsets[member + 1] - off;
-        }
+        bool have_ol = false;
+        if (mine) member = idx[r.start + lane];
         uint32_t g = 0, lt = 0;
         bool active = mine;
         uint32_t round = r.round;
         for (;;) {
-            const uint64_t key = active ? chunk_key<CODER>(bytes, total_bytes, off, len, round) : 0ull;
+            uint64_t key = 0;
+            if (active) {
+                if (round == 0 && key0) {
+                    key = key0[member];
+                } else {
+                    if (!have_ol) {
+                        off = offsets[member];
+                        len = offsets[member + 1] - off;
+                        have_ol = true;
+                    }
+                    key = chunk_key<CODER>(bytes, total_bytes, off, len, round);
+                }
+            }
             uint32_t first = 0, eq = 0;
             lt = 0;
             for (uint32_t q = 0; q < L; ++q) {
@@ -139,7 +149,8 @@ __global__ __launch_bounds__(BLOCK) void k_fix_medium(const RunItem* __restrict_
                                                       const uint32_t* __restrict__ count,
                                                       uint32_t cap, const uint8_t* __restrict__ bytes,
                                                       const uint64_t* __restrict__ offsets,
-                                                      uint32_t n, uint32_t* __restrict__ idx) {
+                                                      uint32_t n, uint32_t* __restrict__ idx,
+                                                      const uint64_t* __restrict__ key0) {
     const uint64_t total_bytes = offsets[n] * (CODER == 0 ? 1u : 2u);
     extern __shared__ __align__(16) uint8_t lds_raw[];
     MediumLds<MAXL>& S = *reinterpret_cast<MediumLds<MAXL>*>(lds_raw);
@@ -152,11 +163,7 @@ __global__ __launch_bounds__(BLOCK) void k_fix_medium(const RunItem* __restrict_
         while (L2 < L) L2 <<= 1;
         for (uint32_t j = tid; j < L2; j += BLOCK) {
             if (j < L) {
-                const uint32_t m = idx[r.start + j];
-                const uint64_t o = offsets[m];
-                S.mem[j] = m;
-                S.off[j] = o;
-                S.len[j] = (uint32_t)(offsets[m + 1] - o);
+                S.mem[j] = idx[r.start + j];
                 S.act[j] = 1;
                 S.gj[j] = j;  // group 0
             } else {
@@ -167,11 +174,27 @@ __global__ __launch_bounds__(BLOCK) void k_fix_medium(const RunItem* __restrict_
         }
         __syncthreads();
         uint32_t round = r.round;
+        bool have_ol = false;
         for (;;) {
-            for (uint32_t q = tid; q < L; q += BLOCK) {
-                const uint32_t j = S.gj[q] & 0xFFFFu;
-                S.key[q] = S.act[q] ? chunk_key<CODER>(bytes, total_bytes, S.off[j], S.len[j], round)
-                                    : 0ull;
+            if (round == 0 && key0) {
+                for (uint32_t q = tid; q < L; q += BLOCK)
+                    S.key[q] = S.act[q] ? key0[S.mem[S.gj[q] & 0xFFFFu]] : 0ull;
+            } else {
+                if (!have_ol) {  // string offsets and lengths, once a round needs bytes
+                    for (uint32_t j = tid; j < L; j += BLOCK) {
+                        const uint32_t m = S.mem[j];
+                        const uint64_t o = offsets[m];
+                        S.off[j] = o;
+                        S.len[j] = (uint32_t)(offsets[m + 1] - o);
+                    }
+                    have_ol = true;
+                    __syncthreads();
+                }
+                for (uint32_t q = tid; q < L; q += BLOCK) {
+                    const uint32_t j = S.gj[q] & 0xFFFFu;
+                    S.key[q] = S.act[q] ? chunk_key<CODER>(bytes, total_bytes, S.off[j], S.len[j], round)
+                                        : 0ull;
+                }
             }
             __syncthreads();
             // already in (group, key, position) order -- e.g. a run of
@@ -254,6 +277,7 @@ __global__ __launch_bounds__(BLOCK) void k_large_keys(const RunItem* __restrict_
                                                       const uint64_t* __restrict__ offsets,
                                                       uint32_t n,
                                                       const uint32_t* __restrict__ idx,
+                                                      const uint64_t* __restrict__ key0,
                                                       uint64_t* __restrict__ keys) {
     constexpr uint32_t TILE = BLOCK * ITEMS;
     const uint64_t total_bytes = offsets[n] * (CODER == 0 ? 1u : 2u);
@@ -265,6 +289,10 @@ __global__ __launch_bounds__(BLOCK) void k_large_keys(const RunItem* __restrict_
     const uint32_t lt = t - d.first_tile;
     const uint32_t base = d.start + lt * TILE;
     const uint32_t nvalid = min(TILE, d.len - lt * TILE);
+    if (round == 0 && key0) {
+        for (uint32_t i = threadIdx.x; i < nvalid; i += BLOCK) keys[base + i] = key0[idx[base + i]];
+        return;
+    }
     for (uint32_t i = threadIdx.x; i < nvalid; i += BLOCK) {
         const uint32_t m = idx[base + i];
         const uint64_t o = offsets[m];
@@ -292,10 +320,10 @@ hipError_t fixup_small(const FixupArgs& a, const TierLists& tl, uint32_t, hipStr
     ProfScope ps(P_FIX_SMALL, s);
     if (a.coder == 0)
         hipLaunchKernelGGL(k_fix_small<0>, dim3(blocks), dim3(BLOCK), 0, s, tl.small, tl.small_count,
-                           tl.small_cap, (const uint8_t*)a.elems, a.offsets, a.n, a.idx);
+                           tl.small_cap, (const uint8_t*)a.elems, a.offsets, a.n, a.idx, a.key0);
     else
         hipLaunchKernelGGL(k_fix_small<1>, dim3(blocks), dim3(BLOCK), 0, s, tl.small, tl.small_count,
-                           tl.small_cap, (const uint8_t*)a.elems, a.offsets, a.n, a.idx);
+                           tl.small_cap, (const uint8_t*)a.elems, a.offsets, a.n, a.idx, a.key0);
     return hipGetLastError();
 }
 
@@ -314,7 +342,7 @@ static hipError_t medium_impl(const FixupArgs& a, const TierLists& tl, hipStream
     ProfScope ps(P_FIX_MEDIUM, s);
     hipLaunchKernelGGL((k_fix_medium<CODER, MAXL>), dim3(blocks), dim3(BLOCK), lds, s, tl.medium,
                        tl.medium_count, tl.medium_cap, (const uint8_t*)a.elems, a.offsets, a.n,
-                       a.idx);
+                       a.idx, a.key0);
     return hipGetLastError();
 }
 
@@ -339,7 +367,7 @@ hipError_t fixup_large_keys(const FixupArgs& a, const RunItem* items, const Radi
     if (a.coder == C && cfg.items == I) {                                                    \
         hipLaunchKernelGGL((k_large_keys<C, I>), dim3(max_tiles), dim3(BLOCK), 0, s, items,  \
                            seg.segs, seg.counters, (const uint8_t*)a.elems, a.offsets, a.n,  \
-                           a.idx, keys);                                                     \
+                           a.idx, a.key0, keys);                                             \
         return hipGetLastError();                                                            \
     }
     HUSKY_LK(0, 16)

@@ -27,8 +27,11 @@ class ProfScope {
 };
 
 // ---- encode.hip
+// codes, idx and key0 (the first refinement key of every string) may each be
+// null.
 hipError_t launch_encode(int coder, const void* elems, const uint64_t* offsets, uint32_t n,
-                         uint64_t* codes, uint32_t* idx, uint32_t* status, hipStream_t s);
+                         uint64_t* codes, uint32_t* idx, uint64_t* key0, uint32_t* status,
+                         hipStream_t s);
 
 // ---- radix.hip
 struct RadixConfig {
@@ -39,11 +42,14 @@ struct RadixConfig {
 
 // Device scratch used by one segmented sort; carved from the workspace.
 struct RadixScratch {
-    SegDesc* segs;         // [seg_cap]
-    uint32_t* hist;        // [big_cap][MAX_PASSES][256]
-    uint64_t* status;      // [lookback_cap][256] look-back words
-    uint32_t* counters;    // [64]: per-pass tile counters, totals (see radix.hip)
-    uint32_t seg_cap, big_cap, tile_cap, lookback_cap;
+    SegDesc* segs;         // [seg_cap] every segment
+    BigDesc* bigs;         // [big_cap] segments longer than one tile
+    uint64_t* korand;      // [2 * big_tile_cap] OR and AND of the keys of each big tile
+    uint32_t* binstart;    // [big_cap][256] digit starts of the current pass
+    uint32_t* cnt;         // [big_tile_cap][256] tile digit counts / offsets
+    uint32_t* gtot;        // [group_cap][256] group totals / offsets
+    uint32_t* counters;    // [64]: tile and segment totals (see common.h)
+    uint32_t seg_cap, big_cap, big_tile_cap, group_cap;
 };
 
 // Build segment descriptors from uint64 string offsets (n_segs + 1 entries).
@@ -58,14 +64,25 @@ hipError_t radix_segments_from_items(const RunItem* items, const uint32_t* count
                                      uint32_t max_items, const RadixScratch& sc,
                                      const RadixConfig& cfg, hipStream_t s);
 
+// Bits that vary inside every big segment: per-tile OR / AND of the keys
+// (skipped by callers whose key kernel already wrote them), then each big
+// segment's mask of digit passes and their union (counters[C_EXEC_UNION]).
+hipError_t radix_reduce_tiles(const uint64_t* keys, uint32_t max_tiles, const RadixScratch& sc,
+                              const RadixConfig& cfg, hipStream_t s);
+hipError_t radix_exec_masks(int begin_bit, int end_bit, uint32_t max_segs, uint32_t max_tiles,
+                            const RadixScratch& sc, const RadixConfig& cfg, hipStream_t s);
+
 // Stable sort of (keys, vals) by bits [begin_bit, end_bit) inside every
-// segment described in sc (built by one of the functions above); keys_alt /
-// vals_alt are ping-pong buffers of the same size.  The result ends in
-// keys / vals.  max_tiles / max_segs bound the grid sizes.
+// segment described in sc (built by one of the functions above, with the
+// pass masks from radix_exec_masks); keys_alt / vals_alt are ping-pong
+// buffers of the same size.  The result ends in keys / vals.  max_tiles /
+// max_segs bound the grid sizes; passes outside pass_union (a host mask,
+// ~0u when unknown) are not launched.
 hipError_t radix_sort_segments(uint64_t* keys, uint32_t* vals, uint64_t* keys_alt,
                                uint32_t* vals_alt, int begin_bit, int end_bit,
-                               uint32_t max_segs, uint32_t max_tiles, const RadixScratch& sc,
-                               const RadixConfig& cfg, int pclass, hipStream_t s);
+                               uint32_t max_segs, uint32_t max_tiles, uint32_t pass_union,
+                               const RadixScratch& sc, const RadixConfig& cfg, int pclass,
+                               hipStream_t s);
 
 // ---- runs.hip
 struct RunScratch {
@@ -84,7 +101,7 @@ struct TierLists {
     RunItem* large;
     uint32_t* small_count;
     uint32_t* medium_count;
-    uint32_t* large_count;
+    uint32_t* large_count;  // [4]: items, items longer than one tile, their tiles, all their tiles
     uint32_t small_cap, medium_cap, large_cap;
 };
 
@@ -110,6 +127,7 @@ struct FixupArgs {
     const uint64_t* offsets;  // [n + 1]; offsets[n] is the element total
     uint32_t n;
     uint32_t* idx;            // permutation being fixed, in place
+    const uint64_t* key0;     // [n] first refinement key of every string
 };
 
 hipError_t fixup_small(const FixupArgs& a, const TierLists& tl, uint32_t t_small, hipStream_t s);

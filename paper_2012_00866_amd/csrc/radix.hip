@@ -14,15 +14,19 @@
 //  * a segment of at most one tile (256 threads x ITEMS keys) is sorted
 //    entirely in LDS by one workgroup (k_tile_sort), digit passes whose digit
 //    is the same in every key of the segment skipped;
-//  * longer ("big") segments go through one histogram kernel that counts the
-//    digits of every pass at once, one scan kernel per segment (which also
-//    marks passes whose digit is constant across the whole segment), then one
-//    onesweep kernel per digit pass: every tile ranks its keys locally with
-//    wavefront ballots, publishes its per-digit counts, finds its global
-//    offsets by decoupled look-back over earlier tiles of the same segment and
-//    scatters through LDS so that neighbouring lanes write neighbouring
-//    addresses.  Tiles take their index from an atomic counter, so a tile
-//    only ever waits on tiles that are already running.
+//  * longer ("big") segments: one reduction finds the bits that vary inside
+//    each segment (OR and AND of its keys); a digit pass over bits that do
+//    not vary is skipped.  Every remaining pass is reduce-then-scan with no
+//    dependency chain between tiles:
+//      k_count      digit counts of every tile,
+//      k_group_scan exclusive scan of the counts over groups of 64 tiles,
+//      k_seg_scan   scan over a segment's groups, and the digit starts,
+//      k_scatter    every tile ranks its keys with wavefront ballots, adds
+//                   its offsets and scatters through LDS so that
+//                   neighbouring lanes write neighbouring addresses.
+//    A decoupled look-back (one kernel per pass) would save the count pass's
+//    read, but its chain of per-tile flags and its per-tile ticket atomic
+//    cost more than that read on this GPU.
 //  * each big segment's skipped passes are tracked with a bit mask; the
 //    ping-pong buffer holding its data after pass p is the parity of the
 //    passes it ran before p, and a final copy returns odd-parity segments to
@@ -67,23 +71,26 @@ struct SrcItems {
     }
 };
 
-// One workgroup: segment descriptors, the two tile spaces and the big list.
+// One workgroup: segment descriptors, the two tile spaces, the big list and
+// its scan groups.
 template <typename Src>
-__global__ __launch_bounds__(BLOCK) void k_seg_setup(Src src, SegDesc* segs, SegDesc* bigs,
+__global__ __launch_bounds__(BLOCK) void k_seg_setup(Src src, SegDesc* segs, BigDesc* bigs,
                                                      uint32_t* counters, uint32_t tile) {
     __shared__ uint32_t scratch[NWAVES];
     const uint32_t S = src.count();
-    uint32_t carry_all = 0, carry_big = 0, carry_nbig = 0;
+    uint32_t carry_all = 0, carry_big = 0, carry_nbig = 0, carry_grp = 0;
     for (uint32_t base = 0; base < S; base += BLOCK) {
         const uint32_t i = base + threadIdx.x;
         uint32_t st = 0, ln = 0;
         if (i < S) src.get(i, st, ln);
         const uint32_t nt = (ln + tile - 1) / tile;
         const bool big = ln > tile;
-        uint32_t tot_all, tot_big, tot_nbig;
+        const uint32_t ng = big ? (nt + GROUP_TILES - 1) / GROUP_TILES : 0u;
+        uint32_t tot_all, tot_big, tot_nbig, tot_grp;
         const uint32_t ex_all = block_exclusive_sum(nt, scratch, &tot_all);
         const uint32_t ex_big = block_exclusive_sum(big ? nt : 0u, scratch, &tot_big);
         const uint32_t ex_nbig = block_exclusive_sum(big ? 1u : 0u, scratch, &tot_nbig);
+        const uint32_t ex_grp = block_exclusive_sum(ng, scratch, &tot_grp);
         if (i < S) {
             SegDesc d;
             d.start = st;
@@ -92,30 +99,33 @@ __global__ __launch_bounds__(BLOCK) void k_seg_setup(Src src, SegDesc* segs, Seg
             d.aux = big ? carry_nbig + ex_nbig : NOT_BIG;
             segs[i] = d;
             if (big) {
-                SegDesc b;
+                const uint32_t bi = carry_nbig + ex_nbig;
+                BigDesc b;
                 b.start = st;
                 b.len = ln;
                 b.first_tile = carry_big + ex_big;
-                b.aux = 0;  // exec mask, written by the scan kernel
-                bigs[carry_nbig + ex_nbig] = b;
+                b.exec = 0;  // written once the varying bits are known
+                b.first_group = carry_grp + ex_grp;
+                b.ntiles = nt;
+                b.ngroups = ng;
+                b.pad = 0;
+                bigs[bi] = b;
             }
         }
         carry_all += tot_all;
         carry_big += tot_big;
         carry_nbig += tot_nbig;
+        carry_grp += tot_grp;
     }
     if (threadIdx.x == 0) {
         counters[C_ALL_TILES] = carry_all;
         counters[C_BIG_TILES] = carry_big;
         counters[C_NUM_BIG] = carry_nbig;
         counters[C_NUM_SEGS] = S;
+        counters[C_NUM_GROUPS] = carry_grp;
+        counters[C_EXEC_UNION] = 0;
     }
-    if (threadIdx.x < MAX_PASSES) counters[C_TILE0 + threadIdx.x] = 0;
 }
-
-// Bigs are stored after segs in the descriptor array: segs[0, seg_cap),
-// bigs[seg_cap, seg_cap + big_cap).
-static inline SegDesc* bigs_of(const RadixScratch& sc) { return sc.segs + sc.seg_cap; }
 
 hipError_t radix_segments_from_offsets(const uint64_t* seg_offsets, uint32_t n_segs,
                                        const RadixScratch& sc, const RadixConfig& cfg,
@@ -123,7 +133,7 @@ hipError_t radix_segments_from_offsets(const uint64_t* seg_offsets, uint32_t n_s
     SrcOffsets src{seg_offsets, n_segs};
     ProfScope ps(P_SETUP, s);
     hipLaunchKernelGGL(k_seg_setup<SrcOffsets>, dim3(1), dim3(BLOCK), 0, s, src, sc.segs,
-                       bigs_of(sc), sc.counters, (uint32_t)cfg.tile());
+                       sc.bigs, sc.counters, (uint32_t)cfg.tile());
     return hipGetLastError();
 }
 hipError_t radix_segments_single(uint32_t n, const RadixScratch& sc, const RadixConfig& cfg,
@@ -131,7 +141,7 @@ hipError_t radix_segments_single(uint32_t n, const RadixScratch& sc, const Radix
     SrcSingle src{n};
     ProfScope ps(P_SETUP, s);
     hipLaunchKernelGGL(k_seg_setup<SrcSingle>, dim3(1), dim3(BLOCK), 0, s, src, sc.segs,
-                       bigs_of(sc), sc.counters, (uint32_t)cfg.tile());
+                       sc.bigs, sc.counters, (uint32_t)cfg.tile());
     return hipGetLastError();
 }
 hipError_t radix_segments_from_items(const RunItem* items, const uint32_t* count,
@@ -140,104 +150,8 @@ hipError_t radix_segments_from_items(const RunItem* items, const uint32_t* count
     SrcItems src{items, count, max_items};
     ProfScope ps(P_SETUP, s);
     hipLaunchKernelGGL(k_seg_setup<SrcItems>, dim3(1), dim3(BLOCK), 0, s, src, sc.segs,
-                       bigs_of(sc), sc.counters, (uint32_t)cfg.tile());
+                       sc.bigs, sc.counters, (uint32_t)cfg.tile());
     return hipGetLastError();
-}
-
-// ------------------------------------------------------------------ histogram
-// Counts the digit of every pass for the keys of big segments.  Workgroup b
-// covers big-space tiles [b*G, (b+1)*G) and flushes its LDS counts to the
-// segment's row whenever the segment changes.
-template <int BITS>
-__global__ __launch_bounds__(BLOCK) void k_hist(const uint64_t* __restrict__ keys,
-                                                const SegDesc* __restrict__ bigs,
-                                                const uint32_t* __restrict__ counters,
-                                                uint32_t* __restrict__ hist, uint32_t tile,
-                                                uint32_t G, int begin_bit, int end_bit,
-                                                int npasses) {
-    constexpr int R = 1 << BITS;
-    constexpr int ROW = MAX_PASSES * R;
-    // one row of counters per wavefront keeps the LDS atomics of different
-    // wavefronts apart; a wavefront whose 64 digits agree adds 64 once
-    __shared__ uint32_t s_h[NWAVES * ROW];
-    const uint32_t total = counters[C_BIG_TILES], nb = counters[C_NUM_BIG];
-    const uint32_t t0 = blockIdx.x * G;
-    if (t0 >= total) return;
-    const uint32_t t1 = min(total, t0 + G);
-    const uint32_t w = threadIdx.x / WAVE, lane = lane_id();
-    uint32_t* my = s_h + w * ROW;
-    for (uint32_t i = threadIdx.x; i < (uint32_t)(NWAVES * ROW); i += BLOCK) s_h[i] = 0;
-    uint32_t b = find_seg(bigs, nb, t0);
-    SegDesc d = bigs[b];
-    __syncthreads();
-    auto flush = [&](uint32_t seg) {
-        for (uint32_t i = threadIdx.x; i < (uint32_t)(npasses * R); i += BLOCK) {
-            uint32_t v = 0;
-#pragma unroll
-            for (int ww = 0; ww < NWAVES; ++ww) {
-                v += s_h[ww * ROW + i];
-                s_h[ww * ROW + i] = 0;
-            }
-            if (v) atomicAdd(&hist[(size_t)seg * MAX_PASSES * 256 + (i / R) * 256 + (i % R)], v);
-        }
-    };
-    for (uint32_t t = t0; t < t1; ++t) {
-        if (b + 1 < nb && bigs[b + 1].first_tile <= t) {
-            __syncthreads();
-            flush(b);  // segment changes
-            ++b;
-            d = bigs[b];
-            __syncthreads();
-        }
-        const uint32_t lt = t - d.first_tile;
-        const uint32_t pos0 = d.start + lt * tile;
-        const uint32_t cnt = min(tile, d.len - lt * tile);
-        // whole wavefronts walk the tile so that ballots see all 64 lanes
-        for (uint32_t i0 = w * WAVE; i0 < cnt; i0 += BLOCK) {
-            const uint32_t i = i0 + lane;
-            const bool ok = i < cnt;
-            const uint64_t k = ok ? keys[pos0 + i] : 0ull;
-            const bool full = ballot(ok) == ~0ull;
-            for (int p = 0; p < npasses; ++p) {
-                const int sh = begin_bit + p * BITS;
-                const int wd = min(BITS, end_bit - sh);
-                const uint32_t dg = (uint32_t)(k >> sh) & ((1u << wd) - 1u);
-                const uint32_t d0 = readlane(dg, 0);
-                if (full && ballot(dg == d0) == ~0ull) {
-                    if (lane == 0) my[p * R + d0] += WAVE;
-                } else if (ok) {
-                    atomicAdd(&my[p * R + dg], 1u);
-                }
-            }
-        }
-        __syncthreads();
-    }
-    __syncthreads();
-    flush(b);
-}
-
-// Exclusive scan of every pass's counts of one big segment (in place) and
-// the mask of passes whose digit varies inside the segment.
-template <int BITS>
-__global__ __launch_bounds__(BLOCK) void k_hist_scan(SegDesc* __restrict__ bigs,
-                                                     const uint32_t* __restrict__ counters,
-                                                     uint32_t* __restrict__ hist, int npasses) {
-    constexpr int R = 1 << BITS;
-    __shared__ uint32_t scratch[NWAVES];
-    const uint32_t b = blockIdx.x;
-    if (b >= counters[C_NUM_BIG]) return;
-    const uint32_t len = bigs[b].len;
-    uint32_t mask = 0;
-    for (int p = 0; p < npasses; ++p) {
-        uint32_t* row = hist + (size_t)b * MAX_PASSES * 256 + p * 256;
-        const uint32_t v = threadIdx.x < (uint32_t)R ? row[threadIdx.x] : 0u;
-        uint32_t tot;
-        const uint32_t ex = block_exclusive_sum(v, scratch, &tot);
-        const int constant = __syncthreads_or(v == len);
-        if (threadIdx.x < (uint32_t)R) row[threadIdx.x] = ex;
-        if (!constant) mask |= 1u << p;
-    }
-    if (threadIdx.x == 0) bigs[b].aux = mask;
 }
 
 // ------------------------------------------------------------------ tile ranking
@@ -329,95 +243,284 @@ __device__ __forceinline__ void load_striped(const uint64_t* __restrict__ keys,
     }
 }
 
-// ------------------------------------------------------------------ onesweep pass
+// ------------------------------------------------------------------ big-segment passes
+// OR / AND over the workgroup; the result is valid in thread 0.
+__device__ __forceinline__ void block_or_and(uint64_t& o, uint64_t& a, uint64_t* s_o, uint64_t* s_a) {
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) {
+        o |= (uint64_t)__shfl_xor((unsigned long long)o, d, WAVE);
+        a &= (uint64_t)__shfl_xor((unsigned long long)a, d, WAVE);
+    }
+    const uint32_t w = threadIdx.x / WAVE;
+    if (lane_id() == 0) {
+        s_o[w] = o;
+        s_a[w] = a;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int i = 1; i < NWAVES; ++i) {
+            o |= s_o[i];
+            a &= s_a[i];
+        }
+    }
+}
+
+template <typename F>
+__device__ __forceinline__ uint32_t find_big(const BigDesc* bigs, uint32_t nb, uint32_t x, F key) {
+    uint32_t lo = 0, hi = nb;  // largest b with key(bigs[b]) <= x
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (key(bigs[mid]) <= x)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+__device__ __forceinline__ uint32_t big_of_tile(const BigDesc* bigs, uint32_t nb, uint32_t t) {
+    return find_big(bigs, nb, t, [](const BigDesc& b) { return b.first_tile; });
+}
+__device__ __forceinline__ uint32_t big_of_group(const BigDesc* bigs, uint32_t nb, uint32_t g) {
+    return find_big(bigs, nb, g, [](const BigDesc& b) { return b.first_group; });
+}
+
+// OR and AND of the keys of every big tile (bits that vary = OR ^ AND).
+template <int ITEMS>
+__global__ __launch_bounds__(BLOCK) void k_orand(const uint64_t* __restrict__ keys,
+                                                 const BigDesc* __restrict__ bigs,
+                                                 const uint32_t* __restrict__ counters,
+                                                 uint64_t* __restrict__ korand) {
+    constexpr uint32_t TILE = BLOCK * ITEMS;
+    __shared__ uint64_t s_o[NWAVES], s_a[NWAVES];
+    const uint32_t t = blockIdx.x;
+    if (t >= counters[C_BIG_TILES]) return;
+    const BigDesc B = bigs[big_of_tile(bigs, counters[C_NUM_BIG], t)];
+    const uint32_t lt = t - B.first_tile;
+    const uint32_t base = B.start + lt * TILE;
+    const uint32_t nvalid = min(TILE, B.len - lt * TILE);
+    uint64_t o = 0, a = ~0ull;
+    for (uint32_t i = threadIdx.x; i < nvalid; i += BLOCK) {
+        const uint64_t k = keys[base + i];
+        o |= k;
+        a &= k;
+    }
+    block_or_and(o, a, s_o, s_a);
+    if (threadIdx.x == 0) {
+        korand[2 * (size_t)t] = o;
+        korand[2 * (size_t)t + 1] = a;
+    }
+}
+
+// Digit passes a big segment runs: those whose bits vary inside it.
+template <int BITS>
+__global__ __launch_bounds__(BLOCK) void k_exec(BigDesc* __restrict__ bigs,
+                                                uint32_t* __restrict__ counters,
+                                                const uint64_t* __restrict__ korand,
+                                                int begin_bit, int end_bit) {
+    __shared__ uint64_t s_o[NWAVES], s_a[NWAVES];
+    const uint32_t b = blockIdx.x;
+    if (b >= counters[C_NUM_BIG]) return;
+    const BigDesc B = bigs[b];
+    uint64_t o = 0, a = ~0ull;
+    for (uint32_t t = threadIdx.x; t < B.ntiles; t += BLOCK) {
+        o |= korand[2 * (size_t)(B.first_tile + t)];
+        a &= korand[2 * (size_t)(B.first_tile + t) + 1];
+    }
+    block_or_and(o, a, s_o, s_a);
+    if (threadIdx.x == 0) {
+        const uint64_t vary = o ^ a;
+        uint32_t mask = 0;
+        int p = 0;
+        for (int sh = begin_bit; sh < end_bit; sh += BITS, ++p) {
+            const uint32_t dm = (1u << min(BITS, end_bit - sh)) - 1u;
+            if ((uint32_t)(vary >> sh) & dm) mask |= 1u << p;
+        }
+        bigs[b].exec = mask;
+        atomicOr(&counters[C_EXEC_UNION], mask);
+    }
+}
+
+__device__ __forceinline__ bool pass_runs(const BigDesc& B, int pass, bool& flip) {
+    if (!((B.exec >> pass) & 1u)) return false;
+    flip = __popc(B.exec & ((1u << pass) - 1u)) & 1u;
+    return true;
+}
+
+// Digit counts of one tile -> cnt[tile][digit].
 template <int BITS, int ITEMS>
-__global__ __launch_bounds__(BLOCK) void k_onesweep(
-    uint64_t* __restrict__ keysA, uint32_t* __restrict__ valsA, uint64_t* __restrict__ keysB,
-    uint32_t* __restrict__ valsB, const SegDesc* __restrict__ bigs,
-    uint32_t* __restrict__ counters, const uint32_t* __restrict__ hist,
-    uint64_t* __restrict__ status, int pass, int shift, uint32_t dmask) {
+__global__ __launch_bounds__(BLOCK) void k_count(const uint64_t* __restrict__ keysA,
+                                                 const uint64_t* __restrict__ keysB,
+                                                 const BigDesc* __restrict__ bigs,
+                                                 const uint32_t* __restrict__ counters,
+                                                 uint32_t* __restrict__ cnt, int pass, int shift,
+                                                 uint32_t dmask) {
     constexpr int R = 1 << BITS;
     constexpr uint32_t TILE = BLOCK * ITEMS;
-    __shared__ uint64_t s_keys[TILE];
-    __shared__ uint32_t s_vals[TILE];
+    __shared__ uint32_t s_h[NWAVES * R];
+    const uint32_t t = blockIdx.x;
+    if (t >= counters[C_BIG_TILES]) return;
+    const BigDesc B = bigs[big_of_tile(bigs, counters[C_NUM_BIG], t)];
+    bool flip;
+    if (!pass_runs(B, pass, flip)) return;
+    const uint64_t* src = flip ? keysB : keysA;
+    const uint32_t lt = t - B.first_tile;
+    const uint32_t base = B.start + lt * TILE;
+    const uint32_t nvalid = min(TILE, B.len - lt * TILE);
+    const uint32_t w = threadIdx.x / WAVE, lane = lane_id();
+    for (uint32_t i = threadIdx.x; i < (uint32_t)(NWAVES * R); i += BLOCK) s_h[i] = 0;
+    __syncthreads();
+    uint32_t* my = s_h + w * R;
+#pragma unroll 4
+    for (int k = 0; k < ITEMS; ++k) {
+        const uint32_t p = w * WAVE * ITEMS + k * WAVE + lane;
+        const bool ok = p < nvalid;
+        const uint32_t dg = ok ? (uint32_t)(src[base + p] >> shift) & dmask : 0u;
+        const uint32_t d0 = readlane(dg, 0);
+        // a wavefront whose 64 digits agree adds 64 once
+        if (ballot(ok && dg == d0) == ~0ull) {
+            if (lane == 0) my[d0] += WAVE;
+        } else if (ok) {
+            atomicAdd(&my[dg], 1u);
+        }
+    }
+    __syncthreads();
+    for (uint32_t d = threadIdx.x; d < (uint32_t)R; d += BLOCK) {
+        uint32_t v = 0;
+#pragma unroll
+        for (int ww = 0; ww < NWAVES; ++ww) v += s_h[ww * R + d];
+        cnt[(size_t)t * 256 + d] = v;
+    }
+}
+
+// Exclusive scan of the tile counts inside each group of GROUP_TILES tiles
+// (in place); the group's totals go to gtot[group][digit].
+template <int BITS>
+__global__ __launch_bounds__(BLOCK) void k_group_scan(const BigDesc* __restrict__ bigs,
+                                                      const uint32_t* __restrict__ counters,
+                                                      uint32_t* __restrict__ cnt,
+                                                      uint32_t* __restrict__ gtot, int pass) {
+    constexpr int R = 1 << BITS;
+    const uint32_t g = blockIdx.x;
+    if (g >= counters[C_NUM_GROUPS]) return;
+    const BigDesc B = bigs[big_of_group(bigs, counters[C_NUM_BIG], g)];
+    bool flip;
+    if (!pass_runs(B, pass, flip)) return;
+    const uint32_t t0 = B.first_tile + (g - B.first_group) * GROUP_TILES;
+    const uint32_t nt = min((uint32_t)GROUP_TILES, B.first_tile + B.ntiles - t0);
+    for (uint32_t d = threadIdx.x; d < (uint32_t)R; d += BLOCK) {
+        uint32_t v[GROUP_TILES];
+#pragma unroll
+        for (int i = 0; i < GROUP_TILES; ++i) v[i] = (uint32_t)i < nt ? cnt[(size_t)(t0 + i) * 256 + d] : 0u;
+        uint32_t run = 0;
+#pragma unroll
+        for (int i = 0; i < GROUP_TILES; ++i) {
+            if ((uint32_t)i < nt) cnt[(size_t)(t0 + i) * 256 + d] = run;
+            run += v[i];
+        }
+        gtot[(size_t)g * 256 + d] = run;
+    }
+}
+
+// Scan of the group totals of one big segment (in place) and the absolute
+// start of every digit: binstart[segment][digit].
+template <int BITS>
+__global__ __launch_bounds__(BLOCK) void k_seg_scan(const BigDesc* __restrict__ bigs,
+                                                    const uint32_t* __restrict__ counters,
+                                                    uint32_t* __restrict__ gtot,
+                                                    uint32_t* __restrict__ binstart, int pass) {
+    constexpr int R = 1 << BITS;
+    __shared__ uint32_t scratch[NWAVES];
+    const uint32_t b = blockIdx.x;
+    if (b >= counters[C_NUM_BIG]) return;
+    const BigDesc B = bigs[b];
+    bool flip;
+    if (!pass_runs(B, pass, flip)) return;
+    const uint32_t d = threadIdx.x;
+    uint32_t run = 0;
+    if (d < (uint32_t)R) {
+        constexpr int U = 16;
+        for (uint32_t g0 = 0; g0 < B.ngroups; g0 += U) {
+            uint32_t v[U];
+#pragma unroll
+            for (int i = 0; i < U; ++i)
+                v[i] = g0 + i < B.ngroups ? gtot[(size_t)(B.first_group + g0 + i) * 256 + d] : 0u;
+#pragma unroll
+            for (int i = 0; i < U; ++i) {
+                if (g0 + i < B.ngroups) gtot[(size_t)(B.first_group + g0 + i) * 256 + d] = run;
+                run += v[i];
+            }
+        }
+    }
+    uint32_t tot;
+    const uint32_t ex = block_exclusive_sum(d < (uint32_t)R ? run : 0u, scratch, &tot);
+    if (d < (uint32_t)R) binstart[(size_t)b * 256 + d] = B.start + ex;
+}
+
+// Rank and scatter one tile.  The tile is staged through LDS twice, keys
+// first and then indices in the same buffer, which halves the LDS a
+// workgroup needs and lets more workgroups share a compute unit.
+template <int BITS, int ITEMS>
+__global__ __launch_bounds__(BLOCK) void k_scatter(
+    uint64_t* __restrict__ keysA, uint32_t* __restrict__ valsA, uint64_t* __restrict__ keysB,
+    uint32_t* __restrict__ valsB, const BigDesc* __restrict__ bigs,
+    const uint32_t* __restrict__ counters, const uint32_t* __restrict__ cnt,
+    const uint32_t* __restrict__ gtot, const uint32_t* __restrict__ binstart, int pass, int shift,
+    uint32_t dmask) {
+    constexpr int R = 1 << BITS;
+    constexpr uint32_t TILE = BLOCK * ITEMS;
+    __shared__ uint64_t s_buf[TILE];
     __shared__ uint32_t s_whist[NWAVES * R];
     __shared__ uint32_t s_binstart[R];
     __shared__ uint32_t s_gbase[R];
     __shared__ uint32_t s_scan[NWAVES];
-    __shared__ uint32_t s_tile;
-
-    const uint32_t tid = threadIdx.x;
-    // workgroups beyond the tile count leave before taking a tile id, so the
-    // ids handed out are exactly 0 .. tiles-1
-    const uint32_t n_tiles = counters[C_BIG_TILES];
-    if (blockIdx.x >= n_tiles) return;
-    if (tid == 0) s_tile = atomicAdd(&counters[C_TILE0 + pass], 1u);
-    __syncthreads();
-    const uint32_t tile = s_tile;
-    const uint32_t b = find_seg(bigs, counters[C_NUM_BIG], tile);
-    const SegDesc d = bigs[b];
-    const uint32_t exec = d.aux;
-    if (!((exec >> pass) & 1u)) return;  // every tile of this segment skips the pass
-    const bool flip = __popc(exec & ((1u << pass) - 1u)) & 1u;
+    const uint32_t t = blockIdx.x, tid = threadIdx.x;
+    if (t >= counters[C_BIG_TILES]) return;
+    const uint32_t b = big_of_tile(bigs, counters[C_NUM_BIG], t);
+    const BigDesc B = bigs[b];
+    bool flip;
+    if (!pass_runs(B, pass, flip)) return;
     const uint64_t* ksrc = flip ? keysB : keysA;
     const uint32_t* vsrc = flip ? valsB : valsA;
     uint64_t* kdst = flip ? keysA : keysB;
     uint32_t* vdst = flip ? valsA : valsB;
-
-    const uint32_t lt = tile - d.first_tile;
-    const uint32_t base = d.start + lt * TILE;
-    const uint32_t nvalid = min(TILE, d.len - lt * TILE);
+    const uint32_t lt = t - B.first_tile;
+    const uint32_t base = B.start + lt * TILE;
+    const uint32_t nvalid = min(TILE, B.len - lt * TILE);
 
     uint64_t k[ITEMS];
     uint32_t v[ITEMS];
     load_striped<ITEMS>(ksrc, vsrc, base, nvalid, k, v);
     uint32_t pos[ITEMS];
-    uint32_t cnt = 0;
-    rank_tile<BITS, ITEMS>(k, shift, dmask, nvalid, pos, s_whist, s_binstart, s_scan, &cnt);
-
-    // decoupled look-back, one bin per thread
+    uint32_t bc = 0;
+    rank_tile<BITS, ITEMS>(k, shift, dmask, nvalid, pos, s_whist, s_binstart, s_scan, &bc);
     if (tid < (uint32_t)R) {
-        const uint64_t FA = (uint64_t)(2 * pass + 1) << 32;  // aggregate of this tile
-        const uint64_t FI = (uint64_t)(2 * pass + 2) << 32;  // inclusive prefix
-        uint64_t* st = status + (size_t)tile * 256 + tid;
-        uint32_t excl = 0;
-        if (lt == 0) {
-            store_agent(st, FI | cnt);
-        } else {
-            store_agent(st, FA | cnt);
-            uint32_t j = tile - 1;
-            for (;;) {
-                const uint64_t sv = load_agent(status + (size_t)j * 256 + tid);
-                const uint64_t f = sv & 0xFFFFFFFF00000000ull;
-                if (f < FA) {
-                    __builtin_amdgcn_s_sleep(1);
-                    continue;
-                }
-                excl += (uint32_t)sv;
-                if (f == FI) break;
-                --j;
-            }
-            store_agent(st, FI | (excl + cnt));
-        }
-        const uint32_t gstart = hist[(size_t)b * MAX_PASSES * 256 + pass * 256 + tid];
-        s_gbase[tid] = d.start + gstart + excl - s_binstart[tid];
+        const uint32_t g = B.first_group + lt / GROUP_TILES;
+        s_gbase[tid] = binstart[(size_t)b * 256 + tid] + gtot[(size_t)g * 256 + tid] +
+                       cnt[(size_t)t * 256 + tid] - s_binstart[tid];
     }
 #pragma unroll
+    for (int i = 0; i < ITEMS; ++i) s_buf[pos[i]] = k[i];
+    __syncthreads();
+    uint32_t dst[ITEMS];
+#pragma unroll
     for (int i = 0; i < ITEMS; ++i) {
-        s_keys[pos[i]] = k[i];
-        s_vals[pos[i]] = v[i];
+        const uint32_t p = i * BLOCK + tid;
+        dst[i] = 0;
+        if (p < nvalid) {
+            const uint64_t key = s_buf[p];
+            dst[i] = s_gbase[(uint32_t)(key >> shift) & dmask] + p;
+            kdst[dst[i]] = key;
+        }
     }
+    __syncthreads();
+    uint32_t* s_v = (uint32_t*)s_buf;
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i) s_v[pos[i]] = v[i];
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < ITEMS; ++i) {
         const uint32_t p = i * BLOCK + tid;
-        if (p < nvalid) {
-            const uint64_t key = s_keys[p];
-            const uint32_t dg = (uint32_t)(key >> shift) & dmask;
-            const uint32_t dst = s_gbase[dg] + p;
-            kdst[dst] = key;
-            vdst[dst] = s_vals[p];
-        }
+        if (p < nvalid) vdst[dst[i]] = s_v[p];
     }
 }
 
@@ -426,17 +529,16 @@ __global__ __launch_bounds__(BLOCK) void k_copy_back(uint64_t* __restrict__ keys
                                                      uint32_t* __restrict__ valsA,
                                                      const uint64_t* __restrict__ keysB,
                                                      const uint32_t* __restrict__ valsB,
-                                                     const SegDesc* __restrict__ bigs,
+                                                     const BigDesc* __restrict__ bigs,
                                                      const uint32_t* __restrict__ counters,
                                                      uint32_t tile) {
     const uint32_t t = blockIdx.x;
     if (t >= counters[C_BIG_TILES]) return;
-    const uint32_t b = find_seg(bigs, counters[C_NUM_BIG], t);
-    const SegDesc d = bigs[b];
-    if (!(__popc(d.aux) & 1)) return;
-    const uint32_t lt = t - d.first_tile;
-    const uint32_t base = d.start + lt * tile;
-    const uint32_t cnt = min(tile, d.len - lt * tile);
+    const BigDesc B = bigs[big_of_tile(bigs, counters[C_NUM_BIG], t)];
+    if (!(__popc(B.exec) & 1)) return;
+    const uint32_t lt = t - B.first_tile;
+    const uint32_t base = B.start + lt * tile;
+    const uint32_t cnt = min(tile, B.len - lt * tile);
     for (uint32_t i = threadIdx.x; i < cnt; i += BLOCK) {
         keysA[base + i] = keysB[base + i];
         valsA[base + i] = valsB[base + i];
@@ -557,48 +659,53 @@ hipError_t zero_u32(uint32_t* p, size_t n, hipStream_t s) {
 
 // ------------------------------------------------------------------ driver
 template <int BITS, int ITEMS>
+static hipError_t exec_impl(int begin_bit, int end_bit, uint32_t max_segs, uint32_t max_tiles,
+                            const RadixScratch& sc, hipStream_t s) {
+    max_tiles = std::min(max_tiles, sc.big_tile_cap);
+    const uint32_t max_big = std::min(std::min(sc.big_cap, max_tiles / 2 + 1), std::max(max_segs, 1u));
+    ProfScope ps(P_HIST, s);
+    hipLaunchKernelGGL((k_exec<BITS>), dim3(max_big), dim3(BLOCK), 0, s, sc.bigs, sc.counters,
+                       sc.korand, begin_bit, end_bit);
+    return hipGetLastError();
+}
+
+template <int BITS, int ITEMS>
 static hipError_t sort_impl(uint64_t* keys, uint32_t* vals, uint64_t* keys_alt,
                             uint32_t* vals_alt, int begin_bit, int end_bit, uint32_t max_segs,
-                            uint32_t max_tiles, const RadixScratch& sc, int pclass,
-                            hipStream_t s) {
+                            uint32_t max_tiles, uint32_t pass_union, const RadixScratch& sc,
+                            int pclass, hipStream_t s) {
     constexpr uint32_t TILE = BLOCK * ITEMS;
     const int npasses = (end_bit - begin_bit + BITS - 1) / BITS;
-    SegDesc* bigs = bigs_of(sc);
+    BigDesc* bigs = sc.bigs;
     // single-tile segments
     if (max_segs) {
         ProfScope ps(P_TILE_SORT, s);
         hipLaunchKernelGGL((k_tile_sort<BITS, ITEMS>), dim3(max_segs), dim3(BLOCK), 0, s, keys,
                            vals, sc.segs, sc.counters, begin_bit, end_bit);
     }
-    if (max_tiles == 0) return hipGetLastError();
-    // big segments
-    // every multi-tile segment spans two or more tiles, and there are at most
+    max_tiles = std::min(max_tiles, sc.big_tile_cap);
+    if (max_tiles == 0 || pass_union == 0) return hipGetLastError();
+    // every big segment spans two or more tiles, and there are at most
     // max_segs segments
     const uint32_t max_big = std::min(std::min(sc.big_cap, max_tiles / 2 + 1), std::max(max_segs, 1u));
-    hipError_t e = zero_u32(sc.hist, (size_t)max_big * MAX_PASSES * 256, s);
-    if (e != hipSuccess) return e;
-    e = zero_u64(sc.status, (size_t)std::min(max_tiles, sc.lookback_cap) * 256, s);
-    if (e != hipSuccess) return e;
-    e = zero_u32(sc.counters + C_TILE0, MAX_PASSES, s);
-    if (e != hipSuccess) return e;
-    const uint32_t G = 8;
-    {
-        ProfScope ps(P_HIST, s);
-        hipLaunchKernelGGL((k_hist<BITS>), dim3((max_tiles + G - 1) / G), dim3(BLOCK), 0, s, keys,
-                           bigs, sc.counters, sc.hist, TILE, G, begin_bit, end_bit, npasses);
-    }
-    {
-        ProfScope ps(P_HIST_SCAN, s);
-        hipLaunchKernelGGL((k_hist_scan<BITS>), dim3(max_big), dim3(BLOCK), 0, s, bigs,
-                           sc.counters, sc.hist, npasses);
-    }
+    const uint32_t max_groups = std::min(sc.group_cap, max_tiles / GROUP_TILES + max_big + 1);
     for (int p = 0; p < npasses; ++p) {
+        if (!((pass_union >> p) & 1u)) continue;
         const int shift = begin_bit + p * BITS;
-        const uint32_t dmask = (1u << min(BITS, end_bit - shift)) - 1u;  // top digit may be narrower
+        const uint32_t dmask = (1u << std::min(BITS, end_bit - shift)) - 1u;  // top digit may be narrower
+        {
+            ProfScope ps(P_HIST_SCAN, s);
+            hipLaunchKernelGGL((k_count<BITS, ITEMS>), dim3(max_tiles), dim3(BLOCK), 0, s, keys,
+                               keys_alt, bigs, sc.counters, sc.cnt, p, shift, dmask);
+            hipLaunchKernelGGL((k_group_scan<BITS>), dim3(max_groups), dim3(BLOCK), 0, s, bigs,
+                               sc.counters, sc.cnt, sc.gtot, p);
+            hipLaunchKernelGGL((k_seg_scan<BITS>), dim3(max_big), dim3(BLOCK), 0, s, bigs,
+                               sc.counters, sc.gtot, sc.binstart, p);
+        }
         ProfScope ps(pclass, s);
-        hipLaunchKernelGGL((k_onesweep<BITS, ITEMS>), dim3(max_tiles), dim3(BLOCK), 0, s, keys,
-                           vals, keys_alt, vals_alt, bigs, sc.counters, sc.hist, sc.status, p,
-                           shift, dmask);
+        hipLaunchKernelGGL((k_scatter<BITS, ITEMS>), dim3(max_tiles), dim3(BLOCK), 0, s, keys,
+                           vals, keys_alt, vals_alt, bigs, sc.counters, sc.cnt, sc.gtot,
+                           sc.binstart, p, shift, dmask);
     }
     ProfScope ps(P_COPY_BACK, s);
     hipLaunchKernelGGL(k_copy_back, dim3(max_tiles), dim3(BLOCK), 0, s, keys, vals, keys_alt,
@@ -606,14 +713,37 @@ static hipError_t sort_impl(uint64_t* keys, uint32_t* vals, uint64_t* keys_alt,
     return hipGetLastError();
 }
 
+hipError_t radix_reduce_tiles(const uint64_t* keys, uint32_t max_tiles, const RadixScratch& sc,
+                              const RadixConfig& cfg, hipStream_t s) {
+    max_tiles = std::min(max_tiles, sc.big_tile_cap);
+    if (!max_tiles) return hipSuccess;
+    ProfScope ps(P_HIST, s);
+    if (cfg.items == 16)
+        hipLaunchKernelGGL((k_orand<16>), dim3(max_tiles), dim3(BLOCK), 0, s, keys, sc.bigs, sc.counters, sc.korand);
+    else if (cfg.items == 12)
+        hipLaunchKernelGGL((k_orand<12>), dim3(max_tiles), dim3(BLOCK), 0, s, keys, sc.bigs, sc.counters, sc.korand);
+    else
+        hipLaunchKernelGGL((k_orand<8>), dim3(max_tiles), dim3(BLOCK), 0, s, keys, sc.bigs, sc.counters, sc.korand);
+    return hipGetLastError();
+}
+
+hipError_t radix_exec_masks(int begin_bit, int end_bit, uint32_t max_segs, uint32_t max_tiles,
+                            const RadixScratch& sc, const RadixConfig& cfg, hipStream_t s) {
+    if (cfg.bits == 8) return exec_impl<8, 16>(begin_bit, end_bit, max_segs, max_tiles, sc, s);
+    if (cfg.bits == 7) return exec_impl<7, 16>(begin_bit, end_bit, max_segs, max_tiles, sc, s);
+    if (cfg.bits == 6) return exec_impl<6, 16>(begin_bit, end_bit, max_segs, max_tiles, sc, s);
+    return hipErrorInvalidValue;
+}
+
 hipError_t radix_sort_segments(uint64_t* keys, uint32_t* vals, uint64_t* keys_alt,
                                uint32_t* vals_alt, int begin_bit, int end_bit,
-                               uint32_t max_segs, uint32_t max_tiles, const RadixScratch& sc,
-                               const RadixConfig& cfg, int pclass, hipStream_t s) {
+                               uint32_t max_segs, uint32_t max_tiles, uint32_t pass_union,
+                               const RadixScratch& sc, const RadixConfig& cfg, int pclass,
+                               hipStream_t s) {
 #define HUSKY_SORT_CASE(B, I)                                                                 \
     if (cfg.bits == B && cfg.items == I)                                                      \
         return sort_impl<B, I>(keys, vals, keys_alt, vals_alt, begin_bit, end_bit, max_segs, \
-                               max_tiles, sc, pclass, s);
+                               max_tiles, pass_union, sc, pclass, s);
     HUSKY_SORT_CASE(8, 16)
     HUSKY_SORT_CASE(8, 12)
     HUSKY_SORT_CASE(8, 8)

@@ -151,43 +151,83 @@ __global__ __launch_bounds__(BLOCK) void k_runs_write(const uint64_t* __restrict
     }
 }
 
-// Append one item to a list with one atomic per wavefront and list.
-__device__ __forceinline__ void wave_append(bool take, const RunItem& it, RunItem* list,
-                                            uint32_t* count, uint32_t cap) {
-    const uint64_t m = ballot(take);
-    if (!m) return;
-    const uint32_t leader = (uint32_t)__ffsll((unsigned long long)m) - 1u;
-    uint32_t base = 0;
-    if (lane_id() == leader) base = atomicAdd(count, (uint32_t)__popcll(m));
-    base = readlane(base, (int)leader);
-    if (take) {
-        const uint32_t o = base + mbcnt(m);
-        if (o < cap) list[o] = it;
-    }
+// Work items for the three tiers.  Each workgroup takes a contiguous share
+// of the run table, counts its items per tier (one LDS atomic per wavefront
+// and tier), reserves its slots with one device atomic per tier, and writes
+// them; the order inside a list does not matter.  For the device-wide list it
+// also adds up what the host needs to size that tier's launches: the number
+// of items longer than one radix tile and the tiles they span.
+__device__ __forceinline__ int tier_of(uint32_t len, uint32_t t_small, uint32_t t_medium) {
+    return len <= t_small ? 0 : (len <= t_medium ? 1 : 2);
 }
 
 __global__ __launch_bounds__(BLOCK) void k_runs_classify(
     const uint32_t* __restrict__ run_start, const uint32_t* __restrict__ run_end,
     const uint32_t* __restrict__ run_seg, const uint32_t* __restrict__ num_runs,
     const RunItem* __restrict__ items, TierLists tl, uint32_t t_small, uint32_t t_medium,
-    uint32_t* __restrict__ runs_seen) {
+    uint32_t tile, uint32_t* __restrict__ runs_seen) {
+    __shared__ uint32_t s_n[6], s_base[3], s_fill[3];
     const uint32_t nr = *num_runs;
-    const uint32_t stride = gridDim.x * BLOCK;
-    // loop bound rounded up to a multiple of the block so whole wavefronts
-    // reach the ballots together
-    const uint32_t lim = (nr + BLOCK - 1) / BLOCK * BLOCK;
-    for (uint32_t r = blockIdx.x * BLOCK + threadIdx.x; r < lim; r += stride) {
+    const uint32_t per = ((nr + gridDim.x - 1) / gridDim.x + BLOCK - 1) / BLOCK * BLOCK;
+    const uint32_t r0 = blockIdx.x * per, r1 = min(nr, r0 + per);
+    if (threadIdx.x < 6) s_n[threadIdx.x] = 0;
+    if (threadIdx.x < 3) s_fill[threadIdx.x] = 0;
+    __syncthreads();
+    const uint32_t lane = lane_id();
+    // pass 1: counts
+    for (uint32_t r = r0 + threadIdx.x; r < r0 + per; r += BLOCK) {
+        const bool ok = r < r1;
+        uint32_t len = 0;
+        if (ok) len = run_end[r] - run_start[r] + 1;
+        const int tr = ok ? tier_of(len, t_small, t_medium) : -1;
+        const uint32_t big = (tr == 2 && len > tile) ? 1u : 0u;
+        const uint32_t bt = big ? (len + tile - 1) / tile : 0u;
+        const uint32_t at = tr == 2 ? (len + tile - 1) / tile : 0u;
+        uint32_t c[6] = {(uint32_t)__popcll(ballot(tr == 0)), (uint32_t)__popcll(ballot(tr == 1)),
+                         (uint32_t)__popcll(ballot(tr == 2)), (uint32_t)__popcll(ballot(big != 0)), bt, at};
+#pragma unroll
+        for (int d = 32; d >= 1; d >>= 1) {
+            c[4] += __shfl_xor(c[4], d, WAVE);
+            c[5] += __shfl_xor(c[5], d, WAVE);
+        }
+        if (lane == 0)
+            for (int q = 0; q < 6; ++q)
+                if (c[q]) atomicAdd(&s_n[q], c[q]);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        s_base[0] = s_n[0] ? atomicAdd(tl.small_count, s_n[0]) : 0u;
+        s_base[1] = s_n[1] ? atomicAdd(tl.medium_count, s_n[1]) : 0u;
+        s_base[2] = s_n[2] ? atomicAdd(tl.large_count, s_n[2]) : 0u;
+        if (s_n[3]) atomicAdd(tl.large_count + 1, s_n[3]);
+        if (s_n[4]) atomicAdd(tl.large_count + 2, s_n[4]);
+        if (s_n[5]) atomicAdd(tl.large_count + 3, s_n[5]);
+    }
+    __syncthreads();
+    // pass 2: items
+    for (uint32_t r = r0 + threadIdx.x; r < r0 + per; r += BLOCK) {
+        const bool ok = r < r1;
         RunItem it{0, 0, 0, 0};
-        bool ok = r < nr;
+        int tr = -1;
         if (ok) {
             it.start = run_start[r];
             it.len = run_end[r] - it.start + 1;
             it.round = items ? items[run_seg[r]].round + 1 : 0;
+            tr = tier_of(it.len, t_small, t_medium);
         }
-        wave_append(ok && it.len <= t_small, it, tl.small, tl.small_count, tl.small_cap);
-        wave_append(ok && it.len > t_small && it.len <= t_medium, it, tl.medium, tl.medium_count,
-                    tl.medium_cap);
-        wave_append(ok && it.len > t_medium, it, tl.large, tl.large_count, tl.large_cap);
+        for (int q = 0; q < 3; ++q) {
+            const uint64_t m = ballot(tr == q);
+            if (!m) continue;
+            const uint32_t leader = (uint32_t)__ffsll((unsigned long long)m) - 1u;
+            uint32_t o = 0;
+            if (lane == leader) o = atomicAdd(&s_fill[q], (uint32_t)__popcll(m));
+            o = readlane(o, (int)leader) + mbcnt(m) + s_base[q];
+            if (tr == q) {
+                RunItem* list = q == 0 ? tl.small : (q == 1 ? tl.medium : tl.large);
+                const uint32_t cap = q == 0 ? tl.small_cap : (q == 1 ? tl.medium_cap : tl.large_cap);
+                if (o < cap) list[o] = it;
+            }
+        }
     }
     if (runs_seen && blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(runs_seen, nr);
 }
@@ -207,10 +247,11 @@ static hipError_t find_runs_impl(const uint64_t* keys, const RadixScratch& seg,
     hipLaunchKernelGGL((k_runs_write<CODER, REFINE, ITEMS>), dim3(max_tiles), dim3(BLOCK), 0, s,
                        keys, seg.segs, seg.counters, rs.tile_counts, rs.run_start, rs.run_end,
                        rs.run_start + rs.run_cap);
-    const uint32_t blocks = 512;
+    const uint32_t blocks = 96;
     hipLaunchKernelGGL(k_runs_classify, dim3(blocks), dim3(BLOCK), 0, s, rs.run_start, rs.run_end,
                        rs.run_start + rs.run_cap, num_runs, REFINE ? items : nullptr, tl,
-                       t_small, t_medium, REFINE ? nullptr : rs.runs_seen);
+                       t_small, t_medium, (uint32_t)(BLOCK * ITEMS),
+                       REFINE ? nullptr : rs.runs_seen);
     return hipGetLastError();
 }
 
