@@ -78,7 +78,7 @@ typedef struct {
     uint32_t domain_violations; /* ASCII7 strings with a byte >= 0x80 among the first nine */
     uint32_t large_rounds;      /* device-wide refinement rounds the last fix-up ran */
     uint32_t runs_fixed;        /* equal-code runs (length >= 2) the last fix-up visited */
-    uint32_t reserved;
+    uint32_t unresolved;        /* groups left tied after max_rounds fixed rounds (else 0) */
 } husky_device_status;
 
 /* Launch tuning.  Zero in a field selects the library default.  The values
@@ -88,12 +88,21 @@ typedef struct {
  *   t_small    -- equal-code runs of at most this many strings are sorted by
  *                 one wavefront (2..64);
  *   t_medium   -- runs of at most this many by one workgroup in LDS
- *                 (t_small < t_medium <= 8192); longer runs device-wide. */
+ *                 (t_small < t_medium <= 4096); longer runs device-wide;
+ *   max_rounds -- 0: the device-wide fix-up reads its work counts back to
+ *                 the host once per refinement round (adaptive).  k > 0: it
+ *                 runs exactly k rounds sized from host bounds, with no
+ *                 host synchronisation, so the whole call can be captured
+ *                 into a HIP graph.  Round r compares elements up to
+ *                 m + C*(r+1) (ASCII: 9 + 7(r+1) bytes; UTF-16: 4 + 3(r+1)
+ *                 units); groups still tied after k rounds are counted in
+ *                 husky_device_status.unresolved and then perm is not final. */
 typedef struct {
     int32_t radix_bits;
     int32_t tile_items;
     uint32_t t_small;
     uint32_t t_medium;
+    uint32_t max_rounds;
 } husky_tuning;
 
 /* Workspace bytes that every call below needs for n strings in n_segs
@@ -156,6 +165,20 @@ husky_status husky_sort_batched(husky_coder coder, const void* elems, const uint
                                 uint64_t n, const uint64_t* seg_offsets, uint64_t n_segs,
                                 uint32_t* perm, void* ws, size_t ws_bytes,
                                 const husky_tuning* tuning, void* stream);
+
+/* Exactness check on the device.  perm (uint32[n]) is the stable sorting
+ * permutation -- of every instance's range when seg_offsets_or_null (uint64
+ * [n_segs + 1]) is given -- iff the check finds no violation: every entry a
+ * distinct index of its own instance, every adjacent pair inside an instance
+ * ordered by the full comparator with equal strings in ascending index
+ * (Sec. 3.2: the final pass must leave no inversion).  *violations (device
+ * uint32) receives the number of failing positions.  ws needs (n + 31) / 32 *
+ * 4 bytes (a bitmap).  Asynchronous on stream.  Errors: HUSKY_ERR_ARG,
+ * HUSKY_ERR_WORKSPACE, HUSKY_ERR_HIP. */
+husky_status husky_check_perm(husky_coder coder, const void* elems, const uint64_t* offsets,
+                              uint64_t n, const uint64_t* seg_offsets_or_null, uint64_t n_segs,
+                              const uint32_t* perm, void* ws, size_t ws_bytes,
+                              uint32_t* violations, void* stream);
 
 /* Kernel timing (diagnostics).  husky_profile_begin() starts bracketing
  * every launch of the library with a pair of HIP events recorded on that

@@ -38,21 +38,28 @@ class DomainError(HuskyError):
 
 class Tuning(ctypes.Structure):
     _fields_ = [("radix_bits", ctypes.c_int32), ("tile_items", ctypes.c_int32),
-                ("t_small", ctypes.c_uint32), ("t_medium", ctypes.c_uint32)]
+                ("t_small", ctypes.c_uint32), ("t_medium", ctypes.c_uint32),
+                ("max_rounds", ctypes.c_uint32)]
 
     def as_dict(self):
         return {f: int(getattr(self, f)) for f, _ in self._fields_}
 
 
-def make_tuning(radix_bits=0, tile_items=0, t_small=0, t_medium=0) -> Tuning:
-    return Tuning(int(radix_bits), int(tile_items), int(t_small), int(t_medium))
+def make_tuning(radix_bits=0, tile_items=0, t_small=0, t_medium=0, max_rounds=0) -> Tuning:
+    return Tuning(int(radix_bits), int(tile_items), int(t_small), int(t_medium), int(max_rounds))
+
+
+def rounds_for(max_len: int, coder="ascii7") -> int:
+    """Fixed device-wide rounds that resolve any run of strings of at most max_len elements."""
+    m, c = (9, 7) if _coder(coder) == 0 else (4, 3)
+    return max(1, -(-(max(int(max_len), m) - m) // c))
 
 
 _lib = None
 
 EXPORTS = ("husky_workspace_bytes", "husky_encode", "husky_sort_pairs", "husky_fixup",
-           "husky_sort", "husky_sort_batched", "husky_profile_begin", "husky_profile_end",
-           "husky_status_string")
+           "husky_sort", "husky_sort_batched", "husky_check_perm", "husky_profile_begin",
+           "husky_profile_end", "husky_status_string")
 
 # kernel classes of husky_profile_end (include/husky.h)
 PROFILE_CLASSES = ("encode", "radix_hist", "radix_hist_scan", "radix_onesweep", "radix_copy_back",
@@ -82,6 +89,8 @@ def load(path: str = LIB_PATH):
     lib.husky_sort.argtypes = [i32, vp, vp, u64, vp, vp, sz, tp, vp]
     lib.husky_sort_batched.restype = i32
     lib.husky_sort_batched.argtypes = [i32, vp, vp, u64, vp, u64, vp, vp, sz, tp, vp]
+    lib.husky_check_perm.restype = i32
+    lib.husky_check_perm.argtypes = [i32, vp, vp, u64, vp, u64, vp, vp, sz, vp, vp]
     lib.husky_profile_begin.restype = None
     lib.husky_profile_begin.argtypes = []
     lib.husky_profile_end.restype = i32
@@ -130,7 +139,8 @@ def alloc_workspace(n: int, n_segs: int = 1, device="cuda"):
 def read_status(ws) -> dict:
     """Device status block (first 16 bytes of the workspace); synchronizes."""
     v = ws[:16].cpu().numpy().view(np.uint32)
-    return {"domain_violations": int(v[0]), "large_rounds": int(v[1]), "runs_fixed": int(v[2])}
+    return {"domain_violations": int(v[0]), "large_rounds": int(v[1]), "runs_fixed": int(v[2]),
+            "unresolved": int(v[3])}
 
 
 def to_device(batch, device="cuda"):
@@ -231,6 +241,20 @@ def sort_batched(elems, offsets, seg_offsets, coder="ascii7", tuning: Optional[T
         if st["domain_violations"]:
             raise DomainError(2, f"husky_sort_batched ({st['domain_violations']} strings)")
     return perm[:n]
+
+
+def check_perm(elems, offsets, perm, coder="ascii7", seg_offsets=None, stream=None) -> int:
+    """Violations of the stable-sort property found on the device (0 = exact)."""
+    torch = _torch()
+    lib = load()
+    n = _n_of(offsets)
+    ns = 1 if seg_offsets is None else int(seg_offsets.numel()) - 1
+    ws = torch.empty(max(4, (n + 31) // 32 * 4), dtype=torch.uint8, device=offsets.device)
+    out = torch.zeros(1, dtype=torch.int32, device=offsets.device)
+    _check(lib.husky_check_perm(_coder(coder), _ptr(elems), _ptr(offsets), n, _ptr(seg_offsets), ns,
+                                _ptr(perm), _ptr(ws), ws.numel(), _ptr(out), _stream(stream)),
+           "husky_check_perm")
+    return int(out.item())
 
 
 def profile_begin():

@@ -130,17 +130,19 @@ Ctx make_ctx(void* ws, uint64_t n, uint64_t n_segs) {
 
 struct Tune {
     RadixConfig rc;
-    uint32_t t_small, t_medium;
+    uint32_t t_small, t_medium, max_rounds;
 };
 
 husky_status resolve_tuning(const husky_tuning* t, Tune* out) {
-    Tune r{{8, 16}, 64, 4096};
+    Tune r{{8, 16}, 64, 4096, 0};
     if (t) {
         if (t->radix_bits) r.rc.bits = t->radix_bits;
         if (t->tile_items) r.rc.items = t->tile_items;
         if (t->t_small) r.t_small = t->t_small;
         if (t->t_medium) r.t_medium = t->t_medium;
+        r.max_rounds = t->max_rounds;
     }
+    if (r.max_rounds > 4096) return HUSKY_ERR_UNSUPPORTED;
     if (r.rc.bits < 6 || r.rc.bits > 8) return HUSKY_ERR_UNSUPPORTED;
     if (r.rc.items != 8 && r.rc.items != 12 && r.rc.items != 16) return HUSKY_ERR_UNSUPPORTED;
     if (r.t_small < 2 || r.t_small > MAX_T_SMALL) return HUSKY_ERR_UNSUPPORTED;
@@ -158,6 +160,7 @@ husky_status check_ws(void* ws, size_t ws_bytes, uint64_t n, uint64_t n_segs) {
 }
 
 __global__ void k_set_u32(uint32_t* p, uint32_t v) { *p = v; }
+__global__ void k_copy_u32(uint32_t* dst, const uint32_t* src) { *dst = *src; }
 
 husky_status hip_status(hipError_t e) { return e == hipSuccess ? HUSKY_OK : HUSKY_ERR_HIP; }
 
@@ -194,23 +197,37 @@ husky_status run_fixup(Ctx& c, const Tune& tn, int coder, const void* elems,
     RunItem* nxt = c.at<RunItem>(c.L.large_b);
     uint32_t* cur_cnt = c.counters + CNT_LARGE_A;
     uint32_t* nxt_cnt = c.counters + CNT_LARGE_B;
+    const bool fixed = tn.max_rounds > 0;
+    // host bounds for the fixed-round mode: every device-wide item is longer
+    // than t_medium, so there are at most n / (t_medium + 1) of them and
+    // their tiles number at most n / tile + items
+    const uint32_t nl_bound = std::min<uint32_t>(c.L.large_cap, (uint32_t)(n / (tn.t_medium + 1) + 1));
+    const uint32_t tiles_bound_l = (uint32_t)(n / tn.rc.tile()) + nl_bound + 1;
     for (;;) {
-        // items, items longer than one tile, their tiles, all their tiles
-        uint32_t st[4];
-        HUSKY_TRY(hipMemcpyAsync(st, cur_cnt, sizeof(st), hipMemcpyDeviceToHost, s));
-        HUSKY_TRY(hipStreamSynchronize(s));
-        const uint32_t nl = std::min(st[0], c.L.large_cap);
-        if (nl == 0) break;
+        uint32_t nl, all_tiles, big_tiles;
+        if (fixed) {
+            if (rounds == tn.max_rounds) break;
+            nl = nl_bound;
+            all_tiles = big_tiles = tiles_bound_l;
+        } else {
+            // items, items longer than one tile, their tiles, all their tiles
+            uint32_t st[4];
+            HUSKY_TRY(hipMemcpyAsync(st, cur_cnt, sizeof(st), hipMemcpyDeviceToHost, s));
+            HUSKY_TRY(hipStreamSynchronize(s));
+            nl = std::min(st[0], c.L.large_cap);
+            if (nl == 0) break;
+            all_tiles = st[3] + 1;
+            big_tiles = st[1] ? st[2] + 1 : 0;
+        }
         HUSKY_TRY(radix_segments_from_items(cur, cur_cnt, c.L.large_cap, c.rad, tn.rc, s));
-        const uint32_t all_tiles = st[3] + 1, big_tiles = st[1] ? st[2] + 1 : 0;
         HUSKY_TRY(fixup_large_keys(fa, cur, c.rad, tn.rc, all_tiles, keys, s));
-        uint32_t pass_union = 0;
+        uint32_t pass_union = ~0u;
         if (big_tiles) {
             HUSKY_TRY(radix_reduce_tiles(keys, big_tiles, c.rad, tn.rc, s));
             HUSKY_TRY(radix_exec_masks(0, 64, nl, big_tiles, c.rad, tn.rc, s));
             // the digit passes any group needs: refinement keys hold long
             // constant stretches, so passes nobody runs are not launched
-            HUSKY_TRY(read_u32(c.counters + C_EXEC_UNION, &pass_union, s));
+            if (!fixed) HUSKY_TRY(read_u32(c.counters + C_EXEC_UNION, &pass_union, s));
         }
         HUSKY_TRY(radix_sort_segments(keys, idx, keys_alt, c.at<uint32_t>(c.L.idx_b), 0, 64, nl,
                                       big_tiles, pass_union, c.rad, tn.rc, P_ONESWEEP_FIX, s));
@@ -223,6 +240,10 @@ husky_status run_fixup(Ctx& c, const Tune& tn, int coder, const void* elems,
         std::swap(cur, nxt);
         std::swap(cur_cnt, nxt_cnt);
         ++rounds;
+    }
+    if (fixed) {
+        hipLaunchKernelGGL(k_copy_u32, dim3(1), dim3(1), 0, s, &c.status->unresolved, cur_cnt);
+        HUSKY_TRY(hipGetLastError());
     }
     HUSKY_TRY(fixup_medium(fa, c.tiers, tn.t_medium, s));
     HUSKY_TRY(fixup_small(fa, c.tiers, tn.t_small, s));
