@@ -9,12 +9,14 @@ detection, tiered fix-up) of the collision-heavy workload: 2^24 ASCII strings,
 random 12-character prefixes plus a 4..20 character suffix (seed 1).  Inputs
 are resident in HBM before the timed region starts.  Prints one JSON line.
 
-The roofline object is for the radix onesweep pass (the kernel with the most
-time): its algorithmic traffic is 24 bytes per string per launch (read and
-write of the 8-byte code and the 4-byte index), divided by the pass's average
-launch duration measured with HIP events on the library's stream during the
-timed steps.  The CPU baseline is the plain oracle (single thread) on the same
-input.
+The roofline object is for the radix scatter pass (k_scatter, the kernel with
+the most time): its algorithmic traffic is 24 bytes per string per launch
+(read and write of the 8-byte code and the 4-byte index), divided by the
+pass's average launch duration measured with HIP events on the library's
+stream during the timed steps.  `traffic` is the HBM bytes per launch from
+the committed FETCH_SIZE / WRITE_SIZE counter summary (null once radix.hip has
+changed since).  The CPU baseline is the plain oracle (single thread) on the
+same input.
 """
 
 from __future__ import annotations
@@ -30,17 +32,30 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
-COUNTERS_FILE = os.path.join(ROOT, "profiles", "radix_onesweep_config2_counters.txt")
+COUNTERS_FILE = os.path.join(ROOT, "profiles", "radix_scatter_config2_counters.txt")
 RADIX_SRC = os.path.join(ROOT, "paper_2012_00866_amd", "csrc", "radix.hip")
 
 
+def _function_text(src: str, signature: str) -> str:
+    """Text of one function from its signature line to the closing brace at column 0."""
+    i = src.index(signature)
+    j = src.index("\n}\n", i)
+    return src[i:j + 3]
+
+
 def _src_sha(path: str) -> str:
-    with open(path, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    """Hash of the scatter kernel's own source: k_scatter, rank_tile and load_striped."""
+    with open(path) as f:
+        src = f.read()
+    parts = [_function_text(src, sig) for sig in (
+        "__device__ __forceinline__ void rank_tile(",
+        "__device__ __forceinline__ void load_striped(",
+        "__global__ __launch_bounds__(BLOCK) void k_scatter(")]
+    return hashlib.sha256("".join(parts).encode()).hexdigest()[:16]
 
 
 def _traffic_per_launch():
-    """HBM bytes per onesweep launch from the committed counter summary, or None.
+    """HBM bytes per scatter-pass launch from the committed counter summary, or None.
 
     Only used while radix.hip is byte-identical to the source the counters
     were taken from."""
@@ -83,6 +98,10 @@ def main(argv=None):
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--n", type=int, default=1 << 24, help="strings (default 2^24)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run a 256 MiB device copy (calibrates HBM byte counters)")
+    ap.add_argument("--mode", choices=["plain", "batched"], default="plain",
+                    help="plain: the metric's workload; batched: 4,096 instances vs a loop of plain sorts")
     args = ap.parse_args(argv)
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the sort is not "
@@ -95,6 +114,15 @@ def main(argv=None):
     from workloads import config2
 
     husky.load()
+    if args.copy_probe:
+        src = torch.ones(256 << 20, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(2):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+    if args.mode == "batched":
+        return bench_batched(args)
     batch = config2(seed=1, n=args.n)
     n = batch.n
     elems, offsets = husky.to_device(batch)
@@ -123,7 +151,7 @@ def main(argv=None):
 
     ms_per_step = (t1 - t0) * 1e3 / args.steps
     value = n / (ms_per_step / 1e3) / 1e6
-    os_ms, os_launches = prof["radix_onesweep"]
+    os_ms, os_launches = prof["radix_scatter"]
     avg_ms = os_ms / max(os_launches, 1)
     algo_bytes = 24.0 * n
     achieved = algo_bytes / (avg_ms / 1e3) / 1e9 if avg_ms > 0 else 0.0
@@ -155,7 +183,7 @@ def main(argv=None):
             "large_rounds": status["large_rounds"],
         },
         "roofline": {
-            "kernel": "radix onesweep pass",
+            "kernel": "radix scatter pass (k_scatter)",
             "bound": "hbm",
             "achieved": round(achieved, 1),
             "peak": HBM_PEAK_GBS,
@@ -171,6 +199,99 @@ def main(argv=None):
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = _cpu_baseline(batch)
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+def _time(fn, steps, warmup):
+    import torch
+
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) * 1e3 / steps
+
+
+def bench_batched(args):
+    """4,096 instances (config 4): one batched call vs a loop of plain calls, tuned and graph forms."""
+    import numpy as np
+    import torch
+
+    import paper_2012_00866_amd as husky
+    from paper_2012_00866_amd import tuner
+    from workloads import config4
+
+    t_gen = time.perf_counter()
+    batch = config4(seed=1)
+    t_gen = time.perf_counter() - t_gen
+    n, S = batch.n, batch.seg_offsets.size - 1
+    elems, offsets = husky.to_device(batch)
+    seg = torch.from_numpy(batch.seg_offsets.view(np.int64)).cuda()
+    ws = husky.alloc_workspace(n, S)
+    perm = torch.empty(n, dtype=torch.int32, device="cuda")
+    max_len = int(np.diff(batch.offsets).max())
+    steps = max(3, min(args.steps, 10))
+
+    def batched(t=None):
+        husky.sort_batched(elems, offsets, seg, "ascii7", tuning=t, ws=ws, perm=perm, check_status=False)
+
+    ms_default = _time(batched, steps, 1)
+    ref = perm.clone()
+    assert husky.check_perm(elems, offsets, ref, "ascii7", seg) == 0, "batched result not exact"
+    res = tuner.tune(elems, offsets, "ascii7", seg, repeats=3)
+    tuned = husky.make_tuning(**res["tuning"])
+    ms_tuned = _time(lambda: batched(tuned), steps, 1)
+    assert torch.equal(perm, ref)
+    # graph: fixed rounds, captured once, replayed
+    fixed = husky.make_tuning(**res["tuning"], max_rounds=husky.rounds_for(max_len))
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        batched(fixed)
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        batched(fixed)
+    ms_graph = _time(g.replay, steps, 1)
+    assert torch.equal(perm, ref) and husky.read_status(ws)["unresolved"] == 0
+    # loop of plain sorts, one call per instance, same tuning
+    ws1 = husky.alloc_workspace(int(np.diff(batch.seg_offsets).max()))
+    offs = [(int(batch.seg_offsets[k]), int(batch.seg_offsets[k + 1])) for k in range(S)]
+
+    def loop():
+        for lo, hi in offs:
+            husky.sort(elems, offsets[lo:hi + 1], "ascii7", tuning=tuned, ws=ws1, perm=perm[lo:hi],
+                       check_status=False)
+
+    ms_loop = _time(loop, max(1, steps // 3), 1)
+    lp = perm.cpu().numpy().view(np.uint32).astype(np.int64)
+    for k, (lo, hi) in enumerate(offs):
+        lp[lo:hi] += lo
+    assert np.array_equal(lp.astype(np.uint32), ref.cpu().numpy().view(np.uint32)), "loop differs"
+    out = {
+        "metric": "Mstrings/s sorted (bit-exact), batched form",
+        "value": round(n / (ms_tuned / 1e3) / 1e6, 3),
+        "unit": "Mstrings/s",
+        "n_gpus": 1,
+        "ms_per_step": round(ms_tuned, 4),
+        "higher_is_better": True,
+        "dtype": "u64",
+        "data": "synthetic",
+        "config": {"workload": "4,096 independent instances of the collision-heavy distribution, "
+                               "sizes log-uniform in [64, 262144]", "n": n, "instances": S,
+                   "seed": 1, "generation_s": round(t_gen, 1)},
+        "forms_ms": {"batched_default": round(ms_default, 3), "batched_tuned": round(ms_tuned, 3),
+                     "batched_graph_replay": round(ms_graph, 3),
+                     "loop_of_plain_sorts": round(ms_loop, 3)},
+        "speedup_batched_vs_loop": round(ms_loop / ms_tuned, 2),
+        "tuning": res["tuning"],
+        "tuner_table": [{"params": r["params"], "ms": round(r["ms"], 3)} for r in res["table"]],
+    }
     print(json.dumps(out), flush=True)
     return 0
 

@@ -185,12 +185,12 @@ husky_status husky_check_perm(husky_coder coder, const void* elems, const uint64
  * launch's stream; husky_profile_end() waits for them and writes, for each
  * kernel class c < n_classes, the summed milliseconds ms[c] and the launch
  * count launches[c] (host arrays), then stops profiling.  Classes:
- * 0 encode, 1 radix histogram, 2 histogram scan, 3 radix onesweep pass,
- * 4 radix copy-back, 5 single-tile LDS sort, 6 run detection (all four
- * kernels), 7 wavefront fix-up, 8 workgroup fix-up, 9 device-wide
- * refinement keys, 10 segment setup, 11 radix onesweep pass of the
- * device-wide fix-up (class 3 counts only the sort of the codes).  Not for
- * use during graph capture.
+ * 0 encode, 1 radix varying-bit reduction and pass masks, 2 radix digit
+ * counts and their scans, 3 radix scatter pass, 4 radix copy-back,
+ * 5 single-tile LDS sort, 6 run detection, 7 wavefront fix-up, 8 workgroup
+ * fix-up, 9 device-wide refinement keys, 10 segment setup, 11 radix scatter
+ * pass of the device-wide fix-up (class 3 counts only the sort of the
+ * codes).  Not for use during graph capture.
  * Returns HUSKY_OK or HUSKY_ERR_HIP. */
 void husky_profile_begin(void);
 int husky_profile_end(double* ms, uint32_t* launches, int n_classes);

@@ -62,9 +62,9 @@ EXPORTS = ("husky_workspace_bytes", "husky_encode", "husky_sort_pairs", "husky_f
            "husky_profile_end", "husky_status_string")
 
 # kernel classes of husky_profile_end (include/husky.h)
-PROFILE_CLASSES = ("encode", "radix_hist", "radix_hist_scan", "radix_onesweep", "radix_copy_back",
+PROFILE_CLASSES = ("encode", "radix_vary", "radix_count_scan", "radix_scatter", "radix_copy_back",
                    "tile_sort", "runs", "fixup_small", "fixup_medium", "large_keys", "segment_setup",
-                   "radix_onesweep_fixup")
+                   "radix_scatter_fixup")
 
 
 def load(path: str = LIB_PATH):

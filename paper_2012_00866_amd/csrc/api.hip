@@ -230,7 +230,7 @@ husky_status run_fixup(Ctx& c, const Tune& tn, int coder, const void* elems,
             if (!fixed) HUSKY_TRY(read_u32(c.counters + C_EXEC_UNION, &pass_union, s));
         }
         HUSKY_TRY(radix_sort_segments(keys, idx, keys_alt, c.at<uint32_t>(c.L.idx_b), 0, 64, nl,
-                                      big_tiles, pass_union, c.rad, tn.rc, P_ONESWEEP_FIX, s));
+                                      big_tiles, pass_union, c.rad, tn.rc, P_SCATTER_FIX, s));
         TierLists t2 = c.tiers;
         t2.large = nxt;
         t2.large_count = nxt_cnt;
@@ -297,7 +297,7 @@ husky_status husky_sort_pairs(uint64_t* codes, uint32_t* idx, uint64_t n, int be
     HUSKY_TRY(radix_reduce_tiles(codes, tb, c.rad, tn.rc, s));
     HUSKY_TRY(radix_exec_masks(begin_bit, end_bit, 1, tb, c.rad, tn.rc, s));
     HUSKY_TRY(radix_sort_segments(codes, idx, c.at<uint64_t>(c.L.codes_b), c.at<uint32_t>(c.L.idx_b),
-                                  begin_bit, end_bit, 1, tb, ~0u, c.rad, tn.rc, P_ONESWEEP, s));
+                                  begin_bit, end_bit, 1, tb, ~0u, c.rad, tn.rc, P_SCATTER, s));
     return HUSKY_OK;
 }
 
@@ -359,7 +359,7 @@ static husky_status sort_common(husky_coder coder, const void* elems, const uint
     HUSKY_TRY(radix_reduce_tiles(codes, tb, c.rad, tn.rc, s));
     HUSKY_TRY(radix_exec_masks(0, end_bit, (uint32_t)n_segs, tb, c.rad, tn.rc, s));
     HUSKY_TRY(radix_sort_segments(codes, perm, codes_b, c.at<uint32_t>(c.L.idx_b), 0, end_bit,
-                                  (uint32_t)n_segs, tb, ~0u, c.rad, tn.rc, P_ONESWEEP, s));
+                                  (uint32_t)n_segs, tb, ~0u, c.rad, tn.rc, P_SCATTER, s));
     // the sorted codes are not needed once the runs are listed, so the
     // device-wide fix-up reuses both code buffers for its keys
     return run_fixup(c, tn, coder, elems, offsets, n, n_segs, codes, codes, codes_b, perm, s);

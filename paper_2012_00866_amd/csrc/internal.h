@@ -11,9 +11,9 @@ namespace husky {
 
 // ---- profile.hip: per-launch HIP-event timing, off unless husky_profile_begin ran
 enum ProfClass {
-    P_ENCODE = 0, P_HIST = 1, P_HIST_SCAN = 2, P_ONESWEEP = 3, P_COPY_BACK = 4, P_TILE_SORT = 5,
+    P_ENCODE = 0, P_VARY = 1, P_COUNT_SCAN = 2, P_SCATTER = 3, P_COPY_BACK = 4, P_TILE_SORT = 5,
     P_RUNS = 6, P_FIX_SMALL = 7, P_FIX_MEDIUM = 8, P_LARGE_KEYS = 9, P_SETUP = 10,
-    P_ONESWEEP_FIX = 11, P_NUM = 12
+    P_SCATTER_FIX = 11, P_NUM = 12
 };
 bool prof_on();
 class ProfScope {

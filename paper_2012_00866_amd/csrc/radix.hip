@@ -663,7 +663,7 @@ static hipError_t exec_impl(int begin_bit, int end_bit, uint32_t max_segs, uint3
                             const RadixScratch& sc, hipStream_t s) {
     max_tiles = std::min(max_tiles, sc.big_tile_cap);
     const uint32_t max_big = std::min(std::min(sc.big_cap, max_tiles / 2 + 1), std::max(max_segs, 1u));
-    ProfScope ps(P_HIST, s);
+    ProfScope ps(P_VARY, s);
     hipLaunchKernelGGL((k_exec<BITS>), dim3(max_big), dim3(BLOCK), 0, s, sc.bigs, sc.counters,
                        sc.korand, begin_bit, end_bit);
     return hipGetLastError();
@@ -694,7 +694,7 @@ static hipError_t sort_impl(uint64_t* keys, uint32_t* vals, uint64_t* keys_alt,
         const int shift = begin_bit + p * BITS;
         const uint32_t dmask = (1u << std::min(BITS, end_bit - shift)) - 1u;  // top digit may be narrower
         {
-            ProfScope ps(P_HIST_SCAN, s);
+            ProfScope ps(P_COUNT_SCAN, s);
             hipLaunchKernelGGL((k_count<BITS, ITEMS>), dim3(max_tiles), dim3(BLOCK), 0, s, keys,
                                keys_alt, bigs, sc.counters, sc.cnt, p, shift, dmask);
             hipLaunchKernelGGL((k_group_scan<BITS>), dim3(max_groups), dim3(BLOCK), 0, s, bigs,
@@ -717,7 +717,7 @@ hipError_t radix_reduce_tiles(const uint64_t* keys, uint32_t max_tiles, const Ra
                               const RadixConfig& cfg, hipStream_t s) {
     max_tiles = std::min(max_tiles, sc.big_tile_cap);
     if (!max_tiles) return hipSuccess;
-    ProfScope ps(P_HIST, s);
+    ProfScope ps(P_VARY, s);
     if (cfg.items == 16)
         hipLaunchKernelGGL((k_orand<16>), dim3(max_tiles), dim3(BLOCK), 0, s, keys, sc.bigs, sc.counters, sc.korand);
     else if (cfg.items == 12)
