@@ -1,0 +1,197 @@
+"""Float64 oracle of the learned-CDF model -- test infrastructure only.
+
+The model is a monotone MLP 1 -> 64 -> 64 -> 1 with ReLU activations whose
+weights are softplus of free parameters (so every weight is positive and the
+output never decreases as the input grows); with monotone=False the raw
+parameters are the weights (the deliberately unconstrained variant).
+Parameter vector layout (4,353 floats): v1[64], b1[64], v2[64][64] (row =
+output unit), b2[64], v3[64], b3.  Loss: mean squared error against target
+CDF values.
+
+The fit's deterministic parts are here too, from their definitions: the
+SplitMix64 sample indices, the 24-bit cell of a code, the dense cells of a
+sorted sample, the cumulative distribution the LUT quantises, and the
+equal-depth splitters.
+
+Everything here is written from the definitions with numpy in float64; it
+shares nothing with the HIP kernels.
+"""
+
+from __future__ import annotations
+
+import numpy as np
+
+H = 64
+P = H + H + H * H + H + H + 1  # 4353
+
+
+def split(p):
+    p = np.asarray(p, dtype=np.float64)
+    o = 0
+    v1 = p[o:o + H]; o += H
+    b1 = p[o:o + H]; o += H
+    v2 = p[o:o + H * H].reshape(H, H); o += H * H
+    b2 = p[o:o + H]; o += H
+    v3 = p[o:o + H]; o += H
+    b3 = p[o]
+    return v1, b1, v2, b2, v3, b3
+
+
+def softplus(v):
+    return np.logaddexp(0.0, v)
+
+
+def sigmoid(v):
+    return 1.0 / (1.0 + np.exp(-v))
+
+
+def _weight(v, monotone):
+    return softplus(v) if monotone else v
+
+
+def _dweight(v, monotone):
+    return sigmoid(v) if monotone else np.ones_like(v)
+
+
+def forward(p, x, monotone=True):
+    """Network output for inputs x (float64 array)."""
+    v1, b1, v2, b2, v3, b3 = split(p)
+    x = np.asarray(x, dtype=np.float64)
+    z1 = np.outer(x, _weight(v1, monotone)) + b1
+    h1 = np.maximum(z1, 0.0)
+    z2 = h1 @ _weight(v2, monotone).T + b2
+    h2 = np.maximum(z2, 0.0)
+    return h2 @ _weight(v3, monotone) + b3
+
+
+def loss(p, x, y, monotone=True):
+    d = forward(p, x, monotone) - np.asarray(y, dtype=np.float64)
+    return float(np.mean(d * d))
+
+
+def grad(p, x, y, monotone=True):
+    """(loss, gradient w.r.t. the parameter vector) by the chain rule."""
+    v1, b1, v2, b2, v3, b3 = split(p)
+    x = np.asarray(x, dtype=np.float64)
+    y = np.asarray(y, dtype=np.float64)
+    B = x.shape[0]
+    w1, w2, w3 = _weight(v1, monotone), _weight(v2, monotone), _weight(v3, monotone)
+    z1 = np.outer(x, w1) + b1
+    h1 = np.maximum(z1, 0.0)
+    z2 = h1 @ w2.T + b2
+    h2 = np.maximum(z2, 0.0)
+    out = h2 @ w3 + b3
+    d = out - y
+    L = float(np.mean(d * d))
+    g_out = 2.0 * d / B
+    dw3 = h2.T @ g_out
+    db3 = g_out.sum()
+    dz2 = np.outer(g_out, w3) * (z2 > 0)
+    dw2 = dz2.T @ h1
+    db2 = dz2.sum(axis=0)
+    dz1 = (dz2 @ w2) * (z1 > 0)
+    dw1 = dz1.T @ x
+    db1 = dz1.sum(axis=0)
+    g = np.concatenate([dw1 * _dweight(v1, monotone), db1,
+                        (dw2 * _dweight(v2, monotone)).ravel(), db2,
+                        dw3 * _dweight(v3, monotone), [db3]])
+    return L, g
+
+
+def numeric_grad(p, x, y, idx, h=1e-6, monotone=True):
+    """Central finite differences of the loss at the given parameter indices."""
+    p = np.asarray(p, dtype=np.float64).copy()
+    out = []
+    for i in idx:
+        old = p[i]
+        p[i] = old + h
+        lp = loss(p, x, y, monotone)
+        p[i] = old - h
+        lm = loss(p, x, y, monotone)
+        p[i] = old
+        out.append((lp - lm) / (2 * h))
+    return np.array(out)
+
+
+# ----------------------------------------------------------------- the fit's deterministic parts
+BUCKETS = 65536
+CELLS = 1 << 24
+_M64 = (1 << 64) - 1
+_GOLDEN = 0x9E3779B97F4A7C15
+
+
+def splitmix64(x: int) -> int:
+    """SplitMix64 output for state x (Steele, Lea and Flood, OOPSLA 2014)."""
+    z = (x + _GOLDEN) & _M64
+    z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & _M64
+    z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & _M64
+    return z ^ (z >> 31)
+
+
+def sample_indices(n: int, S: int, seed: int) -> np.ndarray:
+    """String j of the sample: splitmix64(seed + golden * (j + 1)) mod n (with replacement)."""
+    return np.array([splitmix64((seed + _GOLDEN * (j + 1)) & _M64) % n for j in range(S)],
+                    dtype=np.int64)
+
+
+def header(sorted_sample):
+    """(lo, hi, cp): the sample extremes and the bits of their common prefix."""
+    lo, hi = int(sorted_sample[0]), int(sorted_sample[-1])
+    cp = 64 if lo == hi else 64 - (lo ^ hi).bit_length()
+    return lo, hi, cp
+
+
+def cell(code: int, lo: int, hi: int, cp: int) -> int:
+    """The 24 bits right below the common prefix of the code clamped to [lo, hi]."""
+    c = min(max(int(code), lo), hi)
+    if cp >= 64:
+        return 0
+    return ((c << cp) & _M64) >> 40
+
+
+def dense_cells(sorted_sample, B: int = BUCKETS):
+    """Cells holding count * B >= 2 * S sample keys: (cells ascending, dense keys
+    before each cell (one more entry: all dense keys), per-key flag)."""
+    lo, hi, cp = header(sorted_sample)
+    S = len(sorted_sample)
+    w = np.array([cell(c, lo, hi, cp) for c in sorted_sample], dtype=np.int64)
+    cells, counts = np.unique(w, return_counts=True)
+    dense = cells[counts.astype(np.int64) * B >= 2 * S]
+    flag = np.isin(w, dense)
+    cum = [0]
+    for d in dense:
+        cum.append(cum[-1] + int(np.sum(w == d)))
+    return dense, np.array(cum, dtype=np.int64), flag
+
+
+def cdf_table(f_of_x, dense, cum, S: int):
+    """The non-decreasing table of 0.32 fixed-point F(W) for W in [0, 2^24]:
+    F(W) = (dense keys in cells < W + (S - dense keys) * f(W / 2^24)) / S,
+    then a running maximum, with F(0) = 0 and F(2^24) = 2^32 - 1."""
+    W = np.arange(CELLS + 1, dtype=np.int64)
+    x = W.astype(np.float64) / CELLS
+    before = cum[np.searchsorted(dense, W, side="left")] if len(dense) else np.zeros_like(W)
+    F = (before + (S - cum[-1]) * np.clip(f_of_x(x), 0.0, 1.0)) / S
+    q = np.minimum(np.floor(F * 4294967295.0), 4294967295.0).astype(np.int64)
+    q[0] = 0
+    q[-1] = 4294967295
+    return np.maximum.accumulate(q)
+
+
+def splitters(lut, sorted_sample, B: int = BUCKETS):
+    """For every cell owning k >= 2 buckets [b0, b1): splitter i (1 <= i < k) =
+    the cell's sample key of rank floor(i * m / k) (m = its sample keys),
+    stored at b0 + i - 1; all ones when the cell has no sample keys.
+    Returns {bucket slot: splitter}."""
+    lo, hi, cp = header(sorted_sample)
+    w = np.array([cell(c, lo, hi, cp) for c in sorted_sample], dtype=np.int64)
+    b = (lut.astype(np.int64) * B) >> 32
+    owned = b[1:] - b[:-1]
+    out = {}
+    for W in np.nonzero(owned >= 2)[0]:
+        b0, k = int(b[W]), int(owned[W])
+        s_lo = int(np.searchsorted(w, W, side="left"))
+        m = int(np.searchsorted(w, W, side="right")) - s_lo
+        for i in range(1, k):
+            out[b0 + i - 1] = int(sorted_sample[s_lo + (i * m) // k]) if m else _M64
+    return out
