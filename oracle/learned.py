@@ -149,14 +149,19 @@ def cell(code: int, lo: int, hi: int, cp: int) -> int:
     return ((c << cp) & _M64) >> 40
 
 
-def dense_cells(sorted_sample, B: int = BUCKETS):
-    """Cells holding count * B >= 2 * S sample keys: (cells ascending, dense keys
-    before each cell (one more entry: all dense keys), per-key flag)."""
+DENSE_MIN = 16
+
+
+def dense_cells(sorted_sample, B: int = BUCKETS, min_count: int = DENSE_MIN):
+    """Cells holding count * B >= 2 * S sample keys and at least min_count of
+    them: (cells ascending, dense keys before each cell (one more entry: all
+    dense keys), per-key flag)."""
     lo, hi, cp = header(sorted_sample)
     S = len(sorted_sample)
     w = np.array([cell(c, lo, hi, cp) for c in sorted_sample], dtype=np.int64)
     cells, counts = np.unique(w, return_counts=True)
-    dense = cells[counts.astype(np.int64) * B >= 2 * S]
+    c = counts.astype(np.int64)
+    dense = cells[(c * B >= 2 * S) & (c >= min_count)]
     flag = np.isin(w, dense)
     cum = [0]
     for d in dense:

@@ -108,17 +108,21 @@ def test_dense_cells_brute_force():
     # B = 8 buckets, S = 16 keys: dense when a cell holds >= 4 sample keys
     lo = 0
     hi = (1 << 63) - 1  # cp = 1: the cell is bits 62..39
-    cells = [3, 3, 3, 3, 3, 9, 9, 12, 12, 12, 12, 20, 21, 22, 23, 0xFFFFFF]
+    cells = [3, 3, 3, 3, 3, 3, 9, 9, 12, 12, 12, 12, 20, 21, 22, 0xFFFFFF]
     sample = np.array(sorted(c << 39 for c in cells), dtype=object)
     sample[0] = lo
     sample[-1] = hi
-    dense, cum, flag = learned.dense_cells(sample, B=8)
+    dense, cum, flag = learned.dense_cells(sample, B=8, min_count=1)
     w = [learned.cell(int(c), lo, hi, 1) for c in sample]
     counts = {c: w.count(c) for c in set(w)}
     expect = sorted(c for c, k in counts.items() if k * 8 >= 2 * 16)
     assert list(dense) == expect == [3, 12]
     assert list(cum) == [0, counts[3], counts[3] + counts[12]]
     assert int(flag.sum()) == cum[-1]
+    # the floor on the count: cell 3 keeps 5 keys (the first became lo), cell
+    # 12 has 4, so only cell 3 is dense with min_count 5
+    dense5, cum5, _ = learned.dense_cells(sample, B=8, min_count=5)
+    assert list(dense5) == [3] and list(cum5) == [0, counts[3]]
 
 
 def test_cdf_table_closed_forms():
