@@ -44,13 +44,14 @@ def _function_text(src: str, signature: str) -> str:
 
 
 def _src_sha(path: str) -> str:
-    """Hash of the scatter kernel's own source: k_scatter, rank_tile and load_striped."""
+    """Hash of the scatter kernel's own source: rank_tile and load_striped (rank.h), k_scatter."""
+    with open(os.path.join(os.path.dirname(path), "rank.h")) as f:
+        rank = f.read()
     with open(path) as f:
         src = f.read()
-    parts = [_function_text(src, sig) for sig in (
-        "__device__ __forceinline__ void rank_tile(",
-        "__device__ __forceinline__ void load_striped(",
-        "__global__ __launch_bounds__(BLOCK) void k_scatter(")]
+    parts = [_function_text(rank, "__device__ __forceinline__ void rank_tile("),
+             _function_text(rank, "__device__ __forceinline__ void load_striped("),
+             _function_text(src, "__global__ __launch_bounds__(BLOCK) void k_scatter(")]
     return hashlib.sha256("".join(parts).encode()).hexdigest()[:16]
 
 

@@ -35,7 +35,7 @@
  * Memory.  Every pointer argument is a DEVICE pointer owned by the caller,
  * unless marked "host".  The library allocates no device memory: scratch
  * space comes from the caller's workspace `ws`, at least
- * husky_workspace_bytes(n, n_segs) bytes, 256-byte aligned.  The first 16
+ * husky_workspace_bytes(n, n_segs) bytes, 256-byte aligned.  The first 24
  * bytes of the workspace are the device status block (husky_device_status
  * below), written by every call that takes `ws`.
  *
@@ -79,6 +79,8 @@ typedef struct {
     uint32_t large_rounds;      /* device-wide refinement rounds the last fix-up ran */
     uint32_t runs_fixed;        /* equal-code runs (length >= 2) the last fix-up visited */
     uint32_t unresolved;        /* groups left tied after max_rounds fixed rounds (else 0) */
+    uint32_t overflow_buckets;  /* learned form: buckets holding more than one radix tile */
+    uint32_t overflow_keys;     /* learned form: strings in those buckets */
 } husky_device_status;
 
 /* Launch tuning.  Zero in a field selects the library default.  The values
@@ -190,10 +192,137 @@ husky_status husky_check_perm(husky_coder coder, const void* elems, const uint64
  * 5 single-tile LDS sort, 6 run detection, 7 wavefront fix-up, 8 workgroup
  * fix-up, 9 device-wide refinement keys, 10 segment setup, 11 radix scatter
  * pass of the device-wide fix-up (class 3 counts only the sort of the
- * codes).  Not for use during graph capture.
+ * codes), 12 learned bucket scatter pass, 13 learned bucket ids, 14 learned
+ * bucket bounds.  Not for use during graph capture.
  * Returns HUSKY_OK or HUSKY_ERR_HIP. */
 void husky_profile_begin(void);
 int husky_profile_end(double* ms, uint32_t* launches, int n_classes);
+
+/* ---------------------------------------------------------------------
+ * Learned-CDF form (an extension of the method, not part of the paper).
+ *
+ * A model maps every code to one of HUSKY_LEARNED_BUCKETS buckets by a
+ * function that never decreases as the code grows, so sorting the pairs
+ * becomes: bucket ids, a stable scatter of (code, index) into bucket order,
+ * and independent sorts of the buckets by code -- in LDS for buckets of at
+ * most one radix tile, by the multi-tile radix passes for larger ("overflow")
+ * buckets.  Step 3 then runs as in husky_sort.  Since equal codes always
+ * share a bucket and buckets are in code order, the permutation is exactly
+ * husky_sort's whatever the model's quality; a poor model only costs time.
+ *
+ * The bucket function, for a model fitted on a sample of codes:
+ *   - clamp the code to [lo, hi], the sample's extremes; W = its 24 bits
+ *     right below the common prefix of lo and hi (a "cell"), x = W / 2^24;
+ *   - cells holding at least two buckets' worth of the sample and at least
+ *     16 sample keys ("dense cells", unless HUSKY_LEARNED_NO_DENSE) take their sample share of the
+ *     buckets exactly; the network models the cumulative distribution of the
+ *     remaining sample keys over x:  F(W) = (dense sample keys in cells
+ *     below W + (other sample keys) * net(x)) / sample size;
+ *   - LUT[W] = F(W) in 0.32 fixed point for all 2^24 + 1 cell starts, made
+ *     non-decreasing by a running maximum (whatever the network computes),
+ *     LUT[0] = 0, LUT[2^24] = 2^32 - 1; cell W owns the buckets
+ *     [LUT[W] * B >> 32, LUT[W + 1] * B >> 32);
+ *   - a cell owning k >= 2 buckets splits its codes by k - 1 equal-depth
+ *     splitters taken from the cell's sorted sample codes.
+ * The network: 1 -> 64 -> 64 -> 1, ReLU after both hidden layers, every
+ * weight softplus(raw parameter) > 0 (so it never decreases in x), output
+ * clamped to [0, 1]; trained in FP32 by mean squared error against the
+ * targets (rank + 0.5) / count with Adam, on the GPU.
+ */
+#define HUSKY_LEARNED_BUCKETS 65536u
+#define HUSKY_LEARNED_HIDDEN 64
+#define HUSKY_LEARNED_NPARAM 4353 /* v1[64] b1[64] v2[64][64] b2[64] v3[64] b3 */
+#define HUSKY_LEARNED_CELLS (1u << 24)
+#define HUSKY_LEARNED_NO_DENSE 1u /* husky_learned_params.flags: the network alone */
+
+typedef enum {
+    HUSKY_LEARNED_MONOTONE = 0,      /* the trained monotone network (default) */
+    HUSKY_LEARNED_UNCONSTRAINED = 1, /* raw weights, trained: not monotone (tests) */
+    HUSKY_LEARNED_EQUAL_WIDTH = 2,   /* no network: net(x) = x (equal-width cells) */
+    HUSKY_LEARNED_UNTRAINED = 3,     /* the monotone network at its initialisation */
+    HUSKY_LEARNED_CONSTANT = 4       /* no network: net(x) = 0 (tests) */
+} husky_learned_mode;
+
+/* Fit parameters; a zero field selects the default. */
+typedef struct {
+    double sample_frac; /* fraction of the strings sampled, (0, 1]; default 0.01 */
+    uint64_t seed;      /* sample and initialisation seed; default 1 */
+    uint32_t epochs;    /* default 6 */
+    uint32_t batch;     /* samples per Adam step; default 16384 */
+    float lr;           /* Adam step size; default 0.01 */
+    uint32_t mode;      /* husky_learned_mode */
+    uint32_t flags;     /* HUSKY_LEARNED_NO_DENSE */
+    uint32_t reserved;
+} husky_learned_params;
+
+/* First bytes of the model buffer (device memory). */
+typedef struct {
+    uint64_t lo, hi;     /* sample extremes */
+    uint32_t cp;         /* common-prefix bits of lo and hi (64 if equal) */
+    uint32_t buckets;    /* B */
+    uint32_t mode;       /* husky_learned_mode */
+    uint32_t sample;     /* sample size S */
+    uint32_t steps;      /* Adam steps taken */
+    float last_loss;     /* mean loss of the last epoch */
+    uint32_t heavy;      /* cells owning two or more buckets */
+    uint32_t dense;      /* dense cells */
+    uint32_t dense_keys; /* sample keys in dense cells */
+    uint32_t trained;    /* sample keys the network was trained on */
+    uint32_t flags;
+    uint32_t pad[5];
+} husky_learned_header;
+
+/* Parts of the model buffer, for husky_learned_offset. */
+typedef enum {
+    HUSKY_LM_HEADER = 0,    /* husky_learned_header */
+    HUSKY_LM_PARAMS = 1,    /* float[NPARAM], raw parameters */
+    HUSKY_LM_ADAM_M = 2,    /* float[NPARAM] */
+    HUSKY_LM_ADAM_V = 3,    /* float[NPARAM] */
+    HUSKY_LM_LUT = 4,       /* uint32[2^24 + 1] */
+    HUSKY_LM_SPLITTERS = 5, /* uint64[B] */
+    HUSKY_LM_DENSE = 6,     /* uint32[B / 2] dense cells, ascending */
+    HUSKY_LM_DENSE_CUM = 7  /* uint32[B / 2 + 1] dense sample keys before each */
+} husky_learned_part;
+
+/* Size of the model buffer, and the byte offset of each part in it (SIZE_MAX
+ * for an unknown part). */
+size_t husky_learned_model_bytes(void);
+size_t husky_learned_offset(int part);
+
+/* Workspace bytes of husky_learned_fit and husky_sort_learned for n strings. */
+size_t husky_learned_workspace_bytes(uint64_t n);
+
+/* Fit the model: draw S = ceil(sample_frac * n) string indices by a seeded
+ * counter-based hash (with replacement), code them with Step 1, sort the
+ * sample codes (Step 2), find the dense cells, train the network on the
+ * other sample keys, then build the LUT and the splitters.  `model` (device,
+ * husky_learned_model_bytes(), 256-aligned) is overwritten.  Synchronizes
+ * `stream` once (to size the training loop).  params may be NULL.  Domain
+ * violations among the sampled strings are counted in the status block.
+ * Errors: HUSKY_ERR_ARG (n == 0, bad params), HUSKY_ERR_WORKSPACE,
+ * HUSKY_ERR_HIP. */
+husky_status husky_learned_fit(husky_coder coder, const void* elems, const uint64_t* offsets,
+                               uint64_t n, const husky_learned_params* params, void* model,
+                               size_t model_bytes, void* ws, size_t ws_bytes, void* stream);
+
+/* Sort with a fitted model.  perm receives the stable sorting permutation,
+ * identical to husky_sort's.  The status block reports domain violations and
+ * overflow_buckets / overflow_keys.  With tuning->max_rounds == 0 the call
+ * synchronizes like husky_sort when long equal-code runs exist.
+ * Errors: as husky_sort. */
+husky_status husky_sort_learned(husky_coder coder, const void* elems, const uint64_t* offsets,
+                                uint64_t n, const void* model, uint32_t* perm, void* ws,
+                                size_t ws_bytes, const husky_tuning* tuning, void* stream);
+
+/* The training kernel alone, for checking it: grad (float[NPARAM + 1]) gets
+ * the gradient of the mean squared error of the network (monotone != 0:
+ * softplus weights; 0: raw weights) over the `count` samples (x[i], y[i])
+ * with respect to the raw parameters, and grad[NPARAM] the sum of squared
+ * errors.  ws needs husky_mlp_grad_workspace_bytes(count).
+ * Errors: HUSKY_ERR_ARG, HUSKY_ERR_WORKSPACE, HUSKY_ERR_HIP. */
+size_t husky_mlp_grad_workspace_bytes(uint32_t count);
+husky_status husky_mlp_grad(const float* params, const float* x, const float* y, uint32_t count,
+                            int monotone, float* grad, void* ws, size_t ws_bytes, void* stream);
 
 /* Static text for a status code (host). */
 const char* husky_status_string(husky_status s);

@@ -59,12 +59,42 @@ _lib = None
 
 EXPORTS = ("husky_workspace_bytes", "husky_encode", "husky_sort_pairs", "husky_fixup",
            "husky_sort", "husky_sort_batched", "husky_check_perm", "husky_profile_begin",
-           "husky_profile_end", "husky_status_string")
+           "husky_profile_end", "husky_learned_model_bytes", "husky_learned_offset",
+           "husky_learned_workspace_bytes", "husky_learned_fit", "husky_sort_learned",
+           "husky_mlp_grad_workspace_bytes", "husky_mlp_grad", "husky_status_string")
 
 # kernel classes of husky_profile_end (include/husky.h)
 PROFILE_CLASSES = ("encode", "radix_vary", "radix_count_scan", "radix_scatter", "radix_copy_back",
                    "tile_sort", "runs", "fixup_small", "fixup_medium", "large_keys", "segment_setup",
-                   "radix_scatter_fixup")
+                   "radix_scatter_fixup", "learned_bucket_scatter", "learned_bucket_ids",
+                   "learned_bucket_bounds")
+
+# learned form (include/husky.h)
+LEARNED_BUCKETS = 65536
+LEARNED_NPARAM = 4353
+LEARNED_CELLS = 1 << 24
+LEARNED_MODES = {"monotone": 0, "unconstrained": 1, "equal_width": 2, "untrained": 3,
+                 "constant": 4}
+LEARNED_NO_DENSE = 1
+LM_PARTS = {"header": 0, "params": 1, "adam_m": 2, "adam_v": 3, "lut": 4, "splitters": 5,
+            "dense": 6, "dense_cum": 7}
+
+
+class LearnedParams(ctypes.Structure):
+    _fields_ = [("sample_frac", ctypes.c_double), ("seed", ctypes.c_uint64),
+                ("epochs", ctypes.c_uint32), ("batch", ctypes.c_uint32), ("lr", ctypes.c_float),
+                ("mode", ctypes.c_uint32), ("flags", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32)]
+
+
+class LearnedHeader(ctypes.Structure):
+    _fields_ = [("lo", ctypes.c_uint64), ("hi", ctypes.c_uint64), ("cp", ctypes.c_uint32),
+                ("buckets", ctypes.c_uint32), ("mode", ctypes.c_uint32),
+                ("sample", ctypes.c_uint32), ("steps", ctypes.c_uint32),
+                ("last_loss", ctypes.c_float), ("heavy", ctypes.c_uint32),
+                ("dense", ctypes.c_uint32), ("dense_keys", ctypes.c_uint32),
+                ("trained", ctypes.c_uint32), ("flags", ctypes.c_uint32),
+                ("pad", ctypes.c_uint32 * 5)]
 
 
 def load(path: str = LIB_PATH):
@@ -95,6 +125,21 @@ def load(path: str = LIB_PATH):
     lib.husky_profile_begin.argtypes = []
     lib.husky_profile_end.restype = i32
     lib.husky_profile_end.argtypes = [vp, vp, i32]
+    lib.husky_learned_model_bytes.restype = sz
+    lib.husky_learned_model_bytes.argtypes = []
+    lib.husky_learned_offset.restype = sz
+    lib.husky_learned_offset.argtypes = [i32]
+    lib.husky_learned_workspace_bytes.restype = sz
+    lib.husky_learned_workspace_bytes.argtypes = [u64]
+    lib.husky_learned_fit.restype = i32
+    lib.husky_learned_fit.argtypes = [i32, vp, vp, u64, ctypes.POINTER(LearnedParams), vp, sz, vp,
+                                      sz, vp]
+    lib.husky_sort_learned.restype = i32
+    lib.husky_sort_learned.argtypes = [i32, vp, vp, u64, vp, vp, vp, sz, tp, vp]
+    lib.husky_mlp_grad_workspace_bytes.restype = sz
+    lib.husky_mlp_grad_workspace_bytes.argtypes = [ctypes.c_uint32]
+    lib.husky_mlp_grad.restype = i32
+    lib.husky_mlp_grad.argtypes = [vp, vp, vp, ctypes.c_uint32, i32, vp, vp, sz, vp]
     lib.husky_status_string.restype = ctypes.c_char_p
     lib.husky_status_string.argtypes = [i32]
     _lib = lib
@@ -136,11 +181,14 @@ def alloc_workspace(n: int, n_segs: int = 1, device="cuda"):
     return torch.empty(workspace_bytes(n, n_segs), dtype=torch.uint8, device=device)
 
 
+STATUS_FIELDS = ("domain_violations", "large_rounds", "runs_fixed", "unresolved",
+                 "overflow_buckets", "overflow_keys")
+
+
 def read_status(ws) -> dict:
-    """Device status block (first 16 bytes of the workspace); synchronizes."""
-    v = ws[:16].cpu().numpy().view(np.uint32)
-    return {"domain_violations": int(v[0]), "large_rounds": int(v[1]), "runs_fixed": int(v[2]),
-            "unresolved": int(v[3])}
+    """Device status block (first 24 bytes of the workspace); synchronizes."""
+    v = ws[:4 * len(STATUS_FIELDS)].cpu().numpy().view(np.uint32)
+    return {f: int(v[i]) for i, f in enumerate(STATUS_FIELDS)}
 
 
 def to_device(batch, device="cuda"):
@@ -255,6 +303,97 @@ def check_perm(elems, offsets, perm, coder="ascii7", seg_offsets=None, stream=No
                                 _ptr(perm), _ptr(ws), ws.numel(), _ptr(out), _stream(stream)),
            "husky_check_perm")
     return int(out.item())
+
+
+# ----------------------------------------------------------------- learned form
+def learned_model_bytes() -> int:
+    return int(load().husky_learned_model_bytes())
+
+
+def learned_offset(part) -> int:
+    return int(load().husky_learned_offset(LM_PARTS[part] if isinstance(part, str) else int(part)))
+
+
+def learned_workspace_bytes(n: int) -> int:
+    return int(load().husky_learned_workspace_bytes(int(n)))
+
+
+def alloc_learned_workspace(n: int, device="cuda"):
+    torch = _torch()
+    return torch.empty(learned_workspace_bytes(n), dtype=torch.uint8, device=device)
+
+
+def make_learned_params(sample_frac=0.0, seed=0, epochs=0, batch=0, lr=0.0, mode="monotone",
+                        dense=True) -> LearnedParams:
+    m = LEARNED_MODES[mode] if isinstance(mode, str) else int(mode)
+    return LearnedParams(float(sample_frac), int(seed), int(epochs), int(batch), float(lr), m,
+                         0 if dense else LEARNED_NO_DENSE, 0)
+
+
+def fit_learned(elems, offsets, coder="ascii7", params: Optional[LearnedParams] = None,
+                model=None, ws=None, stream=None):
+    """Fit the learned-CDF model on a sample of the strings; returns the model buffer."""
+    torch = _torch()
+    lib = load()
+    n = _n_of(offsets)
+    if model is None:
+        model = torch.empty(learned_model_bytes(), dtype=torch.uint8, device=offsets.device)
+    if ws is None:
+        ws = alloc_learned_workspace(n, offsets.device)
+    _check(lib.husky_learned_fit(_coder(coder), _ptr(elems), _ptr(offsets), n,
+                                 ctypes.byref(params) if params else None, _ptr(model),
+                                 model.numel(), _ptr(ws), ws.numel(), _stream(stream)),
+           "husky_learned_fit")
+    return model
+
+
+def learned_header(model) -> dict:
+    """Header of a fitted model (synchronizes)."""
+    raw = model[:ctypes.sizeof(LearnedHeader)].cpu().numpy().tobytes()
+    h = LearnedHeader.from_buffer_copy(raw)
+    return {f: getattr(h, f) for f, _ in LearnedHeader._fields_ if f != "pad"}
+
+
+def learned_part(model, part, dtype, count):
+    """A view of one part of the model buffer as a typed device tensor."""
+    torch = _torch()
+    off = learned_offset(part)
+    size = torch.empty(0, dtype=dtype).element_size()
+    return model[off:off + count * size].view(dtype)
+
+
+def sort_learned(elems, offsets, model, coder="ascii7", tuning: Optional[Tuning] = None, ws=None,
+                 perm=None, stream=None, check_status=True):
+    """Learned-CDF form: the same stable permutation as sort(), bucketed by the model."""
+    torch = _torch()
+    lib = load()
+    n = _n_of(offsets)
+    if ws is None:
+        ws = alloc_learned_workspace(n, offsets.device)
+    if perm is None:
+        perm = torch.empty(max(n, 1), dtype=torch.int32, device=offsets.device)
+    _check(lib.husky_sort_learned(_coder(coder), _ptr(elems), _ptr(offsets), n, _ptr(model),
+                                  _ptr(perm), _ptr(ws), ws.numel(),
+                                  ctypes.byref(tuning) if tuning else None, _stream(stream)),
+           "husky_sort_learned")
+    if check_status:
+        st = read_status(ws)
+        if st["domain_violations"]:
+            raise DomainError(2, f"husky_sort_learned ({st['domain_violations']} strings)")
+    return perm[:n]
+
+
+def mlp_grad(params, x, y, monotone=True, stream=None):
+    """Gradient (float32[NPARAM]) and summed squared error of the network on (x, y)."""
+    torch = _torch()
+    lib = load()
+    count = int(x.numel())
+    ws = torch.empty(int(lib.husky_mlp_grad_workspace_bytes(count)), dtype=torch.uint8,
+                     device=x.device)
+    g = torch.empty(LEARNED_NPARAM + 1, dtype=torch.float32, device=x.device)
+    _check(lib.husky_mlp_grad(_ptr(params), _ptr(x), _ptr(y), count, 1 if monotone else 0,
+                              _ptr(g), _ptr(ws), ws.numel(), _stream(stream)), "husky_mlp_grad")
+    return g[:LEARNED_NPARAM], g[LEARNED_NPARAM]
 
 
 def profile_begin():

@@ -4,6 +4,7 @@
 // runs.hip and fixup.hip (Step 3).
 
 #include <algorithm>
+#include <cmath>
 
 #include "../../include/husky.h"
 #include "common.h"
@@ -20,16 +21,25 @@ constexpr uint32_t MAX_T_SMALL = 64;
 
 size_t align_up(size_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
 
-// Byte offsets of every region inside the caller's workspace.
+// Learned form: training workgroups at most, and the per-workgroup
+// gradient partials they need.
+constexpr uint32_t LEARN_MAX_BLOCKS = 256;
+
+// Byte offsets of every region inside the caller's workspace.  The learned
+// form adds the bucket ids (two u16 arrays), the bucket bounds and the
+// training scratch; its fit borrows the sort's regions for the sample (see
+// husky_learned_fit).
 struct Layout {
     size_t status, counters, codes_a, codes_b, idx_b, key0, segs, bigs, korand, binstart, cnt, gtot,
-        tile_counts, run_start, run_end, small, medium, large_a, large_b, total;
+        tile_counts, run_start, run_end, small, medium, large_a, large_b, bid, bseg, lpartial, lgrad,
+        ltmax, total;
     uint32_t seg_cap, big_cap, tile_cap, big_tile_cap, group_cap, run_cap, small_cap, medium_cap,
         large_cap;
 };
 
-Layout make_layout(uint64_t n, uint64_t n_segs) {
+Layout make_layout(uint64_t n, uint64_t n_segs, bool learned = false) {
     Layout L{};
+    if (learned) n_segs = std::max<uint64_t>(n_segs, LEARNED_BUCKETS);
     const uint64_t S = n_segs ? n_segs : 1;
     L.large_cap = (uint32_t)(n / (MIN_T_MEDIUM + 1) + 2);
     L.seg_cap = (uint32_t)std::max<uint64_t>(S, L.large_cap);
@@ -68,6 +78,13 @@ Layout make_layout(uint64_t n, uint64_t n_segs) {
     L.medium = take((size_t)L.medium_cap * sizeof(RunItem));
     L.large_a = take((size_t)L.large_cap * sizeof(RunItem));
     L.large_b = take((size_t)L.large_cap * sizeof(RunItem));
+    if (learned) {
+        L.bid = take(n * 4);
+        L.bseg = take(((size_t)LEARNED_BUCKETS + 1) * 8);
+        L.lpartial = take(learned_partial_bytes(LEARN_MAX_BLOCKS));
+        L.lgrad = take(((size_t)learned_nparam() + 1) * 4 + 256);
+        L.ltmax = take((size_t)learned_lut_tiles() * 4);
+    }
     L.total = o;
     return L;
 }
@@ -92,9 +109,9 @@ struct Ctx {
     }
 };
 
-Ctx make_ctx(void* ws, uint64_t n, uint64_t n_segs) {
+Ctx make_ctx(void* ws, uint64_t n, uint64_t n_segs, bool learned = false) {
     Ctx c;
-    c.L = make_layout(n, n_segs);
+    c.L = make_layout(n, n_segs, learned);
     c.ws = (uint8_t*)ws;
     c.status = c.at<husky_device_status>(c.L.status);
     c.counters = c.at<uint32_t>(c.L.counters);
@@ -152,12 +169,15 @@ husky_status resolve_tuning(const husky_tuning* t, Tune* out) {
     return HUSKY_OK;
 }
 
-husky_status check_ws(void* ws, size_t ws_bytes, uint64_t n, uint64_t n_segs) {
+husky_status check_ws(void* ws, size_t ws_bytes, uint64_t n, uint64_t n_segs,
+                      bool learned = false) {
     if (!ws) return HUSKY_ERR_WORKSPACE;
     if (((uintptr_t)ws) % ALIGN) return HUSKY_ERR_WORKSPACE;
-    if (ws_bytes < make_layout(n, n_segs).total) return HUSKY_ERR_WORKSPACE;
+    if (ws_bytes < make_layout(n, n_segs, learned).total) return HUSKY_ERR_WORKSPACE;
     return HUSKY_OK;
 }
+
+constexpr size_t STATUS_WORDS = sizeof(husky_device_status) / sizeof(uint32_t);
 
 __global__ void k_set_u32(uint32_t* p, uint32_t v) { *p = v; }
 __global__ void k_copy_u32(uint32_t* dst, const uint32_t* src) { *dst = *src; }
@@ -317,7 +337,7 @@ husky_status husky_fixup(husky_coder coder, const void* elems, const uint64_t* o
     if (st != HUSKY_OK) return st;
     hipStream_t s = (hipStream_t)stream;
     Ctx c = make_ctx(ws, n, n_segs);
-    HUSKY_TRY(zero_u32((uint32_t*)c.status, 4, s));
+    HUSKY_TRY(zero_u32((uint32_t*)c.status, STATUS_WORDS, s));
     if (n < 2) return HUSKY_OK;
     if (seg_offsets_or_null)
         HUSKY_TRY(radix_segments_from_offsets(seg_offsets_or_null, (uint32_t)n_segs, c.rad, tn.rc, s));
@@ -344,7 +364,7 @@ static husky_status sort_common(husky_coder coder, const void* elems, const uint
     if (st != HUSKY_OK) return st;
     hipStream_t s = (hipStream_t)stream;
     Ctx c = make_ctx(ws, n, n_segs);
-    HUSKY_TRY(zero_u32((uint32_t*)c.status, 4, s));
+    HUSKY_TRY(zero_u32((uint32_t*)c.status, STATUS_WORDS, s));
     if (n == 0) return HUSKY_OK;
     uint64_t* codes = c.at<uint64_t>(c.L.codes_a);
     uint64_t* codes_b = c.at<uint64_t>(c.L.codes_b);
@@ -378,6 +398,145 @@ husky_status husky_sort_batched(husky_coder coder, const void* elems, const uint
     if (!seg_offsets || n_segs == 0 || n_segs >= (1ull << 32)) return HUSKY_ERR_ARG;
     return sort_common(coder, elems, offsets, n, seg_offsets, n_segs, perm, ws, ws_bytes, tuning,
                        stream);
+}
+
+// ---------------------------------------------------------------- learned form
+
+size_t husky_learned_model_bytes(void) { return learned_model_bytes(); }
+size_t husky_learned_offset(int part) { return learned_model_offset(part); }
+size_t husky_learned_workspace_bytes(uint64_t n) { return make_layout(n, 1, true).total; }
+
+static husky_status check_model(const void* model, size_t model_bytes) {
+    if (!model || ((uintptr_t)model) % ALIGN) return HUSKY_ERR_ARG;
+    if (model_bytes < learned_model_bytes()) return HUSKY_ERR_ARG;
+    return HUSKY_OK;
+}
+
+husky_status husky_learned_fit(husky_coder coder, const void* elems, const uint64_t* offsets,
+                               uint64_t n, const husky_learned_params* params, void* model,
+                               size_t model_bytes, void* ws, size_t ws_bytes, void* stream) {
+    husky_status st = check_common(coder, elems, offsets, n);
+    if (st != HUSKY_OK) return st;
+    if (n == 0) return HUSKY_ERR_ARG;
+    if ((st = check_model(model, model_bytes)) != HUSKY_OK) return st;
+    husky_learned_params p{0.01, 1, 6, 16384, 0.01f, HUSKY_LEARNED_MONOTONE, 0, 0};
+    if (params) {
+        if (params->sample_frac != 0.0) p.sample_frac = params->sample_frac;
+        if (params->seed) p.seed = params->seed;
+        if (params->epochs) p.epochs = params->epochs;
+        if (params->batch) p.batch = params->batch;
+        if (params->lr != 0.f) p.lr = params->lr;
+        p.mode = params->mode;
+        p.flags = params->flags;
+    }
+    if (!(p.sample_frac > 0.0 && p.sample_frac <= 1.0)) return HUSKY_ERR_ARG;
+    if (p.mode > HUSKY_LEARNED_CONSTANT || (p.flags & ~HUSKY_LEARNED_NO_DENSE)) return HUSKY_ERR_ARG;
+    if (p.epochs > 10000 || !(p.lr > 0.f)) return HUSKY_ERR_ARG;
+    if ((st = check_ws(ws, ws_bytes, n, 1, true)) != HUSKY_OK) return st;
+    hipStream_t s = (hipStream_t)stream;
+    Ctx c = make_ctx(ws, n, 1, true);
+    const Layout& L = c.L;
+    const uint32_t S = (uint32_t)std::min<uint64_t>(
+        n, std::max<uint64_t>(1, (uint64_t)std::ceil(p.sample_frac * (double)n)));
+    // sample regions, borrowed from the sort's (S <= n): indices in the bucket
+    // id region, codes in the two code buffers, the indices the sort carries
+    // in run_start / idx_b, training pairs in key0, flags in run_end, tile
+    // sums in the small-run list
+    uint32_t* sel = c.at<uint32_t>(L.bid);
+    uint64_t* sc = c.at<uint64_t>(L.codes_a);
+    uint32_t* sv = c.at<uint32_t>(L.run_start);
+    float* x = c.at<float>(L.key0);
+    float* y = x + S;
+    uint8_t* fl = c.at<uint8_t>(L.run_end);
+    uint2* tsum = c.at<uint2>(L.small);
+    float* grad = c.at<float>(L.lgrad);
+    float* loss_acc = grad + learned_nparam() + 1;
+    HUSKY_TRY(zero_u32((uint32_t*)c.status, STATUS_WORDS, s));
+    HUSKY_TRY(learned_sample(sel, S, (uint32_t)n, p.seed, s));
+    HUSKY_TRY(launch_encode(coder, elems, offsets, (uint32_t)n, sc, sv, nullptr,
+                            &c.status->domain_violations, s, sel, S));
+    Tune tn;
+    (void)resolve_tuning(nullptr, &tn);  // library defaults
+    const int end_bit = coder == HUSKY_CODER_ASCII7 ? 63 : 64;
+    if (S > 1) {
+        HUSKY_TRY(radix_segments_single(S, c.rad, tn.rc, s));
+        const uint32_t tb = tiles_bound(S, 1, tn.rc);
+        HUSKY_TRY(radix_reduce_tiles(sc, tb, c.rad, tn.rc, s));
+        HUSKY_TRY(radix_exec_masks(0, end_bit, 1, tb, c.rad, tn.rc, s));
+        HUSKY_TRY(radix_sort_segments(sc, sv, c.at<uint64_t>(L.codes_b), c.at<uint32_t>(L.idx_b), 0,
+                                      end_bit, 1, tb, ~0u, c.rad, tn.rc, P_SCATTER, s));
+    }
+    HUSKY_TRY(learned_prepare(model, sc, S, p.mode, p.flags, fl, tsum, x, y, s));
+    uint32_t dense_keys = 0;
+    HUSKY_TRY(read_u32(learned_dense_keys_ptr(model), &dense_keys, s));
+    const uint32_t count = S - std::min(dense_keys, S);
+    HUSKY_TRY(learned_init(model, p.seed, p.mode == HUSKY_LEARNED_UNCONSTRAINED, s));
+    const bool train = p.mode == HUSKY_LEARNED_MONOTONE || p.mode == HUSKY_LEARNED_UNCONSTRAINED;
+    HUSKY_TRY(learned_train(model, x, y, train ? count : 0u, p.epochs, p.batch, p.lr,
+                            p.mode != HUSKY_LEARNED_UNCONSTRAINED, c.at<float>(L.lpartial),
+                            LEARN_MAX_BLOCKS, grad, loss_acc, s));
+    HUSKY_TRY(learned_build_lut(model, p.mode, c.at<uint32_t>(L.ltmax), s));
+    HUSKY_TRY(learned_splitters(model, sc, S, s));
+    return HUSKY_OK;
+}
+
+husky_status husky_sort_learned(husky_coder coder, const void* elems, const uint64_t* offsets,
+                                uint64_t n, const void* model, uint32_t* perm, void* ws,
+                                size_t ws_bytes, const husky_tuning* tuning, void* stream) {
+    husky_status st = check_common(coder, elems, offsets, n);
+    if (st != HUSKY_OK) return st;
+    if (n > 0 && !perm) return HUSKY_ERR_ARG;
+    if ((st = check_model(model, learned_model_bytes())) != HUSKY_OK) return st;
+    Tune tn;
+    if ((st = resolve_tuning(tuning, &tn)) != HUSKY_OK) return st;
+    if ((st = check_ws(ws, ws_bytes, n, 1, true)) != HUSKY_OK) return st;
+    hipStream_t s = (hipStream_t)stream;
+    Ctx c = make_ctx(ws, n, 1, true);
+    const Layout& L = c.L;
+    HUSKY_TRY(zero_u32((uint32_t*)c.status, STATUS_WORDS, s));
+    if (n == 0) return HUSKY_OK;
+    uint64_t* codes = c.at<uint64_t>(L.codes_a);
+    uint64_t* codes_b = c.at<uint64_t>(L.codes_b);
+    uint32_t* idx_b = c.at<uint32_t>(L.idx_b);
+    uint16_t* bid_a = c.at<uint16_t>(L.bid);
+    uint16_t* bid_b = bid_a + n;
+    uint64_t* bseg = c.at<uint64_t>(L.bseg);
+    const uint32_t nn = (uint32_t)n;
+    HUSKY_TRY(launch_encode(coder, elems, offsets, nn, codes, perm, c.at<uint64_t>(L.key0),
+                            &c.status->domain_violations, s));
+    // bucket ids, then two stable 8-bit passes over them (low byte, high byte)
+    HUSKY_TRY(learned_bucket_ids(model, codes, nn, bid_a, s));
+    HUSKY_TRY(learned_bucket_pass(0, codes, perm, bid_a, codes_b, idx_b, bid_b, nn, c.rad.cnt,
+                                  c.rad.gtot, c.rad.binstart, s));
+    HUSKY_TRY(learned_bucket_pass(1, codes_b, idx_b, bid_b, codes, perm, bid_a, nn, c.rad.cnt,
+                                  c.rad.gtot, c.rad.binstart, s));
+    HUSKY_TRY(learned_bucket_bounds(bid_a, nn, bseg, &c.status->overflow_buckets, tn.rc.tile(), s));
+    // every bucket sorted by code: one tile in LDS, larger ones by the
+    // multi-tile passes
+    const uint32_t B = LEARNED_BUCKETS;
+    HUSKY_TRY(radix_segments_from_offsets(bseg, B, c.rad, tn.rc, s));
+    const int end_bit = coder == HUSKY_CODER_ASCII7 ? 63 : 64;
+    const uint32_t tb = tiles_bound(n, B, tn.rc);
+    HUSKY_TRY(radix_reduce_tiles(codes, tb, c.rad, tn.rc, s));
+    HUSKY_TRY(radix_exec_masks(0, end_bit, B, tb, c.rad, tn.rc, s));
+    HUSKY_TRY(radix_sort_segments(codes, perm, codes_b, idx_b, 0, end_bit, B, tb, ~0u, c.rad, tn.rc,
+                                  P_SCATTER, s));
+    // equal codes share a bucket, so runs never cross bucket boundaries
+    return run_fixup(c, tn, coder, elems, offsets, n, B, codes, codes, codes_b, perm, s);
+}
+
+size_t husky_mlp_grad_workspace_bytes(uint32_t count) {
+    const uint32_t blocks = std::max(1u, std::min(LEARN_MAX_BLOCKS, (count + 255) / 256));
+    return learned_partial_bytes(blocks);
+}
+
+husky_status husky_mlp_grad(const float* params, const float* x, const float* y, uint32_t count,
+                            int monotone, float* grad, void* ws, size_t ws_bytes, void* stream) {
+    if (!params || !grad) return HUSKY_ERR_ARG;
+    if (count > 0 && (!x || !y)) return HUSKY_ERR_ARG;
+    if (!ws || ws_bytes < husky_mlp_grad_workspace_bytes(count)) return HUSKY_ERR_WORKSPACE;
+    return hip_status(learned_grad(params, x, y, count, monotone != 0, (float*)ws, LEARN_MAX_BLOCKS,
+                                   grad, (hipStream_t)stream));
 }
 
 const char* husky_status_string(husky_status s) {

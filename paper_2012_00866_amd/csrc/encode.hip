@@ -26,12 +26,16 @@ __global__ __launch_bounds__(BLOCK) void k_encode(const uint8_t* __restrict__ by
                                                   uint64_t* __restrict__ codes,
                                                   uint32_t* __restrict__ idx,
                                                   uint64_t* __restrict__ key0,
-                                                  uint32_t* __restrict__ status) {
+                                                  uint32_t* __restrict__ status,
+                                                  const uint32_t* __restrict__ sel,
+                                                  uint32_t n_out) {
     // bytes in the element buffer (uniform scalar load): the three-word
     // window below is used only where it stays inside the buffer.
     const uint64_t total_bytes = offsets[n] * (CODER == 0 ? 1u : 2u);
     uint32_t bad_here = 0;
-    for (uint32_t i = blockIdx.x * BLOCK + threadIdx.x; i < n; i += gridDim.x * BLOCK) {
+    const uint32_t count = sel ? n_out : n;
+    for (uint32_t t = blockIdx.x * BLOCK + threadIdx.x; t < count; t += gridDim.x * BLOCK) {
+        const uint32_t i = sel ? sel[t] : t;
         const uint64_t o0 = offsets[i], o1 = offsets[i + 1];
         const uint64_t len = o1 - o0;
         // string bytes 0..7 (lo) and 8..15 (mid), little-endian; bytes past
@@ -90,9 +94,9 @@ __global__ __launch_bounds__(BLOCK) void k_encode(const uint8_t* __restrict__ by
                 k0 = ((uint64_t)L << 60) | (ch << 12) | clen;
             }
         }
-        if (codes) codes[i] = code;
-        if (idx) idx[i] = i;
-        if (key0) key0[i] = k0;
+        if (codes) codes[t] = code;
+        if (idx) idx[t] = i;
+        if (key0) key0[t] = k0;
     }
     if (CODER == 0 && status) {
         // one atomic per wavefront that saw a violation
@@ -108,16 +112,17 @@ __global__ __launch_bounds__(BLOCK) void k_encode(const uint8_t* __restrict__ by
 
 hipError_t launch_encode(int coder, const void* elems, const uint64_t* offsets, uint32_t n,
                          uint64_t* codes, uint32_t* idx, uint64_t* key0, uint32_t* status,
-                         hipStream_t s) {
-    if (n == 0) return hipSuccess;
-    const uint32_t blocks = (n + BLOCK - 1) / BLOCK;
+                         hipStream_t s, const uint32_t* sel, uint32_t n_out) {
+    const uint32_t count = sel ? n_out : n;
+    if (count == 0) return hipSuccess;
+    const uint32_t blocks = (count + BLOCK - 1) / BLOCK;
     ProfScope ps(P_ENCODE, s);
     if (coder == 0)
         hipLaunchKernelGGL(k_encode<0>, dim3(blocks), dim3(BLOCK), 0, s, (const uint8_t*)elems,
-                           offsets, n, codes, idx, key0, status);
+                           offsets, n, codes, idx, key0, status, sel, n_out);
     else
         hipLaunchKernelGGL(k_encode<1>, dim3(blocks), dim3(BLOCK), 0, s, (const uint8_t*)elems,
-                           offsets, n, codes, idx, key0, status);
+                           offsets, n, codes, idx, key0, status, sel, n_out);
     return hipGetLastError();
 }
 

@@ -150,7 +150,8 @@ __global__ __launch_bounds__(BLOCK) void k_fix_medium(const RunItem* __restrict_
                                                       uint32_t cap, const uint8_t* __restrict__ bytes,
                                                       const uint64_t* __restrict__ offsets,
                                                       uint32_t n, uint32_t* __restrict__ idx,
-                                                      const uint64_t* __restrict__ key0) {
+                                                      const uint64_t* __restrict__ key0,
+                                                      uint32_t lmin, uint32_t lmax) {
     const uint64_t total_bytes = offsets[n] * (CODER == 0 ? 1u : 2u);
     extern __shared__ __align__(16) uint8_t lds_raw[];
     MediumLds<MAXL>& S = *reinterpret_cast<MediumLds<MAXL>*>(lds_raw);
@@ -159,6 +160,7 @@ __global__ __launch_bounds__(BLOCK) void k_fix_medium(const RunItem* __restrict_
     for (uint32_t it = blockIdx.x; it < n_items; it += gridDim.x) {
         const RunItem r = items[it];
         const uint32_t L = r.len;
+        if (L <= lmin || L > lmax || L > (uint32_t)MAXL) continue;  // another size class's launch
         uint32_t L2 = 1;
         while (L2 < L) L2 <<= 1;
         for (uint32_t j = tid; j < L2; j += BLOCK) {
@@ -327,8 +329,12 @@ hipError_t fixup_small(const FixupArgs& a, const TierLists& tl, uint32_t, hipStr
     return hipGetLastError();
 }
 
+// One launch per size class of the medium list, each sized for its longest
+// run: a class of short runs needs little LDS, so many workgroups share a CU
+// and hide the latency of the idx / key / string gathers.
 template <int CODER, int MAXL>
-static hipError_t medium_impl(const FixupArgs& a, const TierLists& tl, hipStream_t s) {
+static hipError_t medium_impl(const FixupArgs& a, const TierLists& tl, uint32_t lmin,
+                              uint32_t lmax, hipStream_t s) {
     const size_t lds = sizeof(MediumLds<MAXL>);
     static bool attr_set = false;
     if (!attr_set) {
@@ -337,25 +343,29 @@ static hipError_t medium_impl(const FixupArgs& a, const TierLists& tl, hipStream
         if (e != hipSuccess) return e;
         attr_set = true;
     }
-    const uint32_t per_cu = lds > 80 * 1024 ? 1 : (lds > 52 * 1024 ? 2 : 3);
+    const uint32_t per_cu = (uint32_t)std::max<size_t>(1, std::min<size_t>(8, (160 * 1024) / lds));
     const uint32_t blocks = persistent_blocks() * per_cu;
     ProfScope ps(P_FIX_MEDIUM, s);
     hipLaunchKernelGGL((k_fix_medium<CODER, MAXL>), dim3(blocks), dim3(BLOCK), lds, s, tl.medium,
                        tl.medium_count, tl.medium_cap, (const uint8_t*)a.elems, a.offsets, a.n,
-                       a.idx, a.key0);
+                       a.idx, a.key0, lmin, lmax);
     return hipGetLastError();
+}
+
+template <int CODER>
+static hipError_t medium_classes(const FixupArgs& a, const TierLists& tl, uint32_t t_medium,
+                                 hipStream_t s) {
+    hipError_t e = medium_impl<CODER, 256>(a, tl, 0, std::min(t_medium, 256u), s);
+    if (e != hipSuccess || t_medium <= 256) return e;
+    e = medium_impl<CODER, 1024>(a, tl, 256, std::min(t_medium, 1024u), s);
+    if (e != hipSuccess || t_medium <= 1024) return e;
+    if (t_medium <= 2048) return medium_impl<CODER, 2048>(a, tl, 1024, t_medium, s);
+    return medium_impl<CODER, 4096>(a, tl, 1024, t_medium, s);
 }
 
 hipError_t fixup_medium(const FixupArgs& a, const TierLists& tl, uint32_t t_medium,
                         hipStream_t s) {
-    if (a.coder == 0) {
-        if (t_medium <= 1024) return medium_impl<0, 1024>(a, tl, s);
-        if (t_medium <= 2048) return medium_impl<0, 2048>(a, tl, s);
-        return medium_impl<0, 4096>(a, tl, s);
-    }
-    if (t_medium <= 1024) return medium_impl<1, 1024>(a, tl, s);
-    if (t_medium <= 2048) return medium_impl<1, 2048>(a, tl, s);
-    return medium_impl<1, 4096>(a, tl, s);
+    return a.coder == 0 ? medium_classes<0>(a, tl, t_medium, s) : medium_classes<1>(a, tl, t_medium, s);
 }
 
 hipError_t fixup_large_keys(const FixupArgs& a, const RunItem* items, const RadixScratch& seg,

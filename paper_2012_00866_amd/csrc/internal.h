@@ -13,7 +13,7 @@ namespace husky {
 enum ProfClass {
     P_ENCODE = 0, P_VARY = 1, P_COUNT_SCAN = 2, P_SCATTER = 3, P_COPY_BACK = 4, P_TILE_SORT = 5,
     P_RUNS = 6, P_FIX_SMALL = 7, P_FIX_MEDIUM = 8, P_LARGE_KEYS = 9, P_SETUP = 10,
-    P_SCATTER_FIX = 11, P_NUM = 12
+    P_SCATTER_FIX = 11, P_BUCKET = 12, P_BUCKET_MAP = 13, P_BUCKET_BOUNDS = 14, P_NUM = 15
 };
 bool prof_on();
 class ProfScope {
@@ -28,10 +28,10 @@ class ProfScope {
 
 // ---- encode.hip
 // codes, idx and key0 (the first refinement key of every string) may each be
-// null.
+// null.  With sel, entry i codes string sel[i] (i < n_out) instead of string i.
 hipError_t launch_encode(int coder, const void* elems, const uint64_t* offsets, uint32_t n,
                          uint64_t* codes, uint32_t* idx, uint64_t* key0, uint32_t* status,
-                         hipStream_t s);
+                         hipStream_t s, const uint32_t* sel = nullptr, uint32_t n_out = 0);
 
 // ---- radix.hip
 struct RadixConfig {
@@ -137,6 +137,35 @@ hipError_t fixup_medium(const FixupArgs& a, const TierLists& tl, uint32_t t_medi
 hipError_t fixup_large_keys(const FixupArgs& a, const RunItem* items, const RadixScratch& seg,
                             const RadixConfig& cfg, uint32_t max_tiles, uint64_t* keys,
                             hipStream_t s);
+
+// ---- learned.hip
+constexpr uint32_t LEARNED_BUCKETS = 65536;
+size_t learned_model_bytes();
+size_t learned_model_offset(int part);
+uint32_t learned_nparam();
+uint32_t learned_lut_tiles();
+size_t learned_partial_bytes(uint32_t max_blocks);
+uint32_t learned_pass_tiles(uint32_t n);
+const uint32_t* learned_dense_keys_ptr(void* model);
+hipError_t learned_sample(uint32_t* sel, uint32_t S, uint32_t n, uint64_t seed, hipStream_t s);
+hipError_t learned_prepare(void* model, const uint64_t* sorted_sample, uint32_t S, uint32_t mode,
+                           uint32_t flags, uint8_t* fl, uint2* tsum, float* x, float* y,
+                           hipStream_t s);
+hipError_t learned_init(void* model, uint64_t seed, bool raw, hipStream_t s);
+hipError_t learned_grad(const float* params, const float* x, const float* y, uint32_t count,
+                        bool mono, float* partial, uint32_t max_blocks, float* grad, hipStream_t s);
+hipError_t learned_train(void* model, const float* x, const float* y, uint32_t count,
+                         uint32_t epochs, uint32_t batch, float lr, bool mono, float* partial,
+                         uint32_t max_blocks, float* grad, float* loss_acc, hipStream_t s);
+hipError_t learned_build_lut(void* model, uint32_t mode, uint32_t* tmax, hipStream_t s);
+hipError_t learned_splitters(void* model, const uint64_t* sorted_sample, uint32_t S, hipStream_t s);
+hipError_t learned_bucket_ids(const void* model, const uint64_t* codes, uint32_t n, uint16_t* bid,
+                              hipStream_t s);
+hipError_t learned_bucket_pass(int pass, const uint64_t* ks, const uint32_t* vs, const uint16_t* bs,
+                               uint64_t* kd, uint32_t* vd, uint16_t* bd, uint32_t n, uint32_t* cnt,
+                               uint32_t* gtot, uint32_t* binstart, hipStream_t s);
+hipError_t learned_bucket_bounds(const uint16_t* bid, uint32_t n, uint64_t* seg, uint32_t* overflow,
+                                 uint32_t tile, hipStream_t s);
 
 // Chunk geometry of the refinement keys.
 constexpr int ascii_m = 9, ascii_chunk = 7;

@@ -1,0 +1,1050 @@
+// Learned-CDF form of the code sort.
+//
+// A small monotone network maps the top bits of a husky code to its
+// approximate rank (a cumulative distribution), so that one pass can send
+// every (code, index) pair near its final place: the sort becomes a bucket
+// scatter plus independent sorts of small buckets.  The paper's coder is
+// order-preserving (Sec. 3.2); the bucket function built here is made
+// order-preserving too, which is what keeps the result exact:
+//
+//  * window: codes are clamped to [lo, hi] (the sample's range) and W = the
+//    24 bits right below the common prefix of lo and hi, so W never
+//    decreases as the code grows;
+//  * network 1 -> 64 -> 64 -> 1, ReLU, every weight = softplus(parameter) > 0,
+//    so its output never decreases in x = W / 2^24; trained in FP32 on a
+//    seeded 1 % sample of codes (targets (rank + 0.5) / S) with mean squared
+//    error and Adam, by the forward/backward/update kernels below;
+//  * LUT[W] = network(W / 2^24) quantised to u32 for all 2^24 + 1 cell
+//    starts, then a running maximum, so the table is monotone whatever the
+//    network does (LUT[0] = 0, LUT[2^24] = 2^32 - 1);
+//  * cell W owns buckets [b(W), b(W+1)), b(W) = LUT[W] * B >> 32.  A cell
+//    owning two or more buckets splits its keys by equal-depth splitters
+//    taken from the sorted sample (full 64-bit codes), so even a cell that
+//    holds one heavy key prefix is spread over its share of buckets;
+//  * bucket ids (16 bits, B = 65,536) drive two stable 8-bit LSD passes that
+//    move (code, index, id); each bucket then holds its keys in input order,
+//    and the segmented radix sort of radix.hip sorts every bucket by code:
+//    buckets of at most one tile in LDS, larger ("overflowing") buckets by
+//    its multi-tile passes.  Runs of equal codes never cross buckets, so the
+//    fix-up that follows is the plain path's.
+
+#include <algorithm>
+#include <cmath>
+
+#include "../../include/husky.h"
+#include "common.h"
+#include "internal.h"
+#include "rank.h"
+
+namespace husky {
+
+constexpr int HID = 64;
+constexpr int NPARAM = HID + HID + HID * HID + HID + HID + 1;  // 4353
+constexpr int O_V1 = 0, O_B1 = HID, O_V2 = 2 * HID, O_B2 = 2 * HID + HID * HID, O_V3 = O_B2 + HID,
+              O_B3 = O_V3 + HID;
+constexpr uint32_t LUT_CELLS = 1u << 24;
+constexpr int MLP_T = 256;  // threads (and samples per round) of the training kernel
+
+using LearnedHeader = husky_learned_header;
+static_assert(sizeof(LearnedHeader) <= 256, "header fits its slot");
+
+struct ModelView {
+    LearnedHeader* hdr;
+    float* params;
+    float* adam_m;
+    float* adam_v;
+    uint32_t* lut;        // [LUT_CELLS + 1]
+    uint64_t* splitters;  // [B]
+    uint32_t* dense;      // [B / 2] dense cells, ascending
+    uint32_t* dense_cum;  // [B / 2 + 1] dense sample keys in the dense cells before each
+};
+constexpr uint32_t MAX_DENSE = LEARNED_BUCKETS / 2;
+constexpr uint32_t DENSE_MIN = 16;
+
+static size_t al256(size_t x) { return (x + 255) / 256 * 256; }
+
+// Byte offsets of the model's parts (husky_learned_part order), then the total.
+static void model_offsets(size_t off[9]) {
+    size_t o = 0;
+    const size_t sz[8] = {256, NPARAM * 4, NPARAM * 4, NPARAM * 4, (size_t)(LUT_CELLS + 1) * 4,
+                          (size_t)LEARNED_BUCKETS * 8, (size_t)MAX_DENSE * 4, (size_t)(MAX_DENSE + 1) * 4};
+    for (int i = 0; i < 8; ++i) {
+        off[i] = o;
+        o += al256(sz[i]);
+    }
+    off[8] = o;
+}
+
+static ModelView model_view(void* model) {
+    size_t off[9];
+    model_offsets(off);
+    uint8_t* p = (uint8_t*)model;
+    ModelView m;
+    m.hdr = (LearnedHeader*)(p + off[0]);
+    m.params = (float*)(p + off[1]);
+    m.adam_m = (float*)(p + off[2]);
+    m.adam_v = (float*)(p + off[3]);
+    m.lut = (uint32_t*)(p + off[4]);
+    m.splitters = (uint64_t*)(p + off[5]);
+    m.dense = (uint32_t*)(p + off[6]);
+    m.dense_cum = (uint32_t*)(p + off[7]);
+    return m;
+}
+
+__device__ __forceinline__ float softplusf(float v) { return v > 20.f ? v : log1pf(expf(v)); }
+__device__ __forceinline__ float sigmoidf(float v) { return 1.f / (1.f + expf(-v)); }
+
+// Effective weight of a raw parameter: softplus for the monotone network,
+// the raw value for the deliberately unconstrained one (fault injection).
+template <bool MONO>
+__device__ __forceinline__ float eff(float v) { return MONO ? softplusf(v) : v; }
+template <bool MONO>
+__device__ __forceinline__ float deff(float v) { return MONO ? sigmoidf(v) : 1.f; }
+
+// SplitMix64 (Steele, Lea, Flood 2014): counter-based 64-bit generator.
+__device__ __forceinline__ uint64_t splitmix64(uint64_t x) {
+    x += 0x9E3779B97F4A7C15ull;
+    x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
+    x = (x ^ (x >> 27)) * 0x94D049BB133111EBull;
+    return x ^ (x >> 31);
+}
+__device__ __forceinline__ float unit_noise(uint64_t seed, uint64_t i) {  // in [-1, 1)
+    return (float)((double)(splitmix64(seed * 0x100000001B3ull + i) >> 11) * (1.0 / 9007199254740992.0)) * 2.f - 1.f;
+}
+
+// ------------------------------------------------------------------ init
+// Deterministic start: first-layer knots spread over [0, 1] (w1 ~ 1,
+// b1 = -(j + 0.5) / 64), second layer ~ 1/64, output ~ 1/32, small seeded
+// noise on every parameter; Adam moments zero.  The raw-weight network
+// starts from the same function (its weights are the softplus values).
+__global__ void k_mlp_init(float* params, float* m, float* v, uint64_t seed, int raw) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= NPARAM) return;
+    const float e = 0.05f * unit_noise(seed, (uint64_t)i);
+    float p;
+    if (i < O_B1) p = 0.5413f + e;  // softplus^-1(1)
+    else if (i < O_V2) p = -((float)(i - O_B1) + 0.5f) / HID + 0.1f * e;
+    else if (i < O_B2) p = -4.15f + e;  // softplus^-1(1/64)
+    else if (i < O_V3) p = 0.1f * e;
+    else if (i < O_B3) p = -3.45f + e;  // softplus^-1(1/32)
+    else p = 0.f;
+    const bool weight = i < O_B1 || (i >= O_V2 && i < O_B2) || (i >= O_V3 && i < O_B3);
+    if (raw && weight) p = softplusf(p);
+    params[i] = p;
+    m[i] = 0.f;
+    v[i] = 0.f;
+}
+
+// ------------------------------------------------------------------ forward / backward
+// One workgroup takes `per_block` consecutive samples of the batch in rounds
+// of 256 (one per thread) and writes the gradient of the batch's mean
+// squared error, summed over its samples, to partial[block][NPARAM]; the
+// loss sum goes to partial[block][NPARAM].  Per round, with h1 / h2 the two
+// hidden activations of the round's samples staged in LDS:
+//   forward: each thread its sample's h1, z2 = W2 h1 + b2, out;
+//   dW2 = sum_s dz2_s h1_s^T (4x4 register block per thread), dw3, db2,
+//   db3 by column sums; dz1 = (W2^T dz2) * [h1 > 0], then dw1, db1.
+template <bool MONO>
+__global__ __launch_bounds__(MLP_T) void k_mlp_grad(const float* __restrict__ params,
+                                                    const float* __restrict__ xs,
+                                                    const float* __restrict__ ys, uint32_t first,
+                                                    uint32_t count, uint32_t stride,
+                                                    uint32_t per_block, float inv_batch,
+                                                    float* __restrict__ partial) {
+    extern __shared__ __align__(16) float lds[];
+    float* W2 = lds;                    // [HID][HID] effective weights
+    float* w1 = W2 + HID * HID;         // [HID]
+    float* b1 = w1 + HID;
+    float* b2 = b1 + HID;
+    float* w3 = b2 + HID;
+    float* sx = w3 + HID;               // [MLP_T]
+    float* sg = sx + MLP_T;             // [MLP_T] dL/dout per sample
+    float* h1 = sg + MLP_T;             // [MLP_T][HID + 1]
+    float* h2 = h1 + MLP_T * (HID + 1); // [MLP_T][HID + 1], later dz1
+    __shared__ float s_red[MLP_T / WAVE];
+    const int tid = threadIdx.x;
+    for (int i = tid; i < HID * HID; i += MLP_T) W2[i] = eff<MONO>(params[O_V2 + i]);
+    if (tid < HID) {
+        w1[tid] = eff<MONO>(params[O_V1 + tid]);
+        b1[tid] = params[O_B1 + tid];
+        b2[tid] = params[O_B2 + tid];
+        w3[tid] = eff<MONO>(params[O_V3 + tid]);
+    }
+    const float b3 = params[O_B3];
+    __syncthreads();
+    // per-thread accumulators: a 4x4 block of dW2, and (threads < 64) one
+    // column of dw3 / db2 / dw1 / db1
+    const int kb = (tid / 16) * 4, jb = (tid % 16) * 4;
+    float acc[4][4] = {};
+    float a_w3 = 0.f, a_b2 = 0.f, a_w1 = 0.f, a_b1 = 0.f, a_b3 = 0.f, a_loss = 0.f;
+    const uint32_t s0 = blockIdx.x * per_block;
+    const uint32_t s1 = min(count, s0 + per_block);
+    for (uint32_t base = s0; base < s1; base += MLP_T) {
+        const uint32_t s = base + tid;
+        const bool ok = s < s1;
+        const uint32_t src = first + s * stride;
+        const float x = ok ? xs[src] : 0.f;
+        float z2[HID];
+#pragma unroll
+        for (int k = 0; k < HID; ++k) z2[k] = b2[k];
+        float* hrow = h1 + tid * (HID + 1);
+        for (int j = 0; j < HID; ++j) {
+            const float h = fmaxf(w1[j] * x + b1[j], 0.f);
+            hrow[j] = h;
+#pragma unroll
+            for (int k = 0; k < HID; ++k) z2[k] += W2[k * HID + j] * h;
+        }
+        float out = b3;
+        float* h2row = h2 + tid * (HID + 1);
+#pragma unroll
+        for (int k = 0; k < HID; ++k) {
+            const float h = fmaxf(z2[k], 0.f);
+            h2row[k] = h;
+            out += w3[k] * h;
+        }
+        const float d = ok ? out - ys[src] : 0.f;
+        sx[tid] = x;
+        sg[tid] = 2.f * d * inv_batch;
+        a_loss += d * d;
+        __syncthreads();
+        // weight gradients of the round: column sums over its samples
+        const int nr = (int)min((uint32_t)MLP_T, s1 - base);
+        for (int r = 0; r < nr; ++r) {
+            const float g = sg[r];
+            const float* a = h2 + r * (HID + 1);
+            const float* b = h1 + r * (HID + 1);
+            float dz[4], hv[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                dz[q] = a[kb + q] > 0.f ? g * w3[kb + q] : 0.f;
+                hv[q] = b[jb + q];
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+#pragma unroll
+                for (int u = 0; u < 4; ++u) acc[q][u] += dz[q] * hv[u];
+            if (tid < HID) {
+                a_w3 += g * a[tid];
+                a_b2 += a[tid] > 0.f ? g * w3[tid] : 0.f;
+            }
+            if (tid == 0) a_b3 += g;
+        }
+        __syncthreads();
+        // dz1 of this thread's sample, written over its h2 row
+        {
+            const float g = sg[tid];
+            float dz2v[HID];
+#pragma unroll
+            for (int k = 0; k < HID; ++k) dz2v[k] = h2row[k] > 0.f ? g * w3[k] : 0.f;
+            for (int j = 0; j < HID; ++j) {
+                float dh = 0.f;
+#pragma unroll
+                for (int k = 0; k < HID; ++k) dh += dz2v[k] * W2[k * HID + j];
+                h2row[j] = hrow[j] > 0.f ? dh : 0.f;
+            }
+        }
+        __syncthreads();
+        if (tid < HID) {
+            for (int r = 0; r < nr; ++r) {
+                const float dz1 = h2[r * (HID + 1) + tid];
+                a_w1 += dz1 * sx[r];
+                a_b1 += dz1;
+            }
+        }
+        __syncthreads();
+    }
+    // chain rule through the weight parametrisation, then write this block's sums
+    float* out = partial + (size_t)blockIdx.x * (NPARAM + 1);
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int i = (kb + q) * HID + jb + u;
+            out[O_V2 + i] = acc[q][u] * deff<MONO>(params[O_V2 + i]);
+        }
+    if (tid < HID) {
+        out[O_V1 + tid] = a_w1 * deff<MONO>(params[O_V1 + tid]);
+        out[O_B1 + tid] = a_b1;
+        out[O_B2 + tid] = a_b2;
+        out[O_V3 + tid] = a_w3 * deff<MONO>(params[O_V3 + tid]);
+    }
+    if (tid == 0) out[O_B3] = a_b3;
+    // loss sum
+#pragma unroll
+    for (int dd = 32; dd >= 1; dd >>= 1) a_loss += __shfl_xor(a_loss, dd, WAVE);
+    if (lane_id() == 0) s_red[tid / WAVE] = a_loss;
+    __syncthreads();
+    if (tid == 0) {
+        float t = 0.f;
+        for (int i = 0; i < MLP_T / WAVE; ++i) t += s_red[i];
+        out[NPARAM] = t;
+    }
+}
+
+// Sum of the per-block gradients (and loss) into grad[NPARAM + 1].
+__global__ void k_mlp_reduce(const float* __restrict__ partial, uint32_t blocks,
+                             float* __restrict__ grad) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i > NPARAM) return;
+    float s = 0.f;
+    for (uint32_t b = 0; b < blocks; ++b) s += partial[(size_t)b * (NPARAM + 1) + i];
+    grad[i] = s;
+}
+
+// Adam (Kingma & Ba 2015) on every parameter; loss_acc collects the epoch's
+// loss sum.
+__global__ void k_adam(float* __restrict__ params, float* __restrict__ m, float* __restrict__ v,
+                       const float* __restrict__ grad, float lr, float b1, float b2, float eps,
+                       float c1, float c2, float* __restrict__ loss_acc) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i == 0) *loss_acc += grad[NPARAM];
+    if (i >= NPARAM) return;
+    const float g = grad[i];
+    const float mi = b1 * m[i] + (1.f - b1) * g;
+    const float vi = b2 * v[i] + (1.f - b2) * g * g;
+    m[i] = mi;
+    v[i] = vi;
+    params[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+// ------------------------------------------------------------------ LUT
+// F(W) = (dense sample keys in cells < W + rest * f(W / 2^24)) / S, in 0.32
+// fixed point, for every cell start W in [0, 2^24]; f = the network clamped
+// to [0, 1] (KIND 0), x (KIND 1, equal-width cells) or 0 (KIND 2).
+enum { LUT_NET = 0, LUT_IDENTITY = 1, LUT_ZERO = 2 };
+
+__device__ __forceinline__ uint32_t dense_before(const uint32_t* __restrict__ dense,
+                                                 const uint32_t* __restrict__ dense_cum,
+                                                 uint32_t nd, uint32_t w) {
+    uint32_t a = 0, z = nd;  // dense cells < w
+    while (a < z) {
+        const uint32_t mid = (a + z) >> 1;
+        if (dense[mid] < w) a = mid + 1; else z = mid;
+    }
+    return dense_cum[a];
+}
+
+template <bool MONO, int KIND>
+__global__ __launch_bounds__(256) void k_lut_eval(const float* __restrict__ params,
+                                                  const LearnedHeader* __restrict__ hdr,
+                                                  const uint32_t* __restrict__ dense,
+                                                  const uint32_t* __restrict__ dense_cum,
+                                                  uint32_t* __restrict__ lut) {
+    __shared__ float W2[HID * HID], w1[HID], b1[HID], b2[HID], w3[HID];
+    if (KIND == LUT_NET) {
+        for (int i = threadIdx.x; i < HID * HID; i += 256) W2[i] = eff<MONO>(params[O_V2 + i]);
+        if (threadIdx.x < HID) {
+            w1[threadIdx.x] = eff<MONO>(params[O_V1 + threadIdx.x]);
+            b1[threadIdx.x] = params[O_B1 + threadIdx.x];
+            b2[threadIdx.x] = params[O_B2 + threadIdx.x];
+            w3[threadIdx.x] = eff<MONO>(params[O_V3 + threadIdx.x]);
+        }
+        __syncthreads();
+    }
+    const float b3 = KIND == LUT_NET ? params[O_B3] : 0.f;
+    const uint32_t nd = hdr->dense, S = hdr->sample;
+    const double rest = (double)(S - hdr->dense_keys), invS = 1.0 / (double)S;
+    for (uint32_t c = blockIdx.x * 256 + threadIdx.x; c <= LUT_CELLS; c += gridDim.x * 256) {
+        const float x = (float)c * (1.f / (float)LUT_CELLS);
+        float f;
+        if (KIND == LUT_NET) {
+            float z2[HID];
+#pragma unroll
+            for (int k = 0; k < HID; ++k) z2[k] = b2[k];
+            for (int j = 0; j < HID; ++j) {
+                const float h = fmaxf(w1[j] * x + b1[j], 0.f);
+#pragma unroll
+                for (int k = 0; k < HID; ++k) z2[k] += W2[k * HID + j] * h;
+            }
+            float out = b3;
+#pragma unroll
+            for (int k = 0; k < HID; ++k) out += w3[k] * fmaxf(z2[k], 0.f);
+            f = fminf(fmaxf(out, 0.f), 1.f);
+        } else {
+            f = KIND == LUT_IDENTITY ? x : 0.f;
+        }
+        const double F = ((double)dense_before(dense, dense_cum, nd, c) + rest * (double)f) * invS;
+        uint32_t q = (uint32_t)fmin(F * 4294967295.0, 4294967295.0);
+        if (c == 0) q = 0;
+        if (c == LUT_CELLS) q = 0xFFFFFFFFu;
+        lut[c] = q;
+    }
+}
+
+// Running maximum over the 2^24 + 1 LUT entries: per-tile scan, scan of the
+// tile maxima (one workgroup), then each tile applies its carry.
+constexpr int LUT_TILE = 4096;
+__device__ __forceinline__ uint32_t wave_inclusive_max(uint32_t v) {
+    const uint32_t lane = lane_id();
+#pragma unroll
+    for (int d = 1; d < WAVE; d <<= 1) {
+        const uint32_t t = __shfl_up(v, d, WAVE);
+        if (lane >= (uint32_t)d) v = max(v, t);
+    }
+    return v;
+}
+__global__ __launch_bounds__(256) void k_lut_tilemax(const uint32_t* __restrict__ lut, uint32_t n,
+                                                     uint32_t* __restrict__ tmax) {
+    __shared__ uint32_t s[NWAVES];
+    const uint32_t t0 = blockIdx.x * LUT_TILE;
+    uint32_t m = 0;
+    for (uint32_t i = t0 + threadIdx.x; i < min(n, t0 + LUT_TILE); i += 256) m = max(m, lut[i]);
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) m = max(m, (uint32_t)__shfl_xor(m, d, WAVE));
+    if (lane_id() == 0) s[threadIdx.x / WAVE] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) tmax[blockIdx.x] = max(max(s[0], s[1]), max(s[2], s[3]));
+}
+__global__ __launch_bounds__(256) void k_lut_carry(uint32_t* tmax, uint32_t tiles) {
+    // exclusive running max of the tile maxima (one workgroup)
+    __shared__ uint32_t s[NWAVES];
+    uint32_t carry = 0;
+    for (uint32_t b = 0; b < tiles; b += 256) {
+        const uint32_t i = b + threadIdx.x;
+        const uint32_t v = i < tiles ? tmax[i] : 0u;
+        const uint32_t inc = wave_inclusive_max(v);
+        if (lane_id() == WAVE - 1) s[threadIdx.x / WAVE] = inc;
+        __syncthreads();
+        uint32_t before = carry, all = carry;
+        for (int w = 0; w < NWAVES; ++w) {
+            if (w < (int)(threadIdx.x / WAVE)) before = max(before, s[w]);
+            all = max(all, s[w]);
+        }
+        const uint32_t excl = max(before, __shfl_up(inc, 1, WAVE) * (lane_id() > 0 ? 1u : 0u));
+        __syncthreads();
+        if (i < tiles) tmax[i] = excl;
+        carry = all;
+    }
+}
+__global__ __launch_bounds__(256) void k_lut_apply(uint32_t* __restrict__ lut, uint32_t n,
+                                                   const uint32_t* __restrict__ tcarry) {
+    __shared__ uint32_t s[NWAVES];
+    const uint32_t t0 = blockIdx.x * LUT_TILE;
+    uint32_t carry = tcarry[blockIdx.x];
+    // 16 consecutive entries per thread, scanned in place
+    const uint32_t i0 = t0 + threadIdx.x * 16;
+    uint32_t v[16], m = 0;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+        v[k] = i0 + k < n ? lut[i0 + k] : 0u;
+        m = max(m, v[k]);
+        v[k] = m;
+    }
+    const uint32_t inc = wave_inclusive_max(m);
+    if (lane_id() == WAVE - 1) s[threadIdx.x / WAVE] = inc;
+    __syncthreads();
+    uint32_t before = carry;
+    for (int w = 0; w < (int)(threadIdx.x / WAVE); ++w) before = max(before, s[w]);
+    uint32_t prev = __shfl_up(inc, 1, WAVE);
+    if (lane_id() == 0) prev = 0;
+    before = max(before, prev);
+#pragma unroll
+    for (int k = 0; k < 16; ++k)
+        if (i0 + k < n) lut[i0 + k] = max(before, v[k]);
+}
+
+// ------------------------------------------------------------------ buckets
+__device__ __forceinline__ uint32_t window_of(uint64_t code, uint64_t lo, uint64_t hi, uint32_t cp) {
+    const uint64_t c = code < lo ? lo : (code > hi ? hi : code);
+    return cp >= 64 ? 0u : (uint32_t)((c << cp) >> 40);
+}
+__device__ __forceinline__ uint32_t bucket_of_lut(uint32_t q, uint32_t B) {
+    return (uint32_t)(((uint64_t)q * B) >> 32);
+}
+
+// Splitters of every cell that owns two or more buckets: for cell W with
+// buckets [b0, b1) and sample keys sample[s_lo, s_hi) (sorted), splitter i
+// (1 <= i < b1 - b0) is sample[s_lo + i * m / (b1 - b0)], stored at
+// splitters[b0 + i - 1]; a cell with no sample keys gets +inf splitters.
+__global__ __launch_bounds__(256) void k_splitters(const uint32_t* __restrict__ lut,
+                                                   const uint64_t* __restrict__ sample,
+                                                   uint32_t S, LearnedHeader* hdr,
+                                                   uint64_t* __restrict__ splitters) {
+    const uint64_t lo = hdr->lo, hi = hdr->hi;
+    const uint32_t cp = hdr->cp, B = hdr->buckets;
+    uint32_t heavy = 0;
+    for (uint32_t w = blockIdx.x * 256 + threadIdx.x; w < LUT_CELLS; w += gridDim.x * 256) {
+        const uint32_t b0 = bucket_of_lut(lut[w], B), b1 = bucket_of_lut(lut[w + 1], B);
+        if (b1 < b0 + 2) continue;
+        ++heavy;
+        // sample range of cell w (windows of the sorted sample never decrease)
+        uint32_t a = 0, z = S;
+        while (a < z) {
+            const uint32_t mid = (a + z) >> 1;
+            if (window_of(sample[mid], lo, hi, cp) < w) a = mid + 1; else z = mid;
+        }
+        const uint32_t s_lo = a;
+        z = S;
+        while (a < z) {
+            const uint32_t mid = (a + z) >> 1;
+            if (window_of(sample[mid], lo, hi, cp) <= w) a = mid + 1; else z = mid;
+        }
+        const uint32_t m = a - s_lo, k = b1 - b0;
+        for (uint32_t i = 1; i < k; ++i)
+            splitters[b0 + i - 1] = m ? sample[s_lo + (uint32_t)(((uint64_t)i * m) / k)] : ~0ull;
+    }
+    if (heavy) atomicAdd(&hdr->heavy, heavy);
+}
+
+// Bucket id of every code (u16): the cell's first bucket, plus the number of
+// the cell's splitters not above the (clamped) code when it owns several.
+__global__ __launch_bounds__(256) void k_bucket_ids(const uint64_t* __restrict__ codes, uint32_t n,
+                                                    const LearnedHeader* __restrict__ hdr,
+                                                    const uint32_t* __restrict__ lut,
+                                                    const uint64_t* __restrict__ splitters,
+                                                    uint16_t* __restrict__ bid) {
+    const uint64_t lo = hdr->lo, hi = hdr->hi;
+    const uint32_t cp = hdr->cp, B = hdr->buckets;
+    for (uint32_t i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) {
+        const uint64_t code = codes[i];
+        const uint32_t w = window_of(code, lo, hi, cp);
+        const uint32_t b0 = bucket_of_lut(lut[w], B), b1 = bucket_of_lut(lut[w + 1], B);
+        uint32_t b = b0;
+        if (b1 >= b0 + 2) {
+            const uint64_t c = code < lo ? lo : (code > hi ? hi : code);
+            uint32_t a = 0, z = b1 - b0 - 1;  // count of splitters[b0 + .] <= c
+            while (a < z) {
+                const uint32_t mid = (a + z) >> 1;
+                if (splitters[b0 + mid] <= c) a = mid + 1; else z = mid;
+            }
+            b = b0 + a;
+        }
+        bid[i] = (uint16_t)b;
+    }
+}
+
+// ------------------------------------------------------------------ bucket passes
+// Two stable LSD passes over the 16-bit ids (low byte, then high byte) on
+// the whole array as one segment; the same tile / group / segment scans as
+// radix.hip.  The pass moves (code, index, id) through LDS one array at a
+// time.
+template <int ITEMS>
+__global__ __launch_bounds__(BLOCK) void k_bcount(const uint16_t* __restrict__ bid, uint32_t n,
+                                                  int shift, uint32_t* __restrict__ cnt) {
+    constexpr uint32_t TILE = BLOCK * ITEMS;
+    __shared__ uint32_t s_h[NWAVES * 256];
+    const uint32_t t = blockIdx.x, w = threadIdx.x / WAVE, lane = lane_id();
+    const uint32_t base = t * TILE;
+    if (base >= n) return;
+    const uint32_t nvalid = min(TILE, n - base);
+    for (uint32_t i = threadIdx.x; i < NWAVES * 256; i += BLOCK) s_h[i] = 0;
+    __syncthreads();
+    uint32_t* my = s_h + w * 256;
+#pragma unroll 4
+    for (int k = 0; k < ITEMS; ++k) {
+        const uint32_t p = w * WAVE * ITEMS + k * WAVE + lane;
+        const bool ok = p < nvalid;
+        const uint32_t dg = ok ? ((uint32_t)bid[base + p] >> shift) & 255u : 0u;
+        const uint32_t d0 = readlane(dg, 0);
+        if (ballot(ok && dg == d0) == ~0ull) {
+            if (lane == 0) my[d0] += WAVE;
+        } else if (ok) {
+            atomicAdd(&my[dg], 1u);
+        }
+    }
+    __syncthreads();
+    for (uint32_t d = threadIdx.x; d < 256; d += BLOCK) {
+        uint32_t v = 0;
+#pragma unroll
+        for (int ww = 0; ww < NWAVES; ++ww) v += s_h[ww * 256 + d];
+        cnt[(size_t)t * 256 + d] = v;
+    }
+}
+
+template <int ITEMS>
+__global__ __launch_bounds__(BLOCK) void k_bscatter(const uint64_t* __restrict__ ksrc,
+                                                    const uint32_t* __restrict__ vsrc,
+                                                    const uint16_t* __restrict__ bsrc,
+                                                    uint64_t* __restrict__ kdst,
+                                                    uint32_t* __restrict__ vdst,
+                                                    uint16_t* __restrict__ bdst, uint32_t n,
+                                                    int shift, const uint32_t* __restrict__ cnt,
+                                                    const uint32_t* __restrict__ gtot,
+                                                    const uint32_t* __restrict__ binstart) {
+    constexpr uint32_t TILE = BLOCK * ITEMS;
+    __shared__ uint64_t s_buf[TILE];
+    __shared__ uint32_t s_whist[NWAVES * 256];
+    __shared__ uint32_t s_binstart[256];
+    __shared__ uint32_t s_gbase[256];
+    __shared__ uint32_t s_scan[NWAVES];
+    const uint32_t t = blockIdx.x, tid = threadIdx.x, w = tid / WAVE, lane = lane_id();
+    const uint32_t base = t * TILE;
+    if (base >= n) return;
+    const uint32_t nvalid = min(TILE, n - base);
+    uint64_t dk[ITEMS];  // ranking key: the id's digit
+    uint32_t bv[ITEMS];
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i) {
+        const uint32_t p = w * WAVE * ITEMS + i * WAVE + lane;
+        bv[i] = p < nvalid ? bsrc[base + p] : 0xFFFFu;
+        dk[i] = bv[i];
+    }
+    uint32_t pos[ITEMS], bc = 0;
+    rank_tile<8, ITEMS>(dk, shift, 255u, nvalid, pos, s_whist, s_binstart, s_scan, &bc);
+    if (tid < 256) {
+        const uint32_t g = t / GROUP_TILES;
+        s_gbase[tid] = binstart[tid] + gtot[(size_t)g * 256 + tid] + cnt[(size_t)t * 256 + tid] -
+                       s_binstart[tid];
+    }
+    // id, then destination of every tile position
+    uint16_t* s_b = (uint16_t*)s_buf;
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i) s_b[pos[i]] = (uint16_t)bv[i];
+    __syncthreads();
+    uint32_t dst[ITEMS];
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i) {
+        const uint32_t p = i * BLOCK + tid;
+        dst[i] = 0;
+        if (p < nvalid) {
+            const uint32_t b = s_b[p];
+            dst[i] = s_gbase[(b >> shift) & 255u] + p;
+            if (bdst) bdst[dst[i]] = (uint16_t)b;
+        }
+    }
+    __syncthreads();
+    // codes
+    {
+        uint64_t kv[ITEMS];
+#pragma unroll
+        for (int i = 0; i < ITEMS; ++i) {
+            const uint32_t p = w * WAVE * ITEMS + i * WAVE + lane;
+            kv[i] = p < nvalid ? ksrc[base + p] : 0ull;
+        }
+#pragma unroll
+        for (int i = 0; i < ITEMS; ++i) s_buf[pos[i]] = kv[i];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i)
+        if (i * BLOCK + tid < nvalid) kdst[dst[i]] = s_buf[i * BLOCK + tid];
+    __syncthreads();
+    // indices
+    {
+        uint32_t* s_v = (uint32_t*)s_buf;
+        uint32_t vv[ITEMS];
+#pragma unroll
+        for (int i = 0; i < ITEMS; ++i) {
+            const uint32_t p = w * WAVE * ITEMS + i * WAVE + lane;
+            vv[i] = p < nvalid ? vsrc[base + p] : 0u;
+        }
+#pragma unroll
+        for (int i = 0; i < ITEMS; ++i) s_v[pos[i]] = vv[i];
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < ITEMS; ++i)
+            if (i * BLOCK + tid < nvalid) vdst[dst[i]] = s_v[i * BLOCK + tid];
+    }
+}
+
+// seg[b] = first position whose id is >= b, for b in [0, B]; ids sorted.
+__global__ __launch_bounds__(256) void k_bucket_bounds(const uint16_t* __restrict__ bid, uint32_t n,
+                                                       uint32_t B, uint64_t* __restrict__ seg) {
+    for (uint32_t i = blockIdx.x * 256 + threadIdx.x; i <= n; i += gridDim.x * 256) {
+        const uint32_t prev = i == 0 ? 0u : (uint32_t)bid[i - 1] + 1u;  // first bucket starting here
+        const uint32_t cur = i == n ? B : (uint32_t)bid[i];
+        for (uint32_t b = (i == 0 ? 0u : prev); b <= cur && b <= B; ++b) seg[b] = i;
+    }
+}
+
+// Exclusive scan of the tile counts within groups of GROUP_TILES tiles (in
+// place) and the group totals, for the whole array as one segment.
+__global__ __launch_bounds__(256) void k_lgroup_scan(uint32_t* __restrict__ cnt, uint32_t tiles,
+                                                     uint32_t* __restrict__ gtot) {
+    const uint32_t g = blockIdx.x, d = threadIdx.x;
+    const uint32_t t0 = g * GROUP_TILES, nt = min((uint32_t)GROUP_TILES, tiles - t0);
+    uint32_t v[GROUP_TILES];
+#pragma unroll
+    for (int i = 0; i < GROUP_TILES; ++i) v[i] = (uint32_t)i < nt ? cnt[(size_t)(t0 + i) * 256 + d] : 0u;
+    uint32_t run = 0;
+#pragma unroll
+    for (int i = 0; i < GROUP_TILES; ++i) {
+        if ((uint32_t)i < nt) cnt[(size_t)(t0 + i) * 256 + d] = run;
+        run += v[i];
+    }
+    gtot[(size_t)g * 256 + d] = run;
+}
+// Scan of the group totals (in place) and the digit starts (one workgroup).
+__global__ __launch_bounds__(256) void k_lseg_scan(uint32_t* __restrict__ gtot, uint32_t groups,
+                                                   uint32_t* __restrict__ binstart) {
+    __shared__ uint32_t scratch[NWAVES];
+    const uint32_t d = threadIdx.x;
+    uint32_t run = 0;
+    constexpr int U = 16;
+    for (uint32_t g0 = 0; g0 < groups; g0 += U) {
+        uint32_t v[U];
+#pragma unroll
+        for (int i = 0; i < U; ++i) v[i] = g0 + i < groups ? gtot[(size_t)(g0 + i) * 256 + d] : 0u;
+#pragma unroll
+        for (int i = 0; i < U; ++i) {
+            if (g0 + i < groups) gtot[(size_t)(g0 + i) * 256 + d] = run;
+            run += v[i];
+        }
+    }
+    uint32_t tot;
+    binstart[d] = block_exclusive_sum(run, scratch, &tot);
+}
+
+// Seeded sample: string index splitmix64(seed + golden * (j + 1)) mod n for
+// j < S, drawn with replacement.
+__global__ void k_sample_idx(uint32_t* __restrict__ sel, uint32_t S, uint32_t n, uint64_t seed) {
+    for (uint32_t j = blockIdx.x * 256 + threadIdx.x; j < S; j += gridDim.x * 256)
+        sel[j] = (uint32_t)(splitmix64(seed + 0x9E3779B97F4A7C15ull * ((uint64_t)j + 1)) % n);
+}
+
+// Header from the sorted sample: extremes and their common prefix.
+__global__ void k_learned_header(const uint64_t* __restrict__ sample, uint32_t S,
+                                 LearnedHeader* hdr, uint32_t mode, uint32_t flags) {
+    const uint64_t lo = sample[0], hi = sample[S - 1];
+    hdr->lo = lo;
+    hdr->hi = hi;
+    hdr->cp = lo == hi ? 64u : (uint32_t)__clzll((long long)(lo ^ hi));
+    hdr->buckets = LEARNED_BUCKETS;
+    hdr->mode = mode;
+    hdr->sample = S;
+    hdr->steps = 0;
+    hdr->last_loss = 0.f;
+    hdr->heavy = 0;
+    hdr->dense = 0;
+    hdr->dense_keys = 0;
+    hdr->trained = 0;
+    hdr->flags = flags;
+}
+
+// Dense-cell flags of every sample position j (sorted sample): bit 0 = its
+// cell holds at least two buckets' worth of sample keys (count * B >= 2 S)
+// and at least DENSE_MIN of them (fewer is sampling noise, not a spike),
+// bit 1 = j is the first sample key of such a cell.  The cell's sample range
+// comes from two binary searches (windows of the sorted sample never
+// decrease).
+__global__ __launch_bounds__(256) void k_dense_flags(const uint64_t* __restrict__ sample, uint32_t S,
+                                                     const LearnedHeader* __restrict__ hdr,
+                                                     uint32_t use_dense, uint8_t* __restrict__ flags) {
+    const uint64_t lo = hdr->lo, hi = hdr->hi;
+    const uint32_t cp = hdr->cp;
+    for (uint32_t j = blockIdx.x * 256 + threadIdx.x; j < S; j += gridDim.x * 256) {
+        uint8_t f = 0;
+        if (use_dense) {
+            const uint32_t w = window_of(sample[j], lo, hi, cp);
+            uint32_t a = 0, z = j;
+            while (a < z) {
+                const uint32_t mid = (a + z) >> 1;
+                if (window_of(sample[mid], lo, hi, cp) < w) a = mid + 1; else z = mid;
+            }
+            const uint32_t first = a;
+            a = j + 1;
+            z = S;
+            while (a < z) {
+                const uint32_t mid = (a + z) >> 1;
+                if (window_of(sample[mid], lo, hi, cp) <= w) a = mid + 1; else z = mid;
+            }
+            const uint64_t cnt = a - first;
+            if (cnt * LEARNED_BUCKETS >= 2ull * S && cnt >= DENSE_MIN)
+                f = (uint8_t)(1u | (j == first ? 2u : 0u));
+        }
+        flags[j] = f;
+    }
+}
+
+// Two counters per position scanned over the sample in tiles of SCAN_TILE:
+// dense keys before j, and dense cells started before j.
+constexpr uint32_t SCAN_TILE = 4096;
+__global__ __launch_bounds__(256) void k_flag_sums(const uint8_t* __restrict__ flags, uint32_t S,
+                                                   uint2* __restrict__ tsum) {
+    __shared__ uint32_t s0[NWAVES], s1[NWAVES];
+    const uint32_t t0 = blockIdx.x * SCAN_TILE;
+    uint32_t a = 0, b = 0;
+    for (uint32_t i = t0 + threadIdx.x; i < min(S, t0 + SCAN_TILE); i += 256) {
+        a += flags[i] & 1u;
+        b += (flags[i] >> 1) & 1u;
+    }
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) {
+        a += __shfl_xor(a, d, WAVE);
+        b += __shfl_xor(b, d, WAVE);
+    }
+    if (lane_id() == 0) {
+        s0[threadIdx.x / WAVE] = a;
+        s1[threadIdx.x / WAVE] = b;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) tsum[blockIdx.x] = make_uint2(s0[0] + s0[1] + s0[2] + s0[3], s1[0] + s1[1] + s1[2] + s1[3]);
+}
+// Exclusive scan of the tile sums (one workgroup); totals into the header.
+__global__ __launch_bounds__(256) void k_flag_scan(uint2* __restrict__ tsum, uint32_t tiles,
+                                                   LearnedHeader* hdr) {
+    __shared__ uint32_t sc0[NWAVES], sc1[NWAVES];
+    uint32_t c0 = 0, c1 = 0;
+    for (uint32_t b = 0; b < tiles; b += 256) {
+        const uint32_t i = b + threadIdx.x;
+        const uint2 v = i < tiles ? tsum[i] : make_uint2(0u, 0u);
+        uint32_t t0, t1;
+        const uint32_t e0 = block_exclusive_sum(v.x, sc0, &t0);
+        const uint32_t e1 = block_exclusive_sum(v.y, sc1, &t1);
+        if (i < tiles) tsum[i] = make_uint2(c0 + e0, c1 + e1);
+        c0 += t0;
+        c1 += t1;
+    }
+    if (threadIdx.x == 0) {
+        hdr->dense_keys = c0;
+        hdr->dense = c1;
+    }
+}
+// Per tile: positions of every sample key among the dense / other keys; the
+// other keys become training pairs x = W / 2^24, y = (rank + 0.5) / count,
+// written compactly; each dense cell's first key records the cell and the
+// dense keys before it.
+__global__ __launch_bounds__(256) void k_flag_apply(const uint8_t* __restrict__ flags,
+                                                    const uint64_t* __restrict__ sample, uint32_t S,
+                                                    const uint2* __restrict__ tsum,
+                                                    const LearnedHeader* __restrict__ hdr,
+                                                    float* __restrict__ x, float* __restrict__ y,
+                                                    uint32_t* __restrict__ dense,
+                                                    uint32_t* __restrict__ dense_cum) {
+    __shared__ uint32_t sc0[NWAVES], sc1[NWAVES];
+    const uint64_t lo = hdr->lo, hi = hdr->hi;
+    const uint32_t cp = hdr->cp, nd = hdr->dense, dk = hdr->dense_keys;
+    const uint32_t rest = S - dk;
+    const float inv_rest = rest ? 1.f / (float)rest : 0.f;
+    const uint32_t t0 = blockIdx.x * SCAN_TILE;
+    uint2 run = tsum[blockIdx.x];
+    for (uint32_t b = t0; b < min(S, t0 + SCAN_TILE); b += 256) {
+        const uint32_t j = b + threadIdx.x;
+        const uint32_t f = j < S ? flags[j] : 0u;
+        uint32_t t_a, t_b;
+        const uint32_t e0 = block_exclusive_sum(f & 1u, sc0, &t_a);
+        const uint32_t e1 = block_exclusive_sum((f >> 1) & 1u, sc1, &t_b);
+        if (j < S) {
+            const uint32_t before_dense = run.x + e0;
+            const uint32_t w = window_of(sample[j], lo, hi, cp);
+            if (f & 1u) {
+                if (f & 2u) {
+                    dense[run.y + e1] = w;
+                    dense_cum[run.y + e1] = before_dense;
+                }
+            } else {
+                const uint32_t r = j - before_dense;
+                x[r] = (float)w * (1.f / (float)LUT_CELLS);
+                y[r] = ((float)r + 0.5f) * inv_rest;
+            }
+        }
+        run.x += t_a;
+        run.y += t_b;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) dense_cum[nd] = dk;
+}
+
+__global__ void k_learned_finish(LearnedHeader* hdr, const float* __restrict__ loss_acc,
+                                 uint32_t steps, uint32_t trained) {
+    hdr->steps = steps;
+    hdr->trained = trained;
+    hdr->last_loss = trained ? *loss_acc / (float)trained : 0.f;
+}
+
+// Buckets larger than one radix tile go to the multi-tile passes (overflow):
+// their number and their keys.
+__global__ void k_overflow_stats(const uint64_t* __restrict__ seg, uint32_t B, uint32_t tile,
+                                 uint32_t* __restrict__ out) {
+    uint32_t nb = 0, nk = 0;
+    for (uint32_t b = blockIdx.x * 256 + threadIdx.x; b < B; b += gridDim.x * 256) {
+        const uint32_t len = (uint32_t)(seg[b + 1] - seg[b]);
+        if (len > tile) {
+            ++nb;
+            nk += len;
+        }
+    }
+    if (nb) {
+        atomicAdd(&out[0], nb);
+        atomicAdd(&out[1], nk);
+    }
+}
+
+// ------------------------------------------------------------------ host side
+size_t learned_model_bytes() {
+    size_t off[9];
+    model_offsets(off);
+    return off[8];
+}
+size_t learned_model_offset(int part) {
+    if (part < 0 || part > 7) return ~(size_t)0;
+    size_t off[9];
+    model_offsets(off);
+    return off[part];
+}
+uint32_t learned_nparam() { return NPARAM; }
+uint32_t learned_lut_tiles() { return (LUT_CELLS + 1 + LUT_TILE - 1) / LUT_TILE; }
+
+static uint32_t grid_for(uint64_t n, uint32_t cap = 8192) {
+    return (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>((n + 255) / 256, cap));
+}
+
+hipError_t learned_sample(uint32_t* sel, uint32_t S, uint32_t n, uint64_t seed, hipStream_t s) {
+    hipLaunchKernelGGL(k_sample_idx, dim3(grid_for(S)), dim3(256), 0, s, sel, S, n, seed);
+    return hipGetLastError();
+}
+
+hipError_t learned_prepare(void* model, const uint64_t* sorted_sample, uint32_t S, uint32_t mode,
+                           uint32_t flags, uint8_t* fl, uint2* tsum, float* x, float* y,
+                           hipStream_t s) {
+    ModelView m = model_view(model);
+    hipLaunchKernelGGL(k_learned_header, dim3(1), dim3(1), 0, s, sorted_sample, S, m.hdr, mode, flags);
+    const uint32_t use_dense = (flags & HUSKY_LEARNED_NO_DENSE) ? 0u : 1u;
+    hipLaunchKernelGGL(k_dense_flags, dim3(grid_for(S)), dim3(256), 0, s, sorted_sample, S,
+                       (const LearnedHeader*)m.hdr, use_dense, fl);
+    const uint32_t tiles = (S + SCAN_TILE - 1) / SCAN_TILE;
+    hipLaunchKernelGGL(k_flag_sums, dim3(tiles), dim3(256), 0, s, (const uint8_t*)fl, S, tsum);
+    hipLaunchKernelGGL(k_flag_scan, dim3(1), dim3(256), 0, s, tsum, tiles, m.hdr);
+    hipLaunchKernelGGL(k_flag_apply, dim3(tiles), dim3(256), 0, s, (const uint8_t*)fl, sorted_sample, S,
+                       (const uint2*)tsum, (const LearnedHeader*)m.hdr, x, y, m.dense, m.dense_cum);
+    return hipGetLastError();
+}
+
+const uint32_t* learned_dense_keys_ptr(void* model) { return &model_view(model).hdr->dense_keys; }
+
+hipError_t learned_init(void* model, uint64_t seed, bool raw, hipStream_t s) {
+    ModelView m = model_view(model);
+    hipLaunchKernelGGL(k_mlp_init, dim3((NPARAM + 255) / 256), dim3(256), 0, s, m.params, m.adam_m,
+                       m.adam_v, seed, raw ? 1 : 0);
+    return hipGetLastError();
+}
+
+static size_t mlp_lds() { return (size_t)(HID * HID + 4 * HID + 2 * MLP_T + 2 * MLP_T * (HID + 1)) * 4; }
+
+template <bool MONO>
+static hipError_t mlp_grad_launch(const float* params, const float* x, const float* y,
+                                  uint32_t first, uint32_t count, uint32_t stride, uint32_t blocks,
+                                  float inv_batch, float* partial, float* grad, hipStream_t s) {
+    static bool attr = false;
+    if (!attr) {
+        hipError_t e = hipFuncSetAttribute((const void*)k_mlp_grad<MONO>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)mlp_lds());
+        if (e != hipSuccess) return e;
+        attr = true;
+    }
+    const uint32_t per_block = (count + blocks - 1) / blocks;
+    hipLaunchKernelGGL(k_mlp_grad<MONO>, dim3(blocks), dim3(MLP_T), mlp_lds(), s, params, x, y, first,
+                       count, stride, per_block, inv_batch, partial);
+    hipLaunchKernelGGL(k_mlp_reduce, dim3((NPARAM + 1 + 255) / 256), dim3(256), 0, s,
+                       (const float*)partial, blocks, grad);
+    return hipGetLastError();
+}
+
+static uint32_t grad_blocks(uint32_t count, uint32_t max_blocks) {
+    return std::max(1u, std::min(max_blocks, (count + MLP_T - 1) / MLP_T));
+}
+size_t learned_partial_bytes(uint32_t max_blocks) { return (size_t)max_blocks * (NPARAM + 1) * 4; }
+
+hipError_t learned_grad(const float* params, const float* x, const float* y, uint32_t count,
+                        bool mono, float* partial, uint32_t max_blocks, float* grad, hipStream_t s) {
+    const uint32_t blocks = grad_blocks(count, max_blocks);
+    const float inv = 1.f / (float)std::max(count, 1u);
+    return mono ? mlp_grad_launch<true>(params, x, y, 0, count, 1, blocks, inv, partial, grad, s)
+                : mlp_grad_launch<false>(params, x, y, 0, count, 1, blocks, inv, partial, grad, s);
+}
+
+hipError_t learned_train(void* model, const float* x, const float* y, uint32_t count,
+                         uint32_t epochs, uint32_t batch, float lr, bool mono, float* partial,
+                         uint32_t max_blocks, float* grad, float* loss_acc, hipStream_t s) {
+    ModelView m = model_view(model);
+    const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
+    uint32_t step = 0;
+    hipError_t e = hipSuccess;
+    if (count) {
+        const uint32_t nb = std::max(1u, (count + batch - 1) / batch);  // batches per epoch
+        for (uint32_t ep = 0; ep < epochs; ++ep) {
+            if ((e = zero_u32((uint32_t*)loss_acc, 1, s)) != hipSuccess) return e;
+            for (uint32_t b = 0; b < nb; ++b) {
+                // batch b takes samples b, b + nb, b + 2 nb, ...: every batch
+                // spans the whole key range
+                const uint32_t cnt = (count - b + nb - 1) / nb;
+                const uint32_t blocks = grad_blocks(cnt, max_blocks);
+                const float inv = 1.f / (float)cnt;
+                e = mono ? mlp_grad_launch<true>(m.params, x, y, b, cnt, nb, blocks, inv, partial, grad, s)
+                         : mlp_grad_launch<false>(m.params, x, y, b, cnt, nb, blocks, inv, partial, grad, s);
+                if (e != hipSuccess) return e;
+                ++step;
+                const float c1 = 1.f - powf(b1, (float)step), c2 = 1.f - powf(b2, (float)step);
+                hipLaunchKernelGGL(k_adam, dim3((NPARAM + 255) / 256), dim3(256), 0, s, m.params,
+                                   m.adam_m, m.adam_v, (const float*)grad, lr, b1, b2, eps, c1, c2,
+                                   loss_acc);
+            }
+        }
+    }
+    hipLaunchKernelGGL(k_learned_finish, dim3(1), dim3(1), 0, s, m.hdr, (const float*)loss_acc, step,
+                       step ? count : 0u);
+    return hipGetLastError();
+}
+
+hipError_t learned_build_lut(void* model, uint32_t mode, uint32_t* tmax, hipStream_t s) {
+    ModelView m = model_view(model);
+    const LearnedHeader* h = m.hdr;
+    const float* p = m.params;
+    const dim3 g(8192), t(256);
+    switch (mode) {
+        case HUSKY_LEARNED_EQUAL_WIDTH:
+            hipLaunchKernelGGL((k_lut_eval<true, LUT_IDENTITY>), g, t, 0, s, p, h, m.dense, m.dense_cum, m.lut);
+            break;
+        case HUSKY_LEARNED_CONSTANT:
+            hipLaunchKernelGGL((k_lut_eval<true, LUT_ZERO>), g, t, 0, s, p, h, m.dense, m.dense_cum, m.lut);
+            break;
+        case HUSKY_LEARNED_UNCONSTRAINED:
+            hipLaunchKernelGGL((k_lut_eval<false, LUT_NET>), g, t, 0, s, p, h, m.dense, m.dense_cum, m.lut);
+            break;
+        default:
+            hipLaunchKernelGGL((k_lut_eval<true, LUT_NET>), g, t, 0, s, p, h, m.dense, m.dense_cum, m.lut);
+    }
+    const uint32_t n = LUT_CELLS + 1, tiles = (n + LUT_TILE - 1) / LUT_TILE;
+    hipLaunchKernelGGL(k_lut_tilemax, dim3(tiles), dim3(256), 0, s, (const uint32_t*)m.lut, n, tmax);
+    hipLaunchKernelGGL(k_lut_carry, dim3(1), dim3(256), 0, s, tmax, tiles);
+    hipLaunchKernelGGL(k_lut_apply, dim3(tiles), dim3(256), 0, s, m.lut, n, (const uint32_t*)tmax);
+    return hipGetLastError();
+}
+
+hipError_t learned_splitters(void* model, const uint64_t* sorted_sample, uint32_t S, hipStream_t s) {
+    ModelView m = model_view(model);
+    hipLaunchKernelGGL(k_splitters, dim3(8192), dim3(256), 0, s, (const uint32_t*)m.lut, sorted_sample,
+                       S, m.hdr, m.splitters);
+    return hipGetLastError();
+}
+
+hipError_t learned_bucket_ids(const void* model, const uint64_t* codes, uint32_t n, uint16_t* bid,
+                              hipStream_t s) {
+    ModelView m = model_view((void*)model);
+    ProfScope ps(P_BUCKET_MAP, s);
+    hipLaunchKernelGGL(k_bucket_ids, dim3(grid_for(n)), dim3(256), 0, s, codes, n,
+                       (const LearnedHeader*)m.hdr, (const uint32_t*)m.lut,
+                       (const uint64_t*)m.splitters, bid);
+    return hipGetLastError();
+}
+
+hipError_t learned_bucket_pass(int pass, const uint64_t* ks, const uint32_t* vs, const uint16_t* bs,
+                               uint64_t* kd, uint32_t* vd, uint16_t* bd, uint32_t n, uint32_t* cnt,
+                               uint32_t* gtot, uint32_t* binstart, hipStream_t s) {
+    constexpr int ITEMS = 16;
+    constexpr uint32_t TILE = BLOCK * ITEMS;
+    const uint32_t tiles = (n + TILE - 1) / TILE, groups = (tiles + GROUP_TILES - 1) / GROUP_TILES;
+    const int shift = 8 * pass;
+    {
+        ProfScope ps(P_COUNT_SCAN, s);
+        hipLaunchKernelGGL(k_bcount<ITEMS>, dim3(tiles), dim3(BLOCK), 0, s, bs, n, shift, cnt);
+        hipLaunchKernelGGL(k_lgroup_scan, dim3(groups), dim3(256), 0, s, cnt, tiles, gtot);
+        hipLaunchKernelGGL(k_lseg_scan, dim3(1), dim3(256), 0, s, gtot, groups, binstart);
+    }
+    ProfScope ps(P_BUCKET, s);
+    hipLaunchKernelGGL(k_bscatter<ITEMS>, dim3(tiles), dim3(BLOCK), 0, s, ks, vs, bs, kd, vd, bd, n,
+                       shift, (const uint32_t*)cnt, (const uint32_t*)gtot, (const uint32_t*)binstart);
+    return hipGetLastError();
+}
+uint32_t learned_pass_tiles(uint32_t n) { return (n + BLOCK * 16 - 1) / (BLOCK * 16); }
+
+hipError_t learned_bucket_bounds(const uint16_t* bid, uint32_t n, uint64_t* seg, uint32_t* overflow,
+                                 uint32_t tile, hipStream_t s) {
+    ProfScope ps(P_BUCKET_BOUNDS, s);
+    hipLaunchKernelGGL(k_bucket_bounds, dim3(grid_for((uint64_t)n + 1)), dim3(256), 0, s, bid, n,
+                       (uint32_t)LEARNED_BUCKETS, seg);
+    hipLaunchKernelGGL(k_overflow_stats, dim3(256), dim3(256), 0, s, (const uint64_t*)seg,
+                       (uint32_t)LEARNED_BUCKETS, tile, overflow);
+    return hipGetLastError();
+}
+
+}  // namespace husky

@@ -1,0 +1,98 @@
+// Stable ranking of one tile of keys by one digit (wavefront ballots), shared
+// by the radix sort and the learned bucket passes.
+#pragma once
+
+#include "common.h"
+
+namespace husky {
+
+// ------------------------------------------------------------------ tile ranking
+// Ranks the ITEMS keys of every thread of one tile by their digit
+// (key >> shift) & dmask, dmask < 2^BITS.
+// Keys sit in "wave-striped" order: item k of lane l of wave w is tile
+// position w*64*ITEMS + k*64 + l; positions >= nvalid are padding and rank
+// last.  On return pos[k] is the key's position in the digit-sorted tile
+// (stable in tile position) and, for tid < R, *bin_count holds the number of
+// valid keys with digit tid and s_binstart[tid] its first position.
+template <int BITS, int ITEMS>
+__device__ __forceinline__ void rank_tile(const uint64_t (&keys)[ITEMS], int shift,
+                                          uint32_t dmask, uint32_t nvalid, uint32_t (&pos)[ITEMS],
+                                          uint32_t* s_whist, uint32_t* s_binstart,
+                                          uint32_t* s_scan, uint32_t* bin_count) {
+    constexpr int R = 1 << BITS;
+    const uint32_t tid = threadIdx.x, w = tid / WAVE, lane = lane_id();
+    for (uint32_t i = tid; i < (uint32_t)(NWAVES * R); i += BLOCK) s_whist[i] = 0;
+    __syncthreads();
+    // Each wavefront owns one histogram row.  Within an iteration every lane
+    // reads its digit's count before the one lane per digit updates it; LDS
+    // operations of one wavefront complete in order, and the empty asm with a
+    // memory clobber keeps the compiler from reusing a count across
+    // iterations.
+    uint32_t* wh = s_whist + w * R;
+    uint32_t rank[ITEMS], dig[ITEMS];
+#pragma unroll
+    for (int k = 0; k < ITEMS; ++k) {
+        const uint32_t p = w * WAVE * ITEMS + k * WAVE + lane;
+        const uint32_t d = p < nvalid ? ((uint32_t)(keys[k] >> shift) & dmask) : (uint32_t)(R - 1);
+        dig[k] = d;
+        // lanes holding the same digit: for every digit bit keep the lanes
+        // whose bit agrees (ballot, inverted where this lane's bit is 0)
+        uint32_t plo = ~0u, phi = ~0u;
+#pragma unroll
+        for (int b = 0; b < BITS; ++b) {
+            const uint32_t bit = (d >> b) & 1u;
+            const uint64_t bal = ballot(bit != 0);
+            const uint32_t flip = bit - 1u;  // 0 when set, all ones when clear
+            plo &= (uint32_t)bal ^ flip;
+            phi &= (uint32_t)(bal >> 32) ^ flip;
+        }
+        const uint32_t below = __builtin_amdgcn_mbcnt_hi(phi, __builtin_amdgcn_mbcnt_lo(plo, 0u));
+        const uint32_t cnt = (uint32_t)__popc(plo) + (uint32_t)__popc(phi);
+        const uint32_t base = wh[d];
+        __asm__ volatile("" ::: "memory");
+        if (below == cnt - 1) wh[d] = base + cnt;
+        __asm__ volatile("" ::: "memory");
+        rank[k] = base + below;
+    }
+    __syncthreads();
+    uint32_t tot = 0;
+    if (tid < (uint32_t)R) {
+#pragma unroll
+        for (int ww = 0; ww < NWAVES; ++ww) {
+            const uint32_t c = s_whist[ww * R + tid];
+            s_whist[ww * R + tid] = tot;
+            tot += c;
+        }
+    }
+    uint32_t all;
+    const uint32_t ex = block_exclusive_sum(tid < (uint32_t)R ? tot : 0u, s_scan, &all);
+    if (tid < (uint32_t)R) {
+        s_binstart[tid] = ex;
+        const uint32_t pad = (uint32_t)(BLOCK * ITEMS) - nvalid;
+        *bin_count = (tid == (uint32_t)(R - 1)) ? tot - pad : tot;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < ITEMS; ++k) pos[k] = s_binstart[dig[k]] + s_whist[w * R + dig[k]] + rank[k];
+}
+
+template <int ITEMS>
+__device__ __forceinline__ void load_striped(const uint64_t* __restrict__ keys,
+                                             const uint32_t* __restrict__ vals, uint32_t base,
+                                             uint32_t nvalid, uint64_t (&k)[ITEMS],
+                                             uint32_t (&v)[ITEMS]) {
+    const uint32_t w = threadIdx.x / WAVE, lane = lane_id();
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i) {
+        const uint32_t p = w * WAVE * ITEMS + i * WAVE + lane;
+        if (p < nvalid) {
+            k[i] = keys[base + p];
+            v[i] = vals[base + p];
+        } else {
+            k[i] = ~0ull;
+            v[i] = 0;
+        }
+    }
+}
+
+}  // namespace husky

@@ -1,0 +1,197 @@
+"""GPU: the learned-CDF form.
+
+* the training kernel's gradient (FP32) against the float64 oracle's chain
+  rule, for the monotone and the raw-weight network, on ragged batch sizes
+  that span one and many workgroups;
+* the fit's deterministic parts against the oracle's definitions: sample
+  extremes and common prefix, dense cells and their counts, the CDF table
+  (equal-width mode, within two units of 2^-32) and the splitters;
+* the LUT is non-decreasing over all 2^24 + 1 entries, whatever the network;
+* husky_sort_learned's permutation equals the oracle's on every workload
+  shape, with the trained network, with deliberately broken models
+  (unconstrained, constant) and with a model fitted on other data.
+"""
+
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import learned as ol
+from _progress import say
+from workloads import ADVERSARIAL_FAMILIES, adversarial, config1, config2, config3, config5
+
+pytestmark = pytest.mark.gpu
+
+
+def _u32(t):
+    return t.cpu().numpy().view(np.uint32)
+
+
+def _params(seed):
+    rng = np.random.default_rng(seed)
+    p = np.empty(ol.P)
+    p[0:64] = rng.normal(0.54, 0.4, 64)
+    p[64:128] = -(np.arange(64) + 0.5) / 64 + rng.normal(0, 0.02, 64)
+    p[128:128 + 4096] = rng.normal(-4.15, 0.4, 4096)
+    p[4224:4288] = rng.normal(0.0, 0.05, 64)
+    p[4288:4352] = rng.normal(-3.45, 0.4, 64)
+    p[4352] = 0.05
+    return p.astype(np.float32)
+
+
+@pytest.mark.parametrize("monotone", [True, False], ids=["softplus", "raw"])
+@pytest.mark.parametrize("count", [1, 300, 1000, 70_001])
+def test_mlp_grad_matches_oracle(gpu_lib, monotone, count):
+    import torch
+
+    p = _params(count)
+    if not monotone:
+        p = (p * 0.2).astype(np.float32)  # keep the raw network's outputs moderate
+    rng = np.random.default_rng(count + 7)
+    x = rng.random(count).astype(np.float32)
+    y = np.sort(rng.random(count)).astype(np.float32)
+    g, sse = gpu_lib.mlp_grad(torch.from_numpy(p).cuda(), torch.from_numpy(x).cuda(),
+                              torch.from_numpy(y).cuda(), monotone=monotone)
+    g = g.cpu().numpy().astype(np.float64)
+    L, ref = ol.grad(p.astype(np.float64), x.astype(np.float64), y.astype(np.float64), monotone)
+    assert math.isclose(float(sse) / count, L, rel_tol=1e-4, abs_tol=1e-9)
+    scale = np.abs(ref).max()
+    assert np.linalg.norm(g - ref) <= 1e-4 * np.linalg.norm(ref) + 1e-7
+    np.testing.assert_allclose(g, ref, rtol=1e-3, atol=1e-5 * scale)
+
+
+def _fit(gpu_lib, b, e, o, **kw):
+    params = gpu_lib.make_learned_params(**kw)
+    ws = gpu_lib.alloc_learned_workspace(b.n)
+    model = gpu_lib.fit_learned(e, o, b.coder, params, ws=ws)
+    return model, ws
+
+
+def test_fit_matches_definitions(gpu_lib):
+    import torch
+
+    b = config5(n=300_000, seed=3)
+    e, o = gpu_lib.to_device(b)
+    frac, seed = 0.05, 11
+    model, _ = _fit(gpu_lib, b, e, o, sample_frac=frac, seed=seed, mode="equal_width")
+    h = gpu_lib.learned_header(model)
+    S = math.ceil(frac * b.n)
+    codes, _ = oracle.encode(b)
+    sample = np.sort(codes[ol.sample_indices(b.n, S, seed)]).astype(object)
+    lo, hi, cp = ol.header(sample)
+    assert (h["lo"], h["hi"], h["cp"], h["sample"], h["buckets"]) == (lo, hi, cp, S, 65536)
+    dense, cum, _ = ol.dense_cells(sample)
+    assert h["dense"] == len(dense) and h["dense_keys"] == cum[-1]
+    assert h["steps"] == 0 and h["trained"] == 0
+    got_dense = gpu_lib.learned_part(model, "dense", torch.int32, len(dense)).cpu().numpy()
+    got_cum = gpu_lib.learned_part(model, "dense_cum", torch.int32, len(dense) + 1).cpu().numpy()
+    np.testing.assert_array_equal(got_dense.view(np.uint32), dense)
+    np.testing.assert_array_equal(got_cum.view(np.uint32), cum)
+    say("dense cells", len(dense), "holding", cum[-1], "of", S)
+    lut = gpu_lib.learned_part(model, "lut", torch.int32, ol.CELLS + 1).cpu().numpy()
+    lut = lut.view(np.uint32).astype(np.int64)
+    ref = ol.cdf_table(lambda x: x, dense, cum, S)
+    assert np.abs(lut - ref).max() <= 2
+    # splitters from the GPU's own table, by the oracle's definition
+    spl = gpu_lib.learned_part(model, "splitters", torch.int64, 65536).cpu().numpy().view(np.uint64)
+    want = ol.splitters(lut, sample)
+    assert h["heavy"] == int(np.sum(((lut[1:] * 65536) >> 32) - ((lut[:-1] * 65536) >> 32) >= 2))
+    for slot, v in want.items():
+        assert int(spl[slot]) == v, slot
+
+
+@pytest.mark.parametrize("mode", ["monotone", "unconstrained"])
+def test_lut_non_decreasing_everywhere(gpu_lib, mode):
+    import torch
+
+    b = config5(n=200_000, seed=4)
+    e, o = gpu_lib.to_device(b)
+    model, _ = _fit(gpu_lib, b, e, o, mode=mode, sample_frac=0.05, epochs=3, lr=0.05)
+    lut = gpu_lib.learned_part(model, "lut", torch.int32, ol.CELLS + 1).to(torch.int64) & 0xFFFFFFFF
+    assert int(lut[0]) == 0 and int(lut[-1]) == 2**32 - 1
+    assert bool((lut[1:] >= lut[:-1]).all())
+    h = gpu_lib.learned_header(model)
+    assert h["steps"] > 0 and h["trained"] == h["sample"] - h["dense_keys"]
+    if mode == "monotone":
+        assert np.isfinite(h["last_loss"]) and h["last_loss"] < 0.05
+
+
+def _learned_equals_oracle(gpu_lib, b, **kw):
+    e, o = gpu_lib.to_device(b)
+    model, ws = _fit(gpu_lib, b, e, o, **kw)
+    perm = _u32(gpu_lib.sort_learned(e, o, model, b.coder, ws=ws))
+    st = gpu_lib.read_status(ws)
+    ref, bad = oracle.sort(b)
+    assert bad == 0
+    np.testing.assert_array_equal(perm, ref)
+    return st
+
+
+@pytest.mark.parametrize("maker", [lambda: config1(n=100_000), lambda: config2(n=300_000),
+                                   lambda: config3(n=200_000), lambda: config5(n=400_000)],
+                         ids=["config1", "config2", "config3_utf16", "config5"])
+def test_learned_sort_exact(gpu_lib, maker):
+    b = maker()
+    st = _learned_equals_oracle(gpu_lib, b)
+    say(b.name, "overflow buckets", st["overflow_buckets"], "keys", st["overflow_keys"])
+
+
+@pytest.mark.parametrize("family", ADVERSARIAL_FAMILIES)
+def test_learned_sort_adversarial(gpu_lib, family):
+    b = adversarial(family, n=3000)
+    if b.n == 0:
+        pytest.skip("the fit needs at least one string")
+    _learned_equals_oracle(gpu_lib, b, sample_frac=0.1)
+
+
+@pytest.mark.parametrize("mode,dense", [("unconstrained", True), ("constant", True),
+                                        ("constant", False), ("untrained", True),
+                                        ("equal_width", True)])
+def test_broken_or_weak_models_stay_exact(gpu_lib, mode, dense):
+    b = config5(n=250_000, seed=6)
+    st = _learned_equals_oracle(gpu_lib, b, mode=mode, dense=dense, sample_frac=0.02)
+    if mode == "constant" and not dense:
+        # every key outside the top cell lands in bucket 0: one giant overflow
+        assert st["overflow_keys"] > b.n // 2
+
+
+def test_single_level_form_exact(gpu_lib):
+    # the network alone, no dense cells
+    _learned_equals_oracle(gpu_lib, config5(n=250_000, seed=7), dense=False)
+
+
+def test_model_from_other_data(gpu_lib):
+    # codes outside the fitted [lo, hi] clamp to the extreme cells
+    fit_on = config5(n=100_000, seed=8)
+    e1, o1 = gpu_lib.to_device(fit_on)
+    model, _ = _fit(gpu_lib, fit_on, e1, o1)
+    b = config2(n=200_000, seed=9)
+    e, o = gpu_lib.to_device(b)
+    perm = _u32(gpu_lib.sort_learned(e, o, model, "ascii7"))
+    np.testing.assert_array_equal(perm, oracle.sort(b)[0])
+
+
+def test_tiny_and_empty_inputs(gpu_lib):
+    import torch
+
+    b = config1(n=1, seed=2)
+    e, o = gpu_lib.to_device(b)
+    model, _ = _fit(gpu_lib, b, e, o)
+    assert _u32(gpu_lib.sort_learned(e, o, model)).tolist() == [0]
+    empty_off = torch.zeros(1, dtype=torch.int64, device="cuda")
+    assert gpu_lib.sort_learned(e, empty_off, model).numel() == 0
+    for n in (2, 3, 17, 4097):
+        bb = config2(n=n, seed=n)
+        ee, oo = gpu_lib.to_device(bb)
+        m2, _ = _fit(gpu_lib, bb, ee, oo, sample_frac=1.0)
+        np.testing.assert_array_equal(_u32(gpu_lib.sort_learned(ee, oo, m2)), oracle.sort(bb)[0])
+
+
+def test_fit_rejects_bad_arguments(gpu_lib):
+    b = config1(n=100)
+    e, o = gpu_lib.to_device(b)
+    for kw in (dict(sample_frac=1.5), dict(sample_frac=-0.1), dict(mode=9)):
+        with pytest.raises(gpu_lib.HuskyError):
+            _fit(gpu_lib, b, e, o, **kw)
