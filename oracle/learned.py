@@ -200,3 +200,24 @@ def splitters(lut, sorted_sample, B: int = BUCKETS):
         for i in range(1, k):
             out[b0 + i - 1] = int(sorted_sample[s_lo + (i * m) // k]) if m else _M64
     return out
+
+
+def sub_bits(k: int, cp: int) -> int:
+    """Bits of the sub-cell index of a heavy cell owning k >= 2 buckets."""
+    avail = max(0, 40 - cp)
+    return min(avail, 16, (k - 1).bit_length() + 1)
+
+
+def subtable(lut, split_slots, lo: int, cp: int, W: int, B: int = BUCKETS):
+    """(first bucket, s, table) of heavy cell W: table[v] = the cell's splitters
+    below the first code whose s bits right below the cell are v."""
+    b = (lut.astype(np.int64) * B) >> 32
+    b0, k = int(b[W]), int(b[W + 1] - b[W])
+    s = sub_bits(k, cp)
+    spl = np.array([split_slots[b0 + i] for i in range(k - 1)], dtype=np.uint64)
+    prefix = (lo >> (64 - cp)) << (64 - cp) if cp else 0
+    starts = np.array([prefix | (W << (40 - cp)) | (v << (40 - cp - s)) for v in range(1 << s)],
+                      dtype=np.uint64)
+    # splitters come from the sorted sample, so they are sorted
+    table = np.searchsorted(spl, starts, side="left")
+    return b0, s, [int(t) for t in table]

@@ -161,3 +161,23 @@ def test_splitters_brute_force():
     in_cell = sorted(k for k in keys if k >> 39 == 2)
     # cell 2 owns [1, 5): k = 4 buckets, m = 6 keys, splitters at ranks 6i // 4
     assert {s: out[s] for s in range(1, 4)} == {1 + i - 1: in_cell[(6 * i) // 4] for i in range(1, 4)}
+
+
+def test_subtable_brute_force():
+    # one heavy cell (cell 2) owning buckets [1, 5) of B = 8, cp = 1 (cells
+    # are bits 62..39), so sub-cells are the next s bits below bit 39
+    B = 8
+    step = (1 << 32) // B
+    lut = np.zeros(learned.CELLS + 1, dtype=np.int64)
+    lut[2] = step
+    lut[3:] = 5 * step
+    lut[-1] = 2**32 - 1
+    k = 4
+    s = learned.sub_bits(k, 1)
+    assert s == 3  # ceil(log2 4) + 1
+    subs = [0, 3, 3]  # sub-cell of each splitter
+    spl = {1 + i: (2 << 39) | (v << (39 - s)) | 5 for i, v in enumerate(subs)}
+    b0, s2, table = learned.subtable(lut, spl, 0, 1, 2, B=B)
+    assert (b0, s2) == (1, 3)
+    # splitters strictly below the first code of sub-cell v
+    assert table == [0, 1, 1, 1, 3, 3, 3, 3]
