@@ -202,22 +202,24 @@ def splitters(lut, sorted_sample, B: int = BUCKETS):
     return out
 
 
-def sub_bits(k: int, cp: int) -> int:
-    """Bits of the sub-cell index of a heavy cell owning k >= 2 buckets."""
-    avail = max(0, 40 - cp)
-    return min(avail, 16, (k - 1).bit_length() + 1)
+def sub_bits(k: int, P: int) -> int:
+    """Bits of the sub-cell index of a heavy cell owning k >= 2 buckets whose
+    splitters share their top P bits."""
+    return min(64 - P, 16, (k - 1).bit_length() + 1)
 
 
-def subtable(lut, split_slots, lo: int, cp: int, W: int, B: int = BUCKETS):
-    """(first bucket, s, table) of heavy cell W: table[v] = the cell's splitters
-    below the first code whose s bits right below the cell are v."""
+def subtable(lut, split_slots, W: int, B: int = BUCKETS):
+    """(first bucket, P, s, prefix, table) of heavy cell W: P = bits shared by its
+    first and last splitter, prefix = those bits (the rest zero), table[v] = the
+    cell's splitters below prefix | v << (64 - P - s)."""
     b = (lut.astype(np.int64) * B) >> 32
     b0, k = int(b[W]), int(b[W + 1] - b[W])
-    s = sub_bits(k, cp)
     spl = np.array([split_slots[b0 + i] for i in range(k - 1)], dtype=np.uint64)
-    prefix = (lo >> (64 - cp)) << (64 - cp) if cp else 0
-    starts = np.array([prefix | (W << (40 - cp)) | (v << (40 - cp - s)) for v in range(1 << s)],
-                      dtype=np.uint64)
+    first, last = int(spl[0]), int(spl[-1])
+    P = 64 if first == last else 64 - (first ^ last).bit_length()
+    s = sub_bits(k, P)
+    prefix = first if P == 64 else (first >> (64 - P)) << (64 - P)
+    starts = np.array([prefix | (v << (64 - P - s)) for v in range(1 << s)], dtype=np.uint64)
     # splitters come from the sorted sample, so they are sorted
     table = np.searchsorted(spl, starts, side="left")
-    return b0, s, [int(t) for t in table]
+    return b0, P, s, prefix, [int(t) for t in table]

@@ -164,20 +164,22 @@ def test_splitters_brute_force():
 
 
 def test_subtable_brute_force():
-    # one heavy cell (cell 2) owning buckets [1, 5) of B = 8, cp = 1 (cells
-    # are bits 62..39), so sub-cells are the next s bits below bit 39
+    # one heavy cell (cell 2) owning buckets [1, 5) of B = 8: three splitters
+    # sharing their top 44 bits, then sub-cells of the next s bits
     B = 8
     step = (1 << 32) // B
     lut = np.zeros(learned.CELLS + 1, dtype=np.int64)
     lut[2] = step
     lut[3:] = 5 * step
     lut[-1] = 2**32 - 1
-    k = 4
-    s = learned.sub_bits(k, 1)
-    assert s == 3  # ceil(log2 4) + 1
-    subs = [0, 3, 3]  # sub-cell of each splitter
-    spl = {1 + i: (2 << 39) | (v << (39 - s)) | 5 for i, v in enumerate(subs)}
-    b0, s2, table = learned.subtable(lut, spl, 0, 1, 2, B=B)
-    assert (b0, s2) == (1, 3)
-    # splitters strictly below the first code of sub-cell v
-    assert table == [0, 1, 1, 1, 3, 3, 3, 3]
+    base = 2 << 39
+    spl_vals = [base | (0b000 << 17) | 5, base | (0b011 << 17) | 9, base | (0b101 << 17) | 1]
+    spl = {1 + i: v for i, v in enumerate(spl_vals)}
+    b0, P, s, prefix, table = learned.subtable(lut, spl, 2, B=B)
+    assert b0 == 1 and P == 44 and s == 3 and prefix == base  # k = 4: ceil(log2 4) + 1
+    # splitters strictly below the first code of sub-cell v (bits 19..17)
+    brute = [sum(1 for x in spl_vals if x < (base | (v << 17))) for v in range(8)]
+    assert table == brute == [0, 1, 1, 1, 2, 2, 3, 3]
+    # all splitters equal: P = 64, no sub-cells
+    same = {1: base | 7, 2: base | 7, 3: base | 7}
+    assert learned.subtable(lut, same, 2, B=B)[1:4] == (64, 0, base | 7)
