@@ -205,7 +205,7 @@ def splitters(lut, sorted_sample, B: int = BUCKETS):
 def sub_bits(k: int, P: int) -> int:
     """Bits of the sub-cell index of a heavy cell owning k >= 2 buckets whose
     splitters share their top P bits."""
-    return min(64 - P, 16, (k - 1).bit_length() + 1)
+    return min(64 - P, 16, (k - 1).bit_length() + 3)
 
 
 def subtable(lut, split_slots, W: int, B: int = BUCKETS):

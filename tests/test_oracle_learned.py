@@ -176,10 +176,11 @@ def test_subtable_brute_force():
     spl_vals = [base | (0b000 << 17) | 5, base | (0b011 << 17) | 9, base | (0b101 << 17) | 1]
     spl = {1 + i: v for i, v in enumerate(spl_vals)}
     b0, P, s, prefix, table = learned.subtable(lut, spl, 2, B=B)
-    assert b0 == 1 and P == 44 and s == 3 and prefix == base  # k = 4: ceil(log2 4) + 1
-    # splitters strictly below the first code of sub-cell v (bits 19..17)
-    brute = [sum(1 for x in spl_vals if x < (base | (v << 17))) for v in range(8)]
-    assert table == brute == [0, 1, 1, 1, 2, 2, 3, 3]
+    assert b0 == 1 and P == 44 and s == 5 and prefix == base  # k = 4: ceil(log2 4) + 3
+    # splitters strictly below the first code of sub-cell v (bits 19..15)
+    brute = [sum(1 for x in spl_vals if x < (base | (v << 15))) for v in range(32)]
+    assert table == brute
+    assert table[:4] == [0, 1, 1, 1] and table[12] == 1 and table[13] == 2 and table[21] == 3
     # all splitters equal: P = 64, no sub-cells
     same = {1: base | 7, 2: base | 7, 3: base | 7}
     assert learned.subtable(lut, same, 2, B=B)[1:4] == (64, 0, base | 7)
