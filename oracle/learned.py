@@ -223,3 +223,26 @@ def subtable(lut, split_slots, W: int, B: int = BUCKETS):
     # splitters come from the sorted sample, so they are sorted
     table = np.searchsorted(spl, starts, side="left")
     return b0, P, s, prefix, [int(t) for t in table]
+
+
+def bucket_ids(codes, lut, splitters, lo: int, hi: int, cp: int, B: int = BUCKETS):
+    """Bucket of every code: clamp to [lo, hi], cell W; b0 = LUT[W] * B >> 32,
+    b1 likewise from LUT[W + 1]; a cell owning k = b1 - b0 >= 2 buckets adds
+    the number of its splitters (slots b0 .. b0 + k - 2) not above the code."""
+    c = np.clip(np.asarray(codes, dtype=np.uint64), np.uint64(lo), np.uint64(hi))
+    if cp >= 64:
+        W = np.zeros(c.shape, dtype=np.int64)
+    else:
+        W = ((c << np.uint64(cp)) >> np.uint64(40)).astype(np.int64)
+    b = (np.asarray(lut, dtype=np.int64) * B) >> 32
+    b0, b1 = b[W], b[W + 1]
+    out = b0.copy()
+    heavy = np.nonzero(b1 - b0 >= 2)[0]
+    if heavy.size:
+        cells = W[heavy]
+        for w in np.unique(cells):
+            sel = heavy[cells == w]
+            lo_b, k = int(b[w]), int(b[w + 1] - b[w])
+            spl = np.asarray(splitters[lo_b:lo_b + k - 1], dtype=np.uint64)
+            out[sel] = lo_b + np.searchsorted(spl, c[sel], side="right")
+    return out

@@ -184,3 +184,33 @@ def test_subtable_brute_force():
     # all splitters equal: P = 64, no sub-cells
     same = {1: base | 7, 2: base | 7, 3: base | 7}
     assert learned.subtable(lut, same, 2, B=B)[1:4] == (64, 0, base | 7)
+
+
+def test_bucket_ids_brute_force():
+    # B = 8; cells 0-1 own nothing, cell 2 owns [1, 5) with splitters, cell 3
+    # onwards own [5, 7) but cell 3 alone starts there (one bucket each side)
+    B = 8
+    step = (1 << 32) // B
+    lut = np.zeros(learned.CELLS + 1, dtype=np.int64)
+    lut[2] = step
+    lut[3] = 5 * step
+    lut[4:] = 6 * step
+    lut[-1] = 2**32 - 1
+    lo, hi, cp = 0, (1 << 63) - 1, 1  # cells are bits 62..39
+    base = 2 << 39
+    spl = np.zeros(B, dtype=np.uint64)
+    spl[1:4] = [base | 100, base | 200, base | 200]
+    codes = np.array([0, 1 << 39, base, base | 100, base | 150, base | 200, base | 201,
+                      3 << 39, 4 << 39, hi], dtype=np.uint64)
+    got = learned.bucket_ids(codes, lut, spl, lo, hi, cp, B=B)
+
+    def brute(c):
+        W = (int(c) >> 39) & 0xFFFFFF
+        b0, b1 = (lut[W] * B) >> 32, (lut[W + 1] * B) >> 32
+        if b1 - b0 < 2:
+            return b0
+        return b0 + sum(1 for j in range(b1 - b0 - 1) if int(spl[b0 + j]) <= int(c))
+
+    assert [int(g) for g in got] == [brute(c) for c in codes] == [0, 0, 1, 2, 2, 4, 4, 5, 6, 6]
+    # monotone in the code
+    assert np.all(np.diff(got) >= 0)
