@@ -44,12 +44,14 @@ def _function_text(src: str, signature: str) -> str:
 
 
 def _src_sha(path: str) -> str:
-    """Hash of the scatter kernel's own source: rank_tile and load_striped (rank.h), k_scatter."""
+    """Hash of the scatter kernel's own source: rank_digits, rank_tile and load_striped
+    (rank.h), k_scatter."""
     with open(os.path.join(os.path.dirname(path), "rank.h")) as f:
         rank = f.read()
     with open(path) as f:
         src = f.read()
-    parts = [_function_text(rank, "__device__ __forceinline__ void rank_tile("),
+    parts = [_function_text(rank, "__device__ __forceinline__ void rank_digits("),
+             _function_text(rank, "__device__ __forceinline__ void rank_tile("),
              _function_text(rank, "__device__ __forceinline__ void load_striped("),
              _function_text(src, "__global__ __launch_bounds__(BLOCK) void k_scatter(")]
     return hashlib.sha256("".join(parts).encode()).hexdigest()[:16]
@@ -101,8 +103,9 @@ def main(argv=None):
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a 256 MiB device copy (calibrates HBM byte counters)")
-    ap.add_argument("--mode", choices=["plain", "batched"], default="plain",
-                    help="plain: the metric's workload; batched: 4,096 instances vs a loop of plain sorts")
+    ap.add_argument("--mode", choices=["plain", "batched", "learned"], default="plain",
+                    help="plain: the metric's workload; batched: 4,096 instances vs a loop of "
+                         "plain sorts; learned: 2e8 URL-like strings, learned-CDF vs plain")
     args = ap.parse_args(argv)
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the sort is not "
@@ -122,6 +125,8 @@ def main(argv=None):
             dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    if args.mode == "learned":
+        return bench_learned(args)
     if args.mode == "batched":
         return bench_batched(args)
     batch = config2(seed=1, n=args.n)
@@ -292,6 +297,111 @@ def bench_batched(args):
         "speedup_batched_vs_loop": round(ms_loop / ms_tuned, 2),
         "tuning": res["tuning"],
         "tuner_table": [{"params": r["params"], "ms": round(r["ms"], 3)} for r in res["table"]],
+    }
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+def _kernels(prof, steps):
+    return {k: {"ms_per_step": round(v[0] / steps, 4), "launches_per_step": round(v[1] / steps, 2)}
+            for k, v in prof.items() if v[1]}
+
+
+def bench_learned(args):
+    """Config 5 (2e8 URL-like strings): learned-CDF form vs the plain GPU path, same input."""
+    import torch
+
+    import paper_2012_00866_amd as husky
+    from workloads import config5
+
+    n = args.n if args.n != (1 << 24) else 200_000_000
+    t_gen = time.perf_counter()
+    batch = config5(n=n, seed=1)
+    t_gen = time.perf_counter() - t_gen
+    mean_len = batch.elems.size / n
+    elems, offsets = husky.to_device(batch)
+    del batch
+    print(f"[bench] {n} strings resident ({t_gen:.1f} s to generate)", file=sys.stderr, flush=True)
+    ws = husky.alloc_learned_workspace(n)
+    perm = torch.empty(n, dtype=torch.int32, device="cuda")
+    steps = max(3, min(args.steps, 10))
+
+    def plain():
+        husky.sort(elems, offsets, "ascii7", ws=ws, perm=perm, check_status=False)
+
+    ms_plain = _time(plain, steps, 1)
+    ref = perm.clone()
+    husky.profile_begin()
+    for _ in range(steps):
+        plain()
+    k_plain = _kernels(husky.profile_end(), steps)
+
+    def fit(**kw):
+        return husky.fit_learned(elems, offsets, "ascii7", husky.make_learned_params(**kw), ws=ws)
+
+    variants = {}
+    model = None
+    for name, kw in (("monotone", {}), ("equal_width", {"mode": "equal_width"}),
+                     ("untrained", {"mode": "untrained"}), ("network_alone", {"dense": False}),
+                     ("equal_width_alone", {"mode": "equal_width", "dense": False})):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        m = fit(**kw)
+        torch.cuda.synchronize()
+        ms_fit = (time.perf_counter() - t0) * 1e3
+        ms = _time(lambda: husky.sort_learned(elems, offsets, m, "ascii7", ws=ws, perm=perm,
+                                              check_status=False), steps, 1)
+        st = husky.read_status(ws)
+        same = bool(torch.equal(perm, ref))
+        assert same, f"learned form ({name}) differs from the plain path"
+        h = husky.learned_header(m)
+        ids = husky.learned_buckets(elems, offsets, m, "ascii7").to(torch.int64) & 0xFFFF
+        load = torch.bincount(ids, minlength=husky.LEARNED_BUCKETS).to(torch.float64)
+        exp_load = float((load * load).sum() / n)
+        del ids, load
+        variants[name] = {"sort_ms": round(ms, 3), "fit_ms": round(ms_fit, 2), "identical": same,
+                          "expected_bucket_load": round(exp_load, 1),
+                          "overflow_buckets": st["overflow_buckets"],
+                          "overflow_keys_frac": round(st["overflow_keys"] / n, 4),
+                          "adam_steps": h["steps"], "dense_cells": h["dense"],
+                          "dense_sample_frac": round(h["dense_keys"] / max(h["sample"], 1), 4),
+                          "trained_on": h["trained"], "last_loss": round(float(h["last_loss"]), 6)}
+        print(f"[bench] {name}: {variants[name]}", file=sys.stderr, flush=True)
+        if name == "monotone":
+            model = m
+        else:
+            del m
+    ms_learned = variants["monotone"]["sort_ms"]
+    husky.profile_begin()
+    for _ in range(steps):
+        husky.sort_learned(elems, offsets, model, "ascii7", ws=ws, perm=perm, check_status=False)
+    prof = husky.profile_end()
+    k_learned = _kernels(prof, steps)
+    ms_bs, nb = prof["learned_bucket_scatter"]
+    out = {
+        "metric": "Mstrings/s sorted (bit-exact), learned-CDF form vs plain",
+        "value": round(n / (ms_learned / 1e3) / 1e6, 3),
+        "unit": "Mstrings/s",
+        "n_gpus": 1,
+        "steps": steps,
+        "ms_per_step": ms_learned,
+        "higher_is_better": True,
+        "dtype": "u64",
+        "data": "synthetic",
+        "config": {"workload": "URL-like strings: 'h' + host id (Zipf 1.2 over 10,000 hosts, "
+                               "seeded id permutation) + '/' + 1-4 lowercase segments of 3-10",
+                   "n": n, "mean_bytes": round(mean_len, 2), "seed": 1, "sample_frac": 0.01,
+                   "buckets": 65536, "ideal_bucket_load": round(n / 65536, 1)},
+        "plain_ms": round(ms_plain, 3),
+        "plain_mstrings_s": round(n / (ms_plain / 1e3) / 1e6, 3),
+        "speedup_learned_vs_plain": round(ms_plain / ms_learned, 3),
+        "fit_ms": variants["monotone"]["fit_ms"],
+        "inclusive_ms": round(ms_learned + variants["monotone"]["fit_ms"], 3),
+        "variants": variants,
+        # each bucket pass reads and writes the 8-byte code, the 4-byte index and the 2-byte id
+        "bucket_scatter_gbs": round(28.0 * n * nb / (ms_bs / 1e3) / 1e9, 1) if nb else None,
+        "kernels_learned": k_learned,
+        "kernels_plain": k_plain,
     }
     print(json.dumps(out), flush=True)
     return 0

@@ -90,7 +90,9 @@ typedef struct {
  *   t_small    -- equal-code runs of at most this many strings are sorted by
  *                 one wavefront (2..64);
  *   t_medium   -- runs of at most this many by one workgroup in LDS
- *                 (t_small < t_medium <= 4096); longer runs device-wide;
+ *                 (t_small < t_medium <= 4096, default 1024); longer runs
+ *                 device-wide (a run of at most one radix tile is then
+ *                 sorted in LDS by the segmented radix sort);
  *   max_rounds -- 0: the device-wide fix-up reads its work counts back to
  *                 the host once per refinement round (adaptive).  k > 0: it
  *                 runs exactly k rounds sized from host bounds, with no
@@ -192,8 +194,9 @@ husky_status husky_check_perm(husky_coder coder, const void* elems, const uint64
  * 5 single-tile LDS sort, 6 run detection, 7 wavefront fix-up, 8 workgroup
  * fix-up, 9 device-wide refinement keys, 10 segment setup, 11 radix scatter
  * pass of the device-wide fix-up (class 3 counts only the sort of the
- * codes), 12 learned bucket scatter pass, 13 learned bucket ids, 14 learned
- * bucket bounds.  Not for use during graph capture.
+ * codes), 12 learned bucket scatter pass, 13 learned bucket bounds (the
+ * learned form's bucket ids are computed by the encode kernel, class 0).
+ * Not for use during graph capture.
  * Returns HUSKY_OK or HUSKY_ERR_HIP. */
 void husky_profile_begin(void);
 int husky_profile_end(double* ms, uint32_t* launches, int n_classes);
@@ -223,7 +226,9 @@ int husky_profile_end(double* ms, uint32_t* launches, int n_classes);
  *     LUT[0] = 0, LUT[2^24] = 2^32 - 1; cell W owns the buckets
  *     [LUT[W] * B >> 32, LUT[W + 1] * B >> 32);
  *   - a cell owning k >= 2 buckets splits its codes by k - 1 equal-depth
- *     splitters taken from the cell's sorted sample codes.
+ *     splitters taken from the cell's sorted sample codes; a table over the
+ *     bits right below the splitters' common prefix ("sub-cells") narrows
+ *     each key's search to the splitters of its sub-cell.
  * The network: 1 -> 64 -> 64 -> 1, ReLU after both hidden layers, every
  * weight softplus(raw parameter) > 0 (so it never decreases in x), output
  * clamped to [0, 1]; trained in FP32 by mean squared error against the
@@ -247,8 +252,8 @@ typedef enum {
 typedef struct {
     double sample_frac; /* fraction of the strings sampled, (0, 1]; default 0.01 */
     uint64_t seed;      /* sample and initialisation seed; default 1 */
-    uint32_t epochs;    /* default 6 */
-    uint32_t batch;     /* samples per Adam step; default 16384 */
+    uint32_t epochs;    /* default (0): enough for at least 400 Adam steps, at most 200 */
+    uint32_t batch;     /* samples per Adam step; default 4096 */
     float lr;           /* Adam step size; default 0.01 */
     uint32_t mode;      /* husky_learned_mode */
     uint32_t flags;     /* HUSKY_LEARNED_NO_DENSE */
@@ -281,7 +286,13 @@ typedef enum {
     HUSKY_LM_LUT = 4,       /* uint32[2^24 + 1] */
     HUSKY_LM_SPLITTERS = 5, /* uint64[B] */
     HUSKY_LM_DENSE = 6,     /* uint32[B / 2] dense cells, ascending */
-    HUSKY_LM_DENSE_CUM = 7  /* uint32[B / 2 + 1] dense sample keys before each */
+    HUSKY_LM_DENSE_CUM = 7, /* uint32[B / 2 + 1] dense sample keys before each */
+    HUSKY_LM_SUBTAB = 8,    /* uint16[16 B]: per heavy cell at 16 * first bucket: header {u16 P,
+                             * u16 s, u32 0, u64 prefix}, then 2^s splitter counts, one per
+                             * sub-cell (the s bits below the splitters' P-bit common prefix) */
+    HUSKY_LM_CELLINFO = 9   /* uint64[2^24]: per cell, first bucket | end bucket << 16, and for
+                             * a heavy cell P << 32 | s << 39 | the prefix bits below the cell
+                             * << 44 (bit 63: read P, s and prefix from its subtab header) */
 } husky_learned_part;
 
 /* Size of the model buffer, and the byte offset of each part in it (SIZE_MAX
@@ -313,6 +324,14 @@ husky_status husky_learned_fit(husky_coder coder, const void* elems, const uint6
 husky_status husky_sort_learned(husky_coder coder, const void* elems, const uint64_t* offsets,
                                 uint64_t n, const void* model, uint32_t* perm, void* ws,
                                 size_t ws_bytes, const husky_tuning* tuning, void* stream);
+
+/* The bucket function alone: bucket[i] (uint16, device) = the bucket of
+ * string i's code under the fitted model (the ids husky_sort_learned sorts
+ * by; also the unit a sort would be range-partitioned by across devices).
+ * status as in husky_encode (may be NULL).  Errors: HUSKY_ERR_ARG, HUSKY_ERR_HIP. */
+husky_status husky_learned_buckets(husky_coder coder, const void* elems, const uint64_t* offsets,
+                                   uint64_t n, const void* model, uint16_t* bucket,
+                                   uint32_t* status, void* stream);
 
 /* The training kernel alone, for checking it: grad (float[NPARAM + 1]) gets
  * the gradient of the mean squared error of the network (monotone != 0:

@@ -61,13 +61,13 @@ EXPORTS = ("husky_workspace_bytes", "husky_encode", "husky_sort_pairs", "husky_f
            "husky_sort", "husky_sort_batched", "husky_check_perm", "husky_profile_begin",
            "husky_profile_end", "husky_learned_model_bytes", "husky_learned_offset",
            "husky_learned_workspace_bytes", "husky_learned_fit", "husky_sort_learned",
+           "husky_learned_buckets",
            "husky_mlp_grad_workspace_bytes", "husky_mlp_grad", "husky_status_string")
 
 # kernel classes of husky_profile_end (include/husky.h)
 PROFILE_CLASSES = ("encode", "radix_vary", "radix_count_scan", "radix_scatter", "radix_copy_back",
                    "tile_sort", "runs", "fixup_small", "fixup_medium", "large_keys", "segment_setup",
-                   "radix_scatter_fixup", "learned_bucket_scatter", "learned_bucket_ids",
-                   "learned_bucket_bounds")
+                   "radix_scatter_fixup", "learned_bucket_scatter", "learned_bucket_bounds")
 
 # learned form (include/husky.h)
 LEARNED_BUCKETS = 65536
@@ -77,7 +77,7 @@ LEARNED_MODES = {"monotone": 0, "unconstrained": 1, "equal_width": 2, "untrained
                  "constant": 4}
 LEARNED_NO_DENSE = 1
 LM_PARTS = {"header": 0, "params": 1, "adam_m": 2, "adam_v": 3, "lut": 4, "splitters": 5,
-            "dense": 6, "dense_cum": 7}
+            "dense": 6, "dense_cum": 7, "subtab": 8, "cellinfo": 9}
 
 
 class LearnedParams(ctypes.Structure):
@@ -136,6 +136,8 @@ def load(path: str = LIB_PATH):
                                       sz, vp]
     lib.husky_sort_learned.restype = i32
     lib.husky_sort_learned.argtypes = [i32, vp, vp, u64, vp, vp, vp, sz, tp, vp]
+    lib.husky_learned_buckets.restype = i32
+    lib.husky_learned_buckets.argtypes = [i32, vp, vp, u64, vp, vp, vp, vp]
     lib.husky_mlp_grad_workspace_bytes.restype = sz
     lib.husky_mlp_grad_workspace_bytes.argtypes = [ctypes.c_uint32]
     lib.husky_mlp_grad.restype = i32
@@ -381,6 +383,17 @@ def sort_learned(elems, offsets, model, coder="ascii7", tuning: Optional[Tuning]
         if st["domain_violations"]:
             raise DomainError(2, f"husky_sort_learned ({st['domain_violations']} strings)")
     return perm[:n]
+
+
+def learned_buckets(elems, offsets, model, coder="ascii7", stream=None):
+    """Bucket id (int16 storage of uint16[n]) of every string under a fitted model."""
+    torch = _torch()
+    lib = load()
+    n = _n_of(offsets)
+    out = torch.empty(max(n, 1), dtype=torch.int16, device=offsets.device)
+    _check(lib.husky_learned_buckets(_coder(coder), _ptr(elems), _ptr(offsets), n, _ptr(model),
+                                     _ptr(out), None, _stream(stream)), "husky_learned_buckets")
+    return out[:n]
 
 
 def mlp_grad(params, x, y, monotone=True, stream=None):

@@ -7,6 +7,7 @@
 #include <cmath>
 
 #include "../../include/husky.h"
+#include "bucket.h"
 #include "common.h"
 #include "internal.h"
 
@@ -151,7 +152,7 @@ struct Tune {
 };
 
 husky_status resolve_tuning(const husky_tuning* t, Tune* out) {
-    Tune r{{8, 16}, 64, 4096, 0};
+    Tune r{{8, 16}, 64, 1024, 0};
     if (t) {
         if (t->radix_bits) r.rc.bits = t->radix_bits;
         if (t->tile_items) r.rc.items = t->tile_items;
@@ -419,7 +420,7 @@ husky_status husky_learned_fit(husky_coder coder, const void* elems, const uint6
     if (st != HUSKY_OK) return st;
     if (n == 0) return HUSKY_ERR_ARG;
     if ((st = check_model(model, model_bytes)) != HUSKY_OK) return st;
-    husky_learned_params p{0.01, 1, 6, 16384, 0.01f, HUSKY_LEARNED_MONOTONE, 0, 0};
+    husky_learned_params p{0.01, 1, 0, 4096, 0.01f, HUSKY_LEARNED_MONOTONE, 0, 0};
     if (params) {
         if (params->sample_frac != 0.0) p.sample_frac = params->sample_frac;
         if (params->seed) p.seed = params->seed;
@@ -472,7 +473,14 @@ husky_status husky_learned_fit(husky_coder coder, const void* elems, const uint6
     const uint32_t count = S - std::min(dense_keys, S);
     HUSKY_TRY(learned_init(model, p.seed, p.mode == HUSKY_LEARNED_UNCONSTRAINED, s));
     const bool train = p.mode == HUSKY_LEARNED_MONOTONE || p.mode == HUSKY_LEARNED_UNCONSTRAINED;
-    HUSKY_TRY(learned_train(model, x, y, train ? count : 0u, p.epochs, p.batch, p.lr,
+    // epochs 0: as many as give at least MIN_STEPS Adam steps (at most 200)
+    uint32_t epochs = p.epochs;
+    if (!epochs) {
+        constexpr uint32_t MIN_STEPS = 400;
+        const uint32_t per_epoch = std::max(1u, (count + p.batch - 1) / p.batch);
+        epochs = std::min(200u, std::max(1u, (MIN_STEPS + per_epoch - 1) / per_epoch));
+    }
+    HUSKY_TRY(learned_train(model, x, y, train ? count : 0u, epochs, p.batch, p.lr,
                             p.mode != HUSKY_LEARNED_UNCONSTRAINED, c.at<float>(L.lpartial),
                             LEARN_MAX_BLOCKS, grad, loss_acc, s));
     HUSKY_TRY(learned_build_lut(model, p.mode, c.at<uint32_t>(L.ltmax), s));
@@ -502,11 +510,13 @@ husky_status husky_sort_learned(husky_coder coder, const void* elems, const uint
     uint16_t* bid_b = bid_a + n;
     uint64_t* bseg = c.at<uint64_t>(L.bseg);
     const uint32_t nn = (uint32_t)n;
-    HUSKY_TRY(launch_encode(coder, elems, offsets, nn, codes, perm, c.at<uint64_t>(L.key0),
-                            &c.status->domain_violations, s));
-    // bucket ids, then two stable 8-bit passes over them (low byte, high byte)
-    HUSKY_TRY(learned_bucket_ids(model, codes, nn, bid_a, s));
-    HUSKY_TRY(learned_bucket_pass(0, codes, perm, bid_a, codes_b, idx_b, bid_b, nn, c.rad.cnt,
+    // codes, first refinement keys and bucket ids in one pass over the strings,
+    // then two stable 8-bit passes over the ids (low byte, high byte); the
+    // first pass takes the indices from the input order
+    const BucketArgs ba = learned_bucket_args(model, bid_a);
+    HUSKY_TRY(launch_encode(coder, elems, offsets, nn, codes, nullptr, c.at<uint64_t>(L.key0),
+                            &c.status->domain_violations, s, nullptr, 0, &ba));
+    HUSKY_TRY(learned_bucket_pass(0, codes, nullptr, bid_a, codes_b, idx_b, bid_b, nn, c.rad.cnt,
                                   c.rad.gtot, c.rad.binstart, s));
     HUSKY_TRY(learned_bucket_pass(1, codes_b, idx_b, bid_b, codes, perm, bid_a, nn, c.rad.cnt,
                                   c.rad.gtot, c.rad.binstart, s));
@@ -521,8 +531,22 @@ husky_status husky_sort_learned(husky_coder coder, const void* elems, const uint
     HUSKY_TRY(radix_exec_masks(0, end_bit, B, tb, c.rad, tn.rc, s));
     HUSKY_TRY(radix_sort_segments(codes, perm, codes_b, idx_b, 0, end_bit, B, tb, ~0u, c.rad, tn.rc,
                                   P_SCATTER, s));
-    // equal codes share a bucket, so runs never cross bucket boundaries
-    return run_fixup(c, tn, coder, elems, offsets, n, B, codes, codes, codes_b, perm, s);
+    // the array is now sorted by code as a whole (buckets are in code order),
+    // so the fix-up sees it as one instance, as in husky_sort
+    HUSKY_TRY(radix_segments_single(nn, c.rad, tn.rc, s));
+    return run_fixup(c, tn, coder, elems, offsets, n, 1, codes, codes, codes_b, perm, s);
+}
+
+husky_status husky_learned_buckets(husky_coder coder, const void* elems, const uint64_t* offsets,
+                                   uint64_t n, const void* model, uint16_t* bucket,
+                                   uint32_t* status, void* stream) {
+    husky_status st = check_common(coder, elems, offsets, n);
+    if (st != HUSKY_OK) return st;
+    if (n > 0 && !bucket) return HUSKY_ERR_ARG;
+    if ((st = check_model(model, learned_model_bytes())) != HUSKY_OK) return st;
+    const BucketArgs ba = learned_bucket_args(model, bucket);
+    return hip_status(launch_encode(coder, elems, offsets, (uint32_t)n, nullptr, nullptr, nullptr,
+                                    status, (hipStream_t)stream, nullptr, 0, &ba));
 }
 
 size_t husky_mlp_grad_workspace_bytes(uint32_t count) {

@@ -97,6 +97,17 @@ __device__ __forceinline__ uint32_t wave_inclusive_sum(uint32_t v) {
 // Exclusive prefix sum over the BLOCK threads of a workgroup.  `scratch`
 // holds NWAVES words of LDS.  Returns the exclusive prefix; *total gets the
 // block total.  Every thread of the block must call it.
+// Workgroups of a launch are dispatched to the 8 XCDs round-robin (block b
+// on XCD b % 8), each XCD behind its own L2.  xcd_remap(b, G) hands each XCD a
+// contiguous range of the G tiles instead, so that neighbouring tiles -- whose
+// scattered writes share cache lines -- complete their lines in one L2.  It is
+// a bijection of [0, G), so it only changes which workgroup runs which tile.
+__device__ __forceinline__ uint32_t xcd_remap(uint32_t b, uint32_t G) {
+    constexpr uint32_t X = 8;
+    const uint32_t q = G / X, r = G % X, x = b % X, i = b / X;
+    return x * q + (x < r ? x : r) + i;
+}
+
 __device__ __forceinline__ uint32_t block_exclusive_sum(uint32_t v, uint32_t* scratch,
                                                         uint32_t* total) {
     const uint32_t lane = lane_id(), wid = threadIdx.x / WAVE;

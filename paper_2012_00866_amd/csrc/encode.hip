@@ -10,6 +10,7 @@
 // which is stringToLong's "shift in each character, then shift in the
 // padding" written as fixed bit positions.
 
+#include "bucket.h"
 #include "common.h"
 #include "internal.h"
 
@@ -19,7 +20,9 @@ namespace husky {
 // chunk the fix-up compares first inside a run of equal codes (see
 // fixup.hip for its layout).  Computing it here, while the string's bytes are
 // streamed in order, spares the fix-up a random gather per run member.
-template <int CODER>
+// With LEARNED, each code's bucket under a fitted learned-CDF model is
+// computed here as well, while the code is still in a register.
+template <int CODER, bool LEARNED>
 __global__ __launch_bounds__(BLOCK) void k_encode(const uint8_t* __restrict__ bytes,
                                                   const uint64_t* __restrict__ offsets,
                                                   uint32_t n,
@@ -28,12 +31,19 @@ __global__ __launch_bounds__(BLOCK) void k_encode(const uint8_t* __restrict__ by
                                                   uint64_t* __restrict__ key0,
                                                   uint32_t* __restrict__ status,
                                                   const uint32_t* __restrict__ sel,
-                                                  uint32_t n_out) {
+                                                  uint32_t n_out, BucketArgs bucket) {
     // bytes in the element buffer (uniform scalar load): the three-word
     // window below is used only where it stays inside the buffer.
     const uint64_t total_bytes = offsets[n] * (CODER == 0 ? 1u : 2u);
     uint32_t bad_here = 0;
     const uint32_t count = sel ? n_out : n;
+    uint64_t m_lo = 0, m_hi = 0;
+    uint32_t m_cp = 0;
+    if (LEARNED) {
+        m_lo = bucket.hdr->lo;
+        m_hi = bucket.hdr->hi;
+        m_cp = bucket.hdr->cp;
+    }
     for (uint32_t t = blockIdx.x * BLOCK + threadIdx.x; t < count; t += gridDim.x * BLOCK) {
         const uint32_t i = sel ? sel[t] : t;
         const uint64_t o0 = offsets[i], o1 = offsets[i + 1];
@@ -97,6 +107,7 @@ __global__ __launch_bounds__(BLOCK) void k_encode(const uint8_t* __restrict__ by
         if (codes) codes[t] = code;
         if (idx) idx[t] = i;
         if (key0) key0[t] = k0;
+        if (LEARNED) bucket.bid[t] = (uint16_t)bucket_of(bucket, code, m_lo, m_hi, m_cp);
     }
     if (CODER == 0 && status) {
         // one atomic per wavefront that saw a violation
@@ -112,17 +123,23 @@ __global__ __launch_bounds__(BLOCK) void k_encode(const uint8_t* __restrict__ by
 
 hipError_t launch_encode(int coder, const void* elems, const uint64_t* offsets, uint32_t n,
                          uint64_t* codes, uint32_t* idx, uint64_t* key0, uint32_t* status,
-                         hipStream_t s, const uint32_t* sel, uint32_t n_out) {
+                         hipStream_t s, const uint32_t* sel, uint32_t n_out,
+                         const BucketArgs* bucket) {
     const uint32_t count = sel ? n_out : n;
     if (count == 0) return hipSuccess;
     const uint32_t blocks = (count + BLOCK - 1) / BLOCK;
     ProfScope ps(P_ENCODE, s);
-    if (coder == 0)
-        hipLaunchKernelGGL(k_encode<0>, dim3(blocks), dim3(BLOCK), 0, s, (const uint8_t*)elems,
-                           offsets, n, codes, idx, key0, status, sel, n_out);
-    else
-        hipLaunchKernelGGL(k_encode<1>, dim3(blocks), dim3(BLOCK), 0, s, (const uint8_t*)elems,
-                           offsets, n, codes, idx, key0, status, sel, n_out);
+    const BucketArgs b = bucket ? *bucket : BucketArgs{};
+    const uint8_t* e = (const uint8_t*)elems;
+#define HUSKY_ENC(C, L)                                                                           \
+    hipLaunchKernelGGL((k_encode<C, L>), dim3(blocks), dim3(BLOCK), 0, s, e, offsets, n, codes, idx, \
+                       key0, status, sel, n_out, b)
+    if (coder == 0) {
+        if (bucket) HUSKY_ENC(0, true); else HUSKY_ENC(0, false);
+    } else {
+        if (bucket) HUSKY_ENC(1, true); else HUSKY_ENC(1, false);
+    }
+#undef HUSKY_ENC
     return hipGetLastError();
 }
 

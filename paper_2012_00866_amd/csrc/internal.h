@@ -13,7 +13,7 @@ namespace husky {
 enum ProfClass {
     P_ENCODE = 0, P_VARY = 1, P_COUNT_SCAN = 2, P_SCATTER = 3, P_COPY_BACK = 4, P_TILE_SORT = 5,
     P_RUNS = 6, P_FIX_SMALL = 7, P_FIX_MEDIUM = 8, P_LARGE_KEYS = 9, P_SETUP = 10,
-    P_SCATTER_FIX = 11, P_BUCKET = 12, P_BUCKET_MAP = 13, P_BUCKET_BOUNDS = 14, P_NUM = 15
+    P_SCATTER_FIX = 11, P_BUCKET = 12, P_BUCKET_BOUNDS = 13, P_NUM = 14
 };
 bool prof_on();
 class ProfScope {
@@ -29,9 +29,12 @@ class ProfScope {
 // ---- encode.hip
 // codes, idx and key0 (the first refinement key of every string) may each be
 // null.  With sel, entry i codes string sel[i] (i < n_out) instead of string i.
+// With bucket, every code's learned bucket id is written too (bucket.h).
+struct BucketArgs;
 hipError_t launch_encode(int coder, const void* elems, const uint64_t* offsets, uint32_t n,
                          uint64_t* codes, uint32_t* idx, uint64_t* key0, uint32_t* status,
-                         hipStream_t s, const uint32_t* sel = nullptr, uint32_t n_out = 0);
+                         hipStream_t s, const uint32_t* sel = nullptr, uint32_t n_out = 0,
+                         const BucketArgs* bucket = nullptr);
 
 // ---- radix.hip
 struct RadixConfig {
@@ -159,8 +162,7 @@ hipError_t learned_train(void* model, const float* x, const float* y, uint32_t c
                          uint32_t max_blocks, float* grad, float* loss_acc, hipStream_t s);
 hipError_t learned_build_lut(void* model, uint32_t mode, uint32_t* tmax, hipStream_t s);
 hipError_t learned_splitters(void* model, const uint64_t* sorted_sample, uint32_t S, hipStream_t s);
-hipError_t learned_bucket_ids(const void* model, const uint64_t* codes, uint32_t n, uint16_t* bid,
-                              hipStream_t s);
+BucketArgs learned_bucket_args(const void* model, uint16_t* bid);
 hipError_t learned_bucket_pass(int pass, const uint64_t* ks, const uint32_t* vs, const uint16_t* bs,
                                uint64_t* kd, uint32_t* vd, uint16_t* bd, uint32_t n, uint32_t* cnt,
                                uint32_t* gtot, uint32_t* binstart, hipStream_t s);

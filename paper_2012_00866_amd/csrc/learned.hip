@@ -34,6 +34,7 @@
 #include "../../include/husky.h"
 #include "common.h"
 #include "internal.h"
+#include "bucket.h"
 #include "rank.h"
 
 namespace husky {
@@ -42,7 +43,6 @@ constexpr int HID = 64;
 constexpr int NPARAM = HID + HID + HID * HID + HID + HID + 1;  // 4353
 constexpr int O_V1 = 0, O_B1 = HID, O_V2 = 2 * HID, O_B2 = 2 * HID + HID * HID, O_V3 = O_B2 + HID,
               O_B3 = O_V3 + HID;
-constexpr uint32_t LUT_CELLS = 1u << 24;
 constexpr int MLP_T = 256;  // threads (and samples per round) of the training kernel
 
 using LearnedHeader = husky_learned_header;
@@ -57,6 +57,8 @@ struct ModelView {
     uint64_t* splitters;  // [B]
     uint32_t* dense;      // [B / 2] dense cells, ascending
     uint32_t* dense_cum;  // [B / 2 + 1] dense sample keys in the dense cells before each
+    uint16_t* subtab;     // [16 B] per heavy cell: header, then splitters below each sub-cell
+    uint64_t* cellinfo;   // [2^24] buckets of every cell (and sub-cell keys of heavy ones)
 };
 constexpr uint32_t MAX_DENSE = LEARNED_BUCKETS / 2;
 constexpr uint32_t DENSE_MIN = 16;
@@ -64,19 +66,22 @@ constexpr uint32_t DENSE_MIN = 16;
 static size_t al256(size_t x) { return (x + 255) / 256 * 256; }
 
 // Byte offsets of the model's parts (husky_learned_part order), then the total.
-static void model_offsets(size_t off[9]) {
+constexpr int N_PARTS = 10;
+static void model_offsets(size_t off[N_PARTS + 1]) {
     size_t o = 0;
-    const size_t sz[8] = {256, NPARAM * 4, NPARAM * 4, NPARAM * 4, (size_t)(LUT_CELLS + 1) * 4,
-                          (size_t)LEARNED_BUCKETS * 8, (size_t)MAX_DENSE * 4, (size_t)(MAX_DENSE + 1) * 4};
-    for (int i = 0; i < 8; ++i) {
+    const size_t sz[N_PARTS] = {256, NPARAM * 4, NPARAM * 4, NPARAM * 4, (size_t)(LUT_CELLS + 1) * 4,
+                                (size_t)LEARNED_BUCKETS * 8, (size_t)MAX_DENSE * 4,
+                                (size_t)(MAX_DENSE + 1) * 4, (size_t)LEARNED_BUCKETS * SUB_SLOT * 2,
+                                (size_t)LUT_CELLS * 8};
+    for (int i = 0; i < N_PARTS; ++i) {
         off[i] = o;
         o += al256(sz[i]);
     }
-    off[8] = o;
+    off[N_PARTS] = o;
 }
 
 static ModelView model_view(void* model) {
-    size_t off[9];
+    size_t off[N_PARTS + 1];
     model_offsets(off);
     uint8_t* p = (uint8_t*)model;
     ModelView m;
@@ -88,6 +93,8 @@ static ModelView model_view(void* model) {
     m.splitters = (uint64_t*)(p + off[5]);
     m.dense = (uint32_t*)(p + off[6]);
     m.dense_cum = (uint32_t*)(p + off[7]);
+    m.subtab = (uint16_t*)(p + off[8]);
+    m.cellinfo = (uint64_t*)(p + off[9]);
     return m;
 }
 
@@ -444,10 +451,6 @@ __global__ __launch_bounds__(256) void k_lut_apply(uint32_t* __restrict__ lut, u
 }
 
 // ------------------------------------------------------------------ buckets
-__device__ __forceinline__ uint32_t window_of(uint64_t code, uint64_t lo, uint64_t hi, uint32_t cp) {
-    const uint64_t c = code < lo ? lo : (code > hi ? hi : code);
-    return cp >= 64 ? 0u : (uint32_t)((c << cp) >> 40);
-}
 __device__ __forceinline__ uint32_t bucket_of_lut(uint32_t q, uint32_t B) {
     return (uint32_t)(((uint64_t)q * B) >> 32);
 }
@@ -486,30 +489,91 @@ __global__ __launch_bounds__(256) void k_splitters(const uint32_t* __restrict__ 
     if (heavy) atomicAdd(&hdr->heavy, heavy);
 }
 
-// Bucket id of every code (u16): the cell's first bucket, plus the number of
-// the cell's splitters not above the (clamped) code when it owns several.
-__global__ __launch_bounds__(256) void k_bucket_ids(const uint64_t* __restrict__ codes, uint32_t n,
-                                                    const LearnedHeader* __restrict__ hdr,
-                                                    const uint32_t* __restrict__ lut,
-                                                    const uint64_t* __restrict__ splitters,
-                                                    uint16_t* __restrict__ bid) {
-    const uint64_t lo = hdr->lo, hi = hdr->hi;
-    const uint32_t cp = hdr->cp, B = hdr->buckets;
-    for (uint32_t i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) {
-        const uint64_t code = codes[i];
-        const uint32_t w = window_of(code, lo, hi, cp);
+// Sub-cells of a heavy cell.  Its k - 1 splitters share their top P bits (P =
+// common prefix of the first and the last); a key whose top P bits are below
+// (above) that prefix counts 0 (k - 1) splitters.  Otherwise its next s bits,
+// s = min(16, 64 - P, ceil(log2 k) + 3), index a table of 2^s entries:
+// entry v = the splitters below the first code with those bits equal to v,
+// so the key only searches the splitters of its own sub-cell -- with about
+// eight sub-cells per bucket, mostly none or one.  The cell's slot at
+// subtab[16 b0 ..] holds a 16-byte header {u16 P, u16 s, u32 0, u64 prefix}
+// and the 2^s entries (2^s + 8 <= 16k: slots never overlap, since cells own
+// disjoint bucket ranges).
+__device__ __forceinline__ uint32_t sub_bits_for(uint32_t k, uint32_t P) {
+    const uint32_t lg = 32u - (uint32_t)__clz(k - 1u);  // ceil(log2 k), k >= 2
+    return min(64u - P, min(16u, lg + 3u));
+}
+
+// Per-cell info for the sort (see bucket.h): buckets of every cell and, for
+// heavy cells, the sub-cell key when the splitters' prefix extends at most
+// INLINE_PREFIX_BITS below the cell.
+__global__ __launch_bounds__(256) void k_cellinfo(const uint32_t* __restrict__ lut,
+                                                  const LearnedHeader* __restrict__ hdr,
+                                                  const uint64_t* __restrict__ splitters,
+                                                  uint64_t* __restrict__ info) {
+    const uint32_t B = hdr->buckets, cp = hdr->cp;
+    for (uint32_t w = blockIdx.x * 256 + threadIdx.x; w < LUT_CELLS; w += gridDim.x * 256) {
         const uint32_t b0 = bucket_of_lut(lut[w], B), b1 = bucket_of_lut(lut[w + 1], B);
-        uint32_t b = b0;
+        uint64_t v = (uint64_t)b0 | ((uint64_t)b1 << 16);
         if (b1 >= b0 + 2) {
-            const uint64_t c = code < lo ? lo : (code > hi ? hi : code);
-            uint32_t a = 0, z = b1 - b0 - 1;  // count of splitters[b0 + .] <= c
-            while (a < z) {
-                const uint32_t mid = (a + z) >> 1;
-                if (splitters[b0 + mid] <= c) a = mid + 1; else z = mid;
+            const uint32_t k = b1 - b0;
+            const uint64_t first = splitters[b0], last = splitters[b0 + k - 2];
+            const uint32_t P = first == last ? 64u : (uint32_t)__clzll((long long)(first ^ last));
+            const uint32_t s = sub_bits_for(k, P);
+            const uint32_t below = cp + 24;  // bits of prefix and cell
+            if (P < 64 && below < 64 && P >= below && P - below <= (uint32_t)INLINE_PREFIX_BITS) {
+                const uint32_t e = P - below;
+                const uint64_t extra = e ? (first << below) >> (64 - e) : 0ull;
+                v |= ((uint64_t)P << 32) | ((uint64_t)s << 39) | (extra << 44);
+            } else {
+                v |= 1ull << 63;
             }
-            b = b0 + a;
         }
-        bid[i] = (uint16_t)b;
+        info[w] = v;
+    }
+}
+
+// One thread per slot e of subtab: the cell owning bucket e / SUB_SLOT (the
+// last cell whose first bucket is <= that bucket), then its header or entry.
+__global__ __launch_bounds__(256) void k_subtables(const uint32_t* __restrict__ lut,
+                                                   const LearnedHeader* __restrict__ hdr,
+                                                   const uint64_t* __restrict__ splitters,
+                                                   uint16_t* __restrict__ subtab) {
+    const uint32_t B = hdr->buckets;
+    for (uint32_t e = blockIdx.x * 256 + threadIdx.x; e < SUB_SLOT * B; e += gridDim.x * 256) {
+        const uint32_t bk = e / SUB_SLOT;
+        uint32_t a = 0, z = LUT_CELLS;  // first cell whose first bucket is > bk
+        while (a < z) {
+            const uint32_t mid = (a + z) >> 1;
+            if (bucket_of_lut(lut[mid], B) <= bk) a = mid + 1; else z = mid;
+        }
+        if (a == 0) continue;
+        const uint32_t W = a - 1;
+        const uint32_t b0 = bucket_of_lut(lut[W], B), b1 = bucket_of_lut(lut[W + 1], B);
+        if (b1 < b0 + 2 || bk >= b1) continue;
+        const uint32_t k = b1 - b0;
+        const uint64_t first = splitters[b0], last = splitters[b0 + k - 2];
+        const uint32_t P = first == last ? 64u : (uint32_t)__clzll((long long)(first ^ last));
+        const uint32_t s = sub_bits_for(k, P);
+        const uint64_t prefix = P >= 64 ? first : (P ? first & ~(~0ull >> P) : 0ull);
+        const uint32_t local = e - SUB_SLOT * b0;
+        if (local < 8) {
+            uint32_t v = 0;
+            if (local == 0) v = P;
+            else if (local == 1) v = s;
+            else if (local >= 4) v = (uint32_t)(prefix >> (16 * (local - 4))) & 0xFFFFu;
+            subtab[e] = (uint16_t)v;
+            continue;
+        }
+        const uint32_t v = local - 8;
+        if (v >= (1u << s)) continue;
+        const uint64_t start = prefix | ((uint64_t)v << (64 - P - s));
+        uint32_t x = 0, y = k - 1;  // splitters < start
+        while (x < y) {
+            const uint32_t mid = (x + y) >> 1;
+            if (splitters[b0 + mid] < start) x = mid + 1; else y = mid;
+        }
+        subtab[e] = (uint16_t)x;
     }
 }
 
@@ -523,7 +587,7 @@ __global__ __launch_bounds__(BLOCK) void k_bcount(const uint16_t* __restrict__ b
                                                   int shift, uint32_t* __restrict__ cnt) {
     constexpr uint32_t TILE = BLOCK * ITEMS;
     __shared__ uint32_t s_h[NWAVES * 256];
-    const uint32_t t = blockIdx.x, w = threadIdx.x / WAVE, lane = lane_id();
+    const uint32_t t = xcd_remap(blockIdx.x, gridDim.x), w = threadIdx.x / WAVE, lane = lane_id();
     const uint32_t base = t * TILE;
     if (base >= n) return;
     const uint32_t nvalid = min(TILE, n - base);
@@ -563,77 +627,64 @@ __global__ __launch_bounds__(BLOCK) void k_bscatter(const uint64_t* __restrict__
                                                     const uint32_t* __restrict__ binstart) {
     constexpr uint32_t TILE = BLOCK * ITEMS;
     __shared__ uint64_t s_buf[TILE];
+    __shared__ uint16_t s_bid[TILE];
     __shared__ uint32_t s_whist[NWAVES * 256];
     __shared__ uint32_t s_binstart[256];
     __shared__ uint32_t s_gbase[256];
     __shared__ uint32_t s_scan[NWAVES];
-    const uint32_t t = blockIdx.x, tid = threadIdx.x, w = tid / WAVE, lane = lane_id();
+    const uint32_t t = xcd_remap(blockIdx.x, gridDim.x), tid = threadIdx.x, w = tid / WAVE,
+                   lane = lane_id();
     const uint32_t base = t * TILE;
     if (base >= n) return;
     const uint32_t nvalid = min(TILE, n - base);
-    uint64_t dk[ITEMS];  // ranking key: the id's digit
-    uint32_t bv[ITEMS];
+    // all three arrays are loaded before the ranking so that their loads overlap
+    uint64_t kv[ITEMS];
+    uint32_t vv[ITEMS], bv[ITEMS], dig[ITEMS];
 #pragma unroll
     for (int i = 0; i < ITEMS; ++i) {
         const uint32_t p = w * WAVE * ITEMS + i * WAVE + lane;
-        bv[i] = p < nvalid ? bsrc[base + p] : 0xFFFFu;
-        dk[i] = bv[i];
+        const bool ok = p < nvalid;
+        bv[i] = ok ? bsrc[base + p] : 0xFFFFu;
+        kv[i] = ok ? ksrc[base + p] : 0ull;
+        vv[i] = vsrc ? (ok ? vsrc[base + p] : 0u) : base + p;  // no source: input order
+        dig[i] = (bv[i] >> shift) & 255u;
     }
     uint32_t pos[ITEMS], bc = 0;
-    rank_tile<8, ITEMS>(dk, shift, 255u, nvalid, pos, s_whist, s_binstart, s_scan, &bc);
+    rank_digits<8, ITEMS>(dig, nvalid, pos, s_whist, s_binstart, s_scan, &bc);
     if (tid < 256) {
         const uint32_t g = t / GROUP_TILES;
         s_gbase[tid] = binstart[tid] + gtot[(size_t)g * 256 + tid] + cnt[(size_t)t * 256 + tid] -
                        s_binstart[tid];
     }
-    // id, then destination of every tile position
-    uint16_t* s_b = (uint16_t*)s_buf;
 #pragma unroll
-    for (int i = 0; i < ITEMS; ++i) s_b[pos[i]] = (uint16_t)bv[i];
+    for (int i = 0; i < ITEMS; ++i) {
+        s_buf[pos[i]] = kv[i];
+        s_bid[pos[i]] = (uint16_t)bv[i];
+    }
     __syncthreads();
+    // codes and ids leave in digit order: neighbouring lanes write neighbouring
+    // addresses inside each digit's run
     uint32_t dst[ITEMS];
 #pragma unroll
     for (int i = 0; i < ITEMS; ++i) {
         const uint32_t p = i * BLOCK + tid;
         dst[i] = 0;
         if (p < nvalid) {
-            const uint32_t b = s_b[p];
-            dst[i] = s_gbase[(b >> shift) & 255u] + p;
-            if (bdst) bdst[dst[i]] = (uint16_t)b;
+            const uint32_t bb = s_bid[p];
+            dst[i] = s_gbase[(bb >> shift) & 255u] + p;
+            kdst[dst[i]] = s_buf[p];
+            if (bdst) bdst[dst[i]] = (uint16_t)bb;
         }
     }
     __syncthreads();
-    // codes
-    {
-        uint64_t kv[ITEMS];
+    uint32_t* s_v = (uint32_t*)s_buf;
 #pragma unroll
-        for (int i = 0; i < ITEMS; ++i) {
-            const uint32_t p = w * WAVE * ITEMS + i * WAVE + lane;
-            kv[i] = p < nvalid ? ksrc[base + p] : 0ull;
-        }
-#pragma unroll
-        for (int i = 0; i < ITEMS; ++i) s_buf[pos[i]] = kv[i];
-    }
+    for (int i = 0; i < ITEMS; ++i) s_v[pos[i]] = vv[i];
     __syncthreads();
 #pragma unroll
-    for (int i = 0; i < ITEMS; ++i)
-        if (i * BLOCK + tid < nvalid) kdst[dst[i]] = s_buf[i * BLOCK + tid];
-    __syncthreads();
-    // indices
-    {
-        uint32_t* s_v = (uint32_t*)s_buf;
-        uint32_t vv[ITEMS];
-#pragma unroll
-        for (int i = 0; i < ITEMS; ++i) {
-            const uint32_t p = w * WAVE * ITEMS + i * WAVE + lane;
-            vv[i] = p < nvalid ? vsrc[base + p] : 0u;
-        }
-#pragma unroll
-        for (int i = 0; i < ITEMS; ++i) s_v[pos[i]] = vv[i];
-        __syncthreads();
-#pragma unroll
-        for (int i = 0; i < ITEMS; ++i)
-            if (i * BLOCK + tid < nvalid) vdst[dst[i]] = s_v[i * BLOCK + tid];
+    for (int i = 0; i < ITEMS; ++i) {
+        const uint32_t p = i * BLOCK + tid;
+        if (p < nvalid) vdst[dst[i]] = s_v[p];
     }
 }
 
@@ -861,13 +912,13 @@ __global__ void k_overflow_stats(const uint64_t* __restrict__ seg, uint32_t B, u
 
 // ------------------------------------------------------------------ host side
 size_t learned_model_bytes() {
-    size_t off[9];
+    size_t off[N_PARTS + 1];
     model_offsets(off);
-    return off[8];
+    return off[N_PARTS];
 }
 size_t learned_model_offset(int part) {
-    if (part < 0 || part > 7) return ~(size_t)0;
-    size_t off[9];
+    if (part < 0 || part >= N_PARTS) return ~(size_t)0;
+    size_t off[N_PARTS + 1];
     model_offsets(off);
     return off[part];
 }
@@ -1004,17 +1055,17 @@ hipError_t learned_splitters(void* model, const uint64_t* sorted_sample, uint32_
     ModelView m = model_view(model);
     hipLaunchKernelGGL(k_splitters, dim3(8192), dim3(256), 0, s, (const uint32_t*)m.lut, sorted_sample,
                        S, m.hdr, m.splitters);
+    hipLaunchKernelGGL(k_subtables, dim3(grid_for((uint64_t)SUB_SLOT * LEARNED_BUCKETS)), dim3(256), 0, s,
+                       (const uint32_t*)m.lut, (const LearnedHeader*)m.hdr,
+                       (const uint64_t*)m.splitters, m.subtab);
+    hipLaunchKernelGGL(k_cellinfo, dim3(8192), dim3(256), 0, s, (const uint32_t*)m.lut,
+                       (const LearnedHeader*)m.hdr, (const uint64_t*)m.splitters, m.cellinfo);
     return hipGetLastError();
 }
 
-hipError_t learned_bucket_ids(const void* model, const uint64_t* codes, uint32_t n, uint16_t* bid,
-                              hipStream_t s) {
+BucketArgs learned_bucket_args(const void* model, uint16_t* bid) {
     ModelView m = model_view((void*)model);
-    ProfScope ps(P_BUCKET_MAP, s);
-    hipLaunchKernelGGL(k_bucket_ids, dim3(grid_for(n)), dim3(256), 0, s, codes, n,
-                       (const LearnedHeader*)m.hdr, (const uint32_t*)m.lut,
-                       (const uint64_t*)m.splitters, bid);
-    return hipGetLastError();
+    return BucketArgs{m.hdr, m.cellinfo, m.splitters, m.subtab, bid};
 }
 
 hipError_t learned_bucket_pass(int pass, const uint64_t* ks, const uint32_t* vs, const uint16_t* bs,

@@ -269,8 +269,9 @@ __global__ __launch_bounds__(BLOCK) void k_count(const uint64_t* __restrict__ ke
     constexpr int R = 1 << BITS;
     constexpr uint32_t TILE = BLOCK * ITEMS;
     __shared__ uint32_t s_h[NWAVES * R];
-    const uint32_t t = blockIdx.x;
-    if (t >= counters[C_BIG_TILES]) return;
+    const uint32_t nbt = counters[C_BIG_TILES];  // the grid is an upper bound
+    if (blockIdx.x >= nbt) return;
+    const uint32_t t = xcd_remap(blockIdx.x, nbt);
     const BigDesc B = bigs[big_of_tile(bigs, counters[C_NUM_BIG], t)];
     bool flip;
     if (!pass_runs(B, pass, flip)) return;
@@ -385,8 +386,9 @@ __global__ __launch_bounds__(BLOCK) void k_scatter(
     __shared__ uint32_t s_binstart[R];
     __shared__ uint32_t s_gbase[R];
     __shared__ uint32_t s_scan[NWAVES];
-    const uint32_t t = blockIdx.x, tid = threadIdx.x;
-    if (t >= counters[C_BIG_TILES]) return;
+    const uint32_t nbt = counters[C_BIG_TILES];  // the grid is an upper bound
+    if (blockIdx.x >= nbt) return;
+    const uint32_t t = xcd_remap(blockIdx.x, nbt), tid = threadIdx.x;
     const uint32_t b = big_of_tile(bigs, counters[C_NUM_BIG], t);
     const BigDesc B = bigs[b];
     bool flip;

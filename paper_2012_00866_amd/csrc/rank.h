@@ -7,18 +7,17 @@
 namespace husky {
 
 // ------------------------------------------------------------------ tile ranking
-// Ranks the ITEMS keys of every thread of one tile by their digit
-// (key >> shift) & dmask, dmask < 2^BITS.
-// Keys sit in "wave-striped" order: item k of lane l of wave w is tile
-// position w*64*ITEMS + k*64 + l; positions >= nvalid are padding and rank
-// last.  On return pos[k] is the key's position in the digit-sorted tile
-// (stable in tile position) and, for tid < R, *bin_count holds the number of
-// valid keys with digit tid and s_binstart[tid] its first position.
+// Ranks the ITEMS digits (< 2^BITS) of every thread of one tile.  Digits sit
+// in "wave-striped" order: item k of lane l of wave w is tile position
+// w*64*ITEMS + k*64 + l; positions >= nvalid are padding and rank last.  On
+// return pos[k] is the item's position in the digit-sorted tile (stable in
+// tile position) and, for tid < R, *bin_count holds the number of valid items
+// with digit tid and s_binstart[tid] its first position.
 template <int BITS, int ITEMS>
-__device__ __forceinline__ void rank_tile(const uint64_t (&keys)[ITEMS], int shift,
-                                          uint32_t dmask, uint32_t nvalid, uint32_t (&pos)[ITEMS],
-                                          uint32_t* s_whist, uint32_t* s_binstart,
-                                          uint32_t* s_scan, uint32_t* bin_count) {
+__device__ __forceinline__ void rank_digits(uint32_t (&dig)[ITEMS], uint32_t nvalid,
+                                            uint32_t (&pos)[ITEMS], uint32_t* s_whist,
+                                            uint32_t* s_binstart, uint32_t* s_scan,
+                                            uint32_t* bin_count) {
     constexpr int R = 1 << BITS;
     const uint32_t tid = threadIdx.x, w = tid / WAVE, lane = lane_id();
     for (uint32_t i = tid; i < (uint32_t)(NWAVES * R); i += BLOCK) s_whist[i] = 0;
@@ -29,11 +28,11 @@ __device__ __forceinline__ void rank_tile(const uint64_t (&keys)[ITEMS], int shi
     // memory clobber keeps the compiler from reusing a count across
     // iterations.
     uint32_t* wh = s_whist + w * R;
-    uint32_t rank[ITEMS], dig[ITEMS];
+    uint32_t rank[ITEMS];
 #pragma unroll
     for (int k = 0; k < ITEMS; ++k) {
         const uint32_t p = w * WAVE * ITEMS + k * WAVE + lane;
-        const uint32_t d = p < nvalid ? ((uint32_t)(keys[k] >> shift) & dmask) : (uint32_t)(R - 1);
+        const uint32_t d = p < nvalid ? dig[k] : (uint32_t)(R - 1);
         dig[k] = d;
         // lanes holding the same digit: for every digit bit keep the lanes
         // whose bit agrees (ballot, inverted where this lane's bit is 0)
@@ -74,6 +73,18 @@ __device__ __forceinline__ void rank_tile(const uint64_t (&keys)[ITEMS], int shi
     __syncthreads();
 #pragma unroll
     for (int k = 0; k < ITEMS; ++k) pos[k] = s_binstart[dig[k]] + s_whist[w * R + dig[k]] + rank[k];
+}
+
+// The same ranking by the digit (key >> shift) & dmask, dmask < 2^BITS.
+template <int BITS, int ITEMS>
+__device__ __forceinline__ void rank_tile(const uint64_t (&keys)[ITEMS], int shift,
+                                          uint32_t dmask, uint32_t nvalid, uint32_t (&pos)[ITEMS],
+                                          uint32_t* s_whist, uint32_t* s_binstart,
+                                          uint32_t* s_scan, uint32_t* bin_count) {
+    uint32_t dig[ITEMS];
+#pragma unroll
+    for (int k = 0; k < ITEMS; ++k) dig[k] = (uint32_t)(keys[k] >> shift) & dmask;
+    rank_digits<BITS, ITEMS>(dig, nvalid, pos, s_whist, s_binstart, s_scan, bin_count);
 }
 
 template <int ITEMS>

@@ -31,7 +31,7 @@ from . import (Tuning, check_perm, make_tuning, sort, sort_batched, alloc_worksp
 RADIX = [(8, 16), (8, 12), (8, 8), (7, 16), (7, 12), (6, 16)]
 T_SMALL = [8, 16, 32, 64]
 T_MEDIUM = [256, 1024, 2048, 4096]
-DEFAULT = dict(radix_bits=8, tile_items=16, t_small=64, t_medium=4096)
+DEFAULT = dict(radix_bits=8, tile_items=16, t_small=64, t_medium=1024)
 
 
 def cache_path() -> str:
