@@ -200,6 +200,9 @@ husky_status husky_check_perm(husky_coder coder, const void* elems, const uint64
  * Returns HUSKY_OK or HUSKY_ERR_HIP. */
 void husky_profile_begin(void);
 int husky_profile_end(double* ms, uint32_t* launches, int n_classes);
+/* Bracket only the classes whose bit is set in class_mask (default: all), so
+ * that timing one kernel class barely perturbs the others. */
+void husky_profile_select(uint32_t class_mask);
 
 /* ---------------------------------------------------------------------
  * Learned-CDF form (an extension of the method, not part of the paper).

@@ -59,7 +59,7 @@ _lib = None
 
 EXPORTS = ("husky_workspace_bytes", "husky_encode", "husky_sort_pairs", "husky_fixup",
            "husky_sort", "husky_sort_batched", "husky_check_perm", "husky_profile_begin",
-           "husky_profile_end", "husky_learned_model_bytes", "husky_learned_offset",
+           "husky_profile_end", "husky_profile_select", "husky_learned_model_bytes", "husky_learned_offset",
            "husky_learned_workspace_bytes", "husky_learned_fit", "husky_sort_learned",
            "husky_learned_buckets",
            "husky_mlp_grad_workspace_bytes", "husky_mlp_grad", "husky_status_string")
@@ -125,6 +125,8 @@ def load(path: str = LIB_PATH):
     lib.husky_profile_begin.argtypes = []
     lib.husky_profile_end.restype = i32
     lib.husky_profile_end.argtypes = [vp, vp, i32]
+    lib.husky_profile_select.restype = None
+    lib.husky_profile_select.argtypes = [ctypes.c_uint32]
     lib.husky_learned_model_bytes.restype = sz
     lib.husky_learned_model_bytes.argtypes = []
     lib.husky_learned_offset.restype = sz
@@ -409,8 +411,11 @@ def mlp_grad(params, x, y, monotone=True, stream=None):
     return g[:LEARNED_NPARAM], g[LEARNED_NPARAM]
 
 
-def profile_begin():
-    """Start per-launch HIP-event timing of every library kernel."""
+def profile_begin(classes=None):
+    """Start per-launch HIP-event timing of the library's kernels (all classes,
+    or only the named ones)."""
+    mask = 0xFFFFFFFF if classes is None else sum(1 << PROFILE_CLASSES.index(c) for c in classes)
+    load().husky_profile_select(mask)
     load().husky_profile_begin()
 
 

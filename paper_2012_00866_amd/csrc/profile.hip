@@ -20,6 +20,7 @@ struct Pair {
 
 std::mutex g_mu;
 bool g_on = false;
+uint32_t g_mask = ~0u;  // kernel classes to bracket
 std::vector<Pair> g_used;
 std::vector<Pair> g_free;
 
@@ -28,7 +29,7 @@ std::vector<Pair> g_free;
 bool prof_on() { return g_on; }
 
 ProfScope::ProfScope(int cls, hipStream_t s) : cls_(cls), s_(s), idx_(-1) {
-    if (!g_on) return;
+    if (!g_on || cls < 0 || cls >= 32 || !((g_mask >> cls) & 1u)) return;
     std::lock_guard<std::mutex> lk(g_mu);
     Pair p;
     if (!g_free.empty()) {
@@ -57,6 +58,11 @@ ProfScope::~ProfScope() {
 using namespace husky;
 
 extern "C" {
+
+void husky_profile_select(uint32_t class_mask) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_mask = class_mask;
+}
 
 void husky_profile_begin(void) {
     std::lock_guard<std::mutex> lk(g_mu);
