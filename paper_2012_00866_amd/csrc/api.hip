@@ -32,8 +32,8 @@ constexpr uint32_t LEARN_MAX_BLOCKS = 256;
 // husky_learned_fit).
 struct Layout {
     size_t status, counters, codes_a, codes_b, idx_b, key0, segs, bigs, korand, binstart, cnt, gtot,
-        tile_counts, run_start, run_end, small, medium, large_a, large_b, bid, bseg, lpartial, lgrad,
-        ltmax, total;
+        tile_counts, run_start, run_end, small, medium, large_a, large_b, bid, bseg, k0a, k0b,
+        lpartial, lgrad, ltmax, total;
     uint32_t seg_cap, big_cap, tile_cap, big_tile_cap, group_cap, run_cap, small_cap, medium_cap,
         large_cap;
 };
@@ -82,6 +82,8 @@ Layout make_layout(uint64_t n, uint64_t n_segs, bool learned = false) {
     if (learned) {
         L.bid = take(n * 4);
         L.bseg = take(((size_t)LEARNED_BUCKETS + 1) * 8);
+        L.k0a = take(n * 8);  // first refinement keys in bucket order (ping-pong)
+        L.k0b = take(n * 8);
         L.lpartial = take(learned_partial_bytes(LEARN_MAX_BLOCKS));
         L.lgrad = take(((size_t)learned_nparam() + 1) * 4 + 256);
         L.ltmax = take((size_t)learned_lut_tiles() * 4);
@@ -511,18 +513,21 @@ husky_status husky_sort_learned(husky_coder coder, const void* elems, const uint
     uint64_t* bseg = c.at<uint64_t>(L.bseg);
     const uint32_t nn = (uint32_t)n;
     // codes, first refinement keys and bucket ids in one pass over the strings,
-    // then two stable 8-bit passes over the ids (low byte, high byte); the
-    // first pass takes the indices from the input order
+    // then two stable 8-bit passes over the ids (low byte, high byte) that
+    // carry (code, index, id, first refinement key); the first pass takes the
+    // indices from the input order
+    uint64_t* key0 = c.at<uint64_t>(L.key0);
+    uint64_t* k0a = c.at<uint64_t>(L.k0a);
+    uint64_t* k0b = c.at<uint64_t>(L.k0b);
     const BucketArgs ba = learned_bucket_args(model, bid_a);
-    HUSKY_TRY(launch_encode(coder, elems, offsets, nn, codes, nullptr, c.at<uint64_t>(L.key0),
+    HUSKY_TRY(launch_encode(coder, elems, offsets, nn, codes, nullptr, key0,
                             &c.status->domain_violations, s, nullptr, 0, &ba));
-    HUSKY_TRY(learned_bucket_pass(0, codes, nullptr, bid_a, codes_b, idx_b, bid_b, nn, c.rad.cnt,
-                                  c.rad.gtot, c.rad.binstart, s));
-    HUSKY_TRY(learned_bucket_pass(1, codes_b, idx_b, bid_b, codes, perm, bid_a, nn, c.rad.cnt,
-                                  c.rad.gtot, c.rad.binstart, s));
+    HUSKY_TRY(learned_bucket_pass(0, codes, nullptr, bid_a, key0, codes_b, idx_b, bid_b, k0b, nn,
+                                  c.rad.cnt, c.rad.gtot, c.rad.binstart, s));
+    HUSKY_TRY(learned_bucket_pass(1, codes_b, idx_b, bid_b, k0b, codes, perm, bid_a, k0a, nn,
+                                  c.rad.cnt, c.rad.gtot, c.rad.binstart, s));
     HUSKY_TRY(learned_bucket_bounds(bid_a, nn, bseg, &c.status->overflow_buckets, tn.rc.tile(), s));
-    // every bucket sorted by code: one tile in LDS, larger ones by the
-    // multi-tile passes
+    // buckets of more than one tile: the multi-tile radix passes on the code
     const uint32_t B = LEARNED_BUCKETS;
     HUSKY_TRY(radix_segments_from_offsets(bseg, B, c.rad, tn.rc, s));
     const int end_bit = coder == HUSKY_CODER_ASCII7 ? 63 : 64;
@@ -530,11 +535,12 @@ husky_status husky_sort_learned(husky_coder coder, const void* elems, const uint
     HUSKY_TRY(radix_reduce_tiles(codes, tb, c.rad, tn.rc, s));
     HUSKY_TRY(radix_exec_masks(0, end_bit, B, tb, c.rad, tn.rc, s));
     HUSKY_TRY(radix_sort_segments(codes, perm, codes_b, idx_b, 0, end_bit, B, tb, ~0u, c.rad, tn.rc,
-                                  P_SCATTER, s));
-    // the array is now sorted by code as a whole (buckets are in code order),
-    // so the fix-up sees it as one instance, as in husky_sort
-    HUSKY_TRY(radix_segments_single(nn, c.rad, tn.rc, s));
-    return run_fixup(c, tn, coder, elems, offsets, n, 1, codes, codes, codes_b, perm, s);
+                                  P_SCATTER, s, false));
+    // every other bucket in LDS: by code, then by the first refinement key
+    // inside runs of equal codes; its codes become tie keys
+    HUSKY_TRY(learned_bucket_refine(coder, codes, perm, k0a, c.rad, B, tn.rc.tile(), s));
+    // equal codes share a bucket, so runs never cross bucket boundaries
+    return run_fixup(c, tn, coder, elems, offsets, n, B, codes, codes, codes_b, perm, s);
 }
 
 husky_status husky_learned_buckets(husky_coder coder, const void* elems, const uint64_t* offsets,

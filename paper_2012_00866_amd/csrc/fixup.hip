@@ -58,11 +58,6 @@ __device__ __forceinline__ uint64_t chunk_key(const uint8_t* __restrict__ bytes,
     }
 }
 
-template <int CODER>
-__device__ __forceinline__ bool key_continues(uint64_t key) {
-    return (key & 0xFull) == (CODER == 0 ? (uint64_t)ascii_chunk + 1 : (uint64_t)utf16_chunk + 1);
-}
-
 // ------------------------------------------------------------------ small tier
 template <int CODER>
 __global__ __launch_bounds__(BLOCK) void k_fix_small(const RunItem* __restrict__ items,

@@ -81,11 +81,12 @@ hipError_t radix_exec_masks(int begin_bit, int end_bit, uint32_t max_segs, uint3
 // buffers of the same size.  The result ends in keys / vals.  max_tiles /
 // max_segs bound the grid sizes; passes outside pass_union (a host mask,
 // ~0u when unknown) are not launched.
+// tile_segments false: single-tile segments are left to the caller.
 hipError_t radix_sort_segments(uint64_t* keys, uint32_t* vals, uint64_t* keys_alt,
                                uint32_t* vals_alt, int begin_bit, int end_bit,
                                uint32_t max_segs, uint32_t max_tiles, uint32_t pass_union,
                                const RadixScratch& sc, const RadixConfig& cfg, int pclass,
-                               hipStream_t s);
+                               hipStream_t s, bool tile_segments = true);
 
 // ---- runs.hip
 struct RunScratch {
@@ -164,13 +165,24 @@ hipError_t learned_build_lut(void* model, uint32_t mode, uint32_t* tmax, hipStre
 hipError_t learned_splitters(void* model, const uint64_t* sorted_sample, uint32_t S, hipStream_t s);
 BucketArgs learned_bucket_args(const void* model, uint16_t* bid);
 hipError_t learned_bucket_pass(int pass, const uint64_t* ks, const uint32_t* vs, const uint16_t* bs,
-                               uint64_t* kd, uint32_t* vd, uint16_t* bd, uint32_t n, uint32_t* cnt,
-                               uint32_t* gtot, uint32_t* binstart, hipStream_t s);
+                               const uint64_t* k0s, uint64_t* kd, uint32_t* vd, uint16_t* bd,
+                               uint64_t* k0d, uint32_t n, uint32_t* cnt, uint32_t* gtot,
+                               uint32_t* binstart, hipStream_t s);
+hipError_t learned_bucket_refine(int coder, uint64_t* codes, uint32_t* perm, const uint64_t* k0,
+                                 const RadixScratch& sc, uint32_t max_segs, uint32_t cap,
+                                 hipStream_t s);
 hipError_t learned_bucket_bounds(const uint16_t* bid, uint32_t n, uint64_t* seg, uint32_t* overflow,
                                  uint32_t tile, hipStream_t s);
 
 // Chunk geometry of the refinement keys.
 constexpr int ascii_m = 9, ascii_chunk = 7;
 constexpr int utf16_m = 4, utf16_chunk = 3;
+
+// A refinement key whose length field says the string goes on past its chunk:
+// two such equal keys are still tied.
+template <int CODER>
+__device__ __forceinline__ bool key_continues(uint64_t key) {
+    return (key & 0xFull) == (CODER == 0 ? (uint64_t)ascii_chunk + 1 : (uint64_t)utf16_chunk + 1);
+}
 
 }  // namespace husky

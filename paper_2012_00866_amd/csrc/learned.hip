@@ -615,13 +615,15 @@ __global__ __launch_bounds__(BLOCK) void k_bcount(const uint16_t* __restrict__ b
     }
 }
 
-template <int ITEMS>
+template <int ITEMS, bool CARRY>
 __global__ __launch_bounds__(BLOCK) void k_bscatter(const uint64_t* __restrict__ ksrc,
                                                     const uint32_t* __restrict__ vsrc,
                                                     const uint16_t* __restrict__ bsrc,
+                                                    const uint64_t* __restrict__ k0src,
                                                     uint64_t* __restrict__ kdst,
                                                     uint32_t* __restrict__ vdst,
-                                                    uint16_t* __restrict__ bdst, uint32_t n,
+                                                    uint16_t* __restrict__ bdst,
+                                                    uint64_t* __restrict__ k0dst, uint32_t n,
                                                     int shift, const uint32_t* __restrict__ cnt,
                                                     const uint32_t* __restrict__ gtot,
                                                     const uint32_t* __restrict__ binstart) {
@@ -638,7 +640,7 @@ __global__ __launch_bounds__(BLOCK) void k_bscatter(const uint64_t* __restrict__
     if (base >= n) return;
     const uint32_t nvalid = min(TILE, n - base);
     // all three arrays are loaded before the ranking so that their loads overlap
-    uint64_t kv[ITEMS];
+    uint64_t kv[ITEMS], k0v[ITEMS];
     uint32_t vv[ITEMS], bv[ITEMS], dig[ITEMS];
 #pragma unroll
     for (int i = 0; i < ITEMS; ++i) {
@@ -646,6 +648,7 @@ __global__ __launch_bounds__(BLOCK) void k_bscatter(const uint64_t* __restrict__
         const bool ok = p < nvalid;
         bv[i] = ok ? bsrc[base + p] : 0xFFFFu;
         kv[i] = ok ? ksrc[base + p] : 0ull;
+        if (CARRY) k0v[i] = ok ? k0src[base + p] : 0ull;
         vv[i] = vsrc ? (ok ? vsrc[base + p] : 0u) : base + p;  // no source: input order
         dig[i] = (bv[i] >> shift) & 255u;
     }
@@ -677,6 +680,17 @@ __global__ __launch_bounds__(BLOCK) void k_bscatter(const uint64_t* __restrict__
         }
     }
     __syncthreads();
+    if (CARRY) {  // the first refinement key travels like the code
+#pragma unroll
+        for (int i = 0; i < ITEMS; ++i) s_buf[pos[i]] = k0v[i];
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < ITEMS; ++i) {
+            const uint32_t p = i * BLOCK + tid;
+            if (p < nvalid) k0dst[dst[i]] = s_buf[p];
+        }
+        __syncthreads();
+    }
     uint32_t* s_v = (uint32_t*)s_buf;
 #pragma unroll
     for (int i = 0; i < ITEMS; ++i) s_v[pos[i]] = vv[i];
@@ -910,6 +924,236 @@ __global__ void k_overflow_stats(const uint64_t* __restrict__ seg, uint32_t B, u
     }
 }
 
+// ------------------------------------------------------------------ per-bucket sort with the first refinement round
+// One workgroup per bucket of 2..cap keys, in LDS:
+//  1. sort (code, slot) by the code's varying digits (slot = position in the
+//     bucket, which is input order);
+//  2. run start of every position (the first position with the same code);
+//  3. if some code repeats: sort (run start, first refinement key, slot) by
+//     the key's varying digits, then by the run start's -- so every run of
+//     equal codes is ordered by its first refinement key, ties by slot;
+//  4. write the permutation (indices gathered by slot) and, in place of the
+//     codes, a tie key per position: the first position of its group, where
+//     a group is a run of equal (code, refinement key) whose key continues.
+// Step 3's run detection then finds only those groups (and the runs of the
+// larger buckets, whose codes are left as they are); every later refinement
+// round proceeds as for any run.
+// Running maximum over the tile in position order, with positions held in the
+// wave-striped layout of rank_digits: every position's value replaced by the
+// maximum of the values at or before it.  s_tmp: BLOCK * ITEMS words.
+template <int ITEMS>
+__device__ __forceinline__ void tile_running_max(uint32_t (&v)[ITEMS], uint32_t* s_tmp,
+                                                 uint32_t* s_scan) {
+    const uint32_t tid = threadIdx.x, w = tid / WAVE, lane = lane_id();
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i) s_tmp[w * WAVE * ITEMS + i * WAVE + lane] = v[i];
+    __syncthreads();
+    // thread t owns positions [ITEMS t, ITEMS t + ITEMS)
+    uint32_t m = 0, loc[ITEMS];
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i) {
+        m = max(m, s_tmp[tid * ITEMS + i]);
+        loc[i] = m;
+    }
+    uint32_t inc = m;
+#pragma unroll
+    for (int d = 1; d < WAVE; d <<= 1) {
+        const uint32_t t = __shfl_up(inc, d, WAVE);
+        if (lane >= (uint32_t)d) inc = max(inc, t);
+    }
+    if (lane == WAVE - 1) s_scan[w] = inc;
+    uint32_t prev = __shfl_up(inc, 1, WAVE);
+    if (lane == 0) prev = 0;
+    __syncthreads();
+    for (uint32_t ww = 0; ww < w; ++ww) prev = max(prev, s_scan[ww]);
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i) s_tmp[tid * ITEMS + i] = max(prev, loc[i]);
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i) v[i] = s_tmp[w * WAVE * ITEMS + i * WAVE + lane];
+    __syncthreads();
+}
+
+// One size class of buckets: lmin < len <= lmax (and 2 <= len <= BLOCK * ITEMS).
+// Per item: its key and one word sr = slot | run start << 16 (both < 4096).
+template <int CODER, int ITEMS>
+__global__ __launch_bounds__(BLOCK) void k_bucket_refine(uint64_t* __restrict__ codes,
+                                                         uint32_t* __restrict__ perm,
+                                                         const uint64_t* __restrict__ k0,
+                                                         const SegDesc* __restrict__ segs,
+                                                         const uint32_t* __restrict__ counters,
+                                                         uint32_t lmin, uint32_t lmax, int code_bits) {
+    constexpr uint32_t TILE = BLOCK * ITEMS;
+    __shared__ uint64_t s_k[TILE];
+    __shared__ uint32_t s_sr[TILE];
+    __shared__ uint32_t s_whist[NWAVES * 256];
+    __shared__ uint32_t s_binstart[256];
+    __shared__ uint32_t s_scan[NWAVES];
+    __shared__ uint64_t s_or[NWAVES], s_and[NWAVES];
+    uint32_t* s_k32 = reinterpret_cast<uint32_t*>(s_k);  // scratch while keys sit in registers
+    const uint32_t sidx = blockIdx.x;
+    if (sidx >= counters[C_NUM_SEGS]) return;
+    const SegDesc d = segs[sidx];
+    if (d.len < 2 || d.len <= lmin || d.len > lmax || d.len > TILE) return;
+    const uint32_t nvalid = d.len, start = d.start;
+    const uint32_t w = threadIdx.x / WAVE, lane = lane_id();
+    auto posof = [&](int i) { return w * WAVE * ITEMS + i * WAVE + lane; };
+    // bits of 64-bit keys that vary over the valid items
+    auto vary_of = [&](const uint64_t(&k)[ITEMS]) {
+        uint64_t o = 0, a = ~0ull;
+#pragma unroll
+        for (int i = 0; i < ITEMS; ++i)
+            if (posof(i) < nvalid) {
+                o |= k[i];
+                a &= k[i];
+            }
+#pragma unroll
+        for (int dd = 32; dd >= 1; dd >>= 1) {
+            o |= (uint64_t)__shfl_xor((unsigned long long)o, dd, WAVE);
+            a &= (uint64_t)__shfl_xor((unsigned long long)a, dd, WAVE);
+        }
+        if (lane == 0) {
+            s_or[w] = o;
+            s_and[w] = a;
+        }
+        __syncthreads();
+        uint64_t oo = 0, aa = ~0ull;
+#pragma unroll
+        for (int ww = 0; ww < NWAVES; ++ww) {
+            oo |= s_or[ww];
+            aa &= s_and[ww];
+        }
+        __syncthreads();
+        return oo ^ aa;
+    };
+    uint64_t k[ITEMS];
+    uint32_t sr[ITEMS], dig[ITEMS], pos[ITEMS];
+    // one digit pass of (k, sr) through LDS
+    auto pass = [&]() {
+        uint32_t bc;
+        rank_digits<8, ITEMS>(dig, nvalid, pos, s_whist, s_binstart, s_scan, &bc);
+#pragma unroll
+        for (int i = 0; i < ITEMS; ++i) {
+            s_k[pos[i]] = k[i];
+            s_sr[pos[i]] = sr[i];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < ITEMS; ++i) {
+            k[i] = s_k[posof(i)];
+            sr[i] = s_sr[posof(i)];
+        }
+        __syncthreads();
+    };
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i) {
+        const uint32_t p = posof(i);
+        k[i] = p < nvalid ? codes[start + p] : ~0ull;
+        sr[i] = p;
+    }
+    // 1. by code
+    uint64_t vary = vary_of(k);
+    for (int shift = 0; shift < code_bits; shift += 8) {
+        const uint32_t dmask = (1u << min(8, code_bits - shift)) - 1u;
+        if (!((uint32_t)(vary >> shift) & dmask)) continue;
+#pragma unroll
+        for (int i = 0; i < ITEMS; ++i) dig[i] = (uint32_t)(k[i] >> shift) & dmask;
+        pass();
+    }
+    // 2. run starts (items are in code order now)
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i) s_k[posof(i)] = k[i];
+    __syncthreads();
+    bool repeats = false;
+    uint32_t t[ITEMS];
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i) {
+        const uint32_t p = posof(i);
+        const bool head = p == 0 || p >= nvalid || s_k[p - 1] != k[i];
+        repeats = repeats || !head;
+        t[i] = head ? p : 0u;
+    }
+    repeats = __syncthreads_or(repeats);
+    if (repeats) {
+        tile_running_max<ITEMS>(t, s_k32, s_scan);
+#pragma unroll
+        for (int i = 0; i < ITEMS; ++i) sr[i] |= t[i] << 16;
+        // 3. by (run start, refinement key), stable in slot
+#pragma unroll
+        for (int i = 0; i < ITEMS; ++i) k[i] = posof(i) < nvalid ? k0[start + (sr[i] & 0xFFFFu)] : ~0ull;
+        vary = vary_of(k);
+        for (int shift = 0; shift < 64; shift += 8) {
+            if (!((uint32_t)(vary >> shift) & 0xFFu)) continue;
+#pragma unroll
+            for (int i = 0; i < ITEMS; ++i) dig[i] = (uint32_t)(k[i] >> shift) & 0xFFu;
+            pass();
+        }
+        for (int shift = 16; shift < 28; shift += 8) {  // run starts are < 4096
+#pragma unroll
+            for (int i = 0; i < ITEMS; ++i) dig[i] = (sr[i] >> shift) & 0xFFu;
+            pass();
+        }
+        // 4. groups: same run, same key, and the key continues
+#pragma unroll
+        for (int i = 0; i < ITEMS; ++i) {
+            s_k[posof(i)] = k[i];
+            s_sr[posof(i)] = sr[i];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < ITEMS; ++i) {
+            const uint32_t p = posof(i);
+            const bool same = p > 0 && p < nvalid && (s_sr[p - 1] >> 16) == (sr[i] >> 16) &&
+                              s_k[p - 1] == k[i] && key_continues<CODER>(k[i]);
+            t[i] = same ? 0u : p;
+        }
+        __syncthreads();
+        tile_running_max<ITEMS>(t, s_k32, s_scan);
+    } else {
+#pragma unroll
+        for (int i = 0; i < ITEMS; ++i) t[i] = posof(i);
+    }
+    // indices gathered by slot into LDS before any is overwritten
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i)
+        if (posof(i) < nvalid) s_k32[posof(i)] = perm[start + (sr[i] & 0xFFFFu)];
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i) {
+        const uint32_t p = posof(i);
+        if (p < nvalid) {
+            perm[start + p] = s_k32[p];
+            codes[start + p] = (uint64_t)start + t[i];
+        }
+    }
+}
+
+hipError_t learned_bucket_refine(int coder, uint64_t* codes, uint32_t* perm, const uint64_t* k0,
+                                 const RadixScratch& sc, uint32_t max_segs, uint32_t cap,
+                                 hipStream_t s) {
+    if (!max_segs) return hipSuccess;
+    ProfScope ps(P_TILE_SORT, s);
+    // two size classes: the smaller one needs fewer registers and LDS, so more
+    // workgroups share a CU
+    const SegDesc* sg = sc.segs;
+    const uint32_t* ct = sc.counters;
+    const uint32_t c1 = std::min(cap, BLOCK * 12u), c2 = std::min(cap, BLOCK * 16u);
+    if (coder == 0) {
+        hipLaunchKernelGGL((k_bucket_refine<0, 12>), dim3(max_segs), dim3(BLOCK), 0, s, codes, perm, k0,
+                           sg, ct, 0u, c1, 63);
+        if (c2 > c1)
+            hipLaunchKernelGGL((k_bucket_refine<0, 16>), dim3(max_segs), dim3(BLOCK), 0, s, codes, perm,
+                               k0, sg, ct, c1, c2, 63);
+    } else {
+        hipLaunchKernelGGL((k_bucket_refine<1, 12>), dim3(max_segs), dim3(BLOCK), 0, s, codes, perm, k0,
+                           sg, ct, 0u, c1, 64);
+        if (c2 > c1)
+            hipLaunchKernelGGL((k_bucket_refine<1, 16>), dim3(max_segs), dim3(BLOCK), 0, s, codes, perm,
+                               k0, sg, ct, c1, c2, 64);
+    }
+    return hipGetLastError();
+}
+
 // ------------------------------------------------------------------ host side
 size_t learned_model_bytes() {
     size_t off[N_PARTS + 1];
@@ -1069,8 +1313,9 @@ BucketArgs learned_bucket_args(const void* model, uint16_t* bid) {
 }
 
 hipError_t learned_bucket_pass(int pass, const uint64_t* ks, const uint32_t* vs, const uint16_t* bs,
-                               uint64_t* kd, uint32_t* vd, uint16_t* bd, uint32_t n, uint32_t* cnt,
-                               uint32_t* gtot, uint32_t* binstart, hipStream_t s) {
+                               const uint64_t* k0s, uint64_t* kd, uint32_t* vd, uint16_t* bd,
+                               uint64_t* k0d, uint32_t n, uint32_t* cnt, uint32_t* gtot,
+                               uint32_t* binstart, hipStream_t s) {
     constexpr int ITEMS = 16;
     constexpr uint32_t TILE = BLOCK * ITEMS;
     const uint32_t tiles = (n + TILE - 1) / TILE, groups = (tiles + GROUP_TILES - 1) / GROUP_TILES;
@@ -1082,8 +1327,14 @@ hipError_t learned_bucket_pass(int pass, const uint64_t* ks, const uint32_t* vs,
         hipLaunchKernelGGL(k_lseg_scan, dim3(1), dim3(256), 0, s, gtot, groups, binstart);
     }
     ProfScope ps(P_BUCKET, s);
-    hipLaunchKernelGGL(k_bscatter<ITEMS>, dim3(tiles), dim3(BLOCK), 0, s, ks, vs, bs, kd, vd, bd, n,
-                       shift, (const uint32_t*)cnt, (const uint32_t*)gtot, (const uint32_t*)binstart);
+    if (k0s)
+        hipLaunchKernelGGL((k_bscatter<ITEMS, true>), dim3(tiles), dim3(BLOCK), 0, s, ks, vs, bs, k0s, kd,
+                           vd, bd, k0d, n, shift, (const uint32_t*)cnt, (const uint32_t*)gtot,
+                           (const uint32_t*)binstart);
+    else
+        hipLaunchKernelGGL((k_bscatter<ITEMS, false>), dim3(tiles), dim3(BLOCK), 0, s, ks, vs, bs, k0s, kd,
+                           vd, bd, k0d, n, shift, (const uint32_t*)cnt, (const uint32_t*)gtot,
+                           (const uint32_t*)binstart);
     return hipGetLastError();
 }
 uint32_t learned_pass_tiles(uint32_t n) { return (n + BLOCK * 16 - 1) / (BLOCK * 16); }

@@ -587,12 +587,12 @@ template <int BITS, int ITEMS>
 static hipError_t sort_impl(uint64_t* keys, uint32_t* vals, uint64_t* keys_alt,
                             uint32_t* vals_alt, int begin_bit, int end_bit, uint32_t max_segs,
                             uint32_t max_tiles, uint32_t pass_union, const RadixScratch& sc,
-                            int pclass, hipStream_t s) {
+                            int pclass, bool tile_segments, hipStream_t s) {
     constexpr uint32_t TILE = BLOCK * ITEMS;
     const int npasses = (end_bit - begin_bit + BITS - 1) / BITS;
     BigDesc* bigs = sc.bigs;
-    // single-tile segments
-    if (max_segs) {
+    // single-tile segments (unless the caller sorts them itself)
+    if (max_segs && tile_segments) {
         ProfScope ps(P_TILE_SORT, s);
         hipLaunchKernelGGL((k_tile_sort<BITS, ITEMS>), dim3(max_segs), dim3(BLOCK), 0, s, keys,
                            vals, sc.segs, sc.counters, begin_bit, end_bit);
@@ -653,11 +653,11 @@ hipError_t radix_sort_segments(uint64_t* keys, uint32_t* vals, uint64_t* keys_al
                                uint32_t* vals_alt, int begin_bit, int end_bit,
                                uint32_t max_segs, uint32_t max_tiles, uint32_t pass_union,
                                const RadixScratch& sc, const RadixConfig& cfg, int pclass,
-                               hipStream_t s) {
+                               hipStream_t s, bool tile_segments) {
 #define HUSKY_SORT_CASE(B, I)                                                                 \
     if (cfg.bits == B && cfg.items == I)                                                      \
         return sort_impl<B, I>(keys, vals, keys_alt, vals_alt, begin_bit, end_bit, max_segs, \
-                               max_tiles, pass_union, sc, pclass, s);
+                               max_tiles, pass_union, sc, pclass, tile_segments, s);
     HUSKY_SORT_CASE(8, 16)
     HUSKY_SORT_CASE(8, 12)
     HUSKY_SORT_CASE(8, 8)
