@@ -284,3 +284,32 @@ def torch_from(a):
     import torch
 
     return torch.from_numpy(np.ascontiguousarray(a).view(np.int32)).cuda()
+
+
+@pytest.mark.parametrize("coder", ["ascii7", "utf16"])
+def test_learned_long_shared_prefixes(gpu_lib, coder):
+    # groups that stay tied after the code and the first refinement key (the
+    # first 16 bytes / 7 units agree) inside buckets sorted in LDS, plus
+    # identical strings and strings ending inside the shared part: the later
+    # refinement rounds must run on exactly those groups
+    from workloads import from_strings
+
+    rng = np.random.default_rng(21 if coder == "ascii7" else 22)
+    n = 60_000
+    if coder == "ascii7":
+        prefixes = [bytes(rng.integers(97, 123, size=24, dtype=np.uint8)) for _ in range(40)]
+        out = []
+        for _ in range(n):
+            p = prefixes[int(rng.integers(0, 40))]
+            cut = int(rng.integers(5, 25))  # sometimes ends inside the prefix
+            out.append(p[:cut] + bytes(rng.integers(97, 100, size=int(rng.integers(0, 4)), dtype=np.uint8)))
+    else:
+        prefixes = [rng.integers(0x4E00, 0x4E10, size=12).tolist() for _ in range(40)]
+        out = []
+        for _ in range(n):
+            p = prefixes[int(rng.integers(0, 40))]
+            cut = int(rng.integers(2, 13))
+            out.append(p[:cut] + rng.integers(0x4E00, 0x4E03, size=int(rng.integers(0, 3))).tolist())
+    b = from_strings(out, coder)
+    st = _learned_equals_oracle(gpu_lib, b, sample_frac=0.05)
+    say(coder, "shared prefixes: runs visited", st["runs_fixed"], "rounds", st["large_rounds"])
