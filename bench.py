@@ -407,8 +407,10 @@ def bench_learned(args):
         "fit_ms": variants["monotone"]["fit_ms"],
         "inclusive_ms": round(ms_learned + variants["monotone"]["fit_ms"], 3),
         "variants": variants,
-        # each bucket pass reads and writes the 8-byte code, the 4-byte index and the 2-byte id
-        "bucket_scatter_gbs": round(28.0 * n * nb / (ms_bs / 1e3) / 1e9, 1) if nb else None,
+        # the two bucket passes move the 8-byte code, the 2-byte id and the 8-byte
+        # first refinement key; the index is written by both and read by the second:
+        # 40 + 44 bytes per string for the pair of passes
+        "bucket_scatter_gbs": round(42.0 * n * nb / (ms_bs / 1e3) / 1e9, 1) if nb else None,
         "kernels_learned": k_learned,
         "kernels_plain": k_plain,
     }
