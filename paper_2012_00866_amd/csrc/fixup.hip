@@ -331,13 +331,10 @@ template <int CODER, int MAXL>
 static hipError_t medium_impl(const FixupArgs& a, const TierLists& tl, uint32_t lmin,
                               uint32_t lmax, hipStream_t s) {
     const size_t lds = sizeof(MediumLds<MAXL>);
-    static bool attr_set = false;
-    if (!attr_set) {
-        hipError_t e = hipFuncSetAttribute((const void*)k_fix_medium<CODER, MAXL>,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        if (e != hipSuccess) return e;
-        attr_set = true;
-    }
+    // set on every launch: cheap on the host, and right for whichever device is current
+    hipError_t e = hipFuncSetAttribute((const void*)k_fix_medium<CODER, MAXL>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
     const uint32_t per_cu = (uint32_t)std::max<size_t>(1, std::min<size_t>(8, (160 * 1024) / lds));
     const uint32_t blocks = persistent_blocks() * per_cu;
     ProfScope ps(P_FIX_MEDIUM, s);

@@ -1209,13 +1209,10 @@ template <bool MONO>
 static hipError_t mlp_grad_launch(const float* params, const float* x, const float* y,
                                   uint32_t first, uint32_t count, uint32_t stride, uint32_t blocks,
                                   float inv_batch, float* partial, float* grad, hipStream_t s) {
-    static bool attr = false;
-    if (!attr) {
-        hipError_t e = hipFuncSetAttribute((const void*)k_mlp_grad<MONO>,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)mlp_lds());
-        if (e != hipSuccess) return e;
-        attr = true;
-    }
+    // set on every launch: cheap on the host, and right for whichever device is current
+    hipError_t e = hipFuncSetAttribute((const void*)k_mlp_grad<MONO>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)mlp_lds());
+    if (e != hipSuccess) return e;
     const uint32_t per_block = (count + blocks - 1) / blocks;
     hipLaunchKernelGGL(k_mlp_grad<MONO>, dim3(blocks), dim3(MLP_T), mlp_lds(), s, params, x, y, first,
                        count, stride, per_block, inv_batch, partial);

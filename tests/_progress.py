@@ -1,17 +1,17 @@
-"""Progress lines for long GPU tests: stderr plus gpurun_out/progress.log when present."""
+"""Progress lines for long GPU tests: to stderr, and appended to the file named
+by $HUSKY_PROGRESS_LOG when it is set."""
 
 import os
 import sys
 import time
 
-_ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 _T0 = time.time()
 
 
 def say(*parts):
     msg = f"[{time.time() - _T0:7.1f}s] " + " ".join(str(p) for p in parts)
     print(msg, file=sys.stderr, flush=True)
-    out = os.path.join(_ROOT, "gpurun_out")
-    if os.path.isdir(out):
-        with open(os.path.join(out, "progress.log"), "a") as f:
+    path = os.environ.get("HUSKY_PROGRESS_LOG")
+    if path:
+        with open(path, "a") as f:
             f.write(msg + "\n")
