@@ -32,7 +32,7 @@ constexpr uint32_t LEARN_MAX_BLOCKS = 256;
 // husky_learned_fit).
 struct Layout {
     size_t status, counters, codes_a, codes_b, idx_b, key0, segs, bigs, korand, binstart, cnt, gtot,
-        tile_counts, run_start, run_end, small, medium, large_a, large_b, bid, bseg, k0a, k0b,
+        tile_counts, run_start, run_end, small, medium, large_a, large_b, bid, bseg, k0a, k0b, scan,
         lpartial, lgrad, ltmax, total;
     uint32_t seg_cap, big_cap, tile_cap, big_tile_cap, group_cap, run_cap, small_cap, medium_cap,
         large_cap;
@@ -84,6 +84,7 @@ Layout make_layout(uint64_t n, uint64_t n_segs, bool learned = false) {
         L.bseg = take(((size_t)LEARNED_BUCKETS + 1) * 8);
         L.k0a = take(n * 8);  // first refinement keys in bucket order (ping-pong)
         L.k0b = take(n * 8);
+        L.scan = take((size_t)LEARNED_BUCKETS * sizeof(RunItem));  // buckets Step 3 scans
         L.lpartial = take(learned_partial_bytes(LEARN_MAX_BLOCKS));
         L.lgrad = take(((size_t)learned_nparam() + 1) * 4 + 256);
         L.ltmax = take((size_t)learned_lut_tiles() * 4);
@@ -96,7 +97,8 @@ Layout make_layout(uint64_t n, uint64_t n_segs, bool learned = false) {
 // [80] small count, [81] medium count; [84, 88) and [88, 92) the two
 // device-wide lists: item count, items longer than one tile, their tiles,
 // tiles of all items
-constexpr int CNT_RUNS = 64, CNT_SMALL = 80, CNT_MEDIUM = 81, CNT_LARGE_A = 84, CNT_LARGE_B = 88;
+constexpr int CNT_RUNS = 64, CNT_SMALL = 80, CNT_MEDIUM = 81, CNT_LARGE_A = 84, CNT_LARGE_B = 88,
+              CNT_SCAN = 96;  // learned form: buckets on the run-detection list
 
 struct Ctx {
     Layout L;
@@ -526,7 +528,11 @@ husky_status husky_sort_learned(husky_coder coder, const void* elems, const uint
                                   c.rad.cnt, c.rad.gtot, c.rad.binstart, s));
     HUSKY_TRY(learned_bucket_pass(1, codes_b, idx_b, bid_b, k0b, codes, perm, bid_a, k0a, nn,
                                   c.rad.cnt, c.rad.gtot, c.rad.binstart, s));
-    HUSKY_TRY(learned_bucket_bounds(bid_a, nn, bseg, &c.status->overflow_buckets, tn.rc.tile(), s));
+    RunItem* scan = c.at<RunItem>(L.scan);
+    uint32_t* scan_count = c.counters + CNT_SCAN;
+    HUSKY_TRY(zero_u32(scan_count, 1, s));
+    HUSKY_TRY(learned_bucket_bounds(bid_a, nn, bseg, &c.status->overflow_buckets, tn.rc.tile(), scan,
+                                    scan_count, s));
     // buckets of more than one tile: the multi-tile radix passes on the code
     const uint32_t B = LEARNED_BUCKETS;
     HUSKY_TRY(radix_segments_from_offsets(bseg, B, c.rad, tn.rc, s));
@@ -538,8 +544,11 @@ husky_status husky_sort_learned(husky_coder coder, const void* elems, const uint
                                   P_SCATTER, s, false));
     // every other bucket in LDS: by code, then by the first refinement key
     // inside runs of equal codes; its codes become tie keys
-    HUSKY_TRY(learned_bucket_refine(coder, codes, perm, k0a, c.rad, B, tn.rc.tile(), s));
-    // equal codes share a bucket, so runs never cross bucket boundaries
+    HUSKY_TRY(learned_bucket_refine(coder, codes, perm, k0a, c.rad, B, tn.rc.tile(), scan, scan_count,
+                                    s));
+    // Step 3 scans only the buckets listed: the larger ones and those with a
+    // group still tied (equal codes share a bucket, so no run crosses one)
+    HUSKY_TRY(radix_segments_from_items(scan, scan_count, B, c.rad, tn.rc, s));
     return run_fixup(c, tn, coder, elems, offsets, n, B, codes, codes, codes_b, perm, s);
 }
 

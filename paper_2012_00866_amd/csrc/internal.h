@@ -170,9 +170,10 @@ hipError_t learned_bucket_pass(int pass, const uint64_t* ks, const uint32_t* vs,
                                uint32_t* binstart, hipStream_t s);
 hipError_t learned_bucket_refine(int coder, uint64_t* codes, uint32_t* perm, const uint64_t* k0,
                                  const RadixScratch& sc, uint32_t max_segs, uint32_t cap,
-                                 hipStream_t s);
+                                 RunItem* scan_list, uint32_t* scan_count, hipStream_t s);
 hipError_t learned_bucket_bounds(const uint16_t* bid, uint32_t n, uint64_t* seg, uint32_t* overflow,
-                                 uint32_t tile, hipStream_t s);
+                                 uint32_t tile, RunItem* scan_list, uint32_t* scan_count,
+                                 hipStream_t s);
 
 // Chunk geometry of the refinement keys.
 constexpr int ascii_m = 9, ascii_chunk = 7;

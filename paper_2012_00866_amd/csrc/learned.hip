@@ -907,15 +907,19 @@ __global__ void k_learned_finish(LearnedHeader* hdr, const float* __restrict__ l
 }
 
 // Buckets larger than one radix tile go to the multi-tile passes (overflow):
-// their number and their keys.
+// their number and their keys, and each one joins the list of segments that
+// Step 3's run detection will scan.
 __global__ void k_overflow_stats(const uint64_t* __restrict__ seg, uint32_t B, uint32_t tile,
-                                 uint32_t* __restrict__ out) {
+                                 uint32_t* __restrict__ out, RunItem* __restrict__ scan_list,
+                                 uint32_t* __restrict__ scan_count) {
     uint32_t nb = 0, nk = 0;
     for (uint32_t b = blockIdx.x * 256 + threadIdx.x; b < B; b += gridDim.x * 256) {
         const uint32_t len = (uint32_t)(seg[b + 1] - seg[b]);
         if (len > tile) {
             ++nb;
             nk += len;
+            const uint32_t at = atomicAdd(scan_count, 1u);
+            scan_list[at] = RunItem{(uint32_t)seg[b], len, 0u, 0u};
         }
     }
     if (nb) {
@@ -934,10 +938,11 @@ __global__ void k_overflow_stats(const uint64_t* __restrict__ seg, uint32_t B, u
 //     equal codes is ordered by its first refinement key, ties by slot;
 //  4. write the permutation (indices gathered by slot) and, in place of the
 //     codes, a tie key per position: the first position of its group, where
-//     a group is a run of equal (code, refinement key) whose key continues.
-// Step 3's run detection then finds only those groups (and the runs of the
-// larger buckets, whose codes are left as they are); every later refinement
-// round proceeds as for any run.
+//     a group is a run of equal (code, refinement key) whose key continues;
+//     a bucket that still holds such a group joins the list of segments that
+//     Step 3's run detection scans (with the larger buckets, whose codes are
+//     left as they are).
+// Every later refinement round proceeds as for any run.
 // Running maximum over the tile in position order, with positions held in the
 // wave-striped layout of rank_digits: every position's value replaced by the
 // maximum of the values at or before it.  s_tmp: BLOCK * ITEMS words.
@@ -982,7 +987,9 @@ __global__ __launch_bounds__(BLOCK) void k_bucket_refine(uint64_t* __restrict__ 
                                                          const uint64_t* __restrict__ k0,
                                                          const SegDesc* __restrict__ segs,
                                                          const uint32_t* __restrict__ counters,
-                                                         uint32_t lmin, uint32_t lmax, int code_bits) {
+                                                         uint32_t lmin, uint32_t lmax, int code_bits,
+                                                         RunItem* __restrict__ scan_list,
+                                                         uint32_t* __restrict__ scan_count) {
     constexpr uint32_t TILE = BLOCK * ITEMS;
     __shared__ uint64_t s_k[TILE];
     __shared__ uint32_t s_sr[TILE];
@@ -1100,14 +1107,17 @@ __global__ __launch_bounds__(BLOCK) void k_bucket_refine(uint64_t* __restrict__ 
             s_sr[posof(i)] = sr[i];
         }
         __syncthreads();
+        bool tied = false;
 #pragma unroll
         for (int i = 0; i < ITEMS; ++i) {
             const uint32_t p = posof(i);
             const bool same = p > 0 && p < nvalid && (s_sr[p - 1] >> 16) == (sr[i] >> 16) &&
                               s_k[p - 1] == k[i] && key_continues<CODER>(k[i]);
+            tied = tied || same;
             t[i] = same ? 0u : p;
         }
-        __syncthreads();
+        tied = __syncthreads_or(tied);
+        if (tied && threadIdx.x == 0) scan_list[atomicAdd(scan_count, 1u)] = RunItem{start, nvalid, 0u, 0u};
         tile_running_max<ITEMS>(t, s_k32, s_scan);
     } else {
 #pragma unroll
@@ -1130,7 +1140,7 @@ __global__ __launch_bounds__(BLOCK) void k_bucket_refine(uint64_t* __restrict__ 
 
 hipError_t learned_bucket_refine(int coder, uint64_t* codes, uint32_t* perm, const uint64_t* k0,
                                  const RadixScratch& sc, uint32_t max_segs, uint32_t cap,
-                                 hipStream_t s) {
+                                 RunItem* scan_list, uint32_t* scan_count, hipStream_t s) {
     if (!max_segs) return hipSuccess;
     ProfScope ps(P_TILE_SORT, s);
     // two size classes: the smaller one needs fewer registers and LDS, so more
@@ -1140,16 +1150,16 @@ hipError_t learned_bucket_refine(int coder, uint64_t* codes, uint32_t* perm, con
     const uint32_t c1 = std::min(cap, BLOCK * 12u), c2 = std::min(cap, BLOCK * 16u);
     if (coder == 0) {
         hipLaunchKernelGGL((k_bucket_refine<0, 12>), dim3(max_segs), dim3(BLOCK), 0, s, codes, perm, k0,
-                           sg, ct, 0u, c1, 63);
+                           sg, ct, 0u, c1, 63, scan_list, scan_count);
         if (c2 > c1)
             hipLaunchKernelGGL((k_bucket_refine<0, 16>), dim3(max_segs), dim3(BLOCK), 0, s, codes, perm,
-                               k0, sg, ct, c1, c2, 63);
+                               k0, sg, ct, c1, c2, 63, scan_list, scan_count);
     } else {
         hipLaunchKernelGGL((k_bucket_refine<1, 12>), dim3(max_segs), dim3(BLOCK), 0, s, codes, perm, k0,
-                           sg, ct, 0u, c1, 64);
+                           sg, ct, 0u, c1, 64, scan_list, scan_count);
         if (c2 > c1)
             hipLaunchKernelGGL((k_bucket_refine<1, 16>), dim3(max_segs), dim3(BLOCK), 0, s, codes, perm,
-                               k0, sg, ct, c1, c2, 64);
+                               k0, sg, ct, c1, c2, 64, scan_list, scan_count);
     }
     return hipGetLastError();
 }
@@ -1337,12 +1347,13 @@ hipError_t learned_bucket_pass(int pass, const uint64_t* ks, const uint32_t* vs,
 uint32_t learned_pass_tiles(uint32_t n) { return (n + BLOCK * 16 - 1) / (BLOCK * 16); }
 
 hipError_t learned_bucket_bounds(const uint16_t* bid, uint32_t n, uint64_t* seg, uint32_t* overflow,
-                                 uint32_t tile, hipStream_t s) {
+                                 uint32_t tile, RunItem* scan_list, uint32_t* scan_count,
+                                 hipStream_t s) {
     ProfScope ps(P_BUCKET_BOUNDS, s);
     hipLaunchKernelGGL(k_bucket_bounds, dim3(grid_for((uint64_t)n + 1)), dim3(256), 0, s, bid, n,
                        (uint32_t)LEARNED_BUCKETS, seg);
     hipLaunchKernelGGL(k_overflow_stats, dim3(256), dim3(256), 0, s, (const uint64_t*)seg,
-                       (uint32_t)LEARNED_BUCKETS, tile, overflow);
+                       (uint32_t)LEARNED_BUCKETS, tile, overflow, scan_list, scan_count);
     return hipGetLastError();
 }
 
