@@ -79,7 +79,7 @@ typedef struct {
     uint32_t large_rounds;      /* device-wide refinement rounds the last fix-up ran */
     uint32_t runs_fixed;        /* equal-code runs (length >= 2) the last fix-up visited */
     uint32_t unresolved;        /* groups left tied after max_rounds fixed rounds (else 0) */
-    uint32_t overflow_buckets;  /* learned form: buckets holding more than one radix tile */
+    uint32_t overflow_buckets;  /* learned form: buckets above the LDS sort's 8,192 keys */
     uint32_t overflow_keys;     /* learned form: strings in those buckets */
 } husky_device_status;
 
@@ -210,9 +210,10 @@ void husky_profile_select(uint32_t class_mask);
  * A model maps every code to one of HUSKY_LEARNED_BUCKETS buckets by a
  * function that never decreases as the code grows, so sorting the pairs
  * becomes: bucket ids, a stable scatter of (code, index) into bucket order,
- * and independent sorts of the buckets by code -- in LDS for buckets of at
- * most one radix tile, by the multi-tile radix passes for larger ("overflow")
- * buckets.  Step 3 then runs as in husky_sort.  Since equal codes always
+ * and independent sorts of the buckets -- in LDS for buckets of at most 8,192
+ * keys (by code, then by the first refinement key inside runs of equal codes,
+ * so most of Step 3 happens there too), by the multi-tile radix passes for
+ * larger ("overflow") buckets.  Step 3 then runs on what is still tied.  Since equal codes always
  * share a bucket and buckets are in code order, the permutation is exactly
  * husky_sort's whatever the model's quality; a poor model only costs time.
  *

@@ -33,7 +33,7 @@ constexpr uint32_t LEARN_MAX_BLOCKS = 256;
 struct Layout {
     size_t status, counters, codes_a, codes_b, idx_b, key0, segs, bigs, korand, binstart, cnt, gtot,
         tile_counts, run_start, run_end, small, medium, large_a, large_b, bid, bseg, k0a, k0b, scan,
-        lpartial, lgrad, ltmax, total;
+        biglist, lpartial, lgrad, ltmax, total;
     uint32_t seg_cap, big_cap, tile_cap, big_tile_cap, group_cap, run_cap, small_cap, medium_cap,
         large_cap;
 };
@@ -84,7 +84,8 @@ Layout make_layout(uint64_t n, uint64_t n_segs, bool learned = false) {
         L.bseg = take(((size_t)LEARNED_BUCKETS + 1) * 8);
         L.k0a = take(n * 8);  // first refinement keys in bucket order (ping-pong)
         L.k0b = take(n * 8);
-        L.scan = take((size_t)LEARNED_BUCKETS * sizeof(RunItem));  // buckets Step 3 scans
+        L.scan = take((size_t)LEARNED_BUCKETS * sizeof(RunItem));     // buckets Step 3 scans
+        L.biglist = take((size_t)LEARNED_BUCKETS * sizeof(RunItem));  // buckets the radix passes sort
         L.lpartial = take(learned_partial_bytes(LEARN_MAX_BLOCKS));
         L.lgrad = take(((size_t)learned_nparam() + 1) * 4 + 256);
         L.ltmax = take((size_t)learned_lut_tiles() * 4);
@@ -98,7 +99,8 @@ Layout make_layout(uint64_t n, uint64_t n_segs, bool learned = false) {
 // device-wide lists: item count, items longer than one tile, their tiles,
 // tiles of all items
 constexpr int CNT_RUNS = 64, CNT_SMALL = 80, CNT_MEDIUM = 81, CNT_LARGE_A = 84, CNT_LARGE_B = 88,
-              CNT_SCAN = 96;  // learned form: buckets on the run-detection list
+              CNT_SCAN = 96,  // learned form: buckets on the run-detection list
+              CNT_BIG = 97;   // learned form: buckets for the multi-tile radix passes
 
 struct Ctx {
     Layout L;
@@ -529,24 +531,27 @@ husky_status husky_sort_learned(husky_coder coder, const void* elems, const uint
     HUSKY_TRY(learned_bucket_pass(1, codes_b, idx_b, bid_b, k0b, codes, perm, bid_a, k0a, nn,
                                   c.rad.cnt, c.rad.gtot, c.rad.binstart, s));
     RunItem* scan = c.at<RunItem>(L.scan);
+    RunItem* biglist = c.at<RunItem>(L.biglist);
     uint32_t* scan_count = c.counters + CNT_SCAN;
-    HUSKY_TRY(zero_u32(scan_count, 1, s));
-    HUSKY_TRY(learned_bucket_bounds(bid_a, nn, bseg, &c.status->overflow_buckets, tn.rc.tile(), scan,
-                                    scan_count, s));
-    // buckets of more than one tile: the multi-tile radix passes on the code
+    uint32_t* big_count = c.counters + CNT_BIG;
+    HUSKY_TRY(zero_u32(scan_count, 2, s));
+    HUSKY_TRY(learned_bucket_bounds(bid_a, nn, bseg, &c.status->overflow_buckets, biglist, big_count,
+                                    scan, scan_count, s));
+    // buckets of at most LEARNED_LDS_CAP keys, in LDS: by code, then by the
+    // first refinement key inside runs of equal codes; their codes become tie
+    // keys, and those with a group still tied join the scan list
     const uint32_t B = LEARNED_BUCKETS;
     HUSKY_TRY(radix_segments_from_offsets(bseg, B, c.rad, tn.rc, s));
+    HUSKY_TRY(learned_bucket_refine(coder, codes, perm, k0a, c.rad, B, scan, scan_count, s));
+    // larger buckets: the multi-tile radix passes on the code
+    HUSKY_TRY(radix_segments_from_items(biglist, big_count, B, c.rad, tn.rc, s));
     const int end_bit = coder == HUSKY_CODER_ASCII7 ? 63 : 64;
     const uint32_t tb = tiles_bound(n, B, tn.rc);
     HUSKY_TRY(radix_reduce_tiles(codes, tb, c.rad, tn.rc, s));
     HUSKY_TRY(radix_exec_masks(0, end_bit, B, tb, c.rad, tn.rc, s));
     HUSKY_TRY(radix_sort_segments(codes, perm, codes_b, idx_b, 0, end_bit, B, tb, ~0u, c.rad, tn.rc,
                                   P_SCATTER, s, false));
-    // every other bucket in LDS: by code, then by the first refinement key
-    // inside runs of equal codes; its codes become tie keys
-    HUSKY_TRY(learned_bucket_refine(coder, codes, perm, k0a, c.rad, B, tn.rc.tile(), scan, scan_count,
-                                    s));
-    // Step 3 scans only the buckets listed: the larger ones and those with a
+    // Step 3 scans only the listed buckets: the larger ones and those with a
     // group still tied (equal codes share a bucket, so no run crosses one)
     HUSKY_TRY(radix_segments_from_items(scan, scan_count, B, c.rad, tn.rc, s));
     return run_fixup(c, tn, coder, elems, offsets, n, B, codes, codes, codes_b, perm, s);

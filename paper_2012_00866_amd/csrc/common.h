@@ -94,9 +94,6 @@ __device__ __forceinline__ uint32_t wave_inclusive_sum(uint32_t v) {
     return v;
 }
 
-// Exclusive prefix sum over the BLOCK threads of a workgroup.  `scratch`
-// holds NWAVES words of LDS.  Returns the exclusive prefix; *total gets the
-// block total.  Every thread of the block must call it.
 // Workgroups of a launch are dispatched to the 8 XCDs round-robin (block b
 // on XCD b % 8), each XCD behind its own L2.  xcd_remap(b, G) hands each XCD a
 // contiguous range of the G tiles instead, so that neighbouring tiles -- whose
@@ -108,6 +105,10 @@ __device__ __forceinline__ uint32_t xcd_remap(uint32_t b, uint32_t G) {
     return x * q + (x < r ? x : r) + i;
 }
 
+// Exclusive prefix sum over the NW * 64 threads of a workgroup.  `scratch`
+// holds NW words of LDS.  Returns the exclusive prefix; *total gets the block
+// total.  Every thread of the block must call it.
+template <int NW = NWAVES>
 __device__ __forceinline__ uint32_t block_exclusive_sum(uint32_t v, uint32_t* scratch,
                                                         uint32_t* total) {
     const uint32_t lane = lane_id(), wid = threadIdx.x / WAVE;
@@ -116,7 +117,7 @@ __device__ __forceinline__ uint32_t block_exclusive_sum(uint32_t v, uint32_t* sc
     __syncthreads();
     uint32_t before = 0, all = 0;
 #pragma unroll
-    for (int w = 0; w < NWAVES; ++w) {
+    for (int w = 0; w < NW; ++w) {
         uint32_t s = scratch[w];
         before += (w < (int)wid) ? s : 0u;
         all += s;

@@ -144,6 +144,7 @@ hipError_t fixup_large_keys(const FixupArgs& a, const RunItem* items, const Radi
 
 // ---- learned.hip
 constexpr uint32_t LEARNED_BUCKETS = 65536;
+constexpr uint32_t LEARNED_LDS_CAP = 8192;  // largest bucket sorted in LDS
 size_t learned_model_bytes();
 size_t learned_model_offset(int part);
 uint32_t learned_nparam();
@@ -169,11 +170,11 @@ hipError_t learned_bucket_pass(int pass, const uint64_t* ks, const uint32_t* vs,
                                uint64_t* k0d, uint32_t n, uint32_t* cnt, uint32_t* gtot,
                                uint32_t* binstart, hipStream_t s);
 hipError_t learned_bucket_refine(int coder, uint64_t* codes, uint32_t* perm, const uint64_t* k0,
-                                 const RadixScratch& sc, uint32_t max_segs, uint32_t cap,
-                                 RunItem* scan_list, uint32_t* scan_count, hipStream_t s);
+                                 const RadixScratch& sc, uint32_t max_segs, RunItem* scan_list,
+                                 uint32_t* scan_count, hipStream_t s);
 hipError_t learned_bucket_bounds(const uint16_t* bid, uint32_t n, uint64_t* seg, uint32_t* overflow,
-                                 uint32_t tile, RunItem* scan_list, uint32_t* scan_count,
-                                 hipStream_t s);
+                                 RunItem* big_list, uint32_t* big_count, RunItem* scan_list,
+                                 uint32_t* scan_count, hipStream_t s);
 
 // Chunk geometry of the refinement keys.
 constexpr int ascii_m = 9, ascii_chunk = 7;

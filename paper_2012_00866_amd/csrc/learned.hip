@@ -906,20 +906,22 @@ __global__ void k_learned_finish(LearnedHeader* hdr, const float* __restrict__ l
     hdr->last_loss = trained ? *loss_acc / (float)trained : 0.f;
 }
 
-// Buckets larger than one radix tile go to the multi-tile passes (overflow):
-// their number and their keys, and each one joins the list of segments that
-// Step 3's run detection will scan.
-__global__ void k_overflow_stats(const uint64_t* __restrict__ seg, uint32_t B, uint32_t tile,
-                                 uint32_t* __restrict__ out, RunItem* __restrict__ scan_list,
+// Buckets larger than the LDS sort's capacity go to the multi-tile radix
+// passes (overflow): their number and their keys; each one joins the list the
+// radix passes sort and the list of segments Step 3's run detection scans.
+__global__ void k_overflow_stats(const uint64_t* __restrict__ seg, uint32_t B, uint32_t cap,
+                                 uint32_t* __restrict__ out, RunItem* __restrict__ big_list,
+                                 uint32_t* __restrict__ big_count, RunItem* __restrict__ scan_list,
                                  uint32_t* __restrict__ scan_count) {
     uint32_t nb = 0, nk = 0;
     for (uint32_t b = blockIdx.x * 256 + threadIdx.x; b < B; b += gridDim.x * 256) {
         const uint32_t len = (uint32_t)(seg[b + 1] - seg[b]);
-        if (len > tile) {
+        if (len > cap) {
             ++nb;
             nk += len;
-            const uint32_t at = atomicAdd(scan_count, 1u);
-            scan_list[at] = RunItem{(uint32_t)seg[b], len, 0u, 0u};
+            const RunItem it{(uint32_t)seg[b], len, 0u, 0u};
+            big_list[atomicAdd(big_count, 1u)] = it;
+            scan_list[atomicAdd(scan_count, 1u)] = it;
         }
     }
     if (nb) {
@@ -945,8 +947,8 @@ __global__ void k_overflow_stats(const uint64_t* __restrict__ seg, uint32_t B, u
 // Every later refinement round proceeds as for any run.
 // Running maximum over the tile in position order, with positions held in the
 // wave-striped layout of rank_digits: every position's value replaced by the
-// maximum of the values at or before it.  s_tmp: BLOCK * ITEMS words.
-template <int ITEMS>
+// maximum of the values at or before it.  s_tmp: NW * 64 * ITEMS words.
+template <int ITEMS, int NW>
 __device__ __forceinline__ void tile_running_max(uint32_t (&v)[ITEMS], uint32_t* s_tmp,
                                                  uint32_t* s_scan) {
     const uint32_t tid = threadIdx.x, w = tid / WAVE, lane = lane_id();
@@ -979,10 +981,11 @@ __device__ __forceinline__ void tile_running_max(uint32_t (&v)[ITEMS], uint32_t*
     __syncthreads();
 }
 
-// One size class of buckets: lmin < len <= lmax (and 2 <= len <= BLOCK * ITEMS).
-// Per item: its key and one word sr = slot | run start << 16 (both < 4096).
-template <int CODER, int ITEMS>
-__global__ __launch_bounds__(BLOCK) void k_bucket_refine(uint64_t* __restrict__ codes,
+// One size class of buckets: lmin < len <= lmax (and 2 <= len <= NW * 64 * ITEMS),
+// one workgroup of NW wavefronts per bucket.
+// Per item: its key and one word sr = slot | run start << 16 (both < 2^16).
+template <int CODER, int ITEMS, int NW>
+__global__ __launch_bounds__(NW * WAVE) void k_bucket_refine(uint64_t* __restrict__ codes,
                                                          uint32_t* __restrict__ perm,
                                                          const uint64_t* __restrict__ k0,
                                                          const SegDesc* __restrict__ segs,
@@ -990,13 +993,14 @@ __global__ __launch_bounds__(BLOCK) void k_bucket_refine(uint64_t* __restrict__ 
                                                          uint32_t lmin, uint32_t lmax, int code_bits,
                                                          RunItem* __restrict__ scan_list,
                                                          uint32_t* __restrict__ scan_count) {
-    constexpr uint32_t TILE = BLOCK * ITEMS;
+    constexpr uint32_t TILE = NW * WAVE * ITEMS;
+    static_assert(TILE <= 65536, "slots and run starts fit 16 bits");
     __shared__ uint64_t s_k[TILE];
     __shared__ uint32_t s_sr[TILE];
-    __shared__ uint32_t s_whist[NWAVES * 256];
+    __shared__ uint32_t s_whist[NW * 256];
     __shared__ uint32_t s_binstart[256];
-    __shared__ uint32_t s_scan[NWAVES];
-    __shared__ uint64_t s_or[NWAVES], s_and[NWAVES];
+    __shared__ uint32_t s_scan[NW];
+    __shared__ uint64_t s_or[NW], s_and[NW];
     uint32_t* s_k32 = reinterpret_cast<uint32_t*>(s_k);  // scratch while keys sit in registers
     const uint32_t sidx = blockIdx.x;
     if (sidx >= counters[C_NUM_SEGS]) return;
@@ -1026,7 +1030,7 @@ __global__ __launch_bounds__(BLOCK) void k_bucket_refine(uint64_t* __restrict__ 
         __syncthreads();
         uint64_t oo = 0, aa = ~0ull;
 #pragma unroll
-        for (int ww = 0; ww < NWAVES; ++ww) {
+        for (int ww = 0; ww < NW; ++ww) {
             oo |= s_or[ww];
             aa &= s_and[ww];
         }
@@ -1038,7 +1042,7 @@ __global__ __launch_bounds__(BLOCK) void k_bucket_refine(uint64_t* __restrict__ 
     // one digit pass of (k, sr) through LDS
     auto pass = [&]() {
         uint32_t bc;
-        rank_digits<8, ITEMS>(dig, nvalid, pos, s_whist, s_binstart, s_scan, &bc);
+        rank_digits<8, ITEMS, NW>(dig, nvalid, pos, s_whist, s_binstart, s_scan, &bc);
 #pragma unroll
         for (int i = 0; i < ITEMS; ++i) {
             s_k[pos[i]] = k[i];
@@ -1082,7 +1086,7 @@ __global__ __launch_bounds__(BLOCK) void k_bucket_refine(uint64_t* __restrict__ 
     }
     repeats = __syncthreads_or(repeats);
     if (repeats) {
-        tile_running_max<ITEMS>(t, s_k32, s_scan);
+        tile_running_max<ITEMS, NW>(t, s_k32, s_scan);
 #pragma unroll
         for (int i = 0; i < ITEMS; ++i) sr[i] |= t[i] << 16;
         // 3. by (run start, refinement key), stable in slot
@@ -1095,7 +1099,7 @@ __global__ __launch_bounds__(BLOCK) void k_bucket_refine(uint64_t* __restrict__ 
             for (int i = 0; i < ITEMS; ++i) dig[i] = (uint32_t)(k[i] >> shift) & 0xFFu;
             pass();
         }
-        for (int shift = 16; shift < 28; shift += 8) {  // run starts are < 4096
+        for (int shift = 16; shift < 32; shift += 8) {  // run starts are < 2^16
 #pragma unroll
             for (int i = 0; i < ITEMS; ++i) dig[i] = (sr[i] >> shift) & 0xFFu;
             pass();
@@ -1118,7 +1122,7 @@ __global__ __launch_bounds__(BLOCK) void k_bucket_refine(uint64_t* __restrict__ 
         }
         tied = __syncthreads_or(tied);
         if (tied && threadIdx.x == 0) scan_list[atomicAdd(scan_count, 1u)] = RunItem{start, nvalid, 0u, 0u};
-        tile_running_max<ITEMS>(t, s_k32, s_scan);
+        tile_running_max<ITEMS, NW>(t, s_k32, s_scan);
     } else {
 #pragma unroll
         for (int i = 0; i < ITEMS; ++i) t[i] = posof(i);
@@ -1139,28 +1143,30 @@ __global__ __launch_bounds__(BLOCK) void k_bucket_refine(uint64_t* __restrict__ 
 }
 
 hipError_t learned_bucket_refine(int coder, uint64_t* codes, uint32_t* perm, const uint64_t* k0,
-                                 const RadixScratch& sc, uint32_t max_segs, uint32_t cap,
-                                 RunItem* scan_list, uint32_t* scan_count, hipStream_t s) {
+                                 const RadixScratch& sc, uint32_t max_segs, RunItem* scan_list,
+                                 uint32_t* scan_count, hipStream_t s) {
     if (!max_segs) return hipSuccess;
     ProfScope ps(P_TILE_SORT, s);
-    // two size classes: the smaller one needs fewer registers and LDS, so more
-    // workgroups share a CU
+    // four size classes; a smaller one needs fewer registers and less LDS, so
+    // more workgroups share a CU, and wastes fewer padding slots
     const SegDesc* sg = sc.segs;
     const uint32_t* ct = sc.counters;
-    const uint32_t c1 = std::min(cap, BLOCK * 12u), c2 = std::min(cap, BLOCK * 16u);
+    const uint32_t c1 = BLOCK * 12u, c2 = BLOCK * 16u, c3 = 2 * BLOCK * 12u, c4 = LEARNED_LDS_CAP;
+#define HUSKY_RF(C, I, NW, LO, HI, BITS)                                                          \
+    hipLaunchKernelGGL((k_bucket_refine<C, I, NW>), dim3(max_segs), dim3(NW * WAVE), 0, s, codes, \
+                       perm, k0, sg, ct, LO, HI, BITS, scan_list, scan_count)
     if (coder == 0) {
-        hipLaunchKernelGGL((k_bucket_refine<0, 12>), dim3(max_segs), dim3(BLOCK), 0, s, codes, perm, k0,
-                           sg, ct, 0u, c1, 63, scan_list, scan_count);
-        if (c2 > c1)
-            hipLaunchKernelGGL((k_bucket_refine<0, 16>), dim3(max_segs), dim3(BLOCK), 0, s, codes, perm,
-                               k0, sg, ct, c1, c2, 63, scan_list, scan_count);
+        HUSKY_RF(0, 12, 4, 0u, c1, 63);
+        HUSKY_RF(0, 16, 4, c1, c2, 63);
+        HUSKY_RF(0, 12, 8, c2, c3, 63);
+        HUSKY_RF(0, 16, 8, c3, c4, 63);
     } else {
-        hipLaunchKernelGGL((k_bucket_refine<1, 12>), dim3(max_segs), dim3(BLOCK), 0, s, codes, perm, k0,
-                           sg, ct, 0u, c1, 64, scan_list, scan_count);
-        if (c2 > c1)
-            hipLaunchKernelGGL((k_bucket_refine<1, 16>), dim3(max_segs), dim3(BLOCK), 0, s, codes, perm,
-                               k0, sg, ct, c1, c2, 64, scan_list, scan_count);
+        HUSKY_RF(1, 12, 4, 0u, c1, 64);
+        HUSKY_RF(1, 16, 4, c1, c2, 64);
+        HUSKY_RF(1, 12, 8, c2, c3, 64);
+        HUSKY_RF(1, 16, 8, c3, c4, 64);
     }
+#undef HUSKY_RF
     return hipGetLastError();
 }
 
@@ -1347,13 +1353,14 @@ hipError_t learned_bucket_pass(int pass, const uint64_t* ks, const uint32_t* vs,
 uint32_t learned_pass_tiles(uint32_t n) { return (n + BLOCK * 16 - 1) / (BLOCK * 16); }
 
 hipError_t learned_bucket_bounds(const uint16_t* bid, uint32_t n, uint64_t* seg, uint32_t* overflow,
-                                 uint32_t tile, RunItem* scan_list, uint32_t* scan_count,
-                                 hipStream_t s) {
+                                 RunItem* big_list, uint32_t* big_count, RunItem* scan_list,
+                                 uint32_t* scan_count, hipStream_t s) {
     ProfScope ps(P_BUCKET_BOUNDS, s);
     hipLaunchKernelGGL(k_bucket_bounds, dim3(grid_for((uint64_t)n + 1)), dim3(256), 0, s, bid, n,
                        (uint32_t)LEARNED_BUCKETS, seg);
     hipLaunchKernelGGL(k_overflow_stats, dim3(256), dim3(256), 0, s, (const uint64_t*)seg,
-                       (uint32_t)LEARNED_BUCKETS, tile, overflow, scan_list, scan_count);
+                       (uint32_t)LEARNED_BUCKETS, LEARNED_LDS_CAP, overflow, big_list, big_count,
+                       scan_list, scan_count);
     return hipGetLastError();
 }
 

@@ -73,45 +73,65 @@ struct SrcItems {
 };
 
 // One workgroup: segment descriptors, the two tile spaces, the big list and
-// its scan groups.
+// its scan groups.  Each thread takes SEG_K consecutive segments per round, so
+// a round of four block scans covers BLOCK * SEG_K segments.
+constexpr uint32_t SEG_K = 8;
 template <typename Src>
 __global__ __launch_bounds__(BLOCK) void k_seg_setup(Src src, SegDesc* segs, BigDesc* bigs,
                                                      uint32_t* counters, uint32_t tile) {
     __shared__ uint32_t scratch[NWAVES];
     const uint32_t S = src.count();
     uint32_t carry_all = 0, carry_big = 0, carry_nbig = 0, carry_grp = 0;
-    for (uint32_t base = 0; base < S; base += BLOCK) {
-        const uint32_t i = base + threadIdx.x;
-        uint32_t st = 0, ln = 0;
-        if (i < S) src.get(i, st, ln);
-        const uint32_t nt = (ln + tile - 1) / tile;
-        const bool big = ln > tile;
-        const uint32_t ng = big ? (nt + GROUP_TILES - 1) / GROUP_TILES : 0u;
+    for (uint32_t base = 0; base < S; base += BLOCK * SEG_K) {
+        const uint32_t i0 = base + threadIdx.x * SEG_K;
+        uint32_t st[SEG_K], ln[SEG_K];
+        uint32_t s_all = 0, s_big = 0, s_nbig = 0, s_grp = 0;
+#pragma unroll
+        for (uint32_t j = 0; j < SEG_K; ++j) {
+            st[j] = ln[j] = 0;
+            if (i0 + j < S) src.get(i0 + j, st[j], ln[j]);
+            const uint32_t nt = (ln[j] + tile - 1) / tile;
+            const bool big = ln[j] > tile;
+            s_all += nt;
+            s_big += big ? nt : 0u;
+            s_nbig += big ? 1u : 0u;
+            s_grp += big ? (nt + GROUP_TILES - 1) / GROUP_TILES : 0u;
+        }
         uint32_t tot_all, tot_big, tot_nbig, tot_grp;
-        const uint32_t ex_all = block_exclusive_sum(nt, scratch, &tot_all);
-        const uint32_t ex_big = block_exclusive_sum(big ? nt : 0u, scratch, &tot_big);
-        const uint32_t ex_nbig = block_exclusive_sum(big ? 1u : 0u, scratch, &tot_nbig);
-        const uint32_t ex_grp = block_exclusive_sum(ng, scratch, &tot_grp);
-        if (i < S) {
-            SegDesc d;
-            d.start = st;
-            d.len = ln;
-            d.first_tile = carry_all + ex_all;
-            d.aux = big ? carry_nbig + ex_nbig : NOT_BIG;
-            segs[i] = d;
-            if (big) {
-                const uint32_t bi = carry_nbig + ex_nbig;
-                BigDesc b;
-                b.start = st;
-                b.len = ln;
-                b.first_tile = carry_big + ex_big;
-                b.exec = 0;  // written once the varying bits are known
-                b.first_group = carry_grp + ex_grp;
-                b.ntiles = nt;
-                b.ngroups = ng;
-                b.pad = 0;
-                bigs[bi] = b;
+        uint32_t ex_all = block_exclusive_sum(s_all, scratch, &tot_all);
+        uint32_t ex_big = block_exclusive_sum(s_big, scratch, &tot_big);
+        uint32_t ex_nbig = block_exclusive_sum(s_nbig, scratch, &tot_nbig);
+        uint32_t ex_grp = block_exclusive_sum(s_grp, scratch, &tot_grp);
+#pragma unroll
+        for (uint32_t j = 0; j < SEG_K; ++j) {
+            const uint32_t i = i0 + j;
+            const uint32_t nt = (ln[j] + tile - 1) / tile;
+            const bool big = ln[j] > tile;
+            const uint32_t ng = big ? (nt + GROUP_TILES - 1) / GROUP_TILES : 0u;
+            if (i < S) {
+                SegDesc d;
+                d.start = st[j];
+                d.len = ln[j];
+                d.first_tile = carry_all + ex_all;
+                d.aux = big ? carry_nbig + ex_nbig : NOT_BIG;
+                segs[i] = d;
+                if (big) {
+                    BigDesc b;
+                    b.start = st[j];
+                    b.len = ln[j];
+                    b.first_tile = carry_big + ex_big;
+                    b.exec = 0;  // written once the varying bits are known
+                    b.first_group = carry_grp + ex_grp;
+                    b.ntiles = nt;
+                    b.ngroups = ng;
+                    b.pad = 0;
+                    bigs[carry_nbig + ex_nbig] = b;
+                }
             }
+            ex_all += nt;
+            ex_big += big ? nt : 0u;
+            ex_nbig += big ? 1u : 0u;
+            ex_grp += ng;
         }
         carry_all += tot_all;
         carry_big += tot_big;

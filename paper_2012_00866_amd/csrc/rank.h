@@ -7,20 +7,23 @@
 namespace husky {
 
 // ------------------------------------------------------------------ tile ranking
-// Ranks the ITEMS digits (< 2^BITS) of every thread of one tile.  Digits sit
-// in "wave-striped" order: item k of lane l of wave w is tile position
+// Ranks the ITEMS digits (< 2^BITS) of every thread of one tile of a
+// workgroup of NW wavefronts (NW * 64 >= 2^BITS threads).  Digits sit in
+// "wave-striped" order: item k of lane l of wave w is tile position
 // w*64*ITEMS + k*64 + l; positions >= nvalid are padding and rank last.  On
 // return pos[k] is the item's position in the digit-sorted tile (stable in
 // tile position) and, for tid < R, *bin_count holds the number of valid items
-// with digit tid and s_binstart[tid] its first position.
-template <int BITS, int ITEMS>
+// with digit tid and s_binstart[tid] its first position.  s_whist: NW * R
+// words; s_scan: NW words.
+template <int BITS, int ITEMS, int NW = NWAVES>
 __device__ __forceinline__ void rank_digits(uint32_t (&dig)[ITEMS], uint32_t nvalid,
                                             uint32_t (&pos)[ITEMS], uint32_t* s_whist,
                                             uint32_t* s_binstart, uint32_t* s_scan,
                                             uint32_t* bin_count) {
     constexpr int R = 1 << BITS;
+    constexpr uint32_t NT = NW * WAVE;
     const uint32_t tid = threadIdx.x, w = tid / WAVE, lane = lane_id();
-    for (uint32_t i = tid; i < (uint32_t)(NWAVES * R); i += BLOCK) s_whist[i] = 0;
+    for (uint32_t i = tid; i < (uint32_t)(NW * R); i += NT) s_whist[i] = 0;
     __syncthreads();
     // Each wavefront owns one histogram row.  Within an iteration every lane
     // reads its digit's count before the one lane per digit updates it; LDS
@@ -57,17 +60,17 @@ __device__ __forceinline__ void rank_digits(uint32_t (&dig)[ITEMS], uint32_t nva
     uint32_t tot = 0;
     if (tid < (uint32_t)R) {
 #pragma unroll
-        for (int ww = 0; ww < NWAVES; ++ww) {
+        for (int ww = 0; ww < NW; ++ww) {
             const uint32_t c = s_whist[ww * R + tid];
             s_whist[ww * R + tid] = tot;
             tot += c;
         }
     }
     uint32_t all;
-    const uint32_t ex = block_exclusive_sum(tid < (uint32_t)R ? tot : 0u, s_scan, &all);
+    const uint32_t ex = block_exclusive_sum<NW>(tid < (uint32_t)R ? tot : 0u, s_scan, &all);
     if (tid < (uint32_t)R) {
         s_binstart[tid] = ex;
-        const uint32_t pad = (uint32_t)(BLOCK * ITEMS) - nvalid;
+        const uint32_t pad = NT * ITEMS - nvalid;
         *bin_count = (tid == (uint32_t)(R - 1)) ? tot - pad : tot;
     }
     __syncthreads();
