@@ -33,7 +33,7 @@ constexpr uint32_t LEARN_MAX_BLOCKS = 256;
 struct Layout {
     size_t status, counters, codes_a, codes_b, idx_b, key0, segs, bigs, korand, binstart, cnt, gtot,
         tile_counts, run_start, run_end, small, medium, large_a, large_b, bid, bseg, k0a, k0b, scan,
-        biglist, lpartial, lgrad, ltmax, total;
+        biglist, classes, lpartial, lgrad, ltmax, total;
     uint32_t seg_cap, big_cap, tile_cap, big_tile_cap, group_cap, run_cap, small_cap, medium_cap,
         large_cap;
 };
@@ -86,6 +86,7 @@ Layout make_layout(uint64_t n, uint64_t n_segs, bool learned = false) {
         L.k0b = take(n * 8);
         L.scan = take((size_t)LEARNED_BUCKETS * sizeof(RunItem));     // buckets Step 3 scans
         L.biglist = take((size_t)LEARNED_BUCKETS * sizeof(RunItem));  // buckets the radix passes sort
+        L.classes = take((size_t)4 * LEARNED_BUCKETS * sizeof(RunItem));  // LDS size classes
         L.lpartial = take(learned_partial_bytes(LEARN_MAX_BLOCKS));
         L.lgrad = take(((size_t)learned_nparam() + 1) * 4 + 256);
         L.ltmax = take((size_t)learned_lut_tiles() * 4);
@@ -100,7 +101,8 @@ Layout make_layout(uint64_t n, uint64_t n_segs, bool learned = false) {
 // tiles of all items
 constexpr int CNT_RUNS = 64, CNT_SMALL = 80, CNT_MEDIUM = 81, CNT_LARGE_A = 84, CNT_LARGE_B = 88,
               CNT_SCAN = 96,  // learned form: buckets on the run-detection list
-              CNT_BIG = 97;   // learned form: buckets for the multi-tile radix passes
+              CNT_BIG = 97,   // learned form: buckets for the multi-tile radix passes
+              CNT_CLASS = 98; // learned form: buckets per LDS size class (four)
 
 struct Ctx {
     Layout L;
@@ -534,15 +536,18 @@ husky_status husky_sort_learned(husky_coder coder, const void* elems, const uint
     RunItem* biglist = c.at<RunItem>(L.biglist);
     uint32_t* scan_count = c.counters + CNT_SCAN;
     uint32_t* big_count = c.counters + CNT_BIG;
-    HUSKY_TRY(zero_u32(scan_count, 2, s));
+    uint32_t* class_count = c.counters + CNT_CLASS;
+    RunItem* const classes[4] = {c.at<RunItem>(L.classes), c.at<RunItem>(L.classes) + LEARNED_BUCKETS,
+                                 c.at<RunItem>(L.classes) + 2 * LEARNED_BUCKETS,
+                                 c.at<RunItem>(L.classes) + 3 * LEARNED_BUCKETS};
+    HUSKY_TRY(zero_u32(scan_count, 6, s));  // scan, big, four classes
     HUSKY_TRY(learned_bucket_bounds(bid_a, nn, bseg, &c.status->overflow_buckets, biglist, big_count,
-                                    scan, scan_count, s));
+                                    scan, scan_count, classes, class_count, s));
     // buckets of at most LEARNED_LDS_CAP keys, in LDS: by code, then by the
     // first refinement key inside runs of equal codes; their codes become tie
     // keys, and those with a group still tied join the scan list
     const uint32_t B = LEARNED_BUCKETS;
-    HUSKY_TRY(radix_segments_from_offsets(bseg, B, c.rad, tn.rc, s));
-    HUSKY_TRY(learned_bucket_refine(coder, codes, perm, k0a, c.rad, B, scan, scan_count, s));
+    HUSKY_TRY(learned_bucket_refine(coder, codes, perm, k0a, classes, class_count, scan, scan_count, s));
     // larger buckets: the multi-tile radix passes on the code
     HUSKY_TRY(radix_segments_from_items(biglist, big_count, B, c.rad, tn.rc, s));
     const int end_bit = coder == HUSKY_CODER_ASCII7 ? 63 : 64;

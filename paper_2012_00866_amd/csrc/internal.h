@@ -170,11 +170,12 @@ hipError_t learned_bucket_pass(int pass, const uint64_t* ks, const uint32_t* vs,
                                uint64_t* k0d, uint32_t n, uint32_t* cnt, uint32_t* gtot,
                                uint32_t* binstart, hipStream_t s);
 hipError_t learned_bucket_refine(int coder, uint64_t* codes, uint32_t* perm, const uint64_t* k0,
-                                 const RadixScratch& sc, uint32_t max_segs, RunItem* scan_list,
-                                 uint32_t* scan_count, hipStream_t s);
+                                 RunItem* const lists[4], const uint32_t* counts,
+                                 RunItem* scan_list, uint32_t* scan_count, hipStream_t s);
 hipError_t learned_bucket_bounds(const uint16_t* bid, uint32_t n, uint64_t* seg, uint32_t* overflow,
                                  RunItem* big_list, uint32_t* big_count, RunItem* scan_list,
-                                 uint32_t* scan_count, hipStream_t s);
+                                 uint32_t* scan_count, RunItem* const lists[4],
+                                 uint32_t* class_count, hipStream_t s);
 
 // Chunk geometry of the refinement keys.
 constexpr int ascii_m = 9, ascii_chunk = 7;

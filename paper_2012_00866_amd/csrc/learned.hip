@@ -909,20 +909,50 @@ __global__ void k_learned_finish(LearnedHeader* hdr, const float* __restrict__ l
 // Buckets larger than the LDS sort's capacity go to the multi-tile radix
 // passes (overflow): their number and their keys; each one joins the list the
 // radix passes sort and the list of segments Step 3's run detection scans.
-__global__ void k_overflow_stats(const uint64_t* __restrict__ seg, uint32_t B, uint32_t cap,
-                                 uint32_t* __restrict__ out, RunItem* __restrict__ big_list,
-                                 uint32_t* __restrict__ big_count, RunItem* __restrict__ scan_list,
-                                 uint32_t* __restrict__ scan_count) {
+// Every other bucket of two or more keys joins the list of its LDS size
+// class (<= 3,072, <= 4,096, <= 6,144, <= 8,192 keys); one atomic per
+// wavefront and list.
+__device__ __forceinline__ void wave_append(bool mine, const RunItem& it, RunItem* list,
+                                            uint32_t* count) {
+    const uint64_t m = ballot(mine);
+    if (!m) return;
+    const uint32_t lane = lane_id(), leader = (uint32_t)__ffsll((unsigned long long)m) - 1u;
+    uint32_t base = 0;
+    if (lane == leader) base = atomicAdd(count, (uint32_t)__popcll(m));
+    base = readlane(base, (int)leader);
+    if (mine) list[base + mbcnt(m)] = it;
+}
+
+__global__ __launch_bounds__(256) void k_bucket_classes(const uint64_t* __restrict__ seg, uint32_t B,
+                                                        uint32_t* __restrict__ out,
+                                                        RunItem* __restrict__ big_list,
+                                                        uint32_t* __restrict__ big_count,
+                                                        RunItem* __restrict__ scan_list,
+                                                        uint32_t* __restrict__ scan_count,
+                                                        RunItem* l0, RunItem* l1, RunItem* l2,
+                                                        RunItem* l3, uint32_t* __restrict__ class_count) {
     uint32_t nb = 0, nk = 0;
-    for (uint32_t b = blockIdx.x * 256 + threadIdx.x; b < B; b += gridDim.x * 256) {
-        const uint32_t len = (uint32_t)(seg[b + 1] - seg[b]);
-        if (len > cap) {
+    const uint32_t c1 = BLOCK * 12u, c2 = BLOCK * 16u, c3 = 2 * BLOCK * 12u;
+    for (uint32_t b0 = blockIdx.x * 256; b0 < B; b0 += gridDim.x * 256) {  // uniform trip count
+        const uint32_t b = b0 + threadIdx.x;
+        uint32_t len = 0, st = 0;
+        if (b < B) {
+            st = (uint32_t)seg[b];
+            len = (uint32_t)(seg[b + 1] - seg[b]);
+        }
+        const RunItem it{st, len, 0u, 0u};
+        const bool big = len > LEARNED_LDS_CAP;
+        if (big) {
             ++nb;
             nk += len;
-            const RunItem it{(uint32_t)seg[b], len, 0u, 0u};
-            big_list[atomicAdd(big_count, 1u)] = it;
-            scan_list[atomicAdd(scan_count, 1u)] = it;
         }
+        wave_append(big, it, big_list, big_count);
+        wave_append(big, it, scan_list, scan_count);
+        const bool lds = len >= 2 && !big;
+        wave_append(lds && len <= c1, it, l0, class_count + 0);
+        wave_append(lds && len > c1 && len <= c2, it, l1, class_count + 1);
+        wave_append(lds && len > c2 && len <= c3, it, l2, class_count + 2);
+        wave_append(lds && len > c3, it, l3, class_count + 3);
     }
     if (nb) {
         atomicAdd(&out[0], nb);
@@ -988,9 +1018,9 @@ template <int CODER, int ITEMS, int NW>
 __global__ __launch_bounds__(NW * WAVE) void k_bucket_refine(uint64_t* __restrict__ codes,
                                                          uint32_t* __restrict__ perm,
                                                          const uint64_t* __restrict__ k0,
-                                                         const SegDesc* __restrict__ segs,
-                                                         const uint32_t* __restrict__ counters,
-                                                         uint32_t lmin, uint32_t lmax, int code_bits,
+                                                         const RunItem* __restrict__ list,
+                                                         const uint32_t* __restrict__ list_count,
+                                                         int code_bits,
                                                          RunItem* __restrict__ scan_list,
                                                          uint32_t* __restrict__ scan_count) {
     constexpr uint32_t TILE = NW * WAVE * ITEMS;
@@ -1002,10 +1032,10 @@ __global__ __launch_bounds__(NW * WAVE) void k_bucket_refine(uint64_t* __restric
     __shared__ uint32_t s_scan[NW];
     __shared__ uint64_t s_or[NW], s_and[NW];
     uint32_t* s_k32 = reinterpret_cast<uint32_t*>(s_k);  // scratch while keys sit in registers
-    const uint32_t sidx = blockIdx.x;
-    if (sidx >= counters[C_NUM_SEGS]) return;
-    const SegDesc d = segs[sidx];
-    if (d.len < 2 || d.len <= lmin || d.len > lmax || d.len > TILE) return;
+    const uint32_t nlist = *list_count;
+    for (uint32_t it = blockIdx.x; it < nlist; it += gridDim.x) {
+    const RunItem d = list[it];
+    if (d.len < 2 || d.len > TILE) continue;  // never listed so; uniform per workgroup
     const uint32_t nvalid = d.len, start = d.start;
     const uint32_t w = threadIdx.x / WAVE, lane = lane_id();
     auto posof = [&](int i) { return w * WAVE * ITEMS + i * WAVE + lane; };
@@ -1140,31 +1170,37 @@ __global__ __launch_bounds__(NW * WAVE) void k_bucket_refine(uint64_t* __restric
             codes[start + p] = (uint64_t)start + t[i];
         }
     }
+    __syncthreads();  // LDS is reused by the next bucket
+    }
 }
 
 hipError_t learned_bucket_refine(int coder, uint64_t* codes, uint32_t* perm, const uint64_t* k0,
-                                 const RadixScratch& sc, uint32_t max_segs, RunItem* scan_list,
-                                 uint32_t* scan_count, hipStream_t s) {
-    if (!max_segs) return hipSuccess;
+                                 RunItem* const lists[4], const uint32_t* counts,
+                                 RunItem* scan_list, uint32_t* scan_count, hipStream_t s) {
     ProfScope ps(P_TILE_SORT, s);
-    // four size classes; a smaller one needs fewer registers and less LDS, so
-    // more workgroups share a CU, and wastes fewer padding slots
-    const SegDesc* sg = sc.segs;
-    const uint32_t* ct = sc.counters;
-    const uint32_t c1 = BLOCK * 12u, c2 = BLOCK * 16u, c3 = 2 * BLOCK * 12u, c4 = LEARNED_LDS_CAP;
-#define HUSKY_RF(C, I, NW, LO, HI, BITS)                                                          \
-    hipLaunchKernelGGL((k_bucket_refine<C, I, NW>), dim3(max_segs), dim3(NW * WAVE), 0, s, codes, \
-                       perm, k0, sg, ct, LO, HI, BITS, scan_list, scan_count)
+    // four size classes (bucket lists built by k_bucket_classes); a smaller
+    // class needs fewer registers and less LDS, so more workgroups share a
+    // CU, and wastes fewer padding slots; persistent workgroups walk a list
+    uint32_t cus = 256;
+    {
+        int dev = 0, v = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0)
+            cus = (uint32_t)v;
+    }
+#define HUSKY_RF(C, I, NW, L, PER_CU, BITS)                                                         \
+    hipLaunchKernelGGL((k_bucket_refine<C, I, NW>), dim3(cus * PER_CU), dim3(NW * WAVE), 0, s, codes, \
+                       perm, k0, (const RunItem*)lists[L], counts + L, BITS, scan_list, scan_count)
     if (coder == 0) {
-        HUSKY_RF(0, 12, 4, 0u, c1, 63);
-        HUSKY_RF(0, 16, 4, c1, c2, 63);
-        HUSKY_RF(0, 12, 8, c2, c3, 63);
-        HUSKY_RF(0, 16, 8, c3, c4, 63);
+        HUSKY_RF(0, 12, 4, 0, 4, 63);
+        HUSKY_RF(0, 16, 4, 1, 3, 63);
+        HUSKY_RF(0, 12, 8, 2, 2, 63);
+        HUSKY_RF(0, 16, 8, 3, 1, 63);
     } else {
-        HUSKY_RF(1, 12, 4, 0u, c1, 64);
-        HUSKY_RF(1, 16, 4, c1, c2, 64);
-        HUSKY_RF(1, 12, 8, c2, c3, 64);
-        HUSKY_RF(1, 16, 8, c3, c4, 64);
+        HUSKY_RF(1, 12, 4, 0, 4, 64);
+        HUSKY_RF(1, 16, 4, 1, 3, 64);
+        HUSKY_RF(1, 12, 8, 2, 2, 64);
+        HUSKY_RF(1, 16, 8, 3, 1, 64);
     }
 #undef HUSKY_RF
     return hipGetLastError();
@@ -1354,13 +1390,14 @@ uint32_t learned_pass_tiles(uint32_t n) { return (n + BLOCK * 16 - 1) / (BLOCK *
 
 hipError_t learned_bucket_bounds(const uint16_t* bid, uint32_t n, uint64_t* seg, uint32_t* overflow,
                                  RunItem* big_list, uint32_t* big_count, RunItem* scan_list,
-                                 uint32_t* scan_count, hipStream_t s) {
+                                 uint32_t* scan_count, RunItem* const lists[4],
+                                 uint32_t* class_count, hipStream_t s) {
     ProfScope ps(P_BUCKET_BOUNDS, s);
     hipLaunchKernelGGL(k_bucket_bounds, dim3(grid_for((uint64_t)n + 1)), dim3(256), 0, s, bid, n,
                        (uint32_t)LEARNED_BUCKETS, seg);
-    hipLaunchKernelGGL(k_overflow_stats, dim3(256), dim3(256), 0, s, (const uint64_t*)seg,
-                       (uint32_t)LEARNED_BUCKETS, LEARNED_LDS_CAP, overflow, big_list, big_count,
-                       scan_list, scan_count);
+    hipLaunchKernelGGL(k_bucket_classes, dim3(256), dim3(256), 0, s, (const uint64_t*)seg,
+                       (uint32_t)LEARNED_BUCKETS, overflow, big_list, big_count, scan_list, scan_count,
+                       lists[0], lists[1], lists[2], lists[3], class_count);
     return hipGetLastError();
 }
 
