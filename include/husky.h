@@ -256,9 +256,9 @@ typedef enum {
 typedef struct {
     double sample_frac; /* fraction of the strings sampled, (0, 1]; default 0.01 */
     uint64_t seed;      /* sample and initialisation seed; default 1 */
-    uint32_t epochs;    /* default (0): enough for at least 400 Adam steps, at most 200 */
-    uint32_t batch;     /* samples per Adam step; default 4096 */
-    float lr;           /* Adam step size; default 0.01 */
+    uint32_t epochs;    /* default (0): enough for at least 150 Adam steps, at most 200 */
+    uint32_t batch;     /* samples per Adam step; default 65536 */
+    float lr;           /* Adam step size; default 0.02 */
     uint32_t mode;      /* husky_learned_mode */
     uint32_t flags;     /* HUSKY_LEARNED_NO_DENSE */
     uint32_t reserved;

@@ -428,7 +428,7 @@ husky_status husky_learned_fit(husky_coder coder, const void* elems, const uint6
     if (st != HUSKY_OK) return st;
     if (n == 0) return HUSKY_ERR_ARG;
     if ((st = check_model(model, model_bytes)) != HUSKY_OK) return st;
-    husky_learned_params p{0.01, 1, 0, 4096, 0.01f, HUSKY_LEARNED_MONOTONE, 0, 0};
+    husky_learned_params p{0.01, 1, 0, 65536, 0.02f, HUSKY_LEARNED_MONOTONE, 0, 0};
     if (params) {
         if (params->sample_frac != 0.0) p.sample_frac = params->sample_frac;
         if (params->seed) p.seed = params->seed;
@@ -484,7 +484,7 @@ husky_status husky_learned_fit(husky_coder coder, const void* elems, const uint6
     // epochs 0: as many as give at least MIN_STEPS Adam steps (at most 200)
     uint32_t epochs = p.epochs;
     if (!epochs) {
-        constexpr uint32_t MIN_STEPS = 400;
+        constexpr uint32_t MIN_STEPS = 150;
         const uint32_t per_epoch = std::max(1u, (count + p.batch - 1) / p.batch);
         epochs = std::min(200u, std::max(1u, (MIN_STEPS + per_epoch - 1) / per_epoch));
     }
