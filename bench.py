@@ -57,23 +57,54 @@ def _src_sha(path: str) -> str:
     return hashlib.sha256("".join(parts).encode()).hexdigest()[:16]
 
 
+def _read_summary(path: str) -> dict:
+    kv = {}
+    if os.path.exists(path):
+        with open(path) as f:
+            for line in f:
+                if "=" in line and not line.lstrip().startswith("#"):
+                    k, v = line.split("=", 1)
+                    kv[k.strip()] = v.strip()
+    return kv
+
+
 def _traffic_per_launch():
     """HBM bytes per scatter-pass launch from the committed counter summary, or None.
 
-    Only used while radix.hip is byte-identical to the source the counters
+    Only used while the kernel's source is identical to the one the counters
     were taken from."""
-    if not os.path.exists(COUNTERS_FILE):
-        return None
-    kv = {}
-    with open(COUNTERS_FILE) as f:
-        for line in f:
-            if "=" in line and not line.lstrip().startswith("#"):
-                k, v = line.split("=", 1)
-                kv[k.strip()] = v.strip()
+    kv = _read_summary(COUNTERS_FILE)
     if kv.get("radix_src_sha") != _src_sha(RADIX_SRC):
         return None
     try:
         return float(kv["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+BUCKET_COUNTERS_FILE = os.path.join(ROOT, "profiles", "learned_bucket_pass_config5_counters.txt")
+LEARNED_SRC = os.path.join(ROOT, "paper_2012_00866_amd", "csrc", "learned.hip")
+
+
+def _bucket_src_sha() -> str:
+    """Hash of the bucket pass's own source: rank_digits (rank.h) and k_bscatter."""
+    with open(os.path.join(os.path.dirname(LEARNED_SRC), "rank.h")) as f:
+        rank = f.read()
+    with open(LEARNED_SRC) as f:
+        src = f.read()
+    parts = [_function_text(rank, "__device__ __forceinline__ void rank_digits("),
+             _function_text(src, "__global__ __launch_bounds__(BLOCK) void k_bscatter(")]
+    return hashlib.sha256("".join(parts).encode()).hexdigest()[:16]
+
+
+def _bucket_traffic_per_string():
+    """HBM bytes per string for the pair of bucket passes, from the committed
+    counter summary, or None once the kernel's source has changed."""
+    kv = _read_summary(BUCKET_COUNTERS_FILE)
+    if kv.get("bucket_src_sha") != _bucket_src_sha():
+        return None
+    try:
+        return float(kv["hbm_bytes_per_string_both_passes"])
     except (KeyError, ValueError):
         return None
 
@@ -387,6 +418,11 @@ def bench_learned(args):
     prof = husky.profile_end()
     k_learned = _kernels(prof, steps)
     ms_bs, nb = prof["learned_bucket_scatter"]
+    # roofline of the bucket pass: 42 algorithmic bytes per string per pass
+    # (84 for the pair), HIP-event durations on the library's stream
+    bs_avg_ms = ms_bs / max(nb, 1)
+    bs_achieved = 42.0 * n / (bs_avg_ms / 1e3) / 1e9 if nb else 0.0
+    tps = _bucket_traffic_per_string()
     out = {
         "metric": "Mstrings/s sorted (bit-exact), learned-CDF form vs plain",
         "value": round(n / (ms_learned / 1e3) / 1e6, 3),
@@ -410,7 +446,18 @@ def bench_learned(args):
         # the two bucket passes move the 8-byte code, the 2-byte id and the 8-byte
         # first refinement key; the index is written by both and read by the second:
         # 40 + 44 bytes per string for the pair of passes
-        "bucket_scatter_gbs": round(42.0 * n * nb / (ms_bs / 1e3) / 1e9, 1) if nb else None,
+        "roofline": {
+            "kernel": "learned bucket pass (k_bscatter)",
+            "bound": "hbm",
+            "achieved": round(bs_achieved, 1),
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(bs_achieved / HBM_PEAK_GBS, 4),
+            "traffic": round(tps * n / 2) if tps else None,
+            "algorithmic_bytes_per_launch": 42.0 * n,
+            "avg_launch_ms": round(bs_avg_ms, 4),
+            "launches_per_step": nb / steps,
+        },
         "kernels_learned": k_learned,
         "kernels_plain": k_plain,
     }
