@@ -313,3 +313,34 @@ def test_learned_long_shared_prefixes(gpu_lib, coder):
     b = from_strings(out, coder)
     st = _learned_equals_oracle(gpu_lib, b, sample_frac=0.05)
     say(coder, "shared prefixes: runs visited", st["runs_fixed"], "rounds", st["large_rounds"])
+
+
+def test_learned_sort_graph_capture_replay(gpu_lib):
+    # with a fixed round count the learned sort never synchronizes, so it can
+    # be captured into a HIP graph; every replay must give the eager result
+    import torch
+
+    b = config5(n=300_000, seed=23)
+    e, o = gpu_lib.to_device(b)
+    model, ws = _fit(gpu_lib, b, e, o, sample_frac=0.05)
+    max_len = int(np.diff(b.offsets).max())
+    t = gpu_lib.make_tuning(max_rounds=gpu_lib.rounds_for(max_len))
+    perm = torch.empty(b.n, dtype=torch.int32, device="cuda")
+    eager = _u32(gpu_lib.sort_learned(e, o, model, "ascii7", tuning=t, ws=ws, perm=perm)).copy()
+    np.testing.assert_array_equal(eager, oracle.sort(b)[0])
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):  # warm-up on the capture stream
+        gpu_lib.sort_learned(e, o, model, "ascii7", tuning=t, ws=ws, perm=perm, check_status=False)
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        gpu_lib.sort_learned(e, o, model, "ascii7", tuning=t, ws=ws, perm=perm, check_status=False)
+    for rep in range(3):
+        perm.fill_(-1)  # eager work between replays
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(_u32(perm), eager, err_msg=f"replay {rep}")
+        assert gpu_lib.read_status(ws)["unresolved"] == 0
