@@ -90,9 +90,12 @@ typedef struct {
  *   t_small    -- equal-code runs of at most this many strings are sorted by
  *                 one wavefront (2..64);
  *   t_medium   -- runs of at most this many by one workgroup in LDS
- *                 (t_small < t_medium <= 4096, default 1024); longer runs
- *                 device-wide (a run of at most one radix tile is then
- *                 sorted in LDS by the segmented radix sort);
+ *                 (t_small < t_medium <= 4096, default 1024) with a bitonic
+ *                 sort per round; runs of up to 8,192 by one workgroup that
+ *                 keeps the run in LDS for all its rounds (a radix sort per
+ *                 round); longer runs device-wide (a group of at most one
+ *                 radix tile is then sorted in LDS by the segmented radix
+ *                 sort);
  *   max_rounds -- 0: the device-wide fix-up reads its work counts back to
  *                 the host once per refinement round (adaptive).  k > 0: it
  *                 runs exactly k rounds sized from host bounds, with no
@@ -195,7 +198,8 @@ husky_status husky_check_perm(husky_coder coder, const void* elems, const uint64
  * fix-up, 9 device-wide refinement keys, 10 segment setup, 11 radix scatter
  * pass of the device-wide fix-up (class 3 counts only the sort of the
  * codes), 12 learned bucket scatter pass, 13 learned bucket bounds (the
- * learned form's bucket ids are computed by the encode kernel, class 0).
+ * learned form's bucket ids are computed by the encode kernel, class 0),
+ * 14 LDS-resident fix-up of runs longer than t_medium and at most 8,192.
  * Not for use during graph capture.
  * Returns HUSKY_OK or HUSKY_ERR_HIP. */
 void husky_profile_begin(void);

@@ -32,7 +32,7 @@ constexpr uint32_t LEARN_MAX_BLOCKS = 256;
 // husky_learned_fit).
 struct Layout {
     size_t status, counters, codes_a, codes_b, idx_b, key0, segs, bigs, korand, binstart, cnt, gtot,
-        tile_counts, run_start, run_end, small, medium, large_a, large_b, bid, bseg, k0a, k0b, scan,
+        tile_counts, run_start, run_end, small, medium, large_a, large_b, lds, bid, bseg, k0a, k0b, scan,
         biglist, classes, lpartial, lgrad, ltmax, total;
     uint32_t seg_cap, big_cap, tile_cap, big_tile_cap, group_cap, run_cap, small_cap, medium_cap,
         large_cap;
@@ -79,6 +79,8 @@ Layout make_layout(uint64_t n, uint64_t n_segs, bool learned = false) {
     L.medium = take((size_t)L.medium_cap * sizeof(RunItem));
     L.large_a = take((size_t)L.large_cap * sizeof(RunItem));
     L.large_b = take((size_t)L.large_cap * sizeof(RunItem));
+    // LDS-tier runs are disjoint and longer than t_medium >= MIN_T_MEDIUM
+    L.lds = take((size_t)L.large_cap * sizeof(RunItem));
     if (learned) {
         L.bid = take(n * 4);
         L.bseg = take(((size_t)LEARNED_BUCKETS + 1) * 8);
@@ -96,10 +98,11 @@ Layout make_layout(uint64_t n, uint64_t n_segs, bool learned = false) {
 }
 
 // counters region: [0, 64) radix counters; [64, 80) run counters;
-// [80] small count, [81] medium count; [84, 88) and [88, 92) the two
-// device-wide lists: item count, items longer than one tile, their tiles,
-// tiles of all items
-constexpr int CNT_RUNS = 64, CNT_SMALL = 80, CNT_MEDIUM = 81, CNT_LARGE_A = 84, CNT_LARGE_B = 88,
+// [80] small count, [81] medium count, [82] LDS-tier count; [84, 88) and
+// [88, 92) the two device-wide lists: item count, items longer than one
+// tile, their tiles, tiles of all items
+constexpr int CNT_RUNS = 64, CNT_SMALL = 80, CNT_MEDIUM = 81, CNT_LDS = 82, CNT_LARGE_A = 84,
+              CNT_LARGE_B = 88,
               CNT_SCAN = 96,  // learned form: buckets on the run-detection list
               CNT_BIG = 97,   // learned form: buckets for the multi-tile radix passes
               CNT_CLASS = 98; // learned form: buckets per LDS size class (four)
@@ -145,12 +148,16 @@ Ctx make_ctx(void* ws, uint64_t n, uint64_t n_segs, bool learned = false) {
     c.tiers.small = c.at<RunItem>(c.L.small);
     c.tiers.medium = c.at<RunItem>(c.L.medium);
     c.tiers.large = c.at<RunItem>(c.L.large_a);
+    c.tiers.lds = c.at<RunItem>(c.L.lds);
     c.tiers.small_count = c.counters + CNT_SMALL;
     c.tiers.medium_count = c.counters + CNT_MEDIUM;
     c.tiers.large_count = c.counters + CNT_LARGE_A;
+    c.tiers.lds_count = c.counters + CNT_LDS;
     c.tiers.small_cap = c.L.small_cap;
     c.tiers.medium_cap = c.L.medium_cap;
     c.tiers.large_cap = c.L.large_cap;
+    c.tiers.lds_cap = c.L.large_cap;
+    c.tiers.lds_max = 0;
     return c;
 }
 
@@ -217,6 +224,7 @@ husky_status run_fixup(Ctx& c, const Tune& tn, int coder, const void* elems,
                        const uint64_t* codes, uint64_t* keys, uint64_t* keys_alt, uint32_t* idx,
                        hipStream_t s) {
     HUSKY_TRY(zero_u32(c.counters + CNT_SMALL, 12, s));
+    c.tiers.lds_max = tn.t_medium < LDS_RUN_MAX ? LDS_RUN_MAX : 0u;
     const uint32_t tb = tiles_bound(n, n_segs, tn.rc);
     HUSKY_TRY(find_runs(codes, c.rad, tn.rc, tb, coder, false, nullptr, c.runs, c.tiers,
                         tn.t_small, tn.t_medium, s));
@@ -274,6 +282,7 @@ husky_status run_fixup(Ctx& c, const Tune& tn, int coder, const void* elems,
         hipLaunchKernelGGL(k_copy_u32, dim3(1), dim3(1), 0, s, &c.status->unresolved, cur_cnt);
         HUSKY_TRY(hipGetLastError());
     }
+    HUSKY_TRY(fixup_lds(fa, c.tiers, tn.t_medium, s));
     HUSKY_TRY(fixup_medium(fa, c.tiers, tn.t_medium, s));
     HUSKY_TRY(fixup_small(fa, c.tiers, tn.t_small, s));
     hipLaunchKernelGGL(k_set_u32, dim3(1), dim3(1), 0, s, &c.status->large_rounds, rounds);

@@ -22,12 +22,18 @@
 //   small  (<= t_small, <= 64)  one wavefront per run, rank by counting over
 //                               the wavefront's lanes;
 //   medium (<= t_medium)        one workgroup per run, bitonic sort in LDS;
+//   LDS    (<= 8192)            one workgroup per run holding it in LDS for
+//                               every round, each round a stable LSD radix
+//                               sort of (group, key) over the digits that vary;
 //   large                       device-wide: refinement keys for every member
 //                               (k_large_keys), a segmented radix sort, and
 //                               run detection on the keys for the next round.
 
+#include <algorithm>
+
 #include "common.h"
 #include "internal.h"
+#include "rank.h"
 
 namespace husky {
 
@@ -265,6 +271,253 @@ __global__ __launch_bounds__(BLOCK) void k_fix_medium(const RunItem* __restrict_
     }
 }
 
+// ------------------------------------------------------------------ LDS tier
+// One size class of the LDS list: lmin < len <= NW * 64 * ITEMS, one
+// workgroup per run.  Per member: its key and one word
+//     sr = slot | group start << 16 | still tied << 31
+// (slot: the member's place in the run when the kernel started; group start:
+// the position of its group's first member).  Every round computes the keys
+// of the tied members (the others carry 0), sorts them by (group start, key)
+// with stable digit passes over the digits that vary, and splits groups where
+// keys differ or stop continuing.  Members in singleton groups never move, so
+// a round with at most one tied member per thread handles only the tied ones:
+// they are compacted in position order (the tied positions are exactly the
+// union of the tied groups, in group order), each finds its rank inside its
+// group by counting, and moves to the tied position of that rank.  The order
+// reached is the one the device-wide rounds reach.
+template <int CODER, int ITEMS, int NW>
+__global__ __launch_bounds__(NW * WAVE) void k_fix_lds(const RunItem* __restrict__ items,
+                                                   const uint32_t* __restrict__ count, uint32_t cap,
+                                                   const uint8_t* __restrict__ bytes,
+                                                   const uint64_t* __restrict__ offsets, uint32_t n,
+                                                   uint32_t* __restrict__ idx,
+                                                   const uint64_t* __restrict__ key0,
+                                                   uint32_t lmin) {
+    constexpr uint32_t NT = NW * WAVE;
+    constexpr uint32_t TILE = NT * ITEMS;
+    static_assert(TILE <= 32768, "slots and group starts fit 15 bits");
+    constexpr uint32_t TIED = 1u << 31;
+    __shared__ uint64_t s_k[TILE];
+    __shared__ uint32_t s_sr[TILE];
+    __shared__ uint64_t s_ck[NT];   // sparse rounds: compacted keys
+    __shared__ uint32_t s_csr[NT];  // ... their sr words
+    __shared__ uint32_t s_cpos[NT]; // ... and the positions they came from
+    __shared__ uint32_t s_whist[NW * 256];
+    __shared__ uint32_t s_binstart[256];
+    __shared__ uint32_t s_scan[NW];
+    __shared__ uint64_t s_or[NW], s_and[NW];
+    __shared__ uint32_t s_gor[NW], s_gand[NW], s_wt[NW];
+    uint32_t* s_k32 = reinterpret_cast<uint32_t*>(s_k);  // scratch while keys sit in registers
+    const uint64_t total_bytes = offsets[n] * (CODER == 0 ? 1u : 2u);
+    const uint32_t n_items = min(*count, cap);
+    const uint32_t tid = threadIdx.x, w = tid / WAVE, lane = lane_id();
+    auto posof = [&](int i) { return w * WAVE * ITEMS + i * WAVE + lane; };
+    auto key_of = [&](uint32_t m, uint32_t round) -> uint64_t {
+        if (round == 0 && key0) return key0[m];
+        const uint64_t o = offsets[m];
+        return chunk_key<CODER>(bytes, total_bytes, o, offsets[m + 1] - o, round);
+    };
+    // block-wide OR / AND of the keys and group starts each thread passes
+    // (o = 0, a = ~0, g = 0, ga = ~0 for none); returns key bits and
+    // group-start bits that differ among them
+    auto varying = [&](uint64_t o, uint64_t a, uint32_t g, uint32_t ga, uint32_t* gvary) -> uint64_t {
+#pragma unroll
+        for (int d = 32; d >= 1; d >>= 1) {
+            o |= (uint64_t)__shfl_xor((unsigned long long)o, d, WAVE);
+            a &= (uint64_t)__shfl_xor((unsigned long long)a, d, WAVE);
+            g |= __shfl_xor(g, d, WAVE);
+            ga &= __shfl_xor(ga, d, WAVE);
+        }
+        if (lane == 0) {
+            s_or[w] = o;
+            s_and[w] = a;
+            s_gor[w] = g;
+            s_gand[w] = ga;
+        }
+        __syncthreads();
+        uint64_t oo = 0, aa = ~0ull;
+        uint32_t gg = 0, gga = ~0u;
+#pragma unroll
+        for (int ww = 0; ww < NW; ++ww) {
+            oo |= s_or[ww];
+            aa &= s_and[ww];
+            gg |= s_gor[ww];
+            gga &= s_gand[ww];
+        }
+        __syncthreads();
+        *gvary = gg ^ gga;
+        return oo ^ aa;
+    };
+    for (uint32_t it = blockIdx.x; it < n_items; it += gridDim.x) {
+        const RunItem r = items[it];
+        if (r.len <= lmin || r.len > TILE) continue;  // another class's run; uniform per workgroup
+        const uint32_t nvalid = r.len, start = r.start;
+        uint64_t k[ITEMS];
+        uint32_t sr[ITEMS], dig[ITEMS], pos[ITEMS], t[ITEMS];
+        auto pass = [&]() {
+            uint32_t bc;
+            rank_digits<8, ITEMS, NW>(dig, nvalid, pos, s_whist, s_binstart, s_scan, &bc);
+#pragma unroll
+            for (int i = 0; i < ITEMS; ++i) {
+                s_k[pos[i]] = k[i];
+                s_sr[pos[i]] = sr[i];
+            }
+            __syncthreads();
+#pragma unroll
+            for (int i = 0; i < ITEMS; ++i) {
+                k[i] = s_k[posof(i)];
+                sr[i] = s_sr[posof(i)];
+            }
+            __syncthreads();
+        };
+#pragma unroll
+        for (int i = 0; i < ITEMS; ++i) sr[i] = posof(i) | (posof(i) < nvalid ? TIED : 0u);
+        for (uint32_t round = r.round;; ++round) {
+            // tied members in position order: ranks inside the wavefront,
+            // then wavefront bases
+            uint32_t crank[ITEMS], wtot = 0;
+#pragma unroll
+            for (int i = 0; i < ITEMS; ++i) {
+                const uint64_t b = ballot((sr[i] & TIED) != 0);
+                crank[i] = wtot + mbcnt(b);
+                wtot += (uint32_t)__popcll(b);
+            }
+            if (lane == 0) s_wt[w] = wtot;
+            __syncthreads();
+            uint32_t wbase = 0, ntied = 0;
+#pragma unroll
+            for (int ww = 0; ww < NW; ++ww) {
+                const uint32_t v = s_wt[ww];
+                wbase += ww < (int)w ? v : 0u;
+                ntied += v;
+            }
+            __syncthreads();
+            if (ntied <= NT) {
+                // sparse round: one tied member per thread
+#pragma unroll
+                for (int i = 0; i < ITEMS; ++i) {
+                    k[i] = 0;
+                    if (sr[i] & TIED) {
+                        s_csr[wbase + crank[i]] = sr[i];
+                        s_cpos[wbase + crank[i]] = posof(i);
+                    }
+                }
+                __syncthreads();
+                // each tied member's place in its group: members with a
+                // smaller key, or an equal key at an earlier position
+                const bool mine = tid < ntied;
+                const uint32_t csr = mine ? s_csr[tid] : 0u;
+                const uint64_t ck = mine ? key_of(idx[start + (csr & 0xFFFFu)], round) : 0ull;
+                if (mine) s_ck[tid] = ck;
+                __syncthreads();
+                if (mine) {
+                    const uint32_t gs = csr & 0x7FFF0000u;
+                    uint32_t g0 = tid;
+                    while (g0 > 0 && (s_csr[g0 - 1] & 0x7FFF0000u) == gs) --g0;
+                    uint32_t rank = g0;
+                    for (uint32_t j = g0; j < ntied && (s_csr[j] & 0x7FFF0000u) == gs; ++j) {
+                        const uint64_t kj = s_ck[j];
+                        rank += (kj < ck || (kj == ck && j < tid)) ? 1u : 0u;
+                    }
+                    const uint32_t p = s_cpos[rank];
+                    s_k[p] = ck;
+                    s_sr[p] = csr;
+                }
+                __syncthreads();
+#pragma unroll
+                for (int i = 0; i < ITEMS; ++i)
+                    if (sr[i] & TIED) {
+                        k[i] = s_k[posof(i)];
+                        sr[i] = s_sr[posof(i)];
+                    }
+                __syncthreads();
+            } else {
+                // dense round: every gather issued before any is used
+                uint32_t m[ITEMS];
+#pragma unroll
+                for (int i = 0; i < ITEMS; ++i) m[i] = idx[start + ((sr[i] & TIED) ? (sr[i] & 0xFFFFu) : 0u)];
+#pragma unroll
+                for (int i = 0; i < ITEMS; ++i) {
+                    const uint64_t v = key_of(m[i], round);
+                    k[i] = (sr[i] & TIED) ? v : 0ull;
+                }
+                uint64_t o = 0, a = ~0ull;
+                uint32_t g = 0;
+#pragma unroll
+                for (int i = 0; i < ITEMS; ++i) {
+                    if (sr[i] & TIED) {
+                        o |= k[i];
+                        a &= k[i];
+                    }
+                    if (posof(i) < nvalid) g |= sr[i] & ~TIED;
+                }
+                // the first position's group start is 0: a group-start bit
+                // varies where it is set anywhere
+                uint32_t gv;
+                const uint64_t vary = varying(o, a, g, 0u, &gv);
+                for (int shift = 0; shift < 64; shift += 8) {
+                    if (!((uint32_t)(vary >> shift) & 0xFFu)) continue;
+#pragma unroll
+                    for (int i = 0; i < ITEMS; ++i) dig[i] = (uint32_t)(k[i] >> shift) & 0xFFu;
+                    pass();
+                }
+                if ((gv >> 16) & 0xFFu) {
+#pragma unroll
+                    for (int i = 0; i < ITEMS; ++i) dig[i] = (sr[i] >> 16) & 0xFFu;
+                    pass();
+                }
+                if ((gv >> 24) & 0x7Fu) {
+#pragma unroll
+                    for (int i = 0; i < ITEMS; ++i) dig[i] = (sr[i] >> 24) & 0x7Fu;
+                    pass();
+                }
+            }
+            // groups: same group start, same key, and the key continues
+#pragma unroll
+            for (int i = 0; i < ITEMS; ++i) {
+                s_k[posof(i)] = k[i];
+                s_sr[posof(i)] = sr[i];
+            }
+            __syncthreads();
+            uint32_t same = 0;
+#pragma unroll
+            for (int i = 0; i < ITEMS; ++i) {
+                const uint32_t p = posof(i);
+                const bool sm = p > 0 && p < nvalid && (sr[i] & TIED) &&
+                                ((s_sr[p - 1] ^ sr[i]) & 0x7FFF0000u) == 0 && s_k[p - 1] == k[i] &&
+                                key_continues<CODER>(k[i]);
+                same |= (sm ? 1u : 0u) << i;
+                t[i] = sm ? 0u : p;
+            }
+            __syncthreads();
+#pragma unroll
+            for (int i = 0; i < ITEMS; ++i) s_k32[posof(i)] = (same >> i) & 1u;
+            __syncthreads();
+            bool any = false;
+#pragma unroll
+            for (int i = 0; i < ITEMS; ++i) {
+                const uint32_t p = posof(i);
+                const bool tied = ((same >> i) & 1u) || (p + 1 < nvalid && s_k32[p + 1]);
+                sr[i] = (sr[i] & 0xFFFFu) | (tied ? TIED : 0u);
+                any = any || tied;
+            }
+            if (!__syncthreads_or(any)) break;
+            tile_running_max<ITEMS, NW>(t, s_k32, s_scan);
+#pragma unroll
+            for (int i = 0; i < ITEMS; ++i) sr[i] |= t[i] << 16;
+        }
+        // indices gathered by slot into LDS before any is overwritten
+#pragma unroll
+        for (int i = 0; i < ITEMS; ++i)
+            if (posof(i) < nvalid) s_k32[posof(i)] = idx[start + (sr[i] & 0xFFFFu)];
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < ITEMS; ++i)
+            if (posof(i) < nvalid) idx[start + posof(i)] = s_k32[posof(i)];
+        __syncthreads();  // LDS is reused by the next run
+    }
+}
+
 // ------------------------------------------------------------------ large tier keys
 template <int CODER, int ITEMS>
 __global__ __launch_bounds__(BLOCK) void k_large_keys(const RunItem* __restrict__ items,
@@ -358,6 +611,31 @@ static hipError_t medium_classes(const FixupArgs& a, const TierLists& tl, uint32
 hipError_t fixup_medium(const FixupArgs& a, const TierLists& tl, uint32_t t_medium,
                         hipStream_t s) {
     return a.coder == 0 ? medium_classes<0>(a, tl, t_medium, s) : medium_classes<1>(a, tl, t_medium, s);
+}
+
+// The LDS list in four size classes, each a persistent launch walking the
+// whole list: a smaller class needs fewer registers and less LDS, so more
+// workgroups share a CU.
+template <int CODER>
+static hipError_t lds_classes(const FixupArgs& a, const TierLists& tl, uint32_t t_medium,
+                              hipStream_t s) {
+    const uint32_t cus = persistent_blocks();
+    ProfScope ps(P_FIX_LDS, s);
+#define HUSKY_FL(I, NW, PER_CU, LMIN)                                                           \
+    hipLaunchKernelGGL((k_fix_lds<CODER, I, NW>), dim3(cus * PER_CU), dim3(NW * WAVE), 0, s,     \
+                       tl.lds, tl.lds_count, tl.lds_cap, (const uint8_t*)a.elems, a.offsets, a.n, \
+                       a.idx, a.key0, std::max<uint32_t>(t_medium, LMIN))
+    if (t_medium < 3072) HUSKY_FL(12, 4, 4, 0);
+    if (t_medium < 4096) HUSKY_FL(16, 4, 3, 3072);
+    HUSKY_FL(12, 8, 2, 4096);
+    HUSKY_FL(16, 8, 1, 6144);
+#undef HUSKY_FL
+    return hipGetLastError();
+}
+
+hipError_t fixup_lds(const FixupArgs& a, const TierLists& tl, uint32_t t_medium, hipStream_t s) {
+    if (!tl.lds_max) return hipSuccess;
+    return a.coder == 0 ? lds_classes<0>(a, tl, t_medium, s) : lds_classes<1>(a, tl, t_medium, s);
 }
 
 hipError_t fixup_large_keys(const FixupArgs& a, const RunItem* items, const RadixScratch& seg,

@@ -13,7 +13,7 @@ namespace husky {
 enum ProfClass {
     P_ENCODE = 0, P_VARY = 1, P_COUNT_SCAN = 2, P_SCATTER = 3, P_COPY_BACK = 4, P_TILE_SORT = 5,
     P_RUNS = 6, P_FIX_SMALL = 7, P_FIX_MEDIUM = 8, P_LARGE_KEYS = 9, P_SETUP = 10,
-    P_SCATTER_FIX = 11, P_BUCKET = 12, P_BUCKET_BOUNDS = 13, P_NUM = 14
+    P_SCATTER_FIX = 11, P_BUCKET = 12, P_BUCKET_BOUNDS = 13, P_FIX_LDS = 14, P_NUM = 15
 };
 bool prof_on();
 class ProfScope {
@@ -103,17 +103,20 @@ struct TierLists {
     RunItem* small;
     RunItem* medium;
     RunItem* large;
+    RunItem* lds;  // runs of t_medium < len <= lds_max, sorted by the per-run LDS kernel
     uint32_t* small_count;
     uint32_t* medium_count;
     uint32_t* large_count;  // [4]: items, items longer than one tile, their tiles, all their tiles
-    uint32_t small_cap, medium_cap, large_cap;
+    uint32_t* lds_count;
+    uint32_t small_cap, medium_cap, large_cap, lds_cap;
+    uint32_t lds_max;  // 0: no LDS tier (those runs go device-wide)
 };
 
 // Find runs (length >= 2) of equal keys inside every segment of sc; when
 // `require_cont` is set a run is kept only if its keys carry the
 // "continues" marker (refinement keys).  Appends each kept run to the tier
-// list chosen by its length, with refinement round `round_of_run` (or, for
-// refinement, the segment item's round + 1 read from `items`).
+// list chosen by its length, with refinement round 0 (or, when `items` is
+// given, the segment item's round + 1).
 // `max_tiles` bounds the tile count over every segment (grid size).
 hipError_t find_runs(const uint64_t* keys, const RadixScratch& seg, const RadixConfig& cfg,
                      uint32_t max_tiles, int coder, bool refinement, const RunItem* items,
@@ -137,6 +140,9 @@ struct FixupArgs {
 hipError_t fixup_small(const FixupArgs& a, const TierLists& tl, uint32_t t_small, hipStream_t s);
 hipError_t fixup_medium(const FixupArgs& a, const TierLists& tl, uint32_t t_medium,
                         hipStream_t s);
+// Runs of t_medium < len <= LDS_RUN_MAX, every round inside one workgroup.
+constexpr uint32_t LDS_RUN_MAX = 8192;
+hipError_t fixup_lds(const FixupArgs& a, const TierLists& tl, uint32_t t_medium, hipStream_t s);
 // Refinement keys for every position of the large-tier segments.
 hipError_t fixup_large_keys(const FixupArgs& a, const RunItem* items, const RadixScratch& seg,
                             const RadixConfig& cfg, uint32_t max_tiles, uint64_t* keys,

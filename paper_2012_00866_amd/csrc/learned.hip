@@ -975,42 +975,6 @@ __global__ __launch_bounds__(256) void k_bucket_classes(const uint64_t* __restri
 //     Step 3's run detection scans (with the larger buckets, whose codes are
 //     left as they are).
 // Every later refinement round proceeds as for any run.
-// Running maximum over the tile in position order, with positions held in the
-// wave-striped layout of rank_digits: every position's value replaced by the
-// maximum of the values at or before it.  s_tmp: NW * 64 * ITEMS words.
-template <int ITEMS, int NW>
-__device__ __forceinline__ void tile_running_max(uint32_t (&v)[ITEMS], uint32_t* s_tmp,
-                                                 uint32_t* s_scan) {
-    const uint32_t tid = threadIdx.x, w = tid / WAVE, lane = lane_id();
-#pragma unroll
-    for (int i = 0; i < ITEMS; ++i) s_tmp[w * WAVE * ITEMS + i * WAVE + lane] = v[i];
-    __syncthreads();
-    // thread t owns positions [ITEMS t, ITEMS t + ITEMS)
-    uint32_t m = 0, loc[ITEMS];
-#pragma unroll
-    for (int i = 0; i < ITEMS; ++i) {
-        m = max(m, s_tmp[tid * ITEMS + i]);
-        loc[i] = m;
-    }
-    uint32_t inc = m;
-#pragma unroll
-    for (int d = 1; d < WAVE; d <<= 1) {
-        const uint32_t t = __shfl_up(inc, d, WAVE);
-        if (lane >= (uint32_t)d) inc = max(inc, t);
-    }
-    if (lane == WAVE - 1) s_scan[w] = inc;
-    uint32_t prev = __shfl_up(inc, 1, WAVE);
-    if (lane == 0) prev = 0;
-    __syncthreads();
-    for (uint32_t ww = 0; ww < w; ++ww) prev = max(prev, s_scan[ww]);
-#pragma unroll
-    for (int i = 0; i < ITEMS; ++i) s_tmp[tid * ITEMS + i] = max(prev, loc[i]);
-    __syncthreads();
-#pragma unroll
-    for (int i = 0; i < ITEMS; ++i) v[i] = s_tmp[w * WAVE * ITEMS + i * WAVE + lane];
-    __syncthreads();
-}
-
 // One size class of buckets: lmin < len <= lmax (and 2 <= len <= NW * 64 * ITEMS),
 // one workgroup of NW wavefronts per bucket.
 // Per item: its key and one word sr = slot | run start << 16 (both < 2^16).

@@ -1,5 +1,6 @@
-// Stable ranking of one tile of keys by one digit (wavefront ballots), shared
-// by the radix sort and the learned bucket passes.
+// Stable ranking of one tile of keys by one digit (wavefront ballots) and a
+// running maximum over a tile, shared by the radix sort, the LDS fix-up tier
+// and the learned bucket passes.
 #pragma once
 
 #include "common.h"
@@ -88,6 +89,42 @@ __device__ __forceinline__ void rank_tile(const uint64_t (&keys)[ITEMS], int shi
 #pragma unroll
     for (int k = 0; k < ITEMS; ++k) dig[k] = (uint32_t)(keys[k] >> shift) & dmask;
     rank_digits<BITS, ITEMS>(dig, nvalid, pos, s_whist, s_binstart, s_scan, bin_count);
+}
+
+// Running maximum over the tile in position order, with positions held in the
+// wave-striped layout of rank_digits: every position's value replaced by the
+// maximum of the values at or before it.  s_tmp: NW * 64 * ITEMS words.
+template <int ITEMS, int NW>
+__device__ __forceinline__ void tile_running_max(uint32_t (&v)[ITEMS], uint32_t* s_tmp,
+                                                 uint32_t* s_scan) {
+    const uint32_t tid = threadIdx.x, w = tid / WAVE, lane = lane_id();
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i) s_tmp[w * WAVE * ITEMS + i * WAVE + lane] = v[i];
+    __syncthreads();
+    // thread t owns positions [ITEMS t, ITEMS t + ITEMS)
+    uint32_t m = 0, loc[ITEMS];
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i) {
+        m = max(m, s_tmp[tid * ITEMS + i]);
+        loc[i] = m;
+    }
+    uint32_t inc = m;
+#pragma unroll
+    for (int d = 1; d < WAVE; d <<= 1) {
+        const uint32_t t = __shfl_up(inc, d, WAVE);
+        if (lane >= (uint32_t)d) inc = max(inc, t);
+    }
+    if (lane == WAVE - 1) s_scan[w] = inc;
+    uint32_t prev = __shfl_up(inc, 1, WAVE);
+    if (lane == 0) prev = 0;
+    __syncthreads();
+    for (uint32_t ww = 0; ww < w; ++ww) prev = max(prev, s_scan[ww]);
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i) s_tmp[tid * ITEMS + i] = max(prev, loc[i]);
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i) v[i] = s_tmp[w * WAVE * ITEMS + i * WAVE + lane];
+    __syncthreads();
 }
 
 template <int ITEMS>

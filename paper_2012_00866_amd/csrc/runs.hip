@@ -157,8 +157,9 @@ __global__ __launch_bounds__(BLOCK) void k_runs_write(const uint64_t* __restrict
 // them; the order inside a list does not matter.  For the device-wide list it
 // also adds up what the host needs to size that tier's launches: the number
 // of items longer than one radix tile and the tiles they span.
-__device__ __forceinline__ int tier_of(uint32_t len, uint32_t t_small, uint32_t t_medium) {
-    return len <= t_small ? 0 : (len <= t_medium ? 1 : 2);
+__device__ __forceinline__ int tier_of(uint32_t len, uint32_t t_small, uint32_t t_medium,
+                                       uint32_t lds_max) {
+    return len <= t_small ? 0 : (len <= t_medium ? 1 : (len <= lds_max ? 3 : 2));
 }
 
 __global__ __launch_bounds__(BLOCK) void k_runs_classify(
@@ -166,12 +167,12 @@ __global__ __launch_bounds__(BLOCK) void k_runs_classify(
     const uint32_t* __restrict__ run_seg, const uint32_t* __restrict__ num_runs,
     const RunItem* __restrict__ items, TierLists tl, uint32_t t_small, uint32_t t_medium,
     uint32_t tile, uint32_t* __restrict__ runs_seen) {
-    __shared__ uint32_t s_n[6], s_base[3], s_fill[3];
+    __shared__ uint32_t s_n[7], s_base[4], s_fill[4];
     const uint32_t nr = *num_runs;
     const uint32_t per = ((nr + gridDim.x - 1) / gridDim.x + BLOCK - 1) / BLOCK * BLOCK;
     const uint32_t r0 = blockIdx.x * per, r1 = min(nr, r0 + per);
-    if (threadIdx.x < 6) s_n[threadIdx.x] = 0;
-    if (threadIdx.x < 3) s_fill[threadIdx.x] = 0;
+    if (threadIdx.x < 7) s_n[threadIdx.x] = 0;
+    if (threadIdx.x < 4) s_fill[threadIdx.x] = 0;
     __syncthreads();
     const uint32_t lane = lane_id();
     // pass 1: counts
@@ -179,19 +180,20 @@ __global__ __launch_bounds__(BLOCK) void k_runs_classify(
         const bool ok = r < r1;
         uint32_t len = 0;
         if (ok) len = run_end[r] - run_start[r] + 1;
-        const int tr = ok ? tier_of(len, t_small, t_medium) : -1;
+        const int tr = ok ? tier_of(len, t_small, t_medium, tl.lds_max) : -1;
         const uint32_t big = (tr == 2 && len > tile) ? 1u : 0u;
         const uint32_t bt = big ? (len + tile - 1) / tile : 0u;
         const uint32_t at = tr == 2 ? (len + tile - 1) / tile : 0u;
-        uint32_t c[6] = {(uint32_t)__popcll(ballot(tr == 0)), (uint32_t)__popcll(ballot(tr == 1)),
-                         (uint32_t)__popcll(ballot(tr == 2)), (uint32_t)__popcll(ballot(big != 0)), bt, at};
+        uint32_t c[7] = {(uint32_t)__popcll(ballot(tr == 0)), (uint32_t)__popcll(ballot(tr == 1)),
+                         (uint32_t)__popcll(ballot(tr == 2)), (uint32_t)__popcll(ballot(big != 0)), bt, at,
+                         (uint32_t)__popcll(ballot(tr == 3))};
 #pragma unroll
         for (int d = 32; d >= 1; d >>= 1) {
             c[4] += __shfl_xor(c[4], d, WAVE);
             c[5] += __shfl_xor(c[5], d, WAVE);
         }
         if (lane == 0)
-            for (int q = 0; q < 6; ++q)
+            for (int q = 0; q < 7; ++q)
                 if (c[q]) atomicAdd(&s_n[q], c[q]);
     }
     __syncthreads();
@@ -202,6 +204,7 @@ __global__ __launch_bounds__(BLOCK) void k_runs_classify(
         if (s_n[3]) atomicAdd(tl.large_count + 1, s_n[3]);
         if (s_n[4]) atomicAdd(tl.large_count + 2, s_n[4]);
         if (s_n[5]) atomicAdd(tl.large_count + 3, s_n[5]);
+        s_base[3] = s_n[6] ? atomicAdd(tl.lds_count, s_n[6]) : 0u;
     }
     __syncthreads();
     // pass 2: items
@@ -213,9 +216,9 @@ __global__ __launch_bounds__(BLOCK) void k_runs_classify(
             it.start = run_start[r];
             it.len = run_end[r] - it.start + 1;
             it.round = items ? items[run_seg[r]].round + 1 : 0;
-            tr = tier_of(it.len, t_small, t_medium);
+            tr = tier_of(it.len, t_small, t_medium, tl.lds_max);
         }
-        for (int q = 0; q < 3; ++q) {
+        for (int q = 0; q < 4; ++q) {
             const uint64_t m = ballot(tr == q);
             if (!m) continue;
             const uint32_t leader = (uint32_t)__ffsll((unsigned long long)m) - 1u;
@@ -223,8 +226,9 @@ __global__ __launch_bounds__(BLOCK) void k_runs_classify(
             if (lane == leader) o = atomicAdd(&s_fill[q], (uint32_t)__popcll(m));
             o = readlane(o, (int)leader) + mbcnt(m) + s_base[q];
             if (tr == q) {
-                RunItem* list = q == 0 ? tl.small : (q == 1 ? tl.medium : tl.large);
-                const uint32_t cap = q == 0 ? tl.small_cap : (q == 1 ? tl.medium_cap : tl.large_cap);
+                RunItem* list = q == 0 ? tl.small : (q == 1 ? tl.medium : (q == 2 ? tl.large : tl.lds));
+                const uint32_t cap =
+                    q == 0 ? tl.small_cap : (q == 1 ? tl.medium_cap : (q == 2 ? tl.large_cap : tl.lds_cap));
                 if (o < cap) list[o] = it;
             }
         }
@@ -249,7 +253,7 @@ static hipError_t find_runs_impl(const uint64_t* keys, const RadixScratch& seg,
                        rs.run_start + rs.run_cap);
     const uint32_t blocks = 96;
     hipLaunchKernelGGL(k_runs_classify, dim3(blocks), dim3(BLOCK), 0, s, rs.run_start, rs.run_end,
-                       rs.run_start + rs.run_cap, num_runs, REFINE ? items : nullptr, tl,
+                       rs.run_start + rs.run_cap, num_runs, items, tl,
                        t_small, t_medium, (uint32_t)(BLOCK * ITEMS),
                        REFINE ? nullptr : rs.runs_seen);
     return hipGetLastError();

@@ -61,8 +61,9 @@ def test_fixed_rounds_equal_adaptive(gpu_lib, maker):
 
 
 def test_fixed_rounds_reports_unresolved(gpu_lib):
-    # 5,000 identical 60-byte strings need 8 rounds; one round leaves them tied
-    b = from_strings([b"x" * 60] * 5000 + [b"y"])
+    # 9,000 identical 60-byte strings (more than one workgroup holds in LDS,
+    # so the run goes device-wide) need 8 rounds; one round leaves them tied
+    b = from_strings([b"x" * 60] * 9000 + [b"y"])
     e, o = gpu_lib.to_device(b)
     ws = gpu_lib.alloc_workspace(b.n)
     gpu_lib.sort(e, o, "ascii7", tuning=gpu_lib.make_tuning(t_medium=256, max_rounds=1), ws=ws)

@@ -2,7 +2,7 @@
 
 Bit-exact comparisons throughout (codes, sorted pairs, permutations).  Sizes
 run from a few strings to several radix tiles with ragged tails; the full
-workload sizes are covered by tests/test_gpu_full.py.
+workload sizes are covered by tests/test_gpu_sizes_full.py.
 """
 
 import sys
