@@ -35,7 +35,7 @@ struct Layout {
         tile_counts, run_start, run_end, small, medium, large_a, large_b, lds, bid, bseg, k0a, k0b, scan,
         biglist, classes, lpartial, lgrad, ltmax, total;
     uint32_t seg_cap, big_cap, tile_cap, big_tile_cap, group_cap, run_cap, small_cap, medium_cap,
-        large_cap;
+        large_cap, lds_cap[4];
 };
 
 Layout make_layout(uint64_t n, uint64_t n_segs, bool learned = false) {
@@ -79,8 +79,15 @@ Layout make_layout(uint64_t n, uint64_t n_segs, bool learned = false) {
     L.medium = take((size_t)L.medium_cap * sizeof(RunItem));
     L.large_a = take((size_t)L.large_cap * sizeof(RunItem));
     L.large_b = take((size_t)L.large_cap * sizeof(RunItem));
-    // LDS-tier runs are disjoint and longer than t_medium >= MIN_T_MEDIUM
-    L.lds = take((size_t)L.large_cap * sizeof(RunItem));
+    // LDS-tier runs are disjoint and longer than t_medium >= MIN_T_MEDIUM and
+    // than the class below's largest
+    size_t lds_items = 0;
+    for (int k = 0; k < 4; ++k) {
+        const uint64_t shorter = k == 0 ? MIN_T_MEDIUM : lds_class_max(k - 1);
+        L.lds_cap[k] = (uint32_t)(n / (shorter + 1) + 2);
+        lds_items += L.lds_cap[k];
+    }
+    L.lds = take(lds_items * sizeof(RunItem));
     if (learned) {
         L.bid = take(n * 4);
         L.bseg = take(((size_t)LEARNED_BUCKETS + 1) * 8);
@@ -98,14 +105,16 @@ Layout make_layout(uint64_t n, uint64_t n_segs, bool learned = false) {
 }
 
 // counters region: [0, 64) radix counters; [64, 80) run counters;
-// [80] small count, [81] medium count, [82] LDS-tier count; [84, 88) and
+// [80] small count, [81] medium count; [84, 88) and
 // [88, 92) the two device-wide lists: item count, items longer than one
-// tile, their tiles, tiles of all items
-constexpr int CNT_RUNS = 64, CNT_SMALL = 80, CNT_MEDIUM = 81, CNT_LDS = 82, CNT_LARGE_A = 84,
-              CNT_LARGE_B = 88,
+// tile, their tiles, tiles of all items; [92, 96) LDS-tier class counts;
+// [96, 102) learned-form lists; [104, 108) work counters of the LDS tier
+constexpr int CNT_RUNS = 64, CNT_SMALL = 80, CNT_MEDIUM = 81, CNT_LARGE_A = 84, CNT_LARGE_B = 88,
+              CNT_LDS = 92,
               CNT_SCAN = 96,  // learned form: buckets on the run-detection list
               CNT_BIG = 97,   // learned form: buckets for the multi-tile radix passes
-              CNT_CLASS = 98; // learned form: buckets per LDS size class (four)
+              CNT_CLASS = 98, // learned form: buckets per LDS size class (four)
+              CNT_LDS_QUEUE = 104;  // LDS fix-up tier: work counters of its size classes (four)
 
 struct Ctx {
     Layout L;
@@ -148,15 +157,22 @@ Ctx make_ctx(void* ws, uint64_t n, uint64_t n_segs, bool learned = false) {
     c.tiers.small = c.at<RunItem>(c.L.small);
     c.tiers.medium = c.at<RunItem>(c.L.medium);
     c.tiers.large = c.at<RunItem>(c.L.large_a);
-    c.tiers.lds = c.at<RunItem>(c.L.lds);
+    {
+        RunItem* l = c.at<RunItem>(c.L.lds);
+        for (int k = 0; k < 4; ++k) {
+            c.tiers.lds[k] = l;
+            c.tiers.lds_cap[k] = c.L.lds_cap[k];
+            l += c.L.lds_cap[k];
+        }
+    }
     c.tiers.small_count = c.counters + CNT_SMALL;
     c.tiers.medium_count = c.counters + CNT_MEDIUM;
     c.tiers.large_count = c.counters + CNT_LARGE_A;
     c.tiers.lds_count = c.counters + CNT_LDS;
+    c.tiers.lds_queue = c.counters + CNT_LDS_QUEUE;
     c.tiers.small_cap = c.L.small_cap;
     c.tiers.medium_cap = c.L.medium_cap;
     c.tiers.large_cap = c.L.large_cap;
-    c.tiers.lds_cap = c.L.large_cap;
     c.tiers.lds_max = 0;
     return c;
 }
@@ -223,7 +239,7 @@ husky_status run_fixup(Ctx& c, const Tune& tn, int coder, const void* elems,
                        const uint64_t* offsets, uint64_t n, uint64_t n_segs,
                        const uint64_t* codes, uint64_t* keys, uint64_t* keys_alt, uint32_t* idx,
                        hipStream_t s) {
-    HUSKY_TRY(zero_u32(c.counters + CNT_SMALL, 12, s));
+    HUSKY_TRY(zero_u32(c.counters + CNT_SMALL, 16, s));  // tier counts [80, 96)
     c.tiers.lds_max = tn.t_medium < LDS_RUN_MAX ? LDS_RUN_MAX : 0u;
     const uint32_t tb = tiles_bound(n, n_segs, tn.rc);
     HUSKY_TRY(find_runs(codes, c.rad, tn.rc, tb, coder, false, nullptr, c.runs, c.tiers,

@@ -272,7 +272,7 @@ __global__ __launch_bounds__(BLOCK) void k_fix_medium(const RunItem* __restrict_
 }
 
 // ------------------------------------------------------------------ LDS tier
-// One size class of the LDS list: lmin < len <= NW * 64 * ITEMS, one
+// One size class of the LDS tier (runs of at most NW * 64 * ITEMS), one
 // workgroup per run.  Per member: its key and one word
 //     sr = slot | group start << 16 | still tied << 31
 // (slot: the member's place in the run when the kernel started; group start:
@@ -292,7 +292,7 @@ __global__ __launch_bounds__(NW * WAVE) void k_fix_lds(const RunItem* __restrict
                                                    const uint64_t* __restrict__ offsets, uint32_t n,
                                                    uint32_t* __restrict__ idx,
                                                    const uint64_t* __restrict__ key0,
-                                                   uint32_t lmin) {
+                                                   uint32_t* __restrict__ queue) {
     constexpr uint32_t NT = NW * WAVE;
     constexpr uint32_t TILE = NT * ITEMS;
     static_assert(TILE <= 32768, "slots and group starts fit 15 bits");
@@ -307,6 +307,7 @@ __global__ __launch_bounds__(NW * WAVE) void k_fix_lds(const RunItem* __restrict
     __shared__ uint32_t s_scan[NW];
     __shared__ uint64_t s_or[NW], s_and[NW];
     __shared__ uint32_t s_gor[NW], s_gand[NW], s_wt[NW];
+    __shared__ uint32_t s_next;
     uint32_t* s_k32 = reinterpret_cast<uint32_t*>(s_k);  // scratch while keys sit in registers
     const uint64_t total_bytes = offsets[n] * (CODER == 0 ? 1u : 2u);
     const uint32_t n_items = min(*count, cap);
@@ -348,9 +349,19 @@ __global__ __launch_bounds__(NW * WAVE) void k_fix_lds(const RunItem* __restrict
         *gvary = gg ^ gga;
         return oo ^ aa;
     };
-    for (uint32_t it = blockIdx.x; it < n_items; it += gridDim.x) {
+    // workgroup b takes run b first, then runs past the grid one at a time
+    // through a counter, so that workgroups finishing early take more of them
+    for (bool first = true;; first = false) {
+        uint32_t it = blockIdx.x;
+        if (!first) {
+            if (tid == 0) s_next = gridDim.x + atomicAdd(queue, 1u);
+            __syncthreads();
+            it = s_next;
+            __syncthreads();
+        }
+        if (it >= n_items) break;
         const RunItem r = items[it];
-        if (r.len <= lmin || r.len > TILE) continue;  // another class's run; uniform per workgroup
+        if (r.len < 2 || r.len > TILE) continue;  // never listed so; uniform per workgroup
         const uint32_t nvalid = r.len, start = r.start;
         uint64_t k[ITEMS];
         uint32_t sr[ITEMS], dig[ITEMS], pos[ITEMS], t[ITEMS];
@@ -432,14 +443,31 @@ __global__ __launch_bounds__(NW * WAVE) void k_fix_lds(const RunItem* __restrict
                     }
                 __syncthreads();
             } else {
-                // dense round: every gather issued before any is used
+                // dense round: string indices first (every load issued before
+                // any is used), then the keys
                 uint32_t m[ITEMS];
 #pragma unroll
                 for (int i = 0; i < ITEMS; ++i) m[i] = idx[start + ((sr[i] & TIED) ? (sr[i] & 0xFFFFu) : 0u)];
+                if (round == 0 && key0) {
 #pragma unroll
-                for (int i = 0; i < ITEMS; ++i) {
-                    const uint64_t v = key_of(m[i], round);
-                    k[i] = (sr[i] & TIED) ? v : 0ull;
+                    for (int i = 0; i < ITEMS; ++i) {
+                        const uint64_t v = key0[m[i]];
+                        k[i] = (sr[i] & TIED) ? v : 0ull;
+                    }
+                } else {
+                    // keys from the string bytes, staged through LDS so that
+                    // the loop is not unrolled ITEMS times
+#pragma unroll
+                    for (int i = 0; i < ITEMS; ++i) s_sr[posof(i)] = (sr[i] & TIED) ? m[i] : ~0u;
+                    __syncthreads();
+#pragma unroll 2
+                    for (int i = 0; i < ITEMS; ++i) {
+                        const uint32_t mm = s_sr[posof(i)];
+                        s_k[posof(i)] = mm != ~0u ? key_of(mm, round) : 0ull;
+                    }
+                    __syncthreads();
+#pragma unroll
+                    for (int i = 0; i < ITEMS; ++i) k[i] = s_k[posof(i)];
                 }
                 uint64_t o = 0, a = ~0ull;
                 uint32_t g = 0;
@@ -455,20 +483,18 @@ __global__ __launch_bounds__(NW * WAVE) void k_fix_lds(const RunItem* __restrict
                 // varies where it is set anywhere
                 uint32_t gv;
                 const uint64_t vary = varying(o, a, g, 0u, &gv);
-                for (int shift = 0; shift < 64; shift += 8) {
-                    if (!((uint32_t)(vary >> shift) & 0xFFu)) continue;
+                // digits to pass, least significant first: bit j < 8 for key
+                // digit j, bits 8 and 9 for the low and high group-start digits
+                uint32_t todo = ((gv >> 16) & 0xFFu ? 0x100u : 0u) | ((gv >> 24) & 0x7Fu ? 0x200u : 0u);
 #pragma unroll
-                    for (int i = 0; i < ITEMS; ++i) dig[i] = (uint32_t)(k[i] >> shift) & 0xFFu;
-                    pass();
-                }
-                if ((gv >> 16) & 0xFFu) {
+                for (int j = 0; j < 8; ++j) todo |= ((uint32_t)(vary >> (8 * j)) & 0xFFu) ? 1u << j : 0u;
+                while (todo) {
+                    const uint32_t j = (uint32_t)__ffs(todo) - 1u;
+                    todo &= todo - 1u;
 #pragma unroll
-                    for (int i = 0; i < ITEMS; ++i) dig[i] = (sr[i] >> 16) & 0xFFu;
-                    pass();
-                }
-                if ((gv >> 24) & 0x7Fu) {
-#pragma unroll
-                    for (int i = 0; i < ITEMS; ++i) dig[i] = (sr[i] >> 24) & 0x7Fu;
+                    for (int i = 0; i < ITEMS; ++i)
+                        dig[i] = j < 8 ? (uint32_t)(k[i] >> (8 * j)) & 0xFFu
+                                       : (j == 8 ? (sr[i] >> 16) & 0xFFu : (sr[i] >> 24) & 0x7Fu);
                     pass();
                 }
             }
@@ -621,14 +647,17 @@ static hipError_t lds_classes(const FixupArgs& a, const TierLists& tl, uint32_t 
                               hipStream_t s) {
     const uint32_t cus = persistent_blocks();
     ProfScope ps(P_FIX_LDS, s);
-#define HUSKY_FL(I, NW, PER_CU, LMIN)                                                           \
-    hipLaunchKernelGGL((k_fix_lds<CODER, I, NW>), dim3(cus * PER_CU), dim3(NW * WAVE), 0, s,     \
-                       tl.lds, tl.lds_count, tl.lds_cap, (const uint8_t*)a.elems, a.offsets, a.n, \
-                       a.idx, a.key0, std::max<uint32_t>(t_medium, LMIN))
-    if (t_medium < 3072) HUSKY_FL(12, 4, 4, 0);
-    if (t_medium < 4096) HUSKY_FL(16, 4, 3, 3072);
-    HUSKY_FL(12, 8, 2, 4096);
-    HUSKY_FL(16, 8, 1, 6144);
+    hipError_t e = zero_u32(tl.lds_queue, 4, s);
+    if (e != hipSuccess) return e;
+#define HUSKY_FL(I, NW, PER_CU, C)                                                                 \
+    static_assert(NW * WAVE * I == lds_class_max(C), "class tile");                                \
+    hipLaunchKernelGGL((k_fix_lds<CODER, I, NW>), dim3(cus * PER_CU), dim3(NW * WAVE), 0, s,        \
+                       tl.lds[C], tl.lds_count + C, tl.lds_cap[C], (const uint8_t*)a.elems, a.offsets, \
+                       a.n, a.idx, a.key0, tl.lds_queue + C)
+    if (t_medium < lds_class_max(0)) HUSKY_FL(12, 4, 4, 0);
+    if (t_medium < lds_class_max(1)) HUSKY_FL(16, 4, 3, 1);
+    HUSKY_FL(12, 8, 2, 2);
+    HUSKY_FL(16, 8, 1, 3);
 #undef HUSKY_FL
     return hipGetLastError();
 }

@@ -99,16 +99,27 @@ struct RunScratch {
 };
 
 // Fix-up work lists, one per tier (device lists, device counts).
+// The LDS tier (runs of t_medium < len <= 8192) in four size classes by
+// length: up to 3072, 4096, 6144 and 8192.
+__host__ __device__ constexpr uint32_t lds_class_max(int c) {
+    return c == 0 ? 3072u : (c == 1 ? 4096u : (c == 2 ? 6144u : 8192u));
+}
+__host__ __device__ constexpr int lds_class_of(uint32_t len) {
+    return len > 6144u ? 3 : (len > 4096u ? 2 : (len > 3072u ? 1 : 0));
+}
+
 struct TierLists {
     RunItem* small;
     RunItem* medium;
     RunItem* large;
-    RunItem* lds;  // runs of t_medium < len <= lds_max, sorted by the per-run LDS kernel
+    RunItem* lds[4];  // LDS tier, one list per size class
     uint32_t* small_count;
     uint32_t* medium_count;
     uint32_t* large_count;  // [4]: items, items longer than one tile, their tiles, all their tiles
-    uint32_t* lds_count;
-    uint32_t small_cap, medium_cap, large_cap, lds_cap;
+    uint32_t* lds_count;    // [4]
+    uint32_t* lds_queue;    // [4] work counters of the LDS tier's kernels
+    uint32_t small_cap, medium_cap, large_cap;
+    uint32_t lds_cap[4];
     uint32_t lds_max;  // 0: no LDS tier (those runs go device-wide)
 };
 

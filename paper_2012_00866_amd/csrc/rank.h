@@ -26,37 +26,41 @@ __device__ __forceinline__ void rank_digits(uint32_t (&dig)[ITEMS], uint32_t nva
     const uint32_t tid = threadIdx.x, w = tid / WAVE, lane = lane_id();
     for (uint32_t i = tid; i < (uint32_t)(NW * R); i += NT) s_whist[i] = 0;
     __syncthreads();
-    // Each wavefront owns one histogram row.  Within an iteration every lane
-    // reads its digit's count before the one lane per digit updates it; LDS
-    // operations of one wavefront complete in order, and the empty asm with a
-    // memory clobber keeps the compiler from reusing a count across
-    // iterations.
+    // Each wavefront owns one histogram row.  For every item, the lanes
+    // holding the same digit find each other with one ballot per digit bit;
+    // all of them read the row's count for that digit, then the highest of
+    // them adds the group's size with an LDS atomic.  LDS operations of one
+    // wavefront execute in order, so each read sees every earlier item's
+    // add, and no item waits for the previous one's result.
     uint32_t* wh = s_whist + w * R;
-    uint32_t rank[ITEMS];
+    uint32_t base[ITEMS], bl[(ITEMS + 4) / 5];  // counts read; ranks in the group, 6 bits each
 #pragma unroll
     for (int k = 0; k < ITEMS; ++k) {
         const uint32_t p = w * WAVE * ITEMS + k * WAVE + lane;
         const uint32_t d = p < nvalid ? dig[k] : (uint32_t)(R - 1);
         dig[k] = d;
         // lanes holding the same digit: for every digit bit keep the lanes
-        // whose bit agrees (ballot, inverted where this lane's bit is 0)
+        // whose bit agrees (the ballot, inverted where this lane's bit is 0)
+        uint64_t bal[BITS];
+#pragma unroll
+        for (int b = 0; b < BITS; ++b) bal[b] = ballot(((d >> b) & 1u) != 0);
         uint32_t plo = ~0u, phi = ~0u;
 #pragma unroll
         for (int b = 0; b < BITS; ++b) {
-            const uint32_t bit = (d >> b) & 1u;
-            const uint64_t bal = ballot(bit != 0);
-            const uint32_t flip = bit - 1u;  // 0 when set, all ones when clear
-            plo &= (uint32_t)bal ^ flip;
-            phi &= (uint32_t)(bal >> 32) ^ flip;
+            const uint32_t f = 0u - ((d >> b) & 1u);  // all ones when set
+            plo &= ~((uint32_t)bal[b] ^ f);
+            phi &= ~((uint32_t)(bal[b] >> 32) ^ f);
         }
         const uint32_t below = __builtin_amdgcn_mbcnt_hi(phi, __builtin_amdgcn_mbcnt_lo(plo, 0u));
         const uint32_t cnt = (uint32_t)__popc(plo) + (uint32_t)__popc(phi);
-        const uint32_t base = wh[d];
-        __asm__ volatile("" ::: "memory");
-        if (below == cnt - 1) wh[d] = base + cnt;
-        __asm__ volatile("" ::: "memory");
-        rank[k] = base + below;
+        base[k] = wh[d];
+        if (below == cnt - 1)
+            __hip_atomic_fetch_add(&wh[d], cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        bl[k / 5] = (k % 5 ? bl[k / 5] : 0u) | below << (6 * (k % 5));
     }
+    uint32_t rank[ITEMS];
+#pragma unroll
+    for (int k = 0; k < ITEMS; ++k) rank[k] = base[k] + ((bl[k / 5] >> (6 * (k % 5))) & 63u);
     __syncthreads();
     uint32_t tot = 0;
     if (tid < (uint32_t)R) {

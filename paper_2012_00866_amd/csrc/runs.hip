@@ -157,9 +157,11 @@ __global__ __launch_bounds__(BLOCK) void k_runs_write(const uint64_t* __restrict
 // them; the order inside a list does not matter.  For the device-wide list it
 // also adds up what the host needs to size that tier's launches: the number
 // of items longer than one radix tile and the tiles they span.
-__device__ __forceinline__ int tier_of(uint32_t len, uint32_t t_small, uint32_t t_medium,
+// List of a run: 0 wavefront, 1 workgroup, 2 device-wide, 3 + c LDS tier
+// size class c.
+__device__ __forceinline__ int list_of(uint32_t len, uint32_t t_small, uint32_t t_medium,
                                        uint32_t lds_max) {
-    return len <= t_small ? 0 : (len <= t_medium ? 1 : (len <= lds_max ? 3 : 2));
+    return len <= t_small ? 0 : (len <= t_medium ? 1 : (len <= lds_max ? 3 + lds_class_of(len) : 2));
 }
 
 __global__ __launch_bounds__(BLOCK) void k_runs_classify(
@@ -167,12 +169,15 @@ __global__ __launch_bounds__(BLOCK) void k_runs_classify(
     const uint32_t* __restrict__ run_seg, const uint32_t* __restrict__ num_runs,
     const RunItem* __restrict__ items, TierLists tl, uint32_t t_small, uint32_t t_medium,
     uint32_t tile, uint32_t* __restrict__ runs_seen) {
-    __shared__ uint32_t s_n[7], s_base[4], s_fill[4];
+    constexpr int NL = 7;  // lists
+    // s_n: items per list, then the device-wide list's items longer than one
+    // tile, their tiles and the tiles of all its items
+    __shared__ uint32_t s_n[NL + 3], s_base[NL], s_fill[NL];
     const uint32_t nr = *num_runs;
     const uint32_t per = ((nr + gridDim.x - 1) / gridDim.x + BLOCK - 1) / BLOCK * BLOCK;
     const uint32_t r0 = blockIdx.x * per, r1 = min(nr, r0 + per);
-    if (threadIdx.x < 7) s_n[threadIdx.x] = 0;
-    if (threadIdx.x < 4) s_fill[threadIdx.x] = 0;
+    if (threadIdx.x < NL + 3) s_n[threadIdx.x] = 0;
+    if (threadIdx.x < NL) s_fill[threadIdx.x] = 0;
     __syncthreads();
     const uint32_t lane = lane_id();
     // pass 1: counts
@@ -180,55 +185,61 @@ __global__ __launch_bounds__(BLOCK) void k_runs_classify(
         const bool ok = r < r1;
         uint32_t len = 0;
         if (ok) len = run_end[r] - run_start[r] + 1;
-        const int tr = ok ? tier_of(len, t_small, t_medium, tl.lds_max) : -1;
-        const uint32_t big = (tr == 2 && len > tile) ? 1u : 0u;
-        const uint32_t bt = big ? (len + tile - 1) / tile : 0u;
-        const uint32_t at = tr == 2 ? (len + tile - 1) / tile : 0u;
-        uint32_t c[7] = {(uint32_t)__popcll(ballot(tr == 0)), (uint32_t)__popcll(ballot(tr == 1)),
-                         (uint32_t)__popcll(ballot(tr == 2)), (uint32_t)__popcll(ballot(big != 0)), bt, at,
-                         (uint32_t)__popcll(ballot(tr == 3))};
+        const int li = ok ? list_of(len, t_small, t_medium, tl.lds_max) : -1;
+        const uint32_t big = (li == 2 && len > tile) ? 1u : 0u;
+        uint32_t bt = big ? (len + tile - 1) / tile : 0u;
+        uint32_t at = li == 2 ? (len + tile - 1) / tile : 0u;
 #pragma unroll
         for (int d = 32; d >= 1; d >>= 1) {
-            c[4] += __shfl_xor(c[4], d, WAVE);
-            c[5] += __shfl_xor(c[5], d, WAVE);
+            bt += __shfl_xor(bt, d, WAVE);
+            at += __shfl_xor(at, d, WAVE);
         }
-        if (lane == 0)
-            for (int q = 0; q < 7; ++q)
-                if (c[q]) atomicAdd(&s_n[q], c[q]);
+        if (lane == 0) {
+            if (bt) atomicAdd(&s_n[NL + 1], bt);
+            if (at) atomicAdd(&s_n[NL + 2], at);
+        }
+        const uint32_t nbig = (uint32_t)__popcll(ballot(big != 0));
+        if (lane == 0 && nbig) atomicAdd(&s_n[NL], nbig);
+#pragma unroll
+        for (int q = 0; q < NL; ++q) {
+            const uint32_t c = (uint32_t)__popcll(ballot(li == q));
+            if (lane == 0 && c) atomicAdd(&s_n[q], c);
+        }
     }
     __syncthreads();
     if (threadIdx.x == 0) {
         s_base[0] = s_n[0] ? atomicAdd(tl.small_count, s_n[0]) : 0u;
         s_base[1] = s_n[1] ? atomicAdd(tl.medium_count, s_n[1]) : 0u;
         s_base[2] = s_n[2] ? atomicAdd(tl.large_count, s_n[2]) : 0u;
-        if (s_n[3]) atomicAdd(tl.large_count + 1, s_n[3]);
-        if (s_n[4]) atomicAdd(tl.large_count + 2, s_n[4]);
-        if (s_n[5]) atomicAdd(tl.large_count + 3, s_n[5]);
-        s_base[3] = s_n[6] ? atomicAdd(tl.lds_count, s_n[6]) : 0u;
+        if (s_n[NL]) atomicAdd(tl.large_count + 1, s_n[NL]);
+        if (s_n[NL + 1]) atomicAdd(tl.large_count + 2, s_n[NL + 1]);
+        if (s_n[NL + 2]) atomicAdd(tl.large_count + 3, s_n[NL + 2]);
+        for (int c = 0; c < 4; ++c) s_base[3 + c] = s_n[3 + c] ? atomicAdd(tl.lds_count + c, s_n[3 + c]) : 0u;
     }
     __syncthreads();
     // pass 2: items
     for (uint32_t r = r0 + threadIdx.x; r < r0 + per; r += BLOCK) {
         const bool ok = r < r1;
         RunItem it{0, 0, 0, 0};
-        int tr = -1;
+        int li = -1;
         if (ok) {
             it.start = run_start[r];
             it.len = run_end[r] - it.start + 1;
             it.round = items ? items[run_seg[r]].round + 1 : 0;
-            tr = tier_of(it.len, t_small, t_medium, tl.lds_max);
+            li = list_of(it.len, t_small, t_medium, tl.lds_max);
         }
-        for (int q = 0; q < 4; ++q) {
-            const uint64_t m = ballot(tr == q);
+#pragma unroll
+        for (int q = 0; q < NL; ++q) {
+            const uint64_t m = ballot(li == q);
             if (!m) continue;
             const uint32_t leader = (uint32_t)__ffsll((unsigned long long)m) - 1u;
             uint32_t o = 0;
             if (lane == leader) o = atomicAdd(&s_fill[q], (uint32_t)__popcll(m));
             o = readlane(o, (int)leader) + mbcnt(m) + s_base[q];
-            if (tr == q) {
-                RunItem* list = q == 0 ? tl.small : (q == 1 ? tl.medium : (q == 2 ? tl.large : tl.lds));
+            if (li == q) {
+                RunItem* list = q == 0 ? tl.small : (q == 1 ? tl.medium : (q == 2 ? tl.large : tl.lds[q - 3]));
                 const uint32_t cap =
-                    q == 0 ? tl.small_cap : (q == 1 ? tl.medium_cap : (q == 2 ? tl.large_cap : tl.lds_cap));
+                    q == 0 ? tl.small_cap : (q == 1 ? tl.medium_cap : (q == 2 ? tl.large_cap : tl.lds_cap[q - 3]));
                 if (o < cap) list[o] = it;
             }
         }
