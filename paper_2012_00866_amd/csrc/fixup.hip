@@ -483,18 +483,20 @@ __global__ __launch_bounds__(NW * WAVE) void k_fix_lds(const RunItem* __restrict
                 // varies where it is set anywhere
                 uint32_t gv;
                 const uint64_t vary = varying(o, a, g, 0u, &gv);
-                // digits to pass, least significant first: bit j < 8 for key
-                // digit j, bits 8 and 9 for the low and high group-start digits
-                uint32_t todo = ((gv >> 16) & 0xFFu ? 0x100u : 0u) | ((gv >> 24) & 0x7Fu ? 0x200u : 0u);
+                for (int shift = 0; shift < 64; shift += 8) {
+                    if (!((uint32_t)(vary >> shift) & 0xFFu)) continue;
 #pragma unroll
-                for (int j = 0; j < 8; ++j) todo |= ((uint32_t)(vary >> (8 * j)) & 0xFFu) ? 1u << j : 0u;
-                while (todo) {
-                    const uint32_t j = (uint32_t)__ffs(todo) - 1u;
-                    todo &= todo - 1u;
+                    for (int i = 0; i < ITEMS; ++i) dig[i] = (uint32_t)(k[i] >> shift) & 0xFFu;
+                    pass();
+                }
+                if ((gv >> 16) & 0xFFu) {
 #pragma unroll
-                    for (int i = 0; i < ITEMS; ++i)
-                        dig[i] = j < 8 ? (uint32_t)(k[i] >> (8 * j)) & 0xFFu
-                                       : (j == 8 ? (sr[i] >> 16) & 0xFFu : (sr[i] >> 24) & 0x7Fu);
+                    for (int i = 0; i < ITEMS; ++i) dig[i] = (sr[i] >> 16) & 0xFFu;
+                    pass();
+                }
+                if ((gv >> 24) & 0x7Fu) {
+#pragma unroll
+                    for (int i = 0; i < ITEMS; ++i) dig[i] = (sr[i] >> 24) & 0x7Fu;
                     pass();
                 }
             }
