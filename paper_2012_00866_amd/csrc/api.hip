@@ -31,7 +31,8 @@ constexpr uint32_t LEARN_MAX_BLOCKS = 256;
 // training scratch; its fit borrows the sort's regions for the sample (see
 // husky_learned_fit).
 struct Layout {
-    size_t status, counters, codes_a, codes_b, idx_b, key0, segs, bigs, korand, binstart, cnt, gtot,
+    size_t status, counters, codes_a, codes_b, idx_b, key0, segs, bigs, korand, segvary, prog, binstart,
+        cnt, gtot,
         tile_counts, run_start, run_end, small, medium, large_a, large_b, lds, bid, bseg, k0a, k0b, scan,
         biglist, classes, lpartial, lgrad, ltmax, total;
     uint32_t seg_cap, big_cap, tile_cap, big_tile_cap, group_cap, run_cap, small_cap, medium_cap,
@@ -69,6 +70,8 @@ Layout make_layout(uint64_t n, uint64_t n_segs, bool learned = false) {
     L.segs = take((size_t)L.seg_cap * sizeof(SegDesc));
     L.bigs = take((size_t)L.big_cap * sizeof(BigDesc));
     L.korand = take((size_t)L.big_tile_cap * 16);
+    L.segvary = take((size_t)L.big_cap * 8);
+    L.prog = take((size_t)MAX_PASSES * PROG_WORDS * 4);
     L.binstart = take((size_t)L.big_cap * 256 * 4);
     L.cnt = take((size_t)L.big_tile_cap * 256 * 4);
     L.gtot = take((size_t)L.group_cap * 256 * 4);
@@ -139,6 +142,8 @@ Ctx make_ctx(void* ws, uint64_t n, uint64_t n_segs, bool learned = false) {
     c.rad.segs = c.at<SegDesc>(c.L.segs);
     c.rad.bigs = c.at<BigDesc>(c.L.bigs);
     c.rad.korand = c.at<uint64_t>(c.L.korand);
+    c.rad.segvary = c.at<uint64_t>(c.L.segvary);
+    c.rad.prog = c.at<uint32_t>(c.L.prog);
     c.rad.binstart = c.at<uint32_t>(c.L.binstart);
     c.rad.cnt = c.at<uint32_t>(c.L.cnt);
     c.rad.gtot = c.at<uint32_t>(c.L.gtot);
@@ -412,6 +417,8 @@ static husky_status sort_common(husky_coder coder, const void* elems, const uint
     const uint32_t tb = tiles_bound(n, n_segs, tn.rc);
     HUSKY_TRY(radix_reduce_tiles(codes, tb, c.rad, tn.rc, s));
     HUSKY_TRY(radix_exec_masks(0, end_bit, (uint32_t)n_segs, tb, c.rad, tn.rc, s));
+    // every pass is launched (no host synchronisation); passes no instance
+    // needs end at once
     HUSKY_TRY(radix_sort_segments(codes, perm, codes_b, c.at<uint32_t>(c.L.idx_b), 0, end_bit,
                                   (uint32_t)n_segs, tb, ~0u, c.rad, tn.rc, P_SCATTER, s));
     // the sorted codes are not needed once the runs are listed, so the

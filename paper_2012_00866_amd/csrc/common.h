@@ -41,7 +41,18 @@ enum : uint32_t {
     C_NUM_SEGS = 19,   // number of segments
     C_NUM_GROUPS = 20, // scan groups over the multi-tile segments
     C_EXEC_UNION = 21, // OR of the pass masks of all multi-tile segments
+    C_VARY_LO = 22,    // OR of the varying bits of all multi-tile segments,
+    C_VARY_HI = 23,    //   low and high words
+    C_EXEC_DONE = 24,  // big segments whose varying bits are known
 };
+
+// Digit programs of the multi-tile passes: the bits that vary in any
+// multi-tile segment, packed from the least significant up, form the digits
+// (pass p takes packed bits [p * BITS, p * BITS + BITS)).  Per pass PROG_WORDS
+// words: the number of runs, then one word per run of key bits that are
+// adjacent both in the key and in the digit: source shift | length << 8 |
+// destination shift << 16.
+constexpr int PROG_WORDS = 9;
 
 // Largest s < ns with segs[s].first_tile <= tile (segments in tile order).
 __device__ __forceinline__ uint32_t find_seg(const SegDesc* segs, uint32_t ns, uint32_t tile) {

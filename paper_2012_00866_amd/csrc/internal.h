@@ -52,6 +52,8 @@ struct RadixScratch {
     uint32_t* cnt;         // [big_tile_cap][256] tile digit counts / offsets
     uint32_t* gtot;        // [group_cap][256] group totals / offsets
     uint32_t* counters;    // [64]: tile and segment totals (see common.h)
+    uint64_t* segvary;     // [big_cap] bits that vary inside each big segment
+    uint32_t* prog;        // [MAX_PASSES * PROG_WORDS] digit programs (common.h)
     uint32_t seg_cap, big_cap, big_tile_cap, group_cap;
 };
 
@@ -68,8 +70,9 @@ hipError_t radix_segments_from_items(const RunItem* items, const uint32_t* count
                                      const RadixConfig& cfg, hipStream_t s);
 
 // Bits that vary inside every big segment: per-tile OR / AND of the keys
-// (skipped by callers whose key kernel already wrote them), then each big
-// segment's mask of digit passes and their union (counters[C_EXEC_UNION]).
+// (skipped by callers whose key kernel already wrote them), then the digit
+// programs over the bits that vary in any big segment, each big segment's
+// mask of digit passes and their union (counters[C_EXEC_UNION]).
 hipError_t radix_reduce_tiles(const uint64_t* keys, uint32_t max_tiles, const RadixScratch& sc,
                               const RadixConfig& cfg, hipStream_t s);
 hipError_t radix_exec_masks(int begin_bit, int end_bit, uint32_t max_segs, uint32_t max_tiles,

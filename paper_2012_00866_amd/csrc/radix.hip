@@ -11,13 +11,22 @@
 //  * segments: contiguous position ranges sorted independently (one for a
 //    single sort, one per instance for the batched form, one per long run of
 //    equal codes for the device-wide fix-up);
+//  * the multi-tile passes take their digits over the bits that vary, packed,
+//    when that needs fewer passes than fixed-width digits: a key bit that has
+//    the same value in every key of a segment cannot change the segment's
+//    order, so the varying bits, kept in order and packed from the least
+//    significant up, are sorted instead of the whole key (digits vary in 4 of
+//    every 7 bits, lowercase letters in 5, when no string stops inside the
+//    coded prefix);
 //  * a segment of at most one tile (256 threads x ITEMS keys) is sorted
 //    entirely in LDS by one workgroup (k_tile_sort), digit passes whose digit
-//    is the same in every key of the segment skipped;
+//    is the same in every key of the segment skipped (packing pays less
+//    there than the extra work of building digits from several runs);
 //  * longer ("big") segments: one reduction finds the bits that vary inside
-//    each segment (OR and AND of its keys); a digit pass over bits that do
-//    not vary is skipped.  Every remaining pass is reduce-then-scan with no
-//    dependency chain between tiles:
+//    each segment (OR and AND of its keys); the digit programs pack the bits
+//    that vary in any big segment, and a pass that takes no bit varying
+//    inside a segment is skipped for it.  Every remaining pass is
+//    reduce-then-scan with no dependency chain between tiles:
 //      k_count      digit counts of every tile,
 //      k_group_scan exclusive scan of the counts over groups of 64 tiles,
 //      k_seg_scan   scan over a segment's groups, and the digit starts,
@@ -145,6 +154,9 @@ __global__ __launch_bounds__(BLOCK) void k_seg_setup(Src src, SegDesc* segs, Big
         counters[C_NUM_SEGS] = S;
         counters[C_NUM_GROUPS] = carry_grp;
         counters[C_EXEC_UNION] = 0;
+        counters[C_VARY_LO] = 0;
+        counters[C_VARY_HI] = 0;
+        counters[C_EXEC_DONE] = 0;
     }
 }
 
@@ -243,15 +255,92 @@ __global__ __launch_bounds__(BLOCK) void k_orand(const uint64_t* __restrict__ ke
     }
 }
 
-// Digit passes a big segment runs: those whose bits vary inside it.
+// The digit programs over the union of the varying bits, and every big
+// segment's mask of passes (run by one workgroup, the last of k_exec):
+// packed bit c is key bit number c among the union's bits, pass c / BITS,
+// digit bit c % BITS -- or, when packing saves no pass, BITS-wide windows from
+// begin_bit that hold a varying bit.  A segment runs the passes that take a
+// bit varying inside it.  Packing keeps the order of the bits, and a bit
+// outside the union is constant inside every segment, so the passes sort
+// each segment by its keys.
+template <int BITS>
+__device__ void build_programs(BigDesc* __restrict__ bigs, uint32_t* __restrict__ counters,
+                               const uint64_t* __restrict__ segvary, uint32_t* __restrict__ prog,
+                               int begin_bit, int end_bit, uint32_t nb, uint32_t* s_prog,
+                               uint64_t* s_pm, uint32_t* s_or) {
+    if (threadIdx.x == 0) {
+        for (int i = 0; i < MAX_PASSES * PROG_WORDS; ++i) s_prog[i] = 0;
+        for (int p = 0; p < MAX_PASSES; ++p) s_pm[p] = 0;
+        const uint64_t u = (uint64_t)__hip_atomic_load(&counters[C_VARY_LO], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) |
+                           ((uint64_t)__hip_atomic_load(&counters[C_VARY_HI], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) << 32);
+        const uint64_t range = (end_bit >= 64 ? ~0ull : (1ull << end_bit) - 1ull);
+        int nw = 0;
+        for (int sh = begin_bit; sh < end_bit; sh += BITS) nw += ((u >> sh) & ((1ull << BITS) - 1ull)) ? 1 : 0;
+        const bool packed = (__popcll(u) + BITS - 1) / BITS < nw;
+        int c = 0, prev = -2;
+        for (int sh = begin_bit; sh < end_bit && !packed; sh += BITS) {
+            const uint64_t wm = (((1ull << BITS) - 1ull) << sh) & range;
+            if (!(u & wm)) continue;
+            const int len = end_bit - sh < BITS ? end_bit - sh : BITS;
+            s_prog[c * PROG_WORDS] = 1;
+            s_prog[c * PROG_WORDS + 1] = (uint32_t)sh | ((uint32_t)len << 8);
+            s_pm[c] = wm;
+            ++c;
+        }
+        for (int b = 0; b < 64 && packed; ++b) {
+            if (!((u >> b) & 1ull)) continue;
+            const int p = c / BITS, db = c % BITS;
+            uint32_t* pp = s_prog + p * PROG_WORDS;
+            if (db > 0 && prev == b - 1) {
+                pp[pp[0]] += 1u << 8;  // one more bit in the pass's last run
+            } else {
+                pp[0] += 1u;
+                pp[pp[0]] = (uint32_t)b | (1u << 8) | ((uint32_t)db << 16);
+            }
+            s_pm[p] |= 1ull << b;
+            prev = b;
+            ++c;
+        }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < MAX_PASSES * PROG_WORDS; i += BLOCK) prog[i] = s_prog[i];
+    uint32_t all = 0;
+    for (uint32_t b = threadIdx.x; b < nb; b += BLOCK) {
+        const uint64_t v = load_agent(&segvary[b]);  // written by other workgroups
+        uint32_t m = 0;
+#pragma unroll
+        for (int p = 0; p < MAX_PASSES; ++p) m |= (v & s_pm[p]) ? 1u << p : 0u;
+        bigs[b].exec = m;
+        all |= m;
+    }
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) all |= __shfl_xor(all, d, WAVE);
+    if (lane_id() == 0) s_or[threadIdx.x / WAVE] = all;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t u = 0;
+        for (int w = 0; w < NWAVES; ++w) u |= s_or[w];
+        counters[C_EXEC_UNION] = u;
+    }
+}
+
+// Bits that vary inside every big segment (within [begin_bit, end_bit)) and
+// their union; the workgroup that finishes last builds the digit programs.
 template <int BITS>
 __global__ __launch_bounds__(BLOCK) void k_exec(BigDesc* __restrict__ bigs,
                                                 uint32_t* __restrict__ counters,
                                                 const uint64_t* __restrict__ korand,
-                                                int begin_bit, int end_bit) {
+                                                uint64_t* __restrict__ segvary,
+                                                uint32_t* __restrict__ prog, int begin_bit,
+                                                int end_bit) {
     __shared__ uint64_t s_o[NWAVES], s_a[NWAVES];
+    __shared__ uint32_t s_prog[MAX_PASSES * PROG_WORDS];
+    __shared__ uint64_t s_pm[MAX_PASSES];
+    __shared__ uint32_t s_or[NWAVES];
+    __shared__ uint32_t s_last;
     const uint32_t b = blockIdx.x;
-    if (b >= counters[C_NUM_BIG]) return;
+    const uint32_t nb = counters[C_NUM_BIG];
+    if (b >= nb) return;
     const BigDesc B = bigs[b];
     uint64_t o = 0, a = ~0ull;
     for (uint32_t t = threadIdx.x; t < B.ntiles; t += BLOCK) {
@@ -260,16 +349,18 @@ __global__ __launch_bounds__(BLOCK) void k_exec(BigDesc* __restrict__ bigs,
     }
     block_or_and(o, a, s_o, s_a);
     if (threadIdx.x == 0) {
-        const uint64_t vary = o ^ a;
-        uint32_t mask = 0;
-        int p = 0;
-        for (int sh = begin_bit; sh < end_bit; sh += BITS, ++p) {
-            const uint32_t dm = (1u << min(BITS, end_bit - sh)) - 1u;
-            if ((uint32_t)(vary >> sh) & dm) mask |= 1u << p;
-        }
-        bigs[b].exec = mask;
-        atomicOr(&counters[C_EXEC_UNION], mask);
+        const uint64_t range = (end_bit >= 64 ? ~0ull : (1ull << end_bit) - 1ull) & ~((1ull << begin_bit) - 1ull);
+        const uint64_t vary = (o ^ a) & range;
+        store_agent(&segvary[b], vary);
+        if ((uint32_t)vary) atomicOr(&counters[C_VARY_LO], (uint32_t)vary);
+        if (vary >> 32) atomicOr(&counters[C_VARY_HI], (uint32_t)(vary >> 32));
+        __threadfence();
+        s_last = atomicAdd(&counters[C_EXEC_DONE], 1u) == nb - 1 ? 1u : 0u;
     }
+    __syncthreads();
+    if (!s_last) return;
+    __threadfence();
+    build_programs<BITS>(bigs, counters, segvary, prog, begin_bit, end_bit, nb, s_prog, s_pm, s_or);
 }
 
 __device__ __forceinline__ bool pass_runs(const BigDesc& B, int pass, bool& flip) {
@@ -284,8 +375,8 @@ __global__ __launch_bounds__(BLOCK) void k_count(const uint64_t* __restrict__ ke
                                                  const uint64_t* __restrict__ keysB,
                                                  const BigDesc* __restrict__ bigs,
                                                  const uint32_t* __restrict__ counters,
-                                                 uint32_t* __restrict__ cnt, int pass, int shift,
-                                                 uint32_t dmask) {
+                                                 uint32_t* __restrict__ cnt, int pass,
+                                                 const uint32_t* __restrict__ prog) {
     constexpr int R = 1 << BITS;
     constexpr uint32_t TILE = BLOCK * ITEMS;
     __shared__ uint32_t s_h[NWAVES * R];
@@ -296,6 +387,11 @@ __global__ __launch_bounds__(BLOCK) void k_count(const uint64_t* __restrict__ ke
     bool flip;
     if (!pass_runs(B, pass, flip)) return;
     const uint64_t* src = flip ? keysB : keysA;
+    DigitProg dp;
+    dp.load(prog, pass);
+    // a program of one run (the usual case) needs no run loop
+    const bool single = dp.nr <= 1;
+    const uint32_t s0 = dp.run[0] & 63u, m0 = (1u << ((dp.run[0] >> 8) & 15u)) - 1u;
     const uint32_t lt = t - B.first_tile;
     const uint32_t base = B.start + lt * TILE;
     const uint32_t nvalid = min(TILE, B.len - lt * TILE);
@@ -307,7 +403,7 @@ __global__ __launch_bounds__(BLOCK) void k_count(const uint64_t* __restrict__ ke
     for (int k = 0; k < ITEMS; ++k) {
         const uint32_t p = w * WAVE * ITEMS + k * WAVE + lane;
         const bool ok = p < nvalid;
-        const uint32_t dg = ok ? (uint32_t)(src[base + p] >> shift) & dmask : 0u;
+        const uint32_t dg = ok ? (single ? (uint32_t)(src[base + p] >> s0) & m0 : dp.digit(src[base + p])) : 0u;
         const uint32_t d0 = readlane(dg, 0);
         // a wavefront whose 64 digits agree adds 64 once
         if (ballot(ok && dg == d0) == ~0ull) {
@@ -397,8 +493,8 @@ __global__ __launch_bounds__(BLOCK) void k_scatter(
     uint64_t* __restrict__ keysA, uint32_t* __restrict__ valsA, uint64_t* __restrict__ keysB,
     uint32_t* __restrict__ valsB, const BigDesc* __restrict__ bigs,
     const uint32_t* __restrict__ counters, const uint32_t* __restrict__ cnt,
-    const uint32_t* __restrict__ gtot, const uint32_t* __restrict__ binstart, int pass, int shift,
-    uint32_t dmask) {
+    const uint32_t* __restrict__ gtot, const uint32_t* __restrict__ binstart, int pass,
+    const uint32_t* __restrict__ prog) {
     constexpr int R = 1 << BITS;
     constexpr uint32_t TILE = BLOCK * ITEMS;
     __shared__ uint64_t s_buf[TILE];
@@ -421,12 +517,24 @@ __global__ __launch_bounds__(BLOCK) void k_scatter(
     const uint32_t base = B.start + lt * TILE;
     const uint32_t nvalid = min(TILE, B.len - lt * TILE);
 
+    DigitProg dp;
+    dp.load(prog, pass);
     uint64_t k[ITEMS];
     uint32_t v[ITEMS];
     load_striped<ITEMS>(ksrc, vsrc, base, nvalid, k, v);
-    uint32_t pos[ITEMS];
+    // a program of one run (the usual case) needs no run loop
+    const bool single = dp.nr <= 1;
+    const uint32_t s0 = dp.run[0] & 63u, m0 = (1u << ((dp.run[0] >> 8) & 15u)) - 1u;
+    uint32_t pos[ITEMS], dig[ITEMS];
+    if (single) {
+#pragma unroll
+        for (int i = 0; i < ITEMS; ++i) dig[i] = (uint32_t)(k[i] >> s0) & m0;
+    } else {
+#pragma unroll
+        for (int i = 0; i < ITEMS; ++i) dig[i] = dp.digit(k[i]);
+    }
     uint32_t bc = 0;
-    rank_tile<BITS, ITEMS>(k, shift, dmask, nvalid, pos, s_whist, s_binstart, s_scan, &bc);
+    rank_digits<BITS, ITEMS>(dig, nvalid, pos, s_whist, s_binstart, s_scan, &bc);
     if (tid < (uint32_t)R) {
         const uint32_t g = B.first_group + lt / GROUP_TILES;
         s_gbase[tid] = binstart[(size_t)b * 256 + tid] + gtot[(size_t)g * 256 + tid] +
@@ -442,7 +550,7 @@ __global__ __launch_bounds__(BLOCK) void k_scatter(
         dst[i] = 0;
         if (p < nvalid) {
             const uint64_t key = s_buf[p];
-            dst[i] = s_gbase[(uint32_t)(key >> shift) & dmask] + p;
+            dst[i] = s_gbase[single ? (uint32_t)(key >> s0) & m0 : dp.digit(key)] + p;
             kdst[dst[i]] = key;
         }
     }
@@ -599,7 +707,7 @@ static hipError_t exec_impl(int begin_bit, int end_bit, uint32_t max_segs, uint3
     const uint32_t max_big = std::min(std::min(sc.big_cap, max_tiles / 2 + 1), std::max(max_segs, 1u));
     ProfScope ps(P_VARY, s);
     hipLaunchKernelGGL((k_exec<BITS>), dim3(max_big), dim3(BLOCK), 0, s, sc.bigs, sc.counters,
-                       sc.korand, begin_bit, end_bit);
+                       sc.korand, sc.segvary, sc.prog, begin_bit, end_bit);
     return hipGetLastError();
 }
 
@@ -623,14 +731,13 @@ static hipError_t sort_impl(uint64_t* keys, uint32_t* vals, uint64_t* keys_alt,
     // max_segs segments
     const uint32_t max_big = std::min(std::min(sc.big_cap, max_tiles / 2 + 1), std::max(max_segs, 1u));
     const uint32_t max_groups = std::min(sc.group_cap, max_tiles / GROUP_TILES + max_big + 1);
+    // packed varying bits never outnumber the key bits in [begin_bit, end_bit)
     for (int p = 0; p < npasses; ++p) {
         if (!((pass_union >> p) & 1u)) continue;
-        const int shift = begin_bit + p * BITS;
-        const uint32_t dmask = (1u << std::min(BITS, end_bit - shift)) - 1u;  // top digit may be narrower
         {
             ProfScope ps(P_COUNT_SCAN, s);
             hipLaunchKernelGGL((k_count<BITS, ITEMS>), dim3(max_tiles), dim3(BLOCK), 0, s, keys,
-                               keys_alt, bigs, sc.counters, sc.cnt, p, shift, dmask);
+                               keys_alt, bigs, sc.counters, sc.cnt, p, sc.prog);
             hipLaunchKernelGGL((k_group_scan<BITS>), dim3(max_groups), dim3(BLOCK), 0, s, bigs,
                                sc.counters, sc.cnt, sc.gtot, p);
             hipLaunchKernelGGL((k_seg_scan<BITS>), dim3(max_big), dim3(BLOCK), 0, s, bigs,
@@ -639,7 +746,7 @@ static hipError_t sort_impl(uint64_t* keys, uint32_t* vals, uint64_t* keys_alt,
         ProfScope ps(pclass, s);
         hipLaunchKernelGGL((k_scatter<BITS, ITEMS>), dim3(max_tiles), dim3(BLOCK), 0, s, keys,
                            vals, keys_alt, vals_alt, bigs, sc.counters, sc.cnt, sc.gtot,
-                           sc.binstart, p, shift, dmask);
+                           sc.binstart, p, sc.prog);
     }
     ProfScope ps(P_COPY_BACK, s);
     hipLaunchKernelGGL(k_copy_back, dim3(max_tiles), dim3(BLOCK), 0, s, keys, vals, keys_alt,

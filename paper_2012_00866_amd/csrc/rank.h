@@ -131,6 +131,30 @@ __device__ __forceinline__ void tile_running_max(uint32_t (&v)[ITEMS], uint32_t*
     __syncthreads();
 }
 
+// One pass's digit program (common.h), held in scalar registers.
+struct DigitProg {
+    uint32_t nr;
+    uint32_t run[PROG_WORDS - 1];
+    __device__ __forceinline__ void load(const uint32_t* __restrict__ prog, int pass) {
+        const uint32_t* p = prog + pass * PROG_WORDS;
+        nr = p[0];
+#pragma unroll
+        for (int r = 0; r < PROG_WORDS - 1; ++r) run[r] = (uint32_t)r < nr ? p[1 + r] : 0u;
+    }
+    __device__ __forceinline__ uint32_t digit(uint64_t key) const {
+        // the first run starts at digit bit 0
+        uint32_t d = (uint32_t)(key >> (run[0] & 63u)) & ((1u << ((run[0] >> 8) & 15u)) - 1u);
+#pragma unroll
+        for (int r = 1; r < PROG_WORDS - 1; ++r) {
+            if ((uint32_t)r >= nr) break;
+            const uint32_t w = run[r];
+            const uint32_t len = (w >> 8) & 15u;
+            d |= ((uint32_t)(key >> (w & 63u)) & ((1u << len) - 1u)) << ((w >> 16) & 15u);
+        }
+        return d;
+    }
+};
+
 template <int ITEMS>
 __device__ __forceinline__ void load_striped(const uint64_t* __restrict__ keys,
                                              const uint32_t* __restrict__ vals, uint32_t base,
