@@ -31,6 +31,7 @@ namespace husky {
 constexpr uint32_t LUT_CELLS = 1u << 24;
 constexpr uint32_t SUB_SLOT = 16;  // sub-cell table entries per bucket
 constexpr int INLINE_PREFIX_BITS = 19;
+constexpr int LEARNED_K = 4;  // keys whose bucket lookups one thread of the encode kernel overlaps
 
 struct BucketArgs {
     const husky_learned_header* hdr;
@@ -47,52 +48,93 @@ __device__ __forceinline__ uint32_t window_of(uint64_t code, uint64_t lo, uint64
     return cp >= 64 ? 0u : (uint32_t)((c << cp) >> 40);
 }
 
-__device__ __forceinline__ uint32_t bucket_of(const BucketArgs& a, uint64_t code, uint64_t lo,
-                                              uint64_t hi, uint32_t cp) {
-    const uint64_t ci = a.cellinfo[window_of(code, lo, hi, cp)];
-    const uint32_t b0 = (uint32_t)ci & 0xFFFFu, b1 = (uint32_t)(ci >> 16) & 0xFFFFu;
-    if (b1 < b0 + 2) return b0;
-    const uint64_t c = code < lo ? lo : (code > hi ? hi : code);
-    const uint32_t k = b1 - b0;
-    uint32_t P, s;
-    bool below, above;
-    if (ci >> 63) {
-        const uint4 h = *reinterpret_cast<const uint4*>(a.subtab + SUB_SLOT * b0);
-        P = h.x & 0xFFFFu;
-        s = h.x >> 16;
-        const uint64_t prefix = (uint64_t)h.z | ((uint64_t)h.w << 32);
-        const uint64_t ct = P >= 64 ? c : (P ? c >> (64 - P) : 0ull);
-        const uint64_t pt = P >= 64 ? prefix : (P ? prefix >> (64 - P) : 0ull);
-        below = ct < pt;
-        above = ct > pt;
-    } else {
-        P = (uint32_t)(ci >> 32) & 127u;
-        s = (uint32_t)(ci >> 39) & 31u;
-        const uint32_t e = P - cp - 24u;  // prefix bits below the cell, <= 19
-        const uint32_t extra = (uint32_t)(ci >> 44) & ((1u << INLINE_PREFIX_BITS) - 1u);
-        const uint32_t kx = e ? (uint32_t)((c << (cp + 24)) >> (64 - e)) : 0u;
-        below = kx < extra;
-        above = kx > extra;
+// The buckets of K keys at once (ok[j] false: no key, out[j] left 0).  The
+// steps run side by side over the K keys so that each step's table reads for
+// all of them are in flight together.
+template <int K>
+__device__ __forceinline__ void bucket_of(const BucketArgs& a, const uint64_t (&code)[K],
+                                          const bool (&ok)[K], uint64_t lo, uint64_t hi, uint32_t cp,
+                                          uint32_t (&out)[K]) {
+    uint64_t c[K], ci[K];
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+        c[j] = code[j] < lo ? lo : (code[j] > hi ? hi : code[j]);
+        ci[j] = ok[j] ? a.cellinfo[window_of(code[j], lo, hi, cp)] : 0ull;
     }
-    uint32_t x, y;
-    if (below) {
-        x = y = 0;
-    } else if (above) {
-        x = y = k - 1;
-    } else if (s) {
-        const uint32_t v = (uint32_t)((c << P) >> (64 - s));
-        const uint16_t* t = a.subtab + SUB_SLOT * b0 + 8;
-        x = t[v];
-        y = v + 1 < (1u << s) ? t[v + 1] : k - 1;
-    } else {
-        x = 0;
-        y = k - 1;
+    uint32_t b0[K], kk[K];
+    bool heavy[K];
+    uint4 h[K];
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+        b0[j] = (uint32_t)ci[j] & 0xFFFFu;
+        const uint32_t b1 = (uint32_t)(ci[j] >> 16) & 0xFFFFu;
+        heavy[j] = ok[j] && b1 >= b0[j] + 2;
+        kk[j] = b1 - b0[j];
+        h[j] = heavy[j] && (ci[j] >> 63) ? *reinterpret_cast<const uint4*>(a.subtab + SUB_SLOT * b0[j])
+                                         : make_uint4(0, 0, 0, 0);
     }
-    while (x < y) {  // splitters[b0 + .] <= c
-        const uint32_t mid = (x + y) >> 1;
-        if (a.splitters[b0 + mid] <= c) x = mid + 1; else y = mid;
+    uint32_t x[K], y[K], v[K], P[K], s[K];
+    bool look[K];
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+        bool below = false, above = false;
+        P[j] = s[j] = 0;
+        if (!heavy[j]) {
+            // a cell of one bucket
+        } else if (ci[j] >> 63) {
+            P[j] = h[j].x & 0xFFFFu;
+            s[j] = h[j].x >> 16;
+            const uint64_t prefix = (uint64_t)h[j].z | ((uint64_t)h[j].w << 32);
+            const uint64_t ct = P[j] >= 64 ? c[j] : (P[j] ? c[j] >> (64 - P[j]) : 0ull);
+            const uint64_t pt = P[j] >= 64 ? prefix : (P[j] ? prefix >> (64 - P[j]) : 0ull);
+            below = ct < pt;
+            above = ct > pt;
+        } else {
+            P[j] = (uint32_t)(ci[j] >> 32) & 127u;
+            s[j] = (uint32_t)(ci[j] >> 39) & 31u;
+            const uint32_t e = P[j] - cp - 24u;  // prefix bits below the cell, <= 19
+            const uint32_t extra = (uint32_t)(ci[j] >> 44) & ((1u << INLINE_PREFIX_BITS) - 1u);
+            const uint32_t kx = e ? (uint32_t)((c[j] << (cp + 24)) >> (64 - e)) : 0u;
+            below = kx < extra;
+            above = kx > extra;
+        }
+        look[j] = heavy[j] && !below && !above && s[j];
+        v[j] = look[j] ? (uint32_t)((c[j] << P[j]) >> (64 - s[j])) : 0u;
+        x[j] = below ? 0u : (above ? kk[j] - 1 : 0u);
+        y[j] = below ? 0u : (above ? kk[j] - 1 : kk[j] - 1);
+        if (!heavy[j]) x[j] = y[j] = 0;
     }
-    return b0 + x;
+    // the sub-cell's splitter range
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+        if (look[j]) {
+            const uint16_t* t = a.subtab + SUB_SLOT * b0[j] + 8;
+            const uint32_t tx = t[v[j]];
+            const uint32_t ty = v[j] + 1 < (1u << s[j]) ? t[v[j] + 1] : kk[j] - 1;
+            x[j] = tx;
+            y[j] = ty;
+        }
+    }
+    // splitters[b0 + .] <= c, all K searches advancing together
+    for (;;) {
+        bool any = false;
+        uint32_t mid[K];
+        uint64_t sp[K];
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+            mid[j] = (x[j] + y[j]) >> 1;
+            sp[j] = x[j] < y[j] ? a.splitters[b0[j] + mid[j]] : 0ull;
+            any = any || x[j] < y[j];
+        }
+        if (!any) break;
+#pragma unroll
+        for (int j = 0; j < K; ++j)
+            if (x[j] < y[j]) {
+                if (sp[j] <= c[j]) x[j] = mid[j] + 1; else y[j] = mid[j];
+            }
+    }
+#pragma unroll
+    for (int j = 0; j < K; ++j) out[j] = ok[j] ? b0[j] + (heavy[j] ? x[j] : 0u) : 0u;
 }
 
 }  // namespace husky

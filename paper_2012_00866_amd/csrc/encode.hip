@@ -44,7 +44,9 @@ __global__ __launch_bounds__(BLOCK) void k_encode(const uint8_t* __restrict__ by
         m_hi = bucket.hdr->hi;
         m_cp = bucket.hdr->cp;
     }
-    for (uint32_t t = blockIdx.x * BLOCK + threadIdx.x; t < count; t += gridDim.x * BLOCK) {
+    // Step 1 for entry t: writes its code (and index, first refinement key)
+    // and returns the code
+    auto encode_one = [&](uint32_t t) -> uint64_t {
         const uint32_t i = sel ? sel[t] : t;
         const uint64_t o0 = offsets[i], o1 = offsets[i + 1];
         const uint64_t len = o1 - o0;
@@ -107,7 +109,30 @@ __global__ __launch_bounds__(BLOCK) void k_encode(const uint8_t* __restrict__ by
         if (codes) codes[t] = code;
         if (idx) idx[t] = i;
         if (key0) key0[t] = k0;
-        if (LEARNED) bucket.bid[t] = (uint16_t)bucket_of(bucket, code, m_lo, m_hi, m_cp);
+        return code;
+    };
+    if (!LEARNED) {
+        for (uint32_t t = blockIdx.x * BLOCK + threadIdx.x; t < count; t += gridDim.x * BLOCK)
+            encode_one(t);
+    } else {
+        // LEARNED_K entries per thread (BLOCK apart, so stores stay coalesced),
+        // their bucket lookups in flight together (bucket.h)
+        for (uint32_t t0 = blockIdx.x * BLOCK * LEARNED_K + threadIdx.x; t0 < count;
+             t0 += gridDim.x * BLOCK * LEARNED_K) {
+            uint64_t cd[LEARNED_K];
+            bool ok[LEARNED_K];
+#pragma unroll
+            for (int j = 0; j < LEARNED_K; ++j) {
+                const uint32_t t = t0 + j * BLOCK;
+                ok[j] = t < count;
+                cd[j] = ok[j] ? encode_one(t) : 0ull;
+            }
+            uint32_t b[LEARNED_K];
+            bucket_of<LEARNED_K>(bucket, cd, ok, m_lo, m_hi, m_cp, b);
+#pragma unroll
+            for (int j = 0; j < LEARNED_K; ++j)
+                if (ok[j]) bucket.bid[t0 + j * BLOCK] = (uint16_t)b[j];
+        }
     }
     if (CODER == 0 && status) {
         // one atomic per wavefront that saw a violation
@@ -127,7 +152,8 @@ hipError_t launch_encode(int coder, const void* elems, const uint64_t* offsets, 
                          const BucketArgs* bucket) {
     const uint32_t count = sel ? n_out : n;
     if (count == 0) return hipSuccess;
-    const uint32_t blocks = (count + BLOCK - 1) / BLOCK;
+    const uint32_t per_block = bucket ? BLOCK * LEARNED_K : BLOCK;
+    const uint32_t blocks = (count + per_block - 1) / per_block;
     ProfScope ps(P_ENCODE, s);
     const BucketArgs b = bucket ? *bucket : BucketArgs{};
     const uint8_t* e = (const uint8_t*)elems;

@@ -977,7 +977,9 @@ __global__ __launch_bounds__(256) void k_bucket_classes(const uint64_t* __restri
 // Every later refinement round proceeds as for any run.
 // One size class of buckets: lmin < len <= lmax (and 2 <= len <= NW * 64 * ITEMS),
 // one workgroup of NW wavefronts per bucket.
-// Per item: its key and one word sr = slot | run start << 16 (both < 2^16).
+// Per item: its key and one word sr = slot | run start << 16 | the first
+// refinement key continues << 31 (slot < 2^16, run start < 2^15).  Keys are
+// sorted packed to their varying bits when that saves a digit pass.
 template <int CODER, int ITEMS, int NW>
 __global__ __launch_bounds__(NW * WAVE) void k_bucket_refine(uint64_t* __restrict__ codes,
                                                          uint32_t* __restrict__ perm,
@@ -988,7 +990,7 @@ __global__ __launch_bounds__(NW * WAVE) void k_bucket_refine(uint64_t* __restric
                                                          RunItem* __restrict__ scan_list,
                                                          uint32_t* __restrict__ scan_count) {
     constexpr uint32_t TILE = NW * WAVE * ITEMS;
-    static_assert(TILE <= 65536, "slots and run starts fit 16 bits");
+    static_assert(TILE <= 32768, "slots fit 16 bits, run starts 15");
     __shared__ uint64_t s_k[TILE];
     __shared__ uint32_t s_sr[TILE];
     __shared__ uint32_t s_whist[NW * 256];
@@ -1057,7 +1059,7 @@ __global__ __launch_bounds__(NW * WAVE) void k_bucket_refine(uint64_t* __restric
         sr[i] = p;
     }
     // 1. by code
-    uint64_t vary = vary_of(k);
+    uint64_t vary = pack_varying(k, vary_of(k));  // (rank.h)
     for (int shift = 0; shift < code_bits; shift += 8) {
         const uint32_t dmask = (1u << min(8, code_bits - shift)) - 1u;
         if (!((uint32_t)(vary >> shift) & dmask)) continue;
@@ -1085,17 +1087,21 @@ __global__ __launch_bounds__(NW * WAVE) void k_bucket_refine(uint64_t* __restric
         for (int i = 0; i < ITEMS; ++i) sr[i] |= t[i] << 16;
         // 3. by (run start, refinement key), stable in slot
 #pragma unroll
-        for (int i = 0; i < ITEMS; ++i) k[i] = posof(i) < nvalid ? k0[start + (sr[i] & 0xFFFFu)] : ~0ull;
-        vary = vary_of(k);
+        for (int i = 0; i < ITEMS; ++i) {
+            k[i] = posof(i) < nvalid ? k0[start + (sr[i] & 0xFFFFu)] : ~0ull;
+            // whether the key continues, kept in bit 31 while the keys are packed
+            sr[i] |= posof(i) < nvalid && key_continues<CODER>(k[i]) ? 1u << 31 : 0u;
+        }
+        vary = pack_varying(k, vary_of(k));
         for (int shift = 0; shift < 64; shift += 8) {
             if (!((uint32_t)(vary >> shift) & 0xFFu)) continue;
 #pragma unroll
             for (int i = 0; i < ITEMS; ++i) dig[i] = (uint32_t)(k[i] >> shift) & 0xFFu;
             pass();
         }
-        for (int shift = 16; shift < 32; shift += 8) {  // run starts are < 2^16
+        for (int shift = 16; shift < 32; shift += 8) {  // run starts are < 2^15
 #pragma unroll
-            for (int i = 0; i < ITEMS; ++i) dig[i] = (sr[i] >> shift) & 0xFFu;
+            for (int i = 0; i < ITEMS; ++i) dig[i] = (sr[i] >> shift) & (shift == 24 ? 0x7Fu : 0xFFu);
             pass();
         }
         // 4. groups: same run, same key, and the key continues
@@ -1109,8 +1115,8 @@ __global__ __launch_bounds__(NW * WAVE) void k_bucket_refine(uint64_t* __restric
 #pragma unroll
         for (int i = 0; i < ITEMS; ++i) {
             const uint32_t p = posof(i);
-            const bool same = p > 0 && p < nvalid && (s_sr[p - 1] >> 16) == (sr[i] >> 16) &&
-                              s_k[p - 1] == k[i] && key_continues<CODER>(k[i]);
+            const bool same = p > 0 && p < nvalid && ((s_sr[p - 1] ^ sr[i]) & 0x7FFF0000u) == 0 &&
+                              s_k[p - 1] == k[i] && (sr[i] >> 31);
             tied = tied || same;
             t[i] = same ? 0u : p;
         }

@@ -155,6 +155,44 @@ struct DigitProg {
     }
 };
 
+// A 64-bit value that is the same in every lane, moved to scalar registers.
+__device__ __forceinline__ uint64_t uniform64(uint64_t x) {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)x);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(x >> 32));
+    return (uint64_t)lo | ((uint64_t)hi << 32);
+}
+
+// For a sort inside one workgroup: packs the bits of every key that vary
+// (`vary`, the same in every lane) into the key's low bits, in order, when
+// that saves an 8-bit digit pass, and returns the bits that vary afterwards.
+// Bits that do not vary cannot change the order of the keys or which keys
+// are equal, so the packed keys sort and compare like the keys.
+template <int ITEMS>
+__device__ __forceinline__ uint64_t pack_varying(uint64_t (&k)[ITEMS], uint64_t vary) {
+    vary = uniform64(vary);
+    int windows = 0;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) windows += ((vary >> (8 * j)) & 0xFFull) ? 1 : 0;
+    const int bits = __popcll(vary);
+    if ((bits + 7) / 8 >= windows) return vary;
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i) {
+        uint64_t m = vary, out = 0;
+        int dst = 0;
+        while (m) {  // runs of adjacent varying bits
+            const int s = __builtin_ctzll(m);
+            const uint64_t rest = ~(m >> s);
+            const int len = rest ? __builtin_ctzll(rest) : 64 - s;
+            const uint64_t run = len >= 64 ? ~0ull : (1ull << len) - 1ull;
+            out |= ((k[i] >> s) & run) << dst;
+            dst += len;
+            m &= ~(run << s);
+        }
+        k[i] = out;
+    }
+    return bits >= 64 ? ~0ull : (1ull << bits) - 1ull;
+}
+
 template <int ITEMS>
 __device__ __forceinline__ void load_striped(const uint64_t* __restrict__ keys,
                                              const uint32_t* __restrict__ vals, uint32_t base,
