@@ -586,33 +586,19 @@ template <int ITEMS>
 __global__ __launch_bounds__(BLOCK) void k_bcount(const uint16_t* __restrict__ bid, uint32_t n,
                                                   int shift, uint32_t* __restrict__ cnt) {
     constexpr uint32_t TILE = BLOCK * ITEMS;
-    __shared__ uint32_t s_h[NWAVES * 256];
+    __shared__ uint32_t s_h[HIST_WORDS];
     const uint32_t t = xcd_remap(blockIdx.x, gridDim.x), w = threadIdx.x / WAVE, lane = lane_id();
     const uint32_t base = t * TILE;
     if (base >= n) return;
     const uint32_t nvalid = min(TILE, n - base);
-    for (uint32_t i = threadIdx.x; i < NWAVES * 256; i += BLOCK) s_h[i] = 0;
-    __syncthreads();
-    uint32_t* my = s_h + w * 256;
-#pragma unroll 4
-    for (int k = 0; k < ITEMS; ++k) {
-        const uint32_t p = w * WAVE * ITEMS + k * WAVE + lane;
-        const bool ok = p < nvalid;
-        const uint32_t dg = ok ? ((uint32_t)bid[base + p] >> shift) & 255u : 0u;
-        const uint32_t d0 = readlane(dg, 0);
-        if (ballot(ok && dg == d0) == ~0ull) {
-            if (lane == 0) my[d0] += WAVE;
-        } else if (ok) {
-            atomicAdd(&my[dg], 1u);
-        }
-    }
-    __syncthreads();
-    for (uint32_t d = threadIdx.x; d < 256; d += BLOCK) {
-        uint32_t v = 0;
+    uint32_t b[ITEMS];
 #pragma unroll
-        for (int ww = 0; ww < NWAVES; ++ww) v += s_h[ww * 256 + d];
-        cnt[(size_t)t * 256 + d] = v;
+    for (int i = 0; i < ITEMS; ++i) {
+        const uint32_t p = w * WAVE * ITEMS + i * WAVE + lane;
+        b[i] = p < nvalid ? (uint32_t)bid[base + p] : 0u;
     }
+    tile_histogram<ITEMS>([&](int i) { return (b[i] >> shift) & 255u; }, nvalid, s_h,
+                          cnt + (size_t)t * 256);
 }
 
 template <int ITEMS, bool CARRY>

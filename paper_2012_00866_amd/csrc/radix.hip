@@ -377,9 +377,9 @@ __global__ __launch_bounds__(BLOCK) void k_count(const uint64_t* __restrict__ ke
                                                  const uint32_t* __restrict__ counters,
                                                  uint32_t* __restrict__ cnt, int pass,
                                                  const uint32_t* __restrict__ prog) {
-    constexpr int R = 1 << BITS;
+    static_assert(BITS <= 8, "cnt holds 256 digits per tile");
     constexpr uint32_t TILE = BLOCK * ITEMS;
-    __shared__ uint32_t s_h[NWAVES * R];
+    __shared__ uint32_t s_h[HIST_WORDS];
     const uint32_t nbt = counters[C_BIG_TILES];  // the grid is an upper bound
     if (blockIdx.x >= nbt) return;
     const uint32_t t = xcd_remap(blockIdx.x, nbt);
@@ -396,29 +396,15 @@ __global__ __launch_bounds__(BLOCK) void k_count(const uint64_t* __restrict__ ke
     const uint32_t base = B.start + lt * TILE;
     const uint32_t nvalid = min(TILE, B.len - lt * TILE);
     const uint32_t w = threadIdx.x / WAVE, lane = lane_id();
-    for (uint32_t i = threadIdx.x; i < (uint32_t)(NWAVES * R); i += BLOCK) s_h[i] = 0;
-    __syncthreads();
-    uint32_t* my = s_h + w * R;
-#pragma unroll 4
-    for (int k = 0; k < ITEMS; ++k) {
-        const uint32_t p = w * WAVE * ITEMS + k * WAVE + lane;
-        const bool ok = p < nvalid;
-        const uint32_t dg = ok ? (single ? (uint32_t)(src[base + p] >> s0) & m0 : dp.digit(src[base + p])) : 0u;
-        const uint32_t d0 = readlane(dg, 0);
-        // a wavefront whose 64 digits agree adds 64 once
-        if (ballot(ok && dg == d0) == ~0ull) {
-            if (lane == 0) my[d0] += WAVE;
-        } else if (ok) {
-            atomicAdd(&my[dg], 1u);
-        }
-    }
-    __syncthreads();
-    for (uint32_t d = threadIdx.x; d < (uint32_t)R; d += BLOCK) {
-        uint32_t v = 0;
+    uint64_t k[ITEMS];
 #pragma unroll
-        for (int ww = 0; ww < NWAVES; ++ww) v += s_h[ww * R + d];
-        cnt[(size_t)t * 256 + d] = v;
+    for (int i = 0; i < ITEMS; ++i) {
+        const uint32_t p = w * WAVE * ITEMS + i * WAVE + lane;
+        k[i] = p < nvalid ? src[base + p] : 0ull;
     }
+    tile_histogram<ITEMS>(
+        [&](int i) { return single ? (uint32_t)(k[i] >> s0) & m0 : dp.digit(k[i]); }, nvalid, s_h,
+        cnt + (size_t)t * 256);
 }
 
 // Exclusive scan of the tile counts inside each group of GROUP_TILES tiles
@@ -467,7 +453,8 @@ __global__ __launch_bounds__(BLOCK) void k_seg_scan(const BigDesc* __restrict__ 
     const uint32_t d = threadIdx.x;
     uint32_t run = 0;
     if (d < (uint32_t)R) {
-        constexpr int U = 16;
+        // up to 64 group totals in flight per thread (2^24 keys in one pass)
+        constexpr int U = 64;
         for (uint32_t g0 = 0; g0 < B.ngroups; g0 += U) {
             uint32_t v[U];
 #pragma unroll

@@ -83,6 +83,39 @@ __device__ __forceinline__ void rank_digits(uint32_t (&dig)[ITEMS], uint32_t nva
     for (int k = 0; k < ITEMS; ++k) pos[k] = s_binstart[dig[k]] + s_whist[w * R + dig[k]] + rank[k];
 }
 
+// ------------------------------------------------------------------ tile histogram
+// Counts of the 8-bit digits of one tile (wave-striped layout as above,
+// positions >= nvalid skipped): out[d] = number of items with digit d.
+// dig_of(i) gives item i's digit.  Every wavefront keeps HIST_COPIES
+// histograms, lane l adding to copy l % HIST_COPIES, so lanes holding the
+// same digit (skewed digits, or keys grouped by earlier passes) collide at
+// most 64 / HIST_COPIES ways on one LDS address instead of 64; rows are
+// HIST_STRIDE = 257 words apart, so the copies of one digit sit in different
+// banks.  s_h: NWAVES * HIST_COPIES * HIST_STRIDE words.  The caller issues
+// its loads first: the clearing here overlaps them.
+constexpr int HIST_COPIES = 4, HIST_STRIDE = 257, HIST_WORDS = NWAVES * HIST_COPIES * HIST_STRIDE;
+template <int ITEMS, typename F>
+__device__ __forceinline__ void tile_histogram(F dig_of, uint32_t nvalid, uint32_t* s_h,
+                                               uint32_t* __restrict__ out) {
+    const uint32_t w = threadIdx.x / WAVE, lane = lane_id();
+    for (uint32_t i = threadIdx.x; i < (uint32_t)HIST_WORDS; i += BLOCK) s_h[i] = 0;
+    __syncthreads();
+    uint32_t* my = s_h + (w * HIST_COPIES + lane % HIST_COPIES) * HIST_STRIDE;
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i) {
+        const uint32_t p = w * WAVE * ITEMS + i * WAVE + lane;
+        if (p < nvalid)
+            __hip_atomic_fetch_add(&my[dig_of(i)], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    }
+    __syncthreads();
+    for (uint32_t d = threadIdx.x; d < 256u; d += BLOCK) {
+        uint32_t v = 0;
+#pragma unroll
+        for (int r = 0; r < NWAVES * HIST_COPIES; ++r) v += s_h[r * HIST_STRIDE + d];
+        out[d] = v;
+    }
+}
+
 // The same ranking by the digit (key >> shift) & dmask, dmask < 2^BITS.
 template <int BITS, int ITEMS>
 __device__ __forceinline__ void rank_tile(const uint64_t (&keys)[ITEMS], int shift,

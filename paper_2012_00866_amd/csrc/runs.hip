@@ -25,14 +25,46 @@ __device__ __forceinline__ bool continues(uint64_t key) {
     return (key & 0xFull) == (CODER == 0 ? 8ull : 4ull);
 }
 
-// Flags of position i inside segment [s0, s1): multi-run head / tail.
+// Loads one tile's keys (wave-striped: item k of lane l of wave w is tile
+// position w*64*ITEMS + k*64 + l; positions >= nvalid are not read) and
+// stages them in LDS as s_k[1 + p], with the key before the tile at s_k[0]
+// when the segment [s0, s1) has one and the key after it at s_k[nvalid + 1]
+// likewise, so that every key is read from HBM once and its neighbours come
+// from LDS.  s_k: TILE + 2 words.
+template <int ITEMS>
+__device__ __forceinline__ void stage_keys(const uint64_t* __restrict__ keys, uint32_t base,
+                                           uint32_t nvalid, uint32_t s0, uint32_t s1,
+                                           uint64_t* s_k, uint64_t (&k)[ITEMS]) {
+    const uint32_t w = threadIdx.x / WAVE, lane = lane_id();
+    const bool want_prev = threadIdx.x == 0 && base > s0;
+    const bool want_next = threadIdx.x == 1 && base + nvalid < s1;
+    uint64_t halo = 0;
+    if (want_prev) halo = keys[base - 1];
+    if (want_next) halo = keys[base + nvalid];
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i) {
+        const uint32_t p = w * WAVE * ITEMS + i * WAVE + lane;
+        k[i] = p < nvalid ? keys[base + p] : 0ull;
+    }
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i) {
+        const uint32_t p = w * WAVE * ITEMS + i * WAVE + lane;
+        if (p < nvalid) s_k[1 + p] = k[i];
+    }
+    if (want_prev) s_k[0] = halo;
+    if (want_next) s_k[nvalid + 1] = halo;
+    __syncthreads();
+}
+
+// Flags of tile position p (absolute position base + p inside segment
+// [s0, s1), key kc) from the staged keys: multi-run head / tail.
 template <int CODER, bool REFINE>
-__device__ __forceinline__ void run_flags(const uint64_t* __restrict__ keys, uint32_t i,
-                                          uint32_t s0, uint32_t s1, bool& head, bool& tail) {
-    const uint64_t kc = keys[i];
-    const bool has_prev = i > s0, has_next = i + 1 < s1;
-    const bool eq_prev = has_prev && keys[i - 1] == kc;
-    const bool eq_next = has_next && keys[i + 1] == kc;
+__device__ __forceinline__ void run_flags(const uint64_t* s_k, uint64_t kc, uint32_t p,
+                                          uint32_t base, uint32_t s0, uint32_t s1, bool& head,
+                                          bool& tail) {
+    const bool has_prev = base + p > s0, has_next = base + p + 1 < s1;
+    const bool eq_prev = has_prev && s_k[p] == kc;
+    const bool eq_next = has_next && s_k[p + 2] == kc;
     const bool keep = REFINE ? continues<CODER>(kc) : true;
     head = keep && !eq_prev && eq_next;
     tail = keep && eq_prev && !eq_next;
@@ -44,6 +76,7 @@ __global__ __launch_bounds__(BLOCK) void k_runs_count(const uint64_t* __restrict
                                                       const uint32_t* __restrict__ counters,
                                                       uint32_t* __restrict__ tile_counts) {
     constexpr uint32_t TILE = BLOCK * ITEMS;
+    __shared__ uint64_t s_k[TILE + 2];
     __shared__ uint32_t s_cnt[NWAVES];
     const uint32_t t = blockIdx.x;
     if (t >= counters[C_ALL_TILES]) return;
@@ -52,12 +85,14 @@ __global__ __launch_bounds__(BLOCK) void k_runs_count(const uint64_t* __restrict
     const uint32_t base = d.start + lt * TILE;
     const uint32_t nvalid = min(TILE, d.len - lt * TILE);
     const uint32_t w = threadIdx.x / WAVE, lane = lane_id();
+    uint64_t k[ITEMS];
+    stage_keys<ITEMS>(keys, base, nvalid, d.start, d.start + d.len, s_k, k);
     uint32_t heads = 0;
 #pragma unroll
-    for (int k = 0; k < ITEMS; ++k) {
-        const uint32_t p = w * WAVE * ITEMS + k * WAVE + lane;
+    for (int i = 0; i < ITEMS; ++i) {
+        const uint32_t p = w * WAVE * ITEMS + i * WAVE + lane;
         bool h = false, tl = false;
-        if (p < nvalid) run_flags<CODER, REFINE>(keys, base + p, d.start, d.start + d.len, h, tl);
+        if (p < nvalid) run_flags<CODER, REFINE>(s_k, k[i], p, base, d.start, d.start + d.len, h, tl);
         heads += (uint32_t)__popcll(ballot(h));
     }
     if (lane == 0) s_cnt[w] = heads;
@@ -97,6 +132,7 @@ __global__ __launch_bounds__(BLOCK) void k_runs_write(const uint64_t* __restrict
                                                       uint32_t* __restrict__ run_end,
                                                       uint32_t* __restrict__ run_seg) {
     constexpr uint32_t TILE = BLOCK * ITEMS;
+    __shared__ uint64_t s_k[TILE + 2];
     __shared__ uint32_t s_h[NWAVES], s_t[NWAVES];
     const uint32_t t = blockIdx.x;
     if (t >= counters[C_ALL_TILES]) return;
@@ -106,16 +142,18 @@ __global__ __launch_bounds__(BLOCK) void k_runs_write(const uint64_t* __restrict
     const uint32_t base = d.start + lt * TILE;
     const uint32_t nvalid = min(TILE, d.len - lt * TILE);
     const uint32_t w = threadIdx.x / WAVE, lane = lane_id();
+    uint64_t k[ITEMS];
+    stage_keys<ITEMS>(keys, base, nvalid, d.start, d.start + d.len, s_k, k);
 
     bool hf[ITEMS], tf[ITEMS];
     uint32_t nh = 0, nt = 0;
 #pragma unroll
-    for (int k = 0; k < ITEMS; ++k) {
-        const uint32_t p = w * WAVE * ITEMS + k * WAVE + lane;
-        hf[k] = tf[k] = false;
-        if (p < nvalid) run_flags<CODER, REFINE>(keys, base + p, d.start, d.start + d.len, hf[k], tf[k]);
-        nh += (uint32_t)__popcll(ballot(hf[k]));
-        nt += (uint32_t)__popcll(ballot(tf[k]));
+    for (int i = 0; i < ITEMS; ++i) {
+        const uint32_t p = w * WAVE * ITEMS + i * WAVE + lane;
+        hf[i] = tf[i] = false;
+        if (p < nvalid) run_flags<CODER, REFINE>(s_k, k[i], p, base, d.start, d.start + d.len, hf[i], tf[i]);
+        nh += (uint32_t)__popcll(ballot(hf[i]));
+        nt += (uint32_t)__popcll(ballot(tf[i]));
     }
     if (lane == 0) {
         s_h[w] = nh;
@@ -127,8 +165,8 @@ __global__ __launch_bounds__(BLOCK) void k_runs_write(const uint64_t* __restrict
     {
         bool open = false;
         if (base > d.start) {
-            const uint64_t kc = keys[base];
-            open = keys[base - 1] == kc && (REFINE ? continues<CODER>(kc) : true);
+            const uint64_t kc = s_k[1];
+            open = s_k[0] == kc && (REFINE ? continues<CODER>(kc) : true);
         }
         tb = hb - (open ? 1u : 0u);
     }
@@ -137,15 +175,15 @@ __global__ __launch_bounds__(BLOCK) void k_runs_write(const uint64_t* __restrict
         tb += s_t[i];
     }
 #pragma unroll
-    for (int k = 0; k < ITEMS; ++k) {
-        const uint64_t bh = ballot(hf[k]), bt = ballot(tf[k]);
-        const uint32_t p = w * WAVE * ITEMS + k * WAVE + lane;
-        if (hf[k]) {
+    for (int i = 0; i < ITEMS; ++i) {
+        const uint64_t bh = ballot(hf[i]), bt = ballot(tf[i]);
+        const uint32_t p = w * WAVE * ITEMS + i * WAVE + lane;
+        if (hf[i]) {
             const uint32_t o = hb + mbcnt(bh);
             run_start[o] = base + p;
             run_seg[o] = sidx;
         }
-        if (tf[k]) run_end[tb + mbcnt(bt)] = base + p;
+        if (tf[i]) run_end[tb + mbcnt(bt)] = base + p;
         hb += (uint32_t)__popcll(bh);
         tb += (uint32_t)__popcll(bt);
     }
