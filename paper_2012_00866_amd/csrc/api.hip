@@ -243,12 +243,12 @@ uint32_t tiles_bound(uint64_t n, uint64_t segs, const RadixConfig& rc) {
 husky_status run_fixup(Ctx& c, const Tune& tn, int coder, const void* elems,
                        const uint64_t* offsets, uint64_t n, uint64_t n_segs,
                        const uint64_t* codes, uint64_t* keys, uint64_t* keys_alt, uint32_t* idx,
-                       hipStream_t s) {
+                       hipStream_t s, bool perfect_codes = false) {
     HUSKY_TRY(zero_u32(c.counters + CNT_SMALL, 16, s));  // tier counts [80, 96)
     c.tiers.lds_max = tn.t_medium < LDS_RUN_MAX ? LDS_RUN_MAX : 0u;
     const uint32_t tb = tiles_bound(n, n_segs, tn.rc);
     HUSKY_TRY(find_runs(codes, c.rad, tn.rc, tb, coder, false, nullptr, c.runs, c.tiers,
-                        tn.t_small, tn.t_medium, s));
+                        tn.t_small, tn.t_medium, s, perfect_codes));
     FixupArgs fa{coder, elems, offsets, (uint32_t)n, idx, c.at<uint64_t>(c.L.key0)};
     uint32_t rounds = 0;
     RunItem* cur = c.at<RunItem>(c.L.large_a);
@@ -407,13 +407,16 @@ static husky_status sort_common(husky_coder coder, const void* elems, const uint
     if (n == 0) return HUSKY_OK;
     uint64_t* codes = c.at<uint64_t>(c.L.codes_a);
     uint64_t* codes_b = c.at<uint64_t>(c.L.codes_b);
+    // ASCII codes carry the perfect bit (encode.hip): all 64 bits are key
+    // bits, and runs of identical short strings are never listed
+    const bool perfect = coder == HUSKY_CODER_ASCII7;
     HUSKY_TRY(launch_encode(coder, elems, offsets, (uint32_t)n, codes, perm, c.at<uint64_t>(c.L.key0),
-                            &c.status->domain_violations, s));
+                            &c.status->domain_violations, s, nullptr, 0, nullptr, perfect));
     if (seg_offsets)
         HUSKY_TRY(radix_segments_from_offsets(seg_offsets, (uint32_t)n_segs, c.rad, tn.rc, s));
     else
         HUSKY_TRY(radix_segments_single((uint32_t)n, c.rad, tn.rc, s));
-    const int end_bit = coder == HUSKY_CODER_ASCII7 ? 63 : 64;
+    const int end_bit = 64;
     const uint32_t tb = tiles_bound(n, n_segs, tn.rc);
     HUSKY_TRY(radix_reduce_tiles(codes, tb, c.rad, tn.rc, s));
     HUSKY_TRY(radix_exec_masks(0, end_bit, (uint32_t)n_segs, tb, c.rad, tn.rc, s));
@@ -423,7 +426,7 @@ static husky_status sort_common(husky_coder coder, const void* elems, const uint
                                   (uint32_t)n_segs, tb, ~0u, c.rad, tn.rc, P_SCATTER, s));
     // the sorted codes are not needed once the runs are listed, so the
     // device-wide fix-up reuses both code buffers for its keys
-    return run_fixup(c, tn, coder, elems, offsets, n, n_segs, codes, codes, codes_b, perm, s);
+    return run_fixup(c, tn, coder, elems, offsets, n, n_segs, codes, codes, codes_b, perm, s, perfect);
 }
 
 husky_status husky_sort(husky_coder coder, const void* elems, const uint64_t* offsets, uint64_t n,

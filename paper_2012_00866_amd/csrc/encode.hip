@@ -22,6 +22,15 @@ namespace husky {
 // streamed in order, spares the fix-up a random gather per run member.
 // With LEARNED, each code's bucket under a fitted learned-CDF model is
 // computed here as well, while the code is still in a register.
+// With `perfect` (ASCII only) the code is written as code << 1 | f, where
+// f = 0 exactly when the string is at most nine bytes long and none of them
+// is NUL -- the string is then determined by its code alone, the per-string
+// form of the paper's "perfect" coding (Algorithm 3).  The shifted code is
+// still monotone: if s < t and code(s) = code(t) with f(t) = 0, t's bytes
+// are s's first bytes padded by the code's zeros, so s >= t -- a
+// contradiction; hence f(s) <= f(t).  Equal shifted codes with f = 0 are
+// identical strings, which need no fix-up.  (Bit 63 of the ASCII code is
+// always 0, so nothing is lost.)
 template <int CODER, bool LEARNED>
 __global__ __launch_bounds__(BLOCK) void k_encode(const uint8_t* __restrict__ bytes,
                                                   const uint64_t* __restrict__ offsets,
@@ -31,7 +40,7 @@ __global__ __launch_bounds__(BLOCK) void k_encode(const uint8_t* __restrict__ by
                                                   uint64_t* __restrict__ key0,
                                                   uint32_t* __restrict__ status,
                                                   const uint32_t* __restrict__ sel,
-                                                  uint32_t n_out, BucketArgs bucket) {
+                                                  uint32_t n_out, BucketArgs bucket, bool perfect) {
     // bytes in the element buffer (uniform scalar load): the three-word
     // window below is used only where it stays inside the buffer.
     const uint64_t total_bytes = offsets[n] * (CODER == 0 ? 1u : 2u);
@@ -84,6 +93,12 @@ __global__ __launch_bounds__(BLOCK) void k_encode(const uint8_t* __restrict__ by
             const uint64_t keep = L >= 8 ? ~0ull : ((1ull << (8 * L)) - 1ull);
             const bool bad = ((lo & 0x8080808080808080ull) & keep) != 0 || (L == 9 && (b8 & 0x80));
             bad_here += bad ? 1u : 0u;
+            if (perfect) {
+                bool nul = L == 9 && b8 == 0;
+#pragma unroll
+                for (uint32_t j = 0; j < 8; ++j) nul = nul || (j < L && ((lo >> (8 * j)) & 0xFFull) == 0);
+                code = (code << 1) | ((len > 9 || nul) ? 1ull : 0ull);
+            }
             if (key0) {
                 const uint64_t rem = len > 9 ? len - 9 : 0;
                 const uint64_t nb = rem < 7 ? rem : 7;
@@ -149,7 +164,7 @@ __global__ __launch_bounds__(BLOCK) void k_encode(const uint8_t* __restrict__ by
 hipError_t launch_encode(int coder, const void* elems, const uint64_t* offsets, uint32_t n,
                          uint64_t* codes, uint32_t* idx, uint64_t* key0, uint32_t* status,
                          hipStream_t s, const uint32_t* sel, uint32_t n_out,
-                         const BucketArgs* bucket) {
+                         const BucketArgs* bucket, bool perfect) {
     const uint32_t count = sel ? n_out : n;
     if (count == 0) return hipSuccess;
     const uint32_t per_block = bucket ? BLOCK * LEARNED_K : BLOCK;
@@ -159,7 +174,7 @@ hipError_t launch_encode(int coder, const void* elems, const uint64_t* offsets, 
     const uint8_t* e = (const uint8_t*)elems;
 #define HUSKY_ENC(C, L)                                                                           \
     hipLaunchKernelGGL((k_encode<C, L>), dim3(blocks), dim3(BLOCK), 0, s, e, offsets, n, codes, idx, \
-                       key0, status, sel, n_out, b)
+                       key0, status, sel, n_out, b, perfect && coder == 0)
     if (coder == 0) {
         if (bucket) HUSKY_ENC(0, true); else HUSKY_ENC(0, false);
     } else {

@@ -76,18 +76,31 @@ __global__ __launch_bounds__(BLOCK) void k_fix_small(const RunItem* __restrict__
     const uint32_t n_items = min(*count, cap);
     const uint32_t lane = lane_id();
     const uint32_t nw = gridDim.x * NWAVES;
-    for (uint32_t it = blockIdx.x * NWAVES + threadIdx.x / WAVE; it < n_items; it += nw) {
-        const RunItem r = items[it];
+    // Software pipelined over the wavefront's runs: the next run's item is
+    // loaded while this run's first keys are gathered, and its members'
+    // string indices while this run is ranked, so a run costs about one
+    // dependent load instead of three.  Runs are disjoint, so reading the
+    // next run's indices before this run's are written back is safe.
+    uint32_t it = blockIdx.x * NWAVES + threadIdx.x / WAVE;
+    RunItem r{0, 0, 0, 0};
+    uint32_t member = 0;
+    if (it < n_items) {
+        r = items[it];
+        if (lane < r.len) member = idx[r.start + lane];
+    }
+    while (it < n_items) {
+        const uint32_t itn = it + nw;
+        RunItem rn{0, 0, 0, 0};
+        if (itn < n_items) rn = items[itn];
         const uint32_t L = r.len;  // 2..64
         const bool mine = lane < L;
-        uint32_t member = 0;
         uint64_t off = 0, len = 0;
         bool have_ol = false;
-        if (mine) member = idx[r.start + lane];
         uint32_t g = 0, lt = 0;
         bool active = mine;
         uint32_t round = r.round;
-        for (;;) {
+        uint32_t member_next = 0;
+        for (bool first = true;; first = false) {
             uint64_t key = 0;
             if (active) {
                 if (round == 0 && key0) {
@@ -101,24 +114,28 @@ __global__ __launch_bounds__(BLOCK) void k_fix_small(const RunItem* __restrict__
                     key = chunk_key<CODER>(bytes, total_bytes, off, len, round);
                 }
             }
-            uint32_t first = 0, eq = 0;
+            if (first && lane < rn.len) member_next = idx[rn.start + lane];
+            uint32_t first_pos = 0, eq = 0;
             lt = 0;
             for (uint32_t q = 0; q < L; ++q) {
                 const uint32_t gq = readlane(g, (int)q);
                 const uint64_t kq = readlane64(key, (int)q);
                 const bool less = gq < g || (gq == g && kq < key);
                 const bool same = gq == g && kq == key;
-                first += less ? 1u : 0u;
+                first_pos += less ? 1u : 0u;
                 eq += same ? 1u : 0u;
                 lt += (less || (same && q < lane)) ? 1u : 0u;
             }
             const bool cont = active && key_continues<CODER>(key) && eq > 1;
-            g = first;
+            g = first_pos;
             active = cont;
             if (!ballot(cont)) break;
             ++round;
         }
         if (mine) idx[r.start + lt] = member;
+        r = rn;
+        member = member_next;
+        it = itn;
     }
 }
 
@@ -567,14 +584,37 @@ __global__ __launch_bounds__(BLOCK) void k_large_keys(const RunItem* __restrict_
     const uint32_t lt = t - d.first_tile;
     const uint32_t base = d.start + lt * TILE;
     const uint32_t nvalid = min(TILE, d.len - lt * TILE);
+    // Each level of the gather (index, then first refinement key or string
+    // offsets) is issued for all ITEMS members before any is used, so a
+    // thread has ITEMS random loads in flight instead of one.  Padding slots
+    // gather string 0, which exists whenever a tile does.
+    uint32_t m[ITEMS];
+#pragma unroll
+    for (int k = 0; k < ITEMS; ++k) {
+        const uint32_t i = k * BLOCK + threadIdx.x;
+        m[k] = i < nvalid ? idx[base + i] : 0u;
+    }
     if (round == 0 && key0) {
-        for (uint32_t i = threadIdx.x; i < nvalid; i += BLOCK) keys[base + i] = key0[idx[base + i]];
+        uint64_t v[ITEMS];
+#pragma unroll
+        for (int k = 0; k < ITEMS; ++k) v[k] = key0[m[k]];
+#pragma unroll
+        for (int k = 0; k < ITEMS; ++k) {
+            const uint32_t i = k * BLOCK + threadIdx.x;
+            if (i < nvalid) keys[base + i] = v[k];
+        }
         return;
     }
-    for (uint32_t i = threadIdx.x; i < nvalid; i += BLOCK) {
-        const uint32_t m = idx[base + i];
-        const uint64_t o = offsets[m];
-        keys[base + i] = chunk_key<CODER>(bytes, total_bytes, o, offsets[m + 1] - o, round);
+    uint64_t o[ITEMS], e[ITEMS];
+#pragma unroll
+    for (int k = 0; k < ITEMS; ++k) {
+        o[k] = offsets[m[k]];
+        e[k] = offsets[m[k] + 1];
+    }
+#pragma unroll
+    for (int k = 0; k < ITEMS; ++k) {
+        const uint32_t i = k * BLOCK + threadIdx.x;
+        if (i < nvalid) keys[base + i] = chunk_key<CODER>(bytes, total_bytes, o[k], e[k] - o[k], round);
     }
 }
 

@@ -30,11 +30,13 @@ class ProfScope {
 // codes, idx and key0 (the first refinement key of every string) may each be
 // null.  With sel, entry i codes string sel[i] (i < n_out) instead of string i.
 // With bucket, every code's learned bucket id is written too (bucket.h).
+// With perfect (ASCII only), codes are written as code << 1 | f, f = 0 iff
+// the string is at most nine bytes with no NUL (encode.hip).
 struct BucketArgs;
 hipError_t launch_encode(int coder, const void* elems, const uint64_t* offsets, uint32_t n,
                          uint64_t* codes, uint32_t* idx, uint64_t* key0, uint32_t* status,
                          hipStream_t s, const uint32_t* sel = nullptr, uint32_t n_out = 0,
-                         const BucketArgs* bucket = nullptr);
+                         const BucketArgs* bucket = nullptr, bool perfect = false);
 
 // ---- radix.hip
 struct RadixConfig {
@@ -132,10 +134,12 @@ struct TierLists {
 // list chosen by its length, with refinement round 0 (or, when `items` is
 // given, the segment item's round + 1).
 // `max_tiles` bounds the tile count over every segment (grid size).
+// With `perfect_codes` (codes written with the perfect bit, encode.hip) a run
+// of codes whose bit 0 is clear holds identical strings and is not listed.
 hipError_t find_runs(const uint64_t* keys, const RadixScratch& seg, const RadixConfig& cfg,
                      uint32_t max_tiles, int coder, bool refinement, const RunItem* items,
                      const RunScratch& rs, const TierLists& tl, uint32_t t_small,
-                     uint32_t t_medium, hipStream_t s);
+                     uint32_t t_medium, hipStream_t s, bool perfect_codes = false);
 
 // Zero-fill kernels (graph-capture friendly).
 hipError_t zero_u64(uint64_t* p, size_t n, hipStream_t s);

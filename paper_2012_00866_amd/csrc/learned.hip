@@ -691,10 +691,35 @@ __global__ __launch_bounds__(BLOCK) void k_bscatter(const uint64_t* __restrict__
 // seg[b] = first position whose id is >= b, for b in [0, B]; ids sorted.
 __global__ __launch_bounds__(256) void k_bucket_bounds(const uint16_t* __restrict__ bid, uint32_t n,
                                                        uint32_t B, uint64_t* __restrict__ seg) {
-    for (uint32_t i = blockIdx.x * 256 + threadIdx.x; i <= n; i += gridDim.x * 256) {
-        const uint32_t prev = i == 0 ? 0u : (uint32_t)bid[i - 1] + 1u;  // first bucket starting here
-        const uint32_t cur = i == n ? B : (uint32_t)bid[i];
-        for (uint32_t b = (i == 0 ? 0u : prev); b <= cur && b <= B; ++b) seg[b] = i;
+    // thread c takes positions [8c, 8c + 8) of 0..n (one 16-byte load of ids
+    // when the array is 16-byte aligned and the chunk lies inside it)
+    const bool vec = ((uintptr_t)bid & 15u) == 0;
+    for (uint64_t c = blockIdx.x * 256ull + threadIdx.x; c * 8 <= n; c += gridDim.x * 256ull) {
+        const uint32_t i0 = (uint32_t)(c * 8);
+        uint32_t id[8];
+        if (vec && i0 + 8 <= n) {
+            const uint4 q = *reinterpret_cast<const uint4*>(bid + i0);
+            const uint32_t w[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                id[2 * j] = w[j] & 0xFFFFu;
+                id[2 * j + 1] = w[j] >> 16;
+            }
+        } else {
+#pragma unroll
+            for (int j = 0; j < 8; ++j) id[j] = i0 + j < n ? (uint32_t)bid[i0 + j] : B;
+        }
+        // buckets prev..cur start at position i: prev = 1 + the id before i
+        // (0 at i = 0), cur = the id at i (B at i = n)
+        uint32_t prev = i0 == 0 ? 0u : (uint32_t)bid[i0 - 1] + 1u;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const uint32_t i = i0 + j;
+            if (i > n) break;
+            const uint32_t cur = i == n ? B : id[j];
+            for (uint32_t b = prev; b <= cur && b <= B; ++b) seg[b] = i;
+            prev = cur + 1u;
+        }
     }
 }
 
@@ -721,7 +746,7 @@ __global__ __launch_bounds__(256) void k_lseg_scan(uint32_t* __restrict__ gtot, 
     __shared__ uint32_t scratch[NWAVES];
     const uint32_t d = threadIdx.x;
     uint32_t run = 0;
-    constexpr int U = 16;
+    constexpr int U = 64;  // group totals in flight per thread
     for (uint32_t g0 = 0; g0 < groups; g0 += U) {
         uint32_t v[U];
 #pragma unroll
@@ -1349,7 +1374,7 @@ hipError_t learned_bucket_bounds(const uint16_t* bid, uint32_t n, uint64_t* seg,
                                  uint32_t* scan_count, RunItem* const lists[4],
                                  uint32_t* class_count, hipStream_t s) {
     ProfScope ps(P_BUCKET_BOUNDS, s);
-    hipLaunchKernelGGL(k_bucket_bounds, dim3(grid_for((uint64_t)n + 1)), dim3(256), 0, s, bid, n,
+    hipLaunchKernelGGL(k_bucket_bounds, dim3(grid_for((uint64_t)n / 8 + 1)), dim3(256), 0, s, bid, n,
                        (uint32_t)LEARNED_BUCKETS, seg);
     hipLaunchKernelGGL(k_bucket_classes, dim3(256), dim3(256), 0, s, (const uint64_t*)seg,
                        (uint32_t)LEARNED_BUCKETS, overflow, big_list, big_count, scan_list, scan_count,

@@ -58,14 +58,22 @@ __device__ __forceinline__ void stage_keys(const uint64_t* __restrict__ keys, ui
 
 // Flags of tile position p (absolute position base + p inside segment
 // [s0, s1), key kc) from the staged keys: multi-run head / tail.
+// A run is kept if its keys continue (refinement keys) or, for codes with
+// the perfect bit (`perfect`), if bit 0 is set (else its strings are
+// identical).
+template <int CODER, bool REFINE>
+__device__ __forceinline__ bool keep_run(uint64_t kc, bool perfect) {
+    return REFINE ? continues<CODER>(kc) : (!perfect || (kc & 1ull));
+}
+
 template <int CODER, bool REFINE>
 __device__ __forceinline__ void run_flags(const uint64_t* s_k, uint64_t kc, uint32_t p,
-                                          uint32_t base, uint32_t s0, uint32_t s1, bool& head,
-                                          bool& tail) {
+                                          uint32_t base, uint32_t s0, uint32_t s1, bool perfect,
+                                          bool& head, bool& tail) {
     const bool has_prev = base + p > s0, has_next = base + p + 1 < s1;
     const bool eq_prev = has_prev && s_k[p] == kc;
     const bool eq_next = has_next && s_k[p + 2] == kc;
-    const bool keep = REFINE ? continues<CODER>(kc) : true;
+    const bool keep = keep_run<CODER, REFINE>(kc, perfect);
     head = keep && !eq_prev && eq_next;
     tail = keep && eq_prev && !eq_next;
 }
@@ -74,7 +82,8 @@ template <int CODER, bool REFINE, int ITEMS>
 __global__ __launch_bounds__(BLOCK) void k_runs_count(const uint64_t* __restrict__ keys,
                                                       const SegDesc* __restrict__ segs,
                                                       const uint32_t* __restrict__ counters,
-                                                      uint32_t* __restrict__ tile_counts) {
+                                                      uint32_t* __restrict__ tile_counts,
+                                                      bool perfect) {
     constexpr uint32_t TILE = BLOCK * ITEMS;
     __shared__ uint64_t s_k[TILE + 2];
     __shared__ uint32_t s_cnt[NWAVES];
@@ -92,7 +101,8 @@ __global__ __launch_bounds__(BLOCK) void k_runs_count(const uint64_t* __restrict
     for (int i = 0; i < ITEMS; ++i) {
         const uint32_t p = w * WAVE * ITEMS + i * WAVE + lane;
         bool h = false, tl = false;
-        if (p < nvalid) run_flags<CODER, REFINE>(s_k, k[i], p, base, d.start, d.start + d.len, h, tl);
+        if (p < nvalid)
+            run_flags<CODER, REFINE>(s_k, k[i], p, base, d.start, d.start + d.len, perfect, h, tl);
         heads += (uint32_t)__popcll(ballot(h));
     }
     if (lane == 0) s_cnt[w] = heads;
@@ -130,7 +140,8 @@ __global__ __launch_bounds__(BLOCK) void k_runs_write(const uint64_t* __restrict
                                                       const uint32_t* __restrict__ tile_counts,
                                                       uint32_t* __restrict__ run_start,
                                                       uint32_t* __restrict__ run_end,
-                                                      uint32_t* __restrict__ run_seg) {
+                                                      uint32_t* __restrict__ run_seg,
+                                                      bool perfect) {
     constexpr uint32_t TILE = BLOCK * ITEMS;
     __shared__ uint64_t s_k[TILE + 2];
     __shared__ uint32_t s_h[NWAVES], s_t[NWAVES];
@@ -151,7 +162,8 @@ __global__ __launch_bounds__(BLOCK) void k_runs_write(const uint64_t* __restrict
     for (int i = 0; i < ITEMS; ++i) {
         const uint32_t p = w * WAVE * ITEMS + i * WAVE + lane;
         hf[i] = tf[i] = false;
-        if (p < nvalid) run_flags<CODER, REFINE>(s_k, k[i], p, base, d.start, d.start + d.len, hf[i], tf[i]);
+        if (p < nvalid)
+            run_flags<CODER, REFINE>(s_k, k[i], p, base, d.start, d.start + d.len, perfect, hf[i], tf[i]);
         nh += (uint32_t)__popcll(ballot(hf[i]));
         nt += (uint32_t)__popcll(ballot(tf[i]));
     }
@@ -166,7 +178,7 @@ __global__ __launch_bounds__(BLOCK) void k_runs_write(const uint64_t* __restrict
         bool open = false;
         if (base > d.start) {
             const uint64_t kc = s_k[1];
-            open = s_k[0] == kc && (REFINE ? continues<CODER>(kc) : true);
+            open = s_k[0] == kc && keep_run<CODER, REFINE>(kc, perfect);
         }
         tb = hb - (open ? 1u : 0u);
     }
@@ -289,17 +301,17 @@ template <int CODER, bool REFINE, int ITEMS>
 static hipError_t find_runs_impl(const uint64_t* keys, const RadixScratch& seg,
                                  uint32_t max_tiles, const RunItem* items, const RunScratch& rs,
                                  const TierLists& tl, uint32_t t_small, uint32_t t_medium,
-                                 hipStream_t s) {
+                                 hipStream_t s, bool perfect) {
     if (max_tiles == 0) return hipSuccess;
     uint32_t* num_runs = rs.counters + 0;
     ProfScope ps(P_RUNS, s);
     hipLaunchKernelGGL((k_runs_count<CODER, REFINE, ITEMS>), dim3(max_tiles), dim3(BLOCK), 0, s,
-                       keys, seg.segs, seg.counters, rs.tile_counts);
+                       keys, seg.segs, seg.counters, rs.tile_counts, perfect);
     hipLaunchKernelGGL(k_runs_scan, dim3(1), dim3(BLOCK), 0, s, rs.tile_counts, seg.counters,
                        num_runs);
     hipLaunchKernelGGL((k_runs_write<CODER, REFINE, ITEMS>), dim3(max_tiles), dim3(BLOCK), 0, s,
                        keys, seg.segs, seg.counters, rs.tile_counts, rs.run_start, rs.run_end,
-                       rs.run_start + rs.run_cap);
+                       rs.run_start + rs.run_cap, perfect);
     const uint32_t blocks = 96;
     hipLaunchKernelGGL(k_runs_classify, dim3(blocks), dim3(BLOCK), 0, s, rs.run_start, rs.run_end,
                        rs.run_start + rs.run_cap, num_runs, items, tl,
@@ -311,11 +323,11 @@ static hipError_t find_runs_impl(const uint64_t* keys, const RadixScratch& seg,
 hipError_t find_runs(const uint64_t* keys, const RadixScratch& seg, const RadixConfig& cfg,
                      uint32_t max_tiles, int coder, bool refinement, const RunItem* items,
                      const RunScratch& rs, const TierLists& tl, uint32_t t_small,
-                     uint32_t t_medium, hipStream_t s) {
+                     uint32_t t_medium, hipStream_t s, bool perfect_codes) {
 #define HUSKY_RUNS_CASE(C, R, I)                                                               \
     if (coder == C && refinement == R && cfg.items == I)                                       \
         return find_runs_impl<C, R, I>(keys, seg, max_tiles, items, rs, tl, t_small, t_medium, \
-                                       s);
+                                       s, perfect_codes && !R);
     HUSKY_RUNS_CASE(0, false, 16)
     HUSKY_RUNS_CASE(0, true, 16)
     HUSKY_RUNS_CASE(1, false, 16)
