@@ -419,7 +419,7 @@ static husky_status sort_common(husky_coder coder, const void* elems, const uint
     const int end_bit = 64;
     const uint32_t tb = tiles_bound(n, n_segs, tn.rc);
     HUSKY_TRY(radix_reduce_tiles(codes, tb, c.rad, tn.rc, s));
-    HUSKY_TRY(radix_exec_masks(0, end_bit, (uint32_t)n_segs, tb, c.rad, tn.rc, s));
+    HUSKY_TRY(radix_exec_masks(0, end_bit, (uint32_t)n_segs, tb, c.rad, tn.rc, s, perfect));
     // every pass is launched (no host synchronisation); passes no instance
     // needs end at once
     HUSKY_TRY(radix_sort_segments(codes, perm, codes_b, c.at<uint32_t>(c.L.idx_b), 0, end_bit,

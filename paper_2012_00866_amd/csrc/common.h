@@ -44,6 +44,9 @@ enum : uint32_t {
     C_VARY_LO = 22,    // OR of the varying bits of all multi-tile segments,
     C_VARY_HI = 23,    //   low and high words
     C_EXEC_DONE = 24,  // big segments whose varying bits are known
+    C_PERFECT_OFF = 25,// 1 when the multi-tile passes leave out key bit 0
+                       // (the perfect bit of ASCII codes) because it would
+                       // cost a digit pass; run detection then ignores it
 };
 
 // Digit programs of the multi-tile passes: the bits that vary in any

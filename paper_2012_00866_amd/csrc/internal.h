@@ -77,8 +77,11 @@ hipError_t radix_segments_from_items(const RunItem* items, const uint32_t* count
 // mask of digit passes and their union (counters[C_EXEC_UNION]).
 hipError_t radix_reduce_tiles(const uint64_t* keys, uint32_t max_tiles, const RadixScratch& sc,
                               const RadixConfig& cfg, hipStream_t s);
+// With perfect_lsb (ASCII codes with the perfect bit), bit 0 is left out of
+// the digits when that saves a pass (counters[C_PERFECT_OFF] = 1).
 hipError_t radix_exec_masks(int begin_bit, int end_bit, uint32_t max_segs, uint32_t max_tiles,
-                            const RadixScratch& sc, const RadixConfig& cfg, hipStream_t s);
+                            const RadixScratch& sc, const RadixConfig& cfg, hipStream_t s,
+                            bool perfect_lsb = false);
 
 // Stable sort of (keys, vals) by bits [begin_bit, end_bit) inside every
 // segment described in sc (built by one of the functions above, with the
@@ -135,7 +138,9 @@ struct TierLists {
 // given, the segment item's round + 1).
 // `max_tiles` bounds the tile count over every segment (grid size).
 // With `perfect_codes` (codes written with the perfect bit, encode.hip) a run
-// of codes whose bit 0 is clear holds identical strings and is not listed.
+// of codes whose bit 0 is clear holds identical strings and is not listed --
+// unless the sort left bit 0 out (counters[C_PERFECT_OFF]): then keys are
+// compared without it and every run is listed.
 hipError_t find_runs(const uint64_t* keys, const RadixScratch& seg, const RadixConfig& cfg,
                      uint32_t max_tiles, int coder, bool refinement, const RunItem* items,
                      const RunScratch& rs, const TierLists& tl, uint32_t t_small,

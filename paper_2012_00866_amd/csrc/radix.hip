@@ -157,6 +157,7 @@ __global__ __launch_bounds__(BLOCK) void k_seg_setup(Src src, SegDesc* segs, Big
         counters[C_VARY_LO] = 0;
         counters[C_VARY_HI] = 0;
         counters[C_EXEC_DONE] = 0;
+        counters[C_PERFECT_OFF] = 0;
     }
 }
 
@@ -263,17 +264,33 @@ __global__ __launch_bounds__(BLOCK) void k_orand(const uint64_t* __restrict__ ke
 // bit varying inside it.  Packing keeps the order of the bits, and a bit
 // outside the union is constant inside every segment, so the passes sort
 // each segment by its keys.
+// With perfect_lsb (keys are ASCII codes with the perfect bit in bit 0), bit 0
+// is left out of every digit when that saves a pass, and C_PERFECT_OFF tells
+// run detection to compare keys without it (the order of the remaining bits
+// is the order of the codes, so runs of equal codes are still contiguous).
+template <int BITS>
+__device__ __forceinline__ int passes_for(uint64_t u, int begin_bit, int end_bit) {
+    int nw = 0;
+    for (int sh = begin_bit; sh < end_bit; sh += BITS) nw += ((u >> sh) & ((1ull << BITS) - 1ull)) ? 1 : 0;
+    const int np = (__popcll(u) + BITS - 1) / BITS;
+    return np < nw ? np : nw;
+}
+
 template <int BITS>
 __device__ void build_programs(BigDesc* __restrict__ bigs, uint32_t* __restrict__ counters,
                                const uint64_t* __restrict__ segvary, uint32_t* __restrict__ prog,
                                int begin_bit, int end_bit, uint32_t nb, uint32_t* s_prog,
-                               uint64_t* s_pm, uint32_t* s_or) {
+                               uint64_t* s_pm, uint32_t* s_or, bool perfect_lsb) {
     if (threadIdx.x == 0) {
         for (int i = 0; i < MAX_PASSES * PROG_WORDS; ++i) s_prog[i] = 0;
         for (int p = 0; p < MAX_PASSES; ++p) s_pm[p] = 0;
-        const uint64_t u = (uint64_t)__hip_atomic_load(&counters[C_VARY_LO], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) |
-                           ((uint64_t)__hip_atomic_load(&counters[C_VARY_HI], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) << 32);
+        uint64_t u = (uint64_t)__hip_atomic_load(&counters[C_VARY_LO], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) |
+                     ((uint64_t)__hip_atomic_load(&counters[C_VARY_HI], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) << 32);
         const uint64_t range = (end_bit >= 64 ? ~0ull : (1ull << end_bit) - 1ull);
+        const bool drop = perfect_lsb && begin_bit == 0 && (u & 1ull) &&
+                          passes_for<BITS>(u & ~1ull, begin_bit, end_bit) < passes_for<BITS>(u, begin_bit, end_bit);
+        if (drop) u &= ~1ull;
+        counters[C_PERFECT_OFF] = drop ? 1u : 0u;
         int nw = 0;
         for (int sh = begin_bit; sh < end_bit; sh += BITS) nw += ((u >> sh) & ((1ull << BITS) - 1ull)) ? 1 : 0;
         const bool packed = (__popcll(u) + BITS - 1) / BITS < nw;
@@ -332,7 +349,7 @@ __global__ __launch_bounds__(BLOCK) void k_exec(BigDesc* __restrict__ bigs,
                                                 const uint64_t* __restrict__ korand,
                                                 uint64_t* __restrict__ segvary,
                                                 uint32_t* __restrict__ prog, int begin_bit,
-                                                int end_bit) {
+                                                int end_bit, bool perfect_lsb) {
     __shared__ uint64_t s_o[NWAVES], s_a[NWAVES];
     __shared__ uint32_t s_prog[MAX_PASSES * PROG_WORDS];
     __shared__ uint64_t s_pm[MAX_PASSES];
@@ -360,7 +377,8 @@ __global__ __launch_bounds__(BLOCK) void k_exec(BigDesc* __restrict__ bigs,
     __syncthreads();
     if (!s_last) return;
     __threadfence();
-    build_programs<BITS>(bigs, counters, segvary, prog, begin_bit, end_bit, nb, s_prog, s_pm, s_or);
+    build_programs<BITS>(bigs, counters, segvary, prog, begin_bit, end_bit, nb, s_prog, s_pm, s_or,
+                         perfect_lsb);
 }
 
 __device__ __forceinline__ bool pass_runs(const BigDesc& B, int pass, bool& flip) {
@@ -689,12 +707,12 @@ hipError_t zero_u32(uint32_t* p, size_t n, hipStream_t s) {
 // ------------------------------------------------------------------ driver
 template <int BITS, int ITEMS>
 static hipError_t exec_impl(int begin_bit, int end_bit, uint32_t max_segs, uint32_t max_tiles,
-                            const RadixScratch& sc, hipStream_t s) {
+                            const RadixScratch& sc, hipStream_t s, bool perfect_lsb) {
     max_tiles = std::min(max_tiles, sc.big_tile_cap);
     const uint32_t max_big = std::min(std::min(sc.big_cap, max_tiles / 2 + 1), std::max(max_segs, 1u));
     ProfScope ps(P_VARY, s);
     hipLaunchKernelGGL((k_exec<BITS>), dim3(max_big), dim3(BLOCK), 0, s, sc.bigs, sc.counters,
-                       sc.korand, sc.segvary, sc.prog, begin_bit, end_bit);
+                       sc.korand, sc.segvary, sc.prog, begin_bit, end_bit, perfect_lsb);
     return hipGetLastError();
 }
 
@@ -756,10 +774,11 @@ hipError_t radix_reduce_tiles(const uint64_t* keys, uint32_t max_tiles, const Ra
 }
 
 hipError_t radix_exec_masks(int begin_bit, int end_bit, uint32_t max_segs, uint32_t max_tiles,
-                            const RadixScratch& sc, const RadixConfig& cfg, hipStream_t s) {
-    if (cfg.bits == 8) return exec_impl<8, 16>(begin_bit, end_bit, max_segs, max_tiles, sc, s);
-    if (cfg.bits == 7) return exec_impl<7, 16>(begin_bit, end_bit, max_segs, max_tiles, sc, s);
-    if (cfg.bits == 6) return exec_impl<6, 16>(begin_bit, end_bit, max_segs, max_tiles, sc, s);
+                            const RadixScratch& sc, const RadixConfig& cfg, hipStream_t s,
+                            bool perfect_lsb) {
+    if (cfg.bits == 8) return exec_impl<8, 16>(begin_bit, end_bit, max_segs, max_tiles, sc, s, perfect_lsb);
+    if (cfg.bits == 7) return exec_impl<7, 16>(begin_bit, end_bit, max_segs, max_tiles, sc, s, perfect_lsb);
+    if (cfg.bits == 6) return exec_impl<6, 16>(begin_bit, end_bit, max_segs, max_tiles, sc, s, perfect_lsb);
     return hipErrorInvalidValue;
 }
 

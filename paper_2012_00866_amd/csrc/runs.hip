@@ -58,22 +58,33 @@ __device__ __forceinline__ void stage_keys(const uint64_t* __restrict__ keys, ui
 
 // Flags of tile position p (absolute position base + p inside segment
 // [s0, s1), key kc) from the staged keys: multi-run head / tail.
-// A run is kept if its keys continue (refinement keys) or, for codes with
-// the perfect bit (`perfect`), if bit 0 is set (else its strings are
-// identical).
+// How keys are compared: codes with the perfect bit (`perfect`, encode.hip)
+// are compared whole and a run is kept only if bit 0 is set (else its strings
+// are identical) -- unless the sort left bit 0 out of its digits, when keys
+// are compared without it (shift 1) and every run is kept; refinement keys
+// are kept if they continue.
+struct RunCmp {
+    uint32_t shift;
+    bool use_bit;
+    __device__ static RunCmp make(bool perfect, const uint32_t* __restrict__ counters) {
+        const bool off = perfect && counters[C_PERFECT_OFF] != 0;
+        return RunCmp{off ? 1u : 0u, perfect && !off};
+    }
+};
+
 template <int CODER, bool REFINE>
-__device__ __forceinline__ bool keep_run(uint64_t kc, bool perfect) {
-    return REFINE ? continues<CODER>(kc) : (!perfect || (kc & 1ull));
+__device__ __forceinline__ bool keep_run(uint64_t kc, RunCmp rc) {
+    return REFINE ? continues<CODER>(kc) : (!rc.use_bit || (kc & 1ull));
 }
 
 template <int CODER, bool REFINE>
 __device__ __forceinline__ void run_flags(const uint64_t* s_k, uint64_t kc, uint32_t p,
-                                          uint32_t base, uint32_t s0, uint32_t s1, bool perfect,
+                                          uint32_t base, uint32_t s0, uint32_t s1, RunCmp rc,
                                           bool& head, bool& tail) {
     const bool has_prev = base + p > s0, has_next = base + p + 1 < s1;
-    const bool eq_prev = has_prev && s_k[p] == kc;
-    const bool eq_next = has_next && s_k[p + 2] == kc;
-    const bool keep = keep_run<CODER, REFINE>(kc, perfect);
+    const bool eq_prev = has_prev && (s_k[p] >> rc.shift) == (kc >> rc.shift);
+    const bool eq_next = has_next && (s_k[p + 2] >> rc.shift) == (kc >> rc.shift);
+    const bool keep = keep_run<CODER, REFINE>(kc, rc);
     head = keep && !eq_prev && eq_next;
     tail = keep && eq_prev && !eq_next;
 }
@@ -90,6 +101,7 @@ __global__ __launch_bounds__(BLOCK) void k_runs_count(const uint64_t* __restrict
     const uint32_t t = blockIdx.x;
     if (t >= counters[C_ALL_TILES]) return;
     const SegDesc d = segs[find_seg(segs, counters[C_NUM_SEGS], t)];
+    const RunCmp rc = RunCmp::make(perfect, counters);
     const uint32_t lt = t - d.first_tile;
     const uint32_t base = d.start + lt * TILE;
     const uint32_t nvalid = min(TILE, d.len - lt * TILE);
@@ -102,7 +114,7 @@ __global__ __launch_bounds__(BLOCK) void k_runs_count(const uint64_t* __restrict
         const uint32_t p = w * WAVE * ITEMS + i * WAVE + lane;
         bool h = false, tl = false;
         if (p < nvalid)
-            run_flags<CODER, REFINE>(s_k, k[i], p, base, d.start, d.start + d.len, perfect, h, tl);
+            run_flags<CODER, REFINE>(s_k, k[i], p, base, d.start, d.start + d.len, rc, h, tl);
         heads += (uint32_t)__popcll(ballot(h));
     }
     if (lane == 0) s_cnt[w] = heads;
@@ -149,6 +161,7 @@ __global__ __launch_bounds__(BLOCK) void k_runs_write(const uint64_t* __restrict
     if (t >= counters[C_ALL_TILES]) return;
     const uint32_t sidx = find_seg(segs, counters[C_NUM_SEGS], t);
     const SegDesc d = segs[sidx];
+    const RunCmp rc = RunCmp::make(perfect, counters);
     const uint32_t lt = t - d.first_tile;
     const uint32_t base = d.start + lt * TILE;
     const uint32_t nvalid = min(TILE, d.len - lt * TILE);
@@ -163,7 +176,7 @@ __global__ __launch_bounds__(BLOCK) void k_runs_write(const uint64_t* __restrict
         const uint32_t p = w * WAVE * ITEMS + i * WAVE + lane;
         hf[i] = tf[i] = false;
         if (p < nvalid)
-            run_flags<CODER, REFINE>(s_k, k[i], p, base, d.start, d.start + d.len, perfect, hf[i], tf[i]);
+            run_flags<CODER, REFINE>(s_k, k[i], p, base, d.start, d.start + d.len, rc, hf[i], tf[i]);
         nh += (uint32_t)__popcll(ballot(hf[i]));
         nt += (uint32_t)__popcll(ballot(tf[i]));
     }
@@ -178,7 +191,7 @@ __global__ __launch_bounds__(BLOCK) void k_runs_write(const uint64_t* __restrict
         bool open = false;
         if (base > d.start) {
             const uint64_t kc = s_k[1];
-            open = s_k[0] == kc && keep_run<CODER, REFINE>(kc, perfect);
+            open = (s_k[0] >> rc.shift) == (kc >> rc.shift) && keep_run<CODER, REFINE>(kc, rc);
         }
         tb = hb - (open ? 1u : 0u);
     }

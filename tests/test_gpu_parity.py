@@ -159,3 +159,58 @@ def test_domain_violation_raises(gpu_lib):
     e, o = gpu_lib.to_device(b)
     with pytest.raises(gpu_lib.DomainError):
         gpu_lib.sort(e, o, "ascii7")
+
+
+def _perfect_bit_batch(n, seed, short_only_group):
+    """Strings c0 + "bbbb" + c5 [+ NUL NUL NUL + 1..5 letters]: codes vary in
+    exactly eight bits (c0 in {a, c}: one bit; c5 in 0x01..0x7F: seven), and
+    the perfect bit varies too, so with it the code sort needs two 8-bit
+    passes and without it one.  With short_only_group the c0 = 'c' strings
+    are all six bytes long: their runs hold identical strings only."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(n):
+        c0 = b"a" if rng.random() < 0.5 else b"c"
+        s = c0 + b"bbbb" + bytes([int(rng.integers(1, 128))])
+        if not (short_only_group and c0 == b"c") and rng.random() < 0.6:
+            s += b"\0\0\0" + bytes(rng.integers(97, 123, size=int(rng.integers(1, 6)), dtype=np.uint8))
+        out.append(s)
+    return from_strings(out, "ascii7", name=f"perfect_bit(n={n},seed={seed})")
+
+
+@pytest.mark.parametrize("short_only_group", [False, True])
+def test_sort_perfect_bit_left_out(gpu_lib, short_only_group):
+    # the perfect bit would cost a digit pass here, so the code sort leaves it
+    # out and run detection compares codes without it: every run of equal
+    # codes is listed (those of identical short strings too), and the
+    # permutation is the oracle's
+    b = _perfect_bit_batch(20_000, 77, short_only_group)
+    _say("sort perfect bit left out", b.name)
+    e, o = gpu_lib.to_device(b)
+    ws = gpu_lib.alloc_workspace(b.n, 1, o.device)
+    perm = _u32(gpu_lib.sort(e, o, b.coder, ws=ws))
+    ref, bad = oracle.sort(b)
+    assert bad == 0
+    np.testing.assert_array_equal(perm, ref)
+    codes = oracle.encode(b)[0]
+    _, counts = np.unique(codes, return_counts=True)
+    assert gpu_lib.read_status(ws)["runs_fixed"] == int((counts >= 2).sum())
+
+
+def test_sort_perfect_bit_kept(gpu_lib):
+    # config-1 strings: the perfect bit costs no pass (codes vary in 61 bits),
+    # so runs of identical strings of at most nine bytes are never listed
+    b = config1(seed=9, n=30_000)
+    _say("sort perfect bit kept", b.name)
+    e, o = gpu_lib.to_device(b)
+    ws = gpu_lib.alloc_workspace(b.n, 1, o.device)
+    perm = _u32(gpu_lib.sort(e, o, b.coder, ws=ws))
+    ref, bad = oracle.sort(b)
+    assert bad == 0
+    np.testing.assert_array_equal(perm, ref)
+    lens = np.diff(b.offsets)
+    codes = oracle.encode(b)[0].astype(np.uint64)
+    keys = (codes << np.uint64(1)) | (lens > 9).astype(np.uint64)  # no NULs in config 1
+    uk, counts = np.unique(keys, return_counts=True)
+    flagged = (uk & np.uint64(1)) == 1
+    assert gpu_lib.read_status(ws)["runs_fixed"] == int(((counts >= 2) & flagged).sum())
