@@ -34,7 +34,7 @@ struct Layout {
     size_t status, counters, codes_a, codes_b, idx_b, key0, segs, bigs, korand, segvary, prog, binstart,
         cnt, gtot,
         tile_counts, run_start, run_end, small, medium, large_a, large_b, lds, bid, bseg, k0a, k0b, scan,
-        biglist, classes, lpartial, lgrad, ltmax, total;
+        biglist, classes, fallback, lpartial, lgrad, ltmax, total;
     uint32_t seg_cap, big_cap, tile_cap, big_tile_cap, group_cap, run_cap, small_cap, medium_cap,
         large_cap, lds_cap[4];
 };
@@ -99,6 +99,7 @@ Layout make_layout(uint64_t n, uint64_t n_segs, bool learned = false) {
         L.scan = take((size_t)LEARNED_BUCKETS * sizeof(RunItem));     // buckets Step 3 scans
         L.biglist = take((size_t)LEARNED_BUCKETS * sizeof(RunItem));  // buckets the radix passes sort
         L.classes = take((size_t)4 * LEARNED_BUCKETS * sizeof(RunItem));  // LDS size classes
+        L.fallback = take((size_t)4 * LEARNED_BUCKETS * sizeof(RunItem)); // ... not on the packed path
         L.lpartial = take(learned_partial_bytes(LEARN_MAX_BLOCKS));
         L.lgrad = take(((size_t)learned_nparam() + 1) * 4 + 256);
         L.ltmax = take((size_t)learned_lut_tiles() * 4);
@@ -117,7 +118,8 @@ constexpr int CNT_RUNS = 64, CNT_SMALL = 80, CNT_MEDIUM = 81, CNT_LARGE_A = 84, 
               CNT_SCAN = 96,  // learned form: buckets on the run-detection list
               CNT_BIG = 97,   // learned form: buckets for the multi-tile radix passes
               CNT_CLASS = 98, // learned form: buckets per LDS size class (four)
-              CNT_LDS_QUEUE = 104;  // LDS fix-up tier: work counters of its size classes (four)
+              CNT_LDS_QUEUE = 104,  // LDS fix-up tier: work counters of its size classes (four)
+              CNT_FALLBACK = 108;   // learned form: buckets per class off the packed path (four)
 
 struct Ctx {
     Layout L;
@@ -582,7 +584,12 @@ husky_status husky_sort_learned(husky_coder coder, const void* elems, const uint
     // first refinement key inside runs of equal codes; their codes become tie
     // keys, and those with a group still tied join the scan list
     const uint32_t B = LEARNED_BUCKETS;
-    HUSKY_TRY(learned_bucket_refine(coder, codes, perm, k0a, classes, class_count, scan, scan_count, s));
+    RunItem* const fallback[4] = {c.at<RunItem>(L.fallback), c.at<RunItem>(L.fallback) + LEARNED_BUCKETS,
+                                  c.at<RunItem>(L.fallback) + 2 * LEARNED_BUCKETS,
+                                  c.at<RunItem>(L.fallback) + 3 * LEARNED_BUCKETS};
+    HUSKY_TRY(zero_u32(c.counters + CNT_FALLBACK, 4, s));
+    HUSKY_TRY(learned_bucket_refine(coder, codes, perm, k0a, classes, class_count, fallback,
+                                    c.counters + CNT_FALLBACK, scan, scan_count, s));
     // larger buckets: the multi-tile radix passes on the code
     HUSKY_TRY(radix_segments_from_items(biglist, big_count, B, c.rad, tn.rc, s));
     const int end_bit = coder == HUSKY_CODER_ASCII7 ? 63 : 64;

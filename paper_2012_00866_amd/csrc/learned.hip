@@ -1155,8 +1155,155 @@ __global__ __launch_bounds__(NW * WAVE) void k_bucket_refine(uint64_t* __restric
     }
 }
 
+// ------------------------------------------------------------------ per-bucket sort on packed (code, key)
+// The same result as k_bucket_refine for a bucket whose code bits and first
+// refinement key bits that vary over the bucket number at most 64 together:
+// both are packed to their varying bits (code above key) in one word, and
+// one LSD sequence over that word orders the bucket by code, then by key,
+// ties in slot (input) order -- k_bucket_refine's order, without its passes
+// by run start.  Equal words are exactly equal (code, key) pairs, so the
+// groups (equal pair whose key continues) and the tie keys written in place
+// of the codes are the same too.  A bucket whose bits do not fit goes to
+// `fallback` for k_bucket_refine.
+template <int CODER, int ITEMS, int NW>
+__global__ __launch_bounds__(NW * WAVE) void k_bucket_pack(uint64_t* __restrict__ codes,
+                                                       uint32_t* __restrict__ perm,
+                                                       const uint64_t* __restrict__ k0,
+                                                       const RunItem* __restrict__ list,
+                                                       const uint32_t* __restrict__ list_count,
+                                                       RunItem* __restrict__ fallback,
+                                                       uint32_t* __restrict__ fallback_count,
+                                                       RunItem* __restrict__ scan_list,
+                                                       uint32_t* __restrict__ scan_count) {
+    constexpr uint32_t TILE = NW * WAVE * ITEMS;
+    static_assert(TILE <= 32768, "slots fit 16 bits");
+    __shared__ uint64_t s_k[TILE];
+    __shared__ uint32_t s_sr[TILE];
+    __shared__ uint32_t s_whist[NW * 256];
+    __shared__ uint32_t s_binstart[256];
+    __shared__ uint32_t s_scan[NW];
+    __shared__ uint64_t s_or[NW], s_and[NW], s_or2[NW], s_and2[NW];
+    uint32_t* s_k32 = reinterpret_cast<uint32_t*>(s_k);  // scratch while keys sit in registers
+    const uint32_t nlist = *list_count;
+    const uint32_t w = threadIdx.x / WAVE, lane = lane_id();
+    for (uint32_t it = blockIdx.x; it < nlist; it += gridDim.x) {
+        const RunItem d = list[it];
+        if (d.len < 2 || d.len > TILE) continue;  // never listed so; uniform per workgroup
+        const uint32_t nvalid = d.len, start = d.start;
+        auto posof = [&](int i) { return w * WAVE * ITEMS + i * WAVE + lane; };
+        // per item: key, and slot | key continues << 31
+        uint64_t k[ITEMS], q[ITEMS];
+        uint32_t sr[ITEMS], dig[ITEMS], pos[ITEMS], t[ITEMS];
+#pragma unroll
+        for (int i = 0; i < ITEMS; ++i) {
+            const uint32_t p = posof(i);
+            k[i] = p < nvalid ? codes[start + p] : ~0ull;
+            q[i] = p < nvalid ? k0[start + p] : 0ull;
+            sr[i] = p | (p < nvalid && key_continues<CODER>(q[i]) ? 1u << 31 : 0u);
+        }
+        // bits that vary over the bucket, of the codes and of the keys
+        uint64_t o = 0, a = ~0ull, o2 = 0, a2 = ~0ull;
+#pragma unroll
+        for (int i = 0; i < ITEMS; ++i)
+            if (posof(i) < nvalid) {
+                o |= k[i];
+                a &= k[i];
+                o2 |= q[i];
+                a2 &= q[i];
+            }
+#pragma unroll
+        for (int dd = 32; dd >= 1; dd >>= 1) {
+            o |= (uint64_t)__shfl_xor((unsigned long long)o, dd, WAVE);
+            a &= (uint64_t)__shfl_xor((unsigned long long)a, dd, WAVE);
+            o2 |= (uint64_t)__shfl_xor((unsigned long long)o2, dd, WAVE);
+            a2 &= (uint64_t)__shfl_xor((unsigned long long)a2, dd, WAVE);
+        }
+        if (lane == 0) {
+            s_or[w] = o;
+            s_and[w] = a;
+            s_or2[w] = o2;
+            s_and2[w] = a2;
+        }
+        __syncthreads();
+        uint64_t vc = 0, vq = 0;
+        {
+            uint64_t oo = 0, aa = ~0ull, oo2 = 0, aa2 = ~0ull;
+#pragma unroll
+            for (int ww = 0; ww < NW; ++ww) {
+                oo |= s_or[ww];
+                aa &= s_and[ww];
+                oo2 |= s_or2[ww];
+                aa2 &= s_and2[ww];
+            }
+            vc = oo ^ aa;
+            vq = oo2 ^ aa2;
+        }
+        __syncthreads();
+        const int cb = __popcll(vc), kb = __popcll(vq);
+        if (cb + kb > 64) {
+            if (threadIdx.x == 0) fallback[atomicAdd(fallback_count, 1u)] = d;
+            continue;
+        }
+        pack_bits(q, vq);  // (rank.h)
+        pack_bits(k, vc);
+#pragma unroll
+        for (int i = 0; i < ITEMS; ++i) k[i] = (kb >= 64 ? 0ull : k[i] << kb) | q[i];
+        // LSD passes over the packed word (every packed bit varies)
+        for (int shift = 0; shift < cb + kb; shift += 8) {
+#pragma unroll
+            for (int i = 0; i < ITEMS; ++i) dig[i] = (uint32_t)(k[i] >> shift) & 0xFFu;
+            uint32_t bc;
+            rank_digits<8, ITEMS, NW>(dig, nvalid, pos, s_whist, s_binstart, s_scan, &bc);
+#pragma unroll
+            for (int i = 0; i < ITEMS; ++i) {
+                s_k[pos[i]] = k[i];
+                s_sr[pos[i]] = sr[i];
+            }
+            __syncthreads();
+#pragma unroll
+            for (int i = 0; i < ITEMS; ++i) {
+                k[i] = s_k[posof(i)];
+                sr[i] = s_sr[posof(i)];
+            }
+            __syncthreads();
+        }
+        // groups: equal words whose key continues; tie key = first position
+#pragma unroll
+        for (int i = 0; i < ITEMS; ++i) s_k[posof(i)] = k[i];
+        __syncthreads();
+        bool tied = false;
+#pragma unroll
+        for (int i = 0; i < ITEMS; ++i) {
+            const uint32_t p = posof(i);
+            const bool same = p > 0 && p < nvalid && s_k[p - 1] == k[i] && (sr[i] >> 31);
+            tied = tied || same;
+            t[i] = same ? 0u : p;
+        }
+        tied = __syncthreads_or(tied);
+        if (tied) {
+            if (threadIdx.x == 0) scan_list[atomicAdd(scan_count, 1u)] = RunItem{start, nvalid, 0u, 0u};
+            tile_running_max<ITEMS, NW>(t, s_k32, s_scan);
+        }
+        // indices gathered by slot into LDS before any is overwritten
+#pragma unroll
+        for (int i = 0; i < ITEMS; ++i)
+            if (posof(i) < nvalid) s_k32[posof(i)] = perm[start + (sr[i] & 0xFFFFu)];
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < ITEMS; ++i) {
+            const uint32_t p = posof(i);
+            if (p < nvalid) {
+                perm[start + p] = s_k32[p];
+                codes[start + p] = (uint64_t)start + t[i];
+            }
+        }
+        __syncthreads();  // LDS is reused by the next bucket
+    }
+}
+
 hipError_t learned_bucket_refine(int coder, uint64_t* codes, uint32_t* perm, const uint64_t* k0,
                                  RunItem* const lists[4], const uint32_t* counts,
+                                 RunItem* const fallback[4], uint32_t* fallback_counts,
                                  RunItem* scan_list, uint32_t* scan_count, hipStream_t s) {
     ProfScope ps(P_TILE_SORT, s);
     // four size classes (bucket lists built by k_bucket_classes); a smaller
@@ -1169,9 +1316,15 @@ hipError_t learned_bucket_refine(int coder, uint64_t* codes, uint32_t* perm, con
             hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0)
             cus = (uint32_t)v;
     }
+    // per class: buckets whose (code, key) bits fit one word on the packed
+    // path, the others on the general one
 #define HUSKY_RF(C, I, NW, L, PER_CU, BITS)                                                         \
+    hipLaunchKernelGGL((k_bucket_pack<C, I, NW>), dim3(cus * PER_CU), dim3(NW * WAVE), 0, s, codes,  \
+                       perm, k0, (const RunItem*)lists[L], counts + L, fallback[L],                  \
+                       fallback_counts + L, scan_list, scan_count);                                 \
     hipLaunchKernelGGL((k_bucket_refine<C, I, NW>), dim3(cus * PER_CU), dim3(NW * WAVE), 0, s, codes, \
-                       perm, k0, (const RunItem*)lists[L], counts + L, BITS, scan_list, scan_count)
+                       perm, k0, (const RunItem*)fallback[L], fallback_counts + L, BITS, scan_list,  \
+                       scan_count)
     if (coder == 0) {
         HUSKY_RF(0, 12, 4, 0, 4, 63);
         HUSKY_RF(0, 16, 4, 1, 3, 63);
