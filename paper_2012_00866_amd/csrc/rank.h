@@ -228,26 +228,26 @@ __device__ __forceinline__ uint64_t pack_varying(uint64_t (&k)[ITEMS], uint64_t 
 
 // The bits of every x[i] selected by m (the same in every lane), packed in
 // order from bit 0 up, in place: bit order is kept, so packed values compare
-// like the selected bits.
+// like the selected bits.  One item at a time, so that only one packed value
+// is live besides the inputs.
 template <int ITEMS>
 __device__ __forceinline__ void pack_bits(uint64_t (&x)[ITEMS], uint64_t m) {
     m = uniform64(m);
-    uint64_t out[ITEMS];
 #pragma unroll
-    for (int i = 0; i < ITEMS; ++i) out[i] = 0;
-    int dst = 0;
-    while (m) {  // runs of adjacent selected bits
-        const int s = __builtin_ctzll(m);
-        const uint64_t rest = ~(m >> s);
-        const int len = rest ? __builtin_ctzll(rest) : 64 - s;
-        const uint64_t run = len >= 64 ? ~0ull : (1ull << len) - 1ull;
-#pragma unroll
-        for (int i = 0; i < ITEMS; ++i) out[i] |= ((x[i] >> s) & run) << dst;
-        dst += len;
-        m &= ~(run << s);
+    for (int i = 0; i < ITEMS; ++i) {
+        uint64_t mm = m, out = 0;
+        int dst = 0;
+        while (mm) {  // runs of adjacent selected bits
+            const int s = __builtin_ctzll(mm);
+            const uint64_t rest = ~(mm >> s);
+            const int len = rest ? __builtin_ctzll(rest) : 64 - s;
+            const uint64_t run = len >= 64 ? ~0ull : (1ull << len) - 1ull;
+            out |= ((x[i] >> s) & run) << dst;
+            dst += len;
+            mm &= ~(run << s);
+        }
+        x[i] = out;
     }
-#pragma unroll
-    for (int i = 0; i < ITEMS; ++i) x[i] = out[i];
 }
 
 template <int ITEMS>
