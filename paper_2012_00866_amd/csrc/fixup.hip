@@ -338,7 +338,8 @@ __global__ __launch_bounds__(NW * WAVE) void k_fix_lds(const RunItem* __restrict
     // block-wide OR / AND of the keys and group starts each thread passes
     // (o = 0, a = ~0, g = 0, ga = ~0 for none); returns key bits and
     // group-start bits that differ among them
-    auto varying = [&](uint64_t o, uint64_t a, uint32_t g, uint32_t ga, uint32_t* gvary) -> uint64_t {
+    auto varying = [&](uint64_t o, uint64_t a, uint32_t g, uint32_t ga, uint32_t* gvary,
+                       uint64_t* kand) -> uint64_t {
 #pragma unroll
         for (int d = 32; d >= 1; d >>= 1) {
             o |= (uint64_t)__shfl_xor((unsigned long long)o, d, WAVE);
@@ -364,6 +365,7 @@ __global__ __launch_bounds__(NW * WAVE) void k_fix_lds(const RunItem* __restrict
         }
         __syncthreads();
         *gvary = gg ^ gga;
+        *kand = aa;
         return oo ^ aa;
     };
     // workgroup b takes run b first, then runs past the grid one at a time
@@ -499,22 +501,51 @@ __global__ __launch_bounds__(NW * WAVE) void k_fix_lds(const RunItem* __restrict
                 // the first position's group start is 0: a group-start bit
                 // varies where it is set anywhere
                 uint32_t gv;
-                const uint64_t vary = varying(o, a, g, 0u, &gv);
-                for (int shift = 0; shift < 64; shift += 8) {
-                    if (!((uint32_t)(vary >> shift) & 0xFFu)) continue;
+                uint64_t kand;
+                const uint64_t vary = uniform64(varying(o, a, g, 0u, &gv, &kand));
+                // the varying key bits with the varying group-start bits above
+                // them in one word, when that takes fewer 8-bit passes than
+                // the byte windows that hold a varying bit (in the 8-wave
+                // classes: the 4-wave ones would lose an occupancy level to
+                // the extra registers)
+                constexpr bool PACK = NW >= 8;
+                const uint64_t gvary = uniform64((gv >> 16) & 0x7FFFu);
+                const int kb = __popcll(vary), nb = kb + __popcll(gvary);
+                int nwin = ((gv >> 16) & 0xFFu ? 1 : 0) + ((gv >> 24) & 0x7Fu ? 1 : 0);
+                for (int shift = 0; shift < 64; shift += 8) nwin += ((vary >> shift) & 0xFFull) ? 1 : 0;
+                if (PACK && nb <= 64 && (nb + 7) / 8 < nwin) {
 #pragma unroll
-                    for (int i = 0; i < ITEMS; ++i) dig[i] = (uint32_t)(k[i] >> shift) & 0xFFu;
-                    pass();
-                }
-                if ((gv >> 16) & 0xFFu) {
+                    for (int i = 0; i < ITEMS; ++i)
+                        k[i] = pack1(k[i], vary) |
+                               (kb >= 64 ? 0ull : pack1((sr[i] >> 16) & 0x7FFFu, gvary) << kb);
+                    for (int shift = 0; shift < nb; shift += 8) {
 #pragma unroll
-                    for (int i = 0; i < ITEMS; ++i) dig[i] = (sr[i] >> 16) & 0xFFu;
-                    pass();
-                }
-                if ((gv >> 24) & 0x7Fu) {
+                        for (int i = 0; i < ITEMS; ++i) dig[i] = (uint32_t)(k[i] >> shift) & 0xFFu;
+                        pass();
+                    }
+                    // keys back (the bits no tied key varies in are kand's);
+                    // members no longer tied carry 0 as before
+                    const uint64_t kmask = kb >= 64 ? ~0ull : (1ull << kb) - 1ull;
 #pragma unroll
-                    for (int i = 0; i < ITEMS; ++i) dig[i] = (sr[i] >> 24) & 0x7Fu;
-                    pass();
+                    for (int i = 0; i < ITEMS; ++i)
+                        k[i] = (sr[i] & TIED) ? unpack1(k[i] & kmask, vary) | (kand & ~vary) : 0ull;
+                } else {
+                    for (int shift = 0; shift < 64; shift += 8) {
+                        if (!((uint32_t)(vary >> shift) & 0xFFu)) continue;
+#pragma unroll
+                        for (int i = 0; i < ITEMS; ++i) dig[i] = (uint32_t)(k[i] >> shift) & 0xFFu;
+                        pass();
+                    }
+                    if ((gv >> 16) & 0xFFu) {
+#pragma unroll
+                        for (int i = 0; i < ITEMS; ++i) dig[i] = (sr[i] >> 16) & 0xFFu;
+                        pass();
+                    }
+                    if ((gv >> 24) & 0x7Fu) {
+#pragma unroll
+                        for (int i = 0; i < ITEMS; ++i) dig[i] = (sr[i] >> 24) & 0x7Fu;
+                        pass();
+                    }
                 }
             }
             // groups: same group start, same key, and the key continues

@@ -226,28 +226,45 @@ __device__ __forceinline__ uint64_t pack_varying(uint64_t (&k)[ITEMS], uint64_t 
     return bits >= 64 ? ~0ull : (1ull << bits) - 1ull;
 }
 
-// The bits of every x[i] selected by m (the same in every lane), packed in
-// order from bit 0 up, in place: bit order is kept, so packed values compare
-// like the selected bits.  One item at a time, so that only one packed value
-// is live besides the inputs.
+// The bits of x selected by m (the same in every lane), packed in order from
+// bit 0 up: bit order is kept, so packed values compare like the selected
+// bits.  unpack1 puts them back (unselected bits 0).
+__device__ __forceinline__ uint64_t pack1(uint64_t x, uint64_t m) {
+    uint64_t out = 0;
+    int dst = 0;
+    while (m) {  // runs of adjacent selected bits
+        const int s = __builtin_ctzll(m);
+        const uint64_t rest = ~(m >> s);
+        const int len = rest ? __builtin_ctzll(rest) : 64 - s;
+        const uint64_t run = len >= 64 ? ~0ull : (1ull << len) - 1ull;
+        out |= ((x >> s) & run) << dst;
+        dst += len;
+        m &= ~(run << s);
+    }
+    return out;
+}
+__device__ __forceinline__ uint64_t unpack1(uint64_t p, uint64_t m) {
+    uint64_t out = 0;
+    int src = 0;
+    while (m) {
+        const int s = __builtin_ctzll(m);
+        const uint64_t rest = ~(m >> s);
+        const int len = rest ? __builtin_ctzll(rest) : 64 - s;
+        const uint64_t run = len >= 64 ? ~0ull : (1ull << len) - 1ull;
+        out |= ((p >> src) & run) << s;
+        src += len;
+        m &= ~(run << s);
+    }
+    return out;
+}
+
+// pack1 over every item, in place (one item at a time, so that only one
+// packed value is live besides the inputs).
 template <int ITEMS>
 __device__ __forceinline__ void pack_bits(uint64_t (&x)[ITEMS], uint64_t m) {
     m = uniform64(m);
 #pragma unroll
-    for (int i = 0; i < ITEMS; ++i) {
-        uint64_t mm = m, out = 0;
-        int dst = 0;
-        while (mm) {  // runs of adjacent selected bits
-            const int s = __builtin_ctzll(mm);
-            const uint64_t rest = ~(mm >> s);
-            const int len = rest ? __builtin_ctzll(rest) : 64 - s;
-            const uint64_t run = len >= 64 ? ~0ull : (1ull << len) - 1ull;
-            out |= ((x[i] >> s) & run) << dst;
-            dst += len;
-            mm &= ~(run << s);
-        }
-        x[i] = out;
-    }
+    for (int i = 0; i < ITEMS; ++i) x[i] = pack1(x[i], m);
 }
 
 template <int ITEMS>
