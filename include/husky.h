@@ -77,7 +77,7 @@ typedef enum {
 typedef struct {
     uint32_t domain_violations; /* ASCII7 strings with a byte >= 0x80 among the first nine */
     uint32_t large_rounds;      /* device-wide refinement rounds the last fix-up ran */
-    uint32_t runs_fixed;        /* equal-code runs (length >= 2) the last fix-up visited */
+    uint32_t runs_fixed;        /* equal-key runs (length >= 2) the last fix-up visited */
     uint32_t unresolved;        /* groups left tied after max_rounds fixed rounds (else 0) */
     uint32_t overflow_buckets;  /* learned form: buckets above the LDS sort's 8,192 keys */
     uint32_t overflow_keys;     /* learned form: strings in those buckets */
@@ -156,6 +156,12 @@ husky_status husky_fixup(husky_coder coder, const void* elems, const uint64_t* o
 /* Algorithm 1 end to end on the GPU: encode, stable pair sort, fix-up.
  * perm receives uint32[n], the stable sorting permutation.  The device status
  * block in ws reports domain violations.  tuning may be NULL.
+ * For ASCII7 the pair sort's key is code << 1 | f, f = 0 exactly when the
+ * string has at most nine bytes and none is NUL (a per-string form of the
+ * perfect coding of Algorithm 3 and Sec. 3.4; still monotone): runs of keys
+ * with f = 0 hold identical strings and are not visited, so runs_fixed counts
+ * only the others.  When f would cost a radix pass it is left out of the
+ * digits and every run is visited.  The permutation is the same either way.
  * Errors: as husky_fixup. */
 husky_status husky_sort(husky_coder coder, const void* elems, const uint64_t* offsets,
                         uint64_t n, uint32_t* perm, void* ws, size_t ws_bytes,
