@@ -5,6 +5,8 @@
 
 #include <algorithm>
 #include <cmath>
+#include <map>
+#include <mutex>
 
 #include "../../include/husky.h"
 #include "bucket.h"
@@ -239,6 +241,72 @@ uint32_t tiles_bound(uint64_t n, uint64_t segs, const RadixConfig& rc) {
     return (uint32_t)((n + rc.tile() - 1) / rc.tile() + segs + 1);
 }
 
+// Two streams per device (default priority) that the wavefront and workgroup
+// tiers of Step 3 run on, beside the LDS tier on the caller's stream: the
+// tiers touch disjoint runs, and the LDS tier's largest class holds one
+// workgroup per CU, so the others can use the rest of each CU.  Created on
+// the first call on a device that is not being captured into a graph; until
+// then the tiers run one after the other.  Calls on one device share them,
+// and the fork and join events are recorded and waited on under a lock, so
+// concurrent calls from several host threads stay ordered.
+struct SideStreams {
+    hipStream_t st[2];
+    hipEvent_t fork, join[2];
+};
+static std::mutex g_side_mutex;
+static std::map<int, SideStreams> g_side;
+
+static const SideStreams* side_streams(bool create) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+    auto it = g_side.find(dev);
+    if (it != g_side.end()) return &it->second;
+    if (!create) return nullptr;
+    SideStreams ss{};
+    bool ok = true;
+    for (int i = 0; i < 2 && ok; ++i) ok = hipStreamCreateWithFlags(&ss.st[i], hipStreamNonBlocking) == hipSuccess;
+    ok = ok && hipEventCreateWithFlags(&ss.fork, hipEventDisableTiming) == hipSuccess;
+    for (int i = 0; i < 2 && ok; ++i)
+        ok = hipEventCreateWithFlags(&ss.join[i], hipEventDisableTiming) == hipSuccess;
+    if (!ok) return nullptr;  // the tiers then share the caller's stream
+    return &(g_side[dev] = ss);
+}
+
+// Below this many strings the fork and join (about 50 µs per call) cost more
+// than running the tiers side by side saves.
+constexpr uint64_t SIDE_MIN_N = 1ull << 21;
+
+// Work enqueued on s so far must finish before anything enqueued on the side
+// streams from now on; *out is null when there are no side streams or n is
+// small (then everything stays on s).
+static hipError_t side_fork(hipStream_t s, uint64_t n, const SideStreams** out) {
+    *out = nullptr;
+    if (n < SIDE_MIN_N) return hipSuccess;
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    hipError_t e = hipStreamIsCapturing(s, &cap);
+    if (e != hipSuccess) return e;
+    std::lock_guard<std::mutex> lock(g_side_mutex);
+    const SideStreams* ss = side_streams(cap == hipStreamCaptureStatusNone);
+    if (!ss) return hipSuccess;
+    e = hipEventRecord(ss->fork, s);
+    for (int i = 0; i < 2 && e == hipSuccess; ++i) e = hipStreamWaitEvent(ss->st[i], ss->fork, 0);
+    if (e == hipSuccess) *out = ss;
+    return e;
+}
+
+// Work enqueued on s from now on waits for everything enqueued on the side
+// streams so far.
+static hipError_t side_join(hipStream_t s, const SideStreams* ss) {
+    if (!ss) return hipSuccess;
+    std::lock_guard<std::mutex> lock(g_side_mutex);
+    hipError_t e = hipSuccess;
+    for (int i = 0; i < 2 && e == hipSuccess; ++i) {
+        e = hipEventRecord(ss->join[i], ss->st[i]);
+        if (e == hipSuccess) e = hipStreamWaitEvent(s, ss->join[i], 0);
+    }
+    return e;
+}
+
 // Step 3 over the segments currently described in c.rad (the instances the
 // codes were sorted in).  `codes` are the sorted codes; `keys`/`keys_alt`
 // are scratch key buffers (may alias `codes` once the runs are found).
@@ -305,9 +373,14 @@ husky_status run_fixup(Ctx& c, const Tune& tn, int coder, const void* elems,
         hipLaunchKernelGGL(k_copy_u32, dim3(1), dim3(1), 0, s, &c.status->unresolved, cur_cnt);
         HUSKY_TRY(hipGetLastError());
     }
+    // the three run-local tiers: workgroup and wavefront tiers on the side
+    // streams (when there are any), the LDS tier on the caller's stream
+    const SideStreams* ss = nullptr;
+    HUSKY_TRY(side_fork(s, n, &ss));
+    HUSKY_TRY(fixup_medium(fa, c.tiers, tn.t_medium, ss ? ss->st[0] : s));
+    HUSKY_TRY(fixup_small(fa, c.tiers, tn.t_small, ss ? ss->st[1] : s));
     HUSKY_TRY(fixup_lds(fa, c.tiers, tn.t_medium, s));
-    HUSKY_TRY(fixup_medium(fa, c.tiers, tn.t_medium, s));
-    HUSKY_TRY(fixup_small(fa, c.tiers, tn.t_small, s));
+    HUSKY_TRY(side_join(s, ss));
     hipLaunchKernelGGL(k_set_u32, dim3(1), dim3(1), 0, s, &c.status->large_rounds, rounds);
     HUSKY_TRY(hipGetLastError());
     return HUSKY_OK;
@@ -588,8 +661,17 @@ husky_status husky_sort_learned(husky_coder coder, const void* elems, const uint
                                   c.at<RunItem>(L.fallback) + 2 * LEARNED_BUCKETS,
                                   c.at<RunItem>(L.fallback) + 3 * LEARNED_BUCKETS};
     HUSKY_TRY(zero_u32(c.counters + CNT_FALLBACK, 4, s));
+    // the size classes of the LDS sort (two on each side stream) and the
+    // radix passes of the larger buckets (on s) touch disjoint buckets and run
+    // side by side
+    const SideStreams* ss = nullptr;
+    HUSKY_TRY(side_fork(s, n, &ss));
     HUSKY_TRY(learned_bucket_refine(coder, codes, perm, k0a, classes, class_count, fallback,
-                                    c.counters + CNT_FALLBACK, scan, scan_count, s));
+                                    c.counters + CNT_FALLBACK, scan, scan_count, 0, 2,
+                                    ss ? ss->st[0] : s));
+    HUSKY_TRY(learned_bucket_refine(coder, codes, perm, k0a, classes, class_count, fallback,
+                                    c.counters + CNT_FALLBACK, scan, scan_count, 2, 4,
+                                    ss ? ss->st[1] : s));
     // larger buckets: the multi-tile radix passes on the code
     HUSKY_TRY(radix_segments_from_items(biglist, big_count, B, c.rad, tn.rc, s));
     const int end_bit = coder == HUSKY_CODER_ASCII7 ? 63 : 64;
@@ -598,6 +680,7 @@ husky_status husky_sort_learned(husky_coder coder, const void* elems, const uint
     HUSKY_TRY(radix_exec_masks(0, end_bit, B, tb, c.rad, tn.rc, s));
     HUSKY_TRY(radix_sort_segments(codes, perm, codes_b, idx_b, 0, end_bit, B, tb, ~0u, c.rad, tn.rc,
                                   P_SCATTER, s, false));
+    HUSKY_TRY(side_join(s, ss));
     // Step 3 scans only the listed buckets: the larger ones and those with a
     // group still tied (equal codes share a bucket, so no run crosses one)
     HUSKY_TRY(radix_segments_from_items(scan, scan_count, B, c.rad, tn.rc, s));

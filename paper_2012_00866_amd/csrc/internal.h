@@ -200,10 +200,12 @@ hipError_t learned_bucket_pass(int pass, const uint64_t* ks, const uint32_t* vs,
                                uint32_t* binstart, hipStream_t s);
 // fallback[c] (LEARNED_BUCKETS entries, count zeroed by the caller) receives
 // class c's buckets whose varying (code, key) bits exceed one word.
+// Size classes [c_begin, c_end) only.
 hipError_t learned_bucket_refine(int coder, uint64_t* codes, uint32_t* perm, const uint64_t* k0,
                                  RunItem* const lists[4], const uint32_t* counts,
                                  RunItem* const fallback[4], uint32_t* fallback_counts,
-                                 RunItem* scan_list, uint32_t* scan_count, hipStream_t s);
+                                 RunItem* scan_list, uint32_t* scan_count, int c_begin, int c_end,
+                                 hipStream_t s);
 hipError_t learned_bucket_bounds(const uint16_t* bid, uint32_t n, uint64_t* seg, uint32_t* overflow,
                                  RunItem* big_list, uint32_t* big_count, RunItem* scan_list,
                                  uint32_t* scan_count, RunItem* const lists[4],

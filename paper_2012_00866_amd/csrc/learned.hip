@@ -1304,7 +1304,8 @@ __global__ __launch_bounds__(NW * WAVE) void k_bucket_pack(uint64_t* __restrict_
 hipError_t learned_bucket_refine(int coder, uint64_t* codes, uint32_t* perm, const uint64_t* k0,
                                  RunItem* const lists[4], const uint32_t* counts,
                                  RunItem* const fallback[4], uint32_t* fallback_counts,
-                                 RunItem* scan_list, uint32_t* scan_count, hipStream_t s) {
+                                 RunItem* scan_list, uint32_t* scan_count, int c_begin, int c_end,
+                                 hipStream_t s) {
     ProfScope ps(P_TILE_SORT, s);
     // four size classes (bucket lists built by k_bucket_classes); a smaller
     // class needs fewer registers and less LDS, so more workgroups share a
@@ -1318,13 +1319,15 @@ hipError_t learned_bucket_refine(int coder, uint64_t* codes, uint32_t* perm, con
     }
     // per class: buckets whose (code, key) bits fit one word on the packed
     // path, the others on the general one
-#define HUSKY_RF(C, I, NW, L, PER_CU, BITS)                                                         \
-    hipLaunchKernelGGL((k_bucket_pack<C, I, NW>), dim3(cus * PER_CU), dim3(NW * WAVE), 0, s, codes,  \
-                       perm, k0, (const RunItem*)lists[L], counts + L, fallback[L],                  \
-                       fallback_counts + L, scan_list, scan_count);                                 \
-    hipLaunchKernelGGL((k_bucket_refine<C, I, NW>), dim3(cus * PER_CU), dim3(NW * WAVE), 0, s, codes, \
-                       perm, k0, (const RunItem*)fallback[L], fallback_counts + L, BITS, scan_list,  \
-                       scan_count)
+#define HUSKY_RF(C, I, NW, L, PER_CU, BITS)                                                           \
+    if (L >= c_begin && L < c_end) {                                                                  \
+        hipLaunchKernelGGL((k_bucket_pack<C, I, NW>), dim3(cus * PER_CU), dim3(NW * WAVE), 0, s,      \
+                           codes, perm, k0, (const RunItem*)lists[L], counts + L, fallback[L],        \
+                           fallback_counts + L, scan_list, scan_count);                              \
+        hipLaunchKernelGGL((k_bucket_refine<C, I, NW>), dim3(cus * PER_CU), dim3(NW * WAVE), 0, s,    \
+                           codes, perm, k0, (const RunItem*)fallback[L], fallback_counts + L, BITS,  \
+                           scan_list, scan_count);                                                   \
+    }
     if (coder == 0) {
         HUSKY_RF(0, 12, 4, 0, 4, 63);
         HUSKY_RF(0, 16, 4, 1, 3, 63);

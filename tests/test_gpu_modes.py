@@ -1,5 +1,6 @@
 """GPU: the device exactness check, the fixed-round (graph-capturable) mode,
-HIP-graph capture and replay of the batched sort, and the autotuner."""
+HIP-graph capture and replay of the batched sort and of a sort whose fix-up
+tiers run on side streams, and the autotuner."""
 
 import numpy as np
 import pytest
@@ -91,6 +92,38 @@ def test_graph_capture_replay_batched(gpu_lib):
     g = torch.cuda.CUDAGraph()
     with torch.cuda.graph(g):
         gpu_lib.sort_batched(e, o, seg, "ascii7", tuning=t, ws=ws, perm=perm, check_status=False)
+    for rep in range(3):
+        perm.fill_(-1)  # eager work between replays
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(_u32(perm), eager, err_msg=f"replay {rep}")
+        assert gpu_lib.read_status(ws)["unresolved"] == 0
+
+
+def test_graph_capture_replay_side_streams(gpu_lib):
+    # a sort large enough that Step 3's tiers run on the library's side
+    # streams: the fork and join are captured with the graph, and every
+    # replay gives the eager (and the oracle's) permutation
+    import torch
+
+    b = config2(seed=4, n=(1 << 21) + 12345)
+    e, o = gpu_lib.to_device(b)
+    max_len = int(np.diff(b.offsets).max())
+    t = gpu_lib.make_tuning(max_rounds=gpu_lib.rounds_for(max_len))
+    ws = gpu_lib.alloc_workspace(b.n, 1)
+    perm = torch.empty(b.n, dtype=torch.int32, device="cuda")
+    eager = _u32(gpu_lib.sort(e, o, "ascii7", tuning=t, ws=ws, perm=perm)).copy()
+    np.testing.assert_array_equal(eager, oracle.sort(b)[0])
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):  # warm-up on the capture stream
+        gpu_lib.sort(e, o, "ascii7", tuning=t, ws=ws, perm=perm, check_status=False)
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        gpu_lib.sort(e, o, "ascii7", tuning=t, ws=ws, perm=perm, check_status=False)
     for rep in range(3):
         perm.fill_(-1)  # eager work between replays
         torch.cuda.synchronize()
