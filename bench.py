@@ -13,7 +13,9 @@ The roofline object is for the radix scatter pass (k_scatter, the kernel with
 the most time): its algorithmic traffic is 24 bytes per string per launch
 (read and write of the 8-byte code and the 4-byte index), divided by the
 pass's average launch duration measured with HIP events on the library's
-stream during the timed steps.  `traffic` is the HBM bytes per launch from
+stream during the timed steps (events that the pass's dispatch records
+itself, through hipExtLaunchKernelGGL, so the host's enqueueing is not in
+the interval).  `traffic` is the HBM bytes per launch from
 the committed FETCH_SIZE / WRITE_SIZE counter summary (null once radix.hip has
 changed since).  The CPU baseline is the plain oracle (single thread) on the
 same input.
@@ -172,8 +174,9 @@ def main(argv=None):
         husky.sort(elems, offsets, "ascii7", ws=ws, perm=perm, check_status=False)
     torch.cuda.synchronize()
 
-    # timed region: only the scatter pass is bracketed by HIP events (on the
-    # library's stream), so the step time is not perturbed by the others
+    # timed region: only the scatter pass is bracketed by HIP events (recorded
+    # by its dispatch on the library's stream), so the step time is not
+    # perturbed by the others
     husky.profile_begin(["radix_scatter"])
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)

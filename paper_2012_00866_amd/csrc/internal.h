@@ -19,11 +19,17 @@ bool prof_on();
 class ProfScope {
   public:
     ProfScope(int cls, hipStream_t s);
+    // For one launch made with hipExtLaunchKernelGGL: *start / *stop receive
+    // the scope's events (null when the class is not timed), for the launch
+    // to record with its dispatch, which times the kernel itself rather than
+    // the host's enqueueing around it.
+    ProfScope(int cls, hipStream_t s, hipEvent_t* start, hipEvent_t* stop);
     ~ProfScope();
   private:
     int cls_;
     hipStream_t s_;
     int idx_;
+    bool deferred_ = false;
 };
 
 // ---- encode.hip

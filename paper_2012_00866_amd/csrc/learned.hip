@@ -28,6 +28,7 @@
 //    its multi-tile passes.  Runs of equal codes never cross buckets, so the
 //    fix-up that follows is the plain path's.
 
+#include <hip/hip_ext.h>
 #include <algorithm>
 #include <cmath>
 
@@ -1512,15 +1513,17 @@ hipError_t learned_bucket_pass(int pass, const uint64_t* ks, const uint32_t* vs,
         hipLaunchKernelGGL(k_lgroup_scan, dim3(groups), dim3(256), 0, s, cnt, tiles, gtot);
         hipLaunchKernelGGL(k_lseg_scan, dim3(1), dim3(256), 0, s, gtot, groups, binstart);
     }
-    ProfScope ps(P_BUCKET, s);
+    // timed (when profiling) by events that the dispatch itself records
+    hipEvent_t ev0, ev1;
+    ProfScope ps(P_BUCKET, s, &ev0, &ev1);
     if (k0s)
-        hipLaunchKernelGGL((k_bscatter<ITEMS, true>), dim3(tiles), dim3(BLOCK), 0, s, ks, vs, bs, k0s, kd,
-                           vd, bd, k0d, n, shift, (const uint32_t*)cnt, (const uint32_t*)gtot,
-                           (const uint32_t*)binstart);
+        hipExtLaunchKernelGGL((k_bscatter<ITEMS, true>), dim3(tiles), dim3(BLOCK), 0, s, ev0, ev1, 0u,
+                              ks, vs, bs, k0s, kd, vd, bd, k0d, n, shift, (const uint32_t*)cnt,
+                              (const uint32_t*)gtot, (const uint32_t*)binstart);
     else
-        hipLaunchKernelGGL((k_bscatter<ITEMS, false>), dim3(tiles), dim3(BLOCK), 0, s, ks, vs, bs, k0s, kd,
-                           vd, bd, k0d, n, shift, (const uint32_t*)cnt, (const uint32_t*)gtot,
-                           (const uint32_t*)binstart);
+        hipExtLaunchKernelGGL((k_bscatter<ITEMS, false>), dim3(tiles), dim3(BLOCK), 0, s, ev0, ev1, 0u,
+                              ks, vs, bs, k0s, kd, vd, bd, k0d, n, shift, (const uint32_t*)cnt,
+                              (const uint32_t*)gtot, (const uint32_t*)binstart);
     return hipGetLastError();
 }
 uint32_t learned_pass_tiles(uint32_t n) { return (n + BLOCK * 16 - 1) / (BLOCK * 16); }

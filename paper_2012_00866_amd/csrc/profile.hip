@@ -1,5 +1,6 @@
 // Kernel timing hooks: when enabled, every instrumented launch is bracketed
-// by a pair of HIP events recorded on the launch's own stream, and the
+// by a pair of HIP events recorded on the launch's own stream (or, for a
+// launch made with hipExtLaunchKernelGGL, recorded by its dispatch), and the
 // elapsed times are summed per kernel class when profiling ends.  Disabled by
 // default; enabling it adds two event records per launch and no
 // synchronisation until husky_profile_end.
@@ -47,8 +48,27 @@ ProfScope::ProfScope(int cls, hipStream_t s) : cls_(cls), s_(s), idx_(-1) {
     idx_ = (int)g_used.size() - 1;
 }
 
+ProfScope::ProfScope(int cls, hipStream_t s, hipEvent_t* start, hipEvent_t* stop)
+    : cls_(cls), s_(s), idx_(-1), deferred_(true) {
+    *start = *stop = nullptr;
+    if (!g_on || cls < 0 || cls >= 32 || !((g_mask >> cls) & 1u)) return;
+    std::lock_guard<std::mutex> lk(g_mu);
+    Pair p;
+    if (!g_free.empty()) {
+        p = g_free.back();
+        g_free.pop_back();
+    } else {
+        if (hipEventCreate(&p.a) != hipSuccess || hipEventCreate(&p.b) != hipSuccess) return;
+    }
+    p.cls = cls;
+    g_used.push_back(p);
+    idx_ = (int)g_used.size() - 1;
+    *start = p.a;
+    *stop = p.b;
+}
+
 ProfScope::~ProfScope() {
-    if (idx_ < 0) return;
+    if (idx_ < 0 || deferred_) return;
     std::lock_guard<std::mutex> lk(g_mu);
     (void)hipEventRecord(g_used[idx_].b, s_);
 }

@@ -41,6 +41,8 @@
 //    passes it ran before p, and a final copy returns odd-parity segments to
 //    the primary buffers.
 
+#include <hip/hip_ext.h>
+
 #include <algorithm>
 
 #include "common.h"
@@ -748,10 +750,14 @@ static hipError_t sort_impl(uint64_t* keys, uint32_t* vals, uint64_t* keys_alt,
             hipLaunchKernelGGL((k_seg_scan<BITS>), dim3(max_big), dim3(BLOCK), 0, s, bigs,
                                sc.counters, sc.gtot, sc.binstart, p);
         }
-        ProfScope ps(pclass, s);
-        hipLaunchKernelGGL((k_scatter<BITS, ITEMS>), dim3(max_tiles), dim3(BLOCK), 0, s, keys,
-                           vals, keys_alt, vals_alt, bigs, sc.counters, sc.cnt, sc.gtot,
-                           sc.binstart, p, sc.prog);
+        // timed (when profiling) by events that the dispatch itself records
+        hipEvent_t ev0, ev1;
+        ProfScope ps(pclass, s, &ev0, &ev1);
+        hipExtLaunchKernelGGL((k_scatter<BITS, ITEMS>), dim3(max_tiles), dim3(BLOCK), 0, s, ev0, ev1, 0u,
+                              keys, vals, keys_alt, vals_alt, (const BigDesc*)bigs,
+                              (const uint32_t*)sc.counters, (const uint32_t*)sc.cnt,
+                              (const uint32_t*)sc.gtot, (const uint32_t*)sc.binstart, p,
+                              (const uint32_t*)sc.prog);
     }
     ProfScope ps(P_COPY_BACK, s);
     hipLaunchKernelGGL(k_copy_back, dim3(max_tiles), dim3(BLOCK), 0, s, keys, vals, keys_alt,
