@@ -48,6 +48,15 @@
  * husky_fixup, husky_sort and husky_sort_batched read small counters back
  * to the host (synchronizing `stream`) when a run of equal codes is longer
  * than the workgroup tier's limit, once per refinement round.
+ * Side streams.  For 2^21 strings or more, parts of Step 3 (and of the
+ * learned form's bucket sort) that touch disjoint data run on two streams
+ * the library creates once per device (default priority, kept until the
+ * process ends), forked from and joined back into `stream` through events,
+ * so the call still behaves as work enqueued on `stream` alone.  They are
+ * created on the first such call that is not being captured into a graph;
+ * a captured call before that keeps everything on `stream`.  Calls on one
+ * device share them: calls from several host threads stay correct but
+ * serialize there, and a graph capture must not overlap another call.
  */
 #ifndef HUSKY_H
 #define HUSKY_H
