@@ -3,7 +3,9 @@
 // code, so after sorting by code every inversion sits among equal codes).
 // The paper checks for this globally (its "perfect" flag, Algorithm 3, and
 // Sec. 3.4) and then re-sorts everything; here every run of two or more equal
-// keys becomes a work item, and only those are re-sorted.
+// keys becomes a work item, and only those are re-sorted -- except, for ASCII
+// codes carrying the per-string perfect bit (encode.hip), runs whose bit is
+// clear: their strings are identical and already in index order.
 //
 // A run is a maximal range of equal keys inside a segment (runs never cross
 // segment boundaries).  Three passes over the tile space of the segments:
@@ -56,8 +58,6 @@ __device__ __forceinline__ void stage_keys(const uint64_t* __restrict__ keys, ui
     __syncthreads();
 }
 
-// Flags of tile position p (absolute position base + p inside segment
-// [s0, s1), key kc) from the staged keys: multi-run head / tail.
 // How keys are compared: codes with the perfect bit (`perfect`, encode.hip)
 // are compared whole and a run is kept only if bit 0 is set (else its strings
 // are identical) -- unless the sort left bit 0 out of its digits, when keys
@@ -77,6 +77,8 @@ __device__ __forceinline__ bool keep_run(uint64_t kc, RunCmp rc) {
     return REFINE ? continues<CODER>(kc) : (!rc.use_bit || (kc & 1ull));
 }
 
+// Flags of tile position p (absolute position base + p inside segment
+// [s0, s1), key kc) from the staged keys: multi-run head / tail.
 template <int CODER, bool REFINE>
 __device__ __forceinline__ void run_flags(const uint64_t* s_k, uint64_t kc, uint32_t p,
                                           uint32_t base, uint32_t s0, uint32_t s1, RunCmp rc,
