@@ -114,7 +114,8 @@ Layout make_layout(uint64_t n, uint64_t n_segs, bool learned = false) {
 // [80] small count, [81] medium count; [84, 88) and
 // [88, 92) the two device-wide lists: item count, items longer than one
 // tile, their tiles, tiles of all items; [92, 96) LDS-tier class counts;
-// [96, 102) learned-form lists; [104, 108) work counters of the LDS tier
+// [96, 102) learned-form lists; [104, 108) work counters of the LDS tier;
+// [108, 112) learned-form buckets per size class off the packed path
 constexpr int CNT_RUNS = 64, CNT_SMALL = 80, CNT_MEDIUM = 81, CNT_LARGE_A = 84, CNT_LARGE_B = 88,
               CNT_LDS = 92,
               CNT_SCAN = 96,  // learned form: buckets on the run-detection list
