@@ -142,7 +142,7 @@ def main(argv=None):
     args = ap.parse_args(argv)
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the sort is not "
-              "sharded across GPUs in this build.", file=sys.stderr)
+              "sharded across GPUs.", file=sys.stderr)
         return 2
 
     import torch
