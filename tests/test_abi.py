@@ -82,3 +82,17 @@ def test_argument_errors_are_synchronous(lib):
     assert lib.husky_sort_batched(0, dummy, dummy, 10, None, 1, dummy, dummy, 1 << 30, None, None) == 1
     # checker needs an output
     assert lib.husky_check_perm(0, dummy, dummy, 10, None, 1, dummy, dummy, 64, None, None) == 1
+
+
+def test_bench_refuses_several_gpus():
+    # one GPU per measurement: any other --gpus value exits with status 2 and
+    # says so, before touching a device
+    import subprocess
+    import sys
+
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU only" in r.stderr
+    assert r.stdout.strip() == ""
