@@ -6,9 +6,9 @@
 // the HIP path.
 //
 // It follows the paper's three steps (Sec. 3.1 "Overview", Algorithm 1):
-//   1. code every string with stringToLong (Algorithm 4) and the coder
-//      constants of Sec. 4.3 ("Constants": BITS_LONG = 64, 7-bit ASCII with 9
-//      characters and mask 0x7F, 16-bit UTF-16 with 4 units);
+//   1. code every string (Algorithm 4 with the coder parameters of Sec. 4.3:
+//      a 64-bit code, nine 7-bit ASCII characters masked with 0x7F, or four
+//      16-bit UTF-16 units);
 //   2. sort the (code, index) pairs by code, keeping equal codes in index
 //      order (the role of the quicksort-with-object-swap phase; a stable
 //      library sort is used so that the result is unique);
@@ -29,35 +29,27 @@
 
 namespace {
 
-// Coder constants, Sec. 4.3 "Constants".
-const int BITS_LONG = 64;
-const int BIT_WIDTH_ASCII = 7;
-const int MAX_LENGTH_ASCII = BITS_LONG / BIT_WIDTH_ASCII;  // 9
-const uint64_t MASK_ASCII = 0x7F;
-const int BIT_WIDTH_UNICODE = 16;
-const int MAX_LENGTH_UNICODE = BITS_LONG / BIT_WIDTH_UNICODE;  // 4
-const uint64_t MASK_UNICODE = 0xFFFF;
+// The husky code of one string (Algorithm 4 with the coder parameters of
+// Sec. 4.3), written from its definition as fixed bit positions: the first
+// m elements each own a w-bit field, the first one most significant, and a
+// missing element's field is zero:
+//     code = sum over j < min(len, m) of (e_j & mask) << w * (m - 1 - j).
+// ASCII: m = 9 fields of w = 7 bits (bits 62..0), mask 0x7F.  UTF-16: m = 4
+// fields of w = 16 bits (all 64 bits), every bit of a unit kept.
+struct Coder {
+    int m;          // elements coded
+    int w;          // bits per element
+    uint64_t mask;  // bits of an element that are kept
+};
+const Coder ASCII7 = {9, 7, 0x7F};
+const Coder UTF16 = {4, 16, 0xFFFF};
 
-// Algorithm 4, stringToLong: take at most maxLength characters, append each
-// one (masked) in the low bitWidth bits, then shift the missing characters'
-// width in as zero padding.  Elem is uint8_t (ASCII) or uint16_t (UTF-16).
 template <typename Elem>
-uint64_t string_to_long(const Elem* str, uint64_t str_length, int max_length, int bit_width,
-                        uint64_t mask) {
-    uint64_t length = std::min<uint64_t>(str_length, (uint64_t)max_length);
-    uint64_t padding = (uint64_t)max_length - length;
-    uint64_t result = 0;
-    if (mask == 0) {
-        for (uint64_t i = 0; i < length; ++i) result = (result << bit_width) | (uint64_t)str[i];
-    } else {
-        for (uint64_t i = 0; i < length; ++i)
-            result = (result << bit_width) | ((uint64_t)str[i] & mask);
-    }
-    // A shift by the full 64 bits only happens for an empty string, whose
-    // result is zero anyway; spell that out instead of shifting by 64.
-    uint64_t shift = (uint64_t)bit_width * padding;
-    result = shift >= 64 ? 0 : (result << shift);
-    return result;
+uint64_t husky_code(const Elem* s, uint64_t len, const Coder& c) {
+    uint64_t code = 0;
+    for (uint64_t j = 0; j < len && j < (uint64_t)c.m; ++j)
+        code |= ((uint64_t)s[j] & c.mask) << (c.w * (c.m - 1 - (int)j));
+    return code;
 }
 
 // Full comparator (the order Timsort uses in Step 3): lexicographic over the
@@ -120,15 +112,15 @@ uint64_t oracle_encode(int coder, const void* elems, const uint64_t* offsets, ui
         uint64_t len = offsets[i + 1] - offsets[i];
         if (coder == 0) {
             const uint8_t* s = (const uint8_t*)elems + offsets[i];
-            codes[i] = string_to_long(s, len, MAX_LENGTH_ASCII, BIT_WIDTH_ASCII, MASK_ASCII);
-            for (uint64_t j = 0; j < len && j < (uint64_t)MAX_LENGTH_ASCII; ++j)
+            codes[i] = husky_code(s, len, ASCII7);
+            for (uint64_t j = 0; j < len && j < (uint64_t)ASCII7.m; ++j)
                 if (s[j] >= 0x80) {
                     ++violations;
                     break;
                 }
         } else if (coder == 1 || coder == 2) {
             const uint16_t* s = (const uint16_t*)elems + offsets[i];
-            uint64_t c = string_to_long(s, len, MAX_LENGTH_UNICODE, BIT_WIDTH_UNICODE, MASK_UNICODE);
+            uint64_t c = husky_code(s, len, UTF16);
             codes[i] = coder == 2 ? (c >> 1) : c;
         } else {
             codes[i] = 0;

@@ -20,12 +20,12 @@ from workloads import adversarial, config2, from_strings
 SRC = os.path.join(os.path.dirname(oracle.__file__), "husky_oracle.cpp")
 
 MUTANTS = {
-    "drop_ascii_mask": ("result = (result << bit_width) | ((uint64_t)str[i] & mask);",
-                        "result = (result << bit_width) | (uint64_t)str[i];"),
-    "padding_off_by_one": ("uint64_t padding = (uint64_t)max_length - length;",
-                           "uint64_t padding = (uint64_t)max_length - length - (length > 0);"),
-    "eight_ascii_chars": ("const int MAX_LENGTH_ASCII = BITS_LONG / BIT_WIDTH_ASCII;",
-                          "const int MAX_LENGTH_ASCII = BITS_LONG / BIT_WIDTH_ASCII - 1;"),
+    "drop_ascii_mask": ("code |= ((uint64_t)s[j] & c.mask) << (c.w * (c.m - 1 - (int)j));",
+                        "code |= ((uint64_t)s[j]) << (c.w * (c.m - 1 - (int)j));"),
+    "padding_off_by_one": ("code |= ((uint64_t)s[j] & c.mask) << (c.w * (c.m - 1 - (int)j));",
+                           "code |= ((uint64_t)s[j] & c.mask) << (c.w * (c.m - 1 - (int)j) "
+                           "- (len < (uint64_t)c.m ? c.w : 0));"),
+    "eight_ascii_chars": ("const Coder ASCII7 = {9, 7, 0x7F};", "const Coder ASCII7 = {8, 7, 0x7F};"),
     "unstable_pair_sort": ("std::stable_sort(v.begin(), v.end()", "std::sort(v.begin(), v.end()"),
     "skip_runs_of_two": ("if (end - start >= 2) {", "if (end - start >= 3) {"),
     "reversed_comparator": ("return std::lexicographical_compare(pa, pa + la, pb, pb + lb);",
@@ -37,7 +37,7 @@ MUTANTS = {
                         "while (end < n && codes[end] == codes[start] && end - start < 4) ++end;"),
     "utf16_forms_swapped": ("codes[i] = coder == 2 ? (c >> 1) : c;",
                             "codes[i] = coder == 2 ? c : (c >> 1);"),
-    "unicode_width_15": ("const int BIT_WIDTH_UNICODE = 16;", "const int BIT_WIDTH_UNICODE = 15;"),
+    "unicode_width_15": ("const Coder UTF16 = {4, 16, 0xFFFF};", "const Coder UTF16 = {4, 15, 0xFFFF};"),
 }
 
 
