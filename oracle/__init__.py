@@ -9,7 +9,7 @@ The string oracle lives in ``husky_oracle.cpp`` (plain single-threaded C++,
 loaded through ctypes); the learned-CDF oracle (float64 MLP) lives in
 ``learned.py``.  Coder ids: 0 = ASCII 7-bit x 9, 1 = UTF-16 16-bit x 4
 (unsigned), 2 = UTF-16 as printed in the paper (shifted right one bit),
-3 = null coder (every code 0).
+3 = null coder (every code 0), 4 = full bytes (8 x 8 bits, any byte value).
 """
 
 from __future__ import annotations
@@ -24,7 +24,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "husky_oracle.cpp")
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 
-CODERS = {"ascii7": 0, "utf16": 1, "utf16_paper": 2, "null": 3}
+CODERS = {"ascii7": 0, "utf16": 1, "utf16_paper": 2, "null": 3, "bytes8": 4}
 
 
 def build(force: bool = True) -> str:

@@ -35,7 +35,11 @@ namespace {
 // missing element's field is zero:
 //     code = sum over j < min(len, m) of (e_j & mask) << w * (m - 1 - j).
 // ASCII: m = 9 fields of w = 7 bits (bits 62..0), mask 0x7F.  UTF-16: m = 4
-// fields of w = 16 bits (all 64 bits), every bit of a unit kept.
+// fields of w = 16 bits (all 64 bits), every bit of a unit kept.  Full bytes
+// (the 8-bit member of the family of alphabet-dependent coders that Sec. 3.2
+// discusses -- the wider the alphabet, the fewer characters fit): m = 8
+// fields of w = 8 bits, every bit kept, so the code is the first eight bytes
+// read as a big-endian number and is monotone for every byte value.
 struct Coder {
     int m;          // elements coded
     int w;          // bits per element
@@ -43,6 +47,7 @@ struct Coder {
 };
 const Coder ASCII7 = {9, 7, 0x7F};
 const Coder UTF16 = {4, 16, 0xFFFF};
+const Coder BYTES8 = {8, 8, 0xFF};
 
 template <typename Elem>
 uint64_t husky_code(const Elem* s, uint64_t len, const Coder& c) {
@@ -100,7 +105,8 @@ extern "C" {
 
 // coder: 0 = ASCII 7-bit (9 chars), 1 = UTF-16 16-bit (4 units, unsigned code),
 //        2 = UTF-16 as printed in the paper's unicodeToLong (the same code
-//            shifted right by one bit), 3 = null coder (every code 0).
+//            shifted right by one bit), 3 = null coder (every code 0),
+//        4 = full bytes (8 chars x 8 bits, byte strings of any values).
 
 // Step 1 (Algorithm 2 / Algorithm 3 loop over Algorithm 4).  Returns the number
 // of ASCII strings holding a byte >= 0x80 among their first 9 bytes: masking
@@ -118,6 +124,8 @@ uint64_t oracle_encode(int coder, const void* elems, const uint64_t* offsets, ui
                     ++violations;
                     break;
                 }
+        } else if (coder == 4) {
+            codes[i] = husky_code((const uint8_t*)elems + offsets[i], len, BYTES8);
         } else if (coder == 1 || coder == 2) {
             const uint16_t* s = (const uint16_t*)elems + offsets[i];
             uint64_t c = husky_code(s, len, UTF16);

@@ -15,7 +15,7 @@ import numpy as np
 import pytest
 
 import oracle
-from workloads import adversarial, config2, from_strings
+from workloads import BYTES_FAMILIES, adversarial, adversarial_bytes, config2, from_strings
 
 SRC = os.path.join(os.path.dirname(oracle.__file__), "husky_oracle.cpp")
 
@@ -38,6 +38,8 @@ MUTANTS = {
     "utf16_forms_swapped": ("codes[i] = coder == 2 ? (c >> 1) : c;",
                             "codes[i] = coder == 2 ? c : (c >> 1);"),
     "unicode_width_15": ("const Coder UTF16 = {4, 16, 0xFFFF};", "const Coder UTF16 = {4, 15, 0xFFFF};"),
+    "bytes8_masked": ("const Coder BYTES8 = {8, 8, 0xFF};", "const Coder BYTES8 = {8, 8, 0x7F};"),
+    "bytes8_nine_chars": ("const Coder BYTES8 = {8, 8, 0xFF};", "const Coder BYTES8 = {9, 7, 0xFF};"),
 }
 
 
@@ -47,8 +49,9 @@ def _battery():
 
     failed = []
     for coder, units, code in _golden_rows():
-        b = from_strings([bytes(units)] if coder == "ascii7" else [tuple(units)],
-                         "ascii7" if coder == "ascii7" else "utf16")
+        byte_coder = coder in ("ascii7", "bytes8")
+        b = from_strings([bytes(units)] if byte_coder else [tuple(units)],
+                         coder if byte_coder else "utf16")
         if int(oracle.encode(b, coder)[0][0]) != code:
             failed.append("golden")
             break
@@ -68,6 +71,12 @@ def _battery():
     b = config2(n=3000)
     if not np.array_equal(oracle.sort(b)[0], _brute(b)):
         failed.append("brute:config2")
+    for fam in BYTES_FAMILIES:
+        b = adversarial_bytes(fam, seed=11, n=600)
+        if not np.array_equal(oracle.sort(b)[0], _brute(b)):
+            failed.append(f"brute:{fam}")
+        if [int(x) for x in oracle.encode(b)[0]] != [_bitstring_code(s, "bytes8") for s in b.strings()]:
+            failed.append(f"bitstring:{fam}")
     return failed
 
 

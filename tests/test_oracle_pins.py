@@ -8,8 +8,11 @@
 * the whole sort against a brute-force stable comparison sort (Python's
   ``sorted`` over ``bytes`` / unit tuples) and against invariants;
 * coder independence: with any monotone coder (ASCII, the paper's shifted
-  UTF-16 form, the null coder) the result is the same permutation, because
-  Step 3 removes every inversion left inside equal-code runs (Sec. 3.4).
+  UTF-16 form, the null coder, the full-byte coder) the result is the same
+  permutation, because Step 3 removes every inversion left inside equal-code
+  runs (Sec. 3.4);
+* the full-byte coder (eight 8-bit characters, the widest-alphabet member of
+  Sec. 3.2's alphabet-dependent coders) the same ways, over every byte value.
 """
 
 import itertools
@@ -19,8 +22,8 @@ import numpy as np
 import pytest
 
 import oracle
-from workloads import (ADVERSARIAL_FAMILIES, adversarial, config1, config2, config3, config4,
-                       config5, from_strings)
+from workloads import (ADVERSARIAL_FAMILIES, BYTES_FAMILIES, adversarial, adversarial_bytes,
+                       config1, config2, config3, config4, config5, from_strings, utf8_words)
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "stringToLong_values.tsv")
 
@@ -40,8 +43,8 @@ def _golden_rows():
 @pytest.mark.parametrize("row", _golden_rows(), ids=lambda r: f"{r[0]}:{r[1][:4]}")
 def test_golden_stringToLong(row):
     coder, units, code = row
-    if coder == "ascii7":
-        b = from_strings([bytes(units)], "ascii7")
+    if coder in ("ascii7", "bytes8"):
+        b = from_strings([bytes(units)], coder)
     else:
         b = from_strings([tuple(units)], "utf16")
     codes, _ = oracle.encode(b, coder)
@@ -52,6 +55,9 @@ def _bitstring_code(s, coder):
     """Code as the concatenation of per-character bit groups (independent derivation)."""
     if coder == "ascii7":
         groups = [format(c & 0x7F, "07b") for c in s[:9]] + ["0" * 7] * (9 - min(len(s), 9))
+        return int("".join(groups), 2)
+    if coder == "bytes8":
+        groups = [format(c, "08b") for c in s[:8]] + ["0" * 8] * (8 - min(len(s), 8))
         return int("".join(groups), 2)
     groups = [format(c, "016b") for c in s[:4]] + ["0" * 16] * (4 - min(len(s), 4))
     v = int("".join(groups), 2)
@@ -232,3 +238,59 @@ def test_check_perm_batched_detects_errors():
     # a global sort is not a per-instance sort
     glob, _ = oracle.sort(b)
     assert oracle.check_perm_batched(b, glob)[0] > 0
+
+
+# ------------------------------------------------------------------ full-byte coder
+@pytest.mark.parametrize("family", BYTES_FAMILIES)
+def test_bytes8_encode_matches_bitstring(family):
+    b = adversarial_bytes(family, seed=7, n=400)
+    codes, bad = oracle.encode(b, "bytes8")
+    assert bad == 0  # every byte value is in the domain
+    assert [int(c) for c in codes] == [_bitstring_code(s, "bytes8") for s in b.strings()]
+
+
+@pytest.mark.parametrize("alphabet,max_len", [((0x00, 0x7F, 0x80, 0xFF), 9),
+                                              ((0x00, 0x01, 0xFE, 0xFF), 9)])
+def test_bytes8_coder_monotone_exhaustive(alphabet, max_len):
+    # every string of up to nine bytes over values either side of 0x80: codes
+    # never decrease in byte order, and two strings share a code exactly when
+    # their first eight bytes, zero-padded, agree
+    strs = sorted(bytes(t) for t in _all_strings(alphabet, max_len))
+    codes, bad = oracle.encode(from_strings(strs, "bytes8"))
+    assert bad == 0
+    c = codes.astype(object)
+    assert np.all(np.diff(c) >= 0)
+    pad = [s[:8] + bytes(8 - min(len(s), 8)) for s in strs]
+    same_code = c[1:] == c[:-1]
+    same_pad = np.array([pad[k] == pad[k + 1] for k in range(len(strs) - 1)])
+    np.testing.assert_array_equal(same_code, same_pad)
+
+
+@pytest.mark.parametrize("family", BYTES_FAMILIES)
+def test_bytes8_sort_matches_bruteforce(family):
+    b = adversarial_bytes(family, seed=3, n=1500)
+    perm, bad = oracle.sort(b)
+    assert bad == 0
+    np.testing.assert_array_equal(perm, _brute(b))
+
+
+def test_bytes8_sort_utf8_text():
+    # bytes order of UTF-8 is code point order: the brute force compares the
+    # decoded strings by code points as a second witness
+    b = utf8_words(n=20000, seed=5)
+    perm, _ = oracle.sort(b)
+    np.testing.assert_array_equal(perm, _brute(b))
+    text = [s.decode("utf-8") for s in b.strings()]
+    by_cp = sorted(range(b.n), key=lambda i: [ord(ch) for ch in text[i]])
+    np.testing.assert_array_equal(perm, np.array(by_cp, dtype=np.uint32))
+
+
+def test_coder_independence_bytes8():
+    # on ASCII text the full-byte coder, the 7-bit coder and the null coder
+    # give the same permutation
+    for b in (adversarial("nul", n=800), adversarial("prefix9", n=800), config2(n=4000)):
+        ref, _ = oracle.sort(b, "ascii7")
+        np.testing.assert_array_equal(ref, oracle.sort(b, "bytes8")[0])
+    for fam in BYTES_FAMILIES:
+        b = adversarial_bytes(fam, seed=9, n=600)
+        np.testing.assert_array_equal(oracle.sort(b)[0], oracle.sort(b, "null")[0])

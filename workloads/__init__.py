@@ -4,7 +4,7 @@ This module only draws data: it holds none of the method's arithmetic (no
 coding, no ordering).  Both the CPU oracle (test infrastructure) and the HIP
 path consume what it produces.  Every array it returns is a plain numpy array:
 
-* ``elems``   -- uint8 (ASCII strings, one byte per character) or uint16
+* ``elems``   -- uint8 (ASCII or byte strings, one byte per element) or uint16
                  (UTF-16 strings, one code unit per character), all strings
                  packed back to back;
 * ``offsets`` -- uint64[n + 1], element offsets, ``offsets[0] == 0``, string i
@@ -22,6 +22,9 @@ from .gen import (  # noqa: F401
     config4,
     config5,
     adversarial,
+    adversarial_bytes,
+    utf8_words,
     ADVERSARIAL_FAMILIES,
+    BYTES_FAMILIES,
     CONFIG_SIZES,
 )

@@ -14,7 +14,11 @@ same kind stand in for them:
 * config 4 -- 4,096 independent instances, sizes log-uniform in [64, 262,144],
   each drawn like config 2 with its own seed (batched form);
 * config 5 -- 2e8 URL-like strings ``h<host>/<seg>[/<seg>...]`` with Zipf(1.2)
-  hosts (learned-CDF form).
+  hosts (learned-CDF form);
+* utf8_words -- UTF-8 text of several scripts (bytes of any value, for the
+  full-byte coder), a third of it sharing long prefixes;
+* the ``bytes*`` adversarial families -- byte strings over 0x00..0xFF that
+  stress the full-byte coder's edges.
 
 Every draw goes through ``numpy.random.Generator`` (PCG64) seeded from a
 ``SeedSequence``; the same seed gives the same bytes on every machine with the
@@ -111,8 +115,8 @@ def _scatter_copies(out: np.ndarray, dst_starts: np.ndarray, pool: np.ndarray,
 
 
 def from_strings(strings: Sequence, coder: str = "ascii7", name: str = "list") -> StringBatch:
-    """Pack a Python list of ``bytes`` (ascii7) or unit sequences (utf16)."""
-    if coder == "ascii7":
+    """Pack a Python list of ``bytes`` (ascii7, bytes8) or unit sequences (utf16)."""
+    if coder in ("ascii7", "bytes8"):
         lens = np.array([len(s) for s in strings], dtype=np.int64)
         elems = np.frombuffer(b"".join(bytes(s) for s in strings), dtype=np.uint8).copy()
     elif coder in ("utf16", "utf16_paper"):
@@ -385,3 +389,113 @@ def _adversarial_utf16(family: str, rng: np.random.Generator, n: int) -> StringB
     else:
         raise ValueError(family)
     return from_strings(out, "utf16", name=f"adv:{family}(n={n})")
+
+
+# --------------------------------------------------------------------------- UTF-8 text
+# code point ranges of the scripts drawn, and the share of strings written in each
+UTF8_SCRIPTS = (
+    ("latin_lower", 0x61, 0x7B, 0.40),
+    ("latin_accented", 0xC0, 0x180, 0.15),  # Latin-1 Supplement + Latin Extended-A
+    ("greek", 0x3B1, 0x3CA, 0.10),
+    ("cyrillic", 0x430, 0x450, 0.10),
+    ("cjk", 0x4E00, 0x9FA6, 0.20),
+    ("emoji", 0x1F600, 0x1F650, 0.05),
+)
+
+
+def _utf8_encode(cps: np.ndarray, lens: np.ndarray):
+    """UTF-8 bytes of the code points cps (flat, strings of lens code points each):
+    (bytes uint8, byte offsets uint64[n + 1])."""
+    cps = cps.astype(np.int64)
+    k = 1 + (cps >= 0x80) + (cps >= 0x800) + (cps >= 0x10000)
+    start = np.concatenate([[0], np.cumsum(k)]).astype(np.int64)
+    out = np.empty(int(start[-1]), dtype=np.uint8)
+    lead = np.where(k == 1, cps,
+                    np.where(k == 2, 0xC0 | (cps >> 6),
+                             np.where(k == 3, 0xE0 | (cps >> 12), 0xF0 | (cps >> 18))))
+    out[start[:-1]] = lead.astype(np.uint8)
+    for j in range(1, 4):  # continuation byte j of the code points that have one
+        has = k > j
+        shift = 6 * (k[has] - 1 - j)
+        out[start[:-1][has] + j] = (0x80 | ((cps[has] >> shift) & 0x3F)).astype(np.uint8)
+    cp_off = np.concatenate([[0], np.cumsum(lens)]).astype(np.int64)
+    return out, start[cp_off].astype(np.uint64)
+
+
+def utf8_words(seed: int = 1, n: int = 1 << 20, prefixes: int = 500) -> StringBatch:
+    """UTF-8 strings of 1..12 code points, each in one script of UTF8_SCRIPTS
+    (drawn by its share); a third of them are one of `prefixes` seeded 4..7
+    code point prefixes (8..28 bytes, so their codes tie) plus 0..6 more code
+    points of the prefix's script.  Sorted as bytes this is code point order."""
+    rng = _rng(seed, 6, 0)
+    shares = np.array([s[3] for s in UTF8_SCRIPTS])
+    lo = np.array([s[1] for s in UTF8_SCRIPTS], dtype=np.int64)
+    hi = np.array([s[2] for s in UTF8_SCRIPTS], dtype=np.int64)
+    # the prefixes: script, length, code points
+    p_script = rng.choice(len(UTF8_SCRIPTS), size=prefixes, p=shares)
+    p_len = rng.integers(4, 8, size=prefixes)
+    p_cps = [rng.integers(lo[s], hi[s], size=int(L)) for s, L in zip(p_script, p_len)]
+    rng = _rng(seed, 6, 1)
+    use_prefix = rng.random(n) < 1.0 / 3.0
+    which = rng.integers(0, prefixes, size=n)
+    script = np.where(use_prefix, p_script[which], rng.choice(len(UTF8_SCRIPTS), size=n, p=shares))
+    extra = np.where(use_prefix, rng.integers(0, 7, size=n), rng.integers(1, 13, size=n))
+    plen = np.where(use_prefix, p_len[which], 0)
+    lens = plen + extra
+    total = int(lens.sum())
+    cps = np.empty(total, dtype=np.int64)
+    cp_off = np.concatenate([[0], np.cumsum(lens)]).astype(np.int64)
+    # random code points of each string's script, then the prefixes over them
+    cps[:] = rng.integers(0, 1 << 40, size=total)
+    sc = np.repeat(script, lens)
+    cps = lo[sc] + cps % (hi[sc] - lo[sc])
+    for i in np.nonzero(use_prefix)[0]:
+        p = p_cps[which[i]]
+        cps[cp_off[i]:cp_off[i] + len(p)] = p
+    elems, off = _utf8_encode(cps, lens)
+    return StringBatch(elems, off, "bytes8", name=f"utf8_words(n={n},seed={seed})",
+                       meta={"scripts": [s[0] for s in UTF8_SCRIPTS], "prefixes": prefixes})
+
+
+BYTES_FAMILIES = ("bytes_edges", "bytes_alphabet4", "bytes_prefix8", "bytes_random")
+
+
+def adversarial_bytes(family: str, seed: int = 1, n: int = 2000) -> StringBatch:
+    """Byte strings over the whole range 0x00..0xFF for the full-byte coder: the
+    values either side of 0x80, NULs against the code's zero padding, strings
+    around the coded length, shared 8-byte prefixes."""
+    rng = _rng(seed, 101, BYTES_FAMILIES.index(family))
+
+    def rand_bytes(lo, hi_, k):
+        return bytes(rng.integers(lo, hi_, size=k, dtype=np.uint8).tolist())
+
+    out: List[bytes] = []
+    if family == "bytes_edges":
+        base = [b"", b"\x00", b"\x7f", b"\x80", b"\xff", b"\x80\x00", b"\xff" * 8, b"\xff" * 9,
+                b"\x00" * 8, b"\x00" * 9, b"abcdefgh", b"abcdefgh\x00", b"abcdefgh\x80",
+                b"abcdefgh\xff", b"abcdefg\x80", b"\x7f" * 8 + b"\x80", b"\xc3\xa9", b"e\xcc\x81"]
+        for _ in range(n):
+            if rng.random() < 0.5:
+                out.append(base[int(rng.integers(0, len(base)))])
+            else:
+                k = int(rng.integers(0, 18))
+                vals = np.array([0x00, 0x01, 0x7F, 0x80, 0x81, 0xFE, 0xFF], dtype=np.uint8)
+                out.append(bytes(vals[rng.integers(0, len(vals), size=k)].tolist()))
+    elif family == "bytes_alphabet4":
+        alpha = np.array([0x00, 0x7F, 0x80, 0xFF], dtype=np.uint8)
+        for _ in range(n):
+            k = int(rng.integers(0, 13))
+            out.append(bytes(alpha[rng.integers(0, 4, size=k)].tolist()))
+    elif family == "bytes_prefix8":
+        prefixes = [rand_bytes(0, 256, 8) for _ in range(5)] + [b"\xff" * 8, b"\x80" * 8]
+        for _ in range(n):
+            p = prefixes[int(rng.integers(0, len(prefixes)))]
+            k = int(rng.integers(0, 25))
+            out.append(p[: int(rng.integers(0, 9))] if rng.random() < 0.1
+                       else p + rand_bytes(0x7E, 0x82, k))
+    elif family == "bytes_random":
+        for _ in range(n):
+            out.append(rand_bytes(0, 256, int(rng.integers(0, 40))))
+    else:
+        raise ValueError(family)
+    return from_strings(out, "bytes8", name=f"adv:{family}(n={n},seed={seed})")
