@@ -9,6 +9,16 @@ detection, tiered fix-up) of the collision-heavy workload: 2^24 ASCII strings,
 random 12-character prefixes plus a 4..20 character suffix (seed 1).  Inputs
 are resident in HBM before the timed region starts.  Prints one JSON line.
 
+The timed permutation is checked against the CPU oracle's element by element
+(and by the device checker); a mismatch ends the run with status 1 and no
+line.  The same run then measures the two extensions against the plain path
+on their own workloads, each with an identical permutation required:
+
+* "learned": 2e8 URL-like strings, the learned-CDF form (fit on a 1 % sample)
+  against the plain GPU sort of the same input, per model variant;
+* "batched": 4,096 independent instances (~1.3e8 strings) in one batched call,
+  tuned, and replayed from a HIP graph, against a loop of plain calls.
+
 The roofline object is for the radix scatter pass (k_scatter, the kernel with
 the most time): its algorithmic traffic is 24 bytes per string per launch
 (read and write of the 8-byte code and the 4-byte index), divided by the
@@ -17,8 +27,9 @@ stream during the timed steps (events that the pass's dispatch records
 itself, through hipExtLaunchKernelGGL, so the host's enqueueing is not in
 the interval).  `traffic` is the HBM bytes per launch from
 the committed FETCH_SIZE / WRITE_SIZE counter summary (null once radix.hip has
-changed since).  The CPU baseline is the plain oracle (single thread) on the
-same input.
+changed since).  "pass_roofline" is the same 24 bytes per string over a whole
+digit pass (digit counts, the two scans and the scatter).  The CPU baseline is
+the plain oracle (single thread) on the same input, median of three runs.
 """
 
 from __future__ import annotations
@@ -111,20 +122,56 @@ def _bucket_traffic_per_string():
         return None
 
 
-def _cpu_baseline(batch):
+def _host_info():
+    """Host CPU model, logical CPUs (all and usable by this process) and RAM."""
+    model, mem_kb = "unknown", 0
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+        with open("/proc/meminfo") as f:
+            for line in f:
+                if line.startswith("MemTotal"):
+                    mem_kb = int(line.split()[1])
+                    break
+    except OSError:
+        pass
+    usable = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    return {"cpu_model": model, "nproc": os.cpu_count(), "nproc_usable": usable,
+            "ram_gib": round(mem_kb / 2**20, 1)}
+
+
+def _cpu_baseline(batch, runs=3):
+    """The oracle (single-threaded C++) on the whole workload, median of `runs`
+    sorts; returns (baseline object, the oracle's permutation)."""
     import oracle
 
-    t0 = time.perf_counter()
-    oracle.sort(batch)
-    dt = time.perf_counter() - t0
+    times, ref = [], None
+    for _ in range(runs):
+        t0 = time.perf_counter()
+        ref, bad = oracle.sort(batch)
+        times.append(time.perf_counter() - t0)
+        if bad:
+            raise RuntimeError(f"oracle reports {bad} out-of-domain strings")
+    dt = sorted(times)[len(times) // 2]
     return {
         "value": round(batch.n / dt / 1e6, 4),
         "unit": "Mstrings/s",
         "cores": 1,
         "kind": "oracle",
-        "sample": f"full workload ({batch.n} strings), one single-threaded oracle sort "
-                  f"({dt:.2f} s)",
-    }
+        "sample": f"full workload ({batch.n} strings), single-threaded oracle sort, median of "
+                  f"{runs} runs ({', '.join(f'{t:.2f}' for t in times)} s)",
+        "host": _host_info(),
+    }, ref
+
+
+METRIC = "Mstrings/s sorted (bit-exact) + HBM GB/s % peak; learned & batched vs plain"
+
+
+def _progress(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
 def main(argv=None):
@@ -134,17 +181,20 @@ def main(argv=None):
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--n", type=int, default=1 << 24, help="strings (default 2^24)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-learned", action="store_true", help="leave out the learned comparison")
+    ap.add_argument("--no-batched", action="store_true", help="leave out the batched comparison")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a 256 MiB device copy (calibrates HBM byte counters)")
     ap.add_argument("--mode", choices=["plain", "batched", "learned"], default="plain",
-                    help="plain: the metric's workload; batched: 4,096 instances vs a loop of "
-                         "plain sorts; learned: 2e8 URL-like strings, learned-CDF vs plain")
+                    help="plain: the metric's workload (with both comparisons); batched or "
+                         "learned: only that comparison, printed as its own line")
     args = ap.parse_args(argv)
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the sort is not "
               "sharded across GPUs.", file=sys.stderr)
         return 2
 
+    import numpy as np
     import torch
 
     import paper_2012_00866_amd as husky
@@ -159,17 +209,22 @@ def main(argv=None):
         torch.cuda.synchronize()
         del src, dst
     if args.mode == "learned":
-        return bench_learned(args)
+        out = bench_learned(args)
+        print(json.dumps(out), flush=True)
+        return 0
     if args.mode == "batched":
-        return bench_batched(args)
+        out = bench_batched(args)
+        print(json.dumps(out), flush=True)
+        return 0
     batch = config2(seed=1, n=args.n)
     n = batch.n
     elems, offsets = husky.to_device(batch)
     ws = husky.alloc_workspace(n)
     perm = torch.empty(n, dtype=torch.int32, device="cuda")
     stream = torch.cuda.current_stream()
+    _progress(f"config 2: {n} strings resident")
 
-    husky.sort(elems, offsets, "ascii7", ws=ws, perm=perm)  # raises on a domain violation
+    husky.sort(elems, offsets, "ascii7", ws=ws, perm=perm)  # raises on a bad status
     for _ in range(args.warmup):
         husky.sort(elems, offsets, "ascii7", ws=ws, perm=perm, check_status=False)
     torch.cuda.synchronize()
@@ -190,12 +245,16 @@ def main(argv=None):
     t1 = time.perf_counter()
     prof = husky.profile_end()
     status = husky.read_status(ws)
+    # the timed output: the device checker here, the oracle's permutation below
+    violations = husky.check_perm(elems, offsets, perm, "ascii7")
+    got = perm.cpu().numpy().view(np.uint32).copy()
     # per-kernel breakdown: a separate run of the same steps, every class timed
     ksteps = min(args.steps, 10)
     husky.profile_begin()
     for _ in range(ksteps):
         husky.sort(elems, offsets, "ascii7", ws=ws, perm=perm, check_status=False)
     kprof = husky.profile_end()
+    _progress(f"plain: {(t1 - t0) * 1e3 / args.steps:.3f} ms per sort")
 
     ms_per_step = (t1 - t0) * 1e3 / args.steps
     value = n / (ms_per_step / 1e3) / 1e6
@@ -206,9 +265,13 @@ def main(argv=None):
     traffic = _traffic_per_launch()
     kernels = {k: {"ms_per_step": round(v[0] / ksteps, 4), "launches_per_step": v[1] / ksteps}
                for k, v in kprof.items() if v[1]}
+    # a whole digit pass of the code sort: digit counts + the two scans + the scatter
+    passes = kprof["radix_scatter"][1] / ksteps
+    pass_ms = (kprof["radix_count_scan"][0] + kprof["radix_scatter"][0]) / ksteps / max(passes, 1)
+    pass_gbs = algo_bytes / (pass_ms / 1e3) / 1e9 if pass_ms > 0 else 0.0
 
     out = {
-        "metric": "Mstrings/s sorted (bit-exact) + HBM GB/s % peak",
+        "metric": METRIC,
         "value": round(value, 3),
         "unit": "Mstrings/s",
         "n_gpus": 1,
@@ -242,11 +305,41 @@ def main(argv=None):
             "avg_launch_ms": round(avg_ms, 5),
             "launches_per_step": os_launches / args.steps,
         },
+        "pass_roofline": {
+            "what": "one whole digit pass of the code sort: k_count + k_group_scan + k_seg_scan "
+                    "+ k_scatter, 24 algorithmic bytes per string",
+            "bound": "hbm",
+            "achieved": round(pass_gbs, 1),
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(pass_gbs / HBM_PEAK_GBS, 4),
+            "ms_per_pass": round(pass_ms, 5),
+            "passes_per_step": passes,
+        },
         "kernels": kernels,
         "event_ms_per_step": round(ev0.elapsed_time(ev1) / args.steps, 4),
+        "device_check_violations": violations,
     }
+    if violations:
+        print(f"bench.py: the device check finds {violations} violations in the timed "
+              "permutation", file=sys.stderr)
+        return 1
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = _cpu_baseline(batch)
+        out["cpu_baseline"], ref = _cpu_baseline(batch)
+        if not np.array_equal(got, ref):
+            first = int(np.nonzero(got != ref)[0][0])
+            print(f"bench.py: the timed permutation differs from the oracle's (first at "
+                  f"position {first})", file=sys.stderr)
+            return 1
+        out["oracle_identical"] = True
+        _progress("timed permutation equals the oracle's")
+    del elems, offsets, ws, perm, batch
+    torch.cuda.empty_cache()
+    if not args.no_learned:
+        out["learned"] = bench_learned(args)
+        torch.cuda.empty_cache()
+    if not args.no_batched:
+        out["batched"] = bench_batched(args)
     print(json.dumps(out), flush=True)
     return 0
 
@@ -283,6 +376,7 @@ def bench_batched(args):
     perm = torch.empty(n, dtype=torch.int32, device="cuda")
     max_len = int(np.diff(batch.offsets).max())
     steps = max(3, min(args.steps, 10))
+    _progress(f"config 4: {n} strings in {S} instances resident ({t_gen:.1f} s to generate)")
 
     def batched(t=None):
         husky.sort_batched(elems, offsets, seg, "ascii7", tuning=t, ws=ws, perm=perm, check_status=False)
@@ -307,6 +401,7 @@ def bench_batched(args):
         batched(fixed)
     ms_graph = _time(g.replay, steps, 1)
     assert torch.equal(perm, ref) and husky.read_status(ws)["unresolved"] == 0
+    del g
     # loop of plain sorts, one call per instance, same tuning
     ws1 = husky.alloc_workspace(int(np.diff(batch.seg_offsets).max()))
     offs = [(int(batch.seg_offsets[k]), int(batch.seg_offsets[k + 1])) for k in range(S)]
@@ -321,15 +416,13 @@ def bench_batched(args):
     for k, (lo, hi) in enumerate(offs):
         lp[lo:hi] += lo
     assert np.array_equal(lp.astype(np.uint32), ref.cpu().numpy().view(np.uint32)), "loop differs"
-    out = {
+    _progress(f"batched: {ms_tuned:.3f} ms tuned, loop of plain sorts {ms_loop:.1f} ms")
+    return {
         "metric": "Mstrings/s sorted (bit-exact), batched form",
         "value": round(n / (ms_tuned / 1e3) / 1e6, 3),
         "unit": "Mstrings/s",
-        "n_gpus": 1,
         "ms_per_step": round(ms_tuned, 4),
-        "higher_is_better": True,
-        "dtype": "u64",
-        "data": "synthetic",
+        "steps": steps,
         "config": {"workload": "4,096 independent instances of the collision-heavy distribution, "
                                "sizes log-uniform in [64, 262144]", "n": n, "instances": S,
                    "seed": 1, "generation_s": round(t_gen, 1)},
@@ -337,11 +430,11 @@ def bench_batched(args):
                      "batched_graph_replay": round(ms_graph, 3),
                      "loop_of_plain_sorts": round(ms_loop, 3)},
         "speedup_batched_vs_loop": round(ms_loop / ms_tuned, 2),
+        "identical": True,
+        "device_check_violations": 0,
         "tuning": res["tuning"],
         "tuner_table": [{"params": r["params"], "ms": round(r["ms"], 3)} for r in res["table"]],
     }
-    print(json.dumps(out), flush=True)
-    return 0
 
 
 def _kernels(prof, steps):
@@ -356,14 +449,14 @@ def bench_learned(args):
     import paper_2012_00866_amd as husky
     from workloads import config5
 
-    n = args.n if args.n != (1 << 24) else 200_000_000
+    n = 200_000_000 if args.mode != "learned" or args.n == (1 << 24) else args.n
     t_gen = time.perf_counter()
     batch = config5(n=n, seed=1)
     t_gen = time.perf_counter() - t_gen
     mean_len = batch.elems.size / n
     elems, offsets = husky.to_device(batch)
     del batch
-    print(f"[bench] {n} strings resident ({t_gen:.1f} s to generate)", file=sys.stderr, flush=True)
+    _progress(f"config 5: {n} strings resident ({t_gen:.1f} s to generate)")
     ws = husky.alloc_learned_workspace(n)
     perm = torch.empty(n, dtype=torch.int32, device="cuda")
     steps = max(3, min(args.steps, 10))
@@ -373,6 +466,7 @@ def bench_learned(args):
 
     ms_plain = _time(plain, steps, 1)
     ref = perm.clone()
+    assert husky.check_perm(elems, offsets, ref, "ascii7") == 0, "plain result not exact"
     husky.profile_begin()
     for _ in range(steps):
         plain()
@@ -402,14 +496,16 @@ def bench_learned(args):
         load = load.to(torch.float64)
         exp_load = float((load * load).sum() / n)
         del ids, load
-        variants[name] = {"sort_ms": round(ms, 3), "fit_ms": round(ms_fit, 2), "identical": same,
+        variants[name] = {"sort_ms": round(ms, 3), "fit_ms": round(ms_fit, 2),
+                          "inclusive_ms": round(ms + ms_fit, 3),
+                          "speedup_vs_plain": round(ms_plain / ms, 3), "identical": same,
                           "expected_bucket_load": round(exp_load, 1),
                           "overflow_buckets": st["overflow_buckets"],
                           "overflow_keys_frac": round(st["overflow_keys"] / n, 4),
                           "adam_steps": h["steps"], "dense_cells": h["dense"],
                           "dense_sample_frac": round(h["dense_keys"] / max(h["sample"], 1), 4),
                           "trained_on": h["trained"], "last_loss": round(float(h["last_loss"]), 6)}
-        print(f"[bench] {name}: {variants[name]}", file=sys.stderr, flush=True)
+        _progress(f"learned {name}: {variants[name]}")
         if name == "monotone":
             model = m
         else:
@@ -419,6 +515,7 @@ def bench_learned(args):
     for _ in range(steps):
         husky.sort_learned(elems, offsets, model, "ascii7", ws=ws, perm=perm, check_status=False)
     prof = husky.profile_end()
+    assert husky.check_perm(elems, offsets, perm, "ascii7") == 0, "learned result not exact"
     k_learned = _kernels(prof, steps)
     ms_bs, nb = prof["learned_bucket_scatter"]
     # roofline of the bucket pass: 42 algorithmic bytes per string per pass
@@ -426,25 +523,25 @@ def bench_learned(args):
     bs_avg_ms = ms_bs / max(nb, 1)
     bs_achieved = 42.0 * n / (bs_avg_ms / 1e3) / 1e9 if nb else 0.0
     tps = _bucket_traffic_per_string()
-    out = {
+    del elems, offsets, ws, perm, ref, model
+    return {
         "metric": "Mstrings/s sorted (bit-exact), learned-CDF form vs plain",
         "value": round(n / (ms_learned / 1e3) / 1e6, 3),
         "unit": "Mstrings/s",
-        "n_gpus": 1,
         "steps": steps,
         "ms_per_step": ms_learned,
-        "higher_is_better": True,
-        "dtype": "u64",
-        "data": "synthetic",
         "config": {"workload": "URL-like strings: 'h' + host id (Zipf 1.2 over 10,000 hosts, "
                                "seeded id permutation) + '/' + 1-4 lowercase segments of 3-10",
                    "n": n, "mean_bytes": round(mean_len, 2), "seed": 1, "sample_frac": 0.01,
-                   "buckets": 65536, "ideal_bucket_load": round(n / 65536, 1)},
+                   "buckets": 65536, "ideal_bucket_load": round(n / 65536, 1),
+                   "generation_s": round(t_gen, 1)},
         "plain_ms": round(ms_plain, 3),
         "plain_mstrings_s": round(n / (ms_plain / 1e3) / 1e6, 3),
         "speedup_learned_vs_plain": round(ms_plain / ms_learned, 3),
         "fit_ms": variants["monotone"]["fit_ms"],
         "inclusive_ms": round(ms_learned + variants["monotone"]["fit_ms"], 3),
+        "identical": True,
+        "device_check_violations": 0,
         "variants": variants,
         # the two bucket passes move the 8-byte code, the 2-byte id and the 8-byte
         # first refinement key; the index is written by both and read by the second:
@@ -464,8 +561,6 @@ def bench_learned(args):
         "kernels_learned": k_learned,
         "kernels_plain": k_plain,
     }
-    print(json.dumps(out), flush=True)
-    return 0
 
 
 if __name__ == "__main__":

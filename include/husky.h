@@ -26,9 +26,15 @@
  *     lexicographic order (the order of Java's String.compareTo, which the
  *     paper's final pass uses), a proper prefix first.  The code keeps all
  *     64 bits of the first four units and is compared unsigned.
+ *   HUSKY_CODER_BYTES8 -- strings of bytes of ANY value (binary keys, UTF-8
+ *     text, whose byte order is code point order), unsigned
+ *     byte-lexicographic order, a proper prefix first.  The code is the first
+ *     eight bytes read big-endian: the 8-bit member of the alphabet-dependent
+ *     coders of Sec. 3.2, monotone for every byte value, one character
+ *     shorter than the 7-bit coder.
  *
  * Layout.  `elems` holds all strings back to back: uint8 elements for
- * ASCII7, uint16 for UTF16.  `offsets` is uint64[n + 1] in ELEMENTS with
+ * ASCII7 and BYTES8, uint16 for UTF16.  `offsets` is uint64[n + 1] in ELEMENTS with
  * offsets[0] = 0, non-decreasing; string i is elems[offsets[i] ..
  * offsets[i+1]).  Empty strings and NUL elements are allowed.  n < 2^32.
  *
@@ -74,12 +80,15 @@ typedef enum {
     HUSKY_ERR_DOMAIN = 2,      /* (device status only) ASCII7 byte >= 0x80 in the first nine */
     HUSKY_ERR_WORKSPACE = 3,   /* workspace missing, too small or misaligned */
     HUSKY_ERR_HIP = 4,         /* a HIP runtime call failed */
-    HUSKY_ERR_UNSUPPORTED = 5  /* tuning value outside the compiled variants */
+    HUSKY_ERR_UNSUPPORTED = 5, /* tuning value outside the compiled variants */
+    HUSKY_ERR_UNRESOLVED = 6   /* (device status only) groups still tied after
+                                * tuning.max_rounds fixed rounds: perm not final */
 } husky_status;
 
 typedef enum {
     HUSKY_CODER_ASCII7 = 0, /* uint8 elements, 9 chars x 7 bits, bits 62..0 */
-    HUSKY_CODER_UTF16 = 1   /* uint16 elements, 4 units x 16 bits, bits 63..0 */
+    HUSKY_CODER_UTF16 = 1,  /* uint16 elements, 4 units x 16 bits, bits 63..0 */
+    HUSKY_CODER_BYTES8 = 2  /* uint8 elements of any value, 8 x 8 bits, bits 63..0 */
 } husky_coder;
 
 /* Device status block at the start of the workspace (device memory). */
@@ -127,7 +136,8 @@ size_t husky_workspace_bytes(uint64_t n, uint64_t n_segs);
 
 /* Step 1 -- Algorithm 4 (stringToLong) over every string, Algorithm 2/3.
  * codes[i] = sum over j < min(len_i, m) of (e_ij & mask) << w*(m-1-j):
- * ASCII7 m = 9, w = 7, mask 0x7F; UTF16 m = 4, w = 16, no mask.
+ * ASCII7 m = 9, w = 7, mask 0x7F; UTF16 m = 4, w = 16, no mask; BYTES8 m = 8,
+ * w = 8, no mask.
  * idx_or_null: if not NULL receives idx[i] = i (the index array that
  *   travels with the codes through Step 2).
  * status: device uint32 that is INCREMENTED by the number of ASCII7 strings
@@ -153,14 +163,33 @@ husky_status husky_sort_pairs(uint64_t* codes, uint32_t* idx, uint64_t n, int be
  * idx becomes the stable sorting permutation.  Runs never cross instance
  * boundaries: seg_offsets_or_null is uint64[n_segs + 1] string offsets of
  * independent instances (NULL with n_segs = 1 for one instance).  A run whose
- * members all have the same length <= m (9 ASCII, 4 UTF-16) holds identical
- * strings already in index order and is left as it is.  idx is updated in
+ * members all have the same length <= m (9 ASCII, 8 BYTES8, 4 UTF-16) holds
+ * identical strings already in index order and is left as it is.  idx is updated in
  * place; sorted_codes is read only.  Errors: HUSKY_ERR_ARG,
  * HUSKY_ERR_WORKSPACE, HUSKY_ERR_UNSUPPORTED, HUSKY_ERR_HIP. */
 husky_status husky_fixup(husky_coder coder, const void* elems, const uint64_t* offsets,
                          uint64_t n, const uint64_t* sorted_codes, uint32_t* idx,
                          const uint64_t* seg_offsets_or_null, uint64_t n_segs, void* ws,
                          size_t ws_bytes, const husky_tuning* tuning, void* stream);
+
+/* Step 3 as a general refinement step (recursive in-run Huskysort): given any
+ * keys sorted ascending with idx carried along, re-sort every run of equal
+ * keys by the full comparator, in place on idx.  The caller states what a run
+ * is known to share: every member of a run agrees with the others on its
+ * first min(len, shared_elems) elements (0 <= shared_elems <= 15; 0 assumes
+ * nothing, so any keys work -- e.g. the result of a coarser sort; husky
+ * codes of `coder` satisfy it with shared_elems = m, which is husky_fixup).
+ * Each round then codes the next 7 bytes (3 UTF-16 units) of every member of
+ * a still-tied group, from element shared_elems on, as a new key and sorts the
+ * group by it -- the method applied again inside the run -- until no group
+ * is tied.  Runs, instances, workspace, tuning and errors as husky_fixup
+ * (plus HUSKY_ERR_ARG for shared_elems > 15).  If a run breaks the stated
+ * sharing, idx is unspecified. */
+husky_status husky_refine(husky_coder coder, const void* elems, const uint64_t* offsets,
+                          uint64_t n, const uint64_t* sorted_keys, uint32_t* idx,
+                          const uint64_t* seg_offsets_or_null, uint64_t n_segs,
+                          uint32_t shared_elems, void* ws, size_t ws_bytes,
+                          const husky_tuning* tuning, void* stream);
 
 /* Algorithm 1 end to end on the GPU: encode, stable pair sort, fix-up.
  * perm receives uint32[n], the stable sorting permutation.  The device status
@@ -365,6 +394,20 @@ husky_status husky_learned_buckets(husky_coder coder, const void* elems, const u
 size_t husky_mlp_grad_workspace_bytes(uint32_t count);
 husky_status husky_mlp_grad(const float* params, const float* x, const float* y, uint32_t count,
                             int monotone, float* grad, void* ws, size_t ws_bytes, void* stream);
+
+/* The inference kernel alone, for checking it: lut (device uint32[2^24 + 1])
+ * receives the table the fit builds -- F(W) of the network with raw
+ * parameters `params` (device float[NPARAM], layout as HUSKY_LM_PARAMS) over
+ * the header and dense cells of the fitted `model` (read only), in 0.32
+ * fixed point, made non-decreasing by a running maximum.  mode: a
+ * husky_learned_mode; MONOTONE and UNTRAINED evaluate the softplus-weight
+ * network, UNCONSTRAINED the raw-weight one, EQUAL_WIDTH and CONSTANT ignore
+ * params.  ws (device) needs husky_learned_lut_workspace_bytes() bytes.
+ * Asynchronous on stream.  Errors: HUSKY_ERR_ARG, HUSKY_ERR_WORKSPACE,
+ * HUSKY_ERR_HIP. */
+size_t husky_learned_lut_workspace_bytes(void);
+husky_status husky_learned_eval_lut(const float* params, int mode, const void* model, uint32_t* lut,
+                                    void* ws, size_t ws_bytes, void* stream);
 
 /* Static text for a status code (host). */
 const char* husky_status_string(husky_status s);

@@ -6,7 +6,8 @@ If the library has not been built, every call raises ``RuntimeError``; there
 is no fallback.
 
 Strings are passed as a packed element tensor plus uint64 element offsets:
-``elems`` (uint8 for ASCII, int16/uint16 storage of UTF-16 code units) and
+``elems`` (uint8 for ASCII and byte strings, int16/uint16 storage of UTF-16
+code units) and
 ``offsets`` (int64 storage of uint64[n + 1]), both on the GPU.
 """
 
@@ -21,9 +22,9 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libhusky.so")
 
-CODERS = {"ascii7": 0, "utf16": 1}
+CODERS = {"ascii7": 0, "utf16": 1, "bytes8": 2}
 STATUS = {0: "ok", 1: "invalid argument", 2: "domain violation", 3: "workspace",
-          4: "HIP runtime error", 5: "unsupported tuning"}
+          4: "HIP runtime error", 5: "unsupported tuning", 6: "groups left tied"}
 
 
 class HuskyError(RuntimeError):
@@ -34,6 +35,21 @@ class HuskyError(RuntimeError):
 
 class DomainError(HuskyError):
     """An ASCII7 string holds a byte >= 0x80 among its first nine bytes."""
+
+
+class UnresolvedError(HuskyError):
+    """Groups were still tied after tuning.max_rounds fixed rounds: perm is not final."""
+
+
+def _raise_on_status(ws, what: str):
+    """Read the device status block (synchronizes) and raise on a condition that
+    leaves the permutation unspecified or not final."""
+    st = read_status(ws)
+    if st["domain_violations"]:
+        raise DomainError(2, f"{what} ({st['domain_violations']} strings)")
+    if st["unresolved"]:
+        raise UnresolvedError(6, f"{what} ({st['unresolved']} groups; raise tuning.max_rounds)")
+    return st
 
 
 class Tuning(ctypes.Structure):
@@ -51,18 +67,19 @@ def make_tuning(radix_bits=0, tile_items=0, t_small=0, t_medium=0, max_rounds=0)
 
 def rounds_for(max_len: int, coder="ascii7") -> int:
     """Fixed device-wide rounds that resolve any run of strings of at most max_len elements."""
-    m, c = (9, 7) if _coder(coder) == 0 else (4, 3)
+    m, c = {0: (9, 7), 1: (4, 3), 2: (8, 7)}[_coder(coder)]
     return max(1, -(-(max(int(max_len), m) - m) // c))
 
 
 _lib = None
 
-EXPORTS = ("husky_workspace_bytes", "husky_encode", "husky_sort_pairs", "husky_fixup",
+EXPORTS = ("husky_workspace_bytes", "husky_encode", "husky_sort_pairs", "husky_fixup", "husky_refine",
            "husky_sort", "husky_sort_batched", "husky_check_perm", "husky_profile_begin",
            "husky_profile_end", "husky_profile_select", "husky_learned_model_bytes", "husky_learned_offset",
            "husky_learned_workspace_bytes", "husky_learned_fit", "husky_sort_learned",
            "husky_learned_buckets",
-           "husky_mlp_grad_workspace_bytes", "husky_mlp_grad", "husky_status_string")
+           "husky_mlp_grad_workspace_bytes", "husky_mlp_grad", "husky_learned_lut_workspace_bytes",
+           "husky_learned_eval_lut", "husky_status_string")
 
 # kernel classes of husky_profile_end (include/husky.h)
 PROFILE_CLASSES = ("encode", "radix_vary", "radix_count_scan", "radix_scatter", "radix_copy_back",
@@ -116,6 +133,8 @@ def load(path: str = LIB_PATH):
     lib.husky_sort_pairs.argtypes = [vp, vp, u64, i32, i32, vp, sz, tp, vp]
     lib.husky_fixup.restype = i32
     lib.husky_fixup.argtypes = [i32, vp, vp, u64, vp, vp, vp, u64, vp, sz, tp, vp]
+    lib.husky_refine.restype = i32
+    lib.husky_refine.argtypes = [i32, vp, vp, u64, vp, vp, vp, u64, ctypes.c_uint32, vp, sz, tp, vp]
     lib.husky_sort.restype = i32
     lib.husky_sort.argtypes = [i32, vp, vp, u64, vp, vp, sz, tp, vp]
     lib.husky_sort_batched.restype = i32
@@ -145,6 +164,10 @@ def load(path: str = LIB_PATH):
     lib.husky_mlp_grad_workspace_bytes.argtypes = [ctypes.c_uint32]
     lib.husky_mlp_grad.restype = i32
     lib.husky_mlp_grad.argtypes = [vp, vp, vp, ctypes.c_uint32, i32, vp, vp, sz, vp]
+    lib.husky_learned_lut_workspace_bytes.restype = sz
+    lib.husky_learned_lut_workspace_bytes.argtypes = []
+    lib.husky_learned_eval_lut.restype = i32
+    lib.husky_learned_eval_lut.argtypes = [vp, i32, vp, vp, vp, sz, vp]
     lib.husky_status_string.restype = ctypes.c_char_p
     lib.husky_status_string.argtypes = [i32]
     _lib = lib
@@ -254,6 +277,22 @@ def fixup(elems, offsets, sorted_codes, idx, coder="ascii7", seg_offsets=None,
     return idx
 
 
+def refine(elems, offsets, sorted_keys, idx, shared_elems=0, coder="ascii7", seg_offsets=None,
+           tuning: Optional[Tuning] = None, ws=None, stream=None):
+    """Re-sort every run of equal sorted_keys by the full comparator, in place on idx;
+    every member of a run shares its first min(len, shared_elems) elements (0..15)."""
+    lib = load()
+    n = _n_of(offsets)
+    ns = 1 if seg_offsets is None else int(seg_offsets.numel()) - 1
+    if ws is None:
+        ws = alloc_workspace(n, ns, offsets.device)
+    _check(lib.husky_refine(_coder(coder), _ptr(elems), _ptr(offsets), n, _ptr(sorted_keys),
+                            _ptr(idx), _ptr(seg_offsets), ns, int(shared_elems), _ptr(ws), ws.numel(),
+                            ctypes.byref(tuning) if tuning else None, _stream(stream)),
+           "husky_refine")
+    return idx
+
+
 def sort(elems, offsets, coder="ascii7", tuning: Optional[Tuning] = None, ws=None, perm=None,
          stream=None, check_status=True):
     """Algorithm 1 on the GPU: returns perm (int32 storage of uint32[n])."""
@@ -268,9 +307,7 @@ def sort(elems, offsets, coder="ascii7", tuning: Optional[Tuning] = None, ws=Non
                           ws.numel(), ctypes.byref(tuning) if tuning else None, _stream(stream)),
            "husky_sort")
     if check_status:
-        st = read_status(ws)
-        if st["domain_violations"]:
-            raise DomainError(2, f"husky_sort ({st['domain_violations']} strings)")
+        _raise_on_status(ws, "husky_sort")
     return perm[:n]
 
 
@@ -290,9 +327,7 @@ def sort_batched(elems, offsets, seg_offsets, coder="ascii7", tuning: Optional[T
                                   ctypes.byref(tuning) if tuning else None, _stream(stream)),
            "husky_sort_batched")
     if check_status:
-        st = read_status(ws)
-        if st["domain_violations"]:
-            raise DomainError(2, f"husky_sort_batched ({st['domain_violations']} strings)")
+        _raise_on_status(ws, "husky_sort_batched")
     return perm[:n]
 
 
@@ -382,9 +417,7 @@ def sort_learned(elems, offsets, model, coder="ascii7", tuning: Optional[Tuning]
                                   ctypes.byref(tuning) if tuning else None, _stream(stream)),
            "husky_sort_learned")
     if check_status:
-        st = read_status(ws)
-        if st["domain_violations"]:
-            raise DomainError(2, f"husky_sort_learned ({st['domain_violations']} strings)")
+        _raise_on_status(ws, "husky_sort_learned")
     return perm[:n]
 
 
@@ -410,6 +443,23 @@ def mlp_grad(params, x, y, monotone=True, stream=None):
     _check(lib.husky_mlp_grad(_ptr(params), _ptr(x), _ptr(y), count, 1 if monotone else 0,
                               _ptr(g), _ptr(ws), ws.numel(), _stream(stream)), "husky_mlp_grad")
     return g[:LEARNED_NPARAM], g[LEARNED_NPARAM]
+
+
+def learned_eval_lut(model, params=None, mode="monotone", stream=None):
+    """The inference kernel alone: the LUT (int32 storage of uint32[2^24 + 1]) of the
+    network with raw parameters `params` (float32[NPARAM], default: the model's own)
+    over the model's header and dense cells."""
+    torch = _torch()
+    lib = load()
+    if params is None:
+        params = learned_part(model, "params", torch.float32, LEARNED_NPARAM)
+    m = LEARNED_MODES[mode] if isinstance(mode, str) else int(mode)
+    lut = torch.empty(LEARNED_CELLS + 1, dtype=torch.int32, device=model.device)
+    ws = torch.empty(int(lib.husky_learned_lut_workspace_bytes()), dtype=torch.uint8,
+                     device=model.device)
+    _check(lib.husky_learned_eval_lut(_ptr(params), m, _ptr(model), _ptr(lut), _ptr(ws), ws.numel(),
+                                      _stream(stream)), "husky_learned_eval_lut")
+    return lut
 
 
 def profile_begin(classes=None):

@@ -311,16 +311,17 @@ static hipError_t side_join(hipStream_t s, const SideStreams* ss) {
 // Step 3 over the segments currently described in c.rad (the instances the
 // codes were sorted in).  `codes` are the sorted codes; `keys`/`keys_alt`
 // are scratch key buffers (may alias `codes` once the runs are found).
-husky_status run_fixup(Ctx& c, const Tune& tn, int coder, const void* elems,
+husky_status run_fixup(Ctx& c, const Tune& tn, int coder, uint32_t origin, const void* elems,
                        const uint64_t* offsets, uint64_t n, uint64_t n_segs,
                        const uint64_t* codes, uint64_t* keys, uint64_t* keys_alt, uint32_t* idx,
                        hipStream_t s, bool perfect_codes = false) {
     HUSKY_TRY(zero_u32(c.counters + CNT_SMALL, 16, s));  // tier counts [80, 96)
     c.tiers.lds_max = tn.t_medium < LDS_RUN_MAX ? LDS_RUN_MAX : 0u;
     const uint32_t tb = tiles_bound(n, n_segs, tn.rc);
-    HUSKY_TRY(find_runs(codes, c.rad, tn.rc, tb, coder, false, nullptr, c.runs, c.tiers,
+    const int ek = elem_kind(coder);
+    HUSKY_TRY(find_runs(codes, c.rad, tn.rc, tb, ek, false, nullptr, c.runs, c.tiers,
                         tn.t_small, tn.t_medium, s, perfect_codes));
-    FixupArgs fa{coder, elems, offsets, (uint32_t)n, idx, c.at<uint64_t>(c.L.key0)};
+    FixupArgs fa{ek, elems, offsets, (uint32_t)n, idx, c.at<uint64_t>(c.L.key0), origin};
     uint32_t rounds = 0;
     RunItem* cur = c.at<RunItem>(c.L.large_a);
     RunItem* nxt = c.at<RunItem>(c.L.large_b);
@@ -364,7 +365,7 @@ husky_status run_fixup(Ctx& c, const Tune& tn, int coder, const void* elems,
         t2.large = nxt;
         t2.large_count = nxt_cnt;
         HUSKY_TRY(zero_u32(nxt_cnt, 4, s));
-        HUSKY_TRY(find_runs(keys, c.rad, tn.rc, all_tiles, coder, true, cur, c.runs, t2,
+        HUSKY_TRY(find_runs(keys, c.rad, tn.rc, all_tiles, ek, true, cur, c.runs, t2,
                             tn.t_small, tn.t_medium, s));
         std::swap(cur, nxt);
         std::swap(cur_cnt, nxt_cnt);
@@ -388,7 +389,8 @@ husky_status run_fixup(Ctx& c, const Tune& tn, int coder, const void* elems,
 }
 
 husky_status check_common(int coder, const void* elems, const uint64_t* offsets, uint64_t n) {
-    if (coder != HUSKY_CODER_ASCII7 && coder != HUSKY_CODER_UTF16) return HUSKY_ERR_ARG;
+    if (coder != HUSKY_CODER_ASCII7 && coder != HUSKY_CODER_UTF16 && coder != HUSKY_CODER_BYTES8)
+        return HUSKY_ERR_ARG;
     if (n >= (1ull << 32)) return HUSKY_ERR_ARG;
     if (n > 0 && (!elems || !offsets)) return HUSKY_ERR_ARG;
     return HUSKY_OK;
@@ -436,14 +438,20 @@ husky_status husky_sort_pairs(uint64_t* codes, uint32_t* idx, uint64_t n, int be
     return HUSKY_OK;
 }
 
-husky_status husky_fixup(husky_coder coder, const void* elems, const uint64_t* offsets, uint64_t n,
-                         const uint64_t* sorted_codes, uint32_t* idx,
-                         const uint64_t* seg_offsets_or_null, uint64_t n_segs, void* ws,
-                         size_t ws_bytes, const husky_tuning* tuning, void* stream) {
+// Step 3 over runs of equal keys: husky_fixup (keys are husky codes; the
+// first refinement keys come from the encode kernel) and husky_refine (any
+// sorted keys whose runs share `origin` elements; first keys from the fix-up's
+// own key kernel).
+static husky_status refine_common(husky_coder coder, const void* elems, const uint64_t* offsets,
+                                  uint64_t n, const uint64_t* sorted_keys, uint32_t* idx,
+                                  const uint64_t* seg_offsets_or_null, uint64_t n_segs,
+                                  uint32_t origin, bool codes_are_husky, void* ws, size_t ws_bytes,
+                                  const husky_tuning* tuning, void* stream) {
     husky_status st = check_common(coder, elems, offsets, n);
     if (st != HUSKY_OK) return st;
-    if (n > 0 && (!sorted_codes || !idx)) return HUSKY_ERR_ARG;
+    if (n > 0 && (!sorted_keys || !idx)) return HUSKY_ERR_ARG;
     if (seg_offsets_or_null && (n_segs == 0 || n_segs >= (1ull << 32))) return HUSKY_ERR_ARG;
+    if (origin > 15) return HUSKY_ERR_ARG;
     if (!seg_offsets_or_null) n_segs = 1;
     Tune tn;
     st = resolve_tuning(tuning, &tn);
@@ -459,10 +467,32 @@ husky_status husky_fixup(husky_coder coder, const void* elems, const uint64_t* o
     else
         HUSKY_TRY(radix_segments_single((uint32_t)n, c.rad, tn.rc, s));
     // first refinement key of every string, read in string order
-    HUSKY_TRY(launch_encode(coder, elems, offsets, (uint32_t)n, nullptr, nullptr,
-                            c.at<uint64_t>(c.L.key0), nullptr, s));
-    return run_fixup(c, tn, coder, elems, offsets, n, n_segs, sorted_codes, c.at<uint64_t>(c.L.codes_a),
-                     c.at<uint64_t>(c.L.codes_b), idx, s);
+    uint64_t* key0 = c.at<uint64_t>(c.L.key0);
+    if (codes_are_husky) {
+        HUSKY_TRY(launch_encode(coder, elems, offsets, (uint32_t)n, nullptr, nullptr, key0, nullptr, s));
+    } else {
+        const FixupArgs fa{elem_kind(coder), elems, offsets, (uint32_t)n, idx, nullptr, origin};
+        HUSKY_TRY(fixup_first_keys(fa, key0, s));
+    }
+    return run_fixup(c, tn, coder, origin, elems, offsets, n, n_segs, sorted_keys,
+                     c.at<uint64_t>(c.L.codes_a), c.at<uint64_t>(c.L.codes_b), idx, s);
+}
+
+husky_status husky_fixup(husky_coder coder, const void* elems, const uint64_t* offsets, uint64_t n,
+                         const uint64_t* sorted_codes, uint32_t* idx,
+                         const uint64_t* seg_offsets_or_null, uint64_t n_segs, void* ws,
+                         size_t ws_bytes, const husky_tuning* tuning, void* stream) {
+    return refine_common(coder, elems, offsets, n, sorted_codes, idx, seg_offsets_or_null, n_segs,
+                         coder_m(coder), true, ws, ws_bytes, tuning, stream);
+}
+
+husky_status husky_refine(husky_coder coder, const void* elems, const uint64_t* offsets, uint64_t n,
+                          const uint64_t* sorted_keys, uint32_t* idx,
+                          const uint64_t* seg_offsets_or_null, uint64_t n_segs,
+                          uint32_t shared_elems, void* ws, size_t ws_bytes,
+                          const husky_tuning* tuning, void* stream) {
+    return refine_common(coder, elems, offsets, n, sorted_keys, idx, seg_offsets_or_null, n_segs,
+                         shared_elems, false, ws, ws_bytes, tuning, stream);
 }
 
 static husky_status sort_common(husky_coder coder, const void* elems, const uint64_t* offsets,
@@ -502,7 +532,8 @@ static husky_status sort_common(husky_coder coder, const void* elems, const uint
                                   (uint32_t)n_segs, tb, ~0u, c.rad, tn.rc, P_SCATTER, s));
     // the sorted codes are not needed once the runs are listed, so the
     // device-wide fix-up reuses both code buffers for its keys
-    return run_fixup(c, tn, coder, elems, offsets, n, n_segs, codes, codes, codes_b, perm, s, perfect);
+    return run_fixup(c, tn, coder, coder_m(coder), elems, offsets, n, n_segs, codes, codes, codes_b, perm,
+                     s, perfect);
 }
 
 husky_status husky_sort(husky_coder coder, const void* elems, const uint64_t* offsets, uint64_t n,
@@ -685,7 +716,7 @@ husky_status husky_sort_learned(husky_coder coder, const void* elems, const uint
     // Step 3 scans only the listed buckets: the larger ones and those with a
     // group still tied (equal codes share a bucket, so no run crosses one)
     HUSKY_TRY(radix_segments_from_items(scan, scan_count, B, c.rad, tn.rc, s));
-    return run_fixup(c, tn, coder, elems, offsets, n, B, codes, codes, codes_b, perm, s);
+    return run_fixup(c, tn, coder, coder_m(coder), elems, offsets, n, B, codes, codes, codes_b, perm, s);
 }
 
 husky_status husky_learned_buckets(husky_coder coder, const void* elems, const uint64_t* offsets,
@@ -714,6 +745,21 @@ husky_status husky_mlp_grad(const float* params, const float* x, const float* y,
                                    grad, (hipStream_t)stream));
 }
 
+size_t husky_learned_lut_workspace_bytes(void) { return (size_t)learned_lut_tiles() * 4; }
+
+husky_status husky_learned_eval_lut(const float* params, int mode, const void* model, uint32_t* lut,
+                                    void* ws, size_t ws_bytes, void* stream) {
+    if (!lut || (!params && (mode == HUSKY_LEARNED_MONOTONE || mode == HUSKY_LEARNED_UNCONSTRAINED ||
+                             mode == HUSKY_LEARNED_UNTRAINED)))
+        return HUSKY_ERR_ARG;
+    if (mode < 0 || mode > HUSKY_LEARNED_CONSTANT) return HUSKY_ERR_ARG;
+    husky_status st = check_model(model, learned_model_bytes());
+    if (st != HUSKY_OK) return st;
+    if (!ws || ws_bytes < husky_learned_lut_workspace_bytes()) return HUSKY_ERR_WORKSPACE;
+    return hip_status(learned_eval_lut(params, model, (uint32_t)mode, lut, (uint32_t*)ws,
+                                       (hipStream_t)stream));
+}
+
 const char* husky_status_string(husky_status s) {
     switch (s) {
         case HUSKY_OK: return "ok";
@@ -722,6 +768,7 @@ const char* husky_status_string(husky_status s) {
         case HUSKY_ERR_WORKSPACE: return "workspace missing, misaligned or too small";
         case HUSKY_ERR_HIP: return "HIP runtime error";
         case HUSKY_ERR_UNSUPPORTED: return "tuning value not supported";
+        case HUSKY_ERR_UNRESOLVED: return "groups still tied after the fixed refinement rounds";
     }
     return "unknown status";
 }

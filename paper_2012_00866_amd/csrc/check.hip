@@ -109,7 +109,8 @@ extern "C" husky_status husky_check_perm(husky_coder coder, const void* elems,
                                          const uint64_t* seg_offsets_or_null, uint64_t n_segs,
                                          const uint32_t* perm, void* ws, size_t ws_bytes,
                                          uint32_t* violations, void* stream) {
-    if (coder != HUSKY_CODER_ASCII7 && coder != HUSKY_CODER_UTF16) return HUSKY_ERR_ARG;
+    if (coder != HUSKY_CODER_ASCII7 && coder != HUSKY_CODER_UTF16 && coder != HUSKY_CODER_BYTES8)
+        return HUSKY_ERR_ARG;
     if (n >= (1ull << 32) || !violations) return HUSKY_ERR_ARG;
     if (n > 0 && (!elems || !offsets || !perm)) return HUSKY_ERR_ARG;
     if (seg_offsets_or_null && n_segs == 0) return HUSKY_ERR_ARG;
@@ -122,7 +123,8 @@ extern "C" husky_status husky_check_perm(husky_coder coder, const void* elems,
     const uint32_t blocks = (uint32_t)std::min<uint64_t>((n + BLOCK - 1) / BLOCK, 8192);
     hipLaunchKernelGGL(k_check_perm_range, dim3(blocks), dim3(BLOCK), 0, s, perm, (uint32_t)n,
                        seg_offsets_or_null, n_segs, (uint32_t*)ws, violations);
-    if (coder == HUSKY_CODER_ASCII7)
+    // byte strings (ASCII and full-byte coders) or UTF-16 units
+    if (coder != HUSKY_CODER_UTF16)
         hipLaunchKernelGGL(k_check_order<0>, dim3(blocks), dim3(BLOCK), 0, s, (const uint8_t*)elems,
                            offsets, perm, (uint32_t)n, seg_offsets_or_null, n_segs, violations);
     else

@@ -7,8 +7,11 @@
 // a few cache lines.  The code is assembled in registers:
 //   ASCII7: sum over j < min(len, 9) of (b_j & 0x7F) << 7 * (8 - j)
 //   UTF16 : sum over j < min(len, 4) of u_j << 16 * (3 - j)
+//   BYTES8: sum over j < min(len, 8) of b_j << 8 * (7 - j)
 // which is stringToLong's "shift in each character, then shift in the
-// padding" written as fixed bit positions.
+// padding" written as fixed bit positions.  The full-byte coder is the 8-bit
+// member of the alphabet-dependent coders of Sec. 3.2: every byte value keeps
+// its order, at the cost of one character fewer than the 7-bit coder.
 
 #include "bucket.h"
 #include "common.h"
@@ -43,7 +46,8 @@ __global__ __launch_bounds__(BLOCK) void k_encode(const uint8_t* __restrict__ by
                                                   uint32_t n_out, BucketArgs bucket, bool perfect) {
     // bytes in the element buffer (uniform scalar load): the three-word
     // window below is used only where it stays inside the buffer.
-    const uint64_t total_bytes = offsets[n] * (CODER == 0 ? 1u : 2u);
+    constexpr uint32_t ES = CODER == 1 ? 2u : 1u;  // bytes per element
+    const uint64_t total_bytes = offsets[n] * ES;
     uint32_t bad_here = 0;
     const uint32_t count = sel ? n_out : n;
     uint64_t m_lo = 0, m_hi = 0;
@@ -61,11 +65,11 @@ __global__ __launch_bounds__(BLOCK) void k_encode(const uint8_t* __restrict__ by
         const uint64_t len = o1 - o0;
         // string bytes 0..7 (lo) and 8..15 (mid), little-endian; bytes past
         // the string are masked off below
-        const uint64_t addr = CODER == 0 ? o0 : o0 * 2;
+        const uint64_t addr = o0 * ES;
         const uint64_t base = addr & ~7ull;
         const uint32_t sh = (uint32_t)(addr & 7ull) * 8u;
         const uint64_t need = (CODER == 0 ? 9u : 8u) + (key0 ? 7u : 0u);  // bytes used from addr
-        const uint64_t slen = len * (CODER == 0 ? 1u : 2u);
+        const uint64_t slen = len * ES;
         uint64_t lo = 0, mid = 0;
         if (base + 24 <= total_bytes) {
             const uint64_t* w = (const uint64_t*)(bytes + base);
@@ -104,6 +108,16 @@ __global__ __launch_bounds__(BLOCK) void k_encode(const uint8_t* __restrict__ by
                 const uint64_t nb = rem < 7 ? rem : 7;
                 const uint64_t clen = rem > 7 ? 8 : rem;
                 const uint64_t w = (mid >> 8) & (nb ? ((1ull << (8 * nb)) - 1ull) : 0ull);
+                k0 = ((uint64_t)L << 60) | ((__builtin_bswap64(w) >> 8) << 4) | clen;
+            }
+        } else if (CODER == 2) {
+            const uint32_t L = len < 8 ? (uint32_t)len : 8u;
+            code = L == 0 ? 0ull : (__builtin_bswap64(lo) & (~0ull << (8 * (8 - L))));
+            if (key0) {
+                const uint64_t rem = len > 8 ? len - 8 : 0;
+                const uint64_t nb = rem < 7 ? rem : 7;
+                const uint64_t clen = rem > 7 ? 8 : rem;
+                const uint64_t w = mid & (nb ? ((1ull << (8 * nb)) - 1ull) : 0ull);
                 k0 = ((uint64_t)L << 60) | ((__builtin_bswap64(w) >> 8) << 4) | clen;
             }
         } else {
@@ -175,8 +189,10 @@ hipError_t launch_encode(int coder, const void* elems, const uint64_t* offsets, 
 #define HUSKY_ENC(C, L)                                                                           \
     hipLaunchKernelGGL((k_encode<C, L>), dim3(blocks), dim3(BLOCK), 0, s, e, offsets, n, codes, idx, \
                        key0, status, sel, n_out, b, perfect && coder == 0)
-    if (coder == 0) {
+    if (coder == CODER_ASCII7) {
         if (bucket) HUSKY_ENC(0, true); else HUSKY_ENC(0, false);
+    } else if (coder == CODER_BYTES8) {
+        if (bucket) HUSKY_ENC(2, true); else HUSKY_ENC(2, false);
     } else {
         if (bucket) HUSKY_ENC(1, true); else HUSKY_ENC(1, false);
     }

@@ -5,12 +5,14 @@
 //
 // Inside a run all codes are equal, so (given the coder's domain) every
 // member agrees on its first min(len, m) elements (m = 9 bytes for ASCII7,
-// 4 units for UTF16).  The run is ordered by "refinement keys": round r looks
-// at the chunk of C elements starting at p = m + C*r (C = 7 bytes / 3 units)
+// 8 for the full-byte coder, 4 units for UTF16).  That count is the run's
+// "origin" (any value up to 15 through husky_refine, 0 when equal keys imply
+// nothing).  The run is ordered by "refinement keys": round r looks at the
+// chunk of C elements starting at p = origin + C*r (C = 7 bytes / 3 units)
 // and packs it into one 64-bit key
-//     [63:60] min(len, m)       -- members shorter than m order by length
+//     [63:60] min(len, origin) -- members shorter than the origin order by length
 //     [59: 4] the chunk, big-endian, zero past the string end
-//             (ASCII: 7 bytes in [59:4]; UTF16: 3 units in [59:12])
+//             (bytes: 7 bytes in [59:4]; UTF16: 3 units in [59:12])
 //     [ 3: 0] elements of the chunk present, or C+1 when the string goes on.
 // Comparing these keys is comparing the strings on [p, p + C) with a proper
 // prefix first; members tied on a key whose last field is C+1 continue to
@@ -39,20 +41,21 @@ namespace husky {
 
 template <int CODER>
 __device__ __forceinline__ uint64_t chunk_key(const uint8_t* __restrict__ bytes, uint64_t total_bytes,
-                                              uint64_t off, uint64_t len, uint32_t round) {
+                                              uint64_t off, uint64_t len, uint32_t round,
+                                              uint32_t origin) {
     if (CODER == 0) {
-        const uint64_t p = (uint64_t)ascii_m + (uint64_t)ascii_chunk * round;
-        const uint64_t top = len < (uint64_t)ascii_m ? len : (uint64_t)ascii_m;
+        const uint64_t p = (uint64_t)origin + (uint64_t)byte_chunk * round;
+        const uint64_t top = len < (uint64_t)origin ? len : (uint64_t)origin;
         const uint64_t rem = len > p ? len - p : 0;
-        const uint64_t clen = rem > (uint64_t)ascii_chunk ? (uint64_t)ascii_chunk + 1 : rem;
-        const uint64_t nb = rem < (uint64_t)ascii_chunk ? rem : (uint64_t)ascii_chunk;
+        const uint64_t clen = rem > (uint64_t)byte_chunk ? (uint64_t)byte_chunk + 1 : rem;
+        const uint64_t nb = rem < (uint64_t)byte_chunk ? rem : (uint64_t)byte_chunk;
         uint64_t w = nb ? load8_unaligned(bytes, total_bytes, off + p) : 0ull;
         w &= nb ? ((1ull << (8 * nb)) - 1ull) : 0ull;
         const uint64_t chunk = bswap64(w) >> 8;  // byte p in bits 55..48
         return (top << 60) | (chunk << 4) | clen;
     } else {
-        const uint64_t p = (uint64_t)utf16_m + (uint64_t)utf16_chunk * round;
-        const uint64_t top = len < (uint64_t)utf16_m ? len : (uint64_t)utf16_m;
+        const uint64_t p = (uint64_t)origin + (uint64_t)utf16_chunk * round;
+        const uint64_t top = len < (uint64_t)origin ? len : (uint64_t)origin;
         const uint64_t rem = len > p ? len - p : 0;
         const uint64_t clen = rem > (uint64_t)utf16_chunk ? (uint64_t)utf16_chunk + 1 : rem;
         const uint64_t nu = rem < (uint64_t)utf16_chunk ? rem : (uint64_t)utf16_chunk;
@@ -64,6 +67,19 @@ __device__ __forceinline__ uint64_t chunk_key(const uint8_t* __restrict__ bytes,
     }
 }
 
+// First refinement key of every string, in string order: round 0 from `origin`.
+template <int CODER>
+__global__ __launch_bounds__(BLOCK) void k_first_keys(const uint8_t* __restrict__ bytes,
+                                                      const uint64_t* __restrict__ offsets,
+                                                      uint32_t n, uint32_t origin,
+                                                      uint64_t* __restrict__ key0) {
+    const uint64_t total_bytes = offsets[n] * (CODER == 0 ? 1u : 2u);
+    for (uint32_t i = blockIdx.x * BLOCK + threadIdx.x; i < n; i += gridDim.x * BLOCK) {
+        const uint64_t o = offsets[i];
+        key0[i] = chunk_key<CODER>(bytes, total_bytes, o, offsets[i + 1] - o, 0u, origin);
+    }
+}
+
 // ------------------------------------------------------------------ small tier
 template <int CODER>
 __global__ __launch_bounds__(BLOCK) void k_fix_small(const RunItem* __restrict__ items,
@@ -71,7 +87,8 @@ __global__ __launch_bounds__(BLOCK) void k_fix_small(const RunItem* __restrict__
                                                      uint32_t cap, const uint8_t* __restrict__ bytes,
                                                      const uint64_t* __restrict__ offsets,
                                                      uint32_t n, uint32_t* __restrict__ idx,
-                                                     const uint64_t* __restrict__ key0) {
+                                                     const uint64_t* __restrict__ key0,
+                                                     uint32_t origin) {
     const uint64_t total_bytes = offsets[n] * (CODER == 0 ? 1u : 2u);
     const uint32_t n_items = min(*count, cap);
     const uint32_t lane = lane_id();
@@ -111,7 +128,7 @@ __global__ __launch_bounds__(BLOCK) void k_fix_small(const RunItem* __restrict__
                         len = offsets[member + 1] - off;
                         have_ol = true;
                     }
-                    key = chunk_key<CODER>(bytes, total_bytes, off, len, round);
+                    key = chunk_key<CODER>(bytes, total_bytes, off, len, round, origin);
                 }
             }
             if (first && lane < rn.len) member_next = idx[rn.start + lane];
@@ -169,7 +186,7 @@ __global__ __launch_bounds__(BLOCK) void k_fix_medium(const RunItem* __restrict_
                                                       const uint64_t* __restrict__ offsets,
                                                       uint32_t n, uint32_t* __restrict__ idx,
                                                       const uint64_t* __restrict__ key0,
-                                                      uint32_t lmin, uint32_t lmax) {
+                                                      uint32_t lmin, uint32_t lmax, uint32_t origin) {
     const uint64_t total_bytes = offsets[n] * (CODER == 0 ? 1u : 2u);
     extern __shared__ __align__(16) uint8_t lds_raw[];
     MediumLds<MAXL>& S = *reinterpret_cast<MediumLds<MAXL>*>(lds_raw);
@@ -212,7 +229,7 @@ __global__ __launch_bounds__(BLOCK) void k_fix_medium(const RunItem* __restrict_
                 }
                 for (uint32_t q = tid; q < L; q += BLOCK) {
                     const uint32_t j = S.gj[q] & 0xFFFFu;
-                    S.key[q] = S.act[q] ? chunk_key<CODER>(bytes, total_bytes, S.off[j], S.len[j], round)
+                    S.key[q] = S.act[q] ? chunk_key<CODER>(bytes, total_bytes, S.off[j], S.len[j], round, origin)
                                         : 0ull;
                 }
             }
@@ -309,7 +326,7 @@ __global__ __launch_bounds__(NW * WAVE) void k_fix_lds(const RunItem* __restrict
                                                    const uint64_t* __restrict__ offsets, uint32_t n,
                                                    uint32_t* __restrict__ idx,
                                                    const uint64_t* __restrict__ key0,
-                                                   uint32_t* __restrict__ queue) {
+                                                   uint32_t* __restrict__ queue, uint32_t origin) {
     constexpr uint32_t NT = NW * WAVE;
     constexpr uint32_t TILE = NT * ITEMS;
     static_assert(TILE <= 32768, "slots and group starts fit 15 bits");
@@ -333,7 +350,7 @@ __global__ __launch_bounds__(NW * WAVE) void k_fix_lds(const RunItem* __restrict
     auto key_of = [&](uint32_t m, uint32_t round) -> uint64_t {
         if (round == 0 && key0) return key0[m];
         const uint64_t o = offsets[m];
-        return chunk_key<CODER>(bytes, total_bytes, o, offsets[m + 1] - o, round);
+        return chunk_key<CODER>(bytes, total_bytes, o, offsets[m + 1] - o, round, origin);
     };
     // block-wide OR / AND of the keys and group starts each thread passes
     // (o = 0, a = ~0, g = 0, ga = ~0 for none); returns key bits and
@@ -604,7 +621,7 @@ __global__ __launch_bounds__(BLOCK) void k_large_keys(const RunItem* __restrict_
                                                       uint32_t n,
                                                       const uint32_t* __restrict__ idx,
                                                       const uint64_t* __restrict__ key0,
-                                                      uint64_t* __restrict__ keys) {
+                                                      uint64_t* __restrict__ keys, uint32_t origin) {
     constexpr uint32_t TILE = BLOCK * ITEMS;
     const uint64_t total_bytes = offsets[n] * (CODER == 0 ? 1u : 2u);
     const uint32_t t = blockIdx.x;
@@ -645,7 +662,7 @@ __global__ __launch_bounds__(BLOCK) void k_large_keys(const RunItem* __restrict_
 #pragma unroll
     for (int k = 0; k < ITEMS; ++k) {
         const uint32_t i = k * BLOCK + threadIdx.x;
-        if (i < nvalid) keys[base + i] = chunk_key<CODER>(bytes, total_bytes, o[k], e[k] - o[k], round);
+        if (i < nvalid) keys[base + i] = chunk_key<CODER>(bytes, total_bytes, o[k], e[k] - o[k], round, origin);
     }
 }
 
@@ -669,10 +686,12 @@ hipError_t fixup_small(const FixupArgs& a, const TierLists& tl, uint32_t, hipStr
     ProfScope ps(P_FIX_SMALL, s);
     if (a.coder == 0)
         hipLaunchKernelGGL(k_fix_small<0>, dim3(blocks), dim3(BLOCK), 0, s, tl.small, tl.small_count,
-                           tl.small_cap, (const uint8_t*)a.elems, a.offsets, a.n, a.idx, a.key0);
+                           tl.small_cap, (const uint8_t*)a.elems, a.offsets, a.n, a.idx, a.key0,
+                           a.origin);
     else
         hipLaunchKernelGGL(k_fix_small<1>, dim3(blocks), dim3(BLOCK), 0, s, tl.small, tl.small_count,
-                           tl.small_cap, (const uint8_t*)a.elems, a.offsets, a.n, a.idx, a.key0);
+                           tl.small_cap, (const uint8_t*)a.elems, a.offsets, a.n, a.idx, a.key0,
+                           a.origin);
     return hipGetLastError();
 }
 
@@ -692,7 +711,7 @@ static hipError_t medium_impl(const FixupArgs& a, const TierLists& tl, uint32_t 
     ProfScope ps(P_FIX_MEDIUM, s);
     hipLaunchKernelGGL((k_fix_medium<CODER, MAXL>), dim3(blocks), dim3(BLOCK), lds, s, tl.medium,
                        tl.medium_count, tl.medium_cap, (const uint8_t*)a.elems, a.offsets, a.n,
-                       a.idx, a.key0, lmin, lmax);
+                       a.idx, a.key0, lmin, lmax, a.origin);
     return hipGetLastError();
 }
 
@@ -726,7 +745,7 @@ static hipError_t lds_classes(const FixupArgs& a, const TierLists& tl, uint32_t 
     static_assert(NW * WAVE * I == lds_class_max(C), "class tile");                                \
     hipLaunchKernelGGL((k_fix_lds<CODER, I, NW>), dim3(cus * PER_CU), dim3(NW * WAVE), 0, s,        \
                        tl.lds[C], tl.lds_count + C, tl.lds_cap[C], (const uint8_t*)a.elems, a.offsets, \
-                       a.n, a.idx, a.key0, tl.lds_queue + C)
+                       a.n, a.idx, a.key0, tl.lds_queue + C, a.origin)
     if (t_medium < lds_class_max(0)) HUSKY_FL(12, 4, 4, 0);
     if (t_medium < lds_class_max(1)) HUSKY_FL(16, 4, 3, 1);
     HUSKY_FL(12, 8, 2, 2);
@@ -749,7 +768,7 @@ hipError_t fixup_large_keys(const FixupArgs& a, const RunItem* items, const Radi
     if (a.coder == C && cfg.items == I) {                                                    \
         hipLaunchKernelGGL((k_large_keys<C, I>), dim3(max_tiles), dim3(BLOCK), 0, s, items,  \
                            seg.segs, seg.counters, (const uint8_t*)a.elems, a.offsets, a.n,  \
-                           a.idx, a.key0, keys);                                             \
+                           a.idx, a.key0, keys, a.origin);                                   \
         return hipGetLastError();                                                            \
     }
     HUSKY_LK(0, 16)
@@ -760,6 +779,19 @@ hipError_t fixup_large_keys(const FixupArgs& a, const RunItem* items, const Radi
     HUSKY_LK(1, 8)
 #undef HUSKY_LK
     return hipErrorInvalidValue;
+}
+
+hipError_t fixup_first_keys(const FixupArgs& a, uint64_t* key0, hipStream_t s) {
+    if (!a.n) return hipSuccess;
+    const uint32_t blocks = std::min<uint32_t>((a.n + BLOCK - 1) / BLOCK, 65536u);
+    ProfScope ps(P_LARGE_KEYS, s);
+    if (a.coder == 0)
+        hipLaunchKernelGGL(k_first_keys<0>, dim3(blocks), dim3(BLOCK), 0, s, (const uint8_t*)a.elems,
+                           a.offsets, a.n, a.origin, key0);
+    else
+        hipLaunchKernelGGL(k_first_keys<1>, dim3(blocks), dim3(BLOCK), 0, s, (const uint8_t*)a.elems,
+                           a.offsets, a.n, a.origin, key0);
+    return hipGetLastError();
 }
 
 }  // namespace husky

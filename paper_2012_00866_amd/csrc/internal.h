@@ -158,12 +158,15 @@ hipError_t zero_u32(uint32_t* p, size_t n, hipStream_t s);
 
 // ---- fixup.hip
 struct FixupArgs {
-    int coder;
+    int coder;                // element kind: 0 bytes, 1 UTF-16 units (elem_kind)
     const void* elems;
     const uint64_t* offsets;  // [n + 1]; offsets[n] is the element total
     uint32_t n;
     uint32_t* idx;            // permutation being fixed, in place
     const uint64_t* key0;     // [n] first refinement key of every string
+    uint32_t origin;          // elements every member of a run shares (up to
+                              // its length): refinement round r compares from
+                              // origin + C*r; at most 15
 };
 
 hipError_t fixup_small(const FixupArgs& a, const TierLists& tl, uint32_t t_small, hipStream_t s);
@@ -176,6 +179,8 @@ hipError_t fixup_lds(const FixupArgs& a, const TierLists& tl, uint32_t t_medium,
 hipError_t fixup_large_keys(const FixupArgs& a, const RunItem* items, const RadixScratch& seg,
                             const RadixConfig& cfg, uint32_t max_tiles, uint64_t* keys,
                             hipStream_t s);
+// key0[i] = string i's first refinement key (round 0 from a.origin).
+hipError_t fixup_first_keys(const FixupArgs& a, uint64_t* key0, hipStream_t s);
 
 // ---- learned.hip
 constexpr uint32_t LEARNED_BUCKETS = 65536;
@@ -198,6 +203,10 @@ hipError_t learned_train(void* model, const float* x, const float* y, uint32_t c
                          uint32_t epochs, uint32_t batch, float lr, bool mono, float* partial,
                          uint32_t max_blocks, float* grad, float* loss_acc, hipStream_t s);
 hipError_t learned_build_lut(void* model, uint32_t mode, uint32_t* tmax, hipStream_t s);
+// The LUT of `params` (mode as husky_learned_mode) over the header and dense
+// cells of `model`, written to lut (uint32[2^24 + 1]), running maximum included.
+hipError_t learned_eval_lut(const float* params, const void* model, uint32_t mode, uint32_t* lut,
+                            uint32_t* tmax, hipStream_t s);
 hipError_t learned_splitters(void* model, const uint64_t* sorted_sample, uint32_t S, hipStream_t s);
 BucketArgs learned_bucket_args(const void* model, uint16_t* bid);
 hipError_t learned_bucket_pass(int pass, const uint64_t* ks, const uint32_t* vs, const uint16_t* bs,
@@ -217,15 +226,25 @@ hipError_t learned_bucket_bounds(const uint16_t* bid, uint32_t n, uint64_t* seg,
                                  uint32_t* scan_count, RunItem* const lists[4],
                                  uint32_t* class_count, hipStream_t s);
 
-// Chunk geometry of the refinement keys.
-constexpr int ascii_m = 9, ascii_chunk = 7;
-constexpr int utf16_m = 4, utf16_chunk = 3;
+// Coders (husky_coder) and the geometry of their refinement keys: the code
+// covers the first m elements; a refinement round covers the next chunk of
+// 7 bytes or 3 UTF-16 units.
+constexpr int ascii_m = 9, bytes8_m = 8, utf16_m = 4;
+constexpr int byte_chunk = 7, utf16_chunk = 3;
+constexpr int CODER_ASCII7 = 0, CODER_UTF16 = 1, CODER_BYTES8 = 2;
+// Element kind of a coder (0: bytes, 1: 16-bit units): what the run
+// detection, fix-up and device check depend on.
+__host__ __device__ constexpr int elem_kind(int coder) { return coder == CODER_UTF16 ? 1 : 0; }
+// Elements a husky code covers.
+__host__ __device__ constexpr uint32_t coder_m(int coder) {
+    return coder == CODER_ASCII7 ? ascii_m : (coder == CODER_UTF16 ? utf16_m : bytes8_m);
+}
 
 // A refinement key whose length field says the string goes on past its chunk:
 // two such equal keys are still tied.
 template <int CODER>
 __device__ __forceinline__ bool key_continues(uint64_t key) {
-    return (key & 0xFull) == (CODER == 0 ? (uint64_t)ascii_chunk + 1 : (uint64_t)utf16_chunk + 1);
+    return (key & 0xFull) == (CODER == 0 ? (uint64_t)byte_chunk + 1 : (uint64_t)utf16_chunk + 1);
 }
 
 }  // namespace husky

@@ -1329,11 +1329,18 @@ hipError_t learned_bucket_refine(int coder, uint64_t* codes, uint32_t* perm, con
                            codes, perm, k0, (const RunItem*)fallback[L], fallback_counts + L, BITS,  \
                            scan_list, scan_count);                                                   \
     }
-    if (coder == 0) {
+    // element kind 0 (bytes) or 1 (UTF-16 units); the ASCII code's top bit is
+    // always clear, the other coders use all 64
+    if (coder == CODER_ASCII7) {
         HUSKY_RF(0, 12, 4, 0, 4, 63);
         HUSKY_RF(0, 16, 4, 1, 3, 63);
         HUSKY_RF(0, 12, 8, 2, 2, 63);
         HUSKY_RF(0, 16, 8, 3, 1, 63);
+    } else if (coder == CODER_BYTES8) {
+        HUSKY_RF(0, 12, 4, 0, 4, 64);
+        HUSKY_RF(0, 16, 4, 1, 3, 64);
+        HUSKY_RF(0, 12, 8, 2, 2, 64);
+        HUSKY_RF(0, 16, 8, 3, 1, 64);
     } else {
         HUSKY_RF(1, 12, 4, 0, 4, 64);
         HUSKY_RF(1, 16, 4, 1, 3, 64);
@@ -1457,29 +1464,34 @@ hipError_t learned_train(void* model, const float* x, const float* y, uint32_t c
     return hipGetLastError();
 }
 
-hipError_t learned_build_lut(void* model, uint32_t mode, uint32_t* tmax, hipStream_t s) {
-    ModelView m = model_view(model);
+hipError_t learned_eval_lut(const float* p, const void* model, uint32_t mode, uint32_t* lut,
+                            uint32_t* tmax, hipStream_t s) {
+    ModelView m = model_view(const_cast<void*>(model));
     const LearnedHeader* h = m.hdr;
-    const float* p = m.params;
     const dim3 g(8192), t(256);
     switch (mode) {
         case HUSKY_LEARNED_EQUAL_WIDTH:
-            hipLaunchKernelGGL((k_lut_eval<true, LUT_IDENTITY>), g, t, 0, s, p, h, m.dense, m.dense_cum, m.lut);
+            hipLaunchKernelGGL((k_lut_eval<true, LUT_IDENTITY>), g, t, 0, s, p, h, m.dense, m.dense_cum, lut);
             break;
         case HUSKY_LEARNED_CONSTANT:
-            hipLaunchKernelGGL((k_lut_eval<true, LUT_ZERO>), g, t, 0, s, p, h, m.dense, m.dense_cum, m.lut);
+            hipLaunchKernelGGL((k_lut_eval<true, LUT_ZERO>), g, t, 0, s, p, h, m.dense, m.dense_cum, lut);
             break;
         case HUSKY_LEARNED_UNCONSTRAINED:
-            hipLaunchKernelGGL((k_lut_eval<false, LUT_NET>), g, t, 0, s, p, h, m.dense, m.dense_cum, m.lut);
+            hipLaunchKernelGGL((k_lut_eval<false, LUT_NET>), g, t, 0, s, p, h, m.dense, m.dense_cum, lut);
             break;
         default:
-            hipLaunchKernelGGL((k_lut_eval<true, LUT_NET>), g, t, 0, s, p, h, m.dense, m.dense_cum, m.lut);
+            hipLaunchKernelGGL((k_lut_eval<true, LUT_NET>), g, t, 0, s, p, h, m.dense, m.dense_cum, lut);
     }
     const uint32_t n = LUT_CELLS + 1, tiles = (n + LUT_TILE - 1) / LUT_TILE;
-    hipLaunchKernelGGL(k_lut_tilemax, dim3(tiles), dim3(256), 0, s, (const uint32_t*)m.lut, n, tmax);
+    hipLaunchKernelGGL(k_lut_tilemax, dim3(tiles), dim3(256), 0, s, (const uint32_t*)lut, n, tmax);
     hipLaunchKernelGGL(k_lut_carry, dim3(1), dim3(256), 0, s, tmax, tiles);
-    hipLaunchKernelGGL(k_lut_apply, dim3(tiles), dim3(256), 0, s, m.lut, n, (const uint32_t*)tmax);
+    hipLaunchKernelGGL(k_lut_apply, dim3(tiles), dim3(256), 0, s, lut, n, (const uint32_t*)tmax);
     return hipGetLastError();
+}
+
+hipError_t learned_build_lut(void* model, uint32_t mode, uint32_t* tmax, hipStream_t s) {
+    ModelView m = model_view(model);
+    return learned_eval_lut(m.params, model, mode, m.lut, tmax, s);
 }
 
 hipError_t learned_splitters(void* model, const uint64_t* sorted_sample, uint32_t S, hipStream_t s) {

@@ -67,8 +67,24 @@ def test_fixed_rounds_reports_unresolved(gpu_lib):
     b = from_strings([b"x" * 60] * 9000 + [b"y"])
     e, o = gpu_lib.to_device(b)
     ws = gpu_lib.alloc_workspace(b.n)
-    gpu_lib.sort(e, o, "ascii7", tuning=gpu_lib.make_tuning(t_medium=256, max_rounds=1), ws=ws)
+    t = gpu_lib.make_tuning(t_medium=256, max_rounds=1)
+    gpu_lib.sort(e, o, "ascii7", tuning=t, ws=ws, check_status=False)
     assert gpu_lib.read_status(ws)["unresolved"] > 0
+    # the binding's default status check refuses the unfinished permutation,
+    # for the plain, batched and learned forms
+    with pytest.raises(gpu_lib.UnresolvedError):
+        gpu_lib.sort(e, o, "ascii7", tuning=t, ws=ws)
+    import torch
+
+    seg = torch.tensor([0, 1, b.n], dtype=torch.int64, device="cuda")  # a run of 8,999 in one instance
+    with pytest.raises(gpu_lib.UnresolvedError):
+        gpu_lib.sort_batched(e, o, seg, "ascii7", tuning=t)
+    model = gpu_lib.fit_learned(e, o, "ascii7", gpu_lib.make_learned_params(sample_frac=0.1))
+    with pytest.raises(gpu_lib.UnresolvedError):
+        gpu_lib.sort_learned(e, o, model, "ascii7", tuning=t)
+    # enough rounds: no error, and the oracle's answer
+    ok = gpu_lib.make_tuning(t_medium=256, max_rounds=gpu_lib.rounds_for(60))
+    np.testing.assert_array_equal(_u32(gpu_lib.sort(e, o, "ascii7", tuning=ok, ws=ws)), oracle.sort(b)[0])
 
 
 def test_graph_capture_replay_batched(gpu_lib):

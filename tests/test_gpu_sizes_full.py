@@ -8,7 +8,9 @@ benchmark uses (default tuning, one call per workload).
   order, equal strings in index order -- which together pin the unique stable
   answer), and 48 sampled instances equal the oracle's full sort.
 * 2e8 URL-like strings: the oracle's check over every adjacent pair and the
-  permutation property.
+  permutation property; then the learned-CDF form (fitted on the default 1 %
+  sample) on the same input must give the same permutation element by
+  element, and the device check must find no violation in it.
 """
 
 import numpy as np
@@ -62,12 +64,26 @@ def test_full_size_batched(gpu_lib):
 
 
 def test_full_size_urls(gpu_lib):
+    import torch
+
     b = config5()
     say("urls", b.name, "generated", b.elems.size, "bytes")
     e, o = gpu_lib.to_device(b)
-    perm = _u32(gpu_lib.sort(e, o, "ascii7"))
-    del e, o
+    ws = gpu_lib.alloc_learned_workspace(b.n)
+    plain = gpu_lib.sort(e, o, "ascii7", ws=ws)
+    perm = _u32(plain)
     say("gpu sort done")
     bad, first = oracle.check_perm(b, perm)
     say("oracle check done", bad)
     assert bad == 0, f"first bad position {first}"
+    del perm
+    model = gpu_lib.fit_learned(e, o, "ascii7", ws=ws)
+    learned = gpu_lib.sort_learned(e, o, model, "ascii7", ws=ws)
+    st = gpu_lib.read_status(ws)
+    say("learned sort done: overflow buckets", st["overflow_buckets"], "keys", st["overflow_keys"])
+    same = bool(torch.equal(learned, plain))
+    if not same:
+        diff = torch.nonzero(learned != plain)[:8].flatten().tolist()
+        raise AssertionError(f"learned permutation differs from the plain one at {diff}")
+    assert gpu_lib.check_perm(e, o, learned, "ascii7") == 0
+    say("learned permutation equals the plain one and passes the device check")
