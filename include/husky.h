@@ -81,8 +81,9 @@ typedef enum {
     HUSKY_ERR_WORKSPACE = 3,   /* workspace missing, too small or misaligned */
     HUSKY_ERR_HIP = 4,         /* a HIP runtime call failed */
     HUSKY_ERR_UNSUPPORTED = 5, /* tuning value outside the compiled variants */
-    HUSKY_ERR_UNRESOLVED = 6   /* (device status only) groups still tied after
+    HUSKY_ERR_UNRESOLVED = 6,  /* (device status only) groups still tied after
                                 * tuning.max_rounds fixed rounds: perm not final */
+    HUSKY_ERR_TOO_LARGE = 7    /* husky_sort_noalloc: n above HUSKY_NOALLOC_MAX_STRINGS */
 } husky_status;
 
 typedef enum {
@@ -204,6 +205,28 @@ husky_status husky_refine(husky_coder coder, const void* elems, const uint64_t* 
 husky_status husky_sort(husky_coder coder, const void* elems, const uint64_t* offsets,
                         uint64_t n, uint32_t* perm, void* ws, size_t ws_bytes,
                         const husky_tuning* tuning, void* stream);
+
+/* husky_sort without a workspace argument and without any allocation, for
+ * callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc).  The scratch space
+ * is a fixed array of HUSKY_NOALLOC_SCRATCH_BYTES (64 MiB) in the library's
+ * device memory, one copy per device, held until the process ends; it
+ * covers up to HUSKY_NOALLOC_MAX_STRINGS strings (n above that:
+ * HUSKY_ERR_TOO_LARGE, nothing enqueued).  Same arguments, result, errors
+ * and stream behaviour as husky_sort otherwise; the device status block is
+ * the first 24 bytes of that array, read with husky_noalloc_status.
+ * Every call on one device uses the same array and leaves its contents
+ * there: calls that overlap in time on one device (other streams or host
+ * threads) race and give unspecified results -- order them. */
+#define HUSKY_NOALLOC_SCRATCH_BYTES (64u << 20)
+#define HUSKY_NOALLOC_MAX_STRINGS (1u << 20)
+husky_status husky_sort_noalloc(husky_coder coder, const void* elems, const uint64_t* offsets,
+                                uint64_t n, uint32_t* perm, const husky_tuning* tuning,
+                                void* stream);
+/* Copies the status block of the current device's no-allocation scratch to
+ * *out (host), after synchronizing stream (on which the sort ran).
+ * Errors: HUSKY_ERR_ARG, HUSKY_ERR_HIP. */
+husky_status husky_noalloc_status(husky_device_status* out, void* stream);
 
 /* Batched form: n_segs independent instances sorted in the same launches.
  * n is the total number of strings; seg_offsets is uint64[n_segs + 1]

@@ -24,7 +24,8 @@ LIB_PATH = os.path.join(_HERE, "libhusky.so")
 
 CODERS = {"ascii7": 0, "utf16": 1, "bytes8": 2}
 STATUS = {0: "ok", 1: "invalid argument", 2: "domain violation", 3: "workspace",
-          4: "HIP runtime error", 5: "unsupported tuning", 6: "groups left tied"}
+          4: "HIP runtime error", 5: "unsupported tuning", 6: "groups left tied",
+          7: "too many strings for the no-allocation scratch"}
 
 
 class HuskyError(RuntimeError):
@@ -79,7 +80,8 @@ EXPORTS = ("husky_workspace_bytes", "husky_encode", "husky_sort_pairs", "husky_f
            "husky_learned_workspace_bytes", "husky_learned_fit", "husky_sort_learned",
            "husky_learned_buckets",
            "husky_mlp_grad_workspace_bytes", "husky_mlp_grad", "husky_learned_lut_workspace_bytes",
-           "husky_learned_eval_lut", "husky_status_string")
+           "husky_learned_eval_lut", "husky_sort_noalloc", "husky_noalloc_status",
+           "husky_status_string")
 
 # kernel classes of husky_profile_end (include/husky.h)
 PROFILE_CLASSES = ("encode", "radix_vary", "radix_count_scan", "radix_scatter", "radix_copy_back",
@@ -168,6 +170,10 @@ def load(path: str = LIB_PATH):
     lib.husky_learned_lut_workspace_bytes.argtypes = []
     lib.husky_learned_eval_lut.restype = i32
     lib.husky_learned_eval_lut.argtypes = [vp, i32, vp, vp, vp, sz, vp]
+    lib.husky_sort_noalloc.restype = i32
+    lib.husky_sort_noalloc.argtypes = [i32, vp, vp, u64, vp, tp, vp]
+    lib.husky_noalloc_status.restype = i32
+    lib.husky_noalloc_status.argtypes = [vp, vp]
     lib.husky_status_string.restype = ctypes.c_char_p
     lib.husky_status_string.argtypes = [i32]
     _lib = lib
@@ -309,6 +315,35 @@ def sort(elems, offsets, coder="ascii7", tuning: Optional[Tuning] = None, ws=Non
     if check_status:
         _raise_on_status(ws, "husky_sort")
     return perm[:n]
+
+
+NOALLOC_MAX_STRINGS = 1 << 20
+
+
+def sort_noalloc(elems, offsets, perm, coder="ascii7", tuning: Optional[Tuning] = None, stream=None,
+                 check_status=True):
+    """husky_sort_noalloc: the library allocates nothing and takes no workspace (its
+    scratch is a fixed per-device array); perm (int32 storage of uint32[n]) is the
+    caller's.  Calls that overlap on one device race."""
+    lib = load()
+    n = _n_of(offsets)
+    _check(lib.husky_sort_noalloc(_coder(coder), _ptr(elems), _ptr(offsets), n, _ptr(perm),
+                                  ctypes.byref(tuning) if tuning else None, _stream(stream)),
+           "husky_sort_noalloc")
+    if check_status:
+        st = noalloc_status(stream)
+        if st["domain_violations"]:
+            raise DomainError(2, f"husky_sort_noalloc ({st['domain_violations']} strings)")
+        if st["unresolved"]:
+            raise UnresolvedError(6, f"husky_sort_noalloc ({st['unresolved']} groups)")
+    return perm[:n]
+
+
+def noalloc_status(stream=None) -> dict:
+    """Status block of the no-allocation scratch on the current device (synchronizes)."""
+    v = np.zeros(len(STATUS_FIELDS), dtype=np.uint32)
+    _check(load().husky_noalloc_status(v.ctypes.data, _stream(stream)), "husky_noalloc_status")
+    return {f: int(v[i]) for i, f in enumerate(STATUS_FIELDS)}
 
 
 def sort_batched(elems, offsets, seg_offsets, coder="ascii7", tuning: Optional[Tuning] = None,

@@ -542,6 +542,56 @@ husky_status husky_sort(husky_coder coder, const void* elems, const uint64_t* of
     return sort_common(coder, elems, offsets, n, nullptr, 1, perm, ws, ws_bytes, tuning, stream);
 }
 
+// ------------------------------------------------- sort without allocation
+// Scratch of husky_sort_noalloc: one copy per device, held until the process
+// ends.  Host code never passes `scratch` itself to a kernel or copy (on the
+// host it names a stand-in, not device memory): it uses the address
+// hipGetSymbolAddress gives for the current device, looked up once per
+// device and kept in g_scratch.
+static __device__ __align__(256) uint8_t scratch[HUSKY_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mutex;
+void* g_scratch[MAX_DEVICES];
+}  // namespace
+
+// Device address of this device's scratch array (null on failure).
+static void* device_scratch() {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= MAX_DEVICES) return nullptr;
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (!g_scratch[dev]) {
+        void* ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess) return nullptr;
+        g_scratch[dev] = ptr;
+    }
+    return g_scratch[dev];
+}
+
+husky_status husky_sort_noalloc(husky_coder coder, const void* elems, const uint64_t* offsets,
+                                uint64_t n, uint32_t* perm, const husky_tuning* tuning,
+                                void* stream) {
+    husky_status st = check_common(coder, elems, offsets, n);
+    if (st != HUSKY_OK) return st;
+    if (n > HUSKY_NOALLOC_MAX_STRINGS) return HUSKY_ERR_TOO_LARGE;
+    const size_t need = make_layout(n, 1).total;
+    if (need > (size_t)HUSKY_NOALLOC_SCRATCH_BYTES) return HUSKY_ERR_TOO_LARGE;
+    void* ws = device_scratch();
+    if (!ws) return HUSKY_ERR_HIP;
+    return sort_common(coder, elems, offsets, n, nullptr, 1, perm, ws, need, tuning, stream);
+}
+
+husky_status husky_noalloc_status(husky_device_status* out, void* stream) {
+    if (!out) return HUSKY_ERR_ARG;
+    void* ws = device_scratch();
+    if (!ws) return HUSKY_ERR_HIP;
+    hipStream_t s = (hipStream_t)stream;
+    HUSKY_TRY(hipMemcpyAsync(out, ws, sizeof(husky_device_status), hipMemcpyDeviceToHost, s));
+    HUSKY_TRY(hipStreamSynchronize(s));
+    return HUSKY_OK;
+}
+
 husky_status husky_sort_batched(husky_coder coder, const void* elems, const uint64_t* offsets,
                                 uint64_t n, const uint64_t* seg_offsets, uint64_t n_segs,
                                 uint32_t* perm, void* ws, size_t ws_bytes,
@@ -769,6 +819,7 @@ const char* husky_status_string(husky_status s) {
         case HUSKY_ERR_HIP: return "HIP runtime error";
         case HUSKY_ERR_UNSUPPORTED: return "tuning value not supported";
         case HUSKY_ERR_UNRESOLVED: return "groups still tied after the fixed refinement rounds";
+        case HUSKY_ERR_TOO_LARGE: return "more strings than the no-allocation scratch holds";
     }
     return "unknown status";
 }
