@@ -56,6 +56,10 @@ def _load():
         lib.oracle_sort.argtypes = [i32, i32, vp, vp, u64, vp]
         lib.oracle_sort_batched.restype = u64
         lib.oracle_sort_batched.argtypes = [i32, i32, vp, vp, vp, u64, vp]
+        lib.oracle_fixup_global.restype = None
+        lib.oracle_fixup_global.argtypes = [i32, vp, vp, u64, vp]
+        lib.oracle_sort_lossy.restype = None
+        lib.oracle_sort_lossy.argtypes = [i32, vp, vp, u64, vp, vp]
         lib.oracle_check_perm.restype = u64
         lib.oracle_check_perm.argtypes = [i32, vp, vp, u64, vp, vp]
         lib.oracle_check_perm_batched.restype = u64
@@ -119,6 +123,28 @@ def sort(batch, coder=None):
     bad = lib.oracle_sort(_coder_id(batch, coder), batch.elem_bytes, _ptr(elems), _ptr(offsets),
                           batch.n, _ptr(perm))
     return perm[: batch.n], int(bad)
+
+
+def fixup_global(batch, idx: np.ndarray) -> np.ndarray:
+    """Step 3 as a full stable pass: any order idx -> the stable sorting permutation."""
+    lib = _load()
+    elems, offsets = _prep(batch)
+    i = np.array(idx, dtype=np.uint32, copy=True)
+    if i.size:
+        lib.oracle_fixup_global(batch.elem_bytes, _ptr(elems), _ptr(offsets), i.size, _ptr(i))
+    return i
+
+
+def sort_lossy(batch, codes: np.ndarray) -> np.ndarray:
+    """Algorithm 1 with the given codes (any coder, even one that inverts strings):
+    stable sort by code, then the full stable pass."""
+    lib = _load()
+    elems, offsets = _prep(batch)
+    c = np.ascontiguousarray(codes, dtype=np.uint64)
+    perm = np.zeros(max(batch.n, 1), dtype=np.uint32)
+    if batch.n:
+        lib.oracle_sort_lossy(batch.elem_bytes, _ptr(elems), _ptr(offsets), batch.n, _ptr(c), _ptr(perm))
+    return perm[: batch.n]
 
 
 def sort_batched(batch, coder=None):

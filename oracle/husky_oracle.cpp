@@ -163,6 +163,36 @@ uint64_t oracle_sort(int coder, int elem_bytes, const void* elems, const uint64_
     return bad;
 }
 
+// Step 3 as the paper writes it (Sec. 3.1 Step 3, the final Timsort over the
+// whole array, needed when the coder may invert two objects -- the lossy
+// and deliberately mis-coded coders of Sec. 3.2 and the Appendix): idx holds
+// any order of the strings (typically the result of sorting by such codes)
+// and becomes the stable sorting permutation.  Written as its definition: a
+// sort by (string, original index), which is a total order, so the result is
+// unique whatever order idx arrived in.
+void oracle_fixup_global(int elem_bytes, const void* elems, const uint64_t* offsets, uint64_t n,
+                         uint32_t* idx) {
+    auto by_string_then_index = [&](uint32_t a, uint32_t b) {
+        bool lt = elem_bytes == 1 ? string_less((const uint8_t*)elems, offsets, a, b)
+                                  : string_less((const uint16_t*)elems, offsets, a, b);
+        bool gt = elem_bytes == 1 ? string_less((const uint8_t*)elems, offsets, b, a)
+                                  : string_less((const uint16_t*)elems, offsets, b, a);
+        return lt || (!gt && a < b);
+    };
+    std::sort(idx, idx + n, by_string_then_index);
+}
+
+// Algorithm 1 with caller-given codes of any quality (a lossy or non-monotone
+// coder): Step 2 is the stable sort of (codes[i], i) by code, Step 3 the
+// global pass above.
+void oracle_sort_lossy(int elem_bytes, const void* elems, const uint64_t* offsets, uint64_t n,
+                       const uint64_t* codes, uint32_t* perm) {
+    std::vector<uint64_t> c(codes, codes + n);
+    for (uint64_t i = 0; i < n; ++i) perm[i] = (uint32_t)i;
+    sort_pairs(c.data(), perm, n);
+    oracle_fixup_global(elem_bytes, elems, offsets, n, perm);
+}
+
 // Independent sort instances (batched form): instance k holds strings
 // seg_offsets[k] .. seg_offsets[k+1]-1 and is sorted on its own; perm holds
 // global string indices, each instance's slice a permutation of its range.
