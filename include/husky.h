@@ -266,7 +266,8 @@ husky_status husky_check_perm(husky_coder coder, const void* elems, const uint64
  * pass of the device-wide fix-up (class 3 counts only the sort of the
  * codes), 12 learned bucket scatter pass, 13 learned bucket bounds (the
  * learned form's bucket ids are computed by the encode kernel, class 0),
- * 14 LDS-resident fix-up of runs longer than t_medium and at most 8,192.
+ * 14 LDS-resident fix-up of runs longer than t_medium and at most 8,192,
+ * 15 the full stable pass of the lossy-coder sort (husky_fixup_global).
  * Not for use during graph capture.
  * Returns HUSKY_OK or HUSKY_ERR_HIP. */
 void husky_profile_begin(void);
@@ -274,6 +275,104 @@ int husky_profile_end(double* ms, uint32_t* launches, int n_classes);
 /* Bracket only the classes whose bit is set in class_mask (default: all), so
  * that timing one kernel class barely perturbs the others. */
 void husky_profile_select(uint32_t class_mask);
+
+/* ---------------------------------------------------------------------
+ * Lossy coders.  Sec. 3.2 allows a coder that inverts two objects with some
+ * probability p (x > y but code(x) <= code(y)), and the Appendix sorts with
+ * deliberately mis-coded objects; Step 3 is then the paper's full stable pass
+ * over the whole array (Sec. 3.1 Step 3), which run-local fix-up cannot
+ * replace.  Here that pass is a natural merge sort: the array's maximal
+ * ascending runs are merged in pairs, level by level, every element placed
+ * by binary search in its partner run, comparing (string, original index) --
+ * a total order, so the result is the unique stable sorting permutation for
+ * ANY input order.  Its cost grows with the log of the number of runs, so a
+ * nearly sorted array is cheap.  It never synchronizes with the host. */
+
+/* Workspace bytes of husky_fixup_global for n strings. */
+size_t husky_global_workspace_bytes(uint64_t n);
+/* The full stable pass: idx (device uint32[n]) holds the strings in any order
+ * (e.g. sorted by lossy codes) and becomes the stable sorting permutation.
+ * Errors: HUSKY_ERR_ARG, HUSKY_ERR_WORKSPACE, HUSKY_ERR_HIP. */
+husky_status husky_fixup_global(husky_coder coder, const void* elems, const uint64_t* offsets,
+                                uint64_t n, uint32_t* idx, void* ws, size_t ws_bytes, void* stream);
+
+/* Workspace bytes of husky_sort_lossy for n strings. */
+size_t husky_lossy_workspace_bytes(uint64_t n);
+/* Algorithm 1 with the caller's codes (device uint64[n], from any coder, even
+ * one that inverts strings): Step 2 sorts (codes[i], i) stably, Step 3
+ * re-sorts every run of equal codes by the full comparator from the first
+ * element (the codes promise no shared prefix) and then runs the full stable
+ * pass.  perm receives the stable sorting permutation whatever the codes.
+ * `coder` only selects the element type and comparator (ASCII7 and BYTES8:
+ * bytes, UTF16: units).  Errors: as husky_sort. */
+husky_status husky_sort_lossy(husky_coder coder, const void* elems, const uint64_t* offsets,
+                              uint64_t n, const uint64_t* codes, uint32_t* perm, void* ws,
+                              size_t ws_bytes, const husky_tuning* tuning, void* stream);
+
+/* ---------------------------------------------------------------------
+ * Other object types.  The paper names more types that are costly to
+ * compare and that a husky code speeds up: date-times (a perfect coder for
+ * nanosecond resolution over 128 years, Sec. 3.2), Integer, Long, Double,
+ * BigInteger and BigDecimal, and tuples (Sec. 6).  Records (device bytes):
+ *   INT32, INT64, FLOAT64 -- little-endian values, 4 / 8 / 8 bytes each;
+ *   DATETIME -- 16 bytes: int32 year, uint8 month, day, hour, minute,
+ *     second, 3 pad bytes, uint32 nano (little-endian); compared field by
+ *     field; valid fields: month 1..12, day 1..31, hour <= 23, minute <= 59,
+ *     second <= 59, nano < 10^9 (others are domain violations);
+ *   BIGINT -- two's-complement big-endian bytes of any length up to 32,767
+ *     (an empty record is 0), compared by value;
+ *   DECIMAL -- int32 scale (little-endian) then the unscaled value as
+ *     two's-complement big-endian bytes (at most 16; none = 0): value =
+ *     unscaled x 10^-scale, |scale| <= 16,000; compared by value, so 1.5 and
+ *     1.50 are equal (Java's BigDecimal.compareTo);
+ *   TUPLE -- int64 (little-endian) then a byte string; compared by the
+ *     string (unsigned bytes, a proper prefix first), then the integer.
+ * Variable-length types take offsets (uint64[n + 1], bytes) like strings.
+ * FLOAT64 follows Java's Double.compare: -inf < ... < -0.0 < 0.0 < ... <
+ * inf < NaN, every NaN equal.  Ties keep index order (stable).
+ * Codes (husky_encode_typed): INT32 (x + 2^31) << 32; INT64 x + 2^63;
+ * FLOAT64 the IEEE bits with the sign flipped for positives and every bit
+ * flipped for negatives (NaN made canonical) -- perfect codes, so the sort is
+ * Steps 1 and 2 only; DATETIME 1 + (year - base_year) << 56 | month << 52 |
+ * day << 47 | hour << 42 | minute << 36 | second << 30 | nano for years in
+ * [base_year, base_year + 128) (perfect there), 0 below, 2^63 + 1 above;
+ * BIGINT, DECIMAL, TUPLE the first eight bytes (big-endian) of an
+ * order-preserving byte key (bigint: a 2-byte sign-and-length head and the
+ * shortest two's-complement bytes; decimal: sign class, decimal exponent,
+ * significant digits two per byte; tuple: the string with each 00 written
+ * 00 FF, 00 00, the integer + 2^63 big-endian).  Step 3 compares those keys
+ * (13-byte field keys for date-times) with the full-byte fix-up. */
+typedef enum {
+    HUSKY_TYPE_INT32 = 0,
+    HUSKY_TYPE_INT64 = 1,
+    HUSKY_TYPE_FLOAT64 = 2,
+    HUSKY_TYPE_DATETIME = 3,
+    HUSKY_TYPE_BIGINT = 4,
+    HUSKY_TYPE_DECIMAL = 5,
+    HUSKY_TYPE_TUPLE = 6
+} husky_type;
+
+/* Workspace bytes of husky_sort_typed for n records of record_bytes bytes in
+ * all (the size of the records buffer). */
+size_t husky_typed_workspace_bytes(husky_type type, uint64_t n, uint64_t record_bytes);
+
+/* Step 1 for typed records: codes[i] (device uint64[n]) = the husky code of
+ * record i.  offsets_or_null: uint64[n + 1] byte offsets for BIGINT, DECIMAL
+ * and TUPLE, NULL for the fixed-width types.  status (device, may be NULL) is
+ * INCREMENTED by the number of out-of-domain records.  Errors: HUSKY_ERR_ARG. */
+husky_status husky_encode_typed(husky_type type, const void* records, const uint64_t* offsets_or_null,
+                                uint64_t n, int32_t base_year, uint64_t* codes, uint32_t* status,
+                                void* stream);
+
+/* Huskysort of typed records: perm receives the stable sorting permutation
+ * under the type's comparator.  record_bytes is the size of the records
+ * buffer (it bounds the keys' workspace).  base_year: the date-time window's
+ * first year (ignored by the other types).  The device status block reports
+ * out-of-domain records (perm is then unspecified).  Errors: HUSKY_ERR_ARG,
+ * HUSKY_ERR_WORKSPACE, HUSKY_ERR_UNSUPPORTED, HUSKY_ERR_HIP. */
+husky_status husky_sort_typed(husky_type type, const void* records, const uint64_t* offsets_or_null,
+                              uint64_t n, uint64_t record_bytes, int32_t base_year, uint32_t* perm,
+                              void* ws, size_t ws_bytes, const husky_tuning* tuning, void* stream);
 
 /* ---------------------------------------------------------------------
  * Learned-CDF form (an extension of the method, not part of the paper).

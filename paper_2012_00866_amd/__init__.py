@@ -81,13 +81,15 @@ EXPORTS = ("husky_workspace_bytes", "husky_encode", "husky_sort_pairs", "husky_f
            "husky_learned_buckets",
            "husky_mlp_grad_workspace_bytes", "husky_mlp_grad", "husky_learned_lut_workspace_bytes",
            "husky_learned_eval_lut", "husky_sort_noalloc", "husky_noalloc_status",
-           "husky_status_string")
+           "husky_typed_workspace_bytes", "husky_encode_typed", "husky_sort_typed",
+           "husky_global_workspace_bytes", "husky_fixup_global", "husky_lossy_workspace_bytes",
+           "husky_sort_lossy", "husky_status_string")
 
 # kernel classes of husky_profile_end (include/husky.h)
 PROFILE_CLASSES = ("encode", "radix_vary", "radix_count_scan", "radix_scatter", "radix_copy_back",
                    "tile_sort", "runs", "fixup_small", "fixup_medium", "large_keys", "segment_setup",
                    "radix_scatter_fixup", "learned_bucket_scatter", "learned_bucket_bounds",
-                   "fixup_lds")
+                   "fixup_lds", "global_merge")
 
 # learned form (include/husky.h)
 LEARNED_BUCKETS = 65536
@@ -174,6 +176,20 @@ def load(path: str = LIB_PATH):
     lib.husky_sort_noalloc.argtypes = [i32, vp, vp, u64, vp, tp, vp]
     lib.husky_noalloc_status.restype = i32
     lib.husky_noalloc_status.argtypes = [vp, vp]
+    lib.husky_typed_workspace_bytes.restype = sz
+    lib.husky_typed_workspace_bytes.argtypes = [i32, u64, u64]
+    lib.husky_encode_typed.restype = i32
+    lib.husky_encode_typed.argtypes = [i32, vp, vp, u64, ctypes.c_int32, vp, vp, vp]
+    lib.husky_sort_typed.restype = i32
+    lib.husky_sort_typed.argtypes = [i32, vp, vp, u64, u64, ctypes.c_int32, vp, vp, sz, tp, vp]
+    lib.husky_global_workspace_bytes.restype = sz
+    lib.husky_global_workspace_bytes.argtypes = [u64]
+    lib.husky_fixup_global.restype = i32
+    lib.husky_fixup_global.argtypes = [i32, vp, vp, u64, vp, vp, sz, vp]
+    lib.husky_lossy_workspace_bytes.restype = sz
+    lib.husky_lossy_workspace_bytes.argtypes = [u64]
+    lib.husky_sort_lossy.restype = i32
+    lib.husky_sort_lossy.argtypes = [i32, vp, vp, u64, vp, vp, vp, sz, tp, vp]
     lib.husky_status_string.restype = ctypes.c_char_p
     lib.husky_status_string.argtypes = [i32]
     _lib = lib
@@ -363,6 +379,88 @@ def sort_batched(elems, offsets, seg_offsets, coder="ascii7", tuning: Optional[T
            "husky_sort_batched")
     if check_status:
         _raise_on_status(ws, "husky_sort_batched")
+    return perm[:n]
+
+
+# ----------------------------------------------------------------- lossy coders
+def fixup_global(elems, offsets, idx, coder="ascii7", ws=None, stream=None):
+    """The full stable pass: idx (any order of the strings) becomes the stable
+    sorting permutation, in place."""
+    torch = _torch()
+    lib = load()
+    n = _n_of(offsets)
+    if ws is None:
+        ws = torch.empty(int(lib.husky_global_workspace_bytes(n)), dtype=torch.uint8, device=offsets.device)
+    _check(lib.husky_fixup_global(_coder(coder), _ptr(elems), _ptr(offsets), n, _ptr(idx), _ptr(ws),
+                                  ws.numel(), _stream(stream)), "husky_fixup_global")
+    return idx
+
+
+def sort_lossy(elems, offsets, codes, coder="ascii7", tuning: Optional[Tuning] = None, ws=None, perm=None,
+               stream=None):
+    """Algorithm 1 with the caller's codes of any quality: the stable sorting permutation."""
+    torch = _torch()
+    lib = load()
+    n = _n_of(offsets)
+    if ws is None:
+        ws = torch.empty(int(lib.husky_lossy_workspace_bytes(n)), dtype=torch.uint8, device=offsets.device)
+    if perm is None:
+        perm = torch.empty(max(n, 1), dtype=torch.int32, device=offsets.device)
+    _check(lib.husky_sort_lossy(_coder(coder), _ptr(elems), _ptr(offsets), n, _ptr(codes), _ptr(perm),
+                                _ptr(ws), ws.numel(), ctypes.byref(tuning) if tuning else None,
+                                _stream(stream)), "husky_sort_lossy")
+    return perm[:n]
+
+
+# ----------------------------------------------------------------- typed records
+TYPES = {"int32": 0, "int64": 1, "float64": 2, "datetime": 3, "bigint": 4, "decimal": 5, "tuple": 6}
+TYPE_WIDTH = {"int32": 4, "int64": 8, "float64": 8, "datetime": 16}
+
+
+def _type(t) -> int:
+    return TYPES[t] if isinstance(t, str) else int(t)
+
+
+def typed_to_device(batch, device="cuda"):
+    """(records uint8 tensor, offsets int64 tensor or None) for a workloads.typed batch."""
+    torch = _torch()
+    data = batch.data if batch.data.size else np.zeros(8, dtype=np.uint8)
+    recs = torch.from_numpy(np.ascontiguousarray(data)).to(device)
+    off = None
+    if batch.offsets is not None:
+        off = torch.from_numpy(np.ascontiguousarray(batch.offsets).view(np.int64)).to(device)
+    return recs, off
+
+
+def typed_workspace_bytes(type_, n: int, record_bytes: int) -> int:
+    return int(load().husky_typed_workspace_bytes(_type(type_), int(n), int(record_bytes)))
+
+
+def encode_typed(records, offsets, type_, n: int, base_year=1970, status=None, stream=None):
+    """Step 1 for typed records: the husky codes (int64 storage of uint64[n])."""
+    torch = _torch()
+    codes = torch.empty(max(n, 1), dtype=torch.int64, device=records.device)
+    _check(load().husky_encode_typed(_type(type_), _ptr(records), _ptr(offsets), int(n), int(base_year),
+                                     _ptr(codes), _ptr(status), _stream(stream)), "husky_encode_typed")
+    return codes[:n]
+
+
+def sort_typed(records, offsets, type_, n: int, base_year=1970, tuning: Optional[Tuning] = None,
+               ws=None, perm=None, stream=None, check_status=True):
+    """Huskysort of typed records (numbers, date-times, big numbers, tuples): the
+    stable sorting permutation under the type's comparator."""
+    torch = _torch()
+    lib = load()
+    rb = int(records.numel())
+    if ws is None:
+        ws = torch.empty(typed_workspace_bytes(type_, n, rb), dtype=torch.uint8, device=records.device)
+    if perm is None:
+        perm = torch.empty(max(n, 1), dtype=torch.int32, device=records.device)
+    _check(lib.husky_sort_typed(_type(type_), _ptr(records), _ptr(offsets), int(n), rb, int(base_year),
+                                _ptr(perm), _ptr(ws), ws.numel(), ctypes.byref(tuning) if tuning else None,
+                                _stream(stream)), "husky_sort_typed")
+    if check_status:
+        _raise_on_status(ws, "husky_sort_typed")
     return perm[:n]
 
 

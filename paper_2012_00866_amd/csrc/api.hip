@@ -388,6 +388,20 @@ husky_status run_fixup(Ctx& c, const Tune& tn, int coder, uint32_t origin, const
     return HUSKY_OK;
 }
 
+__global__ void k_copy_codes_iota(const uint64_t* __restrict__ src, uint64_t* __restrict__ dst,
+                                  uint32_t* __restrict__ idx, uint32_t n) {
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        dst[i] = src[i];
+        idx[i] = i;
+    }
+}
+
+hipError_t copy_codes_iota(const uint64_t* src, uint64_t* dst, uint32_t* idx, uint32_t n, hipStream_t s) {
+    const uint32_t blocks = (uint32_t)std::min<uint64_t>((n + 255) / 256, 65536);
+    hipLaunchKernelGGL(k_copy_codes_iota, dim3(blocks), dim3(256), 0, s, src, dst, idx, n);
+    return hipGetLastError();
+}
+
 husky_status check_common(int coder, const void* elems, const uint64_t* offsets, uint64_t n) {
     if (coder != HUSKY_CODER_ASCII7 && coder != HUSKY_CODER_UTF16 && coder != HUSKY_CODER_BYTES8)
         return HUSKY_ERR_ARG;
@@ -599,6 +613,170 @@ husky_status husky_sort_batched(husky_coder coder, const void* elems, const uint
     if (!seg_offsets || n_segs == 0 || n_segs >= (1ull << 32)) return HUSKY_ERR_ARG;
     return sort_common(coder, elems, offsets, n, seg_offsets, n_segs, perm, ws, ws_bytes, tuning,
                        stream);
+}
+
+// ---------------------------------------------------------------- lossy coders
+size_t husky_global_workspace_bytes(uint64_t n) { return merge_workspace_bytes(n); }
+
+husky_status husky_fixup_global(husky_coder coder, const void* elems, const uint64_t* offsets,
+                                uint64_t n, uint32_t* idx, void* ws, size_t ws_bytes, void* stream) {
+    husky_status st = check_common(coder, elems, offsets, n);
+    if (st != HUSKY_OK) return st;
+    if (n > 0 && !idx) return HUSKY_ERR_ARG;
+    if (!ws || ((uintptr_t)ws) % ALIGN || ws_bytes < merge_workspace_bytes(n)) return HUSKY_ERR_WORKSPACE;
+    return hip_status(merge_fixup(elem_kind(coder), elems, offsets, (uint32_t)n, idx, ws, (hipStream_t)stream));
+}
+
+size_t husky_lossy_workspace_bytes(uint64_t n) {
+    return align_up(make_layout(n, 1).total) + merge_workspace_bytes(n);
+}
+
+husky_status husky_sort_lossy(husky_coder coder, const void* elems, const uint64_t* offsets, uint64_t n,
+                              const uint64_t* codes, uint32_t* perm, void* ws, size_t ws_bytes,
+                              const husky_tuning* tuning, void* stream) {
+    husky_status st = check_common(coder, elems, offsets, n);
+    if (st != HUSKY_OK) return st;
+    if (n > 0 && (!codes || !perm)) return HUSKY_ERR_ARG;
+    Tune tn;
+    if ((st = resolve_tuning(tuning, &tn)) != HUSKY_OK) return st;
+    const size_t sort_bytes = align_up(make_layout(n, 1).total);
+    if (!ws || ((uintptr_t)ws) % ALIGN || ws_bytes < sort_bytes + merge_workspace_bytes(n))
+        return HUSKY_ERR_WORKSPACE;
+    hipStream_t s = (hipStream_t)stream;
+    Ctx c = make_ctx(ws, n, 1);
+    HUSKY_TRY(zero_u32((uint32_t*)c.status, STATUS_WORDS, s));
+    if (n == 0) return HUSKY_OK;
+    const uint32_t nn = (uint32_t)n;
+    uint64_t* k = c.at<uint64_t>(c.L.codes_a);
+    uint64_t* kb = c.at<uint64_t>(c.L.codes_b);
+    // Step 2 on the caller's codes (copied, with the index iota)
+    HUSKY_TRY(copy_codes_iota(codes, k, perm, nn, s));
+    HUSKY_TRY(radix_segments_single(nn, c.rad, tn.rc, s));
+    const uint32_t tb = tiles_bound(n, 1, tn.rc);
+    HUSKY_TRY(radix_reduce_tiles(k, tb, c.rad, tn.rc, s));
+    HUSKY_TRY(radix_exec_masks(0, 64, 1, tb, c.rad, tn.rc, s));
+    HUSKY_TRY(radix_sort_segments(k, perm, kb, c.at<uint32_t>(c.L.idx_b), 0, 64, 1, tb, ~0u, c.rad, tn.rc,
+                                  P_SCATTER, s));
+    // runs of equal codes by the full comparator, from the first element (the
+    // codes promise nothing), then the full stable pass for what lies across
+    // codes
+    const FixupArgs fa{elem_kind(coder), elems, offsets, nn, perm, nullptr, 0u};
+    HUSKY_TRY(fixup_first_keys(fa, c.at<uint64_t>(c.L.key0), s));
+    st = run_fixup(c, tn, coder, 0u, elems, offsets, n, 1, k, k, kb, perm, s);
+    if (st != HUSKY_OK) return st;
+    return hip_status(merge_fixup(elem_kind(coder), elems, offsets, nn, perm, (uint8_t*)ws + sort_bytes, s));
+}
+
+// ---------------------------------------------------------------- typed records
+namespace {
+bool typed_fixed(int t) { return t >= HUSKY_TYPE_INT32 && t <= HUSKY_TYPE_DATETIME; }
+uint32_t typed_width(int t) { return t == HUSKY_TYPE_INT32 ? 4u : (t == HUSKY_TYPE_DATETIME ? 16u : 8u); }
+
+// Key bytes that n records of record_bytes bytes can need at most.
+uint64_t typed_key_bound(int t, uint64_t n, uint64_t record_bytes) {
+    switch (t) {
+        case HUSKY_TYPE_DATETIME: return 13 * n;
+        case HUSKY_TYPE_BIGINT: return record_bytes + 3 * n;      // head + shortest form (empty: 00)
+        case HUSKY_TYPE_DECIMAL: return 24 * n;                    // 1 + 2 + 20 digit bytes + FF
+        case HUSKY_TYPE_TUPLE: return 2 * record_bytes + 10 * n;  // escaped string + 00 00 + 8
+        default: return 0;
+    }
+}
+
+struct TypedLayout {
+    size_t sort, key_off, lens, tiles, bad, keys, total;
+};
+
+TypedLayout typed_layout(int t, uint64_t n, uint64_t record_bytes) {
+    TypedLayout T{};
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        size_t at = o;
+        o = align_up(o + bytes);
+        return at;
+    };
+    T.sort = take(make_layout(n, 1).total);
+    if (t == HUSKY_TYPE_DATETIME || !typed_fixed(t)) {
+        T.key_off = take((n + 1) * 8);
+        T.lens = take(n * 8);
+        T.tiles = take((size_t)typed_scan_tiles((uint32_t)n) * 8 + 8);
+        T.bad = take(4);
+        T.keys = take(typed_key_bound(t, n, record_bytes) + 16);
+    }
+    T.total = o;
+    return T;
+}
+
+__global__ void k_add_u32(uint32_t* dst, const uint32_t* src) { *dst += *src; }
+}  // namespace
+
+size_t husky_typed_workspace_bytes(husky_type type, uint64_t n, uint64_t record_bytes) {
+    if (type < HUSKY_TYPE_INT32 || type > HUSKY_TYPE_TUPLE) return 0;
+    return typed_layout(type, n, record_bytes).total;
+}
+
+husky_status husky_encode_typed(husky_type type, const void* records, const uint64_t* offsets_or_null,
+                                uint64_t n, int32_t base_year, uint64_t* codes, uint32_t* status,
+                                void* stream) {
+    if (type < HUSKY_TYPE_INT32 || type > HUSKY_TYPE_TUPLE || n >= (1ull << 32)) return HUSKY_ERR_ARG;
+    if (n > 0 && (!records || !codes)) return HUSKY_ERR_ARG;
+    if (!typed_fixed(type) && n > 0 && !offsets_or_null) return HUSKY_ERR_ARG;
+    hipStream_t s = (hipStream_t)stream;
+    if (typed_fixed(type))
+        return hip_status(typed_fixed_codes(type, records, (uint32_t)n, base_year, codes, nullptr, status, s));
+    return hip_status(typed_key_codes(type, records, offsets_or_null, (uint32_t)n, codes, status, s));
+}
+
+husky_status husky_sort_typed(husky_type type, const void* records, const uint64_t* offsets_or_null,
+                              uint64_t n, uint64_t record_bytes, int32_t base_year, uint32_t* perm,
+                              void* ws, size_t ws_bytes, const husky_tuning* tuning, void* stream) {
+    if (type < HUSKY_TYPE_INT32 || type > HUSKY_TYPE_TUPLE || n >= (1ull << 32)) return HUSKY_ERR_ARG;
+    if (n > 0 && (!records || !perm)) return HUSKY_ERR_ARG;
+    if (!typed_fixed(type) && n > 0 && !offsets_or_null) return HUSKY_ERR_ARG;
+    Tune tn;
+    husky_status st = resolve_tuning(tuning, &tn);
+    if (st != HUSKY_OK) return st;
+    const TypedLayout T = typed_layout(type, n, record_bytes);
+    if (!ws || ((uintptr_t)ws) % ALIGN || ws_bytes < T.total) return HUSKY_ERR_WORKSPACE;
+    hipStream_t s = (hipStream_t)stream;
+    uint8_t* base = (uint8_t*)ws;
+    const uint32_t nn = (uint32_t)n;
+    if (!typed_fixed(type)) {
+        // Step 0: order keys of the records; then Huskysort of the keys with
+        // the full-byte coder (its code is the record's husky code)
+        uint32_t* bad = (uint32_t*)(base + T.bad);
+        uint64_t* key_off = (uint64_t*)(base + T.key_off);
+        uint8_t* keys = base + T.keys;
+        HUSKY_TRY(zero_u32(bad, 1, s));
+        HUSKY_TRY(typed_keys(type, records, offsets_or_null, nn, (uint64_t*)(base + T.lens),
+                             (uint64_t*)(base + T.tiles), key_off, keys, bad, s));
+        st = sort_common(HUSKY_CODER_BYTES8, keys, key_off, n, nullptr, 1, perm, base + T.sort,
+                         make_layout(n, 1).total, tuning, stream);
+        if (st != HUSKY_OK) return st;
+        hipLaunchKernelGGL(k_add_u32, dim3(1), dim3(1), 0, s, (uint32_t*)(base + T.sort), (const uint32_t*)bad);
+        return hip_status(hipGetLastError());
+    }
+    Ctx c = make_ctx(base + T.sort, n, 1);
+    HUSKY_TRY(zero_u32((uint32_t*)c.status, STATUS_WORDS, s));
+    if (n == 0) return HUSKY_OK;
+    uint64_t* codes = c.at<uint64_t>(c.L.codes_a);
+    uint64_t* codes_b = c.at<uint64_t>(c.L.codes_b);
+    HUSKY_TRY(typed_fixed_codes(type, records, nn, base_year, codes, perm, &c.status->domain_violations, s));
+    HUSKY_TRY(radix_segments_single(nn, c.rad, tn.rc, s));
+    const uint32_t tb = tiles_bound(n, 1, tn.rc);
+    HUSKY_TRY(radix_reduce_tiles(codes, tb, c.rad, tn.rc, s));
+    HUSKY_TRY(radix_exec_masks(0, 64, 1, tb, c.rad, tn.rc, s));
+    HUSKY_TRY(radix_sort_segments(codes, perm, codes_b, c.at<uint32_t>(c.L.idx_b), 0, 64, 1, tb, ~0u, c.rad,
+                                  tn.rc, P_SCATTER, s));
+    if (type != HUSKY_TYPE_DATETIME) return HUSKY_OK;  // perfect codes: nothing left to fix
+    // date-times outside the window share codes: Step 3 on their 13-byte
+    // field keys, compared from the first byte
+    uint64_t* key_off = (uint64_t*)(base + T.key_off);
+    uint8_t* keys = base + T.keys;
+    HUSKY_TRY(typed_keys(type, records, nullptr, nn, nullptr, nullptr, key_off, keys, nullptr, s));
+    const FixupArgs fa{0, keys, key_off, nn, perm, nullptr, 0u};
+    HUSKY_TRY(fixup_first_keys(fa, c.at<uint64_t>(c.L.key0), s));
+    return run_fixup(c, tn, HUSKY_CODER_BYTES8, 0u, keys, key_off, n, 1, codes, codes, codes_b, perm, s);
 }
 
 // ---------------------------------------------------------------- learned form

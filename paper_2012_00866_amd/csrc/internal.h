@@ -13,7 +13,7 @@ namespace husky {
 enum ProfClass {
     P_ENCODE = 0, P_VARY = 1, P_COUNT_SCAN = 2, P_SCATTER = 3, P_COPY_BACK = 4, P_TILE_SORT = 5,
     P_RUNS = 6, P_FIX_SMALL = 7, P_FIX_MEDIUM = 8, P_LARGE_KEYS = 9, P_SETUP = 10,
-    P_SCATTER_FIX = 11, P_BUCKET = 12, P_BUCKET_BOUNDS = 13, P_FIX_LDS = 14, P_NUM = 15
+    P_SCATTER_FIX = 11, P_BUCKET = 12, P_BUCKET_BOUNDS = 13, P_FIX_LDS = 14, P_MERGE = 15, P_NUM = 16
 };
 bool prof_on();
 class ProfScope {
@@ -181,6 +181,28 @@ hipError_t fixup_large_keys(const FixupArgs& a, const RunItem* items, const Radi
                             hipStream_t s);
 // key0[i] = string i's first refinement key (round 0 from a.origin).
 hipError_t fixup_first_keys(const FixupArgs& a, uint64_t* key0, hipStream_t s);
+
+// ---- typed.hip (the other object types: numbers, date-times, big numbers, tuples)
+// codes of fixed-width records (int32, int64, float64, date-time) and the
+// index iota; status (may be null) counts date-times outside the field ranges
+hipError_t typed_fixed_codes(int type, const void* recs, uint32_t n, int32_t base_year, uint64_t* codes,
+                             uint32_t* idx, uint32_t* status, hipStream_t s);
+// codes of variable-length records (big integers, decimals, tuples): the first
+// eight bytes of their order keys
+hipError_t typed_key_codes(int type, const void* recs, const uint64_t* offsets, uint32_t n,
+                           uint64_t* codes, uint32_t* status, hipStream_t s);
+// order keys of every record into keys, key_offsets[0 .. n] (lens: n words,
+// tile_tmp: typed_scan_tiles(n) words of scratch); date-times: 13 bytes each
+hipError_t typed_keys(int type, const void* recs, const uint64_t* offsets, uint32_t n, uint64_t* lens,
+                      uint64_t* tile_tmp, uint64_t* key_offsets, uint8_t* keys, uint32_t* status,
+                      hipStream_t s);
+uint32_t typed_scan_tiles(uint32_t n);
+
+// ---- merge.hip: Step 3 as a full stable pass (natural merge sort by
+// (string, index)); idx in place; ek: element kind
+size_t merge_workspace_bytes(uint64_t n);
+hipError_t merge_fixup(int ek, const void* elems, const uint64_t* offsets, uint32_t n, uint32_t* idx,
+                       void* ws, hipStream_t s);
 
 // ---- learned.hip
 constexpr uint32_t LEARNED_BUCKETS = 65536;

@@ -92,7 +92,7 @@ def _edge_records(t):
         for u, s in ((0, 0), (0, 7), (15, 1), (150, 2), (-15, 1), (-150, 2), (1, 0), (10, 1), (100, 0),
                      (1, -2), (151, 2), (-151, 2), (2, 0), (19, 1), (-1, 0), (-2, 0), (1, 20), (-1, 20),
                      ((1 << 127) - 1, 0), (-(1 << 127), 0), (123456789, -16000), (-123456789, 16000)):
-            L = max(1, (u.bit_length() + 8) // 8)
+            L = max(1, ((u if u >= 0 else ~u).bit_length() + 8) // 8)  # shortest form
             recs.append(struct.pack("<i", s) + u.to_bytes(L, "big", signed=True))
         recs.append(struct.pack("<i", 3))  # empty unscaled = 0
         return recs
