@@ -185,9 +185,10 @@ def main(argv=None):
     ap.add_argument("--no-batched", action="store_true", help="leave out the batched comparison")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a 256 MiB device copy (calibrates HBM byte counters)")
-    ap.add_argument("--mode", choices=["plain", "batched", "learned"], default="plain",
+    ap.add_argument("--mode", choices=["plain", "batched", "learned", "lossy", "typed"], default="plain",
                     help="plain: the metric's workload (with both comparisons); batched or "
-                         "learned: only that comparison, printed as its own line")
+                         "learned: only that comparison, printed as its own line; lossy: the "
+                         "mis-coding study; typed: the other object types")
     args = ap.parse_args(argv)
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the sort is not "
@@ -215,6 +216,12 @@ def main(argv=None):
     if args.mode == "batched":
         out = bench_batched(args)
         print(json.dumps(out), flush=True)
+        return 0
+    if args.mode == "lossy":
+        print(json.dumps(bench_lossy(args)), flush=True)
+        return 0
+    if args.mode == "typed":
+        print(json.dumps(bench_typed(args)), flush=True)
         return 0
     batch = config2(seed=1, n=args.n)
     n = batch.n
@@ -435,6 +442,84 @@ def bench_batched(args):
         "tuning": res["tuning"],
         "tuner_table": [{"params": r["params"], "ms": round(r["ms"], 3)} for r in res["table"]],
     }
+
+
+def bench_lossy(args):
+    """The Appendix's mis-coding study on the GPU: config 2 sorted from husky codes of
+    which a fraction p is replaced by random values (Step 2 on those codes, then the
+    run-local and the full stable Step 3), against the plain sort of the same input."""
+    import numpy as np
+    import torch
+
+    import oracle
+    import paper_2012_00866_amd as husky
+    from workloads import config2
+
+    n = args.n if args.n != (1 << 24) else 1 << 22
+    batch = config2(seed=1, n=n)
+    elems, offsets = husky.to_device(batch)
+    codes, _ = oracle.encode(batch)
+    steps = max(3, min(args.steps, 10))
+    ws = husky.alloc_workspace(n)
+    perm = torch.empty(n, dtype=torch.int32, device="cuda")
+    ms_plain = _time(lambda: husky.sort(elems, offsets, "ascii7", ws=ws, perm=perm, check_status=False),
+                     steps, 1)
+    ref = perm.clone()
+    lws = torch.empty(int(husky.load().husky_lossy_workspace_bytes(n)), dtype=torch.uint8, device="cuda")
+    rows = []
+    for p in (0.0, 0.001, 0.01, 0.05, 0.1, 0.25, 0.5, 1.0):
+        rng = np.random.default_rng(int(p * 1000) + 1)
+        c = codes.copy()
+        hit = rng.random(n) < p
+        c[hit] = rng.integers(0, 2**64 - 1, size=int(hit.sum()), dtype=np.uint64, endpoint=True)
+        dc = torch.from_numpy(c.view(np.int64)).cuda()
+        ms = _time(lambda: husky.sort_lossy(elems, offsets, dc, "ascii7", ws=lws, perm=perm), steps, 1)
+        assert torch.equal(perm, ref), f"lossy sort differs at p={p}"
+        husky.profile_begin(["global_merge"])
+        husky.sort_lossy(elems, offsets, dc, "ascii7", ws=lws, perm=perm)
+        gm = husky.profile_end()["global_merge"][0]
+        rows.append({"p": p, "ms": round(ms, 3), "global_pass_ms": round(gm, 3),
+                     "vs_plain": round(ms / ms_plain, 3)})
+        _progress(f"lossy p={p}: {ms:.3f} ms (global pass {gm:.3f} ms)")
+    return {"metric": "ms per sort, lossy codes (mis-coding rate p) vs the plain sort",
+            "config": {"workload": "collision-heavy ASCII strings (config 2)", "n": n, "seed": 1,
+                       "miscoding": "each code replaced by a uniform random 64-bit value with "
+                                    "probability p (seeded)"},
+            "plain_ms": round(ms_plain, 3), "rows": rows, "identical": True}
+
+
+def bench_typed(args):
+    """The other object types: Mrecords/s of husky_sort_typed per type (500,000 records,
+    the paper's largest size, and 2^24 records), every permutation checked on the device
+    against the oracle's at 500,000."""
+    import numpy as np
+    import torch
+
+    import paper_2012_00866_amd as husky
+    from oracle import typed as ot
+    from workloads.typed import TYPED, typed
+
+    steps = max(3, min(args.steps, 10))
+    rows = {}
+    for t in TYPED:
+        for n in (500_000, 1 << 24):
+            if n > 500_000 and t in ("bigint", "decimal", "tuple"):
+                n = 1 << 22  # the Python generator of these records is slow
+            b = typed(t, n=n, seed=1)
+            r, o = husky.typed_to_device(b)
+            ws = torch.empty(husky.typed_workspace_bytes(t, n, int(r.numel())), dtype=torch.uint8,
+                             device="cuda")
+            perm = torch.empty(n, dtype=torch.int32, device="cuda")
+            ms = _time(lambda: husky.sort_typed(r, o, t, n, ws=ws, perm=perm, check_status=False), steps, 1)
+            ok = None
+            if n == 500_000:
+                ok = bool(np.array_equal(perm.cpu().numpy().view(np.uint32), ot.sort(b)[0]))
+                assert ok, f"typed sort of {t} differs from the oracle"
+            rows[f"{t}_{n}"] = {"ms": round(ms, 3), "mrecords_s": round(n / ms / 1e3, 1),
+                                "record_bytes": int(r.numel()), "oracle_identical": ok}
+            _progress(f"typed {t} n={n}: {ms:.3f} ms")
+            del r, o, ws, perm, b
+    return {"metric": "Mrecords/s sorted (bit-exact), other object types", "rows": rows}
 
 
 def _kernels(prof, steps):
