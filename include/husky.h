@@ -51,9 +51,9 @@
  * Conditions that only the device can see (an ASCII7 byte >= 0x80 among the
  * first nine bytes) are recorded in the device status block; read it after
  * synchronizing the stream.  With such a violation `perm` is unspecified.
- * husky_fixup, husky_sort and husky_sort_batched read small counters back
- * to the host (synchronizing `stream`) when a run of equal codes is longer
- * than the workgroup tier's limit, once per refinement round.
+ * No call synchronizes `stream` with the host, except husky_learned_fit
+ * (once, to size its training loop) and the sorts when a caller asks for
+ * adaptive refinement rounds (husky_tuning.max_rounds).
  * Side streams.  For 2^21 strings or more, parts of Step 3 (and of the
  * learned form's bucket sort) that touch disjoint data run on two streams
  * the library creates once per device (default priority, kept until the
@@ -115,14 +115,28 @@ typedef struct {
  *                 round); longer runs device-wide (a group of at most one
  *                 radix tile is then sorted in LDS by the segmented radix
  *                 sort);
- *   max_rounds -- 0: the device-wide fix-up reads its work counts back to
- *                 the host once per refinement round (adaptive).  k > 0: it
- *                 runs exactly k rounds sized from host bounds, with no
- *                 host synchronisation, so the whole call can be captured
- *                 into a HIP graph.  Round r compares elements up to
- *                 m + C*(r+1) (ASCII: 9 + 7(r+1) bytes; UTF-16: 4 + 3(r+1)
- *                 units); groups still tied after k rounds are counted in
- *                 husky_device_status.unresolved and then perm is not final. */
+ *   max_rounds -- device-wide refinement rounds (for runs of equal codes
+ *                 longer than the LDS tier's 8,192 strings).  A round first
+ *                 finds the position where the members of each group first
+ *                 differ and keys the group on the chunk of C elements that
+ *                 holds it (chunks start at m + C*j: ASCII 9 + 7j bytes,
+ *                 UTF-16 4 + 3j units), so no round is spent on chunks all
+ *                 members share, and a group of identical strings is done
+ *                 in the round that meets it.
+ *                 0 (default): one round launched without any host
+ *                 synchronisation, then every group still tied is finished by
+ *                 one workgroup per group running its remaining rounds in
+ *                 global memory: the call never synchronizes, can be
+ *                 captured into a HIP graph, and perm is always final.
+ *                 k in 1..4096: exactly k rounds, no host synchronisation;
+ *                 groups still tied after them are counted in
+ *                 husky_device_status.unresolved and then perm is not final.
+ *                 HUSKY_ROUNDS_ADAPTIVE: the host reads the work counts once
+ *                 per round (synchronizing the stream) and runs rounds until
+ *                 nothing is tied -- for inputs whose long runs still hold
+ *                 long groups after a round (groups that split in few,
+ *                 large parts at one position after another). */
+#define HUSKY_ROUNDS_ADAPTIVE 0xFFFFFFFFu
 typedef struct {
     int32_t radix_bits;
     int32_t tile_items;

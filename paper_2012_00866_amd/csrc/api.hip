@@ -21,6 +21,11 @@ constexpr uint32_t MIN_TILE = BLOCK * 8;  // smallest compiled tile
 constexpr uint32_t MIN_T_MEDIUM = 64;
 constexpr uint32_t MAX_T_MEDIUM = 4096;
 constexpr uint32_t MAX_T_SMALL = 64;
+// Device-wide refinement rounds a call launches without reading anything back
+// (groups still tied after them go to the in-workgroup tail), and the largest
+// grid of their launches (a multiple of 8: the kernels walk their work units).
+constexpr uint32_t DEFAULT_ROUNDS = 1;
+constexpr uint32_t ROUND_GRID_CAP = 2048;
 
 size_t align_up(size_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
 
@@ -201,7 +206,7 @@ husky_status resolve_tuning(const husky_tuning* t, Tune* out) {
         if (t->t_medium) r.t_medium = t->t_medium;
         r.max_rounds = t->max_rounds;
     }
-    if (r.max_rounds > 4096) return HUSKY_ERR_UNSUPPORTED;
+    if (r.max_rounds > 4096 && r.max_rounds != HUSKY_ROUNDS_ADAPTIVE) return HUSKY_ERR_UNSUPPORTED;
     if (r.rc.bits < 6 || r.rc.bits > 8) return HUSKY_ERR_UNSUPPORTED;
     if (r.rc.items != 8 && r.rc.items != 12 && r.rc.items != 16) return HUSKY_ERR_UNSUPPORTED;
     if (r.t_small < 2 || r.t_small > MAX_T_SMALL) return HUSKY_ERR_UNSUPPORTED;
@@ -320,23 +325,33 @@ husky_status run_fixup(Ctx& c, const Tune& tn, int coder, uint32_t origin, const
     const uint32_t tb = tiles_bound(n, n_segs, tn.rc);
     const int ek = elem_kind(coder);
     HUSKY_TRY(find_runs(codes, c.rad, tn.rc, tb, ek, false, nullptr, c.runs, c.tiers,
-                        tn.t_small, tn.t_medium, s, perfect_codes));
+                        tn.t_small, tn.t_medium, origin, s, perfect_codes));
     FixupArgs fa{ek, elems, offsets, (uint32_t)n, idx, c.at<uint64_t>(c.L.key0), origin};
     uint32_t rounds = 0;
     RunItem* cur = c.at<RunItem>(c.L.large_a);
     RunItem* nxt = c.at<RunItem>(c.L.large_b);
     uint32_t* cur_cnt = c.counters + CNT_LARGE_A;
     uint32_t* nxt_cnt = c.counters + CNT_LARGE_B;
-    const bool fixed = tn.max_rounds > 0;
-    // host bounds for the fixed-round mode: every device-wide item is longer
-    // than t_medium, so there are at most n / (t_medium + 1) of them and
-    // their tiles number at most n / tile + items
-    const uint32_t nl_bound = std::min<uint32_t>(c.L.large_cap, (uint32_t)(n / (tn.t_medium + 1) + 1));
+    // Rounds: adaptive (host reads the work counts once per round and stops
+    // when nothing is left), or a fixed number launched without host reads
+    // -- tuning.max_rounds, or the default DEFAULT_ROUNDS followed by the
+    // in-workgroup tail for whatever is still tied.
+    const bool adaptive = tn.max_rounds == HUSKY_ROUNDS_ADAPTIVE;
+    const bool bounded = !adaptive && tn.max_rounds > 0;
+    const uint32_t big_min0 = c.tiers.lds_max ? c.tiers.lds_max : tn.t_medium;
+    // no run can reach the device-wide tier when n is within the run-local ones
+    const uint32_t fixed_rounds = bounded ? tn.max_rounds : (n > big_min0 ? DEFAULT_ROUNDS : 0u);
+    // host bounds for the rounds launched without host reads: every
+    // device-wide item is longer than the LDS tier's (or, without it, the
+    // workgroup tier's) limit, and their tiles number at most n / tile + items
+    const uint32_t big_min = c.tiers.lds_max ? c.tiers.lds_max : tn.t_medium;
+    const uint32_t nl_bound = std::min<uint32_t>(c.L.large_cap, (uint32_t)(n / (big_min + 1) + 1));
     const uint32_t tiles_bound_l = (uint32_t)(n / tn.rc.tile()) + nl_bound + 1;
+    if (!adaptive) c.rad.grid_cap = ROUND_GRID_CAP;
     for (;;) {
         uint32_t nl, all_tiles, big_tiles;
-        if (fixed) {
-            if (rounds == tn.max_rounds) break;
+        if (!adaptive) {
+            if (rounds == fixed_rounds) break;
             nl = nl_bound;
             all_tiles = big_tiles = tiles_bound_l;
         } else {
@@ -350,6 +365,7 @@ husky_status run_fixup(Ctx& c, const Tune& tn, int coder, uint32_t origin, const
             big_tiles = st[1] ? st[2] + 1 : 0;
         }
         HUSKY_TRY(radix_segments_from_items(cur, cur_cnt, c.L.large_cap, c.rad, tn.rc, s));
+        HUSKY_TRY(fixup_large_lcp(fa, cur, c.rad, tn.rc, all_tiles, s));
         HUSKY_TRY(fixup_large_keys(fa, cur, c.rad, tn.rc, all_tiles, keys, s));
         uint32_t pass_union = ~0u;
         if (big_tiles) {
@@ -357,21 +373,24 @@ husky_status run_fixup(Ctx& c, const Tune& tn, int coder, uint32_t origin, const
             HUSKY_TRY(radix_exec_masks(0, 64, nl, big_tiles, c.rad, tn.rc, s));
             // the digit passes any group needs: refinement keys hold long
             // constant stretches, so passes nobody runs are not launched
-            if (!fixed) HUSKY_TRY(read_u32(c.counters + C_EXEC_UNION, &pass_union, s));
+            if (adaptive) HUSKY_TRY(read_u32(c.counters + C_EXEC_UNION, &pass_union, s));
         }
+        // every device-wide item spans several tiles: no single-tile segments
         HUSKY_TRY(radix_sort_segments(keys, idx, keys_alt, c.at<uint32_t>(c.L.idx_b), 0, 64, nl,
-                                      big_tiles, pass_union, c.rad, tn.rc, P_SCATTER_FIX, s));
+                                      big_tiles, pass_union, c.rad, tn.rc, P_SCATTER_FIX, s,
+                                      big_min < (uint32_t)tn.rc.tile()));
         TierLists t2 = c.tiers;
         t2.large = nxt;
         t2.large_count = nxt_cnt;
         HUSKY_TRY(zero_u32(nxt_cnt, 4, s));
         HUSKY_TRY(find_runs(keys, c.rad, tn.rc, all_tiles, ek, true, cur, c.runs, t2,
-                            tn.t_small, tn.t_medium, s));
+                            tn.t_small, tn.t_medium, origin, s));
         std::swap(cur, nxt);
         std::swap(cur_cnt, nxt_cnt);
         ++rounds;
     }
-    if (fixed) {
+    c.rad.grid_cap = ~0u;
+    if (bounded) {
         hipLaunchKernelGGL(k_copy_u32, dim3(1), dim3(1), 0, s, &c.status->unresolved, cur_cnt);
         HUSKY_TRY(hipGetLastError());
     }
@@ -383,6 +402,13 @@ husky_status run_fixup(Ctx& c, const Tune& tn, int coder, uint32_t origin, const
     HUSKY_TRY(fixup_small(fa, c.tiers, tn.t_small, ss ? ss->st[1] : s));
     HUSKY_TRY(fixup_lds(fa, c.tiers, tn.t_medium, s));
     HUSKY_TRY(side_join(s, ss));
+    if (!adaptive && !bounded) {
+        // groups still tied after the default rounds: every remaining round
+        // in one workgroup per group (after the run-local tiers, whose first
+        // refinement keys share the scratch it uses)
+        HUSKY_TRY(fixup_tail(fa, cur, cur_cnt, c.L.large_cap, c.at<uint32_t>(c.L.idx_b), keys, keys_alt,
+                             c.at<uint32_t>(c.L.key0), &c.status->unresolved, s));
+    }
     hipLaunchKernelGGL(k_set_u32, dim3(1), dim3(1), 0, s, &c.status->large_rounds, rounds);
     HUSKY_TRY(hipGetLastError());
     return HUSKY_OK;

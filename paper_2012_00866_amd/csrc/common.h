@@ -76,8 +76,22 @@ struct RunItem {
     uint32_t start;
     uint32_t len;
     uint32_t round;
-    uint32_t pad;
+    // Device-wide tier: a position (in elements) before which every member
+    // equals the group's first member, found by its common-prefix pass
+    // (LCP_NONE, the value items are created with, after that pass: every
+    // member is the same string).
+    uint32_t lcp;
 };
+constexpr uint32_t LCP_NONE = ~0u;
+
+// The round a device-wide group is keyed in: its own, or the later round
+// whose chunk holds the position its members first differ at (every chunk
+// before that one is the same in all of them).
+__device__ __forceinline__ uint32_t keyed_round(const RunItem& r, uint32_t origin, uint32_t chunk) {
+    if (r.lcp == LCP_NONE || r.lcp < origin) return r.round;
+    const uint32_t j = (r.lcp - origin) / chunk;
+    return j > r.round ? j : r.round;
+}
 
 __device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
 
@@ -119,7 +133,21 @@ __device__ __forceinline__ uint32_t xcd_remap(uint32_t b, uint32_t G) {
     return x * q + (x < r ? x : r) + i;
 }
 
-// Exclusive prefix sum over the NW * 64 threads of a workgroup.  `scratch`
+// Work units of a kernel whose grid comes from a host bound: units u =
+// blockIdx.x, blockIdx.x + gridDim.x, ... below the device-side `count`.  A
+// grid of at least `count` workgroups runs each unit in its own workgroup; a
+// capped grid (a multiple of 8, so every unit stays on its workgroup's XCD
+// in xcd_remap) walks several.  The body ends with a barrier when it uses
+// LDS, so the next unit may reuse it; units skipped with `continue` are
+// skipped by the whole workgroup.
+// HUSKY_UNITS_P(PS, ...) walks only when PS (a compile-time flag) is set;
+// otherwise a workgroup runs the one unit of its own index, as straight-line
+// code (grids launched with a unit per workgroup).
+#define HUSKY_UNITS_P(PS, u, count) \
+    for (uint32_t u = blockIdx.x, u##_end = (count); u < u##_end; u = (PS) ? u + gridDim.x : u##_end)
+#define HUSKY_UNITS(u, count) HUSKY_UNITS_P(true, u, count)
+
+// Exclusive prefix sum over the NW * 64 threads of a workgroup.// Exclusive prefix sum over the NW * 64 threads of a workgroup.  `scratch`
 // holds NW words of LDS.  Returns the exclusive prefix; *total gets the block
 // total.  Every thread of the block must call it.
 template <int NW = NWAVES>

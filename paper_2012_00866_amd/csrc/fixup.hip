@@ -611,8 +611,91 @@ __global__ __launch_bounds__(NW * WAVE) void k_fix_lds(const RunItem* __restrict
     }
 }
 
+// ------------------------------------------------------------------ large tier common prefix
+// Every member of a device-wide group is compared with the group's first
+// member from the start of the round's chunk (from its length, for members
+// shorter than that): the smallest position where a member differs from it
+// -- a different element, or one of the two strings ending there -- goes to
+// the item (atomic minimum), LCP_NONE staying when every member is the same
+// string.  All members agree before that position, so the round's keys can
+// start at the chunk holding it instead of walking the chunks they share one
+// round at a time.  A comparison stops after LCP_SPAN elements and reports
+// where it stopped, which is still a position all of them agree before.
+constexpr uint32_t LCP_SPAN = 1024;
+
+template <int CODER, int ITEMS, bool PS>
+__global__ __launch_bounds__(BLOCK) void k_large_lcp(RunItem* __restrict__ items,
+                                                     const SegDesc* __restrict__ segs,
+                                                     const uint32_t* __restrict__ counters,
+                                                     const uint8_t* __restrict__ bytes,
+                                                     const uint64_t* __restrict__ offsets, uint32_t n,
+                                                     const uint32_t* __restrict__ idx, uint32_t origin) {
+    constexpr uint32_t TILE = BLOCK * ITEMS;
+    constexpr uint32_t ES = CODER == 0 ? 1u : 2u;  // bytes per element
+    constexpr uint32_t EPW = 8u / ES;              // elements per 8-byte word
+    constexpr uint32_t C = CODER == 0 ? byte_chunk : utf16_chunk;
+    __shared__ uint32_t s_min[NWAVES];
+    const uint64_t total_bytes = offsets[n] * ES;
+    HUSKY_UNITS_P(PS, t, counters[C_ALL_TILES]) {
+    const uint32_t sidx = find_seg(segs, counters[C_NUM_SEGS], t);
+    const SegDesc d = segs[sidx];
+    const uint32_t lt = t - d.first_tile;
+    const uint32_t base = d.start + lt * TILE;
+    const uint32_t nvalid = min(TILE, d.len - lt * TILE);
+    const uint64_t p = (uint64_t)origin + (uint64_t)C * items[sidx].round;
+    const uint32_t ref = idx[d.start];
+    const uint64_t ro = offsets[ref], rl = offsets[ref + 1] - ro;
+    uint32_t m[ITEMS];
+#pragma unroll
+    for (int k = 0; k < ITEMS; ++k) {
+        const uint32_t i = k * BLOCK + threadIdx.x;
+        m[k] = i < nvalid ? idx[base + i] : ref;
+    }
+    uint64_t o[ITEMS], e[ITEMS];
+#pragma unroll
+    for (int k = 0; k < ITEMS; ++k) {
+        o[k] = offsets[m[k]];
+        e[k] = offsets[m[k] + 1];
+    }
+    uint64_t q = LCP_NONE;
+#pragma unroll
+    for (int k = 0; k < ITEMS; ++k) {
+        const uint64_t len = e[k] - o[k];
+        const uint64_t L = len < rl ? len : rl;
+        uint64_t pos = p < L ? p : L;
+        const uint64_t stop = L - pos > LCP_SPAN ? pos + LCP_SPAN : L;
+        uint64_t at = ~0ull;  // none: the same string
+        while (pos < stop) {
+            const uint64_t cnt = stop - pos < EPW ? stop - pos : EPW;
+            uint64_t x = load8_unaligned(bytes, total_bytes, (o[k] + pos) * ES) ^
+                         load8_unaligned(bytes, total_bytes, (ro + pos) * ES);
+            if (cnt < EPW) x &= (1ull << (cnt * 8 * ES)) - 1ull;
+            if (x) {
+                at = pos + (uint64_t)__builtin_ctzll(x) / (8 * ES);
+                break;
+            }
+            pos += cnt;
+        }
+        if (at == ~0ull && (stop < L || len != rl)) at = stop;  // stopped early, or one string ends
+        // a position past 32 bits is lowered, which keeps it one all agree before
+        if (at != ~0ull) q = min(q, min(at, (uint64_t)LCP_NONE - 1));
+    }
+    uint32_t qw = (uint32_t)q;
+#pragma unroll
+    for (int dd = 32; dd >= 1; dd >>= 1) qw = min(qw, (uint32_t)__shfl_xor((int)qw, dd, WAVE));
+    if (lane_id() == 0) s_min[threadIdx.x / WAVE] = qw;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t tq = s_min[0];
+        for (int w = 1; w < NWAVES; ++w) tq = min(tq, s_min[w]);
+        if (tq != LCP_NONE) atomicMin(&items[sidx].lcp, tq);
+    }
+    if (PS) __syncthreads();
+    }
+}
+
 // ------------------------------------------------------------------ large tier keys
-template <int CODER, int ITEMS>
+template <int CODER, int ITEMS, bool PS>
 __global__ __launch_bounds__(BLOCK) void k_large_keys(const RunItem* __restrict__ items,
                                                       const SegDesc* __restrict__ segs,
                                                       const uint32_t* __restrict__ counters,
@@ -624,14 +707,20 @@ __global__ __launch_bounds__(BLOCK) void k_large_keys(const RunItem* __restrict_
                                                       uint64_t* __restrict__ keys, uint32_t origin) {
     constexpr uint32_t TILE = BLOCK * ITEMS;
     const uint64_t total_bytes = offsets[n] * (CODER == 0 ? 1u : 2u);
-    const uint32_t t = blockIdx.x;
-    if (t >= counters[C_ALL_TILES]) return;
+    HUSKY_UNITS_P(PS, t, counters[C_ALL_TILES]) {
     const uint32_t sidx = find_seg(segs, counters[C_NUM_SEGS], t);
     const SegDesc d = segs[sidx];
-    const uint32_t round = items[sidx].round;
+    const RunItem ri = items[sidx];
     const uint32_t lt = t - d.first_tile;
     const uint32_t base = d.start + lt * TILE;
     const uint32_t nvalid = min(TILE, d.len - lt * TILE);
+    if (ri.lcp == LCP_NONE) {
+        // every member is the same string: one key that does not continue
+        // leaves them in index order
+        for (uint32_t i = threadIdx.x; i < nvalid; i += BLOCK) keys[base + i] = 0;
+        continue;
+    }
+    const uint32_t round = keyed_round(ri, origin, CODER == 0 ? byte_chunk : utf16_chunk);
     // Each level of the gather (index, then first refinement key or string
     // offsets) is issued for all ITEMS members before any is used, so a
     // thread has ITEMS random loads in flight instead of one.  Padding slots
@@ -651,7 +740,7 @@ __global__ __launch_bounds__(BLOCK) void k_large_keys(const RunItem* __restrict_
             const uint32_t i = k * BLOCK + threadIdx.x;
             if (i < nvalid) keys[base + i] = v[k];
         }
-        return;
+        continue;
     }
     uint64_t o[ITEMS], e[ITEMS];
 #pragma unroll
@@ -663,6 +752,254 @@ __global__ __launch_bounds__(BLOCK) void k_large_keys(const RunItem* __restrict_
     for (int k = 0; k < ITEMS; ++k) {
         const uint32_t i = k * BLOCK + threadIdx.x;
         if (i < nvalid) keys[base + i] = chunk_key<CODER>(bytes, total_bytes, o[k], e[k] - o[k], round, origin);
+    }
+    }
+}
+
+// ------------------------------------------------------------------ tail
+// Groups still tied after the device-wide rounds a call launched, too long
+// for the LDS tier: one workgroup takes a group and runs every remaining
+// round itself -- the LDS tier's algorithm with the group in global memory.
+// Per round: the refinement keys of the members still tied; a stable LSD
+// sort of the group's positions by (group start, key) over the 8-bit digits
+// that vary; the new groups (a member starts one where the group start or
+// the key changes) and which of them stay tied (two or more members whose key
+// continues).  The round count is bounded by the longest member, and nothing
+// here waits on another workgroup, so the kernel needs no host decision.
+// Buffers over the group's positions [s, s + L): X = (idx, keyA, gsA) and
+// Y = (idx_alt, keyB, gsB); gs holds the member's group start relative to s,
+// bit 31 set while it is tied (groups of 2^31 members or more are left and
+// counted in *unresolved).
+constexpr uint32_t TAIL_ACTIVE = 1u << 31;
+constexpr int TAIL_ITEMS = 8;
+constexpr uint32_t TAIL_TILE = BLOCK * TAIL_ITEMS;
+
+template <int CODER>
+__global__ __launch_bounds__(BLOCK) void k_fix_tail(const RunItem* __restrict__ items,
+                                                    const uint32_t* __restrict__ count, uint32_t cap,
+                                                    const uint8_t* __restrict__ bytes,
+                                                    const uint64_t* __restrict__ offsets, uint32_t n,
+                                                    uint32_t* idx, uint32_t* idx_alt, uint64_t* keyA,
+                                                    uint64_t* keyB, uint32_t* gsA, uint32_t* gsB,
+                                                    uint32_t origin, uint32_t* __restrict__ unresolved) {
+    __shared__ uint32_t s_whist[NWAVES * 256];
+    __shared__ uint32_t s_binstart[256], s_run[256], s_cnt[256];
+    __shared__ uint32_t s_scan[NWAVES];
+    __shared__ uint32_t s_tmp[TAIL_TILE];
+    __shared__ uint64_t s_or[NWAVES], s_and[NWAVES];
+    __shared__ uint32_t s_gor[NWAVES], s_gand[NWAVES], s_act[NWAVES];
+    __shared__ uint64_t s_prevk;
+    __shared__ uint32_t s_prevg;
+    const uint64_t total_bytes = offsets[n] * (CODER == 0 ? 1u : 2u);
+    const uint32_t tid = threadIdx.x, w = tid / WAVE, lane = lane_id();
+    auto posof = [&](int i) { return w * WAVE * TAIL_ITEMS + i * WAVE + lane; };
+    const uint32_t ni = min(*count, cap);
+    HUSKY_UNITS(it, ni) {
+        const RunItem r = items[it];
+        const uint32_t s0 = r.start, L = r.len;
+        if (L >= TAIL_ACTIVE) {
+            if (tid == 0) atomicAdd(unresolved, 1u);
+            continue;
+        }
+        for (uint32_t p = tid; p < L; p += BLOCK) gsA[s0 + p] = TAIL_ACTIVE;
+        __syncthreads();
+        bool cur = false;  // false: the group is in X, true: in Y
+        for (uint32_t round = r.round;; ++round) {
+            uint32_t* ci = cur ? idx_alt : idx;
+            uint64_t* ck = cur ? keyB : keyA;
+            uint32_t* cg = cur ? gsB : gsA;
+            // 1. keys of the tied members; bits of keys and group starts that vary
+            uint64_t ko = 0, ka = ~0ull;
+            uint32_t go = 0, ga = ~0u;
+            for (uint32_t p = tid; p < L; p += BLOCK) {
+                const uint32_t g = cg[s0 + p];
+                uint64_t k = 0;
+                if (g & TAIL_ACTIVE) {
+                    const uint32_t m = ci[s0 + p];
+                    const uint64_t o = offsets[m];
+                    k = chunk_key<CODER>(bytes, total_bytes, o, offsets[m + 1] - o, round, origin);
+                }
+                ck[s0 + p] = k;
+                ko |= k;
+                ka &= k;
+                go |= g & ~TAIL_ACTIVE;
+                ga &= g & ~TAIL_ACTIVE;
+            }
+#pragma unroll
+            for (int d = 32; d >= 1; d >>= 1) {
+                ko |= (uint64_t)__shfl_xor((unsigned long long)ko, d, WAVE);
+                ka &= (uint64_t)__shfl_xor((unsigned long long)ka, d, WAVE);
+                go |= (uint32_t)__shfl_xor(go, d, WAVE);
+                ga &= (uint32_t)__shfl_xor(ga, d, WAVE);
+            }
+            if (lane == 0) {
+                s_or[w] = ko;
+                s_and[w] = ka;
+                s_gor[w] = go;
+                s_gand[w] = ga;
+            }
+            __syncthreads();
+            uint64_t kv = 0;
+            uint32_t gv = 0;
+            {
+                uint64_t oo = 0, aa = ~0ull;
+                uint32_t gg = 0, gn = ~0u;
+#pragma unroll
+                for (int q = 0; q < NWAVES; ++q) {
+                    oo |= s_or[q];
+                    aa &= s_and[q];
+                    gg |= s_gor[q];
+                    gn &= s_gand[q];
+                }
+                kv = oo ^ aa;
+                gv = gg ^ gn;
+            }
+            __syncthreads();
+            // 2. stable LSD passes by (group start, key): key digits first
+            for (int dg = 0; dg < 12; ++dg) {
+                const uint32_t sh = dg < 8 ? 8u * dg : 8u * (dg - 8);
+                const bool on_key = dg < 8;
+                if (!(on_key ? ((kv >> sh) & 0xFFull) : ((gv >> sh) & 0xFFu))) continue;
+                uint32_t* si = cur ? idx_alt : idx;
+                uint64_t* sk = cur ? keyB : keyA;
+                uint32_t* sg = cur ? gsB : gsA;
+                uint32_t* di = cur ? idx : idx_alt;
+                uint64_t* dk = cur ? keyA : keyB;
+                uint32_t* dgs = cur ? gsA : gsB;
+                auto digit_of = [&](uint64_t k, uint32_t g) {
+                    return on_key ? (uint32_t)(k >> sh) & 0xFFu : ((g & ~TAIL_ACTIVE) >> sh) & 0xFFu;
+                };
+                // digit counts of the whole group, then their starts
+                if (tid < 256) s_cnt[tid] = 0;
+                __syncthreads();
+                for (uint32_t p = tid; p < L; p += BLOCK)
+                    atomicAdd(&s_cnt[digit_of(sk[s0 + p], sg[s0 + p])], 1u);
+                __syncthreads();
+                {
+                    uint32_t tot;
+                    const uint32_t ex = block_exclusive_sum(tid < 256 ? s_cnt[tid] : 0u, s_scan, &tot);
+                    if (tid < 256) s_run[tid] = ex;
+                }
+                __syncthreads();
+                // tiles in order: rank stably inside the tile, place after the
+                // digit's earlier tiles
+                for (uint32_t t0 = 0; t0 < L; t0 += TAIL_TILE) {
+                    const uint32_t nvalid = min(TAIL_TILE, L - t0);
+                    uint64_t k[TAIL_ITEMS];
+                    uint32_t g[TAIL_ITEMS], v[TAIL_ITEMS], dgt[TAIL_ITEMS], pos[TAIL_ITEMS];
+#pragma unroll
+                    for (int i = 0; i < TAIL_ITEMS; ++i) {
+                        const uint32_t p = posof(i);
+                        const bool ok = p < nvalid;
+                        k[i] = ok ? sk[s0 + t0 + p] : 0ull;
+                        g[i] = ok ? sg[s0 + t0 + p] : 0u;
+                        v[i] = ok ? si[s0 + t0 + p] : 0u;
+                        dgt[i] = digit_of(k[i], g[i]);
+                    }
+                    uint32_t bc = 0;
+                    rank_digits<8, TAIL_ITEMS>(dgt, nvalid, pos, s_whist, s_binstart, s_scan, &bc);
+#pragma unroll
+                    for (int i = 0; i < TAIL_ITEMS; ++i) {
+                        if (posof(i) < nvalid) {
+                            const uint32_t d = dgt[i];
+                            const uint32_t o = s0 + s_run[d] + (pos[i] - s_binstart[d]);
+                            dk[o] = k[i];
+                            dgs[o] = g[i];
+                            di[o] = v[i];
+                        }
+                    }
+                    __syncthreads();
+                    if (tid < 256) s_run[tid] += bc;
+                    __syncthreads();
+                }
+                cur = !cur;
+            }
+            // 3. new groups and which stay tied, tile by tile in order (the
+            // old key and group start of the position before a tile are kept
+            // in LDS; the position after it is still unwritten)
+            ci = cur ? idx_alt : idx;
+            ck = cur ? keyB : keyA;
+            cg = cur ? gsB : gsA;
+            uint32_t carry = 0, active = 0;
+            for (uint32_t t0 = 0; t0 < L; t0 += TAIL_TILE) {
+                const uint32_t nvalid = min(TAIL_TILE, L - t0);
+                uint32_t hd[TAIL_ITEMS], nx[TAIL_ITEMS];
+                uint64_t kk[TAIL_ITEMS];
+#pragma unroll
+                for (int i = 0; i < TAIL_ITEMS; ++i) {
+                    const uint32_t p = t0 + posof(i);
+                    hd[i] = nx[i] = 0;
+                    kk[i] = 0;
+                    if (posof(i) < nvalid) {
+                        const uint64_t k = ck[s0 + p];
+                        const uint32_t g = cg[s0 + p] & ~TAIL_ACTIVE;
+                        kk[i] = k;
+                        uint64_t pk;
+                        uint32_t pg;
+                        if (p == 0) {
+                            pk = ~k;
+                            pg = ~g;
+                        } else if (posof(i) == 0) {
+                            pk = s_prevk;
+                            pg = s_prevg;
+                        } else {
+                            pk = ck[s0 + p - 1];
+                            pg = cg[s0 + p - 1] & ~TAIL_ACTIVE;
+                        }
+                        hd[i] = (p == 0 || pk != k || pg != g) ? 1u : 0u;
+                        // does the next position start a group?
+                        if (p + 1 >= L) {
+                            nx[i] = 1;
+                        } else {
+                            const uint64_t k2 = ck[s0 + p + 1];
+                            const uint32_t g2 = cg[s0 + p + 1] & ~TAIL_ACTIVE;
+                            nx[i] = (k2 != k || g2 != g) ? 1u : 0u;
+                        }
+                    }
+                }
+                __syncthreads();
+                if (tid == 0) {
+                    // old values of the tile's last position, for the next tile
+                    s_prevk = ck[s0 + t0 + nvalid - 1];
+                    s_prevg = cg[s0 + t0 + nvalid - 1] & ~TAIL_ACTIVE;
+                }
+                uint32_t st[TAIL_ITEMS];
+#pragma unroll
+                for (int i = 0; i < TAIL_ITEMS; ++i) st[i] = hd[i] ? t0 + posof(i) : 0u;
+                tile_running_max<TAIL_ITEMS, NWAVES>(st, s_tmp, s_scan);
+                uint32_t act = 0;
+#pragma unroll
+                for (int i = 0; i < TAIL_ITEMS; ++i) {
+                    if (posof(i) < nvalid) {
+                        const uint32_t start = max(st[i], carry);
+                        const bool single = hd[i] && nx[i];
+                        const bool tied = !single && key_continues<CODER>(kk[i]);
+                        cg[s0 + t0 + posof(i)] = start | (tied ? TAIL_ACTIVE : 0u);
+                        act += tied ? 1u : 0u;
+                    }
+                }
+                // the carry: the group start of the tile's last position
+#pragma unroll
+                for (int i = 0; i < TAIL_ITEMS; ++i)
+                    if (posof(i) == nvalid - 1) s_tmp[0] = max(st[i], carry);
+                active += act;
+                __syncthreads();
+                carry = s_tmp[0];
+                __syncthreads();
+            }
+#pragma unroll
+            for (int d = 32; d >= 1; d >>= 1) active += __shfl_xor(active, d, WAVE);
+            if (lane == 0) s_act[w] = active;
+            __syncthreads();
+            uint32_t any = 0;
+#pragma unroll
+            for (int q = 0; q < NWAVES; ++q) any += s_act[q];
+            __syncthreads();
+            if (!any) break;
+        }
+        if (cur)
+            for (uint32_t p = tid; p < L; p += BLOCK) idx[s0 + p] = idx_alt[s0 + p];
+        __syncthreads();
     }
 }
 
@@ -766,9 +1103,14 @@ hipError_t fixup_large_keys(const FixupArgs& a, const RunItem* items, const Radi
     ProfScope ps(P_LARGE_KEYS, s);
 #define HUSKY_LK(C, I)                                                                       \
     if (a.coder == C && cfg.items == I) {                                                    \
-        hipLaunchKernelGGL((k_large_keys<C, I>), dim3(max_tiles), dim3(BLOCK), 0, s, items,  \
-                           seg.segs, seg.counters, (const uint8_t*)a.elems, a.offsets, a.n,  \
-                           a.idx, a.key0, keys, a.origin);                                   \
+        if (seg.grid_cap != ~0u)                                                             \
+            hipLaunchKernelGGL((k_large_keys<C, I, true>), dim3(seg.grid(max_tiles)), dim3(BLOCK), 0, s, \
+                               items, seg.segs, seg.counters, (const uint8_t*)a.elems, a.offsets,  \
+                               a.n, a.idx, a.key0, keys, a.origin);                                \
+        else                                                                                 \
+            hipLaunchKernelGGL((k_large_keys<C, I, false>), dim3(seg.grid(max_tiles)), dim3(BLOCK), 0, \
+                               s, items, seg.segs, seg.counters, (const uint8_t*)a.elems, a.offsets, \
+                               a.n, a.idx, a.key0, keys, a.origin);                                \
         return hipGetLastError();                                                            \
     }
     HUSKY_LK(0, 16)
@@ -779,6 +1121,48 @@ hipError_t fixup_large_keys(const FixupArgs& a, const RunItem* items, const Radi
     HUSKY_LK(1, 8)
 #undef HUSKY_LK
     return hipErrorInvalidValue;
+}
+
+hipError_t fixup_large_lcp(const FixupArgs& a, RunItem* items, const RadixScratch& seg,
+                           const RadixConfig& cfg, uint32_t max_tiles, hipStream_t s) {
+    if (!max_tiles) return hipSuccess;
+    ProfScope ps(P_LARGE_KEYS, s);
+#define HUSKY_LCP(C, I)                                                                      \
+    if (a.coder == C && cfg.items == I) {                                                    \
+        if (seg.grid_cap != ~0u)                                                             \
+            hipLaunchKernelGGL((k_large_lcp<C, I, true>), dim3(seg.grid(max_tiles)), dim3(BLOCK), 0, s, \
+                               items, seg.segs, seg.counters, (const uint8_t*)a.elems, a.offsets,  \
+                               a.n, a.idx, a.origin);                                              \
+        else                                                                                 \
+            hipLaunchKernelGGL((k_large_lcp<C, I, false>), dim3(seg.grid(max_tiles)), dim3(BLOCK), 0, \
+                               s, items, seg.segs, seg.counters, (const uint8_t*)a.elems, a.offsets, \
+                               a.n, a.idx, a.origin);                                              \
+        return hipGetLastError();                                                            \
+    }
+    HUSKY_LCP(0, 16)
+    HUSKY_LCP(0, 12)
+    HUSKY_LCP(0, 8)
+    HUSKY_LCP(1, 16)
+    HUSKY_LCP(1, 12)
+    HUSKY_LCP(1, 8)
+#undef HUSKY_LCP
+    return hipErrorInvalidValue;
+}
+
+hipError_t fixup_tail(const FixupArgs& a, const RunItem* items, const uint32_t* count, uint32_t cap,
+                      uint32_t* idx_alt, uint64_t* keyA, uint64_t* keyB, uint32_t* gs, uint32_t* unresolved,
+                      hipStream_t s) {
+    const uint32_t blocks = persistent_blocks() * 2;
+    ProfScope ps(P_LARGE_KEYS, s);
+    if (a.coder == 0)
+        hipLaunchKernelGGL(k_fix_tail<0>, dim3(blocks), dim3(BLOCK), 0, s, items, count, cap,
+                           (const uint8_t*)a.elems, a.offsets, a.n, a.idx, idx_alt, keyA, keyB, gs, gs + a.n,
+                           a.origin, unresolved);
+    else
+        hipLaunchKernelGGL(k_fix_tail<1>, dim3(blocks), dim3(BLOCK), 0, s, items, count, cap,
+                           (const uint8_t*)a.elems, a.offsets, a.n, a.idx, idx_alt, keyA, keyB, gs, gs + a.n,
+                           a.origin, unresolved);
+    return hipGetLastError();
 }
 
 hipError_t fixup_first_keys(const FixupArgs& a, uint64_t* key0, hipStream_t s) {

@@ -63,6 +63,11 @@ struct RadixScratch {
     uint64_t* segvary;     // [big_cap] bits that vary inside each big segment
     uint32_t* prog;        // [MAX_PASSES * PROG_WORDS] digit programs (common.h)
     uint32_t seg_cap, big_cap, big_tile_cap, group_cap;
+    // Largest grid of a launch sized from a host bound (a multiple of 8;
+    // ~0u: none): the kernels walk their work units (HUSKY_UNITS), so a
+    // capped grid only lengthens each workgroup's walk.
+    uint32_t grid_cap = ~0u;
+    uint32_t grid(uint32_t bound) const { return bound < grid_cap ? bound : grid_cap; }
 };
 
 // Build segment descriptors from uint64 string offsets (n_segs + 1 entries).
@@ -150,7 +155,7 @@ struct TierLists {
 hipError_t find_runs(const uint64_t* keys, const RadixScratch& seg, const RadixConfig& cfg,
                      uint32_t max_tiles, int coder, bool refinement, const RunItem* items,
                      const RunScratch& rs, const TierLists& tl, uint32_t t_small,
-                     uint32_t t_medium, hipStream_t s, bool perfect_codes = false);
+                     uint32_t t_medium, uint32_t origin, hipStream_t s, bool perfect_codes = false);
 
 // Zero-fill kernels (graph-capture friendly).
 hipError_t zero_u64(uint64_t* p, size_t n, hipStream_t s);
@@ -175,10 +180,21 @@ hipError_t fixup_medium(const FixupArgs& a, const TierLists& tl, uint32_t t_medi
 // Runs of t_medium < len <= LDS_RUN_MAX, every round inside one workgroup.
 constexpr uint32_t LDS_RUN_MAX = 8192;
 hipError_t fixup_lds(const FixupArgs& a, const TierLists& tl, uint32_t t_medium, hipStream_t s);
+// Device-wide tier, before the keys of a round: the position every group's
+// members first differ at (RunItem::lcp), so that the keys skip the chunks
+// all of them share.
+hipError_t fixup_large_lcp(const FixupArgs& a, RunItem* items, const RadixScratch& seg,
+                           const RadixConfig& cfg, uint32_t max_tiles, hipStream_t s);
 // Refinement keys for every position of the large-tier segments.
 hipError_t fixup_large_keys(const FixupArgs& a, const RunItem* items, const RadixScratch& seg,
                             const RadixConfig& cfg, uint32_t max_tiles, uint64_t* keys,
                             hipStream_t s);
+// Groups left tied after the device-wide rounds (items, device count): one
+// workgroup runs every remaining round of a group in global memory.
+// Scratch: idx_alt u32[n], keyA / keyB u64[n], gs u32[2n].
+hipError_t fixup_tail(const FixupArgs& a, const RunItem* items, const uint32_t* count, uint32_t cap,
+                      uint32_t* idx_alt, uint64_t* keyA, uint64_t* keyB, uint32_t* gs, uint32_t* unresolved,
+                      hipStream_t s);
 // key0[i] = string i's first refinement key (round 0 from a.origin).
 hipError_t fixup_first_keys(const FixupArgs& a, uint64_t* key0, hipStream_t s);
 

@@ -952,7 +952,7 @@ __global__ __launch_bounds__(256) void k_bucket_classes(const uint64_t* __restri
             st = (uint32_t)seg[b];
             len = (uint32_t)(seg[b + 1] - seg[b]);
         }
-        const RunItem it{st, len, 0u, 0u};
+        const RunItem it{st, len, 0u, LCP_NONE};
         const bool big = len > LEARNED_LDS_CAP;
         if (big) {
             ++nb;
@@ -1133,7 +1133,7 @@ __global__ __launch_bounds__(NW * WAVE) void k_bucket_refine(uint64_t* __restric
             t[i] = same ? 0u : p;
         }
         tied = __syncthreads_or(tied);
-        if (tied && threadIdx.x == 0) scan_list[atomicAdd(scan_count, 1u)] = RunItem{start, nvalid, 0u, 0u};
+        if (tied && threadIdx.x == 0) scan_list[atomicAdd(scan_count, 1u)] = RunItem{start, nvalid, 0u, LCP_NONE};
         tile_running_max<ITEMS, NW>(t, s_k32, s_scan);
     } else {
 #pragma unroll
@@ -1282,7 +1282,7 @@ __global__ __launch_bounds__(NW * WAVE) void k_bucket_pack(uint64_t* __restrict_
         }
         tied = __syncthreads_or(tied);
         if (tied) {
-            if (threadIdx.x == 0) scan_list[atomicAdd(scan_count, 1u)] = RunItem{start, nvalid, 0u, 0u};
+            if (threadIdx.x == 0) scan_list[atomicAdd(scan_count, 1u)] = RunItem{start, nvalid, 0u, LCP_NONE};
             tile_running_max<ITEMS, NW>(t, s_k32, s_scan);
         }
         // indices gathered by slot into LDS before any is overwritten

@@ -232,29 +232,30 @@ __device__ __forceinline__ uint32_t big_of_group(const BigDesc* bigs, uint32_t n
 }
 
 // OR and AND of the keys of every big tile (bits that vary = OR ^ AND).
-template <int ITEMS>
+template <int ITEMS, bool PS>
 __global__ __launch_bounds__(BLOCK) void k_orand(const uint64_t* __restrict__ keys,
                                                  const BigDesc* __restrict__ bigs,
                                                  const uint32_t* __restrict__ counters,
                                                  uint64_t* __restrict__ korand) {
     constexpr uint32_t TILE = BLOCK * ITEMS;
     __shared__ uint64_t s_o[NWAVES], s_a[NWAVES];
-    const uint32_t t = blockIdx.x;
-    if (t >= counters[C_BIG_TILES]) return;
-    const BigDesc B = bigs[big_of_tile(bigs, counters[C_NUM_BIG], t)];
-    const uint32_t lt = t - B.first_tile;
-    const uint32_t base = B.start + lt * TILE;
-    const uint32_t nvalid = min(TILE, B.len - lt * TILE);
-    uint64_t o = 0, a = ~0ull;
-    for (uint32_t i = threadIdx.x; i < nvalid; i += BLOCK) {
-        const uint64_t k = keys[base + i];
-        o |= k;
-        a &= k;
-    }
-    block_or_and(o, a, s_o, s_a);
-    if (threadIdx.x == 0) {
-        korand[2 * (size_t)t] = o;
-        korand[2 * (size_t)t + 1] = a;
+    HUSKY_UNITS_P(PS, t, counters[C_BIG_TILES]) {
+        const BigDesc B = bigs[big_of_tile(bigs, counters[C_NUM_BIG], t)];
+        const uint32_t lt = t - B.first_tile;
+        const uint32_t base = B.start + lt * TILE;
+        const uint32_t nvalid = min(TILE, B.len - lt * TILE);
+        uint64_t o = 0, a = ~0ull;
+        for (uint32_t i = threadIdx.x; i < nvalid; i += BLOCK) {
+            const uint64_t k = keys[base + i];
+            o |= k;
+            a &= k;
+        }
+        block_or_and(o, a, s_o, s_a);
+        if (threadIdx.x == 0) {
+            korand[2 * (size_t)t] = o;
+            korand[2 * (size_t)t + 1] = a;
+        }
+        if (PS) __syncthreads();
     }
 }
 
@@ -343,9 +344,20 @@ __device__ void build_programs(BigDesc* __restrict__ bigs, uint32_t* __restrict_
     }
 }
 
+// The workgroup that finished the last big segment: the digit programs.
+template <int BITS>
+__device__ void exec_last(BigDesc* __restrict__ bigs, uint32_t* __restrict__ counters,
+                          uint64_t* __restrict__ segvary, uint32_t* __restrict__ prog, int begin_bit,
+                          int end_bit, uint32_t nb, uint32_t* s_prog, uint64_t* s_pm, uint32_t* s_or,
+                          bool perfect_lsb) {
+    __threadfence();
+    build_programs<BITS>(bigs, counters, segvary, prog, begin_bit, end_bit, nb, s_prog, s_pm, s_or,
+                         perfect_lsb);
+}
+
 // Bits that vary inside every big segment (within [begin_bit, end_bit)) and
 // their union; the workgroup that finishes last builds the digit programs.
-template <int BITS>
+template <int BITS, bool PS>
 __global__ __launch_bounds__(BLOCK) void k_exec(BigDesc* __restrict__ bigs,
                                                 uint32_t* __restrict__ counters,
                                                 const uint64_t* __restrict__ korand,
@@ -357,30 +369,30 @@ __global__ __launch_bounds__(BLOCK) void k_exec(BigDesc* __restrict__ bigs,
     __shared__ uint64_t s_pm[MAX_PASSES];
     __shared__ uint32_t s_or[NWAVES];
     __shared__ uint32_t s_last;
-    const uint32_t b = blockIdx.x;
     const uint32_t nb = counters[C_NUM_BIG];
-    if (b >= nb) return;
-    const BigDesc B = bigs[b];
-    uint64_t o = 0, a = ~0ull;
-    for (uint32_t t = threadIdx.x; t < B.ntiles; t += BLOCK) {
-        o |= korand[2 * (size_t)(B.first_tile + t)];
-        a &= korand[2 * (size_t)(B.first_tile + t) + 1];
+    HUSKY_UNITS_P(PS, b, nb) {
+        const BigDesc B = bigs[b];
+        uint64_t o = 0, a = ~0ull;
+        for (uint32_t t = threadIdx.x; t < B.ntiles; t += BLOCK) {
+            o |= korand[2 * (size_t)(B.first_tile + t)];
+            a &= korand[2 * (size_t)(B.first_tile + t) + 1];
+        }
+        block_or_and(o, a, s_o, s_a);
+        if (threadIdx.x == 0) {
+            const uint64_t range = (end_bit >= 64 ? ~0ull : (1ull << end_bit) - 1ull) & ~((1ull << begin_bit) - 1ull);
+            const uint64_t vary = (o ^ a) & range;
+            store_agent(&segvary[b], vary);
+            if ((uint32_t)vary) atomicOr(&counters[C_VARY_LO], (uint32_t)vary);
+            if (vary >> 32) atomicOr(&counters[C_VARY_HI], (uint32_t)(vary >> 32));
+            __threadfence();
+            s_last = atomicAdd(&counters[C_EXEC_DONE], 1u) == nb - 1 ? 1u : 0u;
+        }
+        __syncthreads();
+        const bool last = s_last != 0;
+        __syncthreads();
+        if (last) exec_last<BITS>(bigs, counters, segvary, prog, begin_bit, end_bit, nb, s_prog, s_pm, s_or,
+                                  perfect_lsb);
     }
-    block_or_and(o, a, s_o, s_a);
-    if (threadIdx.x == 0) {
-        const uint64_t range = (end_bit >= 64 ? ~0ull : (1ull << end_bit) - 1ull) & ~((1ull << begin_bit) - 1ull);
-        const uint64_t vary = (o ^ a) & range;
-        store_agent(&segvary[b], vary);
-        if ((uint32_t)vary) atomicOr(&counters[C_VARY_LO], (uint32_t)vary);
-        if (vary >> 32) atomicOr(&counters[C_VARY_HI], (uint32_t)(vary >> 32));
-        __threadfence();
-        s_last = atomicAdd(&counters[C_EXEC_DONE], 1u) == nb - 1 ? 1u : 0u;
-    }
-    __syncthreads();
-    if (!s_last) return;
-    __threadfence();
-    build_programs<BITS>(bigs, counters, segvary, prog, begin_bit, end_bit, nb, s_prog, s_pm, s_or,
-                         perfect_lsb);
 }
 
 __device__ __forceinline__ bool pass_runs(const BigDesc& B, int pass, bool& flip) {
@@ -390,7 +402,7 @@ __device__ __forceinline__ bool pass_runs(const BigDesc& B, int pass, bool& flip
 }
 
 // Digit counts of one tile -> cnt[tile][digit].
-template <int BITS, int ITEMS>
+template <int BITS, int ITEMS, bool PS>
 __global__ __launch_bounds__(BLOCK) void k_count(const uint64_t* __restrict__ keysA,
                                                  const uint64_t* __restrict__ keysB,
                                                  const BigDesc* __restrict__ bigs,
@@ -400,12 +412,12 @@ __global__ __launch_bounds__(BLOCK) void k_count(const uint64_t* __restrict__ ke
     static_assert(BITS <= 8, "cnt holds 256 digits per tile");
     constexpr uint32_t TILE = BLOCK * ITEMS;
     __shared__ uint32_t s_h[HIST_WORDS];
-    const uint32_t nbt = counters[C_BIG_TILES];  // the grid is an upper bound
-    if (blockIdx.x >= nbt) return;
-    const uint32_t t = xcd_remap(blockIdx.x, nbt);
+    const uint32_t nbt = counters[C_BIG_TILES];
+    HUSKY_UNITS_P(PS, bx, nbt) {
+    const uint32_t t = xcd_remap(bx, nbt);
     const BigDesc B = bigs[big_of_tile(bigs, counters[C_NUM_BIG], t)];
     bool flip;
-    if (!pass_runs(B, pass, flip)) return;
+    if (!pass_runs(B, pass, flip)) continue;
     const uint64_t* src = flip ? keysB : keysA;
     DigitProg dp;
     dp.load(prog, pass);
@@ -425,21 +437,22 @@ __global__ __launch_bounds__(BLOCK) void k_count(const uint64_t* __restrict__ ke
     tile_histogram<ITEMS>(
         [&](int i) { return single ? (uint32_t)(k[i] >> s0) & m0 : dp.digit(k[i]); }, nvalid, s_h,
         cnt + (size_t)t * 256);
+    if (PS) __syncthreads();
+    }
 }
 
 // Exclusive scan of the tile counts inside each group of GROUP_TILES tiles
 // (in place); the group's totals go to gtot[group][digit].
-template <int BITS>
+template <int BITS, bool PS>
 __global__ __launch_bounds__(BLOCK) void k_group_scan(const BigDesc* __restrict__ bigs,
                                                       const uint32_t* __restrict__ counters,
                                                       uint32_t* __restrict__ cnt,
                                                       uint32_t* __restrict__ gtot, int pass) {
     constexpr int R = 1 << BITS;
-    const uint32_t g = blockIdx.x;
-    if (g >= counters[C_NUM_GROUPS]) return;
+    HUSKY_UNITS_P(PS, g, counters[C_NUM_GROUPS]) {
     const BigDesc B = bigs[big_of_group(bigs, counters[C_NUM_BIG], g)];
     bool flip;
-    if (!pass_runs(B, pass, flip)) return;
+    if (!pass_runs(B, pass, flip)) continue;
     const uint32_t t0 = B.first_tile + (g - B.first_group) * GROUP_TILES;
     const uint32_t nt = min((uint32_t)GROUP_TILES, B.first_tile + B.ntiles - t0);
     for (uint32_t d = threadIdx.x; d < (uint32_t)R; d += BLOCK) {
@@ -454,22 +467,22 @@ __global__ __launch_bounds__(BLOCK) void k_group_scan(const BigDesc* __restrict_
         }
         gtot[(size_t)g * 256 + d] = run;
     }
+    }
 }
 
 // Scan of the group totals of one big segment (in place) and the absolute
 // start of every digit: binstart[segment][digit].
-template <int BITS>
+template <int BITS, bool PS>
 __global__ __launch_bounds__(BLOCK) void k_seg_scan(const BigDesc* __restrict__ bigs,
                                                     const uint32_t* __restrict__ counters,
                                                     uint32_t* __restrict__ gtot,
                                                     uint32_t* __restrict__ binstart, int pass) {
     constexpr int R = 1 << BITS;
     __shared__ uint32_t scratch[NWAVES];
-    const uint32_t b = blockIdx.x;
-    if (b >= counters[C_NUM_BIG]) return;
+    HUSKY_UNITS_P(PS, b, counters[C_NUM_BIG]) {
     const BigDesc B = bigs[b];
     bool flip;
-    if (!pass_runs(B, pass, flip)) return;
+    if (!pass_runs(B, pass, flip)) continue;
     const uint32_t d = threadIdx.x;
     uint32_t run = 0;
     if (d < (uint32_t)R) {
@@ -490,12 +503,13 @@ __global__ __launch_bounds__(BLOCK) void k_seg_scan(const BigDesc* __restrict__ 
     uint32_t tot;
     const uint32_t ex = block_exclusive_sum(d < (uint32_t)R ? run : 0u, scratch, &tot);
     if (d < (uint32_t)R) binstart[(size_t)b * 256 + d] = B.start + ex;
+    }
 }
 
 // Rank and scatter one tile.  The tile is staged through LDS twice, keys
 // first and then indices in the same buffer, which halves the LDS a
 // workgroup needs and lets more workgroups share a compute unit.
-template <int BITS, int ITEMS>
+template <int BITS, int ITEMS, bool PS>
 __global__ __launch_bounds__(BLOCK) void k_scatter(
     uint64_t* __restrict__ keysA, uint32_t* __restrict__ valsA, uint64_t* __restrict__ keysB,
     uint32_t* __restrict__ valsB, const BigDesc* __restrict__ bigs,
@@ -509,13 +523,13 @@ __global__ __launch_bounds__(BLOCK) void k_scatter(
     __shared__ uint32_t s_binstart[R];
     __shared__ uint32_t s_gbase[R];
     __shared__ uint32_t s_scan[NWAVES];
-    const uint32_t nbt = counters[C_BIG_TILES];  // the grid is an upper bound
-    if (blockIdx.x >= nbt) return;
-    const uint32_t t = xcd_remap(blockIdx.x, nbt), tid = threadIdx.x;
+    const uint32_t nbt = counters[C_BIG_TILES];
+    HUSKY_UNITS_P(PS, bx, nbt) {
+    const uint32_t t = xcd_remap(bx, nbt), tid = threadIdx.x;
     const uint32_t b = big_of_tile(bigs, counters[C_NUM_BIG], t);
     const BigDesc B = bigs[b];
     bool flip;
-    if (!pass_runs(B, pass, flip)) return;
+    if (!pass_runs(B, pass, flip)) continue;
     const uint64_t* ksrc = flip ? keysB : keysA;
     const uint32_t* vsrc = flip ? valsB : valsA;
     uint64_t* kdst = flip ? keysA : keysB;
@@ -571,9 +585,12 @@ __global__ __launch_bounds__(BLOCK) void k_scatter(
         const uint32_t p = i * BLOCK + tid;
         if (p < nvalid) vdst[dst[i]] = s_v[p];
     }
+    if (PS) __syncthreads();
+    }
 }
 
 // Return odd-parity big segments from the alternate buffers.
+template <bool PS>
 __global__ __launch_bounds__(BLOCK) void k_copy_back(uint64_t* __restrict__ keysA,
                                                      uint32_t* __restrict__ valsA,
                                                      const uint64_t* __restrict__ keysB,
@@ -581,23 +598,23 @@ __global__ __launch_bounds__(BLOCK) void k_copy_back(uint64_t* __restrict__ keys
                                                      const BigDesc* __restrict__ bigs,
                                                      const uint32_t* __restrict__ counters,
                                                      uint32_t tile) {
-    const uint32_t t = blockIdx.x;
-    if (t >= counters[C_BIG_TILES]) return;
-    const BigDesc B = bigs[big_of_tile(bigs, counters[C_NUM_BIG], t)];
-    if (!(__popc(B.exec) & 1)) return;
-    const uint32_t lt = t - B.first_tile;
-    const uint32_t base = B.start + lt * tile;
-    const uint32_t cnt = min(tile, B.len - lt * tile);
-    for (uint32_t i = threadIdx.x; i < cnt; i += BLOCK) {
-        keysA[base + i] = keysB[base + i];
-        valsA[base + i] = valsB[base + i];
+    HUSKY_UNITS_P(PS, t, counters[C_BIG_TILES]) {
+        const BigDesc B = bigs[big_of_tile(bigs, counters[C_NUM_BIG], t)];
+        if (!(__popc(B.exec) & 1)) continue;
+        const uint32_t lt = t - B.first_tile;
+        const uint32_t base = B.start + lt * tile;
+        const uint32_t cnt = min(tile, B.len - lt * tile);
+        for (uint32_t i = threadIdx.x; i < cnt; i += BLOCK) {
+            keysA[base + i] = keysB[base + i];
+            valsA[base + i] = valsB[base + i];
+        }
     }
 }
 
 // ------------------------------------------------------------------ single-tile segments
 // One workgroup sorts a segment of 2..TILE keys entirely in LDS: every pass
 // whose digit varies inside the segment ranks and scatters through LDS.
-template <int BITS, int ITEMS>
+template <int BITS, int ITEMS, bool PS>
 __global__ __launch_bounds__(BLOCK) void k_tile_sort(uint64_t* __restrict__ keys,
                                                      uint32_t* __restrict__ vals,
                                                      const SegDesc* __restrict__ segs,
@@ -612,10 +629,9 @@ __global__ __launch_bounds__(BLOCK) void k_tile_sort(uint64_t* __restrict__ keys
     __shared__ uint32_t s_scan[NWAVES];
     __shared__ uint64_t s_or[NWAVES], s_and[NWAVES];
 
-    const uint32_t sidx = blockIdx.x;
-    if (sidx >= counters[C_NUM_SEGS]) return;
+    HUSKY_UNITS_P(PS, sidx, counters[C_NUM_SEGS]) {
     const SegDesc d = segs[sidx];
-    if (d.len < 2 || d.len > TILE) return;
+    if (d.len < 2 || d.len > TILE) continue;
     const uint32_t nvalid = d.len;
     uint64_t k[ITEMS];
     uint32_t v[ITEMS];
@@ -681,6 +697,8 @@ __global__ __launch_bounds__(BLOCK) void k_tile_sort(uint64_t* __restrict__ keys
             vals[d.start + p] = v[i];
         }
     }
+    if (PS) __syncthreads();
+    }
 }
 
 // Zero-fill (kept as a kernel so that captured graphs hold no memset nodes).
@@ -710,15 +728,20 @@ hipError_t zero_u32(uint32_t* p, size_t n, hipStream_t s) {
 template <int BITS, int ITEMS>
 static hipError_t exec_impl(int begin_bit, int end_bit, uint32_t max_segs, uint32_t max_tiles,
                             const RadixScratch& sc, hipStream_t s, bool perfect_lsb) {
+    const bool walk = sc.grid_cap != ~0u;
     max_tiles = std::min(max_tiles, sc.big_tile_cap);
     const uint32_t max_big = std::min(std::min(sc.big_cap, max_tiles / 2 + 1), std::max(max_segs, 1u));
     ProfScope ps(P_VARY, s);
-    hipLaunchKernelGGL((k_exec<BITS>), dim3(max_big), dim3(BLOCK), 0, s, sc.bigs, sc.counters,
-                       sc.korand, sc.segvary, sc.prog, begin_bit, end_bit, perfect_lsb);
+    if (walk)
+        hipLaunchKernelGGL((k_exec<BITS, true>), dim3(sc.grid(max_big)), dim3(BLOCK), 0, s, sc.bigs,
+                           sc.counters, sc.korand, sc.segvary, sc.prog, begin_bit, end_bit, perfect_lsb);
+    else
+        hipLaunchKernelGGL((k_exec<BITS, false>), dim3(sc.grid(max_big)), dim3(BLOCK), 0, s, sc.bigs,
+                           sc.counters, sc.korand, sc.segvary, sc.prog, begin_bit, end_bit, perfect_lsb);
     return hipGetLastError();
 }
 
-template <int BITS, int ITEMS>
+template <int BITS, int ITEMS, bool PS>
 static hipError_t sort_impl(uint64_t* keys, uint32_t* vals, uint64_t* keys_alt,
                             uint32_t* vals_alt, int begin_bit, int end_bit, uint32_t max_segs,
                             uint32_t max_tiles, uint32_t pass_union, const RadixScratch& sc,
@@ -729,7 +752,7 @@ static hipError_t sort_impl(uint64_t* keys, uint32_t* vals, uint64_t* keys_alt,
     // single-tile segments (unless the caller sorts them itself)
     if (max_segs && tile_segments) {
         ProfScope ps(P_TILE_SORT, s);
-        hipLaunchKernelGGL((k_tile_sort<BITS, ITEMS>), dim3(max_segs), dim3(BLOCK), 0, s, keys,
+        hipLaunchKernelGGL((k_tile_sort<BITS, ITEMS, PS>), dim3(sc.grid(max_segs)), dim3(BLOCK), 0, s, keys,
                            vals, sc.segs, sc.counters, begin_bit, end_bit);
     }
     max_tiles = std::min(max_tiles, sc.big_tile_cap);
@@ -743,26 +766,36 @@ static hipError_t sort_impl(uint64_t* keys, uint32_t* vals, uint64_t* keys_alt,
         if (!((pass_union >> p) & 1u)) continue;
         {
             ProfScope ps(P_COUNT_SCAN, s);
-            hipLaunchKernelGGL((k_count<BITS, ITEMS>), dim3(max_tiles), dim3(BLOCK), 0, s, keys,
+            hipLaunchKernelGGL((k_count<BITS, ITEMS, PS>), dim3(sc.grid(max_tiles)), dim3(BLOCK), 0, s, keys,
                                keys_alt, bigs, sc.counters, sc.cnt, p, sc.prog);
-            hipLaunchKernelGGL((k_group_scan<BITS>), dim3(max_groups), dim3(BLOCK), 0, s, bigs,
+            hipLaunchKernelGGL((k_group_scan<BITS, PS>), dim3(sc.grid(max_groups)), dim3(BLOCK), 0, s, bigs,
                                sc.counters, sc.cnt, sc.gtot, p);
-            hipLaunchKernelGGL((k_seg_scan<BITS>), dim3(max_big), dim3(BLOCK), 0, s, bigs,
+            hipLaunchKernelGGL((k_seg_scan<BITS, PS>), dim3(sc.grid(max_big)), dim3(BLOCK), 0, s, bigs,
                                sc.counters, sc.gtot, sc.binstart, p);
         }
         // timed (when profiling) by events that the dispatch itself records
         hipEvent_t ev0, ev1;
         ProfScope ps(pclass, s, &ev0, &ev1);
-        hipExtLaunchKernelGGL((k_scatter<BITS, ITEMS>), dim3(max_tiles), dim3(BLOCK), 0, s, ev0, ev1, 0u,
+        hipExtLaunchKernelGGL((k_scatter<BITS, ITEMS, PS>), dim3(sc.grid(max_tiles)), dim3(BLOCK), 0, s, ev0, ev1, 0u,
                               keys, vals, keys_alt, vals_alt, (const BigDesc*)bigs,
                               (const uint32_t*)sc.counters, (const uint32_t*)sc.cnt,
                               (const uint32_t*)sc.gtot, (const uint32_t*)sc.binstart, p,
                               (const uint32_t*)sc.prog);
     }
     ProfScope ps(P_COPY_BACK, s);
-    hipLaunchKernelGGL(k_copy_back, dim3(max_tiles), dim3(BLOCK), 0, s, keys, vals, keys_alt,
+    hipLaunchKernelGGL(k_copy_back<PS>, dim3(sc.grid(max_tiles)), dim3(BLOCK), 0, s, keys, vals, keys_alt,
                        vals_alt, bigs, sc.counters, TILE);
     return hipGetLastError();
+}
+
+template <int ITEMS>
+static void orand_launch(const uint64_t* keys, uint32_t max_tiles, const RadixScratch& sc, hipStream_t s) {
+    if (sc.grid_cap != ~0u)
+        hipLaunchKernelGGL((k_orand<ITEMS, true>), dim3(sc.grid(max_tiles)), dim3(BLOCK), 0, s, keys, sc.bigs,
+                           sc.counters, sc.korand);
+    else
+        hipLaunchKernelGGL((k_orand<ITEMS, false>), dim3(sc.grid(max_tiles)), dim3(BLOCK), 0, s, keys, sc.bigs,
+                           sc.counters, sc.korand);
 }
 
 hipError_t radix_reduce_tiles(const uint64_t* keys, uint32_t max_tiles, const RadixScratch& sc,
@@ -771,11 +804,11 @@ hipError_t radix_reduce_tiles(const uint64_t* keys, uint32_t max_tiles, const Ra
     if (!max_tiles) return hipSuccess;
     ProfScope ps(P_VARY, s);
     if (cfg.items == 16)
-        hipLaunchKernelGGL((k_orand<16>), dim3(max_tiles), dim3(BLOCK), 0, s, keys, sc.bigs, sc.counters, sc.korand);
+        orand_launch<16>(keys, max_tiles, sc, s);
     else if (cfg.items == 12)
-        hipLaunchKernelGGL((k_orand<12>), dim3(max_tiles), dim3(BLOCK), 0, s, keys, sc.bigs, sc.counters, sc.korand);
+        orand_launch<12>(keys, max_tiles, sc, s);
     else
-        hipLaunchKernelGGL((k_orand<8>), dim3(max_tiles), dim3(BLOCK), 0, s, keys, sc.bigs, sc.counters, sc.korand);
+        orand_launch<8>(keys, max_tiles, sc, s);
     return hipGetLastError();
 }
 
@@ -793,10 +826,15 @@ hipError_t radix_sort_segments(uint64_t* keys, uint32_t* vals, uint64_t* keys_al
                                uint32_t max_segs, uint32_t max_tiles, uint32_t pass_union,
                                const RadixScratch& sc, const RadixConfig& cfg, int pclass,
                                hipStream_t s, bool tile_segments) {
-#define HUSKY_SORT_CASE(B, I)                                                                 \
-    if (cfg.bits == B && cfg.items == I)                                                      \
-        return sort_impl<B, I>(keys, vals, keys_alt, vals_alt, begin_bit, end_bit, max_segs, \
-                               max_tiles, pass_union, sc, pclass, tile_segments, s);
+#define HUSKY_SORT_CASE(B, I)                                                                      \
+    if (cfg.bits == B && cfg.items == I)                                                           \
+        return sc.grid_cap != ~0u                                                                  \
+                   ? sort_impl<B, I, true>(keys, vals, keys_alt, vals_alt, begin_bit, end_bit,     \
+                                           max_segs, max_tiles, pass_union, sc, pclass,            \
+                                           tile_segments, s)                                       \
+                   : sort_impl<B, I, false>(keys, vals, keys_alt, vals_alt, begin_bit, end_bit,    \
+                                            max_segs, max_tiles, pass_union, sc, pclass,           \
+                                            tile_segments, s);
     HUSKY_SORT_CASE(8, 16)
     HUSKY_SORT_CASE(8, 12)
     HUSKY_SORT_CASE(8, 8)

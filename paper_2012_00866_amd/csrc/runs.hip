@@ -91,7 +91,7 @@ __device__ __forceinline__ void run_flags(const uint64_t* s_k, uint64_t kc, uint
     tail = keep && eq_prev && !eq_next;
 }
 
-template <int CODER, bool REFINE, int ITEMS>
+template <int CODER, bool REFINE, int ITEMS, bool PS>
 __global__ __launch_bounds__(BLOCK) void k_runs_count(const uint64_t* __restrict__ keys,
                                                       const SegDesc* __restrict__ segs,
                                                       const uint32_t* __restrict__ counters,
@@ -100,8 +100,7 @@ __global__ __launch_bounds__(BLOCK) void k_runs_count(const uint64_t* __restrict
     constexpr uint32_t TILE = BLOCK * ITEMS;
     __shared__ uint64_t s_k[TILE + 2];
     __shared__ uint32_t s_cnt[NWAVES];
-    const uint32_t t = blockIdx.x;
-    if (t >= counters[C_ALL_TILES]) return;
+    HUSKY_UNITS_P(PS, t, counters[C_ALL_TILES]) {
     const SegDesc d = segs[find_seg(segs, counters[C_NUM_SEGS], t)];
     const RunCmp rc = RunCmp::make(perfect, counters);
     const uint32_t lt = t - d.first_tile;
@@ -126,6 +125,8 @@ __global__ __launch_bounds__(BLOCK) void k_runs_count(const uint64_t* __restrict
         for (int i = 0; i < NWAVES; ++i) tot += s_cnt[i];
         tile_counts[t] = tot;
     }
+    if (PS) __syncthreads();
+    }
 }
 
 // Exclusive scan of tile_counts[0, total) in place (one workgroup); the grand
@@ -147,7 +148,7 @@ __global__ __launch_bounds__(BLOCK) void k_runs_scan(uint32_t* __restrict__ tile
     if (threadIdx.x == 0) *num_runs = carry;
 }
 
-template <int CODER, bool REFINE, int ITEMS>
+template <int CODER, bool REFINE, int ITEMS, bool PS>
 __global__ __launch_bounds__(BLOCK) void k_runs_write(const uint64_t* __restrict__ keys,
                                                       const SegDesc* __restrict__ segs,
                                                       const uint32_t* __restrict__ counters,
@@ -159,8 +160,7 @@ __global__ __launch_bounds__(BLOCK) void k_runs_write(const uint64_t* __restrict
     constexpr uint32_t TILE = BLOCK * ITEMS;
     __shared__ uint64_t s_k[TILE + 2];
     __shared__ uint32_t s_h[NWAVES], s_t[NWAVES];
-    const uint32_t t = blockIdx.x;
-    if (t >= counters[C_ALL_TILES]) return;
+    HUSKY_UNITS_P(PS, t, counters[C_ALL_TILES]) {
     const uint32_t sidx = find_seg(segs, counters[C_NUM_SEGS], t);
     const SegDesc d = segs[sidx];
     const RunCmp rc = RunCmp::make(perfect, counters);
@@ -214,6 +214,8 @@ __global__ __launch_bounds__(BLOCK) void k_runs_write(const uint64_t* __restrict
         hb += (uint32_t)__popcll(bh);
         tb += (uint32_t)__popcll(bt);
     }
+    if (PS) __syncthreads();
+    }
 }
 
 // Work items for the three tiers.  Each workgroup takes a contiguous share
@@ -233,7 +235,7 @@ __global__ __launch_bounds__(BLOCK) void k_runs_classify(
     const uint32_t* __restrict__ run_start, const uint32_t* __restrict__ run_end,
     const uint32_t* __restrict__ run_seg, const uint32_t* __restrict__ num_runs,
     const RunItem* __restrict__ items, TierLists tl, uint32_t t_small, uint32_t t_medium,
-    uint32_t tile, uint32_t* __restrict__ runs_seen) {
+    uint32_t tile, uint32_t origin, uint32_t chunk, uint32_t* __restrict__ runs_seen) {
     constexpr int NL = 7;  // lists
     // s_n: items per list, then the device-wide list's items longer than one
     // tile, their tiles and the tiles of all its items
@@ -285,12 +287,12 @@ __global__ __launch_bounds__(BLOCK) void k_runs_classify(
     // pass 2: items
     for (uint32_t r = r0 + threadIdx.x; r < r0 + per; r += BLOCK) {
         const bool ok = r < r1;
-        RunItem it{0, 0, 0, 0};
+        RunItem it{0, 0, 0, LCP_NONE};
         int li = -1;
         if (ok) {
             it.start = run_start[r];
             it.len = run_end[r] - it.start + 1;
-            it.round = items ? items[run_seg[r]].round + 1 : 0;
+            it.round = items ? keyed_round(items[run_seg[r]], origin, chunk) + 1 : 0;
             li = list_of(it.len, t_small, t_medium, tl.lds_max);
         }
 #pragma unroll
@@ -312,37 +314,40 @@ __global__ __launch_bounds__(BLOCK) void k_runs_classify(
     if (runs_seen && blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(runs_seen, nr);
 }
 
-template <int CODER, bool REFINE, int ITEMS>
+template <int CODER, bool REFINE, int ITEMS, bool PS>
 static hipError_t find_runs_impl(const uint64_t* keys, const RadixScratch& seg,
                                  uint32_t max_tiles, const RunItem* items, const RunScratch& rs,
                                  const TierLists& tl, uint32_t t_small, uint32_t t_medium,
-                                 hipStream_t s, bool perfect) {
+                                 uint32_t origin, hipStream_t s, bool perfect) {
     if (max_tiles == 0) return hipSuccess;
     uint32_t* num_runs = rs.counters + 0;
     ProfScope ps(P_RUNS, s);
-    hipLaunchKernelGGL((k_runs_count<CODER, REFINE, ITEMS>), dim3(max_tiles), dim3(BLOCK), 0, s,
+    hipLaunchKernelGGL((k_runs_count<CODER, REFINE, ITEMS, PS>), dim3(seg.grid(max_tiles)), dim3(BLOCK), 0, s,
                        keys, seg.segs, seg.counters, rs.tile_counts, perfect);
     hipLaunchKernelGGL(k_runs_scan, dim3(1), dim3(BLOCK), 0, s, rs.tile_counts, seg.counters,
                        num_runs);
-    hipLaunchKernelGGL((k_runs_write<CODER, REFINE, ITEMS>), dim3(max_tiles), dim3(BLOCK), 0, s,
+    hipLaunchKernelGGL((k_runs_write<CODER, REFINE, ITEMS, PS>), dim3(seg.grid(max_tiles)), dim3(BLOCK), 0, s,
                        keys, seg.segs, seg.counters, rs.tile_counts, rs.run_start, rs.run_end,
                        rs.run_start + rs.run_cap, perfect);
     const uint32_t blocks = 96;
     hipLaunchKernelGGL(k_runs_classify, dim3(blocks), dim3(BLOCK), 0, s, rs.run_start, rs.run_end,
                        rs.run_start + rs.run_cap, num_runs, items, tl,
-                       t_small, t_medium, (uint32_t)(BLOCK * ITEMS),
-                       REFINE ? nullptr : rs.runs_seen);
+                       t_small, t_medium, (uint32_t)(BLOCK * ITEMS), origin,
+                       CODER == 0 ? byte_chunk : utf16_chunk, REFINE ? nullptr : rs.runs_seen);
     return hipGetLastError();
 }
 
 hipError_t find_runs(const uint64_t* keys, const RadixScratch& seg, const RadixConfig& cfg,
                      uint32_t max_tiles, int coder, bool refinement, const RunItem* items,
                      const RunScratch& rs, const TierLists& tl, uint32_t t_small,
-                     uint32_t t_medium, hipStream_t s, bool perfect_codes) {
+                     uint32_t t_medium, uint32_t origin, hipStream_t s, bool perfect_codes) {
 #define HUSKY_RUNS_CASE(C, R, I)                                                               \
     if (coder == C && refinement == R && cfg.items == I)                                       \
-        return find_runs_impl<C, R, I>(keys, seg, max_tiles, items, rs, tl, t_small, t_medium, \
-                                       s, perfect_codes && !R);
+        return seg.grid_cap != ~0u                                                               \
+                   ? find_runs_impl<C, R, I, true>(keys, seg, max_tiles, items, rs, tl, t_small,      \
+                                                   t_medium, origin, s, perfect_codes && !R)                  \
+                   : find_runs_impl<C, R, I, false>(keys, seg, max_tiles, items, rs, tl, t_small,     \
+                                                    t_medium, origin, s, perfect_codes && !R);
     HUSKY_RUNS_CASE(0, false, 16)
     HUSKY_RUNS_CASE(0, true, 16)
     HUSKY_RUNS_CASE(1, false, 16)

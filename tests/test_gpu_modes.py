@@ -61,10 +61,19 @@ def test_fixed_rounds_equal_adaptive(gpu_lib, maker):
     np.testing.assert_array_equal(perm, oracle.sort(b)[0])
 
 
+def _two_level_groups():
+    # 20,000 strings sharing 30 bytes, then one of two bytes, 30 more shared
+    # bytes and a distinct tail: the first device-wide round splits the run
+    # at the differing byte into two groups, each still longer than one
+    # workgroup holds in LDS, and only a second round tells them apart
+    rng = np.random.default_rng(7)
+    tails = [bytes(rng.integers(97, 123, size=6, dtype=np.uint8).tolist()) for _ in range(20_000)]
+    return from_strings([b"a"] + [b"x" * 30 + (b"p" if i % 2 else b"q") + b"x" * 30 + t
+                                  for i, t in enumerate(tails)])
+
+
 def test_fixed_rounds_reports_unresolved(gpu_lib):
-    # 9,000 identical 60-byte strings (more than one workgroup holds in LDS,
-    # so the run goes device-wide) need 8 rounds; one round leaves them tied
-    b = from_strings([b"x" * 60] * 9000 + [b"y"])
+    b = _two_level_groups()
     e, o = gpu_lib.to_device(b)
     ws = gpu_lib.alloc_workspace(b.n)
     t = gpu_lib.make_tuning(t_medium=256, max_rounds=1)
@@ -76,14 +85,14 @@ def test_fixed_rounds_reports_unresolved(gpu_lib):
         gpu_lib.sort(e, o, "ascii7", tuning=t, ws=ws)
     import torch
 
-    seg = torch.tensor([0, 1, b.n], dtype=torch.int64, device="cuda")  # a run of 8,999 in one instance
+    seg = torch.tensor([0, 1, b.n], dtype=torch.int64, device="cuda")  # the two groups in one instance
     with pytest.raises(gpu_lib.UnresolvedError):
         gpu_lib.sort_batched(e, o, seg, "ascii7", tuning=t)
     model = gpu_lib.fit_learned(e, o, "ascii7", gpu_lib.make_learned_params(sample_frac=0.1))
     with pytest.raises(gpu_lib.UnresolvedError):
         gpu_lib.sort_learned(e, o, model, "ascii7", tuning=t)
     # enough rounds: no error, and the oracle's answer
-    ok = gpu_lib.make_tuning(t_medium=256, max_rounds=gpu_lib.rounds_for(60))
+    ok = gpu_lib.make_tuning(t_medium=256, max_rounds=gpu_lib.rounds_for(67))
     np.testing.assert_array_equal(_u32(gpu_lib.sort(e, o, "ascii7", tuning=ok, ws=ws)), oracle.sort(b)[0])
 
 
