@@ -366,10 +366,14 @@ husky_status run_fixup(Ctx& c, const Tune& tn, int coder, uint32_t origin, const
         }
         HUSKY_TRY(radix_segments_from_items(cur, cur_cnt, c.L.large_cap, c.rad, tn.rc, s));
         HUSKY_TRY(fixup_large_lcp(fa, cur, c.rad, tn.rc, all_tiles, s));
-        HUSKY_TRY(fixup_large_keys(fa, cur, c.rad, tn.rc, all_tiles, keys, s));
+        // every item is longer than the LDS tier's limit, so longer than a
+        // radix tile: the key tiles are the sort's tiles, and the key kernel
+        // writes their OR / AND itself
+        const bool tile_orand = big_min >= (uint32_t)tn.rc.tile();
+        HUSKY_TRY(fixup_large_keys(fa, cur, c.rad, tn.rc, all_tiles, keys, s, tile_orand));
         uint32_t pass_union = ~0u;
         if (big_tiles) {
-            HUSKY_TRY(radix_reduce_tiles(keys, big_tiles, c.rad, tn.rc, s));
+            if (!tile_orand) HUSKY_TRY(radix_reduce_tiles(keys, big_tiles, c.rad, tn.rc, s));
             HUSKY_TRY(radix_exec_masks(0, 64, nl, big_tiles, c.rad, tn.rc, s));
             // the digit passes any group needs: refinement keys hold long
             // constant stretches, so passes nobody runs are not launched

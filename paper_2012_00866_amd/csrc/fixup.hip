@@ -629,7 +629,8 @@ __global__ __launch_bounds__(BLOCK) void k_large_lcp(RunItem* __restrict__ items
                                                      const uint32_t* __restrict__ counters,
                                                      const uint8_t* __restrict__ bytes,
                                                      const uint64_t* __restrict__ offsets, uint32_t n,
-                                                     const uint32_t* __restrict__ idx, uint32_t origin) {
+                                                     const uint32_t* __restrict__ idx,
+                                                     const uint64_t* __restrict__ key0, uint32_t origin) {
     constexpr uint32_t TILE = BLOCK * ITEMS;
     constexpr uint32_t ES = CODER == 0 ? 1u : 2u;  // bytes per element
     constexpr uint32_t EPW = 8u / ES;              // elements per 8-byte word
@@ -642,27 +643,54 @@ __global__ __launch_bounds__(BLOCK) void k_large_lcp(RunItem* __restrict__ items
     const uint32_t lt = t - d.first_tile;
     const uint32_t base = d.start + lt * TILE;
     const uint32_t nvalid = min(TILE, d.len - lt * TILE);
-    const uint64_t p = (uint64_t)origin + (uint64_t)C * items[sidx].round;
+    const uint32_t round = items[sidx].round;
+    const uint64_t p = (uint64_t)origin + (uint64_t)C * round;
     const uint32_t ref = idx[d.start];
-    const uint64_t ro = offsets[ref], rl = offsets[ref + 1] - ro;
     uint32_t m[ITEMS];
 #pragma unroll
     for (int k = 0; k < ITEMS; ++k) {
         const uint32_t i = k * BLOCK + threadIdx.x;
         m[k] = i < nvalid ? idx[base + i] : ref;
     }
+    // In the first round the first refinement keys settle most members with
+    // one 8-byte gather: a different key puts the difference inside the
+    // first chunk (no chunk to skip), an equal key that does not continue
+    // makes the two the same string; only equal keys that continue are
+    // compared further, from the end of that chunk.
+    uint64_t q = LCP_NONE;
+    bool scan[ITEMS];
+    uint64_t from = p;
+    if (round == 0 && key0) {
+        const uint64_t kr = key0[ref];
+        uint64_t kk[ITEMS];
+#pragma unroll
+        for (int k = 0; k < ITEMS; ++k) kk[k] = key0[m[k]];
+#pragma unroll
+        for (int k = 0; k < ITEMS; ++k) {
+            if (kk[k] != kr) q = p;
+            scan[k] = kk[k] == kr && (kk[k] & 0xFull) == (uint64_t)C + 1;
+        }
+        from = p + C;
+    } else {
+#pragma unroll
+        for (int k = 0; k < ITEMS; ++k) scan[k] = true;
+    }
+    bool any = false;
+#pragma unroll
+    for (int k = 0; k < ITEMS; ++k) any = any || scan[k];
+    const uint64_t ro = offsets[ref], rl = offsets[ref + 1] - ro;
     uint64_t o[ITEMS], e[ITEMS];
 #pragma unroll
     for (int k = 0; k < ITEMS; ++k) {
-        o[k] = offsets[m[k]];
-        e[k] = offsets[m[k] + 1];
+        o[k] = scan[k] ? offsets[m[k]] : 0ull;
+        e[k] = scan[k] ? offsets[m[k] + 1] : 0ull;
     }
-    uint64_t q = LCP_NONE;
 #pragma unroll
     for (int k = 0; k < ITEMS; ++k) {
+        if (!any || !scan[k]) continue;
         const uint64_t len = e[k] - o[k];
         const uint64_t L = len < rl ? len : rl;
-        uint64_t pos = p < L ? p : L;
+        uint64_t pos = from < L ? from : L;
         const uint64_t stop = L - pos > LCP_SPAN ? pos + LCP_SPAN : L;
         uint64_t at = ~0ull;  // none: the same string
         while (pos < stop) {
@@ -695,6 +723,9 @@ __global__ __launch_bounds__(BLOCK) void k_large_lcp(RunItem* __restrict__ items
 }
 
 // ------------------------------------------------------------------ large tier keys
+// Every segment of a round is longer than one radix tile, so the key tiles
+// here are the radix sort's tiles: each tile's OR and AND of its keys (the
+// bits that vary, for the digit programs) go to korand[2t], korand[2t + 1].
 template <int CODER, int ITEMS, bool PS>
 __global__ __launch_bounds__(BLOCK) void k_large_keys(const RunItem* __restrict__ items,
                                                       const SegDesc* __restrict__ segs,
@@ -704,8 +735,10 @@ __global__ __launch_bounds__(BLOCK) void k_large_keys(const RunItem* __restrict_
                                                       uint32_t n,
                                                       const uint32_t* __restrict__ idx,
                                                       const uint64_t* __restrict__ key0,
-                                                      uint64_t* __restrict__ keys, uint32_t origin) {
+                                                      uint64_t* __restrict__ keys, uint32_t origin,
+                                                      uint64_t* __restrict__ korand) {
     constexpr uint32_t TILE = BLOCK * ITEMS;
+    __shared__ uint64_t s_o[NWAVES], s_a[NWAVES];
     const uint64_t total_bytes = offsets[n] * (CODER == 0 ? 1u : 2u);
     HUSKY_UNITS_P(PS, t, counters[C_ALL_TILES]) {
     const uint32_t sidx = find_seg(segs, counters[C_NUM_SEGS], t);
@@ -714,44 +747,69 @@ __global__ __launch_bounds__(BLOCK) void k_large_keys(const RunItem* __restrict_
     const uint32_t lt = t - d.first_tile;
     const uint32_t base = d.start + lt * TILE;
     const uint32_t nvalid = min(TILE, d.len - lt * TILE);
+    uint64_t v[ITEMS];
     if (ri.lcp == LCP_NONE) {
         // every member is the same string: one key that does not continue
         // leaves them in index order
-        for (uint32_t i = threadIdx.x; i < nvalid; i += BLOCK) keys[base + i] = 0;
-        continue;
-    }
-    const uint32_t round = keyed_round(ri, origin, CODER == 0 ? byte_chunk : utf16_chunk);
-    // Each level of the gather (index, then first refinement key or string
-    // offsets) is issued for all ITEMS members before any is used, so a
-    // thread has ITEMS random loads in flight instead of one.  Padding slots
-    // gather string 0, which exists whenever a tile does.
-    uint32_t m[ITEMS];
 #pragma unroll
-    for (int k = 0; k < ITEMS; ++k) {
-        const uint32_t i = k * BLOCK + threadIdx.x;
-        m[k] = i < nvalid ? idx[base + i] : 0u;
-    }
-    if (round == 0 && key0) {
-        uint64_t v[ITEMS];
-#pragma unroll
-        for (int k = 0; k < ITEMS; ++k) v[k] = key0[m[k]];
+        for (int k = 0; k < ITEMS; ++k) v[k] = 0;
+    } else {
+        const uint32_t round = keyed_round(ri, origin, CODER == 0 ? byte_chunk : utf16_chunk);
+        // Each level of the gather (index, then first refinement key or
+        // string offsets) is issued for all ITEMS members before any is
+        // used, so a thread has ITEMS random loads in flight instead of one.
+        // Padding slots gather string 0, which exists whenever a tile does.
+        uint32_t m[ITEMS];
 #pragma unroll
         for (int k = 0; k < ITEMS; ++k) {
             const uint32_t i = k * BLOCK + threadIdx.x;
-            if (i < nvalid) keys[base + i] = v[k];
+            m[k] = i < nvalid ? idx[base + i] : 0u;
         }
-        continue;
-    }
-    uint64_t o[ITEMS], e[ITEMS];
+        if (round == 0 && key0) {
 #pragma unroll
-    for (int k = 0; k < ITEMS; ++k) {
-        o[k] = offsets[m[k]];
-        e[k] = offsets[m[k] + 1];
+            for (int k = 0; k < ITEMS; ++k) v[k] = key0[m[k]];
+        } else {
+            uint64_t o[ITEMS], e[ITEMS];
+#pragma unroll
+            for (int k = 0; k < ITEMS; ++k) {
+                o[k] = offsets[m[k]];
+                e[k] = offsets[m[k] + 1];
+            }
+#pragma unroll
+            for (int k = 0; k < ITEMS; ++k)
+                v[k] = chunk_key<CODER>(bytes, total_bytes, o[k], e[k] - o[k], round, origin);
+        }
     }
+    uint64_t vo = 0, va = ~0ull;
 #pragma unroll
     for (int k = 0; k < ITEMS; ++k) {
         const uint32_t i = k * BLOCK + threadIdx.x;
-        if (i < nvalid) keys[base + i] = chunk_key<CODER>(bytes, total_bytes, o[k], e[k] - o[k], round, origin);
+        if (i < nvalid) {
+            keys[base + i] = v[k];
+            vo |= v[k];
+            va &= v[k];
+        }
+    }
+    if (korand) {
+#pragma unroll
+        for (int dd = 32; dd >= 1; dd >>= 1) {
+            vo |= (uint64_t)__shfl_xor((unsigned long long)vo, dd, WAVE);
+            va &= (uint64_t)__shfl_xor((unsigned long long)va, dd, WAVE);
+        }
+        if (lane_id() == 0) {
+            s_o[threadIdx.x / WAVE] = vo;
+            s_a[threadIdx.x / WAVE] = va;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            for (int w = 1; w < NWAVES; ++w) {
+                vo |= s_o[w];
+                va &= s_a[w];
+            }
+            korand[2 * (size_t)t] = vo;
+            korand[2 * (size_t)t + 1] = va;
+        }
+        if (PS) __syncthreads();
     }
     }
 }
@@ -1098,7 +1156,8 @@ hipError_t fixup_lds(const FixupArgs& a, const TierLists& tl, uint32_t t_medium,
 
 hipError_t fixup_large_keys(const FixupArgs& a, const RunItem* items, const RadixScratch& seg,
                             const RadixConfig& cfg, uint32_t max_tiles, uint64_t* keys,
-                            hipStream_t s) {
+                            hipStream_t s, bool tile_orand) {
+    uint64_t* korand = tile_orand ? seg.korand : nullptr;
     if (!max_tiles) return hipSuccess;
     ProfScope ps(P_LARGE_KEYS, s);
 #define HUSKY_LK(C, I)                                                                       \
@@ -1106,11 +1165,11 @@ hipError_t fixup_large_keys(const FixupArgs& a, const RunItem* items, const Radi
         if (seg.grid_cap != ~0u)                                                             \
             hipLaunchKernelGGL((k_large_keys<C, I, true>), dim3(seg.grid(max_tiles)), dim3(BLOCK), 0, s, \
                                items, seg.segs, seg.counters, (const uint8_t*)a.elems, a.offsets,  \
-                               a.n, a.idx, a.key0, keys, a.origin);                                \
+                               a.n, a.idx, a.key0, keys, a.origin, korand);                        \
         else                                                                                 \
             hipLaunchKernelGGL((k_large_keys<C, I, false>), dim3(seg.grid(max_tiles)), dim3(BLOCK), 0, \
                                s, items, seg.segs, seg.counters, (const uint8_t*)a.elems, a.offsets, \
-                               a.n, a.idx, a.key0, keys, a.origin);                                \
+                               a.n, a.idx, a.key0, keys, a.origin, korand);                        \
         return hipGetLastError();                                                            \
     }
     HUSKY_LK(0, 16)
@@ -1132,11 +1191,11 @@ hipError_t fixup_large_lcp(const FixupArgs& a, RunItem* items, const RadixScratc
         if (seg.grid_cap != ~0u)                                                             \
             hipLaunchKernelGGL((k_large_lcp<C, I, true>), dim3(seg.grid(max_tiles)), dim3(BLOCK), 0, s, \
                                items, seg.segs, seg.counters, (const uint8_t*)a.elems, a.offsets,  \
-                               a.n, a.idx, a.origin);                                              \
+                               a.n, a.idx, a.key0, a.origin);                                      \
         else                                                                                 \
             hipLaunchKernelGGL((k_large_lcp<C, I, false>), dim3(seg.grid(max_tiles)), dim3(BLOCK), 0, \
                                s, items, seg.segs, seg.counters, (const uint8_t*)a.elems, a.offsets, \
-                               a.n, a.idx, a.origin);                                              \
+                               a.n, a.idx, a.key0, a.origin);                                      \
         return hipGetLastError();                                                            \
     }
     HUSKY_LCP(0, 16)

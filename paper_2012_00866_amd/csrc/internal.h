@@ -185,10 +185,12 @@ hipError_t fixup_lds(const FixupArgs& a, const TierLists& tl, uint32_t t_medium,
 // all of them share.
 hipError_t fixup_large_lcp(const FixupArgs& a, RunItem* items, const RadixScratch& seg,
                            const RadixConfig& cfg, uint32_t max_tiles, hipStream_t s);
-// Refinement keys for every position of the large-tier segments.
+// Refinement keys for every position of the large-tier segments; with
+// tile_orand (every segment longer than one radix tile) also each tile's OR
+// and AND of its keys, in place of radix_reduce_tiles.
 hipError_t fixup_large_keys(const FixupArgs& a, const RunItem* items, const RadixScratch& seg,
                             const RadixConfig& cfg, uint32_t max_tiles, uint64_t* keys,
-                            hipStream_t s);
+                            hipStream_t s, bool tile_orand);
 // Groups left tied after the device-wide rounds (items, device count): one
 // workgroup runs every remaining round of a group in global memory.
 // Scratch: idx_alt u32[n], keyA / keyB u64[n], gs u32[2n].

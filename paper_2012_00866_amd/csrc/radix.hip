@@ -412,6 +412,7 @@ __global__ __launch_bounds__(BLOCK) void k_count(const uint64_t* __restrict__ ke
     static_assert(BITS <= 8, "cnt holds 256 digits per tile");
     constexpr uint32_t TILE = BLOCK * ITEMS;
     __shared__ uint32_t s_h[HIST_WORDS];
+    if (!((counters[C_EXEC_UNION] >> pass) & 1u)) return;  // no segment runs this pass
     const uint32_t nbt = counters[C_BIG_TILES];
     HUSKY_UNITS_P(PS, bx, nbt) {
     const uint32_t t = xcd_remap(bx, nbt);
@@ -449,6 +450,7 @@ __global__ __launch_bounds__(BLOCK) void k_group_scan(const BigDesc* __restrict_
                                                       uint32_t* __restrict__ cnt,
                                                       uint32_t* __restrict__ gtot, int pass) {
     constexpr int R = 1 << BITS;
+    if (!((counters[C_EXEC_UNION] >> pass) & 1u)) return;  // no segment runs this pass
     HUSKY_UNITS_P(PS, g, counters[C_NUM_GROUPS]) {
     const BigDesc B = bigs[big_of_group(bigs, counters[C_NUM_BIG], g)];
     bool flip;
@@ -479,6 +481,7 @@ __global__ __launch_bounds__(BLOCK) void k_seg_scan(const BigDesc* __restrict__ 
                                                     uint32_t* __restrict__ binstart, int pass) {
     constexpr int R = 1 << BITS;
     __shared__ uint32_t scratch[NWAVES];
+    if (!((counters[C_EXEC_UNION] >> pass) & 1u)) return;  // no segment runs this pass
     HUSKY_UNITS_P(PS, b, counters[C_NUM_BIG]) {
     const BigDesc B = bigs[b];
     bool flip;
@@ -523,6 +526,7 @@ __global__ __launch_bounds__(BLOCK) void k_scatter(
     __shared__ uint32_t s_binstart[R];
     __shared__ uint32_t s_gbase[R];
     __shared__ uint32_t s_scan[NWAVES];
+    if (!((counters[C_EXEC_UNION] >> pass) & 1u)) return;  // no segment runs this pass
     const uint32_t nbt = counters[C_BIG_TILES];
     HUSKY_UNITS_P(PS, bx, nbt) {
     const uint32_t t = xcd_remap(bx, nbt), tid = threadIdx.x;
