@@ -99,6 +99,8 @@ static ModelView model_view(void* model) {
     return m;
 }
 
+typedef float f32x16 __attribute__((ext_vector_type(16)));  // one 32 x 32 fp32 MFMA block per lane
+
 __device__ __forceinline__ float softplusf(float v) { return v > 20.f ? v : log1pf(expf(v)); }
 __device__ __forceinline__ float sigmoidf(float v) { return 1.f / (1.f + expf(-v)); }
 
@@ -144,14 +146,24 @@ __global__ void k_mlp_init(float* params, float* m, float* v, uint64_t seed, int
 }
 
 // ------------------------------------------------------------------ forward / backward
-// One workgroup takes `per_block` consecutive samples of the batch in rounds
-// of 256 (one per thread) and writes the gradient of the batch's mean
-// squared error, summed over its samples, to partial[block][NPARAM]; the
-// loss sum goes to partial[block][NPARAM].  Per round, with h1 / h2 the two
-// hidden activations of the round's samples staged in LDS:
-//   forward: each thread its sample's h1, z2 = W2 h1 + b2, out;
-//   dW2 = sum_s dz2_s h1_s^T (4x4 register block per thread), dw3, db2,
-//   db3 by column sums; dz1 = (W2^T dz2) * [h1 > 0], then dw1, db1.
+// One workgroup (four wavefronts) takes `per_block` consecutive samples of
+// the batch, 32 per wavefront at a time, and writes the gradient of the
+// batch's mean squared error, summed over its samples, to
+// partial[block][NPARAM]; the loss sum goes to partial[block][NPARAM].  The
+// three 64 x 64 products run on the matrix cores (v_mfma_f32_32x32x2f32: in
+// an output block lane l holds row 8(v / 4) + 4(l / 32) + v % 4 and column
+// l % 32 in register v; the A operand of a step is row l % 32 at column
+// l / 32 of that step's pair, the B operand row l / 32 of the pair at
+// column l % 32):
+//   forward   z2^T = W2 h1^T      rows hidden unit k, columns the 32 samples;
+//   weights   dW2 += dz2^T h1     K runs over the samples, accumulated in
+//                                 registers for all of the wavefront's;
+//   backward  dh1^T = W2^T dz2^T  rows hidden unit j, columns the samples.
+// h1 is recomputed from x wherever an operand needs it; dz2, relu(z2) and
+// dz1 pass through LDS ([sample][unit]) to change layout, and the vector
+// gradients (dw3, db2, dw1, db1) are column sums over them, one unit per
+// lane.  Wavefront partials are added in a fixed order, so the result does
+// not depend on timing.
 template <bool MONO>
 __global__ __launch_bounds__(MLP_T) void k_mlp_grad(const float* __restrict__ params,
                                                     const float* __restrict__ xs,
@@ -159,18 +171,18 @@ __global__ __launch_bounds__(MLP_T) void k_mlp_grad(const float* __restrict__ pa
                                                     uint32_t count, uint32_t stride,
                                                     uint32_t per_block, float inv_batch,
                                                     float* __restrict__ partial) {
-    extern __shared__ __align__(16) float lds[];
-    float* W2 = lds;                    // [HID][HID] effective weights
-    float* w1 = W2 + HID * HID;         // [HID]
-    float* b1 = w1 + HID;
-    float* b2 = b1 + HID;
-    float* w3 = b2 + HID;
-    float* sx = w3 + HID;               // [MLP_T]
-    float* sg = sx + MLP_T;             // [MLP_T] dL/dout per sample
-    float* h1 = sg + MLP_T;             // [MLP_T][HID + 1]
-    float* h2 = h1 + MLP_T * (HID + 1); // [MLP_T][HID + 1], later dz1
-    __shared__ float s_red[MLP_T / WAVE];
-    const int tid = threadIdx.x;
+    constexpr int NWV = MLP_T / WAVE;  // wavefronts
+    constexpr int CH = 32;             // samples per wavefront step
+    constexpr int LD = HID + 1;        // padded LDS row
+    static_assert(NWV * HID * HID <= 2 * NWV * CH * LD, "wavefront dW2 partials fit the staging area");
+    __shared__ float W2[HID * HID];  // effective weights [k][j]
+    __shared__ float w1[HID], b1[HID], b2[HID], w3[HID];
+    __shared__ float s_buf[2 * NWV * CH * LD];
+    __shared__ float s_x[NWV][CH], s_g[NWV][CH];
+    __shared__ float s_vec[NWV][6][HID];  // per wavefront: dw3, db2, dw1, db1, db3 / loss
+    const uint32_t tid = threadIdx.x, w = tid / WAVE, l = lane_id(), half = l / 32, col = l % 32;
+    float* s_dz = s_buf + w * CH * LD;             // dz2 as [sample][k]
+    float* s_r = s_buf + (NWV + w) * CH * LD;      // relu(z2), then dz1, as [sample][unit]
     for (int i = tid; i < HID * HID; i += MLP_T) W2[i] = eff<MONO>(params[O_V2 + i]);
     if (tid < HID) {
         w1[tid] = eff<MONO>(params[O_V1 + tid]);
@@ -180,112 +192,151 @@ __global__ __launch_bounds__(MLP_T) void k_mlp_grad(const float* __restrict__ pa
     }
     const float b3 = params[O_B3];
     __syncthreads();
-    // per-thread accumulators: a 4x4 block of dW2, and (threads < 64) one
-    // column of dw3 / db2 / dw1 / db1
-    const int kb = (tid / 16) * 4, jb = (tid % 16) * 4;
-    float acc[4][4] = {};
-    float a_w3 = 0.f, a_b2 = 0.f, a_w1 = 0.f, a_b1 = 0.f, a_b3 = 0.f, a_loss = 0.f;
+    // forward A operands (rows of W2) and the h1 coefficients this lane's
+    // weight-gradient B operands use
+    float a0[HID / 2], a1[HID / 2];
+#pragma unroll
+    for (int st = 0; st < HID / 2; ++st) {
+        a0[st] = W2[(int)col * HID + 2 * st + (int)half];
+        a1[st] = W2[(32 + (int)col) * HID + 2 * st + (int)half];
+    }
+    const float w1c0 = w1[col], b1c0 = b1[col], w1c1 = w1[32 + col], b1c1 = b1[32 + col];
+    f32x16 gw00 = {}, gw01 = {}, gw10 = {}, gw11 = {};
+    float acc_w3 = 0.f, acc_b2 = 0.f, acc_w1 = 0.f, acc_b1 = 0.f, acc_b3 = 0.f, acc_loss = 0.f;
     const uint32_t s0 = blockIdx.x * per_block;
     const uint32_t s1 = min(count, s0 + per_block);
-    for (uint32_t base = s0; base < s1; base += MLP_T) {
-        const uint32_t s = base + tid;
-        const bool ok = s < s1;
-        const uint32_t src = first + s * stride;
+    for (uint32_t base = s0; base < s1; base += NWV * CH) {  // uniform per workgroup
+        const uint32_t smp = base + w * CH + col;
+        const bool ok = smp < s1;
+        const uint32_t src = first + smp * stride;
         const float x = ok ? xs[src] : 0.f;
-        float z2[HID];
+        const float yv = ok ? ys[src] : 0.f;
+        // forward
+        f32x16 z0 = {}, z1 = {};
 #pragma unroll
-        for (int k = 0; k < HID; ++k) z2[k] = b2[k];
-        float* hrow = h1 + tid * (HID + 1);
-        for (int j = 0; j < HID; ++j) {
+        for (int st = 0; st < HID / 2; ++st) {
+            const int j = 2 * st + (int)half;
             const float h = fmaxf(w1[j] * x + b1[j], 0.f);
-            hrow[j] = h;
-#pragma unroll
-            for (int k = 0; k < HID; ++k) z2[k] += W2[k * HID + j] * h;
+            z0 = __builtin_amdgcn_mfma_f32_32x32x2f32(a0[st], h, z0, 0, 0, 0);
+            z1 = __builtin_amdgcn_mfma_f32_32x32x2f32(a1[st], h, z1, 0, 0, 0);
         }
-        float out = b3;
-        float* h2row = h2 + tid * (HID + 1);
+        float part = 0.f;
 #pragma unroll
-        for (int k = 0; k < HID; ++k) {
-            const float h = fmaxf(z2[k], 0.f);
-            h2row[k] = h;
-            out += w3[k] * h;
+        for (int v = 0; v < 16; ++v) {
+            const int k = 8 * (v / 4) + 4 * (int)half + (v % 4);
+            part += w3[k] * fmaxf(z0[v] + b2[k], 0.f) + w3[32 + k] * fmaxf(z1[v] + b2[32 + k], 0.f);
         }
-        const float d = ok ? out - ys[src] : 0.f;
-        sx[tid] = x;
-        sg[tid] = 2.f * d * inv_batch;
-        a_loss += d * d;
-        __syncthreads();
-        // weight gradients of the round: column sums over its samples
-        const int nr = (int)min((uint32_t)MLP_T, s1 - base);
-        for (int r = 0; r < nr; ++r) {
-            const float g = sg[r];
-            const float* a = h2 + r * (HID + 1);
-            const float* b = h1 + r * (HID + 1);
-            float dz[4], hv[4];
+        const float out = b3 + (part + __shfl_xor(part, 32, WAVE));
+        const float d = ok ? out - yv : 0.f;
+        const float g = 2.f * d * inv_batch;
+        if (half == 0) {
+            acc_loss += d * d;
+            acc_b3 += g;
+            s_x[w][col] = x;
+            s_g[w][col] = g;
+        }
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                dz[q] = a[kb + q] > 0.f ? g * w3[kb + q] : 0.f;
-                hv[q] = b[jb + q];
-            }
-#pragma unroll
-            for (int q = 0; q < 4; ++q)
-#pragma unroll
-                for (int u = 0; u < 4; ++u) acc[q][u] += dz[q] * hv[u];
-            if (tid < HID) {
-                a_w3 += g * a[tid];
-                a_b2 += a[tid] > 0.f ? g * w3[tid] : 0.f;
-            }
-            if (tid == 0) a_b3 += g;
+        for (int v = 0; v < 16; ++v) {
+            const int k = 8 * (v / 4) + 4 * (int)half + (v % 4);
+            const float p0 = z0[v] + b2[k], p1 = z1[v] + b2[32 + k];
+            s_dz[col * LD + k] = p0 > 0.f ? g * w3[k] : 0.f;
+            s_dz[col * LD + 32 + k] = p1 > 0.f ? g * w3[32 + k] : 0.f;
+            s_r[col * LD + k] = fmaxf(p0, 0.f);
+            s_r[col * LD + 32 + k] = fmaxf(p1, 0.f);
         }
         __syncthreads();
-        // dz1 of this thread's sample, written over its h2 row
-        {
-            const float g = sg[tid];
-            float dz2v[HID];
+        // dW2 += dz2^T h1 over the wavefront's 32 samples (two per step)
 #pragma unroll
-            for (int k = 0; k < HID; ++k) dz2v[k] = h2row[k] > 0.f ? g * w3[k] : 0.f;
-            for (int j = 0; j < HID; ++j) {
-                float dh = 0.f;
+        for (int st = 0; st < CH / 2; ++st) {
+            const int sm = 2 * st + (int)half;
+            const float xsm = s_x[w][sm];
+            const float az0 = s_dz[sm * LD + col], az1 = s_dz[sm * LD + 32 + col];
+            const float h0 = fmaxf(w1c0 * xsm + b1c0, 0.f), h1v = fmaxf(w1c1 * xsm + b1c1, 0.f);
+            gw00 = __builtin_amdgcn_mfma_f32_32x32x2f32(az0, h0, gw00, 0, 0, 0);
+            gw01 = __builtin_amdgcn_mfma_f32_32x32x2f32(az0, h1v, gw01, 0, 0, 0);
+            gw10 = __builtin_amdgcn_mfma_f32_32x32x2f32(az1, h0, gw10, 0, 0, 0);
+            gw11 = __builtin_amdgcn_mfma_f32_32x32x2f32(az1, h1v, gw11, 0, 0, 0);
+        }
+        // dw3 and db2: lane l sums unit l over the samples
+        for (int sm = 0; sm < CH; ++sm) {
+            acc_w3 += s_g[w][sm] * s_r[sm * LD + l];
+            acc_b2 += s_dz[sm * LD + l];
+        }
+        // dh1^T = W2^T dz2^T
+        f32x16 dh0 = {}, dh1 = {};
 #pragma unroll
-                for (int k = 0; k < HID; ++k) dh += dz2v[k] * W2[k * HID + j];
-                h2row[j] = hrow[j] > 0.f ? dh : 0.f;
-            }
+        for (int st = 0; st < HID / 2; ++st) {
+            const int k = 2 * st + (int)half;
+            const float bz = s_dz[col * LD + k];
+            dh0 = __builtin_amdgcn_mfma_f32_32x32x2f32(W2[k * HID + col], bz, dh0, 0, 0, 0);
+            dh1 = __builtin_amdgcn_mfma_f32_32x32x2f32(W2[k * HID + 32 + col], bz, dh1, 0, 0, 0);
+        }
+        __syncthreads();  // relu(z2) read before dz1 takes its place
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+            const int j = 8 * (v / 4) + 4 * (int)half + (v % 4);
+            s_r[col * LD + j] = w1[j] * x + b1[j] > 0.f ? dh0[v] : 0.f;
+            s_r[col * LD + 32 + j] = w1[32 + j] * x + b1[32 + j] > 0.f ? dh1[v] : 0.f;
         }
         __syncthreads();
-        if (tid < HID) {
-            for (int r = 0; r < nr; ++r) {
-                const float dz1 = h2[r * (HID + 1) + tid];
-                a_w1 += dz1 * sx[r];
-                a_b1 += dz1;
-            }
+        for (int sm = 0; sm < CH; ++sm) {
+            const float dz1 = s_r[sm * LD + l];
+            acc_w1 += dz1 * s_x[w][sm];
+            acc_b1 += dz1;
         }
-        __syncthreads();
+        __syncthreads();  // staging free for the next step
     }
-    // chain rule through the weight parametrisation, then write this block's sums
-    float* out = partial + (size_t)blockIdx.x * (NPARAM + 1);
+    // wavefront partials: dW2 blocks as [k][j], then the vector sums
+    float* s_gw = s_buf + w * HID * HID;
 #pragma unroll
-    for (int q = 0; q < 4; ++q)
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int i = (kb + q) * HID + jb + u;
-            out[O_V2 + i] = acc[q][u] * deff<MONO>(params[O_V2 + i]);
-        }
-    if (tid < HID) {
-        out[O_V1 + tid] = a_w1 * deff<MONO>(params[O_V1 + tid]);
-        out[O_B1 + tid] = a_b1;
-        out[O_B2 + tid] = a_b2;
-        out[O_V3 + tid] = a_w3 * deff<MONO>(params[O_V3 + tid]);
+    for (int v = 0; v < 16; ++v) {
+        const int k = 8 * (v / 4) + 4 * (int)half + (v % 4);
+        s_gw[k * HID + col] = gw00[v];
+        s_gw[k * HID + 32 + col] = gw01[v];
+        s_gw[(32 + k) * HID + col] = gw10[v];
+        s_gw[(32 + k) * HID + 32 + col] = gw11[v];
     }
-    if (tid == 0) out[O_B3] = a_b3;
-    // loss sum
 #pragma unroll
-    for (int dd = 32; dd >= 1; dd >>= 1) a_loss += __shfl_xor(a_loss, dd, WAVE);
-    if (lane_id() == 0) s_red[tid / WAVE] = a_loss;
+    for (int dd = 32; dd >= 1; dd >>= 1) {
+        acc_loss += __shfl_xor(acc_loss, dd, WAVE);
+        acc_b3 += __shfl_xor(acc_b3, dd, WAVE);
+    }
+    s_vec[w][0][l] = acc_w3;
+    s_vec[w][1][l] = acc_b2;
+    s_vec[w][2][l] = acc_w1;
+    s_vec[w][3][l] = acc_b1;
+    if (l == 0) {
+        s_vec[w][4][0] = acc_b3;
+        s_vec[w][5][0] = acc_loss;
+    }
     __syncthreads();
-    if (tid == 0) {
+    // chain rule through the weight parametrisation, then this block's sums
+    float* out = partial + (size_t)blockIdx.x * (NPARAM + 1);
+    for (int i = tid; i < HID * HID; i += MLP_T) {
         float t = 0.f;
-        for (int i = 0; i < MLP_T / WAVE; ++i) t += s_red[i];
-        out[NPARAM] = t;
+#pragma unroll
+        for (int ww = 0; ww < NWV; ++ww) t += s_buf[ww * HID * HID + i];
+        out[O_V2 + i] = t * deff<MONO>(params[O_V2 + i]);
+    }
+    if (tid < HID) {
+        float v[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int ww = 0; ww < NWV; ++ww)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) v[q] += s_vec[ww][q][tid];
+        out[O_V3 + tid] = v[0] * deff<MONO>(params[O_V3 + tid]);
+        out[O_B2 + tid] = v[1];
+        out[O_V1 + tid] = v[2] * deff<MONO>(params[O_V1 + tid]);
+        out[O_B1 + tid] = v[3];
+    }
+    if (tid == 0) {
+        float t3 = 0.f, tl = 0.f;
+        for (int ww = 0; ww < NWV; ++ww) {
+            t3 += s_vec[ww][4][0];
+            tl += s_vec[ww][5][0];
+        }
+        out[O_B3] = t3;
+        out[NPARAM] = tl;
     }
 }
 
@@ -332,50 +383,89 @@ __device__ __forceinline__ uint32_t dense_before(const uint32_t* __restrict__ de
     return dense_cum[a];
 }
 
-template <bool MONO, int KIND>
-__global__ __launch_bounds__(256) void k_lut_eval(const float* __restrict__ params,
-                                                  const LearnedHeader* __restrict__ hdr,
+// The cells without a network: f = x (equal-width cells) or 0.
+template <int KIND>
+__global__ __launch_bounds__(256) void k_lut_eval(const LearnedHeader* __restrict__ hdr,
                                                   const uint32_t* __restrict__ dense,
                                                   const uint32_t* __restrict__ dense_cum,
                                                   uint32_t* __restrict__ lut) {
-    __shared__ float W2[HID * HID], w1[HID], b1[HID], b2[HID], w3[HID];
-    if (KIND == LUT_NET) {
-        for (int i = threadIdx.x; i < HID * HID; i += 256) W2[i] = eff<MONO>(params[O_V2 + i]);
-        if (threadIdx.x < HID) {
-            w1[threadIdx.x] = eff<MONO>(params[O_V1 + threadIdx.x]);
-            b1[threadIdx.x] = params[O_B1 + threadIdx.x];
-            b2[threadIdx.x] = params[O_B2 + threadIdx.x];
-            w3[threadIdx.x] = eff<MONO>(params[O_V3 + threadIdx.x]);
-        }
-        __syncthreads();
-    }
-    const float b3 = KIND == LUT_NET ? params[O_B3] : 0.f;
     const uint32_t nd = hdr->dense, S = hdr->sample;
     const double rest = (double)(S - hdr->dense_keys), invS = 1.0 / (double)S;
     for (uint32_t c = blockIdx.x * 256 + threadIdx.x; c <= LUT_CELLS; c += gridDim.x * 256) {
         const float x = (float)c * (1.f / (float)LUT_CELLS);
-        float f;
-        if (KIND == LUT_NET) {
-            float z2[HID];
-#pragma unroll
-            for (int k = 0; k < HID; ++k) z2[k] = b2[k];
-            for (int j = 0; j < HID; ++j) {
-                const float h = fmaxf(w1[j] * x + b1[j], 0.f);
-#pragma unroll
-                for (int k = 0; k < HID; ++k) z2[k] += W2[k * HID + j] * h;
-            }
-            float out = b3;
-#pragma unroll
-            for (int k = 0; k < HID; ++k) out += w3[k] * fmaxf(z2[k], 0.f);
-            f = fminf(fmaxf(out, 0.f), 1.f);
-        } else {
-            f = KIND == LUT_IDENTITY ? x : 0.f;
-        }
+        const float f = KIND == LUT_IDENTITY ? x : 0.f;
         const double F = ((double)dense_before(dense, dense_cum, nd, c) + rest * (double)f) * invS;
         uint32_t q = (uint32_t)fmin(F * 4294967295.0, 4294967295.0);
         if (c == 0) q = 0;
         if (c == LUT_CELLS) q = 0xFFFFFFFFu;
         lut[c] = q;
+    }
+}
+
+// The network's LUT entries on the matrix cores (the 64 x 64 layer is a dense
+// contraction over all 2^24 + 1 cells).  Each wavefront takes 32 cells at a
+// time and forms z2^T = W2 h1^T as two 32 x 32 blocks (hidden units 0-31 and
+// 32-63) with K = 64 in 32 steps of v_mfma_f32_32x32x2f32.  In step s lane l
+// supplies W2[32t + l % 32][2s + l / 32] (the A operands of both blocks, held
+// in registers for the whole kernel) and h1 of its cell c = base + l % 32 at
+// hidden unit 2s + l / 32 (the B operand, computed in place), and receives
+// z2 of its cell at units 32t + 8(v / 4) + 4(l / 32) + v % 4 in accumulator
+// register v.  The output layer sums those, the two lanes of a cell (l and
+// l + 32) add their halves, and the first 32 lanes write the cells.  The sums
+// run in another order than the scalar form's, within the same fp32 error
+// bound.
+template <bool MONO>
+__global__ __launch_bounds__(256) void k_lut_net(const float* __restrict__ params,
+                                                 const LearnedHeader* __restrict__ hdr,
+                                                 const uint32_t* __restrict__ dense,
+                                                 const uint32_t* __restrict__ dense_cum,
+                                                 uint32_t* __restrict__ lut) {
+    __shared__ float s_b2[HID], s_w3[HID];
+    const uint32_t l = lane_id(), half = l / 32, col = l % 32;
+    if (threadIdx.x < HID) {
+        s_b2[threadIdx.x] = params[O_B2 + threadIdx.x];
+        s_w3[threadIdx.x] = eff<MONO>(params[O_V3 + threadIdx.x]);
+    }
+    float a0[HID / 2], a1[HID / 2], w1v[HID / 2], b1v[HID / 2];
+#pragma unroll
+    for (int st = 0; st < HID / 2; ++st) {
+        const int j = 2 * st + (int)half;
+        a0[st] = eff<MONO>(params[O_V2 + (int)col * HID + j]);
+        a1[st] = eff<MONO>(params[O_V2 + (32 + (int)col) * HID + j]);
+        w1v[st] = eff<MONO>(params[O_V1 + j]);
+        b1v[st] = params[O_B1 + j];
+    }
+    __syncthreads();
+    const float b3 = params[O_B3];
+    const uint32_t nd = hdr->dense, S = hdr->sample;
+    const double rest = (double)(S - hdr->dense_keys), invS = 1.0 / (double)S;
+    const uint32_t wv = blockIdx.x * (256 / WAVE) + threadIdx.x / WAVE, nwv = gridDim.x * (256 / WAVE);
+    for (uint32_t base = wv * 32; base <= LUT_CELLS; base += nwv * 32) {  // uniform per wavefront
+        const uint32_t c = base + col;
+        const float x = (float)c * (1.f / (float)LUT_CELLS);
+        f32x16 z0 = {}, z1 = {};
+#pragma unroll
+        for (int st = 0; st < HID / 2; ++st) {
+            const float h = fmaxf(w1v[st] * x + b1v[st], 0.f);
+            z0 = __builtin_amdgcn_mfma_f32_32x32x2f32(a0[st], h, z0, 0, 0, 0);
+            z1 = __builtin_amdgcn_mfma_f32_32x32x2f32(a1[st], h, z1, 0, 0, 0);
+        }
+        float part = 0.f;
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+            const int k = 8 * (v / 4) + 4 * (int)half + (v % 4);
+            part += s_w3[k] * fmaxf(z0[v] + s_b2[k], 0.f);
+            part += s_w3[32 + k] * fmaxf(z1[v] + s_b2[32 + k], 0.f);
+        }
+        const float out = b3 + (part + __shfl_xor(part, 32, WAVE));
+        if (half == 0 && c <= LUT_CELLS) {
+            const float f = fminf(fmaxf(out, 0.f), 1.f);
+            const double F = ((double)dense_before(dense, dense_cum, nd, c) + rest * (double)f) * invS;
+            uint32_t q = (uint32_t)fmin(F * 4294967295.0, 4294967295.0);
+            if (c == 0) q = 0;
+            if (c == LUT_CELLS) q = 0xFFFFFFFFu;
+            lut[c] = q;
+        }
     }
 }
 
@@ -1400,18 +1490,13 @@ hipError_t learned_init(void* model, uint64_t seed, bool raw, hipStream_t s) {
     return hipGetLastError();
 }
 
-static size_t mlp_lds() { return (size_t)(HID * HID + 4 * HID + 2 * MLP_T + 2 * MLP_T * (HID + 1)) * 4; }
 
 template <bool MONO>
 static hipError_t mlp_grad_launch(const float* params, const float* x, const float* y,
                                   uint32_t first, uint32_t count, uint32_t stride, uint32_t blocks,
                                   float inv_batch, float* partial, float* grad, hipStream_t s) {
-    // set on every launch: cheap on the host, and right for whichever device is current
-    hipError_t e = hipFuncSetAttribute((const void*)k_mlp_grad<MONO>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)mlp_lds());
-    if (e != hipSuccess) return e;
     const uint32_t per_block = (count + blocks - 1) / blocks;
-    hipLaunchKernelGGL(k_mlp_grad<MONO>, dim3(blocks), dim3(MLP_T), mlp_lds(), s, params, x, y, first,
+    hipLaunchKernelGGL(k_mlp_grad<MONO>, dim3(blocks), dim3(MLP_T), 0, s, params, x, y, first,
                        count, stride, per_block, inv_batch, partial);
     hipLaunchKernelGGL(k_mlp_reduce, dim3((NPARAM + 1 + 255) / 256), dim3(256), 0, s,
                        (const float*)partial, blocks, grad);
@@ -1471,16 +1556,16 @@ hipError_t learned_eval_lut(const float* p, const void* model, uint32_t mode, ui
     const dim3 g(8192), t(256);
     switch (mode) {
         case HUSKY_LEARNED_EQUAL_WIDTH:
-            hipLaunchKernelGGL((k_lut_eval<true, LUT_IDENTITY>), g, t, 0, s, p, h, m.dense, m.dense_cum, lut);
+            hipLaunchKernelGGL((k_lut_eval<LUT_IDENTITY>), g, t, 0, s, h, m.dense, m.dense_cum, lut);
             break;
         case HUSKY_LEARNED_CONSTANT:
-            hipLaunchKernelGGL((k_lut_eval<true, LUT_ZERO>), g, t, 0, s, p, h, m.dense, m.dense_cum, lut);
+            hipLaunchKernelGGL((k_lut_eval<LUT_ZERO>), g, t, 0, s, h, m.dense, m.dense_cum, lut);
             break;
         case HUSKY_LEARNED_UNCONSTRAINED:
-            hipLaunchKernelGGL((k_lut_eval<false, LUT_NET>), g, t, 0, s, p, h, m.dense, m.dense_cum, lut);
+            hipLaunchKernelGGL((k_lut_net<false>), dim3(2048), t, 0, s, p, h, m.dense, m.dense_cum, lut);
             break;
         default:
-            hipLaunchKernelGGL((k_lut_eval<true, LUT_NET>), g, t, 0, s, p, h, m.dense, m.dense_cum, lut);
+            hipLaunchKernelGGL((k_lut_net<true>), dim3(2048), t, 0, s, p, h, m.dense, m.dense_cum, lut);
     }
     const uint32_t n = LUT_CELLS + 1, tiles = (n + LUT_TILE - 1) / LUT_TILE;
     hipLaunchKernelGGL(k_lut_tilemax, dim3(tiles), dim3(256), 0, s, (const uint32_t*)lut, n, tmax);
