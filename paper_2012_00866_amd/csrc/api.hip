@@ -560,15 +560,19 @@ static husky_status sort_common(husky_coder coder, const void* elems, const uint
     // ASCII codes carry the perfect bit (encode.hip): all 64 bits are key
     // bits, and runs of identical short strings are never listed
     const bool perfect = coder == HUSKY_CODER_ASCII7;
+    // one instance: its radix tiles are the string order's, so the encode
+    // kernel reduces each tile's OR / AND as it writes the codes
+    const bool enc_orand = !seg_offsets;
     HUSKY_TRY(launch_encode(coder, elems, offsets, (uint32_t)n, codes, perm, c.at<uint64_t>(c.L.key0),
-                            &c.status->domain_violations, s, nullptr, 0, nullptr, perfect));
+                            &c.status->domain_violations, s, nullptr, 0, nullptr, perfect,
+                            enc_orand ? c.rad.korand : nullptr, (uint32_t)tn.rc.tile()));
     if (seg_offsets)
         HUSKY_TRY(radix_segments_from_offsets(seg_offsets, (uint32_t)n_segs, c.rad, tn.rc, s));
     else
         HUSKY_TRY(radix_segments_single((uint32_t)n, c.rad, tn.rc, s));
     const int end_bit = 64;
     const uint32_t tb = tiles_bound(n, n_segs, tn.rc);
-    HUSKY_TRY(radix_reduce_tiles(codes, tb, c.rad, tn.rc, s));
+    if (!enc_orand) HUSKY_TRY(radix_reduce_tiles(codes, tb, c.rad, tn.rc, s));
     HUSKY_TRY(radix_exec_masks(0, end_bit, (uint32_t)n_segs, tb, c.rad, tn.rc, s, perfect));
     // every pass is launched (no host synchronisation); passes no instance
     // needs end at once

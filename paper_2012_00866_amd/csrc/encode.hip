@@ -43,7 +43,8 @@ __global__ __launch_bounds__(BLOCK) void k_encode(const uint8_t* __restrict__ by
                                                   uint64_t* __restrict__ key0,
                                                   uint32_t* __restrict__ status,
                                                   const uint32_t* __restrict__ sel,
-                                                  uint32_t n_out, BucketArgs bucket, bool perfect) {
+                                                  uint32_t n_out, BucketArgs bucket, bool perfect,
+                                                  uint64_t* __restrict__ korand, uint32_t tile) {
     // bytes in the element buffer (uniform scalar load): the three-word
     // window below is used only where it stays inside the buffer.
     constexpr uint32_t ES = CODER == 1 ? 2u : 1u;  // bytes per element
@@ -140,7 +141,35 @@ __global__ __launch_bounds__(BLOCK) void k_encode(const uint8_t* __restrict__ by
         if (key0) key0[t] = k0;
         return code;
     };
-    if (!LEARNED) {
+    if (!LEARNED && korand) {
+        // workgroup b encodes radix tile b and reduces its codes' OR / AND
+        __shared__ uint64_t s_o[NWAVES], s_a[NWAVES];
+        const uint32_t t0 = blockIdx.x * tile, t1 = min(count, t0 + tile);
+        uint64_t o = 0, a = ~0ull;
+        for (uint32_t t = t0 + threadIdx.x; t < t1; t += BLOCK) {
+            const uint64_t c = encode_one(t);
+            o |= c;
+            a &= c;
+        }
+#pragma unroll
+        for (int d = 32; d >= 1; d >>= 1) {
+            o |= (uint64_t)__shfl_xor((unsigned long long)o, d, WAVE);
+            a &= (uint64_t)__shfl_xor((unsigned long long)a, d, WAVE);
+        }
+        if (lane_id() == 0) {
+            s_o[threadIdx.x / WAVE] = o;
+            s_a[threadIdx.x / WAVE] = a;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            for (int w = 1; w < NWAVES; ++w) {
+                o |= s_o[w];
+                a &= s_a[w];
+            }
+            korand[2 * (size_t)blockIdx.x] = o;
+            korand[2 * (size_t)blockIdx.x + 1] = a;
+        }
+    } else if (!LEARNED) {
         for (uint32_t t = blockIdx.x * BLOCK + threadIdx.x; t < count; t += gridDim.x * BLOCK)
             encode_one(t);
     } else {
@@ -178,17 +207,18 @@ __global__ __launch_bounds__(BLOCK) void k_encode(const uint8_t* __restrict__ by
 hipError_t launch_encode(int coder, const void* elems, const uint64_t* offsets, uint32_t n,
                          uint64_t* codes, uint32_t* idx, uint64_t* key0, uint32_t* status,
                          hipStream_t s, const uint32_t* sel, uint32_t n_out,
-                         const BucketArgs* bucket, bool perfect) {
+                         const BucketArgs* bucket, bool perfect, uint64_t* korand, uint32_t tile) {
     const uint32_t count = sel ? n_out : n;
     if (count == 0) return hipSuccess;
-    const uint32_t per_block = bucket ? BLOCK * LEARNED_K : BLOCK;
+    if (bucket || !tile) korand = nullptr;
+    const uint32_t per_block = korand ? tile : (bucket ? BLOCK * LEARNED_K : BLOCK);
     const uint32_t blocks = (count + per_block - 1) / per_block;
     ProfScope ps(P_ENCODE, s);
     const BucketArgs b = bucket ? *bucket : BucketArgs{};
     const uint8_t* e = (const uint8_t*)elems;
 #define HUSKY_ENC(C, L)                                                                           \
     hipLaunchKernelGGL((k_encode<C, L>), dim3(blocks), dim3(BLOCK), 0, s, e, offsets, n, codes, idx, \
-                       key0, status, sel, n_out, b, perfect && coder == 0)
+                       key0, status, sel, n_out, b, perfect && coder == 0, korand, tile)
     if (coder == CODER_ASCII7) {
         if (bucket) HUSKY_ENC(0, true); else HUSKY_ENC(0, false);
     } else if (coder == CODER_BYTES8) {

@@ -39,10 +39,14 @@ class ProfScope {
 // With perfect (ASCII only), codes are written as code << 1 | f, f = 0 iff
 // the string is at most nine bytes with no NUL (encode.hip).
 struct BucketArgs;
+// With korand (one sort over all n strings): each workgroup encodes one
+// radix tile of `tile` strings and writes its OR and AND of the codes to
+// korand[2t], korand[2t + 1], in place of radix_reduce_tiles.
 hipError_t launch_encode(int coder, const void* elems, const uint64_t* offsets, uint32_t n,
                          uint64_t* codes, uint32_t* idx, uint64_t* key0, uint32_t* status,
                          hipStream_t s, const uint32_t* sel = nullptr, uint32_t n_out = 0,
-                         const BucketArgs* bucket = nullptr, bool perfect = false);
+                         const BucketArgs* bucket = nullptr, bool perfect = false,
+                         uint64_t* korand = nullptr, uint32_t tile = 0);
 
 // ---- radix.hip
 struct RadixConfig {
