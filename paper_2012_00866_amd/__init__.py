@@ -315,12 +315,27 @@ def refine(elems, offsets, sorted_keys, idx, shared_elems=0, coder="ascii7", seg
     return idx
 
 
+def _tuned(tuning, coder, n: int, batched: bool) -> Optional[Tuning]:
+    """tuning="tuned": the autotuner's cached choice for this GPU, coder, size band
+    and form (the library's defaults when nothing is cached); else as given."""
+    if isinstance(tuning, str):
+        if tuning != "tuned":
+            raise ValueError(f"tuning must be a Tuning, None or 'tuned', not {tuning!r}")
+        from .tuner import cached_tuning
+
+        return cached_tuning(coder if isinstance(coder, str) else
+                             {v: k for k, v in CODERS.items()}[int(coder)], n, batched)
+    return tuning
+
+
 def sort(elems, offsets, coder="ascii7", tuning: Optional[Tuning] = None, ws=None, perm=None,
          stream=None, check_status=True):
-    """Algorithm 1 on the GPU: returns perm (int32 storage of uint32[n])."""
+    """Algorithm 1 on the GPU: returns perm (int32 storage of uint32[n]).
+    tuning: None (defaults), a Tuning, or "tuned" (the autotuner's cached choice)."""
     torch = _torch()
     lib = load()
     n = _n_of(offsets)
+    tuning = _tuned(tuning, coder, n, False)
     if ws is None:
         ws = alloc_workspace(n, 1, offsets.device)
     if perm is None:
@@ -364,11 +379,13 @@ def noalloc_status(stream=None) -> dict:
 
 def sort_batched(elems, offsets, seg_offsets, coder="ascii7", tuning: Optional[Tuning] = None,
                  ws=None, perm=None, stream=None, check_status=True):
-    """Batched form: every instance sorted on its own; perm holds global indices."""
+    """Batched form: every instance sorted on its own; perm holds global indices.
+    tuning: None, a Tuning, or "tuned" (the autotuner's cached choice)."""
     torch = _torch()
     lib = load()
     n = _n_of(offsets)
     ns = int(seg_offsets.numel()) - 1
+    tuning = _tuned(tuning, coder, n, True)
     if ws is None:
         ws = alloc_workspace(n, ns, offsets.device)
     if perm is None:

@@ -13,7 +13,16 @@ one workgroup) for a workload already resident on the GPU:
   in order, equal strings in index order -- which pins the unique answer)
   and equals the permutation of the default parameters;
 * results are cached as JSON per (GPU arch, compute units, coder, log2 n band,
-  batched), in $HUSKY_TUNING_CACHE or ~/.cache/husky_mi355x/tuning.json.
+  batched), in $HUSKY_TUNING_CACHE or ~/.cache/husky_mi355x/tuning.json;
+  `sort(..., tuning="tuned")` and `sort_batched(..., tuning="tuned")` use the
+  cached choice (the library's defaults when there is none).
+
+The exactness gate does not need the oracle: husky_check_perm verifies, on
+the device and independently of the sort's kernels, that the output is a
+permutation of every instance, that adjacent strings are in the comparator's
+order and that equal strings keep index order; those three properties
+determine the stable sort uniquely, so a candidate that passes the check
+returns exactly the oracle's permutation.
 """
 
 from __future__ import annotations
@@ -28,9 +37,9 @@ import numpy as np
 
 from . import (Tuning, check_perm, make_tuning, sort, sort_batched, alloc_workspace)
 
-RADIX = [(8, 16), (8, 12), (8, 8), (7, 16), (7, 12), (6, 16)]
+RADIX = [(b, i) for b in (8, 7, 6) for i in (16, 12, 8)]  # every compiled pair
 T_SMALL = [8, 16, 32, 64]
-T_MEDIUM = [256, 1024, 2048, 4096]
+T_MEDIUM = [128, 256, 512, 1024, 2048, 3072, 4096]
 DEFAULT = dict(radix_bits=8, tile_items=16, t_small=64, t_medium=1024)
 
 

@@ -171,3 +171,8 @@ def test_tuner_small(gpu_lib, tmp_path, monkeypatch):
     assert t is not None and t.as_dict()["radix_bits"] == res["tuning"]["radix_bits"]
     perm = _u32(gpu_lib.sort(e, o, "ascii7", tuning=t))
     np.testing.assert_array_equal(perm, oracle.sort(b)[0])
+    # the binding's "tuned" choice reads the same cache entry
+    np.testing.assert_array_equal(_u32(gpu_lib.sort(e, o, "ascii7", tuning="tuned")), perm)
+    assert gpu_lib._tuned("tuned", "ascii7", b.n, False).as_dict() == t.as_dict()
+    # nothing cached for the batched form of this size: the defaults
+    assert gpu_lib._tuned("tuned", "ascii7", b.n, True) is None

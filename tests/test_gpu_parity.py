@@ -122,6 +122,19 @@ def test_sort_threshold_stress(gpu_lib, tuning):
         np.testing.assert_array_equal(_sort_gpu(gpu_lib, b, t), oracle.sort(b)[0])
 
 
+@pytest.mark.parametrize("items", [8, 12, 16])
+def test_sort_tile_edges(gpu_lib, items):
+    # the encode kernel reduces each radix tile's OR / AND itself (one
+    # workgroup per tile): sizes at, just under and just over one, two and
+    # three tiles of every compiled tile size, each checked against the oracle
+    tile = 256 * items
+    t = gpu_lib.make_tuning(tile_items=items)
+    for n in (tile - 1, tile, tile + 1, 2 * tile - 1, 2 * tile + 1, 3 * tile + 7):
+        b = config2(n=n, seed=n)
+        _say("tile edges", items, n)
+        np.testing.assert_array_equal(_sort_gpu(gpu_lib, b, t), oracle.sort(b)[0])
+
+
 def test_sort_empty_and_tiny(gpu_lib):
     for strs in ([b""], [b"b", b"a"], [b"", b""], [b"x"] * 3, [b"ab\0", b"ab", b"ab"]):
         b = from_strings(strs)
