@@ -122,6 +122,43 @@ def test_shared_prefix_beyond_search_span(gpu_lib):
     assert gpu_lib.read_status(ws)["large_rounds"] == 2
 
 
+def _edge_group(coder, seed, n=40_000):
+    """Runs of more than 8,192 equal codes whose members differ only at the
+    common-prefix pass's edges: strings shorter than the coded prefix whose
+    codes tie through zero elements (NUL / 0x00 / U+0000 padding), strings that
+    are prefixes of others, copies, and differences right at the start of the
+    first chunk, at its end and two chunks on."""
+    rng = np.random.default_rng(seed)
+    if coder == "utf16":
+        z, a, b = 0, 0x4E00, 0x4E01
+        head = (a,) * 4
+        pick = [head[:2], head[:2] + (z,), head[:2] + (z, z), head, head + (a,) * 3,
+                head + (a,) * 3 + (b,), head + (a,) * 9, head + (a,) * 9 + (z,), head + (b,)]
+        mk = tuple
+    else:
+        z, a, b = 0, (0xC3 if coder == "bytes8" else ord("q")), (0xFF if coder == "bytes8" else ord("r"))
+        m = 8 if coder == "bytes8" else 9
+        head = bytes([a]) * m
+        pick = [head[:3], head[:3] + b"\0", head[:3] + b"\0\0", head, head + bytes([a]) * 7,
+                head + bytes([a]) * 7 + bytes([b]), head + bytes([a]) * 21, head + bytes([a]) * 21 + b"\0",
+                head + bytes([b])]
+        mk = bytes
+    out = [mk(pick[int(rng.integers(0, len(pick)))]) for _ in range(n)]
+    return from_strings(out, coder)
+
+
+@pytest.mark.parametrize("coder", ["ascii7", "utf16", "bytes8"])
+def test_common_prefix_pass_edges(gpu_lib, coder):
+    b = _edge_group(coder, seed={"ascii7": 5, "utf16": 6, "bytes8": 7}[coder])
+    e, o = gpu_lib.to_device(b)
+    ref = oracle.sort(b)[0]
+    ws = gpu_lib.alloc_workspace(b.n)
+    np.testing.assert_array_equal(_u32(gpu_lib.sort(e, o, coder, ws=ws)), ref)
+    assert gpu_lib.read_status(ws)["unresolved"] == 0
+    ad = _u32(gpu_lib.sort(e, o, coder, tuning=gpu_lib.make_tuning(max_rounds=ADAPTIVE), ws=ws))
+    np.testing.assert_array_equal(ad, ref)
+
+
 def test_default_batched_learned_refine(gpu_lib):
     import torch
 
