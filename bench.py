@@ -143,6 +143,41 @@ def _host_info():
             "ram_gib": round(mem_kb / 2**20, 1)}
 
 
+def _step2_vs_platform(husky, torch, elems, offsets, ws, reps=5):
+    """Step 2 alone (husky_sort_pairs on the codes, 12 bytes per key) against the
+    platform's radix sort (torch.sort, rocPRIM: the same keys with an int64
+    index) on the same codes; HIP events around each sort only."""
+    import numpy as np
+
+    codes, idx = husky.encode(elems, offsets, "ascii7")
+    c2, i2 = torch.empty_like(codes), torch.empty_like(idx)
+    signed = codes ^ torch.tensor(-(1 << 63), dtype=torch.int64, device=codes.device)  # unsigned order
+
+    def timed(prep, run):
+        ms = []
+        for r in range(reps + 1):
+            prep()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            out = run()
+            e1.record()
+            torch.cuda.synchronize()
+            if r:
+                ms.append(e0.elapsed_time(e1))
+        return float(np.median(ms)), out
+
+    def prep():
+        c2.copy_(codes)
+        i2.copy_(idx)
+
+    ours_ms, _ = timed(prep, lambda: husky.sort_pairs(c2, i2, ws=ws))
+    torch_ms, (_, ti) = timed(lambda: None, lambda: torch.sort(signed, stable=True))
+    return {"what": "stable sort of the 2^24 codes with their indices: husky_sort_pairs "
+                    "(u64 code, u32 index) vs torch.sort(stable=True) (rocPRIM, i64 index)",
+            "husky_sort_pairs_ms": round(ours_ms, 4), "torch_sort_ms": round(torch_ms, 4),
+            "identical": bool(torch.equal(ti.to(torch.int32), i2))}
+
+
 def _cpu_baseline(batch, runs=3):
     """The oracle (single-threaded C++) on the whole workload, median of `runs`
     sorts; returns (baseline object, the oracle's permutation)."""
@@ -262,6 +297,8 @@ def main(argv=None):
         husky.sort(elems, offsets, "ascii7", ws=ws, perm=perm, check_status=False)
     kprof = husky.profile_end()
     _progress(f"plain: {(t1 - t0) * 1e3 / args.steps:.3f} ms per sort")
+    step2 = _step2_vs_platform(husky, torch, elems, offsets, ws)
+    _progress(f"step 2 alone: {step2['husky_sort_pairs_ms']} ms, torch.sort {step2['torch_sort_ms']} ms")
 
     ms_per_step = (t1 - t0) * 1e3 / args.steps
     value = n / (ms_per_step / 1e3) / 1e6
@@ -274,6 +311,7 @@ def main(argv=None):
                for k, v in kprof.items() if v[1]}
     # a whole digit pass of the code sort: digit counts + the two scans + the scatter
     passes = kprof["radix_scatter"][1] / ksteps
+    # (the device-wide fix-up's own count and scan launches are a class of their own)
     pass_ms = (kprof["radix_count_scan"][0] + kprof["radix_scatter"][0]) / ksteps / max(passes, 1)
     pass_gbs = algo_bytes / (pass_ms / 1e3) / 1e9 if pass_ms > 0 else 0.0
 
@@ -324,6 +362,7 @@ def main(argv=None):
             "passes_per_step": passes,
         },
         "kernels": kernels,
+        "step2_vs_platform_sort": step2,
         "event_ms_per_step": round(ev0.elapsed_time(ev1) / args.steps, 4),
         "device_check_violations": violations,
     }

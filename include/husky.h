@@ -274,14 +274,16 @@ husky_status husky_check_perm(husky_coder coder, const void* elems, const uint64
  * kernel class c < n_classes, the summed milliseconds ms[c] and the launch
  * count launches[c] (host arrays), then stops profiling.  Classes:
  * 0 encode, 1 radix varying-bit reduction and pass masks, 2 radix digit
- * counts and their scans, 3 radix scatter pass, 4 radix copy-back,
+ * counts and their scans (of the sort of the codes; class 16 for the
+ * device-wide fix-up's), 3 radix scatter pass, 4 radix copy-back,
  * 5 single-tile LDS sort, 6 run detection, 7 wavefront fix-up, 8 workgroup
  * fix-up, 9 device-wide refinement keys, 10 segment setup, 11 radix scatter
  * pass of the device-wide fix-up (class 3 counts only the sort of the
  * codes), 12 learned bucket scatter pass, 13 learned bucket bounds (the
  * learned form's bucket ids are computed by the encode kernel, class 0),
  * 14 LDS-resident fix-up of runs longer than t_medium and at most 8,192,
- * 15 the full stable pass of the lossy-coder sort (husky_fixup_global).
+ * 15 the full stable pass of the lossy-coder sort (husky_fixup_global),
+ * 16 radix digit counts and scans of the device-wide fix-up.
  * Not for use during graph capture.
  * Returns HUSKY_OK or HUSKY_ERR_HIP. */
 void husky_profile_begin(void);

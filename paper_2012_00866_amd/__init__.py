@@ -89,7 +89,7 @@ EXPORTS = ("husky_workspace_bytes", "husky_encode", "husky_sort_pairs", "husky_f
 PROFILE_CLASSES = ("encode", "radix_vary", "radix_count_scan", "radix_scatter", "radix_copy_back",
                    "tile_sort", "runs", "fixup_small", "fixup_medium", "large_keys", "segment_setup",
                    "radix_scatter_fixup", "learned_bucket_scatter", "learned_bucket_bounds",
-                   "fixup_lds", "global_merge")
+                   "fixup_lds", "global_merge", "radix_count_scan_fixup")
 
 # learned form (include/husky.h)
 LEARNED_BUCKETS = 65536

@@ -13,7 +13,8 @@ namespace husky {
 enum ProfClass {
     P_ENCODE = 0, P_VARY = 1, P_COUNT_SCAN = 2, P_SCATTER = 3, P_COPY_BACK = 4, P_TILE_SORT = 5,
     P_RUNS = 6, P_FIX_SMALL = 7, P_FIX_MEDIUM = 8, P_LARGE_KEYS = 9, P_SETUP = 10,
-    P_SCATTER_FIX = 11, P_BUCKET = 12, P_BUCKET_BOUNDS = 13, P_FIX_LDS = 14, P_MERGE = 15, P_NUM = 16
+    P_SCATTER_FIX = 11, P_BUCKET = 12, P_BUCKET_BOUNDS = 13, P_FIX_LDS = 14, P_MERGE = 15,
+    P_COUNT_SCAN_FIX = 16, P_NUM = 17
 };
 bool prof_on();
 class ProfScope {

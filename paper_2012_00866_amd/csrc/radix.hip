@@ -769,7 +769,7 @@ static hipError_t sort_impl(uint64_t* keys, uint32_t* vals, uint64_t* keys_alt,
     for (int p = 0; p < npasses; ++p) {
         if (!((pass_union >> p) & 1u)) continue;
         {
-            ProfScope ps(P_COUNT_SCAN, s);
+            ProfScope ps(pclass == P_SCATTER_FIX ? P_COUNT_SCAN_FIX : P_COUNT_SCAN, s);
             hipLaunchKernelGGL((k_count<BITS, ITEMS, PS>), dim3(sc.grid(max_tiles)), dim3(BLOCK), 0, s, keys,
                                keys_alt, bigs, sc.counters, sc.cnt, p, sc.prog);
             hipLaunchKernelGGL((k_group_scan<BITS, PS>), dim3(sc.grid(max_groups)), dim3(BLOCK), 0, s, bigs,
