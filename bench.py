@@ -220,10 +220,12 @@ def main(argv=None):
     ap.add_argument("--no-batched", action="store_true", help="leave out the batched comparison")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a 256 MiB device copy (calibrates HBM byte counters)")
-    ap.add_argument("--mode", choices=["plain", "batched", "learned", "lossy", "typed"], default="plain",
+    ap.add_argument("--mode", choices=["plain", "batched", "learned", "lossy", "typed", "configs"],
+                    default="plain",
                     help="plain: the metric's workload (with both comparisons); batched or "
                          "learned: only that comparison, printed as its own line; lossy: the "
-                         "mis-coding study; typed: the other object types")
+                         "mis-coding study; typed: the other object types; configs: the plain "
+                         "sort on configs 1 and 3")
     args = ap.parse_args(argv)
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the sort is not "
@@ -257,6 +259,9 @@ def main(argv=None):
         return 0
     if args.mode == "typed":
         print(json.dumps(bench_typed(args)), flush=True)
+        return 0
+    if args.mode == "configs":
+        print(json.dumps(bench_configs(args)), flush=True)
         return 0
     batch = config2(seed=1, n=args.n)
     n = batch.n
@@ -559,6 +564,44 @@ def bench_typed(args):
             _progress(f"typed {t} n={n}: {ms:.3f} ms")
             del r, o, ws, perm, b
     return {"metric": "Mrecords/s sorted (bit-exact), other object types", "rows": rows}
+
+
+def bench_configs(args):
+    """The plain sort on the other string workloads: config 1 (100,000 ASCII strings,
+    the small case) and config 3 (2^23 UTF-16 strings), Mstrings/s with a per-class
+    kernel breakdown; every permutation equal to the oracle's (config 1) or clean
+    under the device check (config 3)."""
+    import numpy as np
+    import torch
+
+    import oracle
+    import paper_2012_00866_amd as husky
+    from workloads import config1, config3
+
+    steps = max(5, min(args.steps, 50))
+    rows = {}
+    for name, make in (("config1", config1), ("config3", config3)):
+        b = make(seed=1)
+        e, o = husky.to_device(b)
+        ws = husky.alloc_workspace(b.n)
+        perm = torch.empty(b.n, dtype=torch.int32, device="cuda")
+        f = lambda: husky.sort(e, o, b.coder, ws=ws, perm=perm, check_status=False)
+        ms = _time(f, steps, 2)
+        husky.profile_begin()
+        f()
+        prof = husky.profile_end()
+        viol = husky.check_perm(e, o, perm, b.coder)
+        assert viol == 0, f"{name}: the device check found {viol} violations"
+        ok = None
+        if b.n <= 200_000:
+            ok = bool(np.array_equal(perm.cpu().numpy().view(np.uint32), oracle.sort(b)[0]))
+            assert ok, f"{name} differs from the oracle"
+        rows[name] = {"n": b.n, "coder": b.coder, "ms": round(ms, 4), "mstrings_s": round(b.n / ms / 1e3, 1),
+                      "launches": sum(v[1] for v in prof.values()), "kernels": _kernels(prof, 1),
+                      "oracle_identical": ok, "device_check_violations": viol}
+        _progress(f"{name}: {ms:.4f} ms")
+        del e, o, ws, perm, b
+    return {"metric": "Mstrings/s sorted (bit-exact), plain sort on configs 1 and 3", "rows": rows}
 
 
 def _kernels(prof, steps):
