@@ -425,7 +425,6 @@ def bench_batched(args):
     seg = torch.from_numpy(batch.seg_offsets.view(np.int64)).cuda()
     ws = husky.alloc_workspace(n, S)
     perm = torch.empty(n, dtype=torch.int32, device="cuda")
-    max_len = int(np.diff(batch.offsets).max())
     steps = max(3, min(args.steps, 10))
     _progress(f"config 4: {n} strings in {S} instances resident ({t_gen:.1f} s to generate)")
 
@@ -439,17 +438,20 @@ def bench_batched(args):
     tuned = husky.make_tuning(**res["tuning"])
     ms_tuned = _time(lambda: batched(tuned), steps, 1)
     assert torch.equal(perm, ref)
-    # graph: fixed rounds, captured once, replayed
-    fixed = husky.make_tuning(**res["tuning"], max_rounds=husky.rounds_for(max_len))
+    husky.profile_begin()
+    batched(tuned)
+    kprof = husky.profile_end()
+    # graph: the same call (it never waits for the host), captured once, replayed
     s = torch.cuda.Stream()
     s.wait_stream(torch.cuda.current_stream())
     with torch.cuda.stream(s):
-        batched(fixed)
+        batched(tuned)
     torch.cuda.current_stream().wait_stream(s)
     torch.cuda.synchronize()
     g = torch.cuda.CUDAGraph()
     with torch.cuda.graph(g):
-        batched(fixed)
+        batched(tuned)
+    perm.fill_(-1)
     ms_graph = _time(g.replay, steps, 1)
     assert torch.equal(perm, ref) and husky.read_status(ws)["unresolved"] == 0
     del g
@@ -481,6 +483,7 @@ def bench_batched(args):
                      "batched_graph_replay": round(ms_graph, 3),
                      "loop_of_plain_sorts": round(ms_loop, 3)},
         "speedup_batched_vs_loop": round(ms_loop / ms_tuned, 2),
+        "kernels_tuned": _kernels(kprof, 1),
         "identical": True,
         "device_check_violations": 0,
         "tuning": res["tuning"],
