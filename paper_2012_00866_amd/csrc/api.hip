@@ -120,14 +120,20 @@ Layout make_layout(uint64_t n, uint64_t n_segs, bool learned = false) {
 // [88, 92) the two device-wide lists: item count, items longer than one
 // tile, their tiles, tiles of all items; [92, 96) LDS-tier class counts;
 // [96, 102) learned-form lists; [104, 108) work counters of the LDS tier;
-// [108, 112) learned-form buckets per size class off the packed path
+// [108, 112) learned-form buckets per size class off the packed path;
+// [112, 118) the small, medium and four LDS-class counts as run detection
+// left them before the device-wide round; [120, 124) work counters of the
+// LDS tier's launch after that round
 constexpr int CNT_RUNS = 64, CNT_SMALL = 80, CNT_MEDIUM = 81, CNT_LARGE_A = 84, CNT_LARGE_B = 88,
               CNT_LDS = 92,
               CNT_SCAN = 96,  // learned form: buckets on the run-detection list
               CNT_BIG = 97,   // learned form: buckets for the multi-tile radix passes
               CNT_CLASS = 98, // learned form: buckets per LDS size class (four)
               CNT_LDS_QUEUE = 104,  // LDS fix-up tier: work counters of its size classes (four)
-              CNT_FALLBACK = 108;   // learned form: buckets per class off the packed path (four)
+              CNT_FALLBACK = 108,   // learned form: buckets per class off the packed path (four)
+              CNT_SNAP = 112,       // tier counts before the device-wide round (six)
+              CNT_LDS_QUEUE2 = 120; // LDS tier after the round: work counters (four)
+static_assert(CNT_LDS == CNT_SMALL + 12 && CNT_MEDIUM == CNT_SMALL + 1, "tier count slots");
 
 struct Ctx {
     Layout L;
@@ -228,6 +234,14 @@ constexpr size_t STATUS_WORDS = sizeof(husky_device_status) / sizeof(uint32_t);
 
 __global__ void k_set_u32(uint32_t* p, uint32_t v) { *p = v; }
 __global__ void k_copy_u32(uint32_t* dst, const uint32_t* src) { *dst = *src; }
+// snap[0..6) = the small, medium and four LDS-class tier counts
+__global__ void k_snap_tiers(uint32_t* __restrict__ snap, const uint32_t* __restrict__ small_count,
+                             const uint32_t* __restrict__ medium_count,
+                             const uint32_t* __restrict__ lds_count) {
+    snap[0] = *small_count;
+    snap[1] = *medium_count;
+    for (int k = 0; k < 4; ++k) snap[2 + k] = lds_count[k];
+}
 
 husky_status hip_status(hipError_t e) { return e == hipSuccess ? HUSKY_OK : HUSKY_ERR_HIP; }
 
@@ -347,6 +361,37 @@ husky_status run_fixup(Ctx& c, const Tune& tn, int coder, uint32_t origin, const
     const uint32_t big_min = c.tiers.lds_max ? c.tiers.lds_max : tn.t_medium;
     const uint32_t nl_bound = std::min<uint32_t>(c.L.large_cap, (uint32_t)(n / (big_min + 1) + 1));
     const uint32_t tiles_bound_l = (uint32_t)(n / tn.rc.tile()) + nl_bound + 1;
+    // Default rounds with side streams: the run-local tiers start on the runs
+    // run detection listed (counts snapshotted first) beside the device-wide
+    // round, which runs on a side stream; the runs the round splits off are
+    // appended past the snapshot and taken by a second launch of each tier
+    // after it.  The two touch disjoint positions and buffers (the round: its
+    // groups' indices, the code buffers, the radix and run-detection scratch;
+    // the tiers: their runs' indices; both only read the first keys).
+    const SideStreams* ss = nullptr;
+    hipStream_t rs = s;  // the rounds' stream
+    uint32_t* snap = c.counters + CNT_SNAP;
+    TierLists after = c.tiers;  // the tiers' launch after an overlapped round
+    if (!adaptive && !bounded && fixed_rounds > 0 && n >= SIDE_MIN_N) {
+        hipLaunchKernelGGL(k_snap_tiers, dim3(1), dim3(1), 0, s, snap, c.tiers.small_count,
+                           c.tiers.medium_count, c.tiers.lds_count);
+        HUSKY_TRY(hipGetLastError());
+        HUSKY_TRY(side_fork(s, n, &ss));
+        if (ss) {
+            TierLists before = c.tiers;
+            before.small_count = snap;
+            before.medium_count = snap + 1;
+            before.lds_count = snap + 2;
+            after.small_first = snap;
+            after.medium_first = snap + 1;
+            after.lds_first = snap + 2;
+            after.lds_queue = c.counters + CNT_LDS_QUEUE2;
+            HUSKY_TRY(fixup_medium(fa, before, tn.t_medium, ss->st[0]));
+            HUSKY_TRY(fixup_small(fa, before, tn.t_small, ss->st[1]));
+            HUSKY_TRY(fixup_lds(fa, before, tn.t_medium, s));
+            rs = ss->st[1];
+        }
+    }
     if (!adaptive) c.rad.grid_cap = ROUND_GRID_CAP;
     for (;;) {
         uint32_t nl, all_tiles, big_tiles;
@@ -364,31 +409,31 @@ husky_status run_fixup(Ctx& c, const Tune& tn, int coder, uint32_t origin, const
             all_tiles = st[3] + 1;
             big_tiles = st[1] ? st[2] + 1 : 0;
         }
-        HUSKY_TRY(radix_segments_from_items(cur, cur_cnt, c.L.large_cap, c.rad, tn.rc, s));
-        HUSKY_TRY(fixup_large_lcp(fa, cur, c.rad, tn.rc, all_tiles, s));
+        HUSKY_TRY(radix_segments_from_items(cur, cur_cnt, c.L.large_cap, c.rad, tn.rc, rs));
+        HUSKY_TRY(fixup_large_lcp(fa, cur, c.rad, tn.rc, all_tiles, rs));
         // every item is longer than the LDS tier's limit, so longer than a
         // radix tile: the key tiles are the sort's tiles, and the key kernel
         // writes their OR / AND itself
         const bool tile_orand = big_min >= (uint32_t)tn.rc.tile();
-        HUSKY_TRY(fixup_large_keys(fa, cur, c.rad, tn.rc, all_tiles, keys, s, tile_orand));
+        HUSKY_TRY(fixup_large_keys(fa, cur, c.rad, tn.rc, all_tiles, keys, rs, tile_orand));
         uint32_t pass_union = ~0u;
         if (big_tiles) {
-            if (!tile_orand) HUSKY_TRY(radix_reduce_tiles(keys, big_tiles, c.rad, tn.rc, s));
-            HUSKY_TRY(radix_exec_masks(0, 64, nl, big_tiles, c.rad, tn.rc, s));
+            if (!tile_orand) HUSKY_TRY(radix_reduce_tiles(keys, big_tiles, c.rad, tn.rc, rs));
+            HUSKY_TRY(radix_exec_masks(0, 64, nl, big_tiles, c.rad, tn.rc, rs));
             // the digit passes any group needs: refinement keys hold long
             // constant stretches, so passes nobody runs are not launched
-            if (adaptive) HUSKY_TRY(read_u32(c.counters + C_EXEC_UNION, &pass_union, s));
+            if (adaptive) HUSKY_TRY(read_u32(c.counters + C_EXEC_UNION, &pass_union, rs));
         }
         // every device-wide item spans several tiles: no single-tile segments
         HUSKY_TRY(radix_sort_segments(keys, idx, keys_alt, c.at<uint32_t>(c.L.idx_b), 0, 64, nl,
-                                      big_tiles, pass_union, c.rad, tn.rc, P_SCATTER_FIX, s,
+                                      big_tiles, pass_union, c.rad, tn.rc, P_SCATTER_FIX, rs,
                                       big_min < (uint32_t)tn.rc.tile()));
         TierLists t2 = c.tiers;
         t2.large = nxt;
         t2.large_count = nxt_cnt;
-        HUSKY_TRY(zero_u32(nxt_cnt, 4, s));
+        HUSKY_TRY(zero_u32(nxt_cnt, 4, rs));
         HUSKY_TRY(find_runs(keys, c.rad, tn.rc, all_tiles, ek, true, cur, c.runs, t2,
-                            tn.t_small, tn.t_medium, origin, s));
+                            tn.t_small, tn.t_medium, origin, rs));
         std::swap(cur, nxt);
         std::swap(cur_cnt, nxt_cnt);
         ++rounds;
@@ -398,14 +443,22 @@ husky_status run_fixup(Ctx& c, const Tune& tn, int coder, uint32_t origin, const
         hipLaunchKernelGGL(k_copy_u32, dim3(1), dim3(1), 0, s, &c.status->unresolved, cur_cnt);
         HUSKY_TRY(hipGetLastError());
     }
-    // the three run-local tiers: workgroup and wavefront tiers on the side
-    // streams (when there are any), the LDS tier on the caller's stream
-    const SideStreams* ss = nullptr;
-    HUSKY_TRY(side_fork(s, n, &ss));
-    HUSKY_TRY(fixup_medium(fa, c.tiers, tn.t_medium, ss ? ss->st[0] : s));
-    HUSKY_TRY(fixup_small(fa, c.tiers, tn.t_small, ss ? ss->st[1] : s));
-    HUSKY_TRY(fixup_lds(fa, c.tiers, tn.t_medium, s));
-    HUSKY_TRY(side_join(s, ss));
+    if (ss) {
+        // the runs the round split off, after it on its stream
+        HUSKY_TRY(fixup_medium(fa, after, tn.t_medium, rs));
+        HUSKY_TRY(fixup_small(fa, after, tn.t_small, rs));
+        HUSKY_TRY(fixup_lds(fa, after, tn.t_medium, rs));
+        HUSKY_TRY(side_join(s, ss));
+    } else {
+        // the three run-local tiers: workgroup and wavefront tiers on the
+        // side streams (when there are any), the LDS tier on the caller's
+        // stream
+        HUSKY_TRY(side_fork(s, n, &ss));
+        HUSKY_TRY(fixup_medium(fa, c.tiers, tn.t_medium, ss ? ss->st[0] : s));
+        HUSKY_TRY(fixup_small(fa, c.tiers, tn.t_small, ss ? ss->st[1] : s));
+        HUSKY_TRY(fixup_lds(fa, c.tiers, tn.t_medium, s));
+        HUSKY_TRY(side_join(s, ss));
+    }
     if (!adaptive && !bounded) {
         // groups still tied after the default rounds: every remaining round
         // in one workgroup per group (after the run-local tiers, whose first

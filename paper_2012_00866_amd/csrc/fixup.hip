@@ -88,9 +88,10 @@ __global__ __launch_bounds__(BLOCK) void k_fix_small(const RunItem* __restrict__
                                                      const uint64_t* __restrict__ offsets,
                                                      uint32_t n, uint32_t* __restrict__ idx,
                                                      const uint64_t* __restrict__ key0,
-                                                     uint32_t origin) {
+                                                     uint32_t origin, const uint32_t* __restrict__ from) {
     const uint64_t total_bytes = offsets[n] * (CODER == 0 ? 1u : 2u);
     const uint32_t n_items = min(*count, cap);
+    const uint32_t it0 = from ? min(*from, n_items) : 0u;
     const uint32_t lane = lane_id();
     const uint32_t nw = gridDim.x * NWAVES;
     // Software pipelined over the wavefront's runs: the next run's item is
@@ -98,7 +99,7 @@ __global__ __launch_bounds__(BLOCK) void k_fix_small(const RunItem* __restrict__
     // string indices while this run is ranked, so a run costs about one
     // dependent load instead of three.  Runs are disjoint, so reading the
     // next run's indices before this run's are written back is safe.
-    uint32_t it = blockIdx.x * NWAVES + threadIdx.x / WAVE;
+    uint32_t it = it0 + blockIdx.x * NWAVES + threadIdx.x / WAVE;
     RunItem r{0, 0, 0, 0};
     uint32_t member = 0;
     if (it < n_items) {
@@ -186,13 +187,14 @@ __global__ __launch_bounds__(BLOCK) void k_fix_medium(const RunItem* __restrict_
                                                       const uint64_t* __restrict__ offsets,
                                                       uint32_t n, uint32_t* __restrict__ idx,
                                                       const uint64_t* __restrict__ key0,
-                                                      uint32_t lmin, uint32_t lmax, uint32_t origin) {
+                                                      uint32_t lmin, uint32_t lmax, uint32_t origin,
+                                                      const uint32_t* __restrict__ from) {
     const uint64_t total_bytes = offsets[n] * (CODER == 0 ? 1u : 2u);
     extern __shared__ __align__(16) uint8_t lds_raw[];
     MediumLds<MAXL>& S = *reinterpret_cast<MediumLds<MAXL>*>(lds_raw);
     const uint32_t n_items = min(*count, cap);
     const uint32_t tid = threadIdx.x;
-    for (uint32_t it = blockIdx.x; it < n_items; it += gridDim.x) {
+    for (uint32_t it = (from ? min(*from, n_items) : 0u) + blockIdx.x; it < n_items; it += gridDim.x) {
         const RunItem r = items[it];
         const uint32_t L = r.len;
         if (L <= lmin || L > lmax || L > (uint32_t)MAXL) continue;  // another size class's launch
@@ -326,7 +328,8 @@ __global__ __launch_bounds__(NW * WAVE) void k_fix_lds(const RunItem* __restrict
                                                    const uint64_t* __restrict__ offsets, uint32_t n,
                                                    uint32_t* __restrict__ idx,
                                                    const uint64_t* __restrict__ key0,
-                                                   uint32_t* __restrict__ queue, uint32_t origin) {
+                                                   uint32_t* __restrict__ queue, uint32_t origin,
+                                                   const uint32_t* __restrict__ from) {
     constexpr uint32_t NT = NW * WAVE;
     constexpr uint32_t TILE = NT * ITEMS;
     static_assert(TILE <= 32768, "slots and group starts fit 15 bits");
@@ -345,6 +348,7 @@ __global__ __launch_bounds__(NW * WAVE) void k_fix_lds(const RunItem* __restrict
     uint32_t* s_k32 = reinterpret_cast<uint32_t*>(s_k);  // scratch while keys sit in registers
     const uint64_t total_bytes = offsets[n] * (CODER == 0 ? 1u : 2u);
     const uint32_t n_items = min(*count, cap);
+    const uint32_t it0 = from ? min(*from, n_items) : 0u;
     const uint32_t tid = threadIdx.x, w = tid / WAVE, lane = lane_id();
     auto posof = [&](int i) { return w * WAVE * ITEMS + i * WAVE + lane; };
     auto key_of = [&](uint32_t m, uint32_t round) -> uint64_t {
@@ -388,9 +392,9 @@ __global__ __launch_bounds__(NW * WAVE) void k_fix_lds(const RunItem* __restrict
     // workgroup b takes run b first, then runs past the grid one at a time
     // through a counter, so that workgroups finishing early take more of them
     for (bool first = true;; first = false) {
-        uint32_t it = blockIdx.x;
+        uint32_t it = it0 + blockIdx.x;
         if (!first) {
-            if (tid == 0) s_next = gridDim.x + atomicAdd(queue, 1u);
+            if (tid == 0) s_next = it0 + gridDim.x + atomicAdd(queue, 1u);
             __syncthreads();
             it = s_next;
             __syncthreads();
@@ -1082,11 +1086,11 @@ hipError_t fixup_small(const FixupArgs& a, const TierLists& tl, uint32_t, hipStr
     if (a.coder == 0)
         hipLaunchKernelGGL(k_fix_small<0>, dim3(blocks), dim3(BLOCK), 0, s, tl.small, tl.small_count,
                            tl.small_cap, (const uint8_t*)a.elems, a.offsets, a.n, a.idx, a.key0,
-                           a.origin);
+                           a.origin, tl.small_first);
     else
         hipLaunchKernelGGL(k_fix_small<1>, dim3(blocks), dim3(BLOCK), 0, s, tl.small, tl.small_count,
                            tl.small_cap, (const uint8_t*)a.elems, a.offsets, a.n, a.idx, a.key0,
-                           a.origin);
+                           a.origin, tl.small_first);
     return hipGetLastError();
 }
 
@@ -1106,7 +1110,7 @@ static hipError_t medium_impl(const FixupArgs& a, const TierLists& tl, uint32_t 
     ProfScope ps(P_FIX_MEDIUM, s);
     hipLaunchKernelGGL((k_fix_medium<CODER, MAXL>), dim3(blocks), dim3(BLOCK), lds, s, tl.medium,
                        tl.medium_count, tl.medium_cap, (const uint8_t*)a.elems, a.offsets, a.n,
-                       a.idx, a.key0, lmin, lmax, a.origin);
+                       a.idx, a.key0, lmin, lmax, a.origin, tl.medium_first);
     return hipGetLastError();
 }
 
@@ -1140,7 +1144,8 @@ static hipError_t lds_classes(const FixupArgs& a, const TierLists& tl, uint32_t 
     static_assert(NW * WAVE * I == lds_class_max(C), "class tile");                                \
     hipLaunchKernelGGL((k_fix_lds<CODER, I, NW>), dim3(cus * PER_CU), dim3(NW * WAVE), 0, s,        \
                        tl.lds[C], tl.lds_count + C, tl.lds_cap[C], (const uint8_t*)a.elems, a.offsets, \
-                       a.n, a.idx, a.key0, tl.lds_queue + C, a.origin)
+                       a.n, a.idx, a.key0, tl.lds_queue + C, a.origin,                             \
+                       tl.lds_first ? tl.lds_first + C : nullptr)
     if (t_medium < lds_class_max(0)) HUSKY_FL(12, 4, 4, 0);
     if (t_medium < lds_class_max(1)) HUSKY_FL(16, 4, 3, 1);
     HUSKY_FL(12, 8, 2, 2);

@@ -145,6 +145,11 @@ struct TierLists {
     uint32_t small_cap, medium_cap, large_cap;
     uint32_t lds_cap[4];
     uint32_t lds_max;  // 0: no LDS tier (those runs go device-wide)
+    // First list entry a tier launch takes (device words; null: 0): a launch
+    // after the device-wide round takes only the runs that round appended.
+    const uint32_t* small_first = nullptr;
+    const uint32_t* medium_first = nullptr;
+    const uint32_t* lds_first = nullptr;  // [4]
 };
 
 // Find runs (length >= 2) of equal keys inside every segment of sc; when
