@@ -54,8 +54,9 @@
  * No call synchronizes `stream` with the host, except husky_learned_fit
  * (once, to size its training loop) and the sorts when a caller asks for
  * adaptive refinement rounds (husky_tuning.max_rounds).
- * Side streams.  For 2^21 strings or more, parts of Step 3 (and of the
- * learned form's bucket sort) that touch disjoint data run on two streams
+ * Side streams.  For 2^21 strings or more, parts of Step 3 (the run-local
+ * tiers and, beside them, the device-wide round; and parts of the learned
+ * form's bucket sort) that touch disjoint data run on two streams
  * the library creates once per device (default priority, kept until the
  * process ends), forked from and joined back into `stream` through events,
  * so the call still behaves as work enqueued on `stream` alone.  They are
