@@ -26,6 +26,9 @@ constexpr uint32_t MAX_T_SMALL = 64;
 // grid of their launches (a multiple of 8: the kernels walk their work units).
 constexpr uint32_t DEFAULT_ROUNDS = 1;
 constexpr uint32_t ROUND_GRID_CAP = 2048;
+// Compute units the LDS tier's largest size class leaves to the device-wide
+// round running beside it (four per XCD).
+constexpr uint32_t ROUND_SPARE_CUS = 32;
 
 size_t align_up(size_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
 
@@ -388,7 +391,9 @@ husky_status run_fixup(Ctx& c, const Tune& tn, int coder, uint32_t origin, const
             after.lds_queue = c.counters + CNT_LDS_QUEUE2;
             HUSKY_TRY(fixup_medium(fa, before, tn.t_medium, ss->st[0]));
             HUSKY_TRY(fixup_small(fa, before, tn.t_small, ss->st[1]));
-            HUSKY_TRY(fixup_lds(fa, before, tn.t_medium, s));
+            // the round's launches would otherwise wait for the largest class,
+            // whose workgroups each hold a compute unit
+            HUSKY_TRY(fixup_lds(fa, before, tn.t_medium, s, ROUND_SPARE_CUS));
             rs = ss->st[1];
         }
     }

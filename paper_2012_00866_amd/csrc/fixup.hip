@@ -1135,7 +1135,7 @@ hipError_t fixup_medium(const FixupArgs& a, const TierLists& tl, uint32_t t_medi
 // workgroups share a CU.
 template <int CODER>
 static hipError_t lds_classes(const FixupArgs& a, const TierLists& tl, uint32_t t_medium,
-                              hipStream_t s) {
+                              hipStream_t s, uint32_t spare_cus) {
     const uint32_t cus = persistent_blocks();
     ProfScope ps(P_FIX_LDS, s);
     hipError_t e = zero_u32(tl.lds_queue, 4, s);
@@ -1149,14 +1149,22 @@ static hipError_t lds_classes(const FixupArgs& a, const TierLists& tl, uint32_t 
     if (t_medium < lds_class_max(0)) HUSKY_FL(12, 4, 4, 0);
     if (t_medium < lds_class_max(1)) HUSKY_FL(16, 4, 3, 1);
     HUSKY_FL(12, 8, 2, 2);
-    HUSKY_FL(16, 8, 1, 3);
+    // the largest class takes a whole compute unit per workgroup: it leaves
+    // `spare_cus` of them to work running beside it on other streams
+    const uint32_t cus3 = cus > spare_cus + 8 ? cus - spare_cus : cus;
+    hipLaunchKernelGGL((k_fix_lds<CODER, 16, 8>), dim3(cus3), dim3(8 * WAVE), 0, s, tl.lds[3],
+                       tl.lds_count + 3, tl.lds_cap[3], (const uint8_t*)a.elems, a.offsets, a.n, a.idx,
+                       a.key0, tl.lds_queue + 3, a.origin, tl.lds_first ? tl.lds_first + 3 : nullptr);
+    static_assert(8 * WAVE * 16 == lds_class_max(3), "class tile");
 #undef HUSKY_FL
     return hipGetLastError();
 }
 
-hipError_t fixup_lds(const FixupArgs& a, const TierLists& tl, uint32_t t_medium, hipStream_t s) {
+hipError_t fixup_lds(const FixupArgs& a, const TierLists& tl, uint32_t t_medium, hipStream_t s,
+                     uint32_t spare_cus) {
     if (!tl.lds_max) return hipSuccess;
-    return a.coder == 0 ? lds_classes<0>(a, tl, t_medium, s) : lds_classes<1>(a, tl, t_medium, s);
+    return a.coder == 0 ? lds_classes<0>(a, tl, t_medium, s, spare_cus)
+                        : lds_classes<1>(a, tl, t_medium, s, spare_cus);
 }
 
 hipError_t fixup_large_keys(const FixupArgs& a, const RunItem* items, const RadixScratch& seg,

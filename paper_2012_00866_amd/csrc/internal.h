@@ -189,7 +189,9 @@ hipError_t fixup_medium(const FixupArgs& a, const TierLists& tl, uint32_t t_medi
                         hipStream_t s);
 // Runs of t_medium < len <= LDS_RUN_MAX, every round inside one workgroup.
 constexpr uint32_t LDS_RUN_MAX = 8192;
-hipError_t fixup_lds(const FixupArgs& a, const TierLists& tl, uint32_t t_medium, hipStream_t s);
+// spare_cus: compute units the largest size class leaves to concurrent work.
+hipError_t fixup_lds(const FixupArgs& a, const TierLists& tl, uint32_t t_medium, hipStream_t s,
+                     uint32_t spare_cus = 0);
 // Device-wide tier, before the keys of a round: the position every group's
 // members first differ at (RunItem::lcp), so that the keys skip the chunks
 // all of them share.
