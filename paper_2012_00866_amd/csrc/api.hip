@@ -41,7 +41,7 @@ constexpr uint32_t LEARN_MAX_BLOCKS = 256;
 // training scratch; its fit borrows the sort's regions for the sample (see
 // husky_learned_fit).
 struct Layout {
-    size_t status, counters, codes_a, codes_b, idx_b, key0, segs, bigs, korand, segvary, prog, binstart,
+    size_t status, counters, codes_a, codes_b, idx_b, key0, segs, bigs, korand, segvary, prog, dig, binstart,
         cnt, gtot,
         tile_counts, run_start, run_end, small, medium, large_a, large_b, lds, bid, bseg, k0a, k0b, scan,
         biglist, classes, fallback, lpartial, lgrad, ltmax, total;
@@ -82,6 +82,7 @@ Layout make_layout(uint64_t n, uint64_t n_segs, bool learned = false) {
     L.korand = take((size_t)L.big_tile_cap * 16);
     L.segvary = take((size_t)L.big_cap * 8);
     L.prog = take((size_t)MAX_PASSES * PROG_WORDS * 4);
+    L.dig = take(n);
     L.binstart = take((size_t)L.big_cap * 256 * 4);
     L.cnt = take((size_t)L.big_tile_cap * 256 * 4);
     L.gtot = take((size_t)L.group_cap * 256 * 4);
@@ -163,6 +164,7 @@ Ctx make_ctx(void* ws, uint64_t n, uint64_t n_segs, bool learned = false) {
     c.rad.korand = c.at<uint64_t>(c.L.korand);
     c.rad.segvary = c.at<uint64_t>(c.L.segvary);
     c.rad.prog = c.at<uint32_t>(c.L.prog);
+    c.rad.dig = c.at<uint8_t>(c.L.dig);
     c.rad.binstart = c.at<uint32_t>(c.L.binstart);
     c.rad.cnt = c.at<uint32_t>(c.L.cnt);
     c.rad.gtot = c.at<uint32_t>(c.L.gtot);
@@ -633,7 +635,9 @@ static husky_status sort_common(husky_coder coder, const void* elems, const uint
     if (!enc_orand) HUSKY_TRY(radix_reduce_tiles(codes, tb, c.rad, tn.rc, s));
     HUSKY_TRY(radix_exec_masks(0, end_bit, (uint32_t)n_segs, tb, c.rad, tn.rc, s, perfect));
     // every pass is launched (no host synchronisation); passes no instance
-    // needs end at once
+    // needs end at once.  The values are string indices (as in the
+    // device-wide fix-up's sorts after it).
+    c.rad.dig_in_vals = n <= DIG_IN_VALS_MAX;
     HUSKY_TRY(radix_sort_segments(codes, perm, codes_b, c.at<uint32_t>(c.L.idx_b), 0, end_bit,
                                   (uint32_t)n_segs, tb, ~0u, c.rad, tn.rc, P_SCATTER, s));
     // the sorted codes are not needed once the runs are listed, so the
@@ -1030,6 +1034,7 @@ husky_status husky_sort_learned(husky_coder coder, const void* elems, const uint
     const uint32_t tb = tiles_bound(n, B, tn.rc);
     HUSKY_TRY(radix_reduce_tiles(codes, tb, c.rad, tn.rc, s));
     HUSKY_TRY(radix_exec_masks(0, end_bit, B, tb, c.rad, tn.rc, s));
+    c.rad.dig_in_vals = n <= DIG_IN_VALS_MAX;  // the values are string indices
     HUSKY_TRY(radix_sort_segments(codes, perm, codes_b, idx_b, 0, end_bit, B, tb, ~0u, c.rad, tn.rc,
                                   P_SCATTER, s, false));
     HUSKY_TRY(side_join(s, ss));

@@ -67,6 +67,15 @@ struct RadixScratch {
     uint32_t* counters;    // [64]: tile and segment totals (see common.h)
     uint64_t* segvary;     // [big_cap] bits that vary inside each big segment
     uint32_t* prog;        // [MAX_PASSES * PROG_WORDS] digit programs (common.h)
+    // [n] per key position, the digit the key there takes in its segment's
+    // next pass, written by the scatter that moved it there; the count
+    // kernel of every pass but a segment's first reads these bytes instead
+    // of the 8-byte keys (nullptr: it always reads the keys)
+    uint8_t* dig = nullptr;
+    // Set by callers whose values (string indices) and positions are below
+    // 2^24: the next digit then rides in each value's top byte instead of in
+    // dig, which spares the scatter a third store per key.
+    bool dig_in_vals = false;
     uint32_t seg_cap, big_cap, big_tile_cap, group_cap;
     // Largest grid of a launch sized from a host bound (a multiple of 8;
     // ~0u: none): the kernels walk their work units (HUSKY_UNITS), so a
@@ -74,6 +83,9 @@ struct RadixScratch {
     uint32_t grid_cap = ~0u;
     uint32_t grid(uint32_t bound) const { return bound < grid_cap ? bound : grid_cap; }
 };
+
+// Largest n whose values and positions leave a value's top byte free.
+constexpr uint64_t DIG_IN_VALS_MAX = 1ull << 24;
 
 // Build segment descriptors from uint64 string offsets (n_segs + 1 entries).
 hipError_t radix_segments_from_offsets(const uint64_t* seg_offsets, uint32_t n_segs,

@@ -27,12 +27,15 @@
 //    that vary in any big segment, and a pass that takes no bit varying
 //    inside a segment is skipped for it.  Every remaining pass is
 //    reduce-then-scan with no dependency chain between tiles:
-//      k_count      digit counts of every tile,
+//      k_count      digit counts of every tile (a segment's first pass
+//                   reads the keys, every later pass one byte per key),
 //      k_group_scan exclusive scan of the counts over groups of 64 tiles,
 //      k_seg_scan   scan over a segment's groups, and the digit starts,
 //      k_scatter    every tile ranks its keys with wavefront ballots, adds
 //                   its offsets and scatters through LDS so that
-//                   neighbouring lanes write neighbouring addresses.
+//                   neighbouring lanes write neighbouring addresses; beside
+//                   each key it writes the key's digit of the next pass,
+//                   which is that pass's count input.
 //    A decoupled look-back (one kernel per pass) would save the count pass's
 //    read, but its chain of per-tile flags and its per-tile ticket atomic
 //    cost more than that read on this GPU.
@@ -401,14 +404,24 @@ __device__ __forceinline__ bool pass_runs(const BigDesc& B, int pass, bool& flip
     return true;
 }
 
-// Digit counts of one tile -> cnt[tile][digit].
+// Where a pass finds the digits the previous scatter left (see k_scatter).
+enum : int { DIG_NONE = 0, DIG_BYTES = 1, DIG_IN_VALS = 2 };
+constexpr uint32_t VAL_MASK = 0x00FFFFFFu;
+
+// Digit counts of one tile -> cnt[tile][digit].  After a segment's first
+// pass the digits come from what the previous scatter left: one byte per
+// key (DIG_BYTES) or the values' top bytes (DIG_IN_VALS), instead of the
+// 8-byte keys.
 template <int BITS, int ITEMS, bool PS>
 __global__ __launch_bounds__(BLOCK) void k_count(const uint64_t* __restrict__ keysA,
                                                  const uint64_t* __restrict__ keysB,
+                                                 const uint32_t* __restrict__ valsA,
+                                                 const uint32_t* __restrict__ valsB,
                                                  const BigDesc* __restrict__ bigs,
                                                  const uint32_t* __restrict__ counters,
                                                  uint32_t* __restrict__ cnt, int pass,
-                                                 const uint32_t* __restrict__ prog) {
+                                                 const uint32_t* __restrict__ prog,
+                                                 const uint8_t* __restrict__ dig, int dmode) {
     static_assert(BITS <= 8, "cnt holds 256 digits per tile");
     constexpr uint32_t TILE = BLOCK * ITEMS;
     __shared__ uint32_t s_h[HIST_WORDS];
@@ -428,16 +441,22 @@ __global__ __launch_bounds__(BLOCK) void k_count(const uint64_t* __restrict__ ke
     const uint32_t lt = t - B.first_tile;
     const uint32_t base = B.start + lt * TILE;
     const uint32_t nvalid = min(TILE, B.len - lt * TILE);
-    const uint32_t w = threadIdx.x / WAVE, lane = lane_id();
-    uint64_t k[ITEMS];
-#pragma unroll
-    for (int i = 0; i < ITEMS; ++i) {
-        const uint32_t p = w * WAVE * ITEMS + i * WAVE + lane;
-        k[i] = p < nvalid ? src[base + p] : 0ull;
+    const bool later_pass = (B.exec & ((1u << pass) - 1u)) != 0;
+    if (dmode == DIG_BYTES && later_pass) {
+        uint8_t d[ITEMS];
+        load_tile<ITEMS>(dig + base, nvalid, d);
+        tile_histogram<ITEMS>([&](int i) { return (uint32_t)d[i]; }, nvalid, s_h, cnt + (size_t)t * 256);
+    } else if (dmode == DIG_IN_VALS && later_pass) {
+        uint32_t v[ITEMS];
+        load_tile<ITEMS>((flip ? valsB : valsA) + base, nvalid, v);
+        tile_histogram<ITEMS>([&](int i) { return v[i] >> 24; }, nvalid, s_h, cnt + (size_t)t * 256);
+    } else {
+        uint64_t k[ITEMS];
+        load_tile<ITEMS>(src + base, nvalid, k);
+        tile_histogram<ITEMS>(
+            [&](int i) { return single ? (uint32_t)(k[i] >> s0) & m0 : dp.digit(k[i]); }, nvalid, s_h,
+            cnt + (size_t)t * 256);
     }
-    tile_histogram<ITEMS>(
-        [&](int i) { return single ? (uint32_t)(k[i] >> s0) & m0 : dp.digit(k[i]); }, nvalid, s_h,
-        cnt + (size_t)t * 256);
     if (PS) __syncthreads();
     }
 }
@@ -511,14 +530,19 @@ __global__ __launch_bounds__(BLOCK) void k_seg_scan(const BigDesc* __restrict__ 
 
 // Rank and scatter one tile.  The tile is staged through LDS twice, keys
 // first and then indices in the same buffer, which halves the LDS a
-// workgroup needs and lets more workgroups share a compute unit.
+// workgroup needs and lets more workgroups share a compute unit.  Each key
+// also leaves, at its new position, its digit of the segment's next pass for
+// that pass's count kernel: in dig (DIG_BYTES), or in the top byte of the
+// value moved with it (DIG_IN_VALS: values and positions below 2^24; the
+// value's low 24 bits are the value, and a segment's last pass leaves the
+// top byte zero).
 template <int BITS, int ITEMS, bool PS>
 __global__ __launch_bounds__(BLOCK) void k_scatter(
     uint64_t* __restrict__ keysA, uint32_t* __restrict__ valsA, uint64_t* __restrict__ keysB,
     uint32_t* __restrict__ valsB, const BigDesc* __restrict__ bigs,
     const uint32_t* __restrict__ counters, const uint32_t* __restrict__ cnt,
     const uint32_t* __restrict__ gtot, const uint32_t* __restrict__ binstart, int pass,
-    const uint32_t* __restrict__ prog) {
+    const uint32_t* __restrict__ prog, uint8_t* __restrict__ dig, int dmode) {
     constexpr int R = 1 << BITS;
     constexpr uint32_t TILE = BLOCK * ITEMS;
     __shared__ uint64_t s_buf[TILE];
@@ -550,16 +574,22 @@ __global__ __launch_bounds__(BLOCK) void k_scatter(
     // a program of one run (the usual case) needs no run loop
     const bool single = dp.nr <= 1;
     const uint32_t s0 = dp.run[0] & 63u, m0 = (1u << ((dp.run[0] >> 8) & 15u)) - 1u;
-    uint32_t pos[ITEMS], dig[ITEMS];
+    uint32_t pos[ITEMS], dg[ITEMS];
     if (single) {
 #pragma unroll
-        for (int i = 0; i < ITEMS; ++i) dig[i] = (uint32_t)(k[i] >> s0) & m0;
+        for (int i = 0; i < ITEMS; ++i) dg[i] = (uint32_t)(k[i] >> s0) & m0;
     } else {
 #pragma unroll
-        for (int i = 0; i < ITEMS; ++i) dig[i] = dp.digit(k[i]);
+        for (int i = 0; i < ITEMS; ++i) dg[i] = dp.digit(k[i]);
     }
+    // the segment's next pass, if any, and its program
+    const uint32_t later = dmode != DIG_NONE ? B.exec & ~((2u << pass) - 1u) : 0u;
+    DigitProg dq;
+    dq.load(prog, later ? __ffs(later) - 1 : pass);
+    const bool single_q = dq.nr <= 1;
+    const uint32_t sq = dq.run[0] & 63u, mq = (1u << ((dq.run[0] >> 8) & 15u)) - 1u;
     uint32_t bc = 0;
-    rank_digits<BITS, ITEMS>(dig, nvalid, pos, s_whist, s_binstart, s_scan, &bc);
+    rank_digits<BITS, ITEMS>(dg, nvalid, pos, s_whist, s_binstart, s_scan, &bc);
     if (tid < (uint32_t)R) {
         const uint32_t g = B.first_group + lt / GROUP_TILES;
         s_gbase[tid] = binstart[(size_t)b * 256 + tid] + gtot[(size_t)g * 256 + tid] +
@@ -577,17 +607,32 @@ __global__ __launch_bounds__(BLOCK) void k_scatter(
             const uint64_t key = s_buf[p];
             dst[i] = s_gbase[single ? (uint32_t)(key >> s0) & m0 : dp.digit(key)] + p;
             kdst[dst[i]] = key;
+            if (later) {
+                const uint32_t nd = single_q ? (uint32_t)(key >> sq) & mq : dq.digit(key);
+                if (dmode == DIG_BYTES)
+                    dig[dst[i]] = (uint8_t)nd;
+                else
+                    dst[i] |= nd << 24;  // positions are below 2^24 here
+            }
         }
     }
     __syncthreads();
     uint32_t* s_v = (uint32_t*)s_buf;
 #pragma unroll
-    for (int i = 0; i < ITEMS; ++i) s_v[pos[i]] = v[i];
+    for (int i = 0; i < ITEMS; ++i) s_v[pos[i]] = dmode == DIG_IN_VALS ? v[i] & VAL_MASK : v[i];
     __syncthreads();
+    if (dmode == DIG_IN_VALS) {
 #pragma unroll
-    for (int i = 0; i < ITEMS; ++i) {
-        const uint32_t p = i * BLOCK + tid;
-        if (p < nvalid) vdst[dst[i]] = s_v[p];
+        for (int i = 0; i < ITEMS; ++i) {
+            const uint32_t p = i * BLOCK + tid;
+            if (p < nvalid) vdst[dst[i] & VAL_MASK] = s_v[p] | (dst[i] & ~VAL_MASK);
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < ITEMS; ++i) {
+            const uint32_t p = i * BLOCK + tid;
+            if (p < nvalid) vdst[dst[i]] = s_v[p];
+        }
     }
     if (PS) __syncthreads();
     }
@@ -765,13 +810,15 @@ static hipError_t sort_impl(uint64_t* keys, uint32_t* vals, uint64_t* keys_alt,
     // max_segs segments
     const uint32_t max_big = std::min(std::min(sc.big_cap, max_tiles / 2 + 1), std::max(max_segs, 1u));
     const uint32_t max_groups = std::min(sc.group_cap, max_tiles / GROUP_TILES + max_big + 1);
+    const int dmode = sc.dig_in_vals ? DIG_IN_VALS : sc.dig ? DIG_BYTES : DIG_NONE;
     // packed varying bits never outnumber the key bits in [begin_bit, end_bit)
     for (int p = 0; p < npasses; ++p) {
         if (!((pass_union >> p) & 1u)) continue;
         {
             ProfScope ps(pclass == P_SCATTER_FIX ? P_COUNT_SCAN_FIX : P_COUNT_SCAN, s);
             hipLaunchKernelGGL((k_count<BITS, ITEMS, PS>), dim3(sc.grid(max_tiles)), dim3(BLOCK), 0, s, keys,
-                               keys_alt, bigs, sc.counters, sc.cnt, p, sc.prog);
+                               keys_alt, vals, vals_alt, bigs, sc.counters, sc.cnt, p, sc.prog,
+                               (const uint8_t*)sc.dig, dmode);
             hipLaunchKernelGGL((k_group_scan<BITS, PS>), dim3(sc.grid(max_groups)), dim3(BLOCK), 0, s, bigs,
                                sc.counters, sc.cnt, sc.gtot, p);
             hipLaunchKernelGGL((k_seg_scan<BITS, PS>), dim3(sc.grid(max_big)), dim3(BLOCK), 0, s, bigs,
@@ -784,7 +831,7 @@ static hipError_t sort_impl(uint64_t* keys, uint32_t* vals, uint64_t* keys_alt,
                               keys, vals, keys_alt, vals_alt, (const BigDesc*)bigs,
                               (const uint32_t*)sc.counters, (const uint32_t*)sc.cnt,
                               (const uint32_t*)sc.gtot, (const uint32_t*)sc.binstart, p,
-                              (const uint32_t*)sc.prog);
+                              (const uint32_t*)sc.prog, sc.dig, dmode);
     }
     ProfScope ps(P_COPY_BACK, s);
     hipLaunchKernelGGL(k_copy_back<PS>, dim3(sc.grid(max_tiles)), dim3(BLOCK), 0, s, keys, vals, keys_alt,

@@ -84,23 +84,42 @@ __device__ __forceinline__ void rank_digits(uint32_t (&dig)[ITEMS], uint32_t nva
 }
 
 // ------------------------------------------------------------------ tile histogram
+// One tile of src in the wave-striped layout, positions >= nvalid zero.  A
+// whole tile loads without per-item conditions, so that every load is in
+// flight before the first is used.
+template <int ITEMS, typename T>
+__device__ __forceinline__ void load_tile(const T* __restrict__ src, uint32_t nvalid, T (&x)[ITEMS]) {
+    const uint32_t w = threadIdx.x / WAVE, lane = lane_id();
+    if (nvalid == (uint32_t)(BLOCK * ITEMS)) {
+#pragma unroll
+        for (int i = 0; i < ITEMS; ++i) x[i] = src[w * WAVE * ITEMS + i * WAVE + lane];
+    } else {
+#pragma unroll
+        for (int i = 0; i < ITEMS; ++i) {
+            const uint32_t p = w * WAVE * ITEMS + i * WAVE + lane;
+            x[i] = p < nvalid ? src[p] : T(0);
+        }
+    }
+}
+
+
 // Counts of the 8-bit digits of one tile (wave-striped layout as above,
 // positions >= nvalid skipped): out[d] = number of items with digit d.
-// dig_of(i) gives item i's digit.  Every wavefront keeps HIST_COPIES
-// histograms, lane l adding to copy l % HIST_COPIES, so lanes holding the
-// same digit (skewed digits, or keys grouped by earlier passes) collide at
-// most 64 / HIST_COPIES ways on one LDS address instead of 64; rows are
-// HIST_STRIDE = 257 words apart, so the copies of one digit sit in different
-// banks.  s_h: NWAVES * HIST_COPIES * HIST_STRIDE words.  The caller issues
-// its loads first: the clearing here overlaps them.
-constexpr int HIST_COPIES = 4, HIST_STRIDE = 257, HIST_WORDS = NWAVES * HIST_COPIES * HIST_STRIDE;
+// dig_of(i) gives item i's digit.  The workgroup keeps HIST_COPIES
+// histograms, lane l of every wavefront adding to copy l % HIST_COPIES, so
+// lanes holding the same digit (skewed digits, or keys grouped by earlier
+// passes) collide at most 64 / HIST_COPIES ways on one LDS address inside
+// one instruction; rows are HIST_STRIDE = 257 words apart, so the copies of
+// one digit sit in different banks.  s_h: HIST_COPIES * HIST_STRIDE words.
+// The caller issues its loads first: the clearing here overlaps them.
+constexpr int HIST_COPIES = 16, HIST_STRIDE = 257, HIST_WORDS = HIST_COPIES * HIST_STRIDE;
 template <int ITEMS, typename F>
 __device__ __forceinline__ void tile_histogram(F dig_of, uint32_t nvalid, uint32_t* s_h,
                                                uint32_t* __restrict__ out) {
     const uint32_t w = threadIdx.x / WAVE, lane = lane_id();
     for (uint32_t i = threadIdx.x; i < (uint32_t)HIST_WORDS; i += BLOCK) s_h[i] = 0;
     __syncthreads();
-    uint32_t* my = s_h + (w * HIST_COPIES + lane % HIST_COPIES) * HIST_STRIDE;
+    uint32_t* my = s_h + (lane % HIST_COPIES) * HIST_STRIDE;
 #pragma unroll
     for (int i = 0; i < ITEMS; ++i) {
         const uint32_t p = w * WAVE * ITEMS + i * WAVE + lane;
@@ -111,7 +130,7 @@ __device__ __forceinline__ void tile_histogram(F dig_of, uint32_t nvalid, uint32
     for (uint32_t d = threadIdx.x; d < 256u; d += BLOCK) {
         uint32_t v = 0;
 #pragma unroll
-        for (int r = 0; r < NWAVES * HIST_COPIES; ++r) v += s_h[r * HIST_STRIDE + d];
+        for (int r = 0; r < HIST_COPIES; ++r) v += s_h[r * HIST_STRIDE + d];
         out[d] = v;
     }
 }
