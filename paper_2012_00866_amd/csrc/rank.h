@@ -8,6 +8,13 @@
 namespace husky {
 
 // ------------------------------------------------------------------ tile ranking
+// m & ~(bal ^ f) in one three-input bit operation: the truth table takes the
+// operands as the columns 0xF0, 0xCC and 0xAA, so this function's table is
+// 0xF0 & ~(0xCC ^ 0xAA) = 0x90.
+__device__ __forceinline__ uint32_t bit_agree(uint32_t m, uint32_t bal, uint32_t f) {
+    return __builtin_amdgcn_bitop3_b32(m, bal, f, 0x90);
+}
+
 // Ranks the ITEMS digits (< 2^BITS) of every thread of one tile of a
 // workgroup of NW wavefronts (NW * 64 >= 2^BITS threads).  Digits sit in
 // "wave-striped" order: item k of lane l of wave w is tile position
@@ -41,15 +48,15 @@ __device__ __forceinline__ void rank_digits(uint32_t (&dig)[ITEMS], uint32_t nva
         dig[k] = d;
         // lanes holding the same digit: for every digit bit keep the lanes
         // whose bit agrees (the ballot, inverted where this lane's bit is 0)
-        uint64_t bal[BITS];
-#pragma unroll
-        for (int b = 0; b < BITS; ++b) bal[b] = ballot(((d >> b) & 1u) != 0);
         uint32_t plo = ~0u, phi = ~0u;
 #pragma unroll
         for (int b = 0; b < BITS; ++b) {
-            const uint32_t f = 0u - ((d >> b) & 1u);  // all ones when set
-            plo &= ~((uint32_t)bal[b] ^ f);
-            phi &= ~((uint32_t)(bal[b] >> 32) ^ f);
+            // the bit as all ones or all zeros (one signed bit-field extract),
+            // its ballot, and one three-input bit operation per mask half
+            const uint32_t f = (uint32_t)__builtin_amdgcn_sbfe((int)d, b, 1);
+            const uint64_t bal = ballot((int32_t)f < 0);
+            plo = bit_agree(plo, (uint32_t)bal, f);
+            phi = bit_agree(phi, (uint32_t)(bal >> 32), f);
         }
         const uint32_t below = __builtin_amdgcn_mbcnt_hi(phi, __builtin_amdgcn_mbcnt_lo(plo, 0u));
         const uint32_t cnt = (uint32_t)__popc(plo) + (uint32_t)__popc(phi);
