@@ -638,8 +638,10 @@ static husky_status sort_common(husky_coder coder, const void* elems, const uint
     // needs end at once.  The values are string indices (as in the
     // device-wide fix-up's sorts after it).
     c.rad.dig_in_vals = n <= DIG_IN_VALS_MAX;
+    // one instance longer than a tile has no single-tile segment to sort
+    const bool tile_segs = !(n_segs == 1 && n > (uint64_t)tn.rc.tile());
     HUSKY_TRY(radix_sort_segments(codes, perm, codes_b, c.at<uint32_t>(c.L.idx_b), 0, end_bit,
-                                  (uint32_t)n_segs, tb, ~0u, c.rad, tn.rc, P_SCATTER, s));
+                                  (uint32_t)n_segs, tb, ~0u, c.rad, tn.rc, P_SCATTER, s, tile_segs));
     // the sorted codes are not needed once the runs are listed, so the
     // device-wide fix-up reuses both code buffers for its keys
     return run_fixup(c, tn, coder, coder_m(coder), elems, offsets, n, n_segs, codes, codes, codes_b, perm,

@@ -287,9 +287,10 @@ __device__ void build_programs(BigDesc* __restrict__ bigs, uint32_t* __restrict_
                                const uint64_t* __restrict__ segvary, uint32_t* __restrict__ prog,
                                int begin_bit, int end_bit, uint32_t nb, uint32_t* s_prog,
                                uint64_t* s_pm, uint32_t* s_or, bool perfect_lsb) {
+    for (int i = threadIdx.x; i < MAX_PASSES * PROG_WORDS; i += BLOCK) s_prog[i] = 0;
+    for (int p = threadIdx.x; p < MAX_PASSES; p += BLOCK) s_pm[p] = 0;
+    __syncthreads();
     if (threadIdx.x == 0) {
-        for (int i = 0; i < MAX_PASSES * PROG_WORDS; ++i) s_prog[i] = 0;
-        for (int p = 0; p < MAX_PASSES; ++p) s_pm[p] = 0;
         uint64_t u = (uint64_t)__hip_atomic_load(&counters[C_VARY_LO], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) |
                      ((uint64_t)__hip_atomic_load(&counters[C_VARY_HI], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) << 32);
         const uint64_t range = (end_bit >= 64 ? ~0ull : (1ull << end_bit) - 1ull);
@@ -376,9 +377,20 @@ __global__ __launch_bounds__(BLOCK) void k_exec(BigDesc* __restrict__ bigs,
     HUSKY_UNITS_P(PS, b, nb) {
         const BigDesc B = bigs[b];
         uint64_t o = 0, a = ~0ull;
-        for (uint32_t t = threadIdx.x; t < B.ntiles; t += BLOCK) {
-            o |= korand[2 * (size_t)(B.first_tile + t)];
-            a &= korand[2 * (size_t)(B.first_tile + t) + 1];
+        // four tiles' words in flight per thread
+        for (uint32_t t0 = threadIdx.x; t0 < B.ntiles; t0 += 4 * BLOCK) {
+            uint64_t vo[4], va[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const uint32_t t = t0 + u * BLOCK;
+                vo[u] = t < B.ntiles ? korand[2 * (size_t)(B.first_tile + t)] : 0ull;
+                va[u] = t < B.ntiles ? korand[2 * (size_t)(B.first_tile + t) + 1] : ~0ull;
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                o |= vo[u];
+                a &= va[u];
+            }
         }
         block_or_and(o, a, s_o, s_a);
         if (threadIdx.x == 0) {
