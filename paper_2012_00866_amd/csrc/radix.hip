@@ -540,6 +540,88 @@ __global__ __launch_bounds__(BLOCK) void k_seg_scan(const BigDesc* __restrict__ 
     }
 }
 
+// The two scans in one launch, for the device-wide fix-up's sorts (whose
+// every pass is launched whether or not a group needs it): each group's
+// workgroup scans its tiles' counts as k_group_scan does; a segment of one
+// group gets its digit starts from that same workgroup, and in a longer
+// segment the workgroup that completes its last group scans the group totals
+// as k_seg_scan does.  Each group's workgroup publishes its totals with a
+// device-scope release and counts itself in the segment's BigDesc::pad
+// (which grows by ngroups per pass, so the count that reaches a multiple of
+// ngroups is the pass's last).
+template <int BITS, bool PS>
+__global__ __launch_bounds__(BLOCK) void k_scans(BigDesc* __restrict__ bigs,
+                                                 const uint32_t* __restrict__ counters,
+                                                 uint32_t* __restrict__ cnt, uint32_t* __restrict__ gtot,
+                                                 uint32_t* __restrict__ binstart, int pass) {
+    constexpr int R = 1 << BITS;
+    static_assert(R <= BLOCK, "one thread per digit");
+    __shared__ uint32_t scratch[NWAVES];
+    __shared__ uint32_t s_last;
+    if (!((counters[C_EXEC_UNION] >> pass) & 1u)) return;  // no segment runs this pass
+    HUSKY_UNITS_P(PS, g, counters[C_NUM_GROUPS]) {
+    const uint32_t b = big_of_group(bigs, counters[C_NUM_BIG], g);
+    const BigDesc B = bigs[b];
+    bool flip;
+    if (!pass_runs(B, pass, flip)) continue;
+    const uint32_t d = threadIdx.x;
+    const uint32_t t0 = B.first_tile + (g - B.first_group) * GROUP_TILES;
+    const uint32_t nt = min((uint32_t)GROUP_TILES, B.first_tile + B.ntiles - t0);
+    uint32_t run = 0;
+    if (d < (uint32_t)R) {
+        uint32_t v[GROUP_TILES];
+#pragma unroll
+        for (int i = 0; i < GROUP_TILES; ++i) v[i] = (uint32_t)i < nt ? cnt[(size_t)(t0 + i) * 256 + d] : 0u;
+#pragma unroll
+        for (int i = 0; i < GROUP_TILES; ++i) {
+            if ((uint32_t)i < nt) cnt[(size_t)(t0 + i) * 256 + d] = run;
+            run += v[i];
+        }
+    }
+    if (B.ngroups == 1) {
+        uint32_t tot;
+        const uint32_t ex = block_exclusive_sum(d < (uint32_t)R ? run : 0u, scratch, &tot);
+        if (d < (uint32_t)R) {
+            gtot[(size_t)g * 256 + d] = 0;
+            binstart[(size_t)b * 256 + d] = B.start + ex;
+        }
+        continue;
+    }
+    if (d < (uint32_t)R) gtot[(size_t)g * 256 + d] = run;
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) s_last = (atomicAdd(&bigs[b].pad, 1u) + 1u) % B.ngroups == 0u ? 1u : 0u;
+    __syncthreads();
+    if (s_last) {
+        __threadfence();
+        // the segment's group totals (written by other workgroups) -> exclusive
+        // over groups, in place; the digit starts from the segment totals
+        uint32_t srun = 0;
+        if (d < (uint32_t)R) {
+            constexpr int U = 64;
+            for (uint32_t g0 = 0; g0 < B.ngroups; g0 += U) {
+                uint32_t v[U];
+#pragma unroll
+                for (int i = 0; i < U; ++i)
+                    v[i] = g0 + i < B.ngroups
+                               ? __hip_atomic_load(&gtot[(size_t)(B.first_group + g0 + i) * 256 + d],
+                                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                               : 0u;
+#pragma unroll
+                for (int i = 0; i < U; ++i) {
+                    if (g0 + i < B.ngroups) gtot[(size_t)(B.first_group + g0 + i) * 256 + d] = srun;
+                    srun += v[i];
+                }
+            }
+        }
+        uint32_t tot;
+        const uint32_t ex = block_exclusive_sum(d < (uint32_t)R ? srun : 0u, scratch, &tot);
+        if (d < (uint32_t)R) binstart[(size_t)b * 256 + d] = B.start + ex;
+    }
+    __syncthreads();  // s_last is reused by the next unit
+    }
+}
+
 // Rank and scatter one tile.  The tile is staged through LDS twice, keys
 // first and then indices in the same buffer, which halves the LDS a
 // workgroup needs and lets more workgroups share a compute unit.  Each key
@@ -831,10 +913,15 @@ static hipError_t sort_impl(uint64_t* keys, uint32_t* vals, uint64_t* keys_alt,
             hipLaunchKernelGGL((k_count<BITS, ITEMS, PS>), dim3(sc.grid(max_tiles)), dim3(BLOCK), 0, s, keys,
                                keys_alt, vals, vals_alt, bigs, sc.counters, sc.cnt, p, sc.prog,
                                (const uint8_t*)sc.dig, dmode);
-            hipLaunchKernelGGL((k_group_scan<BITS, PS>), dim3(sc.grid(max_groups)), dim3(BLOCK), 0, s, bigs,
-                               sc.counters, sc.cnt, sc.gtot, p);
-            hipLaunchKernelGGL((k_seg_scan<BITS, PS>), dim3(sc.grid(max_big)), dim3(BLOCK), 0, s, bigs,
-                               sc.counters, sc.gtot, sc.binstart, p);
+            if (PS) {
+                hipLaunchKernelGGL((k_scans<BITS, PS>), dim3(sc.grid(max_groups)), dim3(BLOCK), 0, s, bigs,
+                                   sc.counters, sc.cnt, sc.gtot, sc.binstart, p);
+            } else {
+                hipLaunchKernelGGL((k_group_scan<BITS, PS>), dim3(sc.grid(max_groups)), dim3(BLOCK), 0, s,
+                                   bigs, sc.counters, sc.cnt, sc.gtot, p);
+                hipLaunchKernelGGL((k_seg_scan<BITS, PS>), dim3(sc.grid(max_big)), dim3(BLOCK), 0, s, bigs,
+                                   sc.counters, sc.gtot, sc.binstart, p);
+            }
         }
         // timed (when profiling) by events that the dispatch itself records
         hipEvent_t ev0, ev1;

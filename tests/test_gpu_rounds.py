@@ -122,6 +122,40 @@ def test_shared_prefix_beyond_search_span(gpu_lib):
     assert gpu_lib.read_status(ws)["large_rounds"] == 2
 
 
+def _wide_groups(seed, n, prefixes=2):
+    """A few groups of hundreds of thousands of strings that share 20 bytes
+    and differ in the 6 after them: the device-wide round sorts segments of
+    more than 64 radix tiles (several scan groups each)."""
+    rng = np.random.default_rng(seed)
+    heads = [bytes(rng.integers(97, 123, size=20, dtype=np.uint8).tolist()) for _ in range(prefixes)]
+    tails = rng.integers(97, 123, size=(n, 6), dtype=np.uint8)
+    pick = rng.integers(0, prefixes, size=n)
+    return from_strings([heads[int(pick[i])] + tails[i].tobytes() for i in range(n)] + [b"a"])
+
+
+@pytest.mark.parametrize("adaptive", [False, True])
+def test_round_segments_of_several_scan_groups(gpu_lib, adaptive):
+    # two groups of ~300,000 (73 tiles each): the round's digit passes scan
+    # their counts in more than one group of 64 tiles
+    b = _wide_groups(seed=21, n=600_000)
+    e, o = gpu_lib.to_device(b)
+    ws = gpu_lib.alloc_workspace(b.n)
+    tn = gpu_lib.make_tuning(max_rounds=ADAPTIVE) if adaptive else None
+    perm = _u32(gpu_lib.sort(e, o, "ascii7", tuning=tn, ws=ws))
+    np.testing.assert_array_equal(perm, oracle.sort(b)[0])
+    assert gpu_lib.read_status(ws)["unresolved"] == 0
+
+
+def test_round_segments_of_several_scan_groups_batched(gpu_lib):
+    import torch
+
+    b = _wide_groups(seed=22, n=700_000, prefixes=1)
+    b.seg_offsets = np.array([0, 250_000, 250_001, b.n], dtype=np.uint64)
+    e, o = gpu_lib.to_device(b)
+    seg = torch.from_numpy(b.seg_offsets.view(np.int64)).cuda()
+    np.testing.assert_array_equal(_u32(gpu_lib.sort_batched(e, o, seg, "ascii7")), oracle.sort_batched(b)[0])
+
+
 def _edge_group(coder, seed, n=40_000):
     """Runs of more than 8,192 equal codes whose members differ only at the
     common-prefix pass's edges: strings shorter than the coded prefix whose
