@@ -623,9 +623,12 @@ static husky_status sort_common(husky_coder coder, const void* elems, const uint
     // one instance: its radix tiles are the string order's, so the encode
     // kernel reduces each tile's OR / AND as it writes the codes
     const bool enc_orand = !seg_offsets;
+    // ... and, for one instance longer than a tile, puts each code's low
+    // byte in its index's top byte for the first digit pass's count
+    const bool low8 = enc_orand && n <= DIG_IN_VALS_MAX && n > (uint64_t)tn.rc.tile();
     HUSKY_TRY(launch_encode(coder, elems, offsets, (uint32_t)n, codes, perm, c.at<uint64_t>(c.L.key0),
                             &c.status->domain_violations, s, nullptr, 0, nullptr, perfect,
-                            enc_orand ? c.rad.korand : nullptr, (uint32_t)tn.rc.tile()));
+                            enc_orand ? c.rad.korand : nullptr, (uint32_t)tn.rc.tile(), low8));
     if (seg_offsets)
         HUSKY_TRY(radix_segments_from_offsets(seg_offsets, (uint32_t)n_segs, c.rad, tn.rc, s));
     else
@@ -640,8 +643,10 @@ static husky_status sort_common(husky_coder coder, const void* elems, const uint
     c.rad.dig_in_vals = n <= DIG_IN_VALS_MAX;
     // one instance longer than a tile has no single-tile segment to sort
     const bool tile_segs = !(n_segs == 1 && n > (uint64_t)tn.rc.tile());
+    c.rad.vals_low8 = low8;
     HUSKY_TRY(radix_sort_segments(codes, perm, codes_b, c.at<uint32_t>(c.L.idx_b), 0, end_bit,
                                   (uint32_t)n_segs, tb, ~0u, c.rad, tn.rc, P_SCATTER, s, tile_segs));
+    c.rad.vals_low8 = false;  // the fix-up's sorts start from clean values
     // the sorted codes are not needed once the runs are listed, so the
     // device-wide fix-up reuses both code buffers for its keys
     return run_fixup(c, tn, coder, coder_m(coder), elems, offsets, n, n_segs, codes, codes, codes_b, perm,

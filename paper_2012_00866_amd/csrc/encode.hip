@@ -44,7 +44,8 @@ __global__ __launch_bounds__(BLOCK) void k_encode(const uint8_t* __restrict__ by
                                                   uint32_t* __restrict__ status,
                                                   const uint32_t* __restrict__ sel,
                                                   uint32_t n_out, BucketArgs bucket, bool perfect,
-                                                  uint64_t* __restrict__ korand, uint32_t tile) {
+                                                  uint64_t* __restrict__ korand, uint32_t tile,
+                                                  bool tag_low8) {
     // bytes in the element buffer (uniform scalar load): the three-word
     // window below is used only where it stays inside the buffer.
     constexpr uint32_t ES = CODER == 1 ? 2u : 1u;  // bytes per element
@@ -137,7 +138,9 @@ __global__ __launch_bounds__(BLOCK) void k_encode(const uint8_t* __restrict__ by
             }
         }
         if (codes) codes[t] = code;
-        if (idx) idx[t] = i;
+        // tag_low8: the code's low byte rides in the index's top byte (indices
+        // below 2^24), as the first digit pass's count input
+        if (idx) idx[t] = tag_low8 ? i | ((uint32_t)code & 0xFFu) << 24 : i;
         if (key0) key0[t] = k0;
         return code;
     };
@@ -207,7 +210,8 @@ __global__ __launch_bounds__(BLOCK) void k_encode(const uint8_t* __restrict__ by
 hipError_t launch_encode(int coder, const void* elems, const uint64_t* offsets, uint32_t n,
                          uint64_t* codes, uint32_t* idx, uint64_t* key0, uint32_t* status,
                          hipStream_t s, const uint32_t* sel, uint32_t n_out,
-                         const BucketArgs* bucket, bool perfect, uint64_t* korand, uint32_t tile) {
+                         const BucketArgs* bucket, bool perfect, uint64_t* korand, uint32_t tile,
+                         bool tag_low8) {
     const uint32_t count = sel ? n_out : n;
     if (count == 0) return hipSuccess;
     if (bucket || !tile) korand = nullptr;
@@ -218,7 +222,8 @@ hipError_t launch_encode(int coder, const void* elems, const uint64_t* offsets, 
     const uint8_t* e = (const uint8_t*)elems;
 #define HUSKY_ENC(C, L)                                                                           \
     hipLaunchKernelGGL((k_encode<C, L>), dim3(blocks), dim3(BLOCK), 0, s, e, offsets, n, codes, idx, \
-                       key0, status, sel, n_out, b, perfect && coder == 0, korand, tile)
+                       key0, status, sel, n_out, b, perfect && coder == 0, korand, tile,        \
+                       tag_low8 && !sel && n <= (1u << 24))
     if (coder == CODER_ASCII7) {
         if (bucket) HUSKY_ENC(0, true); else HUSKY_ENC(0, false);
     } else if (coder == CODER_BYTES8) {

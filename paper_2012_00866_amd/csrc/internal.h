@@ -47,7 +47,7 @@ hipError_t launch_encode(int coder, const void* elems, const uint64_t* offsets, 
                          uint64_t* codes, uint32_t* idx, uint64_t* key0, uint32_t* status,
                          hipStream_t s, const uint32_t* sel = nullptr, uint32_t n_out = 0,
                          const BucketArgs* bucket = nullptr, bool perfect = false,
-                         uint64_t* korand = nullptr, uint32_t tile = 0);
+                         uint64_t* korand = nullptr, uint32_t tile = 0, bool tag_low8 = false);
 
 // ---- radix.hip
 struct RadixConfig {
@@ -76,6 +76,11 @@ struct RadixScratch {
     // 2^24: the next digit then rides in each value's top byte instead of in
     // dig, which spares the scatter a third store per key.
     bool dig_in_vals = false;
+    // Set (with dig_in_vals) by a caller whose encode kernel put each key's
+    // low byte in the top byte of its value: a first pass whose digit is
+    // bits 0..7 counts those bytes instead of the keys, and the values of a
+    // segment that runs no pass are cleaned by the copy-back kernel.
+    bool vals_low8 = false;
     uint32_t seg_cap, big_cap, big_tile_cap, group_cap;
     // Largest grid of a launch sized from a host bound (a multiple of 8;
     // ~0u: none): the kernels walk their work units (HUSKY_UNITS), so a

@@ -433,7 +433,7 @@ __global__ __launch_bounds__(BLOCK) void k_count(const uint64_t* __restrict__ ke
                                                  const uint32_t* __restrict__ counters,
                                                  uint32_t* __restrict__ cnt, int pass,
                                                  const uint32_t* __restrict__ prog,
-                                                 const uint8_t* __restrict__ dig, int dmode) {
+                                                 const uint8_t* __restrict__ dig, int dmode, bool low8) {
     static_assert(BITS <= 8, "cnt holds 256 digits per tile");
     constexpr uint32_t TILE = BLOCK * ITEMS;
     __shared__ uint32_t s_h[HIST_WORDS];
@@ -454,11 +454,13 @@ __global__ __launch_bounds__(BLOCK) void k_count(const uint64_t* __restrict__ ke
     const uint32_t base = B.start + lt * TILE;
     const uint32_t nvalid = min(TILE, B.len - lt * TILE);
     const bool later_pass = (B.exec & ((1u << pass) - 1u)) != 0;
+    // the values' top bytes already hold the keys' low bytes (vals_low8)
+    const bool low8_digit = low8 && pass == 0 && dp.nr == 1 && dp.run[0] == (8u << 8);
     if (dmode == DIG_BYTES && later_pass) {
         uint8_t d[ITEMS];
         load_tile<ITEMS>(dig + base, nvalid, d);
         tile_histogram<ITEMS>([&](int i) { return (uint32_t)d[i]; }, nvalid, s_h, cnt + (size_t)t * 256);
-    } else if (dmode == DIG_IN_VALS && later_pass) {
+    } else if (dmode == DIG_IN_VALS && (later_pass || low8_digit)) {
         uint32_t v[ITEMS];
         load_tile<ITEMS>((flip ? valsB : valsA) + base, nvalid, v);
         tile_histogram<ITEMS>([&](int i) { return v[i] >> 24; }, nvalid, s_h, cnt + (size_t)t * 256);
@@ -740,9 +742,17 @@ __global__ __launch_bounds__(BLOCK) void k_copy_back(uint64_t* __restrict__ keys
                                                      const uint32_t* __restrict__ valsB,
                                                      const BigDesc* __restrict__ bigs,
                                                      const uint32_t* __restrict__ counters,
-                                                     uint32_t tile) {
+                                                     uint32_t tile, bool clean) {
     HUSKY_UNITS_P(PS, t, counters[C_BIG_TILES]) {
         const BigDesc B = bigs[big_of_tile(bigs, counters[C_NUM_BIG], t)];
+        if (clean && B.exec == 0) {
+            // no pass ran: the values still carry the low bytes in their top bytes
+            const uint32_t lt = t - B.first_tile;
+            const uint32_t base = B.start + lt * tile;
+            const uint32_t cnt = min(tile, B.len - lt * tile);
+            for (uint32_t i = threadIdx.x; i < cnt; i += BLOCK) valsA[base + i] &= VAL_MASK;
+            continue;
+        }
         if (!(__popc(B.exec) & 1)) continue;
         const uint32_t lt = t - B.first_tile;
         const uint32_t base = B.start + lt * tile;
@@ -912,7 +922,7 @@ static hipError_t sort_impl(uint64_t* keys, uint32_t* vals, uint64_t* keys_alt,
             ProfScope ps(pclass == P_SCATTER_FIX ? P_COUNT_SCAN_FIX : P_COUNT_SCAN, s);
             hipLaunchKernelGGL((k_count<BITS, ITEMS, PS>), dim3(sc.grid(max_tiles)), dim3(BLOCK), 0, s, keys,
                                keys_alt, vals, vals_alt, bigs, sc.counters, sc.cnt, p, sc.prog,
-                               (const uint8_t*)sc.dig, dmode);
+                               (const uint8_t*)sc.dig, dmode, sc.vals_low8 && dmode == DIG_IN_VALS);
             if (PS) {
                 hipLaunchKernelGGL((k_scans<BITS, PS>), dim3(sc.grid(max_groups)), dim3(BLOCK), 0, s, bigs,
                                    sc.counters, sc.cnt, sc.gtot, sc.binstart, p);
@@ -934,7 +944,7 @@ static hipError_t sort_impl(uint64_t* keys, uint32_t* vals, uint64_t* keys_alt,
     }
     ProfScope ps(P_COPY_BACK, s);
     hipLaunchKernelGGL(k_copy_back<PS>, dim3(sc.grid(max_tiles)), dim3(BLOCK), 0, s, keys, vals, keys_alt,
-                       vals_alt, bigs, sc.counters, TILE);
+                       vals_alt, bigs, sc.counters, TILE, sc.vals_low8);
     return hipGetLastError();
 }
 

@@ -122,6 +122,24 @@ def test_sort_threshold_stress(gpu_lib, tuning):
         np.testing.assert_array_equal(_sort_gpu(gpu_lib, b, t), oracle.sort(b)[0])
 
 
+@pytest.mark.parametrize("kind", ["long_copies", "short_copies", "same_prefix"])
+def test_sort_one_code_over_several_tiles(gpu_lib, kind):
+    # every code equal and more strings than one radix tile: no digit pass
+    # runs, so the indices leave the code sort as the encode kernel wrote them
+    # (for one instance it puts each code's low byte in the index's top byte
+    # for the first pass's count, which must not reach the permutation)
+    rng = np.random.default_rng(31)
+    if kind == "long_copies":
+        strs = [b"abcdefghijklmnop"] * 9000
+    elif kind == "short_copies":
+        strs = [b"abcdefg"] * 9000
+    else:
+        strs = [b"abcdefghi" + bytes(rng.integers(97, 123, size=5, dtype=np.uint8).tolist()) for _ in range(9000)]
+    b = from_strings(strs)
+    _say("one code", kind, b.n)
+    np.testing.assert_array_equal(_sort_gpu(gpu_lib, b), oracle.sort(b)[0])
+
+
 @pytest.mark.parametrize("items", [8, 12, 16])
 def test_sort_tile_edges(gpu_lib, items):
     # the encode kernel reduces each radix tile's OR / AND itself (one
