@@ -338,8 +338,11 @@ static hipError_t side_join(hipStream_t s, const SideStreams* ss) {
 husky_status run_fixup(Ctx& c, const Tune& tn, int coder, uint32_t origin, const void* elems,
                        const uint64_t* offsets, uint64_t n, uint64_t n_segs,
                        const uint64_t* codes, uint64_t* keys, uint64_t* keys_alt, uint32_t* idx,
-                       hipStream_t s, bool perfect_codes = false) {
-    HUSKY_TRY(zero_u32(c.counters + CNT_SMALL, 16, s));  // tier counts [80, 96)
+                       hipStream_t s, bool perfect_codes = false, bool tier_counts_zero = false) {
+    // tier counts [80, 96); with tier_counts_zero the caller cleared all of
+    // [80, 128) (the LDS tier's work counters too)
+    if (!tier_counts_zero) HUSKY_TRY(zero_u32(c.counters + CNT_SMALL, 16, s));
+    c.tiers.lds_queue_zero = tier_counts_zero;
     c.tiers.lds_max = tn.t_medium < LDS_RUN_MAX ? LDS_RUN_MAX : 0u;
     const uint32_t tb = tiles_bound(n, n_segs, tn.rc);
     const int ek = elem_kind(coder);
@@ -613,7 +616,9 @@ static husky_status sort_common(husky_coder coder, const void* elems, const uint
     if (st != HUSKY_OK) return st;
     hipStream_t s = (hipStream_t)stream;
     Ctx c = make_ctx(ws, n, n_segs);
-    HUSKY_TRY(zero_u32((uint32_t*)c.status, STATUS_WORDS, s));
+    // the status and Step 3's counters [80, 128) (tier counts, LDS work
+    // counters: untouched until run detection)
+    HUSKY_TRY(zero_u32_two((uint32_t*)c.status, (uint32_t)STATUS_WORDS, c.counters + CNT_SMALL, 48, s));
     if (n == 0) return HUSKY_OK;
     uint64_t* codes = c.at<uint64_t>(c.L.codes_a);
     uint64_t* codes_b = c.at<uint64_t>(c.L.codes_b);
@@ -650,7 +655,7 @@ static husky_status sort_common(husky_coder coder, const void* elems, const uint
     // the sorted codes are not needed once the runs are listed, so the
     // device-wide fix-up reuses both code buffers for its keys
     return run_fixup(c, tn, coder, coder_m(coder), elems, offsets, n, n_segs, codes, codes, codes_b, perm,
-                     s, perfect);
+                     s, perfect, true);
 }
 
 husky_status husky_sort(husky_coder coder, const void* elems, const uint64_t* offsets, uint64_t n,

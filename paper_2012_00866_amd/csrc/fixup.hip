@@ -1138,7 +1138,7 @@ static hipError_t lds_classes(const FixupArgs& a, const TierLists& tl, uint32_t 
                               hipStream_t s, uint32_t spare_cus) {
     const uint32_t cus = persistent_blocks();
     ProfScope ps(P_FIX_LDS, s);
-    hipError_t e = zero_u32(tl.lds_queue, 4, s);
+    hipError_t e = tl.lds_queue_zero ? hipSuccess : zero_u32(tl.lds_queue, 4, s);
     if (e != hipSuccess) return e;
 #define HUSKY_FL(I, NW, PER_CU, C)                                                                 \
     static_assert(NW * WAVE * I == lds_class_max(C), "class tile");                                \

@@ -167,6 +167,7 @@ struct TierLists {
     const uint32_t* small_first = nullptr;
     const uint32_t* medium_first = nullptr;
     const uint32_t* lds_first = nullptr;  // [4]
+    bool lds_queue_zero = false;  // the caller cleared lds_queue already
 };
 
 // Find runs (length >= 2) of equal keys inside every segment of sc; when
@@ -187,6 +188,8 @@ hipError_t find_runs(const uint64_t* keys, const RadixScratch& seg, const RadixC
 // Zero-fill kernels (graph-capture friendly).
 hipError_t zero_u64(uint64_t* p, size_t n, hipStream_t s);
 hipError_t zero_u32(uint32_t* p, size_t n, hipStream_t s);
+// Two small ranges cleared by one single-workgroup launch.
+hipError_t zero_u32_two(uint32_t* a, uint32_t na, uint32_t* b, uint32_t nb, hipStream_t s);
 
 // ---- fixup.hip
 struct FixupArgs {

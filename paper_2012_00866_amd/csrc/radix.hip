@@ -870,6 +870,16 @@ hipError_t zero_u64(uint64_t* p, size_t n, hipStream_t s) {
     hipLaunchKernelGGL(k_zero_u64, dim3(blocks), dim3(BLOCK), 0, s, p, n);
     return hipGetLastError();
 }
+__global__ void k_zero_u32_two(uint32_t* __restrict__ a, uint32_t na, uint32_t* __restrict__ b, uint32_t nb) {
+    for (uint32_t i = threadIdx.x; i < na; i += blockDim.x) a[i] = 0;
+    for (uint32_t i = threadIdx.x; i < nb; i += blockDim.x) b[i] = 0;
+}
+
+hipError_t zero_u32_two(uint32_t* a, uint32_t na, uint32_t* b, uint32_t nb, hipStream_t s) {
+    hipLaunchKernelGGL(k_zero_u32_two, dim3(1), dim3(BLOCK), 0, s, a, na, b, nb);
+    return hipGetLastError();
+}
+
 hipError_t zero_u32(uint32_t* p, size_t n, hipStream_t s) {
     if (!n) return hipSuccess;
     const uint32_t blocks = (uint32_t)std::min<size_t>((n + BLOCK - 1) / BLOCK, 4096);
