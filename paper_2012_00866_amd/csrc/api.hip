@@ -616,10 +616,17 @@ static husky_status sort_common(husky_coder coder, const void* elems, const uint
     if (st != HUSKY_OK) return st;
     hipStream_t s = (hipStream_t)stream;
     Ctx c = make_ctx(ws, n, n_segs);
-    // the status and Step 3's counters [80, 128) (tier counts, LDS work
-    // counters: untouched until run detection)
-    HUSKY_TRY(zero_u32_two((uint32_t*)c.status, (uint32_t)STATUS_WORDS, c.counters + CNT_SMALL, 48, s));
-    if (n == 0) return HUSKY_OK;
+    if (n == 0) return hip_status(zero_u32((uint32_t*)c.status, STATUS_WORDS, s));
+    // the segment descriptors (they depend on the sizes alone); the same
+    // launch clears the status and Step 3's counters [80, 128) (tier counts,
+    // LDS work counters: untouched until run detection)
+    uint32_t* z0 = (uint32_t*)c.status;
+    uint32_t* z1 = c.counters + CNT_SMALL;
+    if (seg_offsets)
+        HUSKY_TRY(radix_segments_from_offsets(seg_offsets, (uint32_t)n_segs, c.rad, tn.rc, s, z0,
+                                              (uint32_t)STATUS_WORDS, z1, 48));
+    else
+        HUSKY_TRY(radix_segments_single((uint32_t)n, c.rad, tn.rc, s, z0, (uint32_t)STATUS_WORDS, z1, 48));
     uint64_t* codes = c.at<uint64_t>(c.L.codes_a);
     uint64_t* codes_b = c.at<uint64_t>(c.L.codes_b);
     // ASCII codes carry the perfect bit (encode.hip): all 64 bits are key
@@ -634,10 +641,6 @@ static husky_status sort_common(husky_coder coder, const void* elems, const uint
     HUSKY_TRY(launch_encode(coder, elems, offsets, (uint32_t)n, codes, perm, c.at<uint64_t>(c.L.key0),
                             &c.status->domain_violations, s, nullptr, 0, nullptr, perfect,
                             enc_orand ? c.rad.korand : nullptr, (uint32_t)tn.rc.tile(), low8));
-    if (seg_offsets)
-        HUSKY_TRY(radix_segments_from_offsets(seg_offsets, (uint32_t)n_segs, c.rad, tn.rc, s));
-    else
-        HUSKY_TRY(radix_segments_single((uint32_t)n, c.rad, tn.rc, s));
     const int end_bit = 64;
     const uint32_t tb = tiles_bound(n, n_segs, tn.rc);
     if (!enc_orand) HUSKY_TRY(radix_reduce_tiles(codes, tb, c.rad, tn.rc, s));

@@ -93,12 +93,15 @@ struct RadixScratch {
 constexpr uint64_t DIG_IN_VALS_MAX = 1ull << 24;
 
 // Build segment descriptors from uint64 string offsets (n_segs + 1 entries).
+// (z0[0..nz0) and z1[0..nz1) are cleared by the same launch.)
 hipError_t radix_segments_from_offsets(const uint64_t* seg_offsets, uint32_t n_segs,
                                        const RadixScratch& sc, const RadixConfig& cfg,
-                                       hipStream_t s);
+                                       hipStream_t s, uint32_t* z0 = nullptr, uint32_t nz0 = 0,
+                                       uint32_t* z1 = nullptr, uint32_t nz1 = 0);
 // Build segment descriptors for a single segment [0, n).
 hipError_t radix_segments_single(uint32_t n, const RadixScratch& sc, const RadixConfig& cfg,
-                                 hipStream_t s);
+                                 hipStream_t s, uint32_t* z0 = nullptr, uint32_t nz0 = 0,
+                                 uint32_t* z1 = nullptr, uint32_t nz1 = 0);
 // Build segment descriptors from a fix-up work list (count in device memory).
 hipError_t radix_segments_from_items(const RunItem* items, const uint32_t* count,
                                      uint32_t max_items, const RadixScratch& sc,
@@ -188,8 +191,6 @@ hipError_t find_runs(const uint64_t* keys, const RadixScratch& seg, const RadixC
 // Zero-fill kernels (graph-capture friendly).
 hipError_t zero_u64(uint64_t* p, size_t n, hipStream_t s);
 hipError_t zero_u32(uint32_t* p, size_t n, hipStream_t s);
-// Two small ranges cleared by one single-workgroup launch.
-hipError_t zero_u32_two(uint32_t* a, uint32_t na, uint32_t* b, uint32_t nb, hipStream_t s);
 
 // ---- fixup.hip
 struct FixupArgs {

@@ -90,10 +90,16 @@ struct SrcItems {
 // its scan groups.  Each thread takes SEG_K consecutive segments per round, so
 // a round of four block scans covers BLOCK * SEG_K segments.
 constexpr uint32_t SEG_K = 8;
+// z0[0..nz0) and z1[0..nz1) are cleared on the way (a sort's status and
+// Step 3's counters, without a launch of their own).
 template <typename Src>
 __global__ __launch_bounds__(BLOCK) void k_seg_setup(Src src, SegDesc* segs, BigDesc* bigs,
-                                                     uint32_t* counters, uint32_t tile) {
+                                                     uint32_t* counters, uint32_t tile,
+                                                     uint32_t* __restrict__ z0, uint32_t nz0,
+                                                     uint32_t* __restrict__ z1, uint32_t nz1) {
     __shared__ uint32_t scratch[NWAVES];
+    for (uint32_t i = threadIdx.x; i < nz0; i += BLOCK) z0[i] = 0;
+    for (uint32_t i = threadIdx.x; i < nz1; i += BLOCK) z1[i] = 0;
     const uint32_t S = src.count();
     uint32_t carry_all = 0, carry_big = 0, carry_nbig = 0, carry_grp = 0;
     for (uint32_t base = 0; base < S; base += BLOCK * SEG_K) {
@@ -168,19 +174,21 @@ __global__ __launch_bounds__(BLOCK) void k_seg_setup(Src src, SegDesc* segs, Big
 
 hipError_t radix_segments_from_offsets(const uint64_t* seg_offsets, uint32_t n_segs,
                                        const RadixScratch& sc, const RadixConfig& cfg,
-                                       hipStream_t s) {
+                                       hipStream_t s, uint32_t* z0, uint32_t nz0, uint32_t* z1,
+                                       uint32_t nz1) {
     SrcOffsets src{seg_offsets, n_segs};
     ProfScope ps(P_SETUP, s);
     hipLaunchKernelGGL(k_seg_setup<SrcOffsets>, dim3(1), dim3(BLOCK), 0, s, src, sc.segs,
-                       sc.bigs, sc.counters, (uint32_t)cfg.tile());
+                       sc.bigs, sc.counters, (uint32_t)cfg.tile(), z0, nz0, z1, nz1);
     return hipGetLastError();
 }
 hipError_t radix_segments_single(uint32_t n, const RadixScratch& sc, const RadixConfig& cfg,
-                                 hipStream_t s) {
+                                 hipStream_t s, uint32_t* z0, uint32_t nz0, uint32_t* z1,
+                                 uint32_t nz1) {
     SrcSingle src{n};
     ProfScope ps(P_SETUP, s);
     hipLaunchKernelGGL(k_seg_setup<SrcSingle>, dim3(1), dim3(BLOCK), 0, s, src, sc.segs,
-                       sc.bigs, sc.counters, (uint32_t)cfg.tile());
+                       sc.bigs, sc.counters, (uint32_t)cfg.tile(), z0, nz0, z1, nz1);
     return hipGetLastError();
 }
 hipError_t radix_segments_from_items(const RunItem* items, const uint32_t* count,
@@ -189,7 +197,8 @@ hipError_t radix_segments_from_items(const RunItem* items, const uint32_t* count
     SrcItems src{items, count, max_items};
     ProfScope ps(P_SETUP, s);
     hipLaunchKernelGGL(k_seg_setup<SrcItems>, dim3(1), dim3(BLOCK), 0, s, src, sc.segs,
-                       sc.bigs, sc.counters, (uint32_t)cfg.tile());
+                       sc.bigs, sc.counters, (uint32_t)cfg.tile(), (uint32_t*)nullptr, 0u,
+                       (uint32_t*)nullptr, 0u);
     return hipGetLastError();
 }
 
@@ -870,16 +879,6 @@ hipError_t zero_u64(uint64_t* p, size_t n, hipStream_t s) {
     hipLaunchKernelGGL(k_zero_u64, dim3(blocks), dim3(BLOCK), 0, s, p, n);
     return hipGetLastError();
 }
-__global__ void k_zero_u32_two(uint32_t* __restrict__ a, uint32_t na, uint32_t* __restrict__ b, uint32_t nb) {
-    for (uint32_t i = threadIdx.x; i < na; i += blockDim.x) a[i] = 0;
-    for (uint32_t i = threadIdx.x; i < nb; i += blockDim.x) b[i] = 0;
-}
-
-hipError_t zero_u32_two(uint32_t* a, uint32_t na, uint32_t* b, uint32_t nb, hipStream_t s) {
-    hipLaunchKernelGGL(k_zero_u32_two, dim3(1), dim3(BLOCK), 0, s, a, na, b, nb);
-    return hipGetLastError();
-}
-
 hipError_t zero_u32(uint32_t* p, size_t n, hipStream_t s) {
     if (!n) return hipSuccess;
     const uint32_t blocks = (uint32_t)std::min<size_t>((n + BLOCK - 1) / BLOCK, 4096);
