@@ -178,6 +178,7 @@ Ctx make_ctx(void* ws, uint64_t n, uint64_t n_segs, bool learned = false) {
     c.runs.run_end = c.at<uint32_t>(c.L.run_end);
     c.runs.counters = c.counters + CNT_RUNS;
     c.runs.runs_seen = &c.status->runs_fixed;
+    c.runs.flags = c.at<uint8_t>(c.L.dig);  // free whenever runs are detected
     c.runs.tile_cap = c.L.tile_cap;
     c.runs.run_cap = c.L.run_cap;
     c.tiers.small = c.at<RunItem>(c.L.small);

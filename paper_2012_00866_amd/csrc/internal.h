@@ -139,6 +139,10 @@ struct RunScratch {
     uint32_t* run_end;      // [run_cap]
     uint32_t* counters;     // [16]
     uint32_t* runs_seen;    // device counter of runs found by the first detection (or null)
+    // [positions] one byte per key, written by the count kernel (run head,
+    // run tail, inside a run after its head) and read by the write kernel in
+    // place of the keys (null: the write kernel reads the keys again)
+    uint8_t* flags = nullptr;
     uint32_t tile_cap, run_cap;
 };
 

@@ -19,6 +19,7 @@
 
 #include "common.h"
 #include "internal.h"
+#include "rank.h"
 
 namespace husky {
 
@@ -79,24 +80,28 @@ __device__ __forceinline__ bool keep_run(uint64_t kc, RunCmp rc) {
 
 // Flags of tile position p (absolute position base + p inside segment
 // [s0, s1), key kc) from the staged keys: multi-run head / tail.
+// Also `inner`: kept and equal to the key before it (a run continues
+// through p; what the write kernel needs at a tile's first position).
 template <int CODER, bool REFINE>
 __device__ __forceinline__ void run_flags(const uint64_t* s_k, uint64_t kc, uint32_t p,
                                           uint32_t base, uint32_t s0, uint32_t s1, RunCmp rc,
-                                          bool& head, bool& tail) {
+                                          bool& head, bool& tail, bool& inner) {
     const bool has_prev = base + p > s0, has_next = base + p + 1 < s1;
     const bool eq_prev = has_prev && (s_k[p] >> rc.shift) == (kc >> rc.shift);
     const bool eq_next = has_next && (s_k[p + 2] >> rc.shift) == (kc >> rc.shift);
     const bool keep = keep_run<CODER, REFINE>(kc, rc);
     head = keep && !eq_prev && eq_next;
     tail = keep && eq_prev && !eq_next;
+    inner = keep && eq_prev;
 }
+constexpr uint8_t F_HEAD = 1, F_TAIL = 2, F_INNER = 4;
 
 template <int CODER, bool REFINE, int ITEMS, bool PS>
 __global__ __launch_bounds__(BLOCK) void k_runs_count(const uint64_t* __restrict__ keys,
                                                       const SegDesc* __restrict__ segs,
                                                       const uint32_t* __restrict__ counters,
                                                       uint32_t* __restrict__ tile_counts,
-                                                      bool perfect) {
+                                                      bool perfect, uint8_t* __restrict__ flags) {
     constexpr uint32_t TILE = BLOCK * ITEMS;
     __shared__ uint64_t s_k[TILE + 2];
     __shared__ uint32_t s_cnt[NWAVES];
@@ -113,9 +118,11 @@ __global__ __launch_bounds__(BLOCK) void k_runs_count(const uint64_t* __restrict
 #pragma unroll
     for (int i = 0; i < ITEMS; ++i) {
         const uint32_t p = w * WAVE * ITEMS + i * WAVE + lane;
-        bool h = false, tl = false;
-        if (p < nvalid)
-            run_flags<CODER, REFINE>(s_k, k[i], p, base, d.start, d.start + d.len, rc, h, tl);
+        bool h = false, tl = false, in = false;
+        if (p < nvalid) {
+            run_flags<CODER, REFINE>(s_k, k[i], p, base, d.start, d.start + d.len, rc, h, tl, in);
+            if (flags) flags[base + p] = (h ? F_HEAD : 0) | (tl ? F_TAIL : 0) | (in ? F_INNER : 0);
+        }
         heads += (uint32_t)__popcll(ballot(h));
     }
     if (lane == 0) s_cnt[w] = heads;
@@ -156,7 +163,7 @@ __global__ __launch_bounds__(BLOCK) void k_runs_write(const uint64_t* __restrict
                                                       uint32_t* __restrict__ run_start,
                                                       uint32_t* __restrict__ run_end,
                                                       uint32_t* __restrict__ run_seg,
-                                                      bool perfect) {
+                                                      bool perfect, const uint8_t* __restrict__ flags) {
     constexpr uint32_t TILE = BLOCK * ITEMS;
     __shared__ uint64_t s_k[TILE + 2];
     __shared__ uint32_t s_h[NWAVES], s_t[NWAVES];
@@ -168,35 +175,45 @@ __global__ __launch_bounds__(BLOCK) void k_runs_write(const uint64_t* __restrict
     const uint32_t base = d.start + lt * TILE;
     const uint32_t nvalid = min(TILE, d.len - lt * TILE);
     const uint32_t w = threadIdx.x / WAVE, lane = lane_id();
-    uint64_t k[ITEMS];
-    stage_keys<ITEMS>(keys, base, nvalid, d.start, d.start + d.len, s_k, k);
-
     bool hf[ITEMS], tf[ITEMS];
     uint32_t nh = 0, nt = 0;
+    bool open = false;  // a run open at the tile start had its head in an earlier tile
+    if (flags) {
+        // the count kernel's flags: one byte per key instead of the keys
+        uint8_t f[ITEMS];
+        load_tile<ITEMS>(flags + base, nvalid, f);
 #pragma unroll
-    for (int i = 0; i < ITEMS; ++i) {
-        const uint32_t p = w * WAVE * ITEMS + i * WAVE + lane;
-        hf[i] = tf[i] = false;
-        if (p < nvalid)
-            run_flags<CODER, REFINE>(s_k, k[i], p, base, d.start, d.start + d.len, rc, hf[i], tf[i]);
-        nh += (uint32_t)__popcll(ballot(hf[i]));
-        nt += (uint32_t)__popcll(ballot(tf[i]));
+        for (int i = 0; i < ITEMS; ++i) {
+            hf[i] = (f[i] & F_HEAD) != 0;
+            tf[i] = (f[i] & F_TAIL) != 0;
+            nh += (uint32_t)__popcll(ballot(hf[i]));
+            nt += (uint32_t)__popcll(ballot(tf[i]));
+        }
+        open = base > d.start && (flags[base] & F_INNER) != 0;
+    } else {
+        uint64_t k[ITEMS];
+        stage_keys<ITEMS>(keys, base, nvalid, d.start, d.start + d.len, s_k, k);
+#pragma unroll
+        for (int i = 0; i < ITEMS; ++i) {
+            const uint32_t p = w * WAVE * ITEMS + i * WAVE + lane;
+            hf[i] = tf[i] = false;
+            bool in = false;
+            if (p < nvalid)
+                run_flags<CODER, REFINE>(s_k, k[i], p, base, d.start, d.start + d.len, rc, hf[i], tf[i], in);
+            nh += (uint32_t)__popcll(ballot(hf[i]));
+            nt += (uint32_t)__popcll(ballot(tf[i]));
+        }
+        if (base > d.start) {
+            const uint64_t kc = s_k[1];
+            open = (s_k[0] >> rc.shift) == (kc >> rc.shift) && keep_run<CODER, REFINE>(kc, rc);
+        }
     }
     if (lane == 0) {
         s_h[w] = nh;
         s_t[w] = nt;
     }
     __syncthreads();
-    uint32_t hb = tile_counts[t], tb;
-    // a run that is open at the tile start had its head in an earlier tile
-    {
-        bool open = false;
-        if (base > d.start) {
-            const uint64_t kc = s_k[1];
-            open = (s_k[0] >> rc.shift) == (kc >> rc.shift) && keep_run<CODER, REFINE>(kc, rc);
-        }
-        tb = hb - (open ? 1u : 0u);
-    }
+    uint32_t hb = tile_counts[t], tb = hb - (open ? 1u : 0u);
     for (uint32_t i = 0; i < w; ++i) {
         hb += s_h[i];
         tb += s_t[i];
@@ -323,12 +340,12 @@ static hipError_t find_runs_impl(const uint64_t* keys, const RadixScratch& seg,
     uint32_t* num_runs = rs.counters + 0;
     ProfScope ps(P_RUNS, s);
     hipLaunchKernelGGL((k_runs_count<CODER, REFINE, ITEMS, PS>), dim3(seg.grid(max_tiles)), dim3(BLOCK), 0, s,
-                       keys, seg.segs, seg.counters, rs.tile_counts, perfect);
+                       keys, seg.segs, seg.counters, rs.tile_counts, perfect, rs.flags);
     hipLaunchKernelGGL(k_runs_scan, dim3(1), dim3(BLOCK), 0, s, rs.tile_counts, seg.counters,
                        num_runs);
     hipLaunchKernelGGL((k_runs_write<CODER, REFINE, ITEMS, PS>), dim3(seg.grid(max_tiles)), dim3(BLOCK), 0, s,
                        keys, seg.segs, seg.counters, rs.tile_counts, rs.run_start, rs.run_end,
-                       rs.run_start + rs.run_cap, perfect);
+                       rs.run_start + rs.run_cap, perfect, (const uint8_t*)rs.flags);
     const uint32_t blocks = 96;
     hipLaunchKernelGGL(k_runs_classify, dim3(blocks), dim3(BLOCK), 0, s, rs.run_start, rs.run_end,
                        rs.run_start + rs.run_cap, num_runs, items, tl,
