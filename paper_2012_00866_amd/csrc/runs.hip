@@ -141,15 +141,27 @@ __global__ __launch_bounds__(BLOCK) void k_runs_count(const uint64_t* __restrict
 __global__ __launch_bounds__(BLOCK) void k_runs_scan(uint32_t* __restrict__ tile_counts,
                                                      const uint32_t* __restrict__ counters,
                                                      uint32_t* __restrict__ num_runs) {
+    // each thread takes RS consecutive counts per sweep (all loads in
+    // flight together), so 2^24 keys (4,098 tiles) need one block scan
+    constexpr uint32_t RS = 16;
     __shared__ uint32_t scratch[NWAVES];
     const uint32_t total = counters[C_ALL_TILES];
     uint32_t carry = 0;
-    for (uint32_t b = 0; b < total; b += BLOCK) {
-        const uint32_t i = b + threadIdx.x;
-        const uint32_t v = i < total ? tile_counts[i] : 0u;
+    for (uint32_t b = 0; b < total; b += BLOCK * RS) {
+        const uint32_t i0 = b + threadIdx.x * RS;
+        uint32_t v[RS], sum = 0;
+#pragma unroll
+        for (uint32_t j = 0; j < RS; ++j) {
+            v[j] = i0 + j < total ? tile_counts[i0 + j] : 0u;
+            sum += v[j];
+        }
         uint32_t tot;
-        const uint32_t ex = block_exclusive_sum(v, scratch, &tot);
-        if (i < total) tile_counts[i] = carry + ex;
+        uint32_t run = carry + block_exclusive_sum(sum, scratch, &tot);
+#pragma unroll
+        for (uint32_t j = 0; j < RS; ++j) {
+            if (i0 + j < total) tile_counts[i0 + j] = run;
+            run += v[j];
+        }
         carry += tot;
     }
     if (threadIdx.x == 0) *num_runs = carry;
