@@ -932,7 +932,10 @@ static hipError_t sort_impl(uint64_t* keys, uint32_t* vals, uint64_t* keys_alt,
             hipLaunchKernelGGL((k_count<BITS, ITEMS, PS>), dim3(sc.grid(max_tiles)), dim3(BLOCK), 0, s, keys,
                                keys_alt, vals, vals_alt, bigs, sc.counters, sc.cnt, p, sc.prog,
                                (const uint8_t*)sc.dig, dmode, sc.vals_low8 && dmode == DIG_IN_VALS);
-            if (PS) {
+            // one launch where segments are mostly of one scan group (the
+            // fix-up's groups, batched instances); a single long instance
+            // keeps the two launches (its groups' release fences cost more)
+            if (PS || max_segs > 1) {
                 hipLaunchKernelGGL((k_scans<BITS, PS>), dim3(sc.grid(max_groups)), dim3(BLOCK), 0, s, bigs,
                                    sc.counters, sc.cnt, sc.gtot, sc.binstart, p);
             } else {
