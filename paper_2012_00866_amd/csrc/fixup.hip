@@ -529,44 +529,56 @@ __global__ __launch_bounds__(NW * WAVE) void k_fix_lds(const RunItem* __restrict
                 // the byte windows that hold a varying bit (in the 8-wave
                 // classes: the 4-wave ones would lose an occupancy level to
                 // the extra registers)
-                constexpr bool PACK = NW >= 8;
-                const uint64_t gvary = uniform64((gv >> 16) & 0x7FFFu);
-                const int kb = __popcll(vary), nb = kb + __popcll(gvary);
-                int nwin = ((gv >> 16) & 0xFFu ? 1 : 0) + ((gv >> 24) & 0x7Fu ? 1 : 0);
-                for (int shift = 0; shift < 64; shift += 8) nwin += ((vary >> shift) & 0xFFull) ? 1 : 0;
-                if (PACK && nb <= 64 && (nb + 7) / 8 < nwin) {
+                // digits over the bits that vary, in the fewest passes: the
+                // tied keys' varying bits, least significant first, then the
+                // varying group-start bits above them (the order is by group
+                // start, then key).  Each pass's 8-bit digit is read from the
+                // unmodified key and group start as up to eight runs of
+                // adjacent bits, so no packed copy of the keys is kept.
+                const uint32_t gvary = (uint32_t)uniform64((gv >> 16) & 0x7FFFu);
+                const int nb = __popcll(vary) + __popc(gvary);
+                uint64_t km = vary;
+                uint32_t gm = gvary;
+                for (int p0 = 0; p0 < nb; p0 += 8) {
+                    // this pass's runs: source shift | length << 8 | digit
+                    // shift << 16 | from the group start << 24
+                    uint32_t rw[8];
+                    int nr = 0, dst = 0;
 #pragma unroll
-                    for (int i = 0; i < ITEMS; ++i)
-                        k[i] = pack1(k[i], vary) |
-                               (kb >= 64 ? 0ull : pack1((sr[i] >> 16) & 0x7FFFu, gvary) << kb);
-                    for (int shift = 0; shift < nb; shift += 8) {
-#pragma unroll
-                        for (int i = 0; i < ITEMS; ++i) dig[i] = (uint32_t)(k[i] >> shift) & 0xFFu;
-                        pass();
+                    for (int r = 0; r < 8; ++r) {
+                        rw[r] = 0;
+                        if (dst < 8 && (km | gm)) {
+                            const bool g = km == 0;
+                            const uint64_t m = g ? (uint64_t)gm : km;
+                            const int sh = __builtin_ctzll(m);
+                            const uint64_t rest = ~(m >> sh);
+                            int len = rest ? __builtin_ctzll(rest) : 64 - sh;
+                            len = min(len, 8 - dst);
+                            const uint64_t bits = ((1ull << len) - 1ull) << sh;
+                            if (g)
+                                gm &= ~(uint32_t)bits;
+                            else
+                                km &= ~bits;
+                            rw[r] = (uint32_t)sh | (uint32_t)len << 8 | (uint32_t)dst << 16 | (g ? 1u << 24 : 0u);
+                            dst += len;
+                            nr = r + 1;
+                        }
                     }
-                    // keys back (the bits no tied key varies in are kand's);
-                    // members no longer tied carry 0 as before
-                    const uint64_t kmask = kb >= 64 ? ~0ull : (1ull << kb) - 1ull;
 #pragma unroll
-                    for (int i = 0; i < ITEMS; ++i)
-                        k[i] = (sr[i] & TIED) ? unpack1(k[i] & kmask, vary) | (kand & ~vary) : 0ull;
-                } else {
-                    for (int shift = 0; shift < 64; shift += 8) {
-                        if (!((uint32_t)(vary >> shift) & 0xFFu)) continue;
+                    for (int i = 0; i < ITEMS; ++i) {
+                        const uint32_t gsv = (sr[i] >> 16) & 0x7FFFu;
+                        uint32_t d = 0;
 #pragma unroll
-                        for (int i = 0; i < ITEMS; ++i) dig[i] = (uint32_t)(k[i] >> shift) & 0xFFu;
-                        pass();
+                        for (int r = 0; r < 8; ++r) {
+                            if (r >= nr) break;
+                            const uint32_t w = rw[r];
+                            const uint32_t sh = w & 63u, len = (w >> 8) & 15u, dd = (w >> 16) & 7u;
+                            const uint32_t src = (w >> 24) ? gsv >> sh : (uint32_t)(k[i] >> sh);
+                            d |= (src & ((1u << len) - 1u)) << dd;
+                        }
+                        dig[i] = d;
                     }
-                    if ((gv >> 16) & 0xFFu) {
-#pragma unroll
-                        for (int i = 0; i < ITEMS; ++i) dig[i] = (sr[i] >> 16) & 0xFFu;
-                        pass();
-                    }
-                    if ((gv >> 24) & 0x7Fu) {
-#pragma unroll
-                        for (int i = 0; i < ITEMS; ++i) dig[i] = (sr[i] >> 24) & 0x7Fu;
-                        pass();
-                    }
+                    pass();
                 }
             }
             // groups: same group start, same key, and the key continues
