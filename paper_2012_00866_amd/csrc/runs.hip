@@ -86,9 +86,13 @@ template <int CODER, bool REFINE>
 __device__ __forceinline__ void run_flags(const uint64_t* s_k, uint64_t kc, uint32_t p,
                                           uint32_t base, uint32_t s0, uint32_t s1, RunCmp rc,
                                           bool& head, bool& tail, bool& inner) {
+    // both neighbours read whatever the position (s_k[p + 2] is in bounds for
+    // any p < TILE; a word never staged is masked off), so that the reads of
+    // all of a thread's positions go out together
+    const uint64_t kp = s_k[p], kn = s_k[p + 2];
     const bool has_prev = base + p > s0, has_next = base + p + 1 < s1;
-    const bool eq_prev = has_prev && (s_k[p] >> rc.shift) == (kc >> rc.shift);
-    const bool eq_next = has_next && (s_k[p + 2] >> rc.shift) == (kc >> rc.shift);
+    const bool eq_prev = has_prev & ((kp >> rc.shift) == (kc >> rc.shift));
+    const bool eq_next = has_next & ((kn >> rc.shift) == (kc >> rc.shift));
     const bool keep = keep_run<CODER, REFINE>(kc, rc);
     head = keep && !eq_prev && eq_next;
     tail = keep && eq_prev && !eq_next;
@@ -118,11 +122,10 @@ __global__ __launch_bounds__(BLOCK) void k_runs_count(const uint64_t* __restrict
 #pragma unroll
     for (int i = 0; i < ITEMS; ++i) {
         const uint32_t p = w * WAVE * ITEMS + i * WAVE + lane;
-        bool h = false, tl = false, in = false;
-        if (p < nvalid) {
-            run_flags<CODER, REFINE>(s_k, k[i], p, base, d.start, d.start + d.len, rc, h, tl, in);
-            if (flags) flags[base + p] = (h ? F_HEAD : 0) | (tl ? F_TAIL : 0) | (in ? F_INNER : 0);
-        }
+        bool h, tl, in;
+        run_flags<CODER, REFINE>(s_k, k[i], p, base, d.start, d.start + d.len, rc, h, tl, in);
+        h = h && p < nvalid;
+        if (flags && p < nvalid) flags[base + p] = (h ? F_HEAD : 0) | (tl ? F_TAIL : 0) | (in ? F_INNER : 0);
         heads += (uint32_t)__popcll(ballot(h));
     }
     if (lane == 0) s_cnt[w] = heads;
